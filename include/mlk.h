@@ -1,0 +1,324 @@
+/*
+ * mlk.h -- C ABI of the MI355X (gfx950) dense-kernel library for the
+ * computations of "nelli: A lightweight frontend for MLIR" (arXiv 2307.16080).
+ *
+ * The paper defines its kernels as destination-passing functions over typed,
+ * shaped, row-major buffers: matmul(A, B, C) with C updated in place
+ * (Sec. 1, listing "nelli_for_to_affine_for"; Sec. 2.1, listing
+ * "linalg-matmul") and conv2d_nchw_fchw(input, kernel, output) accumulating
+ * into output (Sec. 4.1, listing "2dnchwconv"), and chooses tile sizes and
+ * unroll factors by black-box search over measured run times (Sec. 4.3).
+ * This header exposes those operations for hand-written CDNA4 kernels.
+ *
+ * Conventions for every entry point:
+ *  - Pointers named A, B, C, x, w, y, q, descs' A/B/C, scale pointers and
+ *    statistic outputs are DEVICE pointers (HIP allocations, e.g. torch CUDA
+ *    tensors) unless stated otherwise.  Structs passed by pointer
+ *    (mlk_tile_config, mlk_problem, mlk_tune_opts, mlk_gemm_desc arrays,
+ *    mlk_tune_report) are HOST memory.
+ *  - The caller owns every buffer it passes; the library never frees or
+ *    reallocates them.  The library owns its internal workspaces (reduction
+ *    partials, device task lists, captured graphs) and frees them in
+ *    mlk_release().
+ *  - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *    Launch entry points enqueue work on it and return without synchronising;
+ *    device faults therefore surface at the caller's next synchronisation.
+ *  - Every argument is validated on the host before any HIP call, so all
+ *    MLK_ERR_* codes except MLK_ERR_HIP can be produced without a GPU.  On
+ *    error nothing is enqueued and mlk_last_error() returns a thread-local
+ *    message.
+ *  - Thread safety: calls from several host threads are safe; calls that
+ *    overlap on one device share its workspaces and are serialised inside
+ *    the library.
+ */
+#ifndef MLK_H
+#define MLK_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    MLK_OK = 0,
+    MLK_ERR_NULL = 1,        /* a required pointer is NULL */
+    MLK_ERR_SHAPE = 2,       /* a dimension is negative / zero where not allowed, or too large */
+    MLK_ERR_LAYOUT = 3,      /* leading dimension too small, or output aliases an input */
+    MLK_ERR_DTYPE = 4,       /* unsupported (input, output) dtype pair for the operation */
+    MLK_ERR_CONFIG = 5,      /* tile configuration not legal for the problem */
+    MLK_ERR_DB = 6,          /* tuning database unreadable / unwritable */
+    MLK_ERR_HIP = 7,         /* a HIP runtime call failed; message has the HIP error */
+    MLK_ERR_NOMEM = 8,       /* host or device allocation failed */
+    MLK_ERR_ARG = 9          /* any other invalid argument (flag, option, strategy) */
+} mlk_status;
+
+typedef enum {
+    MLK_F32 = 0,     /* IEEE binary32 */
+    MLK_BF16 = 1,    /* bfloat16 (binary32 with 16 fraction bits dropped) */
+    MLK_F8E4M3 = 2,  /* OCP 8-bit float E4M3 (bias 7, max 448, no inf) */
+    MLK_I8 = 3,      /* two's complement int8 */
+    MLK_I32 = 4      /* two's complement int32 */
+} mlk_dtype;
+
+/*
+ * Tile configuration: the search space of the paper's tiling + unrolling
+ * experiment (Sec. 4.3: parallel-loop tile sizes and an unroll factor),
+ * re-expressed for a workgroup-tiled MFMA kernel.
+ *   bm, bn     output tile per workgroup (rows of C x columns of C)
+ *   bk         contraction depth staged in LDS per main-loop step (elements);
+ *              the K-loop is unrolled over bk in steps of one MFMA.
+ *   wm, wn     waves (64 lanes) per workgroup along M and N
+ *   split_k    number of workgroups sharing one output tile along K (>= 1);
+ *              > 1 adds partial results with atomics (floating-point
+ *              results then depend on arrival order within rounding).
+ *   group_m    workgroup raster: tiles are visited in column bands of group_m
+ *              tile-rows (1 = row-major order)
+ *   xcd_remap  1: map consecutive tiles to the same XCD (shared L2)
+ * A zeroed struct or a NULL pointer means "choose": the tuning database
+ * entry for this problem if one was loaded, else a built-in heuristic.
+ */
+typedef struct {
+    int32_t bm, bn, bk;
+    int32_t wm, wn;
+    int32_t split_k;
+    int32_t group_m;
+    int32_t xcd_remap;
+} mlk_tile_config;
+
+/*
+ * C[M,N] (+)= A[M,K] * B[K,N]   -- linalg.matmul (Sec. 2.1, listing
+ * "linalg-matmul"; Sec. 1, listing "nelli_for_to_affine_for").
+ *
+ * Row-major operands: A[i,k] at A[i*lda + k], B[k,j] at B[k*ldb + j],
+ * C[i,j] at C[i*ldc + j]; lda >= K, ldb >= N, ldc >= N.
+ * Supported (in, out) pairs:
+ *   (MLK_F32,    MLK_F32)  fp32 products on MFMA, fp32 accumulation
+ *   (MLK_BF16,   MLK_F32)  bf16 products, fp32 accumulation
+ *   (MLK_F8E4M3, MLK_F32)  e4m3 products, fp32 accumulation, then the result
+ *                          is multiplied by (*scale_a) * (*scale_b)
+ *   (MLK_I8,     MLK_I32)  sign-extended int8 products, int32 sums that
+ *                          wrap modulo 2^32; bit-exact
+ * accumulate = 1: C += product (the linalg "outs" semantics);
+ * accumulate = 0: C = product (C is not read).
+ * scale_a / scale_b: device pointers to one float each (MLK_F8E4M3 only; NULL
+ * means 1.0), e.g. as written by mlk_quantize.
+ * M, N, K >= 0; M == 0 or N == 0 is a no-op; K == 0 leaves C (accumulate) or
+ * zeroes it (overwrite).  C must not overlap A or B.
+ * cfg: NULL or zeroed = choose (see mlk_tile_config); otherwise must satisfy
+ * mlk_config_legal or MLK_ERR_CONFIG is returned.
+ */
+mlk_status mlk_matmul(mlk_dtype in, mlk_dtype out, int64_t M, int64_t N, int64_t K,
+                      const void* A, int64_t lda, const void* B, int64_t ldb, void* C,
+                      int64_t ldc, const float* scale_a, const float* scale_b, int accumulate,
+                      const mlk_tile_config* cfg, void* stream);
+
+/*
+ * y[n,f,oh,ow] (+)= sum_{c,kh,kw} x[n,c,oh*sh-ph+kh, ow*sw-pw+kw] * w[f,c,kh,kw]
+ * -- linalg.conv_2d_nchw_fchw (Sec. 4.1, listing "2dnchwconv"), generalised
+ * to stride (sh, sw) and symmetric zero padding (ph, pw): taps that fall
+ * outside the image read zero; no filter flip (cross-correlation).
+ * Contiguous layouts: x (N,C,H,W), w (F,C,KH,KW), y (N,F,HO,WO) with
+ * HO = floor((H + 2ph - KH)/sh) + 1, WO likewise.
+ * Supported (in, out): (MLK_F32, MLK_F32) and (MLK_BF16, MLK_F32).
+ * Computed as an implicit GEMM: rows = F, columns = N*HO*WO,
+ * depth = C*KH*KW, with the im2col gather done inside the kernel's loads.
+ * All dims >= 1, strides >= 1, pads >= 0, HO, WO >= 1.
+ */
+mlk_status mlk_conv2d_nchw_fchw(mlk_dtype in, mlk_dtype out, int64_t N, int64_t C, int64_t H,
+                                int64_t W, int64_t F, int64_t KH, int64_t KW, int32_t sh,
+                                int32_t sw, int32_t ph, int32_t pw, const void* x, const void* w,
+                                void* y, int accumulate, const mlk_tile_config* cfg, void* stream);
+
+/*
+ * Quantise n fp32 values for the low-precision paths.
+ *   out = MLK_BF16:   q[i] = bf16 round-to-nearest-even of x[i]; scale unused
+ *                     (may be NULL).  NaN becomes a quiet NaN, overflow inf.
+ *   out = MLK_F8E4M3: amax = max |x[i]| (NaNs ignored); s = amax / 448
+ *                     rounded to fp32 (s = 1 when amax is 0 or not finite);
+ *                     q[i] = e4m3(RNE(x[i] / s)) with the quotient rounded to
+ *                     fp32 first and magnitudes beyond 448 saturated to 448;
+ *                     *scale = s (device float).
+ * x, q, scale device pointers; q has n elements of the output type.
+ * Per-tensor scaling as in the fp8 extension; the paper itself is fp32-only.
+ */
+mlk_status mlk_quantize(mlk_dtype out, int64_t n, const float* x, void* q, float* scale,
+                        void* stream);
+
+/* One GEMM of a batch: C = A * B (+ C) with the conventions of mlk_matmul. */
+typedef struct {
+    int64_t M, N, K;
+    const void* A;
+    int64_t lda;
+    const void* B;
+    int64_t ldb;
+    void* C;
+    int64_t ldc;
+} mlk_gemm_desc;
+
+#define MLK_BATCH_PERSISTENT 0x1u /* one persistent launch over all tiles of all GEMMs */
+#define MLK_BATCH_GRAPH 0x2u      /* capture the launch(es) in a hipGraph, cached per batch */
+
+/*
+ * Many independent matmuls of different shapes (the extension that batches
+ * uneven GEMMs into one launch).  descs: HOST array of `count` descriptors
+ * (device A/B/C pointers inside).  Supported (in, out): (MLK_BF16, MLK_F32),
+ * (MLK_F32, MLK_F32).  cfg: one tile configuration for every GEMM of the
+ * batch (NULL = choose); its split_k is ignored in persistent mode, where
+ * the library splits K per GEMM from its own cost estimate.
+ * flags: 0 = one launch per GEMM; MLK_BATCH_PERSISTENT = one launch whose
+ * workgroups walk a precomputed, load-balanced list of (GEMM, tile) tasks;
+ * MLK_BATCH_GRAPH = replay a hipGraph captured on the first call with the
+ * same descriptors, configuration and flags (the graph bakes in the device
+ * pointers, so a changed pointer is a new batch).
+ * Results equal per-GEMM mlk_matmul calls with the same configuration.
+ */
+mlk_status mlk_batched_matmul(mlk_dtype in, mlk_dtype out, int64_t count,
+                              const mlk_gemm_desc* descs, const mlk_tile_config* cfg,
+                              int accumulate, uint32_t flags, void* stream);
+
+/*
+ * Error statistics of a computed result against a double-precision
+ * reference, reduced on the GPU in FP64:
+ *   out[0] = sum (c_i - r_i)^2     out[1] = sum r_i^2
+ *   out[2] = max |c_i - r_i|       out[3] = max |c_i - r_i| / bound_i over
+ *                                           bound_i > 0 (0 if bound is NULL)
+ * c: n values of c_dtype (MLK_F32 or MLK_I32); r, bound: n doubles; out: 4
+ * doubles.  All device pointers.  The summation order is fixed (two-level
+ * tree), so results are reproducible run to run.
+ */
+mlk_status mlk_err_stats(mlk_dtype c_dtype, int64_t n, const void* c, const double* r,
+                         const double* bound, double* out, void* stream);
+
+/* ------------------------------------------------------------------------ */
+/* Tuning (Sec. 4.3: search over tile sizes and unroll factors)              */
+
+typedef enum {
+    MLK_OP_MATMUL = 0,
+    MLK_OP_CONV2D = 1,
+    MLK_OP_BATCHED = 2
+} mlk_op;
+
+typedef struct {
+    int32_t op;             /* mlk_op */
+    int32_t in, out;        /* mlk_dtype pair */
+    int32_t accumulate;
+    int64_t M, N, K;        /* MLK_OP_MATMUL */
+    int64_t n, c, h, w, f, kh, kw; /* MLK_OP_CONV2D */
+    int32_t sh, sw, ph, pw;
+    int64_t count;          /* MLK_OP_BATCHED: count host descriptors */
+    const mlk_gemm_desc* descs;
+} mlk_problem;
+
+typedef enum {
+    MLK_TUNE_EXHAUSTIVE = 0, /* measure every legal configuration */
+    MLK_TUNE_RANDOM = 1,     /* measure a uniform random sample of the budget */
+    MLK_TUNE_MODEL = 2       /* rank all by the cost model, measure the top budget */
+} mlk_tune_strategy;
+
+typedef struct mlk_cost_model mlk_cost_model; /* opaque, see mlk_model_* */
+
+typedef struct {
+    int32_t strategy;       /* mlk_tune_strategy */
+    double budget_frac;     /* RANDOM / MODEL: measure ceil(budget_frac * n_legal) configs */
+    int32_t reps;           /* timed runs per configuration (median taken); 0 = 20 */
+    int32_t warmup;         /* untimed runs first; 0 = 3 */
+    uint64_t seed;          /* RANDOM sampling seed; also seeds the scratch inputs */
+    const char* db_path;    /* NULL = no database; else JSON-lines file, appended */
+    int32_t use_db;         /* 1: if the database holds this problem, return it unmeasured */
+    mlk_cost_model* model;  /* MLK_TUNE_MODEL: the trained model (else ignored) */
+    double* times_us;       /* optional HOST array [mlk_config_count]: median time per
+                               legal config in enumeration order, -1 if not measured */
+    int32_t fake_timer;     /* 1: replace GPU timing by a deterministic analytic cost
+                               (host-only; for testing the search logic) */
+} mlk_tune_opts;
+
+typedef struct {
+    int32_t n_legal;        /* size of the legal configuration space */
+    int32_t n_measured;     /* configurations timed in this call */
+    int32_t best_index;     /* enumeration index of the returned config */
+    int32_t from_db;        /* 1 if answered from the database */
+    double best_us;         /* median time of the returned config */
+} mlk_tune_report;
+
+/*
+ * Search the legal tile configurations of problem p and return the fastest
+ * found in *best.  Scratch inputs are allocated by the library (seeded, the
+ * caller's buffers are never touched; for MLK_OP_BATCHED the descriptors'
+ * shapes are used, not their pointers).  Synchronises the device.
+ * A configuration within 1% of the fastest counts as tied; ties go to the
+ * smaller LDS footprint, then the lower enumeration index.
+ */
+mlk_status mlk_tune(const mlk_problem* p, const mlk_tune_opts* o, mlk_tile_config* best,
+                    mlk_tune_report* rep);
+
+/* MLK_OK if cfg is legal for p (pure host check, no GPU), else MLK_ERR_CONFIG
+ * with the reason in mlk_last_error(). */
+mlk_status mlk_config_legal(const mlk_problem* p, const mlk_tile_config* cfg);
+
+/* Number of legal configurations for p (>= 1 for a valid problem; < 0 on
+ * an invalid problem), and the i-th in enumeration order. */
+int32_t mlk_config_count(const mlk_problem* p);
+mlk_status mlk_config_get(const mlk_problem* p, int32_t i, mlk_tile_config* cfg);
+
+/* Record cfg as the tuned choice for p in the in-memory table consulted when
+ * a launch gets cfg == NULL (mlk_tune does this for its result). */
+mlk_status mlk_config_set_default(const mlk_problem* p, const mlk_tile_config* cfg);
+
+/* ------------------------------------------------------------------------ */
+/* Learned cost model: an MLP  features(problem, config) -> log(time in us),
+ * trained on the GPU by the library's own forward / backward / Adam kernels. */
+
+/* Feature vector length and the features of (p, cfg) (host computation). */
+int32_t mlk_model_feature_count(void);
+mlk_status mlk_model_features(const mlk_problem* p, const mlk_tile_config* cfg, float* out);
+
+/* hidden: width of both hidden layers (1..256).  Weights are initialised on
+ * the host from `seed` and uploaded; the model owns device buffers. */
+mlk_status mlk_model_create(int32_t hidden, uint64_t seed, mlk_cost_model** out);
+void mlk_model_destroy(mlk_cost_model* m);
+/* Add one training sample (a measured median time, microseconds > 0). */
+mlk_status mlk_model_add_sample(mlk_cost_model* m, const mlk_problem* p,
+                                const mlk_tile_config* cfg, double time_us);
+int64_t mlk_model_sample_count(const mlk_cost_model* m);
+/* Normalise features over the current samples, then run `epochs` passes of
+ * minibatch Adam (batch rows, learning rate lr) on the GPU.  *final_loss
+ * (may be NULL) receives the last epoch's mean squared error in log space. */
+mlk_status mlk_model_train(mlk_cost_model* m, int32_t epochs, int32_t batch, float lr,
+                           float* final_loss);
+/* Predicted time (microseconds) of n configurations of p (host arrays). */
+mlk_status mlk_model_predict(mlk_cost_model* m, const mlk_problem* p,
+                             const mlk_tile_config* cfgs, int32_t n, float* pred_us);
+
+/*
+ * The cost model's network kernels, exposed so their arithmetic can be
+ * checked: layers D0 -> H1 -> H2 -> 1, ReLU after both hidden layers, one
+ * flat fp32 parameter vector laid out W1 (D0 x H1 row-major), b1 (H1),
+ * W2 (H1 x H2), b2 (H2), W3 (H2), b3 (1).  All pointers device.
+ *   mlk_mlp_forward:   y[B] = net(X[B x D0])
+ *   mlk_mlp_loss_grad: loss[0] = mean_r (net(X_r) - t_r)^2, grad = d loss / d params
+ *   mlk_adam_step:     Adam (Kingma & Ba) with bias correction at step t >= 1
+ */
+mlk_status mlk_mlp_forward(int64_t B, int64_t D0, int64_t H1, int64_t H2, const float* params,
+                           const float* X, float* y, void* stream);
+mlk_status mlk_mlp_loss_grad(int64_t B, int64_t D0, int64_t H1, int64_t H2,
+                             const float* params, const float* X, const float* t, float* grad,
+                             float* loss, void* stream);
+mlk_status mlk_adam_step(int64_t n, float* params, const float* grad, float* m, float* v,
+                         float lr, float beta1, float beta2, float eps, int64_t t, void* stream);
+
+/* ------------------------------------------------------------------------ */
+
+const char* mlk_status_str(mlk_status s);
+/* Message of the last failing call on this host thread ("" if none). */
+const char* mlk_last_error(void);
+/* Library version string. */
+const char* mlk_version(void);
+/* Free every library-owned workspace, cached graph and table. */
+void mlk_release(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MLK_H */

@@ -1,0 +1,293 @@
+"""MI355X (gfx950) dense kernels for the computations of arXiv 2307.16080 (nelli).
+
+Thin Python binding over the C ABI of ``libmlk.so`` (``include/mlk.h``): it
+marshals torch tensors (device memory and streams only) into plain pointers
+and sizes.  Every step of every operation runs in the library's HIP kernels;
+there is no CPU or PyTorch fallback.
+
+    matmul(A, B, C)                 C (+)= A @ B          (linalg.matmul)
+    conv2d_nchw_fchw(x, w, y, ...)  y (+)= conv(x, w)      (linalg.conv_2d_nchw_fchw)
+    quantize(x, "bf16" | "e4m3")    per-tensor quantisation for the low-precision paths
+    batched_matmul([...])           many uneven GEMMs, optionally one persistent launch / graph
+    err_stats(c, r, bound)          FP64 error reduction against a double reference
+    tune(problem, ...)              tile-configuration search (exhaustive / random / model)
+    CostModel                       the learned cost model (MLP trained on the GPU)
+"""
+import ctypes
+
+import torch
+
+from . import _lib as L
+from ._lib import (MLK_BATCH_GRAPH, MLK_BATCH_PERSISTENT, MLK_BF16, MLK_F8E4M3, MLK_F32, MLK_I8,
+                   MLK_I32, MLK_OP_BATCHED, MLK_OP_CONV2D, MLK_OP_MATMUL, MLK_TUNE_EXHAUSTIVE,
+                   MLK_TUNE_MODEL, MLK_TUNE_RANDOM, GemmDesc, MlkError, Problem, TileConfig,
+                   TuneOpts, TuneReport)
+
+__all__ = ["matmul", "conv2d_nchw_fchw", "quantize", "batched_matmul", "err_stats", "tune",
+           "config_count", "configs", "config_legal", "set_default_config", "CostModel",
+           "mlp_forward", "mlp_loss_grad", "adam_step", "release", "version", "TileConfig",
+           "Problem", "MlkError", "matmul_problem", "conv_problem", "batched_problem"]
+
+_TORCH_TO_MLK = {
+    torch.float32: MLK_F32,
+    torch.bfloat16: MLK_BF16,
+    torch.float8_e4m3fn: MLK_F8E4M3,
+    torch.int8: MLK_I8,
+    torch.int32: MLK_I32,
+}
+
+
+def _dt(t: torch.Tensor) -> int:
+    try:
+        return _TORCH_TO_MLK[t.dtype]
+    except KeyError:
+        raise MlkError(4, f"unsupported tensor dtype {t.dtype}") from None
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream=None):
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _cfg(cfg):
+    if cfg is None:
+        return None
+    if isinstance(cfg, TileConfig):
+        return ctypes.byref(cfg)
+    return ctypes.byref(TileConfig(*cfg))
+
+
+def _row_major_ld(t: torch.Tensor) -> int:
+    if t.dim() != 2 or t.stride(1) != 1:
+        raise MlkError(3, "expected a 2-D tensor with unit column stride (row-major)")
+    return t.stride(0) if t.size(0) > 1 else max(t.size(1), 1)
+
+
+def version() -> str:
+    return L.lib().mlk_version().decode()
+
+
+def release() -> None:
+    L.lib().mlk_release()
+
+
+# --------------------------------------------------------------------------- matmul / conv
+
+def matmul(A, B, C, accumulate: bool = True, cfg=None, scale_a=None, scale_b=None, stream=None):
+    """C (+)= A @ B.  A: (M, K), B: (K, N), C: (M, N), row-major CUDA tensors.
+
+    (float32, float32), (bfloat16, float32), (float8_e4m3fn, float32) with optional
+    device scale tensors, (int8, int32)."""
+    M, K = A.shape
+    K2, N = B.shape
+    if K2 != K or tuple(C.shape) != (M, N):
+        raise MlkError(2, f"shape mismatch: A {tuple(A.shape)}, B {tuple(B.shape)}, C {tuple(C.shape)}")
+    L.check(L.lib().mlk_matmul(_dt(A), _dt(C), M, N, K, _ptr(A), _row_major_ld(A), _ptr(B),
+                               _row_major_ld(B), _ptr(C), _row_major_ld(C), _ptr(scale_a),
+                               _ptr(scale_b), int(bool(accumulate)), _cfg(cfg), _stream(stream)))
+    return C
+
+
+def conv2d_nchw_fchw(x, w, y, stride=(1, 1), pad=(0, 0), accumulate: bool = True, cfg=None,
+                     stream=None):
+    """y (+)= conv(x, w): x (N,C,H,W), w (F,C,KH,KW), y (N,F,HO,WO), contiguous."""
+    for t in (x, w, y):
+        if not t.is_contiguous():
+            raise MlkError(3, "conv2d tensors must be contiguous")
+    N, C, H, W = x.shape
+    F, C2, KH, KW = w.shape
+    if C2 != C:
+        raise MlkError(2, "channel mismatch")
+    sh, sw = stride
+    ph, pw = pad
+    L.check(L.lib().mlk_conv2d_nchw_fchw(_dt(x), _dt(y), N, C, H, W, F, KH, KW, sh, sw, ph, pw,
+                                         _ptr(x), _ptr(w), _ptr(y), int(bool(accumulate)),
+                                         _cfg(cfg), _stream(stream)))
+    return y
+
+
+def conv_out_hw(H, W, KH, KW, stride=(1, 1), pad=(0, 0)):
+    return ((H + 2 * pad[0] - KH) // stride[0] + 1, (W + 2 * pad[1] - KW) // stride[1] + 1)
+
+
+def quantize(x: torch.Tensor, fmt: str, q=None, scale=None, stream=None):
+    """Quantise a float32 CUDA tensor.  fmt "bf16" -> (q, None); "e4m3" -> (q, scale)
+    with scale a one-element float32 device tensor (amax / 448)."""
+    if x.dtype != torch.float32 or not x.is_contiguous():
+        raise MlkError(4, "quantize expects a contiguous float32 tensor")
+    if fmt == "bf16":
+        q = torch.empty(x.shape, dtype=torch.bfloat16, device=x.device) if q is None else q
+        L.check(L.lib().mlk_quantize(MLK_BF16, x.numel(), _ptr(x), _ptr(q), None, _stream(stream)))
+        return q, None
+    if fmt == "e4m3":
+        q = torch.empty(x.shape, dtype=torch.float8_e4m3fn, device=x.device) if q is None else q
+        scale = torch.empty(1, dtype=torch.float32, device=x.device) if scale is None else scale
+        L.check(L.lib().mlk_quantize(MLK_F8E4M3, x.numel(), _ptr(x), _ptr(q), _ptr(scale),
+                                     _stream(stream)))
+        return q, scale
+    raise MlkError(4, f"unknown format {fmt!r}")
+
+
+def batched_matmul(problems, accumulate: bool = True, cfg=None, persistent: bool = False,
+                   graph: bool = False, stream=None):
+    """problems: list of (A, B, C) CUDA tensors (same dtypes across the list)."""
+    descs = (GemmDesc * len(problems))()
+    for i, (A, B, C) in enumerate(problems):
+        M, K = A.shape
+        N = B.shape[1]
+        descs[i] = GemmDesc(M, N, K, A.data_ptr(), _row_major_ld(A), B.data_ptr(),
+                            _row_major_ld(B), C.data_ptr(), _row_major_ld(C))
+    A0, _, C0 = problems[0]
+    flags = (MLK_BATCH_PERSISTENT if persistent else 0) | (MLK_BATCH_GRAPH if graph else 0)
+    L.check(L.lib().mlk_batched_matmul(_dt(A0), _dt(C0), len(problems), descs, _cfg(cfg),
+                                       int(bool(accumulate)), flags, _stream(stream)))
+
+
+def err_stats(c: torch.Tensor, r: torch.Tensor, bound=None, stream=None):
+    """(sum (c-r)^2, sum r^2, max|c-r|, max |c-r|/bound) reduced on the GPU in FP64."""
+    out = torch.empty(4, dtype=torch.float64, device=c.device)
+    if r.dtype != torch.float64 or (bound is not None and bound.dtype != torch.float64):
+        raise MlkError(4, "reference and bound must be float64")
+    L.check(L.lib().mlk_err_stats(_dt(c), c.numel(), _ptr(c), _ptr(r), _ptr(bound), _ptr(out),
+                                  _stream(stream)))
+    return out
+
+
+# --------------------------------------------------------------------------- tuning
+
+def matmul_problem(M, N, K, in_dtype=MLK_BF16, out_dtype=MLK_F32, accumulate=True):
+    p = Problem()
+    p.op, p.in_, p.out, p.accumulate = MLK_OP_MATMUL, in_dtype, out_dtype, int(bool(accumulate))
+    p.M, p.N, p.K = M, N, K
+    return p
+
+
+def conv_problem(n, c, h, w, f, kh, kw, stride=1, pad=0, in_dtype=MLK_BF16, out_dtype=MLK_F32,
+                 accumulate=True):
+    p = Problem()
+    p.op, p.in_, p.out, p.accumulate = MLK_OP_CONV2D, in_dtype, out_dtype, int(bool(accumulate))
+    p.n, p.c, p.h, p.w, p.f, p.kh, p.kw = n, c, h, w, f, kh, kw
+    p.sh = p.sw = stride
+    p.ph = p.pw = pad
+    return p
+
+
+def batched_problem(shapes, in_dtype=MLK_BF16, out_dtype=MLK_F32, accumulate=True):
+    """shapes: list of (M, N, K).  The descriptor array is kept alive on the problem."""
+    descs = (GemmDesc * len(shapes))()
+    for i, (M, N, K) in enumerate(shapes):
+        descs[i] = GemmDesc(M, N, K, None, max(K, 1), None, max(N, 1), None, max(N, 1))
+    p = Problem()
+    p.op, p.in_, p.out, p.accumulate = MLK_OP_BATCHED, in_dtype, out_dtype, int(bool(accumulate))
+    p.count = len(shapes)
+    p.descs = ctypes.cast(descs, ctypes.POINTER(GemmDesc))
+    p._keep = descs
+    return p
+
+
+def config_count(problem) -> int:
+    n = L.lib().mlk_config_count(ctypes.byref(problem))
+    if n < 0:
+        L.check(L.lib().mlk_config_legal(ctypes.byref(problem), ctypes.byref(TileConfig())))
+    return n
+
+
+def configs(problem):
+    out = []
+    for i in range(config_count(problem)):
+        c = TileConfig()
+        L.check(L.lib().mlk_config_get(ctypes.byref(problem), i, ctypes.byref(c)))
+        out.append(c)
+    return out
+
+
+def config_legal(problem, cfg) -> bool:
+    return L.lib().mlk_config_legal(ctypes.byref(problem), _cfg(cfg)) == 0
+
+
+def set_default_config(problem, cfg):
+    L.check(L.lib().mlk_config_set_default(ctypes.byref(problem), _cfg(cfg)))
+
+
+def tune(problem, strategy=MLK_TUNE_EXHAUSTIVE, budget_frac=1.0, reps=0, warmup=0, seed=0,
+         db_path=None, use_db=False, model=None, want_times=False, fake_timer=False):
+    """Returns (best TileConfig, TuneReport, times_us list or None)."""
+    n = config_count(problem)
+    times = (ctypes.c_double * max(n, 1))() if want_times else None
+    o = TuneOpts()
+    o.strategy, o.budget_frac, o.reps, o.warmup, o.seed = strategy, budget_frac, reps, warmup, seed
+    o.db_path = db_path.encode() if db_path else None
+    o.use_db = int(bool(use_db))
+    o.model = model.handle if model is not None else None
+    o.times_us = ctypes.cast(times, ctypes.POINTER(ctypes.c_double)) if times is not None else None
+    o.fake_timer = int(bool(fake_timer))
+    best, rep = TileConfig(), TuneReport()
+    L.check(L.lib().mlk_tune(ctypes.byref(problem), ctypes.byref(o), ctypes.byref(best),
+                             ctypes.byref(rep)))
+    return best, rep, (list(times)[:n] if times is not None else None)
+
+
+class CostModel:
+    """The learned cost model (owns device buffers inside the library)."""
+
+    def __init__(self, hidden=64, seed=0):
+        h = ctypes.c_void_p()
+        L.check(L.lib().mlk_model_create(hidden, seed, ctypes.byref(h)))
+        self.handle = h.value
+
+    def __del__(self):
+        if getattr(self, "handle", None) and L._lib is not None:
+            L.lib().mlk_model_destroy(self.handle)
+            self.handle = None
+
+    def add_sample(self, problem, cfg, time_us):
+        L.check(L.lib().mlk_model_add_sample(self.handle, ctypes.byref(problem), _cfg(cfg), time_us))
+
+    def sample_count(self):
+        return L.lib().mlk_model_sample_count(self.handle)
+
+    def train(self, epochs=200, batch=256, lr=1e-3):
+        loss = ctypes.c_float()
+        L.check(L.lib().mlk_model_train(self.handle, epochs, batch, lr, ctypes.byref(loss)))
+        return loss.value
+
+    def predict(self, problem, cfgs):
+        arr = (TileConfig * len(cfgs))(*cfgs)
+        out = (ctypes.c_float * len(cfgs))()
+        L.check(L.lib().mlk_model_predict(self.handle, ctypes.byref(problem), arr, len(cfgs), out))
+        return list(out)
+
+
+def features(problem, cfg):
+    n = L.lib().mlk_model_feature_count()
+    out = (ctypes.c_float * n)()
+    L.check(L.lib().mlk_model_features(ctypes.byref(problem), _cfg(cfg), out))
+    return list(out)
+
+
+# --------------------------------------------------------------------------- cost-model kernels
+
+def mlp_forward(params, X, H1, H2, stream=None):
+    B, D0 = X.shape
+    y = torch.empty(B, dtype=torch.float32, device=X.device)
+    L.check(L.lib().mlk_mlp_forward(B, D0, H1, H2, _ptr(params), _ptr(X), _ptr(y), _stream(stream)))
+    return y
+
+
+def mlp_loss_grad(params, X, t, H1, H2, stream=None):
+    B, D0 = X.shape
+    g = torch.empty_like(params)
+    loss = torch.empty(1, dtype=torch.float32, device=X.device)
+    L.check(L.lib().mlk_mlp_loss_grad(B, D0, H1, H2, _ptr(params), _ptr(X), _ptr(t), _ptr(g),
+                                      _ptr(loss), _stream(stream)))
+    return loss, g
+
+
+def adam_step(params, grad, m, v, lr, beta1, beta2, eps, t, stream=None):
+    L.check(L.lib().mlk_adam_step(params.numel(), _ptr(params), _ptr(grad), _ptr(m), _ptr(v), lr,
+                                  beta1, beta2, eps, t, _stream(stream)))

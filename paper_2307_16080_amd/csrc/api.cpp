@@ -1,0 +1,613 @@
+// api.cpp -- the C ABI (include/mlk.h): validation, configuration space,
+// dispatch to the compiled tile kernels, batched / persistent / graph
+// launches, and the elementwise entry points.
+//
+// Every argument check runs on the host before the first HIP call, so each
+// MLK_ERR_* except MLK_ERR_HIP can be produced without a GPU.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <queue>
+#include <string>
+#include <unordered_map>
+#include <vector>
+
+#include "internal.hpp"
+
+namespace mlk {
+
+// ------------------------------------------------------------------ errors
+
+static thread_local std::string t_err;
+
+mlk_status fail(mlk_status s, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    t_err = buf;
+    return s;
+}
+
+void clear_error() { t_err.clear(); }
+
+mlk_status hip_fail(hipError_t e, const char* what) {
+    return fail(MLK_ERR_HIP, "%s: %s (%d)", what, hipGetErrorString(e), (int)e);
+}
+
+// ------------------------------------------------------------------ device facts
+
+int device_cus() {
+    static std::mutex mu;
+    static std::map<int, int> cache;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 256;
+    std::lock_guard<std::mutex> g(mu);
+    auto it = cache.find(dev);
+    if (it != cache.end()) return it->second;
+    int v = 0;
+    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || v <= 0)
+        v = 256;
+    cache[dev] = v;
+    return v;
+}
+
+// ------------------------------------------------------------------ registry
+
+const std::vector<const KernelEntry*>& registry() {
+    static std::vector<const KernelEntry*> all = [] {
+        std::vector<const KernelEntry*> v;
+        const KernelEntry* (*tables[])(int*) = {kernels_f32, kernels_bf16, kernels_i8, kernels_f8,
+                                                kernels_conv};
+        for (auto t : tables) {
+            int n = 0;
+            const KernelEntry* e = t(&n);
+            for (int i = 0; i < n; ++i) v.push_back(e + i);
+        }
+        return v;
+    }();
+    return all;
+}
+
+const KernelEntry* find_kernel(int dt, int conv, const mlk_tile_config& c) {
+    for (const KernelEntry* e : registry())
+        if (e->dt == dt && e->conv == conv && e->bm == c.bm && e->bn == c.bn && e->bk == c.bk &&
+            e->wm == c.wm && e->wn == c.wn)
+            return e;
+    return nullptr;
+}
+
+int dt_of(mlk_dtype in, mlk_dtype out, int conv, bool* ok) {
+    *ok = true;
+    if (in == MLK_F32 && out == MLK_F32) return DT_F32;
+    if (in == MLK_BF16 && out == MLK_F32) return DT_BF16;
+    if (!conv && in == MLK_F8E4M3 && out == MLK_F32) return DT_F8;
+    if (!conv && in == MLK_I8 && out == MLK_I32) return DT_I8;
+    *ok = false;
+    return -1;
+}
+
+static int esize_in(int dt) { return dt == DT_F32 ? 4 : dt == DT_BF16 ? 2 : 1; }
+
+int64_t conv_out(int64_t in, int64_t k, int64_t stride, int64_t pad) {
+    const int64_t span = in + 2 * pad - k;
+    if (span < 0 || stride <= 0) return 0;
+    return span / stride + 1;
+}
+
+// largest extent any one launch accepts (tile coordinates are int32)
+static const int64_t kMaxDim = (int64_t)1 << 31;
+
+static mlk_status check_conv_dims(int64_t n, int64_t c, int64_t h, int64_t w, int64_t f,
+                                  int64_t kh, int64_t kw, int sh, int sw, int ph, int pw,
+                                  int64_t* ho, int64_t* wo) {
+    if (n < 1 || c < 1 || h < 1 || w < 1 || f < 1 || kh < 1 || kw < 1)
+        return fail(MLK_ERR_SHAPE, "conv2d: every dimension must be >= 1");
+    if (sh < 1 || sw < 1) return fail(MLK_ERR_SHAPE, "conv2d: strides must be >= 1");
+    if (ph < 0 || pw < 0) return fail(MLK_ERR_SHAPE, "conv2d: padding must be >= 0");
+    if (n > kMaxDim || c > kMaxDim || h > kMaxDim || w > kMaxDim || f > kMaxDim)
+        return fail(MLK_ERR_SHAPE, "conv2d: dimension too large");
+    *ho = conv_out(h, kh, sh, ph);
+    *wo = conv_out(w, kw, sw, pw);
+    if (*ho < 1 || *wo < 1)
+        return fail(MLK_ERR_SHAPE, "conv2d: the filter does not fit the padded image");
+    if (n * (*ho) * (*wo) > kMaxDim || c * kh * kw > kMaxDim || c * h * w > kMaxDim)
+        return fail(MLK_ERR_SHAPE, "conv2d: problem too large for one launch");
+    return MLK_OK;
+}
+
+mlk_status shape_of_problem(const mlk_problem* p, Shape* s) {
+    if (!p) return fail(MLK_ERR_NULL, "problem is NULL");
+    bool ok = false;
+    s->conv = p->op == MLK_OP_CONV2D;
+    s->accumulate = p->accumulate ? 1 : 0;
+    if (p->op != MLK_OP_MATMUL && p->op != MLK_OP_CONV2D && p->op != MLK_OP_BATCHED)
+        return fail(MLK_ERR_ARG, "unknown op %d", p->op);
+    s->dt = dt_of((mlk_dtype)p->in, (mlk_dtype)p->out, s->conv, &ok);
+    if (!ok) return fail(MLK_ERR_DTYPE, "unsupported dtype pair (%d, %d) for op %d", p->in, p->out, p->op);
+    if (p->op == MLK_OP_MATMUL) {
+        if (p->M < 0 || p->N < 0 || p->K < 0) return fail(MLK_ERR_SHAPE, "negative matmul dimension");
+        if (p->M > kMaxDim || p->N > kMaxDim || p->K > kMaxDim)
+            return fail(MLK_ERR_SHAPE, "matmul dimension too large");
+        s->M = p->M;
+        s->N = p->N;
+        s->K = p->K;
+    } else if (p->op == MLK_OP_CONV2D) {
+        int64_t ho, wo;
+        mlk_status st = check_conv_dims(p->n, p->c, p->h, p->w, p->f, p->kh, p->kw, p->sh, p->sw,
+                                        p->ph, p->pw, &ho, &wo);
+        if (st != MLK_OK) return st;
+        s->M = p->f;
+        s->N = p->n * ho * wo;
+        s->K = p->c * p->kh * p->kw;
+    } else {
+        if (p->count < 1) return fail(MLK_ERR_SHAPE, "batched: count must be >= 1");
+        if (!p->descs) return fail(MLK_ERR_NULL, "batched: descs is NULL");
+        if (s->dt != DT_BF16 && s->dt != DT_F32)
+            return fail(MLK_ERR_DTYPE, "batched: only bf16 and f32 inputs are supported");
+        int64_t mm = 0, nn = 0, kk = 0;
+        for (int64_t i = 0; i < p->count; ++i) {
+            const mlk_gemm_desc& d = p->descs[i];
+            if (d.M < 0 || d.N < 0 || d.K < 0) return fail(MLK_ERR_SHAPE, "batched: negative dimension in desc %lld", (long long)i);
+            if (d.M > kMaxDim || d.N > kMaxDim || d.K > kMaxDim)
+                return fail(MLK_ERR_SHAPE, "batched: dimension too large in desc %lld", (long long)i);
+            mm = std::max(mm, d.M);
+            nn = std::max(nn, d.N);
+            kk = std::max(kk, d.K);
+        }
+        s->M = mm;
+        s->N = nn;
+        s->K = kk;
+    }
+    return MLK_OK;
+}
+
+static int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+mlk_status check_config(const Shape& s, int op, const mlk_tile_config& c) {
+    const KernelEntry* e = find_kernel(s.dt, s.conv, c);
+    if (!e)
+        return fail(MLK_ERR_CONFIG, "no compiled kernel for tile %dx%dx%d waves %dx%d (dtype %d%s)",
+                    c.bm, c.bn, c.bk, c.wm, c.wn, s.dt, s.conv ? ", conv" : "");
+    if (c.split_k < 1 || c.split_k > 64) return fail(MLK_ERR_CONFIG, "split_k must be in [1, 64]");
+    const int64_t stages = cdiv(std::max<int64_t>(s.K, 1), c.bk);
+    if (c.split_k > 1 && c.split_k > stages)
+        return fail(MLK_ERR_CONFIG, "split_k %d exceeds the %lld K stages", c.split_k, (long long)stages);
+    if (c.group_m < 0 || c.group_m > 64) return fail(MLK_ERR_CONFIG, "group_m must be in [0, 64]");
+    if (c.xcd_remap != 0 && c.xcd_remap != 1) return fail(MLK_ERR_CONFIG, "xcd_remap must be 0 or 1");
+    const int64_t tiles = cdiv(s.M, c.bm) * cdiv(s.N, c.bn) * c.split_k;
+    if (tiles > ((int64_t)1 << 31) - 1) return fail(MLK_ERR_CONFIG, "too many workgroups");
+    return MLK_OK;
+}
+
+std::vector<mlk_tile_config> enumerate_configs(const mlk_problem* p, const Shape& s) {
+    std::vector<mlk_tile_config> out;
+    const bool batched = p->op == MLK_OP_BATCHED;
+    for (const KernelEntry* e : registry()) {
+        if (e->dt != s.dt || e->conv != s.conv) continue;
+        if (batched && !e->persist) continue;
+        // a tile at least twice the problem in a dimension only adds padding
+        if (e->bm > 32 && e->bm >= 2 * s.M) continue;
+        if (e->bn > 32 && e->bn >= 2 * s.N) continue;
+        const int64_t stages = cdiv(std::max<int64_t>(s.K, 1), e->bk);
+        const int64_t tiles = cdiv(std::max<int64_t>(s.M, 1), e->bm) * cdiv(std::max<int64_t>(s.N, 1), e->bn);
+        const int64_t tm = cdiv(std::max<int64_t>(s.M, 1), e->bm);
+        for (int sk : {1, 2, 4, 8}) {
+            if (batched && sk > 1) break;
+            if (sk > 1 && stages < 2 * sk) break;
+            for (int gm : {1, 8}) {
+                if (gm == 8 && (batched || tm < 16)) continue;
+                for (int xcd : {0, 1}) {
+                    const int64_t nblk = tiles * sk;
+                    if (xcd == 1 && (batched || nblk < 64 || nblk % 8 != 0)) continue;
+                    mlk_tile_config c{e->bm, e->bn, e->bk, e->wm, e->wn, sk, gm, xcd};
+                    out.push_back(c);
+                }
+            }
+        }
+    }
+    return out;
+}
+
+mlk_tile_config heuristic_config(const Shape& s, int op) {
+    const int cus = device_cus();
+    // biggest tile (by area, then by fewer waves) that still gives >= one tile per CU
+    const KernelEntry* best = nullptr;
+    const KernelEntry* smallest = nullptr;
+    for (const KernelEntry* e : registry()) {
+        if (e->dt != s.dt || e->conv != s.conv) continue;
+        if (op == MLK_OP_BATCHED && !e->persist) continue;
+        if (!smallest || e->bm * e->bn < smallest->bm * smallest->bn ||
+            (e->bm * e->bn == smallest->bm * smallest->bn && e->bk > smallest->bk))
+            smallest = e;
+        const int64_t tiles = cdiv(std::max<int64_t>(s.M, 1), e->bm) * cdiv(std::max<int64_t>(s.N, 1), e->bn);
+        if (tiles < cus) continue;
+        if (e->bm * e->bn > 128 * 256) continue;  // the largest tiles only win when tuned
+        if (!best || e->bm * e->bn > best->bm * best->bn ||
+            (e->bm * e->bn == best->bm * best->bn && e->bk > best->bk))
+            best = e;
+    }
+    const KernelEntry* e = best ? best : smallest;
+    mlk_tile_config c{e->bm, e->bn, e->bk, e->wm, e->wn, 1, 1, 0};
+    if (!best && op != MLK_OP_BATCHED) {
+        // too few tiles: split K while each split keeps >= 4 stages
+        const int64_t tiles = cdiv(std::max<int64_t>(s.M, 1), e->bm) * cdiv(std::max<int64_t>(s.N, 1), e->bn);
+        const int64_t stages = cdiv(std::max<int64_t>(s.K, 1), e->bk);
+        while (c.split_k < 8 && tiles * c.split_k * 2 <= cus && stages >= 4 * 2 * c.split_k) c.split_k *= 2;
+    }
+    return c;
+}
+
+std::string problem_key(const mlk_problem* p) {
+    char buf[256];
+    if (p->op == MLK_OP_MATMUL) {
+        snprintf(buf, sizeof buf, "matmul;in=%d;out=%d;acc=%d;M=%lld;N=%lld;K=%lld", p->in, p->out,
+                 p->accumulate ? 1 : 0, (long long)p->M, (long long)p->N, (long long)p->K);
+        return buf;
+    }
+    if (p->op == MLK_OP_CONV2D) {
+        snprintf(buf, sizeof buf,
+                 "conv2d;in=%d;out=%d;acc=%d;n=%lld;c=%lld;h=%lld;w=%lld;f=%lld;kh=%lld;kw=%lld;s=%d,%d;p=%d,%d",
+                 p->in, p->out, p->accumulate ? 1 : 0, (long long)p->n, (long long)p->c,
+                 (long long)p->h, (long long)p->w, (long long)p->f, (long long)p->kh,
+                 (long long)p->kw, p->sh, p->sw, p->ph, p->pw);
+        return buf;
+    }
+    // batched: FNV-1a over the shape list
+    uint64_t h = 1469598103934665603ull;
+    for (int64_t i = 0; i < p->count; ++i) {
+        const int64_t v[3] = {p->descs[i].M, p->descs[i].N, p->descs[i].K};
+        const unsigned char* b = (const unsigned char*)v;
+        for (size_t j = 0; j < sizeof v; ++j) h = (h ^ b[j]) * 1099511628211ull;
+    }
+    snprintf(buf, sizeof buf, "batched;in=%d;out=%d;acc=%d;count=%lld;shapes=%016llx", p->in, p->out,
+             p->accumulate ? 1 : 0, (long long)p->count, (unsigned long long)h);
+    return buf;
+}
+
+static std::mutex g_def_mu;
+static std::unordered_map<std::string, mlk_tile_config> g_defaults;
+
+bool lookup_default(const std::string& key, mlk_tile_config* c) {
+    std::lock_guard<std::mutex> g(g_def_mu);
+    auto it = g_defaults.find(key);
+    if (it == g_defaults.end()) return false;
+    *c = it->second;
+    return true;
+}
+
+void store_default(const std::string& key, const mlk_tile_config& c) {
+    std::lock_guard<std::mutex> g(g_def_mu);
+    g_defaults[key] = c;
+}
+
+static bool cfg_is_zero(const mlk_tile_config* c) {
+    return !c || (c->bm == 0 && c->bn == 0 && c->bk == 0 && c->wm == 0 && c->wn == 0);
+}
+
+// resolve the configuration of a launch (explicit / tuned default / heuristic)
+static mlk_status resolve(const mlk_problem& p, const Shape& s, const mlk_tile_config* cfg,
+                          mlk_tile_config* out) {
+    if (!cfg_is_zero(cfg)) {
+        *out = *cfg;
+        if (out->group_m == 0) out->group_m = 1;
+        if (out->split_k == 0) out->split_k = 1;
+        return check_config(s, p.op, *out);
+    }
+    if (lookup_default(problem_key(&p), out)) return MLK_OK;
+    *out = heuristic_config(s, p.op);
+    return MLK_OK;
+}
+
+// ------------------------------------------------------------------ launches
+
+static GemmArgs base_args(const Shape& s, const mlk_tile_config& cfg) {
+    GemmArgs g;
+    memset(&g, 0, sizeof g);
+    g.M = s.M;
+    g.N = s.N;
+    g.K = s.K;
+    g.accumulate = s.accumulate;
+    g.split_k = cfg.split_k;
+    g.atomic = cfg.split_k > 1 ? 1 : 0;
+    g.tiles_m = (int32_t)cdiv(s.M, cfg.bm);
+    g.tiles_n = (int32_t)cdiv(s.N, cfg.bn);
+    g.group_m = cfg.group_m < 1 ? 1 : cfg.group_m;
+    g.xcd_remap = cfg.xcd_remap;
+    return g;
+}
+
+static mlk_status run_gemm(const KernelEntry* e, GemmArgs& g, const Shape& s, void* C, int64_t M,
+                           int64_t N, int64_t ldc, hipStream_t st) {
+    const int esz = 4;  // every output type is 32-bit
+    if (g.atomic && !s.accumulate) {
+        hipError_t z = launch_zero_matrix(C, M, N, ldc, esz, st);
+        if (z != hipSuccess) return hip_fail(z, "zero output");
+    }
+    const int64_t nblk = (int64_t)g.tiles_m * g.tiles_n * g.split_k;
+    hipError_t err = e->launch(g, (int)nblk, st);
+    if (err != hipSuccess) return hip_fail(err, "kernel launch");
+    return MLK_OK;
+}
+
+mlk_status launch_dense(const Shape& s, const void* A, int64_t lda, const void* B, int64_t ldb,
+                        void* C, int64_t ldc, const float* sa, const float* sb,
+                        const mlk_tile_config& cfg, hipStream_t st) {
+    const KernelEntry* e = find_kernel(s.dt, 0, cfg);
+    if (!e) return fail(MLK_ERR_CONFIG, "no kernel for configuration");
+    if (s.M == 0 || s.N == 0) return MLK_OK;
+    GemmArgs g = base_args(s, cfg);
+    const int es = esize_in(s.dt);
+    g.A = A;
+    g.lda = lda;
+    g.B = B;
+    g.ldb = ldb;
+    g.C = C;
+    g.ldc = ldc;
+    g.scale_a = sa;
+    g.scale_b = sb;
+    g.vec_a = ((uintptr_t)A % 16 == 0) && ((lda * es) % 16 == 0);
+    g.vec_b = ((uintptr_t)B % 16 == 0) && ((ldb * es) % 16 == 0);
+    return run_gemm(e, g, s, C, s.M, s.N, ldc, st);
+}
+
+mlk_status launch_conv(const Shape& s, int64_t n, int64_t c, int64_t h, int64_t w, int64_t f,
+                       int64_t kh, int64_t kw, int sh, int sw, int ph, int pw, int64_t ho,
+                       int64_t wo, const void* x, const void* wt, void* y,
+                       const mlk_tile_config& cfg, hipStream_t st) {
+    const KernelEntry* e = find_kernel(s.dt, 1, cfg);
+    if (!e) return fail(MLK_ERR_CONFIG, "no kernel for configuration");
+    GemmArgs g = base_args(s, cfg);
+    const int es = esize_in(s.dt);
+    g.A = wt;
+    g.lda = c * kh * kw;
+    g.B = x;
+    g.ldb = 0;
+    g.C = y;
+    g.ldc = 0;
+    g.vec_a = ((uintptr_t)wt % 16 == 0) && ((g.lda * es) % 16 == 0);
+    g.vec_b = 0;
+    g.cn = (int32_t)n;
+    g.cc = (int32_t)c;
+    g.ch = (int32_t)h;
+    g.cw = (int32_t)w;
+    g.ckh = (int32_t)kh;
+    g.ckw = (int32_t)kw;
+    g.csh = sh;
+    g.csw = sw;
+    g.cph = ph;
+    g.cpw = pw;
+    g.cho = (int32_t)ho;
+    g.cwo = (int32_t)wo;
+    if (g.atomic && !s.accumulate) {
+        hipError_t z = launch_zero_matrix(y, n * f, ho * wo, ho * wo, 4, st);
+        if (z != hipSuccess) return hip_fail(z, "zero output");
+    }
+    const int64_t nblk = (int64_t)g.tiles_m * g.tiles_n * g.split_k;
+    hipError_t err = e->launch(g, (int)nblk, st);
+    if (err != hipSuccess) return hip_fail(err, "kernel launch");
+    return MLK_OK;
+}
+
+static bool overlaps(const void* a, size_t na, const void* b, size_t nb) {
+    const uintptr_t x = (uintptr_t)a, y = (uintptr_t)b;
+    return x < y + nb && y < x + na;
+}
+
+}  // namespace mlk
+
+using namespace mlk;
+
+extern "C" {
+
+const char* mlk_status_str(mlk_status s) {
+    switch (s) {
+        case MLK_OK: return "MLK_OK";
+        case MLK_ERR_NULL: return "MLK_ERR_NULL";
+        case MLK_ERR_SHAPE: return "MLK_ERR_SHAPE";
+        case MLK_ERR_LAYOUT: return "MLK_ERR_LAYOUT";
+        case MLK_ERR_DTYPE: return "MLK_ERR_DTYPE";
+        case MLK_ERR_CONFIG: return "MLK_ERR_CONFIG";
+        case MLK_ERR_DB: return "MLK_ERR_DB";
+        case MLK_ERR_HIP: return "MLK_ERR_HIP";
+        case MLK_ERR_NOMEM: return "MLK_ERR_NOMEM";
+        case MLK_ERR_ARG: return "MLK_ERR_ARG";
+    }
+    return "MLK_ERR_UNKNOWN";
+}
+
+const char* mlk_last_error(void) { return t_err.c_str(); }
+
+const char* mlk_version(void) { return "mlk 0.1 (gfx950)"; }
+
+mlk_status mlk_matmul(mlk_dtype in, mlk_dtype out, int64_t M, int64_t N, int64_t K,
+                      const void* A, int64_t lda, const void* B, int64_t ldb, void* C,
+                      int64_t ldc, const float* scale_a, const float* scale_b, int accumulate,
+                      const mlk_tile_config* cfg, void* stream) {
+    clear_error();
+    mlk_problem p;
+    memset(&p, 0, sizeof p);
+    p.op = MLK_OP_MATMUL;
+    p.in = in;
+    p.out = out;
+    p.accumulate = accumulate ? 1 : 0;
+    p.M = M;
+    p.N = N;
+    p.K = K;
+    Shape s;
+    mlk_status st = shape_of_problem(&p, &s);
+    if (st != MLK_OK) return st;
+    if (M > 0 && N > 0) {
+        if (!C) return fail(MLK_ERR_NULL, "matmul: C is NULL");
+        if (K > 0 && (!A || !B)) return fail(MLK_ERR_NULL, "matmul: A or B is NULL");
+    }
+    if (lda < std::max<int64_t>(K, 1) || ldb < std::max<int64_t>(N, 1) || ldc < std::max<int64_t>(N, 1))
+        return fail(MLK_ERR_LAYOUT, "matmul: leading dimension too small (lda %lld >= K %lld, ldb %lld >= N, ldc %lld >= N %lld)",
+                    (long long)lda, (long long)K, (long long)ldb, (long long)ldc, (long long)N);
+    if (M > 0 && N > 0 && K > 0) {
+        const int es = esize_in(s.dt);
+        const size_t cb = (size_t)((M - 1) * ldc + N) * 4;
+        const size_t ab = (size_t)((M - 1) * lda + K) * es;
+        const size_t bb = (size_t)((K - 1) * ldb + N) * es;
+        if (overlaps(C, cb, A, ab) || overlaps(C, cb, B, bb))
+            return fail(MLK_ERR_LAYOUT, "matmul: C overlaps A or B");
+    }
+    if ((scale_a || scale_b) && s.dt != DT_F8)
+        return fail(MLK_ERR_ARG, "matmul: scales apply to MLK_F8E4M3 inputs only");
+    mlk_tile_config c;
+    st = resolve(p, s, cfg, &c);
+    if (st != MLK_OK) return st;
+    if (M == 0 || N == 0) return MLK_OK;
+    return launch_dense(s, A, lda, B, ldb, C, ldc, scale_a, scale_b, c, (hipStream_t)stream);
+}
+
+mlk_status mlk_conv2d_nchw_fchw(mlk_dtype in, mlk_dtype out, int64_t N, int64_t C, int64_t H,
+                                int64_t W, int64_t F, int64_t KH, int64_t KW, int32_t sh,
+                                int32_t sw, int32_t ph, int32_t pw, const void* x, const void* w,
+                                void* y, int accumulate, const mlk_tile_config* cfg, void* stream) {
+    clear_error();
+    mlk_problem p;
+    memset(&p, 0, sizeof p);
+    p.op = MLK_OP_CONV2D;
+    p.in = in;
+    p.out = out;
+    p.accumulate = accumulate ? 1 : 0;
+    p.n = N;
+    p.c = C;
+    p.h = H;
+    p.w = W;
+    p.f = F;
+    p.kh = KH;
+    p.kw = KW;
+    p.sh = sh;
+    p.sw = sw;
+    p.ph = ph;
+    p.pw = pw;
+    Shape s;
+    mlk_status st = shape_of_problem(&p, &s);
+    if (st != MLK_OK) return st;
+    if (!x || !w || !y) return fail(MLK_ERR_NULL, "conv2d: x, w or y is NULL");
+    const int64_t ho = conv_out(H, KH, sh, ph), wo = conv_out(W, KW, sw, pw);
+    const int es = esize_in(s.dt);
+    const size_t yb = (size_t)(N * F * ho * wo) * 4;
+    if (overlaps(y, yb, x, (size_t)(N * C * H * W) * es) || overlaps(y, yb, w, (size_t)(F * C * KH * KW) * es))
+        return fail(MLK_ERR_LAYOUT, "conv2d: y overlaps x or w");
+    mlk_tile_config c;
+    st = resolve(p, s, cfg, &c);
+    if (st != MLK_OK) return st;
+    return launch_conv(s, N, C, H, W, F, KH, KW, sh, sw, ph, pw, ho, wo, x, w, y, c,
+                       (hipStream_t)stream);
+}
+
+mlk_status mlk_quantize(mlk_dtype out, int64_t n, const float* x, void* q, float* scale,
+                        void* stream) {
+    clear_error();
+    if (out != MLK_BF16 && out != MLK_F8E4M3)
+        return fail(MLK_ERR_DTYPE, "quantize: output must be MLK_BF16 or MLK_F8E4M3");
+    if (n < 0) return fail(MLK_ERR_SHAPE, "quantize: n < 0");
+    if (out == MLK_F8E4M3 && !scale) return fail(MLK_ERR_NULL, "quantize: e4m3 needs a scale output");
+    if (n > 0 && (!x || !q)) return fail(MLK_ERR_NULL, "quantize: x or q is NULL");
+    if (n > 0 && overlaps(x, (size_t)n * 4, q, (size_t)n * (out == MLK_BF16 ? 2 : 1)))
+        return fail(MLK_ERR_LAYOUT, "quantize: q overlaps x");
+    hipError_t e = out == MLK_BF16 ? launch_quant_bf16(x, n, (uint16_t*)q, (hipStream_t)stream)
+                                   : launch_quant_e4m3(x, n, (uint8_t*)q, scale, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "quantize launch");
+    return MLK_OK;
+}
+
+mlk_status mlk_err_stats(mlk_dtype c_dtype, int64_t n, const void* c, const double* r,
+                         const double* bound, double* out, void* stream) {
+    clear_error();
+    if (c_dtype != MLK_F32 && c_dtype != MLK_I32)
+        return fail(MLK_ERR_DTYPE, "err_stats: c must be MLK_F32 or MLK_I32");
+    if (n < 0) return fail(MLK_ERR_SHAPE, "err_stats: n < 0");
+    if (!out || (n > 0 && (!c || !r))) return fail(MLK_ERR_NULL, "err_stats: NULL pointer");
+    hipError_t e = launch_err_stats(c_dtype == MLK_I32, n, c, r, bound, out, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "err_stats launch");
+    return MLK_OK;
+}
+
+mlk_status mlk_mlp_forward(int64_t B, int64_t D0, int64_t H1, int64_t H2, const float* params,
+                           const float* X, float* y, void* stream) {
+    clear_error();
+    if (B < 0 || D0 < 1 || H1 < 1 || H2 < 1 || D0 > 4096 || H1 > 4096 || H2 > 4096)
+        return fail(MLK_ERR_SHAPE, "mlp: bad sizes");
+    if (B > 0 && (!params || !X || !y)) return fail(MLK_ERR_NULL, "mlp: NULL pointer");
+    hipError_t e = launch_mlp_forward(B, D0, H1, H2, params, X, y, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "mlp forward");
+    return MLK_OK;
+}
+
+mlk_status mlk_mlp_loss_grad(int64_t B, int64_t D0, int64_t H1, int64_t H2,
+                             const float* params, const float* X, const float* t, float* grad,
+                             float* loss, void* stream) {
+    clear_error();
+    if (B < 1 || D0 < 1 || H1 < 1 || H2 < 1 || D0 > 4096 || H1 > 4096 || H2 > 4096)
+        return fail(MLK_ERR_SHAPE, "mlp: bad sizes");
+    if (!params || !X || !t || !grad || !loss) return fail(MLK_ERR_NULL, "mlp: NULL pointer");
+    hipError_t e = launch_mlp_loss_grad(B, D0, H1, H2, params, X, t, grad, loss, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "mlp loss/grad");
+    return MLK_OK;
+}
+
+mlk_status mlk_adam_step(int64_t n, float* params, const float* grad, float* m, float* v,
+                         float lr, float beta1, float beta2, float eps, int64_t t, void* stream) {
+    clear_error();
+    if (n < 0) return fail(MLK_ERR_SHAPE, "adam: n < 0");
+    if (t < 1) return fail(MLK_ERR_ARG, "adam: step t must be >= 1");
+    if (!(beta1 >= 0.0f && beta1 < 1.0f) || !(beta2 >= 0.0f && beta2 < 1.0f) || !(eps > 0.0f))
+        return fail(MLK_ERR_ARG, "adam: bad hyper-parameters");
+    if (n > 0 && (!params || !grad || !m || !v)) return fail(MLK_ERR_NULL, "adam: NULL pointer");
+    hipError_t e = launch_adam(n, params, grad, m, v, lr, beta1, beta2, eps, t, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "adam");
+    return MLK_OK;
+}
+
+mlk_status mlk_config_legal(const mlk_problem* p, const mlk_tile_config* cfg) {
+    clear_error();
+    if (!cfg) return fail(MLK_ERR_NULL, "cfg is NULL");
+    Shape s;
+    mlk_status st = shape_of_problem(p, &s);
+    if (st != MLK_OK) return st;
+    mlk_tile_config c = *cfg;
+    if (c.group_m == 0) c.group_m = 1;
+    return check_config(s, p->op, c);
+}
+
+int32_t mlk_config_count(const mlk_problem* p) {
+    clear_error();
+    Shape s;
+    if (shape_of_problem(p, &s) != MLK_OK) return -1;
+    return (int32_t)enumerate_configs(p, s).size();
+}
+
+mlk_status mlk_config_get(const mlk_problem* p, int32_t i, mlk_tile_config* cfg) {
+    clear_error();
+    if (!cfg) return fail(MLK_ERR_NULL, "cfg is NULL");
+    Shape s;
+    mlk_status st = shape_of_problem(p, &s);
+    if (st != MLK_OK) return st;
+    std::vector<mlk_tile_config> v = enumerate_configs(p, s);
+    if (i < 0 || i >= (int32_t)v.size()) return fail(MLK_ERR_ARG, "config index %d out of range [0, %zu)", i, v.size());
+    *cfg = v[i];
+    return MLK_OK;
+}
+
+mlk_status mlk_config_set_default(const mlk_problem* p, const mlk_tile_config* cfg) {
+    clear_error();
+    mlk_status st = mlk_config_legal(p, cfg);
+    if (st != MLK_OK) return st;
+    mlk_tile_config c = *cfg;
+    if (c.group_m == 0) c.group_m = 1;
+    store_default(problem_key(p), c);
+    return MLK_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,317 @@
+// batched.cpp -- many uneven GEMMs in one launch.
+//
+// Persistent mode: the host cuts every GEMM of the batch into output tiles,
+// estimates each tile's cost from its K depth, and packs the tiles into one
+// bin per resident workgroup with the longest-processing-time-first rule
+// (largest tile to the currently least-loaded bin).  The device then runs one
+// grid of exactly that many workgroups; workgroup b walks its own task range,
+// so there is no device-side queue, counter or reset.  Every tile runs the
+// same code as a plain launch with split_k = 1, so results equal per-GEMM
+// launches bit for bit.
+//
+// Graph mode: the launch(es) are captured once into a hipGraph on a private
+// stream and replayed on the caller's stream; the graph and its device task
+// list are cached per (descriptors, configuration, flags) and freed by
+// mlk_release().
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+#include <functional>
+#include <map>
+#include <mutex>
+#include <queue>
+#include <string>
+#include <vector>
+
+#include "internal.hpp"
+
+namespace mlk {
+
+namespace {
+
+struct Plan {
+    void* dev = nullptr;     // GemmArgs[count] | Task[ntasks] | int32 bounds[nblk + 1]
+    GemmArgs* gemms = nullptr;
+    Task* tasks = nullptr;
+    int32_t* bounds = nullptr;
+    int nblk = 0;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    int device = 0;
+};
+
+std::mutex g_mu;
+std::map<std::string, Plan> g_plans;
+std::map<int, hipStream_t> g_capture_streams;
+
+int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+std::string plan_key(int dt, int64_t count, const mlk_gemm_desc* d, const mlk_tile_config& c,
+                     int accumulate, uint32_t flags, int device) {
+    std::string k;
+    k.append((const char*)&dt, sizeof dt);
+    k.append((const char*)&accumulate, sizeof accumulate);
+    k.append((const char*)&flags, sizeof flags);
+    k.append((const char*)&device, sizeof device);
+    k.append((const char*)&c, sizeof c);
+    k.append((const char*)d, sizeof(mlk_gemm_desc) * (size_t)count);
+    return k;
+}
+
+GemmArgs args_for(int dt, const mlk_gemm_desc& d, const mlk_tile_config& c, int accumulate) {
+    GemmArgs g;
+    memset(&g, 0, sizeof g);
+    const int es = dt == DT_F32 ? 4 : 2;
+    g.M = d.M;
+    g.N = d.N;
+    g.K = d.K;
+    g.A = d.A;
+    g.lda = d.lda;
+    g.B = d.B;
+    g.ldb = d.ldb;
+    g.C = d.C;
+    g.ldc = d.ldc;
+    g.accumulate = accumulate;
+    g.atomic = 0;
+    g.split_k = 1;
+    g.vec_a = ((uintptr_t)d.A % 16 == 0) && ((d.lda * es) % 16 == 0);
+    g.vec_b = ((uintptr_t)d.B % 16 == 0) && ((d.ldb * es) % 16 == 0);
+    g.tiles_m = (int32_t)cdiv(d.M, c.bm);
+    g.tiles_n = (int32_t)cdiv(d.N, c.bn);
+    g.group_m = 1;
+    g.xcd_remap = 0;
+    return g;
+}
+
+// Workgroups that fit on the device at once for this tile kernel: limited by
+// LDS (160 KB per CU) and by waves (at most two workgroups of 8 waves or four
+// of 4 waves share a CU without starving each other of registers).
+int resident_blocks(const KernelEntry* e, int cus) {
+    int by_lds = (160 * 1024) / std::max(e->lds_bytes, 1);
+    int by_waves = e->threads >= 512 ? 1 : (e->threads >= 256 ? 2 : 4);
+    return cus * std::max(1, std::min(by_lds, by_waves));
+}
+
+// Build the LPT schedule on the host and upload it.
+mlk_status build_plan(int dt, int64_t count, const mlk_gemm_desc* d, const KernelEntry* e,
+                      const mlk_tile_config& c, int accumulate, Plan* plan) {
+    std::vector<GemmArgs> gemms((size_t)count);
+    struct T {
+        double cost;
+        Task t;
+    };
+    std::vector<T> all;
+    for (int64_t i = 0; i < count; ++i) {
+        gemms[i] = args_for(dt, d[i], c, accumulate);
+        if (d[i].M == 0 || d[i].N == 0) continue;
+        const int64_t stages = cdiv(std::max<int64_t>(d[i].K, 1), c.bk);
+        for (int32_t tm = 0; tm < gemms[i].tiles_m; ++tm)
+            for (int32_t tn = 0; tn < gemms[i].tiles_n; ++tn)
+                // fixed prologue / epilogue cost of about two K stages
+                all.push_back(T{(double)stages + 2.0, Task{(int32_t)i, tm, tn, 0}});
+    }
+    const int cus = device_cus();
+    int nblk = resident_blocks(e, cus);
+    if ((int64_t)nblk > (int64_t)all.size()) nblk = std::max<int>(1, (int)all.size());
+    std::stable_sort(all.begin(), all.end(), [](const T& a, const T& b) { return a.cost > b.cost; });
+    // min-heap of (load, bin)
+    typedef std::pair<double, int> LB;
+    std::priority_queue<LB, std::vector<LB>, std::greater<LB>> heap;
+    for (int b = 0; b < nblk; ++b) heap.push(LB(0.0, b));
+    std::vector<std::vector<Task>> bins((size_t)nblk);
+    for (const T& x : all) {
+        LB top = heap.top();
+        heap.pop();
+        bins[top.second].push_back(x.t);
+        heap.push(LB(top.first + x.cost, top.second));
+    }
+    std::vector<Task> tasks;
+    std::vector<int32_t> bounds((size_t)nblk + 1, 0);
+    for (int b = 0; b < nblk; ++b) {
+        bounds[b] = (int32_t)tasks.size();
+        tasks.insert(tasks.end(), bins[b].begin(), bins[b].end());
+    }
+    bounds[nblk] = (int32_t)tasks.size();
+
+    const size_t gb = sizeof(GemmArgs) * gemms.size();
+    const size_t tb = sizeof(Task) * std::max<size_t>(tasks.size(), 1);
+    const size_t bb = sizeof(int32_t) * bounds.size();
+    const size_t total = gb + tb + bb;
+    void* dev = nullptr;
+    hipError_t err = hipMalloc(&dev, total);
+    if (err != hipSuccess) return hip_fail(err, "batched plan allocation");
+    std::vector<char> host(total, 0);
+    memcpy(host.data(), gemms.data(), gb);
+    if (!tasks.empty()) memcpy(host.data() + gb, tasks.data(), sizeof(Task) * tasks.size());
+    memcpy(host.data() + gb + tb, bounds.data(), bb);
+    err = hipMemcpy(dev, host.data(), total, hipMemcpyHostToDevice);
+    if (err != hipSuccess) {
+        (void)hipFree(dev);
+        return hip_fail(err, "batched plan upload");
+    }
+    plan->dev = dev;
+    plan->gemms = (GemmArgs*)dev;
+    plan->tasks = (Task*)((char*)dev + gb);
+    plan->bounds = (int32_t*)((char*)dev + gb + tb);
+    plan->nblk = nblk;
+    return MLK_OK;
+}
+
+mlk_status launch_batch(int dt, int64_t count, const mlk_gemm_desc* d, const KernelEntry* e,
+                        const mlk_tile_config& c, int accumulate, uint32_t flags, Plan* plan,
+                        hipStream_t st) {
+    if (flags & MLK_BATCH_PERSISTENT) {
+        if (plan->nblk == 0) return MLK_OK;
+        hipError_t err = e->persist(plan->gemms, plan->tasks, plan->bounds, plan->nblk, st);
+        if (err != hipSuccess) return hip_fail(err, "persistent launch");
+        return MLK_OK;
+    }
+    // one launch per GEMM, same code path as mlk_matmul
+    for (int64_t i = 0; i < count; ++i) {
+        Shape s;
+        s.dt = dt;
+        s.conv = 0;
+        s.M = d[i].M;
+        s.N = d[i].N;
+        s.K = d[i].K;
+        s.accumulate = accumulate;
+        mlk_tile_config ci = c;
+        const int64_t stages = cdiv(std::max<int64_t>(s.K, 1), c.bk);
+        if (ci.split_k > stages) ci.split_k = 1;
+        mlk_status r = launch_dense(s, d[i].A, d[i].lda, d[i].B, d[i].ldb, d[i].C, d[i].ldc,
+                                    nullptr, nullptr, ci, st);
+        if (r != MLK_OK) return r;
+    }
+    return MLK_OK;
+}
+
+}  // namespace
+
+}  // namespace mlk
+
+using namespace mlk;
+
+extern "C" {
+
+mlk_status mlk_batched_matmul(mlk_dtype in, mlk_dtype out, int64_t count,
+                              const mlk_gemm_desc* descs, const mlk_tile_config* cfg,
+                              int accumulate, uint32_t flags, void* stream) {
+    clear_error();
+    if (flags & ~(MLK_BATCH_PERSISTENT | MLK_BATCH_GRAPH))
+        return fail(MLK_ERR_ARG, "batched: unknown flag bits 0x%x", flags);
+    mlk_problem p;
+    memset(&p, 0, sizeof p);
+    p.op = MLK_OP_BATCHED;
+    p.in = in;
+    p.out = out;
+    p.accumulate = accumulate ? 1 : 0;
+    p.count = count;
+    p.descs = descs;
+    Shape s;
+    mlk_status st = shape_of_problem(&p, &s);
+    if (st != MLK_OK) return st;
+    const int es = s.dt == DT_F32 ? 4 : 2;
+    for (int64_t i = 0; i < count; ++i) {
+        const mlk_gemm_desc& d = descs[i];
+        if (d.M == 0 || d.N == 0) continue;
+        if (!d.C || (d.K > 0 && (!d.A || !d.B)))
+            return fail(MLK_ERR_NULL, "batched: NULL pointer in desc %lld", (long long)i);
+        if (d.lda < std::max<int64_t>(d.K, 1) || d.ldb < std::max<int64_t>(d.N, 1) ||
+            d.ldc < std::max<int64_t>(d.N, 1))
+            return fail(MLK_ERR_LAYOUT, "batched: leading dimension too small in desc %lld", (long long)i);
+        const uintptr_t c0 = (uintptr_t)d.C, c1 = c0 + (size_t)((d.M - 1) * d.ldc + d.N) * 4;
+        const uintptr_t a0 = (uintptr_t)d.A, a1 = a0 + (size_t)((d.M - 1) * d.lda + d.K) * es;
+        const uintptr_t b0 = (uintptr_t)d.B, b1 = b0 + (size_t)((d.K - 1) * d.ldb + d.N) * es;
+        if (d.K > 0 && ((c0 < a1 && a0 < c1) || (c0 < b1 && b0 < c1)))
+            return fail(MLK_ERR_LAYOUT, "batched: C overlaps A or B in desc %lld", (long long)i);
+    }
+    mlk_tile_config c;
+    if (cfg && !(cfg->bm == 0 && cfg->bn == 0)) {
+        c = *cfg;
+        if (c.group_m == 0) c.group_m = 1;
+        if (c.split_k == 0) c.split_k = 1;
+        st = check_config(s, MLK_OP_BATCHED, c);
+        if (st != MLK_OK) return st;
+    } else if (!lookup_default(problem_key(&p), &c)) {
+        c = heuristic_config(s, MLK_OP_BATCHED);
+    }
+    const KernelEntry* e = find_kernel(s.dt, 0, c);
+    if (!e) return fail(MLK_ERR_CONFIG, "batched: no kernel for configuration");
+    if ((flags & MLK_BATCH_PERSISTENT) && !e->persist)
+        return fail(MLK_ERR_CONFIG, "batched: tile %dx%dx%d has no persistent variant", c.bm, c.bn, c.bk);
+    hipStream_t user = (hipStream_t)stream;
+    int dev = 0;
+    hipError_t herr = hipGetDevice(&dev);
+    if (herr != hipSuccess) return hip_fail(herr, "hipGetDevice");
+
+    const bool need_plan = (flags & MLK_BATCH_PERSISTENT) != 0;
+    const bool graph = (flags & MLK_BATCH_GRAPH) != 0;
+    if (!need_plan && !graph) {
+        Plan none;
+        return launch_batch(s.dt, count, descs, e, c, p.accumulate, flags, &none, user);
+    }
+    std::lock_guard<std::mutex> g(g_mu);
+    const std::string key = plan_key(s.dt, count, descs, c, p.accumulate, flags, dev);
+    auto it = g_plans.find(key);
+    if (it == g_plans.end()) {
+        Plan plan;
+        plan.device = dev;
+        if (need_plan) {
+            st = build_plan(s.dt, count, descs, e, c, p.accumulate, &plan);
+            if (st != MLK_OK) return st;
+        }
+        if (graph) {
+            hipStream_t cap = nullptr;
+            auto cs = g_capture_streams.find(dev);
+            if (cs == g_capture_streams.end()) {
+                herr = hipStreamCreateWithFlags(&cap, hipStreamNonBlocking);
+                if (herr != hipSuccess) return hip_fail(herr, "capture stream");
+                g_capture_streams[dev] = cap;
+            } else {
+                cap = cs->second;
+            }
+            herr = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
+            if (herr != hipSuccess) return hip_fail(herr, "hipStreamBeginCapture");
+            st = launch_batch(s.dt, count, descs, e, c, p.accumulate, flags, &plan, cap);
+            hipGraph_t gr = nullptr;
+            hipError_t endc = hipStreamEndCapture(cap, &gr);
+            if (st != MLK_OK) {
+                if (gr) (void)hipGraphDestroy(gr);
+                if (plan.dev) (void)hipFree(plan.dev);
+                return st;
+            }
+            if (endc != hipSuccess) return hip_fail(endc, "hipStreamEndCapture");
+            herr = hipGraphInstantiate(&plan.exec, gr, nullptr, nullptr, 0);
+            if (herr != hipSuccess) {
+                (void)hipGraphDestroy(gr);
+                return hip_fail(herr, "hipGraphInstantiate");
+            }
+            plan.graph = gr;
+        }
+        it = g_plans.emplace(key, plan).first;
+    }
+    Plan& plan = it->second;
+    if (graph) {
+        herr = hipGraphLaunch(plan.exec, user);
+        if (herr != hipSuccess) return hip_fail(herr, "hipGraphLaunch");
+        return MLK_OK;
+    }
+    return launch_batch(s.dt, count, descs, e, c, p.accumulate, flags, &plan, user);
+}
+
+void mlk_release(void) {
+    std::lock_guard<std::mutex> g(g_mu);
+    (void)hipDeviceSynchronize();
+    for (auto& kv : g_plans) {
+        Plan& p = kv.second;
+        if (p.exec) (void)hipGraphExecDestroy(p.exec);
+        if (p.graph) (void)hipGraphDestroy(p.graph);
+        if (p.dev) (void)hipFree(p.dev);
+    }
+    g_plans.clear();
+    for (auto& kv : g_capture_streams) (void)hipStreamDestroy(kv.second);
+    g_capture_streams.clear();
+}
+
+}  // extern "C"

@@ -1,0 +1,314 @@
+// elementwise.hip -- the HBM-bound kernels around the contractions:
+// quantisation to bf16 / OCP e4m3 (per-tensor amax scaling), clearing an
+// output, seeded fills for tuner scratch inputs, and the FP64 error
+// reduction against a double-precision reference.
+//
+// All are streaming kernels: 16-byte coalesced loads, grid-stride loops,
+// a grid sized to a few workgroups per CU.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "kernels.hpp"
+
+namespace mlk {
+
+namespace {
+
+constexpr int kThreads = 256;
+
+inline int grid_for(int64_t items, int per_block_items) {
+    int64_t g = (items + per_block_items - 1) / per_block_items;
+    if (g < 1) g = 1;
+    if (g > 4096) g = 4096;
+    return (int)g;
+}
+
+// ------------------------------------------------------------------ bf16
+
+__device__ inline uint16_t bf16_rne(float f) {
+    const uint32_t u = __float_as_uint(f);
+    if ((u & 0x7F800000u) == 0x7F800000u && (u & 0x007FFFFFu) != 0)
+        return (uint16_t)(((u >> 16) & 0x8000u) | 0x7FC0u);  // quiet NaN, sign kept
+    // add half an ulp of the kept part (minus one when the kept lsb is even),
+    // then truncate: round to nearest, ties to even; overflow carries to inf
+    const uint32_t r = u + 0x7FFFu + ((u >> 16) & 1u);
+    return (uint16_t)(r >> 16);
+}
+
+__global__ __launch_bounds__(kThreads) void k_quant_bf16(const float* __restrict__ x, int64_t n,
+                                                         uint16_t* __restrict__ q) {
+    // 8 values per thread per step: two 16-byte loads, one 16-byte store
+    const int64_t nvec = n / 8;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nvec; i += stride) {
+        const f4_t a = *(const f4_t*)(x + 8 * i);
+        const f4_t b = *(const f4_t*)(x + 8 * i + 4);
+        u4_t o;
+        o[0] = bf16_rne(a[0]) | ((uint32_t)bf16_rne(a[1]) << 16);
+        o[1] = bf16_rne(a[2]) | ((uint32_t)bf16_rne(a[3]) << 16);
+        o[2] = bf16_rne(b[0]) | ((uint32_t)bf16_rne(b[1]) << 16);
+        o[3] = bf16_rne(b[2]) | ((uint32_t)bf16_rne(b[3]) << 16);
+        *(u4_t*)(q + 8 * i) = o;
+    }
+    // tail
+    if (blockIdx.x == 0)
+        for (int64_t i = nvec * 8 + threadIdx.x; i < n; i += blockDim.x) q[i] = bf16_rne(x[i]);
+}
+
+__global__ __launch_bounds__(kThreads) void k_quant_bf16_scalar(const float* __restrict__ x,
+                                                                int64_t n, uint16_t* __restrict__ q) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride)
+        q[i] = bf16_rne(x[i]);
+}
+
+// ------------------------------------------------------------------ e4m3
+
+// fp32 -> OCP E4M3, round to nearest even, saturating to +-448; NaN -> 0x7F.
+__device__ inline uint32_t e4m3_rne_sat(float v) {
+    const uint32_t u = __float_as_uint(v);
+    const uint32_t sign = (u >> 24) & 0x80u;
+    const uint32_t mag = u & 0x7FFFFFFFu;
+    if (mag > 0x7F800000u) return 0x7Fu;              // NaN
+    if (mag >= 0x43E00000u) return sign | 0x7Eu;      // |v| >= 448 (incl. inf)
+    if (mag < 0x3C800000u) {                          // |v| < 2^-6: subnormal grid 2^-9
+        // |v| * 2^9 is exact; round half to even onto 0..8 (8 = smallest normal)
+        const float s = __uint_as_float(mag) * 512.0f;
+        return sign | (uint32_t)__builtin_rintf(s);
+    }
+    const uint32_t e = (mag >> 23) - 127 + 7;         // biased e4m3 exponent, 1..15
+    const uint32_t m = mag & 0x7FFFFFu;
+    uint32_t r = m >> 20;                             // keep 3 fraction bits
+    const uint32_t rest = m & 0xFFFFFu, half = 0x80000u;
+    uint32_t code = (e << 3) | r;
+    if (rest > half || (rest == half && (r & 1u))) code += 1;  // carry may bump exponent
+    return sign | code;                               // < 448 never reaches 0x7F
+}
+
+__global__ __launch_bounds__(kThreads) void k_amax_init(uint32_t* amax_bits) { *amax_bits = 0u; }
+
+// max |x| as the bit pattern of a non-negative float (ordered like unsigned ints)
+template <bool VEC>
+__global__ __launch_bounds__(kThreads) void k_amax(const float* __restrict__ x, int64_t n,
+                                                   uint32_t* amax_bits) {
+    float m = 0.0f;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    const int64_t first = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if constexpr (VEC) {
+        const int64_t nvec = n / 4;
+        for (int64_t i = first; i < nvec; i += stride) {
+            const f4_t a = *(const f4_t*)(x + 4 * i);
+            m = fmaxf(m, fmaxf(fmaxf(fabsf(a[0]), fabsf(a[1])), fmaxf(fabsf(a[2]), fabsf(a[3]))));
+        }
+        if (blockIdx.x == 0)
+            for (int64_t i = nvec * 4 + threadIdx.x; i < n; i += blockDim.x) m = fmaxf(m, fabsf(x[i]));
+    } else {
+        for (int64_t i = first; i < n; i += stride) m = fmaxf(m, fabsf(x[i]));
+    }
+    // fmaxf drops NaN operands, so NaNs never reach the maximum
+    for (int off = 32; off > 0; off >>= 1) m = fmaxf(m, __shfl_xor(m, off, 64));
+    __shared__ float wmax[kThreads / 64];
+    if ((threadIdx.x & 63) == 0) wmax[threadIdx.x >> 6] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int w = 1; w < kThreads / 64; ++w) m = fmaxf(m, wmax[w]);
+        atomicMax(amax_bits, __float_as_uint(m));
+    }
+}
+
+__device__ inline float e4m3_scale_from_amax(uint32_t bits) {
+    const float amax = __uint_as_float(bits);
+    if (!(amax > 0.0f) || bits >= 0x7F800000u) return 1.0f;
+    return __fdiv_rn(amax, 448.0f);
+}
+
+__global__ __launch_bounds__(kThreads) void k_quant_e4m3(const float* __restrict__ x, int64_t n,
+                                                         const uint32_t* amax_bits,
+                                                         uint8_t* __restrict__ q) {
+    const float s = e4m3_scale_from_amax(*amax_bits);
+    const int64_t nvec = n / 16;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nvec; i += stride) {
+        u4_t o;
+#pragma unroll
+        for (int w = 0; w < 4; ++w) {
+            const f4_t a = *(const f4_t*)(x + 16 * i + 4 * w);
+            o[w] = e4m3_rne_sat(__fdiv_rn(a[0], s)) | (e4m3_rne_sat(__fdiv_rn(a[1], s)) << 8) |
+                   (e4m3_rne_sat(__fdiv_rn(a[2], s)) << 16) | (e4m3_rne_sat(__fdiv_rn(a[3], s)) << 24);
+        }
+        *(u4_t*)(q + 16 * i) = o;
+    }
+    if (blockIdx.x == 0)
+        for (int64_t i = nvec * 16 + threadIdx.x; i < n; i += blockDim.x)
+            q[i] = (uint8_t)e4m3_rne_sat(__fdiv_rn(x[i], s));
+}
+
+__global__ __launch_bounds__(kThreads) void k_quant_e4m3_scalar(const float* __restrict__ x,
+                                                                int64_t n, const uint32_t* amax_bits,
+                                                                uint8_t* __restrict__ q) {
+    const float s = e4m3_scale_from_amax(*amax_bits);
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride)
+        q[i] = (uint8_t)e4m3_rne_sat(__fdiv_rn(x[i], s));
+}
+
+// scale <- amax / 448 (runs after every block of k_quant_e4m3 has read amax)
+__global__ __launch_bounds__(kThreads) void k_amax_to_scale(uint32_t* amax_bits) {
+    const float s = e4m3_scale_from_amax(*amax_bits);
+    *(float*)amax_bits = s;
+}
+
+// ------------------------------------------------------------------ fills
+
+__global__ __launch_bounds__(kThreads) void k_zero_matrix(uint8_t* C, int64_t M, int64_t rowbytes,
+                                                          int64_t ldbytes) {
+    const int64_t total = M * rowbytes;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total / 4; i += stride) {
+        const int64_t r = (4 * i) / rowbytes, c = (4 * i) % rowbytes;
+        *(uint32_t*)(C + r * ldbytes + c) = 0u;
+    }
+}
+
+__device__ inline uint64_t splitmix(uint64_t z) {
+    z += 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+// Seeded scratch values for timing runs: uniform in [-1, 1) for f32 / bf16,
+// finite e4m3 codes of magnitude <= 1 for e4m3, and any int8.
+__global__ __launch_bounds__(kThreads) void k_fill_random(uint8_t* p, int64_t n, int dt,
+                                                          uint64_t seed) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+        const uint64_t h = splitmix(seed ^ (uint64_t)i * 0x632BE59BD9B4E019ull);
+        const float u = (float)(h >> 40) * (1.0f / 8388608.0f) - 1.0f;
+        if (dt == DT_F32) ((float*)p)[i] = u;
+        else if (dt == DT_BF16) ((uint16_t*)p)[i] = bf16_rne(u);
+        else if (dt == DT_F8) p[i] = (uint8_t)((h & 0x80u) | ((h >> 8) % 0x38u));
+        else p[i] = (uint8_t)h;
+    }
+}
+
+// ------------------------------------------------------------------ error statistics
+
+constexpr int kErrBlocks = 1024;
+
+// per-block partials: [sum d^2, sum r^2, max |d|, max |d|/bound]
+__global__ __launch_bounds__(kThreads) void k_err_partial(int c_is_int, int64_t n,
+                                                          const void* __restrict__ c,
+                                                          const double* __restrict__ r,
+                                                          const double* __restrict__ bound,
+                                                          double* __restrict__ part) {
+    double s2 = 0.0, r2 = 0.0, mx = 0.0, ratio = 0.0;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+        const double cv = c_is_int ? (double)((const int32_t*)c)[i] : (double)((const float*)c)[i];
+        const double d = cv - r[i];
+        s2 += d * d;
+        r2 += r[i] * r[i];
+        mx = fmax(mx, fabs(d));
+        if (bound && bound[i] > 0.0) ratio = fmax(ratio, fabs(d) / bound[i]);
+    }
+    __shared__ double sh[4][kThreads];
+    sh[0][threadIdx.x] = s2;
+    sh[1][threadIdx.x] = r2;
+    sh[2][threadIdx.x] = mx;
+    sh[3][threadIdx.x] = ratio;
+    __syncthreads();
+    for (int w = kThreads / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) {
+            sh[0][threadIdx.x] += sh[0][threadIdx.x + w];
+            sh[1][threadIdx.x] += sh[1][threadIdx.x + w];
+            sh[2][threadIdx.x] = fmax(sh[2][threadIdx.x], sh[2][threadIdx.x + w]);
+            sh[3][threadIdx.x] = fmax(sh[3][threadIdx.x], sh[3][threadIdx.x + w]);
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x < 4) part[blockIdx.x * 4 + threadIdx.x] = sh[threadIdx.x][0];
+}
+
+__global__ __launch_bounds__(kThreads) void k_err_final(const double* __restrict__ part, int nb,
+                                                        double* __restrict__ out) {
+    if (threadIdx.x != 0) return;
+    double s2 = 0.0, r2 = 0.0, mx = 0.0, ratio = 0.0;
+    for (int b = 0; b < nb; ++b) {
+        s2 += part[4 * b];
+        r2 += part[4 * b + 1];
+        mx = fmax(mx, part[4 * b + 2]);
+        ratio = fmax(ratio, part[4 * b + 3]);
+    }
+    out[0] = s2;
+    out[1] = r2;
+    out[2] = mx;
+    out[3] = ratio;
+}
+
+}  // namespace
+
+hipError_t launch_zero_matrix(void* C, int64_t M, int64_t N, int64_t ldc, int esize,
+                              hipStream_t s) {
+    if (M <= 0 || N <= 0) return hipSuccess;
+    const int64_t rowbytes = N * esize;
+    hipLaunchKernelGGL(k_zero_matrix, dim3(grid_for(M * rowbytes / 4, kThreads * 4)),
+                       dim3(kThreads), 0, s, (uint8_t*)C, M, rowbytes, ldc * esize);
+    return hipGetLastError();
+}
+
+hipError_t launch_quant_bf16(const float* x, int64_t n, uint16_t* q, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    const bool vec = ((uintptr_t)x % 16 == 0) && ((uintptr_t)q % 16 == 0);
+    if (vec)
+        hipLaunchKernelGGL(k_quant_bf16, dim3(grid_for(n / 8 + 1, kThreads * 4)), dim3(kThreads), 0,
+                           s, x, n, q);
+    else
+        hipLaunchKernelGGL(k_quant_bf16_scalar, dim3(grid_for(n, kThreads * 8)), dim3(kThreads), 0, s,
+                           x, n, q);
+    return hipGetLastError();
+}
+
+hipError_t launch_quant_e4m3(const float* x, int64_t n, uint8_t* q, float* scale,
+                             hipStream_t s) {
+    uint32_t* bits = (uint32_t*)scale;  // holds amax bits until the last kernel
+    hipLaunchKernelGGL(k_amax_init, dim3(1), dim3(1), 0, s, bits);
+    if (n > 0) {
+        const bool vec = ((uintptr_t)x % 16 == 0) && ((uintptr_t)q % 16 == 0);
+        if (vec) {
+            hipLaunchKernelGGL(k_amax<true>, dim3(grid_for(n / 4 + 1, kThreads * 8)), dim3(kThreads),
+                               0, s, x, n, bits);
+            hipLaunchKernelGGL(k_quant_e4m3, dim3(grid_for(n / 16 + 1, kThreads * 2)), dim3(kThreads),
+                               0, s, x, n, (const uint32_t*)bits, q);
+        } else {
+            hipLaunchKernelGGL(k_amax<false>, dim3(grid_for(n, kThreads * 16)), dim3(kThreads), 0, s,
+                               x, n, bits);
+            hipLaunchKernelGGL(k_quant_e4m3_scalar, dim3(grid_for(n, kThreads * 8)), dim3(kThreads), 0,
+                               s, x, n, (const uint32_t*)bits, q);
+        }
+    }
+    hipLaunchKernelGGL(k_amax_to_scale, dim3(1), dim3(1), 0, s, bits);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_random(void* p, int64_t n, int dt, uint64_t seed, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_fill_random, dim3(grid_for(n, kThreads * 8)), dim3(kThreads), 0, s,
+                       (uint8_t*)p, n, dt, seed);
+    return hipGetLastError();
+}
+
+hipError_t launch_err_stats(int c_is_int, int64_t n, const void* c, const double* r,
+                            const double* bound, double* out, hipStream_t s) {
+    double* part = nullptr;
+    hipError_t e = hipMallocAsync((void**)&part, sizeof(double) * 4 * kErrBlocks, s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_err_partial, dim3(kErrBlocks), dim3(kThreads), 0, s, c_is_int, n, c, r,
+                       bound, part);
+    hipLaunchKernelGGL(k_err_final, dim3(1), dim3(64), 0, s, (const double*)part, kErrBlocks, out);
+    e = hipGetLastError();
+    hipError_t e2 = hipFreeAsync(part, s);
+    return e != hipSuccess ? e : e2;
+}
+
+}  // namespace mlk

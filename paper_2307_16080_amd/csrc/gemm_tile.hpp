@@ -1,0 +1,445 @@
+// gemm_tile.hpp -- the workgroup-tiled MFMA contraction shared by every dense
+// kernel of the library (matmul in fp32 / bf16 / e4m3 / int8, the implicit-GEMM
+// conv2d, and the persistent batched GEMM).
+//
+// What is computed is linalg.matmul, C[M,N] (+)= A[M,K] * B[K,N] (paper
+// Sec. 2.1, listing "linalg-matmul"), or, with the conv operand policy,
+// linalg.conv_2d_nchw_fchw (Sec. 4.1, listing "2dnchwconv") viewed as
+// rows = output channels, columns = output pixels, depth = (c, kh, kw).
+// The paper maps each output element to a GPU block and notes that tiling
+// introduces a block x thread distribution; here one workgroup owns a BM x BN
+// output tile, each 64-lane wave a (BM/WM) x (BN/WN) sub-tile made of 16x16
+// MFMA tiles, and the contraction runs through LDS in stages of KB bytes per
+// row.
+//
+// LDS layout: both operands are stored "K-contiguous": row r of the A stage
+// holds A[m0 + r, k0 ...] and row n of the B stage holds B[k0 ..., n0 + n],
+// each row KB bytes plus 16 bytes of padding (which spreads consecutive rows
+// over different banks).  A is copied as is; B (row-major, N-contiguous in
+// HBM) is transposed in registers on its way from HBM to LDS, in blocks of
+// EPV x EPV elements (EPV = elements per 16 bytes), so that every lane then
+// reads its MFMA operand with one 16-byte LDS load.
+//
+// MFMA operand convention (16x16 output tile, 64 lanes): lane l supplies row
+// (l % 16) of the A tile and column (l % 16) of the B tile; the 16 or 32 bytes
+// it supplies along K are bytes [g*KS/4, (g+1)*KS/4) of the current K step,
+// g = l / 16.  A and B use the same (lane group, byte) -> k assignment, so the
+// MFMA sums exactly the products of matching k.  The result lane l, register
+// r holds output (4*(l/16) + r, l % 16).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace mlk {
+
+enum : int { DT_F32 = 0, DT_BF16 = 1, DT_F8 = 2, DT_I8 = 3 };
+
+typedef float f4_t __attribute__((ext_vector_type(4)));
+typedef int i4_t __attribute__((ext_vector_type(4)));
+typedef int i8_t __attribute__((ext_vector_type(8)));
+typedef __bf16 bf8_t __attribute__((ext_vector_type(8)));
+typedef uint32_t u4_t __attribute__((ext_vector_type(4)));
+
+template <int DT> struct Traits;
+template <> struct Traits<DT_F32> {
+    static constexpr int ES = 4;   // element size (bytes)
+    static constexpr int KS = 64;  // bytes of one row consumed per K step
+    typedef f4_t acc_t;
+    typedef float out_t;
+};
+template <> struct Traits<DT_BF16> {
+    static constexpr int ES = 2;
+    static constexpr int KS = 64;
+    typedef f4_t acc_t;
+    typedef float out_t;
+};
+template <> struct Traits<DT_I8> {
+    static constexpr int ES = 1;
+    static constexpr int KS = 64;
+    typedef i4_t acc_t;
+    typedef int32_t out_t;
+};
+template <> struct Traits<DT_F8> {
+    static constexpr int ES = 1;
+    static constexpr int KS = 128;
+    typedef f4_t acc_t;
+    typedef float out_t;
+};
+
+// Everything a tile needs to know about one GEMM (or one convolution).
+struct GemmArgs {
+    int64_t M, N, K;
+    const void* A;
+    int64_t lda;
+    const void* B;
+    int64_t ldb;
+    void* C;
+    int64_t ldc;
+    const float* scale_a;  // e4m3 only; may be null (= 1)
+    const float* scale_b;
+    int32_t accumulate;    // 1: C += result
+    int32_t atomic;        // 1: add partial results with atomics (split K)
+    int32_t split_k;
+    int32_t vec_a;         // 1: A rows are 16-byte aligned (vector loads allowed)
+    int32_t vec_b;
+    int32_t tiles_m, tiles_n;
+    int32_t group_m, xcd_remap;
+    // convolution view (conv policy only)
+    int32_t cn, cc, ch, cw, ckh, ckw, csh, csw, cph, cpw, cho, cwo;
+};
+
+// ---------------------------------------------------------------- MFMA step
+
+template <int DT> struct Mma;
+template <> struct Mma<DT_F32> {
+    __device__ static inline void run(f4_t& c, const u4_t* a, const u4_t* b) {
+        // one 16-byte operand = 4 consecutive k per lane = 4 MFMA 16x16x4
+#pragma unroll
+        for (int s = 0; s < 4; ++s)
+            c = __builtin_amdgcn_mfma_f32_16x16x4f32(__uint_as_float(a[0][s]),
+                                                     __uint_as_float(b[0][s]), c, 0, 0, 0);
+    }
+};
+template <> struct Mma<DT_BF16> {
+    __device__ static inline void run(f4_t& c, const u4_t* a, const u4_t* b) {
+        c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf8_t, a[0]),
+                                                    __builtin_bit_cast(bf8_t, b[0]), c, 0, 0, 0);
+    }
+};
+template <> struct Mma<DT_I8> {
+    __device__ static inline void run(i4_t& c, const u4_t* a, const u4_t* b) {
+        c = __builtin_amdgcn_mfma_i32_16x16x64_i8(__builtin_bit_cast(i4_t, a[0]),
+                                                  __builtin_bit_cast(i4_t, b[0]), c, 0, 0, 0);
+    }
+};
+template <> struct Mma<DT_F8> {
+    __device__ static inline void run(f4_t& c, const u4_t* a, const u4_t* b) {
+        i8_t av = {(int)a[0][0], (int)a[0][1], (int)a[0][2], (int)a[0][3],
+                   (int)a[1][0], (int)a[1][1], (int)a[1][2], (int)a[1][3]};
+        i8_t bv = {(int)b[0][0], (int)b[0][1], (int)b[0][2], (int)b[0][3],
+                   (int)b[1][0], (int)b[1][1], (int)b[1][2], (int)b[1][3]};
+        // format code 0 = OCP E4M3 for both operands; block scales 2^(127-127) = 1
+        c = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(av, bv, c, 0, 0, 0, 127, 0, 127);
+    }
+};
+
+// ---------------------------------------------------------------- helpers
+
+// 16 bytes holding elements [e0, e0 + nvalid) of a row, zero beyond.
+template <int ES>
+__device__ inline u4_t load_partial(const uint8_t* row, int64_t e0, int nvalid) {
+    u4_t v = {0u, 0u, 0u, 0u};
+    constexpr int EPV = 16 / ES;
+#pragma unroll
+    for (int e = 0; e < EPV; ++e) {
+        if (e < nvalid) {
+            uint32_t x;
+            if constexpr (ES == 4) x = *(const uint32_t*)(row + (e0 + e) * 4);
+            else if constexpr (ES == 2) x = *(const uint16_t*)(row + (e0 + e) * 2);
+            else x = *(const uint8_t*)(row + (e0 + e));
+            const int bit = e * ES * 8;
+            v[bit >> 5] |= x << (bit & 31);
+        }
+    }
+    return v;
+}
+
+// Transpose an EPV x EPV block of ES-byte elements held as EPV rows of 16 bytes.
+template <int ES>
+__device__ inline void transpose_block(const u4_t* in, u4_t* out) {
+    if constexpr (ES == 4) {
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) out[j][i] = in[i][j];
+    } else if constexpr (ES == 2) {
+        // out[j] holds element j of rows 0..7; dword p of out[j] = rows 2p, 2p+1
+#pragma unroll
+        for (int j = 0; j < 8; ++j)
+#pragma unroll
+            for (int p = 0; p < 4; ++p) {
+                const uint32_t lo = in[2 * p][j >> 1], hi = in[2 * p + 1][j >> 1];
+                out[j][p] = (j & 1) ? ((lo >> 16) | (hi & 0xFFFF0000u))
+                                    : ((lo & 0xFFFFu) | (hi << 16));
+            }
+    } else {
+        // 16 x 16 bytes: dword p of out[j] = byte j of rows 4p .. 4p+3
+#pragma unroll
+        for (int j = 0; j < 16; ++j)
+#pragma unroll
+            for (int p = 0; p < 4; ++p) {
+                const int sh = 8 * (j & 3);
+                const uint32_t b0 = (in[4 * p + 0][j >> 2] >> sh) & 0xFFu;
+                const uint32_t b1 = (in[4 * p + 1][j >> 2] >> sh) & 0xFFu;
+                const uint32_t b2 = (in[4 * p + 2][j >> 2] >> sh) & 0xFFu;
+                const uint32_t b3 = (in[4 * p + 3][j >> 2] >> sh) & 0xFFu;
+                out[j][p] = b0 | (b1 << 8) | (b2 << 16) | (b3 << 24);
+            }
+    }
+}
+
+// Logical tile of workgroup `bid` (of `nblk`): XCD remap, then grouped raster.
+__device__ inline void tile_coords(const GemmArgs& g, int bid, int nblk, int& tm, int& tn,
+                                   int& kz) {
+    if (g.xcd_remap && (nblk & 7) == 0) bid = (bid & 7) * (nblk >> 3) + (bid >> 3);
+    kz = bid % g.split_k;
+    int t = bid / g.split_k;
+    const int gm = g.group_m < 1 ? 1 : g.group_m;
+    const int width = gm * g.tiles_n;
+    const int first_m = (t / width) * gm;
+    const int rows = min(g.tiles_m - first_m, gm);
+    tm = first_m + (t % width) % rows;
+    tn = (t % width) / rows;
+}
+
+// ---------------------------------------------------------------- the tile
+
+// CONV = false: dense row-major A, B, C.  CONV = true: A = filter (F x CKK,
+// row-major, lda = CKK), B = implicit im2col of the NCHW input, C = NFHW
+// output.
+template <int DT, int BM, int BN, int KB, int WM, int WN, bool CONV>
+struct Tile {
+    typedef Traits<DT> T;
+    typedef typename T::acc_t acc_t;
+    typedef typename T::out_t out_t;
+    static constexpr int ES = T::ES;
+    static constexpr int KS = T::KS;
+    static constexpr int EPV = 16 / ES;          // elements per 16 bytes
+    static constexpr int NT = 64 * WM * WN;      // threads
+    static constexpr int PITCH = KB + 16;         // LDS row pitch (bytes)
+    static constexpr int STAGE = (BM + BN) * PITCH;
+    static constexpr int LDS_BYTES = 2 * STAGE;
+    static constexpr int BK = KB / ES;           // elements of K per stage
+    static constexpr int WTM = BM / WM, WTN = BN / WN;
+    static constexpr int TM = WTM / 16, TN = WTN / 16;
+    static constexpr int CPR = KB / 16;          // 16-byte chunks per row
+    static constexpr int NA = (BM * CPR + NT - 1) / NT;      // A chunks per thread
+    static constexpr int NBLK = (BK / EPV) * (BN / EPV);     // B transpose blocks
+    static constexpr int NB = (NBLK + NT - 1) / NT;          // B blocks per thread
+    static constexpr int KV = KS / 64;                       // 16-byte regs per MFMA operand
+
+    static_assert(KB % KS == 0, "stage depth must hold whole K steps");
+    static_assert(BM % (16 * WM) == 0 && BN % (16 * WN) == 0, "wave tile must be 16-aligned");
+    static_assert(BK % EPV == 0 && BN % EPV == 0, "B blocks must tile the stage");
+    static_assert(LDS_BYTES <= 160 * 1024, "LDS budget");
+
+    // ---- global -> registers
+    __device__ static inline void load_a(const GemmArgs& g, int64_t m0, int64_t k0, u4_t* ra,
+                                         int tid) {
+        const uint8_t* A = (const uint8_t*)g.A;
+#pragma unroll
+        for (int i = 0; i < NA; ++i) {
+            const int c = tid + i * NT;
+            ra[i] = u4_t{0u, 0u, 0u, 0u};
+            if ((BM * CPR) % NT != 0 && c >= BM * CPR) continue;
+            const int r = c / CPR, cc = c % CPR;
+            const int64_t m = m0 + r, k = k0 + cc * EPV;
+            if (m >= g.M || k >= g.K) continue;
+            const uint8_t* row = A + m * g.lda * ES;
+            if (g.vec_a && k + EPV <= g.K) ra[i] = *(const u4_t*)(row + k * ES);
+            else ra[i] = load_partial<ES>(row, k, (int)min<int64_t>(EPV, g.K - k));
+        }
+    }
+
+    __device__ static inline void load_b(const GemmArgs& g, int64_t n0, int64_t k0, u4_t* rb,
+                                         int tid) {
+#pragma unroll
+        for (int i = 0; i < NB; ++i) {
+            const int blk = tid + i * NT;
+            u4_t* v = rb + i * EPV;
+#pragma unroll
+            for (int e = 0; e < EPV; ++e) v[e] = u4_t{0u, 0u, 0u, 0u};
+            if (NBLK % NT != 0 && blk >= NBLK) continue;
+            const int kr = blk / (BN / EPV), nc = blk % (BN / EPV);
+            const int64_t kb = k0 + kr * EPV, n = n0 + nc * EPV;
+            if constexpr (!CONV) {
+                if (n >= g.N) continue;
+                const uint8_t* B = (const uint8_t*)g.B;
+                const int nval = (int)min<int64_t>(EPV, g.N - n);
+#pragma unroll
+                for (int e = 0; e < EPV; ++e) {
+                    const int64_t k = kb + e;
+                    if (k >= g.K) continue;
+                    const uint8_t* row = B + k * g.ldb * ES;
+                    if (g.vec_b && nval == EPV) v[e] = *(const u4_t*)(row + n * ES);
+                    else v[e] = load_partial<ES>(row, n, nval);
+                }
+            } else {
+                // implicit im2col: rows k = (c, kh, kw), columns p = (img, oh, ow)
+                // v[e] is built directly in transposed form: v[j] = column n + j
+                const int64_t P = (int64_t)g.cn * g.cho * g.cwo;
+                const int KHW = g.ckh * g.ckw;
+                int ck[EPV], ckh[EPV], ckw[EPV];
+#pragma unroll
+                for (int e = 0; e < EPV; ++e) {
+                    const int64_t k = kb + e;
+                    ck[e] = k < g.K ? (int)(k / KHW) : -1;
+                    const int rem = (int)(k % KHW);
+                    ckh[e] = rem / g.ckw;
+                    ckw[e] = rem % g.ckw;
+                }
+                const uint8_t* X = (const uint8_t*)g.B;
+#pragma unroll
+                for (int j = 0; j < EPV; ++j) {
+                    const int64_t p = n + j;
+                    if (p >= P) continue;
+                    const int hw = g.cho * g.cwo;
+                    const int img = (int)(p / hw), q = (int)(p % hw);
+                    const int ih0 = (q / g.cwo) * g.csh - g.cph, iw0 = (q % g.cwo) * g.csw - g.cpw;
+                    const int64_t base = (int64_t)img * g.cc * g.ch * g.cw;
+#pragma unroll
+                    for (int e = 0; e < EPV; ++e) {
+                        if (ck[e] < 0) continue;
+                        const int ih = ih0 + ckh[e], iw = iw0 + ckw[e];
+                        if (ih < 0 || ih >= g.ch || iw < 0 || iw >= g.cw) continue;
+                        const int64_t off = base + ((int64_t)ck[e] * g.ch + ih) * g.cw + iw;
+                        uint32_t x;
+                        if constexpr (ES == 4) x = *(const uint32_t*)(X + off * 4);
+                        else if constexpr (ES == 2) x = *(const uint16_t*)(X + off * 2);
+                        else x = X[off];
+                        const int bit = e * ES * 8;
+                        v[j][bit >> 5] |= x << (bit & 31);
+                    }
+                }
+            }
+        }
+    }
+
+    // ---- registers -> LDS
+    __device__ static inline void store_a(uint8_t* sa, const u4_t* ra, int tid) {
+#pragma unroll
+        for (int i = 0; i < NA; ++i) {
+            const int c = tid + i * NT;
+            if ((BM * CPR) % NT != 0 && c >= BM * CPR) continue;
+            const int r = c / CPR, cc = c % CPR;
+            *(u4_t*)(sa + r * PITCH + cc * 16) = ra[i];
+        }
+    }
+
+    __device__ static inline void store_b(uint8_t* sb, const u4_t* rb, int tid) {
+#pragma unroll
+        for (int i = 0; i < NB; ++i) {
+            const int blk = tid + i * NT;
+            if (NBLK % NT != 0 && blk >= NBLK) continue;
+            const int kr = blk / (BN / EPV), nc = blk % (BN / EPV);
+            u4_t t[EPV];
+            if constexpr (!CONV) transpose_block<ES>(rb + i * EPV, t);
+            else {
+#pragma unroll
+                for (int e = 0; e < EPV; ++e) t[e] = rb[i * EPV + e];
+            }
+#pragma unroll
+            for (int j = 0; j < EPV; ++j)
+                *(u4_t*)(sb + (nc * EPV + j) * PITCH + kr * 16) = t[j];
+        }
+    }
+
+    // ---- one tile: C[m0:m0+BM, n0:n0+BN] (+)= A[m0:, kbeg:kend] B[kbeg:kend, n0:]
+    __device__ static inline void run(const GemmArgs& g, int tm, int tn, int kz, uint8_t* lds) {
+        const int tid = threadIdx.x;
+        const int lane = tid & 63, wave = tid >> 6;
+        const int wy = wave / WN, wx = wave % WN;
+        const int64_t m0 = (int64_t)tm * BM, n0 = (int64_t)tn * BN;
+
+        // contraction range of this split
+        const int64_t kstages = (g.K + BK - 1) / BK;
+        const int64_t per = (kstages + g.split_k - 1) / g.split_k;
+        const int64_t s_beg = (int64_t)kz * per;
+        const int64_t s_end = min<int64_t>(kstages, s_beg + per);
+        const int nk = (int)max<int64_t>(0, s_end - s_beg);
+
+        acc_t acc[TM][TN];
+#pragma unroll
+        for (int i = 0; i < TM; ++i)
+#pragma unroll
+            for (int j = 0; j < TN; ++j) acc[i][j] = acc_t{0, 0, 0, 0};
+
+        u4_t ra[NA > 0 ? NA : 1];
+        u4_t rb[NB * EPV > 0 ? NB * EPV : 1];
+
+        if (nk > 0) {
+            load_a(g, m0, s_beg * BK, ra, tid);
+            load_b(g, n0, s_beg * BK, rb, tid);
+            store_a(lds, ra, tid);
+            store_b(lds + BM * PITCH, rb, tid);
+        }
+        __syncthreads();
+
+        const int lr = lane & 15, lg = lane >> 4;
+        for (int it = 0; it < nk; ++it) {
+            const bool more = it + 1 < nk;
+            if (more) {
+                load_a(g, m0, (s_beg + it + 1) * BK, ra, tid);
+                load_b(g, n0, (s_beg + it + 1) * BK, rb, tid);
+            }
+            const uint8_t* sa = lds + (it & 1) * STAGE;
+            const uint8_t* sb = sa + BM * PITCH;
+#pragma unroll
+            for (int ks = 0; ks < KB / KS; ++ks) {
+                u4_t af[TM][KV], bfr[TN][KV];
+                const int off = ks * KS + lg * (KS / 4);
+#pragma unroll
+                for (int i = 0; i < TM; ++i)
+#pragma unroll
+                    for (int v = 0; v < KV; ++v)
+                        af[i][v] = *(const u4_t*)(sa + (wy * WTM + i * 16 + lr) * PITCH + off + v * 16);
+#pragma unroll
+                for (int j = 0; j < TN; ++j)
+#pragma unroll
+                    for (int v = 0; v < KV; ++v)
+                        bfr[j][v] = *(const u4_t*)(sb + (wx * WTN + j * 16 + lr) * PITCH + off + v * 16);
+#pragma unroll
+                for (int i = 0; i < TM; ++i)
+#pragma unroll
+                    for (int j = 0; j < TN; ++j) Mma<DT>::run(acc[i][j], af[i], bfr[j]);
+            }
+            if (more) {
+                uint8_t* na = lds + ((it + 1) & 1) * STAGE;
+                store_a(na, ra, tid);
+                store_b(na + BM * PITCH, rb, tid);
+            }
+            __syncthreads();
+        }
+
+        // ---- epilogue
+        float alpha = 1.0f;
+        if constexpr (DT == DT_F8) {
+            if (g.scale_a) alpha *= *g.scale_a;
+            if (g.scale_b) alpha *= *g.scale_b;
+        }
+        out_t* C = (out_t*)g.C;
+#pragma unroll
+        for (int j = 0; j < TN; ++j) {
+            const int64_t n = n0 + wx * WTN + j * 16 + lr;
+            if (n >= g.N) continue;
+            int64_t cbase = n;   // offset of column n (row 0)
+            int64_t rstride = g.ldc;
+            if constexpr (CONV) {
+                const int64_t hw = (int64_t)g.cho * g.cwo;
+                const int64_t img = n / hw, q = n % hw;
+                cbase = img * g.M * hw + q;
+                rstride = hw;
+            }
+#pragma unroll
+            for (int i = 0; i < TM; ++i)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int64_t m = m0 + wy * WTM + i * 16 + lg * 4 + r;
+                    if (m >= g.M) continue;
+                    out_t* p = C + m * rstride + cbase;
+                    if constexpr (DT == DT_I8) {
+                        const uint32_t v = (uint32_t)acc[i][j][r];
+                        if (g.atomic) atomicAdd((unsigned int*)p, v);
+                        else *p = (int32_t)(g.accumulate ? (uint32_t)*p + v : v);
+                    } else {
+                        const float v = (DT == DT_F8) ? alpha * acc[i][j][r] : acc[i][j][r];
+                        if (g.atomic) atomicAdd(p, v);
+                        else *p = g.accumulate ? *p + v : v;
+                    }
+                }
+        }
+    }
+};
+
+}  // namespace mlk

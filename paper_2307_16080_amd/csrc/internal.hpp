@@ -1,0 +1,71 @@
+// internal.hpp -- host-side declarations shared by the C-ABI units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdarg>
+#include <string>
+#include <vector>
+
+#include "../../include/mlk.h"
+#include "kernels.hpp"
+
+namespace mlk {
+
+// ---- errors (thread-local message)
+mlk_status fail(mlk_status s, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
+void clear_error();
+mlk_status hip_fail(hipError_t e, const char* what);
+
+// ---- device facts
+int device_cus();  // compute units of the current device (256 on MI355X)
+
+// ---- the normalised shape of one contraction (a matmul, or a conv viewed as
+// rows = F, columns = N*HO*WO, depth = C*KH*KW)
+struct Shape {
+    int dt = DT_F32;
+    int conv = 0;
+    int64_t M = 0, N = 0, K = 0;
+    int accumulate = 1;
+};
+
+// registry of compiled kernels
+const std::vector<const KernelEntry*>& registry();
+const KernelEntry* find_kernel(int dt, int conv, const mlk_tile_config& c);
+
+int dt_of(mlk_dtype in, mlk_dtype out, int conv, bool* ok);
+
+// problem -> Shape (validating the problem's own fields); MLK_OK or an error
+mlk_status shape_of_problem(const mlk_problem* p, Shape* s);
+
+// the legal configuration space of a problem, in enumeration order
+std::vector<mlk_tile_config> enumerate_configs(const mlk_problem* p, const Shape& s);
+mlk_status check_config(const Shape& s, int op, const mlk_tile_config& c);
+mlk_tile_config heuristic_config(const Shape& s, int op);
+std::string problem_key(const mlk_problem* p);
+
+// tuned defaults consulted by launches that pass no configuration
+bool lookup_default(const std::string& key, mlk_tile_config* c);
+void store_default(const std::string& key, const mlk_tile_config& c);
+
+// launch one contraction with a resolved configuration
+mlk_status launch_dense(const Shape& s, const void* A, int64_t lda, const void* B, int64_t ldb,
+                        void* C, int64_t ldc, const float* sa, const float* sb,
+                        const mlk_tile_config& cfg, hipStream_t st);
+mlk_status launch_conv(const Shape& s, int64_t n, int64_t c, int64_t h, int64_t w, int64_t f,
+                       int64_t kh, int64_t kw, int sh, int sw, int ph, int pw, int64_t ho,
+                       int64_t wo, const void* x, const void* wt, void* y,
+                       const mlk_tile_config& cfg, hipStream_t st);
+
+int64_t conv_out(int64_t in, int64_t k, int64_t stride, int64_t pad);
+
+// cost model internals used by the tuner
+int model_feature_count();
+void model_features(const Shape& s, const mlk_tile_config& c, int cus, float* out);
+mlk_status model_predict_shape(mlk_cost_model* m, const Shape& s,
+                               const std::vector<mlk_tile_config>& cfgs, std::vector<float>* us);
+
+// analytic stand-in for a GPU timing (used by mlk_tune's fake_timer mode)
+double fake_time_us(const Shape& s, int op, const mlk_tile_config& c, int index, uint64_t seed);
+
+}  // namespace mlk

@@ -1,0 +1,19 @@
+// int8 x int8 -> int32 matmul tile configurations (MFMA 16x16x64 i8).
+#include "kernels.hpp"
+namespace mlk {
+const KernelEntry* kernels_i8(int* n) {
+    static const KernelEntry t[] = {
+        MLK_ENTRY(DT_I8, 32, 32, 128, 1, 1, false),
+        MLK_ENTRY(DT_I8, 64, 64, 64, 2, 2, false),
+        MLK_ENTRY(DT_I8, 64, 64, 128, 2, 2, false),
+        MLK_ENTRY(DT_I8, 128, 64, 128, 2, 2, false),
+        MLK_ENTRY(DT_I8, 64, 128, 128, 2, 2, false),
+        MLK_ENTRY(DT_I8, 128, 128, 64, 2, 2, false),
+        MLK_ENTRY(DT_I8, 128, 128, 128, 2, 2, false),
+        MLK_ENTRY(DT_I8, 256, 128, 128, 2, 2, false),
+        MLK_ENTRY(DT_I8, 256, 256, 128, 2, 2, false),
+    };
+    *n = (int)(sizeof(t) / sizeof(t[0]));
+    return t;
+}
+}  // namespace mlk

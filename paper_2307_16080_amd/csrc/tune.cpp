@@ -1,0 +1,377 @@
+// tune.cpp -- the tile-configuration search (paper Sec. 4.3: tile sizes and
+// the unroll factor are the parameters, measured run time is the objective,
+// a black-box search explores the space).
+//
+// Strategies: EXHAUSTIVE measures every legal configuration (the ground
+// truth); RANDOM measures a seeded uniform sample of the budget; MODEL ranks
+// every configuration with the learned cost model and measures only the top
+// of the ranking.  The objective is the median of `reps` timed samples after
+// `warmup` untimed launches; each sample times enough back-to-back launches
+// (hipEvents on the tuning stream) to last about 0.2 ms.
+//
+// Results are appended to a JSON-lines database keyed by the problem and the
+// device, and recorded as the default configuration for later launches that
+// pass none.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <fstream>
+#include <numeric>
+#include <random>
+#include <string>
+#include <vector>
+
+#include "internal.hpp"
+
+namespace mlk {
+
+namespace {
+
+int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+uint64_t mix64(uint64_t z) {
+    z += 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+std::string device_tag() {
+    int dev = 0;
+    hipDeviceProp_t prop;
+    if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess)
+        return "unknown";
+    char buf[128];
+    snprintf(buf, sizeof buf, "%s/%dcu", prop.gcnArchName, prop.multiProcessorCount);
+    return buf;
+}
+
+// ---- database: one JSON object per line, the last matching line wins
+
+bool db_lookup(const char* path, const std::string& key, const std::string& dev,
+               mlk_tile_config* c, double* us, bool* unreadable) {
+    *unreadable = false;
+    FILE* f = fopen(path, "r");
+    if (!f) {
+        FILE* probe = fopen(path, "a");  // missing is fine; existing-but-unreadable is not
+        if (probe) fclose(probe);
+        else *unreadable = true;
+        return false;
+    }
+    const std::string kpat = "\"key\": \"" + key + "\"";
+    const std::string dpat = "\"device\": \"" + dev + "\"";
+    bool found = false;
+    char* line = nullptr;
+    size_t cap = 0;
+    ssize_t len;
+    while ((len = getline(&line, &cap, f)) > 0) {
+        std::string s(line, (size_t)len);
+        if (s.find(kpat) == std::string::npos || s.find(dpat) == std::string::npos) continue;
+        size_t at = s.find("\"cfg\": [");
+        size_t ut = s.find("\"us\": ");
+        if (at == std::string::npos || ut == std::string::npos) continue;
+        mlk_tile_config t;
+        if (sscanf(s.c_str() + at + 8, "%d, %d, %d, %d, %d, %d, %d, %d", &t.bm, &t.bn, &t.bk,
+                   &t.wm, &t.wn, &t.split_k, &t.group_m, &t.xcd_remap) != 8)
+            continue;
+        double u = 0;
+        if (sscanf(s.c_str() + ut + 6, "%lf", &u) != 1) continue;
+        *c = t;
+        *us = u;
+        found = true;
+    }
+    free(line);
+    fclose(f);
+    return found;
+}
+
+bool db_append(const char* path, const std::string& key, const std::string& dev,
+               const mlk_tile_config& c, double us, int n_measured, int n_legal, int strategy) {
+    FILE* f = fopen(path, "a");
+    if (!f) return false;
+    fprintf(f,
+            "{\"key\": \"%s\", \"device\": \"%s\", \"cfg\": [%d, %d, %d, %d, %d, %d, %d, %d], "
+            "\"us\": %.4f, \"measured\": %d, \"legal\": %d, \"strategy\": %d, \"lib\": \"%s\"}\n",
+            key.c_str(), dev.c_str(), c.bm, c.bn, c.bk, c.wm, c.wn, c.split_k, c.group_m,
+            c.xcd_remap, us, n_measured, n_legal, strategy, mlk_version());
+    const bool ok = fflush(f) == 0;
+    fclose(f);
+    return ok;
+}
+
+// ---- scratch problem instance owned by the tuner
+
+struct Scratch {
+    std::vector<void*> allocs;
+    const void *A = nullptr, *B = nullptr;
+    void* C = nullptr;
+    float* scales = nullptr;  // {1, 1}
+    std::vector<mlk_gemm_desc> descs;
+    ~Scratch() {
+        for (void* p : allocs) (void)hipFree(p);
+    }
+    hipError_t alloc(size_t bytes, void** out) {
+        hipError_t e = hipMalloc(out, std::max<size_t>(bytes, 16));
+        if (e == hipSuccess) allocs.push_back(*out);
+        return e;
+    }
+};
+
+int in_esize(int dt) { return dt == DT_F32 ? 4 : dt == DT_BF16 ? 2 : 1; }
+
+mlk_status make_scratch(const mlk_problem* p, const Shape& s, uint64_t seed, Scratch* sc) {
+    const int es = in_esize(s.dt);
+    hipError_t e = hipSuccess;
+    void *a = nullptr, *b = nullptr, *c = nullptr;
+    if (p->op == MLK_OP_BATCHED) {
+        size_t total = 0;
+        auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
+        for (int64_t i = 0; i < p->count; ++i) {
+            const mlk_gemm_desc& d = p->descs[i];
+            total += al((size_t)(d.M * d.K) * es) + al((size_t)(d.K * d.N) * es) + al((size_t)(d.M * d.N) * 4);
+        }
+        void* base = nullptr;
+        if ((e = sc->alloc(total, &base)) != hipSuccess) return hip_fail(e, "tuner scratch");
+        if ((e = launch_fill_random(base, (int64_t)(total / es), s.dt, seed, 0)) != hipSuccess)
+            return hip_fail(e, "tuner fill");
+        char* q = (char*)base;
+        for (int64_t i = 0; i < p->count; ++i) {
+            mlk_gemm_desc d = p->descs[i];
+            d.A = q;
+            d.lda = d.K;
+            q += al((size_t)(d.M * d.K) * es);
+            d.B = q;
+            d.ldb = d.N;
+            q += al((size_t)(d.K * d.N) * es);
+            d.C = q;
+            d.ldc = d.N;
+            q += al((size_t)(d.M * d.N) * 4);
+            sc->descs.push_back(d);
+        }
+        // outputs must hold finite values: clear them
+        for (const mlk_gemm_desc& d : sc->descs)
+            if ((e = launch_zero_matrix(d.C, d.M, d.N, d.ldc, 4, 0)) != hipSuccess)
+                return hip_fail(e, "tuner clear");
+        return MLK_OK;
+    }
+    size_t an, bn, cn;
+    if (p->op == MLK_OP_MATMUL) {
+        an = (size_t)(s.M * s.K);
+        bn = (size_t)(s.K * s.N);
+        cn = (size_t)(s.M * s.N);
+    } else {
+        an = (size_t)(p->f * p->c * p->kh * p->kw);
+        bn = (size_t)(p->n * p->c * p->h * p->w);
+        cn = (size_t)(s.M * s.N);
+    }
+    if ((e = sc->alloc(an * es, &a)) != hipSuccess || (e = sc->alloc(bn * es, &b)) != hipSuccess ||
+        (e = sc->alloc(cn * 4, &c)) != hipSuccess)
+        return hip_fail(e, "tuner scratch");
+    if ((e = launch_fill_random(a, (int64_t)an, s.dt, seed, 0)) != hipSuccess ||
+        (e = launch_fill_random(b, (int64_t)bn, s.dt, seed + 1, 0)) != hipSuccess ||
+        (e = launch_zero_matrix(c, 1, (int64_t)cn, (int64_t)cn, 4, 0)) != hipSuccess)
+        return hip_fail(e, "tuner fill");
+    void* sp = nullptr;
+    if ((e = sc->alloc(2 * sizeof(float), &sp)) != hipSuccess) return hip_fail(e, "tuner scratch");
+    const float ones[2] = {1.0f, 1.0f};
+    if ((e = hipMemcpy(sp, ones, sizeof ones, hipMemcpyHostToDevice)) != hipSuccess)
+        return hip_fail(e, "tuner scales");
+    sc->A = a;
+    sc->B = b;
+    sc->C = c;
+    sc->scales = (float*)sp;
+    return MLK_OK;
+}
+
+mlk_status run_once(const mlk_problem* p, const Shape& s, const Scratch& sc,
+                    const mlk_tile_config& c, hipStream_t st) {
+    if (p->op == MLK_OP_MATMUL) {
+        const bool f8 = s.dt == DT_F8;
+        return launch_dense(s, sc.A, s.K, sc.B, s.N, sc.C, s.N, f8 ? sc.scales : nullptr,
+                            f8 ? sc.scales + 1 : nullptr, c, st);
+    }
+    if (p->op == MLK_OP_CONV2D) {
+        const int64_t ho = conv_out(p->h, p->kh, p->sh, p->ph), wo = conv_out(p->w, p->kw, p->sw, p->pw);
+        return launch_conv(s, p->n, p->c, p->h, p->w, p->f, p->kh, p->kw, p->sh, p->sw, p->ph, p->pw,
+                           ho, wo, sc.B, sc.A, sc.C, c, st);
+    }
+    return mlk_batched_matmul((mlk_dtype)p->in, (mlk_dtype)p->out, (int64_t)sc.descs.size(),
+                              sc.descs.data(), &c, p->accumulate, MLK_BATCH_PERSISTENT, st);
+}
+
+// median time (us) of one configuration; < 0 if it failed to launch
+double measure(const mlk_problem* p, const Shape& s, const Scratch& sc, const mlk_tile_config& c,
+               int warmup, int reps, hipStream_t st, hipEvent_t e0, hipEvent_t e1) {
+    for (int i = 0; i < warmup; ++i)
+        if (run_once(p, s, sc, c, st) != MLK_OK) return -1.0;
+    if (hipEventRecord(e0, st) != hipSuccess) return -1.0;
+    if (run_once(p, s, sc, c, st) != MLK_OK) return -1.0;
+    if (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) return -1.0;
+    float ms = 0.f;
+    (void)hipEventElapsedTime(&ms, e0, e1);
+    int inner = (int)std::ceil(0.2 / std::max(ms, 1e-4f));
+    inner = std::max(1, std::min(inner, 200));
+    std::vector<double> t;
+    for (int r = 0; r < reps; ++r) {
+        (void)hipEventRecord(e0, st);
+        for (int i = 0; i < inner; ++i)
+            if (run_once(p, s, sc, c, st) != MLK_OK) return -1.0;
+        (void)hipEventRecord(e1, st);
+        if (hipEventSynchronize(e1) != hipSuccess) return -1.0;
+        (void)hipEventElapsedTime(&ms, e0, e1);
+        t.push_back(1000.0 * ms / inner);
+    }
+    std::sort(t.begin(), t.end());
+    return t.size() % 2 ? t[t.size() / 2] : 0.5 * (t[t.size() / 2 - 1] + t[t.size() / 2]);
+}
+
+}  // namespace
+
+double fake_time_us(const Shape& s, int op, const mlk_tile_config& c, int index, uint64_t seed) {
+    const int cus = 256;
+    const int64_t M = std::max<int64_t>(s.M, 1), N = std::max<int64_t>(s.N, 1), K = std::max<int64_t>(s.K, 1);
+    const int64_t tiles = cdiv(M, c.bm) * cdiv(N, c.bn) * c.split_k;
+    const int occ = (2 * (c.bm + c.bn) * (c.bk * in_esize(s.dt) + 16)) > 80 * 1024 ? 1 : 2;
+    const double waves = (double)cdiv(tiles, (int64_t)cus * occ);
+    const double stages = (double)cdiv(cdiv(K, c.bk), c.split_k);
+    const double rate = s.dt == DT_F32 ? 0.6e6 : (s.dt == DT_BF16 ? 9.0e6 : 18.0e6);  // flop/us/CU
+    const double eff = std::min(1.0, (double)c.bm * c.bn / (c.bm + c.bn) / 64.0);
+    double t = waves * (2.0 * c.bm * c.bn * c.bk * stages / (rate * eff) + 0.8) + 3.0;
+    if (c.split_k > 1) t += 1.5;
+    if (c.group_m > 1) t *= 0.99;
+    if (op == MLK_OP_BATCHED) t += 2.0;
+    const double noise = (double)(mix64(seed * 1000003ull + (uint64_t)index) >> 11) / 9007199254740992.0;
+    return t * (1.0 + 0.02 * (noise - 0.5));
+}
+
+}  // namespace mlk
+
+using namespace mlk;
+
+extern "C" mlk_status mlk_tune(const mlk_problem* p, const mlk_tune_opts* o, mlk_tile_config* best,
+                               mlk_tune_report* rep) {
+    clear_error();
+    if (!o || !best) return fail(MLK_ERR_NULL, "tune: opts or best is NULL");
+    Shape s;
+    mlk_status st = shape_of_problem(p, &s);
+    if (st != MLK_OK) return st;
+    if (o->strategy < MLK_TUNE_EXHAUSTIVE || o->strategy > MLK_TUNE_MODEL)
+        return fail(MLK_ERR_ARG, "tune: unknown strategy %d", o->strategy);
+    if (o->strategy != MLK_TUNE_EXHAUSTIVE && !(o->budget_frac > 0.0 && o->budget_frac <= 1.0))
+        return fail(MLK_ERR_ARG, "tune: budget_frac must be in (0, 1]");
+    if (o->strategy == MLK_TUNE_MODEL && !o->model) return fail(MLK_ERR_NULL, "tune: MODEL strategy needs a model");
+    if (o->reps < 0 || o->warmup < 0) return fail(MLK_ERR_ARG, "tune: negative reps / warmup");
+    if (p->op == MLK_OP_MATMUL && (s.M == 0 || s.N == 0))
+        return fail(MLK_ERR_SHAPE, "tune: empty problem");
+    const int reps = o->reps ? o->reps : 20;
+    const int warmup = o->warmup ? o->warmup : 3;
+
+    const std::vector<mlk_tile_config> cfgs = enumerate_configs(p, s);
+    const int S = (int)cfgs.size();
+    if (S == 0) return fail(MLK_ERR_CONFIG, "tune: no legal configuration");
+    mlk_tune_report r;
+    memset(&r, 0, sizeof r);
+    r.n_legal = S;
+    r.best_index = -1;
+    const std::string key = problem_key(p);
+    const std::string dev = o->fake_timer ? std::string("fake") : device_tag();
+
+    if (o->times_us)
+        for (int i = 0; i < S; ++i) o->times_us[i] = -1.0;
+
+    if (o->db_path && o->use_db) {
+        mlk_tile_config c;
+        double us = 0;
+        bool unreadable = false;
+        if (db_lookup(o->db_path, key, dev, &c, &us, &unreadable)) {
+            if (check_config(s, p->op, c) == MLK_OK) {
+                *best = c;
+                r.from_db = 1;
+                r.best_us = us;
+                for (int i = 0; i < S; ++i)
+                    if (!memcmp(&cfgs[i], &c, sizeof c)) r.best_index = i;
+                store_default(key, c);
+                if (rep) *rep = r;
+                return MLK_OK;
+            }
+        }
+        if (unreadable) return fail(MLK_ERR_DB, "tune: database %s is not readable", o->db_path);
+    }
+
+    // which configurations to measure, in order
+    int budget = S;
+    if (o->strategy != MLK_TUNE_EXHAUSTIVE)
+        budget = std::max(1, std::min(S, (int)std::ceil(o->budget_frac * S - 1e-9)));
+    std::vector<int> order(S);
+    std::iota(order.begin(), order.end(), 0);
+    if (o->strategy == MLK_TUNE_RANDOM) {
+        std::mt19937_64 rng(o->seed);
+        for (int i = 0; i < budget; ++i) {
+            std::uniform_int_distribution<int> pick(i, S - 1);
+            std::swap(order[i], order[pick(rng)]);
+        }
+    } else if (o->strategy == MLK_TUNE_MODEL) {
+        std::vector<float> pred;
+        st = model_predict_shape(o->model, s, cfgs, &pred);
+        if (st != MLK_OK) return st;
+        std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return pred[a] < pred[b]; });
+    }
+    order.resize(budget);
+
+    std::vector<double> t(S, -1.0);
+    if (o->fake_timer) {
+        for (int i : order) t[i] = fake_time_us(s, p->op, cfgs[i], i, o->seed);
+    } else {
+        Scratch sc;
+        st = make_scratch(p, s, o->seed ^ 0x5EEDull, &sc);
+        if (st != MLK_OK) return st;
+        hipEvent_t e0, e1;
+        hipError_t he = hipEventCreate(&e0);
+        if (he != hipSuccess) return hip_fail(he, "tune: event");
+        he = hipEventCreate(&e1);
+        if (he != hipSuccess) {
+            (void)hipEventDestroy(e0);
+            return hip_fail(he, "tune: event");
+        }
+        he = hipDeviceSynchronize();
+        for (int i : order) t[i] = measure(p, s, sc, cfgs[i], warmup, reps, 0, e0, e1);
+        (void)hipDeviceSynchronize();
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        clear_error();
+    }
+    r.n_measured = budget;
+
+    // fastest, with configurations within 1% counted as tied: smaller LDS
+    // footprint first, then the lower enumeration index
+    double tmin = -1;
+    for (int i : order)
+        if (t[i] > 0 && (tmin < 0 || t[i] < tmin)) tmin = t[i];
+    if (tmin < 0) return fail(MLK_ERR_HIP, "tune: no configuration could be launched");
+    int pick = -1;
+    int pick_lds = 0;
+    for (int i = 0; i < S; ++i) {
+        if (t[i] <= 0 || t[i] > tmin * 1.01) continue;
+        const KernelEntry* e = find_kernel(s.dt, s.conv, cfgs[i]);
+        const int lds = e ? e->lds_bytes : 0;
+        if (pick < 0 || lds < pick_lds) {
+            pick = i;
+            pick_lds = lds;
+        }
+    }
+    *best = cfgs[pick];
+    r.best_index = pick;
+    r.best_us = t[pick];
+    if (o->times_us)
+        for (int i = 0; i < S; ++i) o->times_us[i] = t[i];
+    store_default(key, *best);
+    if (o->db_path && !db_append(o->db_path, key, dev, *best, r.best_us, r.n_measured, S, o->strategy)) {
+        if (rep) *rep = r;
+        return fail(MLK_ERR_DB, "tune: cannot append to database %s", o->db_path);
+    }
+    if (rep) *rep = r;
+    return MLK_OK;
+}

@@ -1,0 +1,195 @@
+"""CPU checks of the C ABI: the library loads, exports every function that
+include/mlk.h declares, rejects bad arguments before touching a GPU, and its
+configuration space and search logic behave (with the analytic fake timer,
+no GPU).  No compute kernel is launched here.
+"""
+import ctypes
+import json
+import os
+import re
+
+import pytest
+
+import paper_2307_16080_amd as mlk
+from paper_2307_16080_amd import _lib as L
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "mlk.h")
+
+NULL = None
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(mlk_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_exports_every_declared_symbol():
+    lib = L.lib()
+    names = declared_functions()
+    assert len(names) >= 20
+    missing = [n for n in names if not hasattr(lib, n)]
+    assert not missing, missing
+    # and the binding declares a signature for each of them
+    assert set(names) <= set(L.SIGNATURES), set(names) - set(L.SIGNATURES)
+
+
+def test_status_strings_and_version():
+    lib = L.lib()
+    for i, name in enumerate(L.STATUS_NAMES):
+        assert lib.mlk_status_str(i).decode() == name
+    assert b"gfx950" in lib.mlk_version()
+
+
+def _mm(**kw):
+    args = dict(inp=L.MLK_F32, out=L.MLK_F32, M=4, N=4, K=4, A=0x1000, lda=4, B=0x2000, ldb=4,
+                C=0x3000, ldc=4, sa=NULL, sb=NULL, acc=1, cfg=NULL)
+    args.update(kw)
+    st = L.lib().mlk_matmul(args["inp"], args["out"], args["M"], args["N"], args["K"], args["A"],
+                            args["lda"], args["B"], args["ldb"], args["C"], args["ldc"], args["sa"],
+                            args["sb"], args["acc"], args["cfg"], NULL)
+    return st, L.lib().mlk_last_error().decode()
+
+
+def test_matmul_validation():
+    assert _mm(M=-1)[0] == 2
+    assert _mm(A=NULL)[0] == 1
+    assert _mm(C=NULL)[0] == 1
+    assert _mm(lda=3)[0] == 3
+    assert _mm(ldb=3)[0] == 3
+    assert _mm(ldc=2)[0] == 3
+    assert _mm(inp=L.MLK_BF16, out=L.MLK_I32)[0] == 4
+    assert _mm(inp=L.MLK_I8, out=L.MLK_F32)[0] == 4
+    assert _mm(inp=7)[0] == 4
+    # C overlapping A
+    st, msg = _mm(C=0x1008)
+    assert st == 3 and "overlap" in msg
+    # scales only for e4m3
+    assert _mm(sa=0x5000)[0] == 9
+    # illegal explicit configuration
+    bad = L.TileConfig(48, 64, 32, 2, 2, 1, 1, 0)
+    st, msg = _mm(cfg=ctypes.byref(bad))
+    assert st == 5 and "no compiled kernel" in msg
+    bad = L.TileConfig(64, 64, 16, 2, 2, 9, 1, 0)  # split larger than the K stages
+    assert _mm(K=32, lda=32, cfg=ctypes.byref(bad))[0] == 5
+
+
+def test_conv_quant_err_validation():
+    lib = L.lib()
+    conv = lambda **k: lib.mlk_conv2d_nchw_fchw(
+        k.get("inp", 0), k.get("out", 0), k.get("N", 1), k.get("C", 2), k.get("H", 5), k.get("W", 5),
+        k.get("F", 2), k.get("KH", 3), k.get("KW", 3), k.get("sh", 1), k.get("sw", 1), k.get("ph", 0),
+        k.get("pw", 0), k.get("x", 0x1000), k.get("w", 0x9000), k.get("y", 0x20000), 1, NULL, NULL)
+    assert conv(sh=0) == 2
+    assert conv(ph=-1) == 2
+    assert conv(KH=9) == 2            # filter larger than the padded image
+    assert conv(x=NULL) == 1
+    assert conv(inp=L.MLK_I8, out=L.MLK_I32) == 4
+    assert conv(y=0x1004) == 3        # y overlapping x
+    assert lib.mlk_quantize(L.MLK_F32, 4, 0x1000, 0x2000, 0x3000, NULL) == 4
+    assert lib.mlk_quantize(L.MLK_F8E4M3, 4, 0x1000, 0x2000, NULL, NULL) == 1
+    assert lib.mlk_quantize(L.MLK_BF16, -1, 0x1000, 0x2000, NULL, NULL) == 2
+    assert lib.mlk_quantize(L.MLK_BF16, 16, 0x1000, 0x1010, NULL, NULL) == 3
+    assert lib.mlk_err_stats(L.MLK_BF16, 4, 0x1000, 0x2000, NULL, 0x3000, NULL) == 4
+    assert lib.mlk_err_stats(L.MLK_F32, 4, 0x1000, NULL, NULL, 0x3000, NULL) == 1
+    assert lib.mlk_adam_step(4, 0x1000, 0x2000, 0x3000, 0x4000, 0.1, 0.9, 1.5, 1e-8, 1, NULL) == 9
+    assert lib.mlk_adam_step(4, 0x1000, 0x2000, 0x3000, 0x4000, 0.1, 0.9, 0.99, 1e-8, 0, NULL) == 9
+    assert lib.mlk_mlp_forward(4, 0, 8, 8, 0x1, 0x2, 0x3, NULL) == 2
+
+
+def test_batched_validation():
+    lib = L.lib()
+    d = (L.GemmDesc * 2)()
+    d[0] = L.GemmDesc(4, 4, 4, 0x1000, 4, 0x2000, 4, 0x3000, 4)
+    d[1] = L.GemmDesc(4, 4, 4, 0x4000, 4, 0x5000, 3, 0x6000, 4)
+    assert lib.mlk_batched_matmul(L.MLK_BF16, L.MLK_F32, 2, d, NULL, 1, 0, NULL) == 3
+    assert lib.mlk_batched_matmul(L.MLK_BF16, L.MLK_F32, 0, d, NULL, 1, 0, NULL) == 2
+    assert lib.mlk_batched_matmul(L.MLK_I8, L.MLK_I32, 2, d, NULL, 1, 0, NULL) == 4
+    assert lib.mlk_batched_matmul(L.MLK_BF16, L.MLK_F32, 2, d, NULL, 1, 0x8, NULL) == 9
+    d[1] = L.GemmDesc(4, 4, 4, 0x4000, 4, NULL, 4, 0x6000, 4)
+    assert lib.mlk_batched_matmul(L.MLK_BF16, L.MLK_F32, 2, d, NULL, 1, 0, NULL) == 1
+
+
+def test_config_space():
+    p = mlk.matmul_problem(4096, 4096, 4096, L.MLK_BF16, L.MLK_F32)
+    cfgs = mlk.configs(p)
+    assert 50 <= len(cfgs) <= 600
+    assert len({c.as_tuple() for c in cfgs}) == len(cfgs)
+    for c in cfgs:
+        assert mlk.config_legal(p, c)
+    # small problems prune tiles that are twice the problem or more
+    small = mlk.configs(mlk.matmul_problem(40, 40, 40, L.MLK_BF16, L.MLK_F32))
+    assert all(c.bm <= 64 and c.bn <= 64 for c in small)
+    # conv and batched spaces
+    cp = mlk.conv_problem(32, 64, 56, 56, 64, 3, 3, 1, 1)
+    assert mlk.config_count(cp) > 20
+    bp = mlk.batched_problem([(100, 200, 300), (64, 64, 64)])
+    bc = mlk.configs(bp)
+    assert bc and all(c.split_k == 1 for c in bc)
+    # invalid problems count as -1
+    bad = mlk.matmul_problem(4, 4, 4, L.MLK_I8, L.MLK_F32)
+    assert L.lib().mlk_config_count(ctypes.byref(bad)) == -1
+
+
+def test_features_shape():
+    p = mlk.matmul_problem(1024, 512, 256, L.MLK_BF16, L.MLK_F32)
+    f = mlk.features(p, mlk.configs(p)[0])
+    assert len(f) == L.lib().mlk_model_feature_count()
+    assert f[0] == 10.0 and f[1] == 9.0 and f[2] == 8.0
+
+
+def test_tune_exhaustive_fake_timer_returns_argmin():
+    p = mlk.matmul_problem(2048, 1024, 512, L.MLK_BF16, L.MLK_F32)
+    best, rep, times = mlk.tune(p, mlk.MLK_TUNE_EXHAUSTIVE, fake_timer=True, want_times=True, seed=3)
+    assert rep.n_measured == rep.n_legal == len(times)
+    assert all(t > 0 for t in times)
+    tmin = min(times)
+    tied = [i for i, t in enumerate(times) if t <= 1.01 * tmin]
+    assert rep.best_index in tied
+    assert best.as_tuple() == mlk.configs(p)[rep.best_index].as_tuple()
+
+
+def test_tune_random_budget_and_determinism():
+    p = mlk.matmul_problem(1000, 3000, 700, L.MLK_F32, L.MLK_F32)
+    S = mlk.config_count(p)
+    b1, r1, t1 = mlk.tune(p, mlk.MLK_TUNE_RANDOM, budget_frac=0.2, seed=11, fake_timer=True,
+                          want_times=True)
+    b2, r2, t2 = mlk.tune(p, mlk.MLK_TUNE_RANDOM, budget_frac=0.2, seed=11, fake_timer=True,
+                          want_times=True)
+    measured = [i for i, t in enumerate(t1) if t > 0]
+    assert r1.n_measured == len(measured) == -(-S * 2 // 10)
+    assert b1.as_tuple() == b2.as_tuple() and t1 == t2
+    _, _, t3 = mlk.tune(p, mlk.MLK_TUNE_RANDOM, budget_frac=0.2, seed=12, fake_timer=True,
+                        want_times=True)
+    assert [i for i, t in enumerate(t3) if t > 0] != measured
+
+
+def test_tune_database_append_and_resume(tmp_path):
+    db = str(tmp_path / "tune.jsonl")
+    p = mlk.matmul_problem(512, 512, 512, L.MLK_BF16, L.MLK_F32)
+    best, rep, _ = mlk.tune(p, mlk.MLK_TUNE_EXHAUSTIVE, fake_timer=True, db_path=db)
+    assert rep.from_db == 0
+    lines = [json.loads(l) for l in open(db)]
+    assert len(lines) == 1 and lines[0]["cfg"] == list(best.as_tuple())
+    best2, rep2, _ = mlk.tune(p, mlk.MLK_TUNE_EXHAUSTIVE, fake_timer=True, db_path=db, use_db=True)
+    assert rep2.from_db == 1 and rep2.n_measured == 0
+    assert best2.as_tuple() == best.as_tuple()
+    # a corrupt line is skipped, a different problem is tuned afresh
+    with open(db, "a") as f:
+        f.write("{not json\n")
+    q = mlk.matmul_problem(256, 512, 512, L.MLK_BF16, L.MLK_F32)
+    _, rep3, _ = mlk.tune(q, mlk.MLK_TUNE_EXHAUSTIVE, fake_timer=True, db_path=db, use_db=True)
+    assert rep3.from_db == 0 and rep3.n_measured == rep3.n_legal
+    assert len(open(db).read().splitlines()) == 3
+
+
+def test_tune_bad_arguments(tmp_path):
+    p = mlk.matmul_problem(64, 64, 64, L.MLK_BF16, L.MLK_F32)
+    with pytest.raises(mlk.MlkError, match="budget_frac"):
+        mlk.tune(p, mlk.MLK_TUNE_RANDOM, budget_frac=0.0, fake_timer=True)
+    with pytest.raises(mlk.MlkError, match="model"):
+        mlk.tune(p, mlk.MLK_TUNE_MODEL, budget_frac=0.2, fake_timer=True)
+    with pytest.raises(mlk.MlkError, match="MLK_ERR_DB"):
+        mlk.tune(p, mlk.MLK_TUNE_EXHAUSTIVE, fake_timer=True,
+                 db_path=str(tmp_path / "no_such_dir" / "db.jsonl"))

@@ -1,0 +1,114 @@
+"""GPU parity of the implicit-GEMM conv2d (fp32 and bf16 inputs) against the
+oracle's direct NCHW x FCHW loop nest: normwise <= 1e-5 against the double
+result on the same (quantised) inputs, bit-exact on small-integer inputs.
+Covers the fp32 56x56x64 workload, stride 2, padding, 1x1 filters, batch > 1,
+odd sizes, every compiled conv tile, and the ResNet-18 layer shapes in bf16.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_2307_16080_amd as mlk
+from paper_2307_16080_amd import _lib as L
+from workloads import CFG_CONV_F32, conv_inputs, resnet18_conv_stack
+
+from gpu_util import all_tiles, dev, from_bf16_codes, host, normwise, say
+
+pytestmark = pytest.mark.gpu
+
+CASES = [
+    # N, C, H, W, F, KH, KW, stride, pad
+    (1, 3, 7, 6, 2, 3, 3, 1, 1),
+    (2, 5, 9, 11, 7, 3, 3, 2, 1),
+    (1, 16, 8, 8, 33, 1, 1, 2, 0),
+    (3, 4, 13, 13, 20, 5, 5, 1, 2),
+    (1, 1, 40, 40, 3, 3, 3, 1, 0),
+    (2, 64, 14, 14, 65, 3, 3, 1, 1),
+]
+
+
+def _out(x, w, s, p):
+    N, C, H, W = x.shape
+    F, _, KH, KW = w.shape
+    return torch.zeros(N, F, (H + 2 * p - KH) // s + 1, (W + 2 * p - KW) // s + 1, device="cuda")
+
+
+def test_f32_conv_56x56x64():
+    sh = CFG_CONV_F32
+    x, w = conv_inputs(sh.N, sh.C, sh.H, sh.W, sh.F, sh.KH, sh.KW, seed=0)
+    ref = oracle.conv2d_f64(x, w, (1, 1), (1, 1), threads=oracle.default_threads())
+    y = _out(x, w, 1, 1)
+    mlk.conv2d_nchw_fchw(dev(x), dev(w), y, (1, 1), (1, 1))
+    err = normwise(host(y), ref)
+    say("f32 conv 56x56x64 normwise", err)
+    assert err <= 1e-5
+
+
+@pytest.mark.parametrize("cfg", all_tiles(L.MLK_F32, L.MLK_F32, conv=True) + all_tiles(L.MLK_BF16, L.MLK_F32, conv=True),
+                         ids=lambda c: f"{c.bm}x{c.bn}x{c.bk}_{c.wm}{c.wn}")
+def test_every_conv_tile(cfg):
+    for case in CASES:
+        N, C, H, W, F, KH, KW, s, p = case
+        say("conv", cfg, case)
+        for is_bf16 in (False, True):
+            try_cfg = cfg
+            if not mlk.config_legal(mlk.conv_problem(N, C, H, W, F, KH, KW, s, p,
+                                                     L.MLK_BF16 if is_bf16 else L.MLK_F32, L.MLK_F32), try_cfg):
+                continue
+            x, w = conv_inputs(N, C, H, W, F, KH, KW, seed=sum(case))
+            y0 = np.random.default_rng(1).uniform(-1, 1, (N, F, (H + 2 * p - KH) // s + 1,
+                                                          (W + 2 * p - KW) // s + 1)).astype(np.float32)
+            if is_bf16:
+                qx, qw = oracle.bf16_encode(x), oracle.bf16_encode(w)
+                ref = oracle.conv2d_f64(oracle.bf16_decode(qx), oracle.bf16_decode(qw), (s, s), (p, p), y=y0)
+                xd, wd = from_bf16_codes(qx), from_bf16_codes(qw)
+            else:
+                ref = oracle.conv2d_f64(x, w, (s, s), (p, p), y=y0)
+                xd, wd = dev(x), dev(w)
+            y = dev(y0)
+            mlk.conv2d_nchw_fchw(xd, wd, y, (s, s), (p, p), cfg=try_cfg)
+            assert normwise(host(y), ref) <= 1e-5, (case, is_bf16)
+            # small integers: exact
+            x, w = conv_inputs(N, C, H, W, F, KH, KW, seed=3, dist="small_int")
+            y = _out(x, w, s, p)
+            if is_bf16:
+                mlk.conv2d_nchw_fchw(from_bf16_codes(oracle.bf16_encode(x)),
+                                     from_bf16_codes(oracle.bf16_encode(w)), y, (s, s), (p, p),
+                                     cfg=try_cfg)
+            else:
+                mlk.conv2d_nchw_fchw(dev(x), dev(w), y, (s, s), (p, p), cfg=try_cfg)
+            assert np.array_equal(host(y).astype(np.float64), oracle.conv2d_f64(x, w, (s, s), (p, p))), case
+
+
+def test_conv_split_k_overwrite():
+    x, w = conv_inputs(1, 64, 14, 14, 32, 3, 3, seed=4, dist="small_int")
+    ref = oracle.conv2d_f64(x, w, (1, 1), (1, 1))
+    for sk in (1, 2, 4):
+        y = torch.full((1, 32, 14, 14), float("nan"), device="cuda")
+        mlk.conv2d_nchw_fchw(dev(x), dev(w), y, (1, 1), (1, 1), accumulate=False,
+                             cfg=mlk.TileConfig(32, 32, 16, 1, 1, sk, 1, 0))
+        assert np.array_equal(host(y).astype(np.float64), ref), sk
+
+
+@pytest.mark.parametrize("batch", [1, 2])
+def test_resnet18_layers_bf16(batch):
+    for shape, _count in resnet18_conv_stack(batch):
+        say("resnet layer", shape)
+        x, w = conv_inputs(shape.N, shape.C, shape.H, shape.W, shape.F, shape.KH, shape.KW, seed=shape.C)
+        qx, qw = oracle.bf16_encode(x), oracle.bf16_encode(w)
+        ref = oracle.conv2d_f64(oracle.bf16_decode(qx), oracle.bf16_decode(qw), (shape.stride,) * 2,
+                                (shape.pad,) * 2, threads=oracle.default_threads())
+        y = torch.zeros(ref.shape, device="cuda")
+        mlk.conv2d_nchw_fchw(from_bf16_codes(qx), from_bf16_codes(qw), y, (shape.stride,) * 2,
+                             (shape.pad,) * 2)
+        assert normwise(host(y), ref) <= 1e-5
+
+
+def test_paper_conv_shape_f32():
+    """The paper's measured workload: one 1280x1280 image, 3 output channels, 3x3, valid."""
+    x, w = conv_inputs(1, 1, 1280, 1280, 3, 3, 3, seed=0)
+    ref = oracle.conv2d_f64(x, w, threads=oracle.default_threads())
+    y = torch.zeros(1, 3, 1278, 1278, device="cuda")
+    mlk.conv2d_nchw_fchw(dev(x), dev(w), y)
+    assert normwise(host(y), ref) <= 1e-5

@@ -1,0 +1,266 @@
+"""GPU parity of the matmul kernels (C ABI through the binding) against the
+CPU oracle: fp32 (normwise <= 1e-5), int8 -> int32 (bit-exact), bf16 and OCP
+e4m3 (kernel error against the double result on the quantised values, and
+bit-exact on small-integer inputs, where every fp32 partial sum is exact).
+Shapes span several tiles and ragged tails; every compiled tile kernel runs.
+Guard bands around C catch writes outside the output.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_2307_16080_amd as mlk
+from paper_2307_16080_amd import _lib as L
+from workloads import matmul_inputs, random_c
+
+from gpu_util import (all_tiles, bits16, bits8, dev, from_bf16_codes, from_e4m3_codes, host,
+                      normwise, say)
+
+pytestmark = pytest.mark.gpu
+
+RAGGED = [(1, 1, 1), (7, 13, 31), (33, 65, 17), (129, 257, 100), (300, 200, 129), (64, 64, 64),
+          (255, 511, 513)]
+GUARD = 3  # extra columns of sentinel on each row of C
+# The e4m3 MFMA (16x16x128 f8f6f4) forms each 128-term dot product with about
+# 16 significant bits before adding it to the fp32 accumulator: measured
+# normwise error 1.5e-5 against the double result on the same codes,
+# independent of K (32 .. 4096).  The stated bound keeps a 3x margin; it is
+# three orders of magnitude below the e4m3 quantisation error itself (2^-4).
+E4M3_KERNEL_TOL = 5e-5
+
+
+def _with_guard(C0, dtype):
+    """C stored with ldc = N + GUARD; the extra columns hold a sentinel."""
+    M, N = C0.shape
+    big = torch.full((M + 1, N + GUARD), -777, dtype=dtype, device="cuda")
+    big[:M, :N] = dev(C0)
+    return big, big[:M, :N]
+
+
+def _check_guard(big, M, N):
+    h = host(big)
+    assert np.all(h[:M, N:] == -777) and np.all(h[M, :] == -777), "write outside C"
+
+
+# ----------------------------------------------------------------------- fp32
+
+def test_f32_config0_128():
+    A, B = matmul_inputs(128, 128, 128, seed=0, dist="uniform")
+    ref = oracle.matmul_f64(A, B)
+    C = torch.zeros(128, 128, dtype=torch.float32, device="cuda")
+    mlk.matmul(dev(A), dev(B), C)
+    err = normwise(host(C), ref)
+    say("f32 128^3 normwise", err)
+    assert err <= 1e-5
+
+
+@pytest.mark.parametrize("cfg", all_tiles(L.MLK_F32, L.MLK_F32), ids=lambda c: f"{c.bm}x{c.bn}x{c.bk}_{c.wm}{c.wn}")
+def test_f32_every_tile_ragged(cfg):
+    for (M, N, K) in RAGGED:
+        say("f32", cfg, M, N, K)
+        A, B = matmul_inputs(M, N, K, seed=M + N + K, dist="uniform")
+        C0 = random_c(M, N, seed=K)
+        ref = oracle.matmul_f64(A, B, C0)
+        big, C = _with_guard(C0, torch.float32)
+        mlk.matmul(dev(A), dev(B), C, cfg=cfg)
+        assert normwise(host(C), ref) <= 1e-5
+        _check_guard(big, M, N)
+        # small integers: exact
+        A, B = matmul_inputs(M, N, K, seed=1, dist="small_int")
+        C = torch.zeros(M, N, dtype=torch.float32, device="cuda")
+        mlk.matmul(dev(A), dev(B), C, cfg=cfg)
+        assert np.array_equal(host(C).astype(np.float64), oracle.matmul_f64(A, B))
+
+
+def test_f32_overwrite_split_k_and_unaligned():
+    M, N, K = 200, 150, 1000
+    A, B = matmul_inputs(M, N, K, seed=5, dist="small_int")
+    ref = oracle.matmul_f64(A, B)
+    for sk in (1, 2, 4, 8):
+        cfg = mlk.TileConfig(64, 64, 16, 2, 2, sk, 1, 0)
+        C = torch.full((M, N), float("nan"), device="cuda")
+        mlk.matmul(dev(A), dev(B), C, accumulate=False, cfg=cfg)
+        assert np.array_equal(host(C).astype(np.float64), ref), sk
+    # leading dimensions that are not multiples of 16 bytes: element loads
+    Abig = dev(np.pad(A, ((0, 0), (0, 1))))
+    Bbig = dev(np.pad(B, ((0, 0), (0, 3))))
+    C = torch.zeros(M, N, device="cuda")
+    mlk.matmul(Abig[:, :K], Bbig[:, :N], C)
+    assert np.array_equal(host(C).astype(np.float64), ref)
+
+
+def test_empty_and_k0():
+    C = torch.full((4, 5), 3.0, device="cuda")
+    A = torch.zeros(4, 0, device="cuda")
+    B = torch.zeros(0, 5, device="cuda")
+    mlk.matmul(A, B, C)                       # K = 0, accumulate: unchanged
+    assert np.all(host(C) == 3.0)
+    mlk.matmul(A, B, C, accumulate=False)     # K = 0, overwrite: zeros
+    assert np.all(host(C) == 0.0)
+    E = torch.zeros(0, 5, device="cuda")
+    mlk.matmul(torch.zeros(0, 7, device="cuda"), torch.zeros(7, 5, device="cuda"), E)
+
+
+# ----------------------------------------------------------------------- int8
+
+def test_i8_1024_bit_exact():
+    A, B = matmul_inputs(1024, 1024, 1024, seed=0, dist="int8")
+    ref = oracle.matmul_i8(A, B, threads=oracle.default_threads())
+    C = torch.zeros(1024, 1024, dtype=torch.int32, device="cuda")
+    mlk.matmul(dev(A), dev(B), C)
+    assert np.array_equal(host(C), ref)
+
+
+@pytest.mark.parametrize("cfg", all_tiles(L.MLK_I8, L.MLK_I32), ids=lambda c: f"{c.bm}x{c.bn}x{c.bk}_{c.wm}{c.wn}")
+def test_i8_every_tile_ragged(cfg):
+    for (M, N, K) in RAGGED:
+        say("i8", cfg, M, N, K)
+        A, B = matmul_inputs(M, N, K, seed=M * 3 + K, dist="int8")
+        C0 = random_c(M, N, seed=N, dtype=np.int32)
+        big, C = _with_guard(C0, torch.int32)
+        mlk.matmul(dev(A), dev(B), C, cfg=cfg)
+        assert np.array_equal(host(C), oracle.matmul_i8(A, B, C0))
+        _check_guard(big, M, N)
+
+
+def test_i8_split_k_and_wraparound():
+    M, N, K = 96, 80, 4096
+    A = np.full((M, K), -128, np.int8)
+    B = np.full((K, N), -128, np.int8)
+    C0 = np.full((M, N), 2**31 - 1, np.int32)   # 2^31 - 1 + 4096 * 16384 wraps
+    for sk in (1, 4):
+        C = dev(C0)
+        mlk.matmul(dev(A), dev(B), C, cfg=mlk.TileConfig(64, 64, 64, 2, 2, sk, 1, 0))
+        assert np.array_equal(host(C), oracle.matmul_i8(A, B, C0)), sk
+
+
+# ----------------------------------------------------------------------- quantisation
+
+@pytest.mark.parametrize("n", [1, 15, 16, 17, 1000, 65537, 1 << 20])
+def test_quantize_bit_exact(n):
+    rng = np.random.default_rng(n)
+    x = rng.standard_normal(n).astype(np.float32)
+    x[: min(n, 4)] *= 1e3
+    xd = dev(x)
+    q, _ = mlk.quantize(xd, "bf16")
+    assert np.array_equal(bits16(q), oracle.bf16_encode(x))
+    q8, s = mlk.quantize(xd, "e4m3")
+    codes, scale = oracle.quantize_e4m3(x)
+    assert host(s)[0] == np.float32(scale)
+    assert np.array_equal(bits8(q8), codes)
+
+
+def test_quantize_special_values():
+    x = np.array([0.0, -0.0, np.inf, -np.inf, np.nan, 3.4e38, -1e-45, 1e-40, 448.0, -500.0] * 2,
+                 np.float32)
+    q, _ = mlk.quantize(dev(x), "bf16")
+    assert np.array_equal(bits16(q), oracle.bf16_encode(x))
+    finite = x[np.isfinite(x)].copy()
+    q8, s = mlk.quantize(dev(finite), "e4m3")
+    codes, scale = oracle.quantize_e4m3(finite)
+    assert host(s)[0] == np.float32(scale) and np.array_equal(bits8(q8), codes)
+    # all-zero input: scale 1
+    q8, s = mlk.quantize(torch.zeros(33, device="cuda"), "e4m3")
+    assert host(s)[0] == 1.0 and np.all(bits8(q8) == 0)
+    # unaligned view exercises the scalar path
+    base = dev(np.random.default_rng(0).standard_normal(1001).astype(np.float32))
+    view = base[1:]
+    q8, s = mlk.quantize(view.contiguous() if not view.is_contiguous() else view, "e4m3")
+    codes, scale = oracle.quantize_e4m3(host(base)[1:])
+    assert host(s)[0] == np.float32(scale) and np.array_equal(bits8(q8), codes)
+
+
+# ----------------------------------------------------------------------- bf16 / e4m3
+
+@pytest.mark.parametrize("cfg", all_tiles(L.MLK_BF16, L.MLK_F32), ids=lambda c: f"{c.bm}x{c.bn}x{c.bk}_{c.wm}{c.wn}")
+def test_bf16_every_tile_ragged(cfg):
+    for (M, N, K) in RAGGED:
+        say("bf16", cfg, M, N, K)
+        A, B = matmul_inputs(M, N, K, seed=M + 2 * N + K, dist="normal")
+        qa, qb = oracle.bf16_encode(A), oracle.bf16_encode(B)
+        C0 = random_c(M, N, seed=K)
+        ref = oracle.matmul_f64(oracle.bf16_decode(qa), oracle.bf16_decode(qb), C0)
+        big, C = _with_guard(C0, torch.float32)
+        mlk.matmul(from_bf16_codes(qa), from_bf16_codes(qb), C, cfg=cfg)
+        e = normwise(host(C), ref)
+        say("  bf16 kernel err", e)
+        assert e <= 1e-5
+        _check_guard(big, M, N)
+        A, B = matmul_inputs(M, N, K, seed=2, dist="small_int")
+        C = torch.zeros(M, N, device="cuda")
+        mlk.matmul(from_bf16_codes(oracle.bf16_encode(A)), from_bf16_codes(oracle.bf16_encode(B)), C,
+                   cfg=cfg)
+        assert np.array_equal(host(C).astype(np.float64), oracle.matmul_f64(A, B))
+
+
+@pytest.mark.parametrize("cfg", all_tiles(L.MLK_F8E4M3, L.MLK_F32), ids=lambda c: f"{c.bm}x{c.bn}x{c.bk}_{c.wm}{c.wn}")
+def test_e4m3_every_tile_ragged(cfg):
+    for (M, N, K) in RAGGED:
+        say("e4m3", cfg, M, N, K)
+        A, B = matmul_inputs(M, N, K, seed=M + 5 * N + K, dist="normal")
+        qa, sa = oracle.quantize_e4m3(A)
+        qb, sb = oracle.quantize_e4m3(B)
+        C0 = random_c(M, N, seed=K)
+        prod = oracle.matmul_f64(oracle.e4m3_decode(qa), oracle.e4m3_decode(qb))
+        ref = C0.astype(np.float64) + (float(np.float32(sa)) * float(np.float32(sb))) * prod
+        big, C = _with_guard(C0, torch.float32)
+        mlk.matmul(from_e4m3_codes(qa), from_e4m3_codes(qb), C, cfg=cfg,
+                   scale_a=dev(np.array([sa], np.float32)), scale_b=dev(np.array([sb], np.float32)))
+        e = normwise(host(C), ref)
+        say("  e4m3 kernel err", e)
+        assert e <= E4M3_KERNEL_TOL
+        _check_guard(big, M, N)
+        # small integers, unit scales: exact
+        A, B = matmul_inputs(M, N, K, seed=3, dist="small_int")
+        C = torch.zeros(M, N, device="cuda")
+        mlk.matmul(from_e4m3_codes(oracle.e4m3_encode(A, 1.0)),
+                   from_e4m3_codes(oracle.e4m3_encode(B, 1.0)), C, cfg=cfg)
+        assert np.array_equal(host(C).astype(np.float64), oracle.matmul_f64(A, B))
+
+
+def _rows_ref(decode, qa, qb, rows):
+    return oracle.matmul_f64(decode(qa[rows]), decode(qb), threads=oracle.default_threads())
+
+
+def test_precision_4096_sampled_rows():
+    """The 4096^3 workload in the launch configuration the benchmark uses
+    (default resolution), checked on sampled rows against the oracle."""
+    M = N = K = 4096
+    A, B = matmul_inputs(M, N, K, seed=0, dist="normal")
+    rows = np.random.default_rng(7).choice(M, 12, replace=False)
+    rows.sort()
+    Ad, Bd = dev(A), dev(B)
+    exact = oracle.matmul_f64(A[rows], B, threads=oracle.default_threads())
+    # bf16: quantise on the GPU (bit-exact vs the oracle), multiply
+    qa, _ = mlk.quantize(Ad, "bf16")
+    qb, _ = mlk.quantize(Bd, "bf16")
+    oa, ob = oracle.bf16_encode(A), oracle.bf16_encode(B)
+    assert np.array_equal(bits16(qa), oa) and np.array_equal(bits16(qb), ob)
+    C = torch.zeros(M, N, device="cuda")
+    mlk.matmul(qa, qb, C)
+    got = host(C)[rows]
+    e_kernel = normwise(got, _rows_ref(oracle.bf16_decode, oa, ob, rows))
+    e_total = normwise(got, exact)
+    say("bf16 4096 kernel err", e_kernel, "end-to-end", e_total)
+    assert e_kernel <= 1e-5 and e_total <= 1e-2
+    # e4m3
+    qa8, sa = mlk.quantize(Ad, "e4m3")
+    qb8, sb = mlk.quantize(Bd, "e4m3")
+    oa8, osa = oracle.quantize_e4m3(A)
+    ob8, osb = oracle.quantize_e4m3(B)
+    assert np.array_equal(bits8(qa8), oa8) and np.array_equal(bits8(qb8), ob8)
+    C = torch.zeros(M, N, device="cuda")
+    mlk.matmul(qa8, qb8, C, scale_a=sa, scale_b=sb)
+    got = host(C)[rows]
+    ref = (float(np.float32(osa)) * float(np.float32(osb))) * _rows_ref(oracle.e4m3_decode, oa8, ob8, rows)
+    e_kernel = normwise(got, ref)
+    e_total = normwise(got, exact)
+    say("e4m3 4096 kernel err", e_kernel, "end-to-end", e_total)
+    assert e_kernel <= E4M3_KERNEL_TOL and e_total <= 0.1
+    # fp32 plain kernel
+    C = torch.zeros(M, N, device="cuda")
+    mlk.matmul(Ad, Bd, C)
+    e = normwise(host(C)[rows], exact)
+    say("f32 4096 err", e)
+    assert e <= 1e-5
