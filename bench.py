@@ -1,0 +1,272 @@
+"""Benchmark: tuned bf16 matmul C[4096,4096] += A[4096,4096] B[4096,4096] on one MI355X.
+
+One step = one tuned bf16 GEMM launch (fp32 accumulation, C += A B) with A and
+B already resident in HBM as bf16 (quantised from seeded normal(0, 1) fp32 by
+the library's quantise kernel before timing).  Prints ONE JSON line with the
+throughput, the roofline of the GEMM kernel, the CPU oracle timed on this
+host (whose rows also give the error of the bf16 / fp32 / e4m3 results
+against the double-precision product of the fp32 inputs), and the other
+hot-path rows measured in the same run (fp32 and e4m3 GEMMs at the same size,
+quantisation, int8 1024^3, the fp32 conv, the batched GEMMs and the ResNet-18
+conv stack).  After the report, one plain 256 MiB device copy runs as the
+reference kernel for HBM byte counters.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--quick] [--no-cpu]
+                    [--tile bm,bn,bk,wm,wn,split_k,group_m,xcd_remap]
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK = {"bf16": 2516.6, "fp8": 5033.2, "i8": 5033.2, "f32": 157.3}  # dense TFLOP/s (TOPS)
+COPY_BYTES = 256 << 20  # the reference copy: bytes read (and written)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--quick", action="store_true", help="skip the secondary rows")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--tile", type=str, default="", help="fixed tile configuration (skips the search)")
+    return ap.parse_args()
+
+
+def source_hash():
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2307_16080_amd", "csrc")
+    for name in sorted(os.listdir(csrc)):
+        with open(os.path.join(csrc, name), "rb") as f:
+            h.update(name.encode() + f.read())
+    return h.hexdigest()[:16]
+
+
+def main():
+    args = parse()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print(json.dumps({"error": "this build runs on one GPU only: the kernels work on one "
+                                   "device's share and no multi-GPU path exists; run with --gpus 1"}))
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_2307_16080_amd as mlk
+    from paper_2307_16080_amd import _lib as L
+    from workloads import (CFG_CONV_F32, batched_inputs, batched_shapes, conv_inputs, matmul_inputs,
+                           resnet18_conv_stack)
+
+    torch.cuda.set_device(0)
+    stream = torch.cuda.current_stream()
+
+    def log(*a):
+        print(*a, file=sys.stderr, flush=True)
+
+    def time_us(fn, iters, warm=3):
+        for _ in range(warm):
+            fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(iters):
+            fn()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) * 1e3 / iters
+
+    M = N = K = 4096
+    flops = 2.0 * M * N * K
+    A32, B32 = matmul_inputs(M, N, K, seed=0, dist="normal")
+    Ad, Bd = torch.from_numpy(A32).cuda(), torch.from_numpy(B32).cuda()
+    qa, _ = mlk.quantize(Ad, "bf16")
+    qb, _ = mlk.quantize(Bd, "bf16")
+    C = torch.zeros(M, N, dtype=torch.float32, device="cuda")
+
+    # tile configuration: exhaustive search over the legal space (not timed as a step)
+    t0 = time.time()
+    prob = mlk.matmul_problem(M, N, K, L.MLK_BF16, L.MLK_F32, accumulate=True)
+    if args.tile:
+        best = mlk.TileConfig(*[int(v) for v in args.tile.split(",")])
+    else:
+        best, rep, _ = mlk.tune(prob, mlk.MLK_TUNE_EXHAUSTIVE, reps=5, warmup=2)
+        log(f"tuned bf16 {M}^3: {best} {rep.best_us:.1f} us over {rep.n_legal} configs in {time.time() - t0:.1f} s")
+
+    # ---------------------------------------------------------------- timed region
+    for _ in range(args.warmup):
+        mlk.matmul(qa, qb, C, cfg=best)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t_start = time.perf_counter()
+    e0.record(stream)
+    for _ in range(args.steps):
+        mlk.matmul(qa, qb, C, cfg=best)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t_start
+    kernel_us = e0.elapsed_time(e1) * 1e3 / args.steps
+    ms_per_step = wall * 1e3 / args.steps
+    value = flops / (ms_per_step * 1e-3) / 1e12
+    achieved = flops / (kernel_us * 1e-6) / 1e12
+    log(f"bf16 GEMM: {kernel_us:.1f} us/launch (events), {ms_per_step * 1e3:.1f} us/step (wall)")
+
+    # one clean launch of the timed configuration, kept for the error report
+    C.zero_()
+    mlk.matmul(qa, qb, C, cfg=best)
+    outputs = {"bf16": C.cpu().numpy()}
+
+    # traffic from committed rocprofv3 counter runs, if they match these sources
+    traffic = None
+    tpath = os.path.join(ROOT, "profiles", "bf16_gemm_4096_traffic.json")
+    if os.path.exists(tpath):
+        with open(tpath) as f:
+            t = json.load(f)
+        if t.get("source_hash") == source_hash() and t.get("config") == list(best.as_tuple()):
+            traffic = t.get("bytes_per_launch")
+
+    result = {
+        "metric": "GEMM/conv TFLOP/s and % MFMA roofline; tuned vs plain fp32 at stated rel err",
+        "value": round(value, 2),
+        "unit": "TFLOP/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "bf16",
+        "data": "synthetic (seeded normal(0,1), quantised to bf16 on the GPU)",
+        "config": {"workload": "linalg.matmul M=N=K=4096, bf16 inputs, fp32 accumulate into C (C += A B), tuned tile",
+                   "tile": list(best.as_tuple()), "global_batch": 1, "parallelism": "none (1 GPU)"},
+        "roofline": {"bound": "mfma", "achieved": round(achieved, 2), "peak": PEAK["bf16"],
+                     "unit": "TFLOP/s", "frac": round(achieved / PEAK["bf16"], 4), "traffic": traffic},
+    }
+
+    # ---------------------------------------------------------------- other rows
+    rows_out = {}
+    if not args.quick:
+        # fp32 plain kernel at the same size (the comparator)
+        pf = mlk.matmul_problem(M, N, K, L.MLK_F32, L.MLK_F32)
+        bf, _, _ = mlk.tune(pf, mlk.MLK_TUNE_EXHAUSTIVE, reps=3, warmup=1)
+        us = time_us(lambda: mlk.matmul(Ad, Bd, C, cfg=bf), 10)
+        rows_out["matmul_f32_4096"] = {"us": round(us, 1), "TFLOP/s": round(flops / us / 1e6, 1),
+                                       "frac_peak": round(flops / us / 1e6 / PEAK["f32"], 3), "tile": list(bf.as_tuple())}
+        C.zero_()
+        mlk.matmul(Ad, Bd, C, cfg=bf)
+        outputs["f32"] = C.cpu().numpy()
+        rows_out["bf16_speedup_over_f32"] = round(rows_out["matmul_f32_4096"]["us"] / kernel_us, 2)
+        # e4m3
+        qa8, sa = mlk.quantize(Ad, "e4m3")
+        qb8, sb = mlk.quantize(Bd, "e4m3")
+        p8 = mlk.matmul_problem(M, N, K, L.MLK_F8E4M3, L.MLK_F32)
+        b8, _, _ = mlk.tune(p8, mlk.MLK_TUNE_EXHAUSTIVE, reps=5, warmup=2)
+        us = time_us(lambda: mlk.matmul(qa8, qb8, C, cfg=b8, scale_a=sa, scale_b=sb), 20)
+        C.zero_()
+        mlk.matmul(qa8, qb8, C, cfg=b8, scale_a=sa, scale_b=sb)
+        outputs["e4m3"] = C.cpu().numpy()
+        rows_out["matmul_e4m3_4096"] = {"us": round(us, 1), "TFLOP/s": round(flops / us / 1e6, 1),
+                                        "frac_peak": round(flops / us / 1e6 / PEAK["fp8"], 3), "tile": list(b8.as_tuple())}
+        # quantisation (HBM-bound)
+        us_q16 = time_us(lambda: mlk.quantize(Ad, "bf16", q=qa), 20)
+        us_q8 = time_us(lambda: mlk.quantize(Ad, "e4m3", q=qa8, scale=sa), 20)
+        n = M * K
+        rows_out["quantize_bf16"] = {"us": round(us_q16, 2), "GB/s": round(6 * n / us_q16 / 1e3, 1)}
+        rows_out["quantize_e4m3"] = {"us": round(us_q8, 2), "GB/s": round(9 * n / us_q8 / 1e3, 1)}
+        # int8 1024^3, bit-exact
+        A8, B8 = matmul_inputs(1024, 1024, 1024, seed=0, dist="int8")
+        a8, b8_ = torch.from_numpy(A8).cuda(), torch.from_numpy(B8).cuda()
+        c8 = torch.zeros(1024, 1024, dtype=torch.int32, device="cuda")
+        pi = mlk.matmul_problem(1024, 1024, 1024, L.MLK_I8, L.MLK_I32)
+        bi, _, _ = mlk.tune(pi, mlk.MLK_TUNE_EXHAUSTIVE, reps=10, warmup=2)
+        us = time_us(lambda: mlk.matmul(a8, b8_, c8, cfg=bi), 50)
+        rows_out["matmul_i8_1024"] = {"us": round(us, 2), "TOPS": round(2 * 1024 ** 3 / us / 1e6, 1),
+                                      "tile": list(bi.as_tuple())}
+        # fp32 conv 1x64x56x56, 64 3x3 filters, s1 p1
+        cs = CFG_CONV_F32
+        x, w = conv_inputs(cs.N, cs.C, cs.H, cs.W, cs.F, cs.KH, cs.KW, seed=0)
+        xd, wd = torch.from_numpy(x).cuda(), torch.from_numpy(w).cuda()
+        y = torch.zeros(1, 64, 56, 56, device="cuda")
+        pc = mlk.conv_problem(1, 64, 56, 56, 64, 3, 3, 1, 1, L.MLK_F32, L.MLK_F32)
+        bc, _, _ = mlk.tune(pc, mlk.MLK_TUNE_EXHAUSTIVE, reps=10, warmup=2)
+        us = time_us(lambda: mlk.conv2d_nchw_fchw(xd, wd, y, (1, 1), (1, 1), cfg=bc), 50)
+        rows_out["conv_f32_56x56x64"] = {"us": round(us, 2), "TFLOP/s": round(cs.flops() / us / 1e6, 2),
+                                         "tile": list(bc.as_tuple())}
+        # 256 uneven bf16 GEMMs
+        shapes = batched_shapes(256, seed=0)
+        ins = batched_inputs(shapes, seed=1)
+        probs = []
+        for (a, b), (m, nn, k) in zip(ins, shapes):
+            qa_, _ = mlk.quantize(torch.from_numpy(a).cuda(), "bf16")
+            qb_, _ = mlk.quantize(torch.from_numpy(b).cuda(), "bf16")
+            probs.append((qa_, qb_, torch.zeros(m, nn, device="cuda")))
+        bflops = sum(2.0 * m * nn * k for m, nn, k in shapes)
+        pb = mlk.batched_problem(shapes, L.MLK_BF16, L.MLK_F32)
+        bb, _, _ = mlk.tune(pb, mlk.MLK_TUNE_EXHAUSTIVE, reps=5, warmup=1)
+        us_pg = time_us(lambda: mlk.batched_matmul(probs, cfg=bb, persistent=True, graph=True), 10)
+        us_loop = time_us(lambda: mlk.batched_matmul(probs, cfg=bb), 5)
+        us_g = time_us(lambda: mlk.batched_matmul(probs, cfg=bb, graph=True), 5)
+        rows_out["batched_256_bf16"] = {"gflop": round(bflops / 1e9, 2), "tile": list(bb.as_tuple()),
+                                        "persistent_graph_us": round(us_pg, 1),
+                                        "per_gemm_launches_us": round(us_loop, 1),
+                                        "graph_of_launches_us": round(us_g, 1),
+                                        "TFLOP/s": round(bflops / us_pg / 1e6, 1)}
+        # ResNet-18 conv stack, batch 32, bf16 (per-layer tuned, default launch uses the tuned entry)
+        stack_us, stack_flops = 0.0, 0.0
+        for shape, count in resnet18_conv_stack(32):
+            xs = torch.randn(shape.N, shape.C, shape.H, shape.W, device="cuda")
+            ws = torch.randn(shape.F, shape.C, shape.KH, shape.KW, device="cuda")
+            qx, _ = mlk.quantize(xs, "bf16")
+            qw, _ = mlk.quantize(ws, "bf16")
+            ho, wo = shape.out_hw()
+            ys = torch.zeros(shape.N, shape.F, ho, wo, device="cuda")
+            pr = mlk.conv_problem(shape.N, shape.C, shape.H, shape.W, shape.F, shape.KH, shape.KW,
+                                  shape.stride, shape.pad, L.MLK_BF16, L.MLK_F32)
+            br, _, _ = mlk.tune(pr, mlk.MLK_TUNE_EXHAUSTIVE, reps=3, warmup=1)
+            us = time_us(lambda: mlk.conv2d_nchw_fchw(qx, qw, ys, (shape.stride,) * 2, (shape.pad,) * 2, cfg=br), 10)
+            stack_us += us * count
+            stack_flops += shape.flops() * count
+        rows_out["resnet18_stack_b32_bf16"] = {"us": round(stack_us, 1), "TFLOP/s": round(stack_flops / stack_us / 1e6, 1)}
+    result["rows"] = rows_out
+
+    # ---------------------------------------------------------------- CPU oracle baseline
+    # The oracle (double-precision loop nest) on a bounded sample of the same
+    # workload: the first `nrows` rows of C = A B, grown until ~10 s of CPU
+    # work.  Its rows double as the reference for the error report.
+    if not args.no_cpu:
+        import oracle
+        threads = oracle.default_threads()
+        nrows = 16
+        while True:
+            t0 = time.perf_counter()
+            ref = oracle.matmul_f64(A32[:nrows], B32, threads=threads)
+            dt = time.perf_counter() - t0
+            if dt >= 8.0 or nrows >= 4096:
+                break
+            nrows = min(4096, max(nrows * 2, int(nrows * 10.0 / max(dt, 1e-3))))
+        result["cpu_baseline"] = {"value": round(2.0 * nrows * N * K / dt / 1e12, 6), "unit": "TFLOP/s",
+                                  "cores": threads, "kind": "oracle",
+                                  "sample": f"REF64 (double) oracle matmul of the first {nrows} rows of the "
+                                            f"4096x4096x4096 workload, {dt:.1f} s on {threads} threads"}
+        rn = np.linalg.norm(ref)
+        result["errors_vs_ref64_fp32_inputs"] = {
+            k: float(np.linalg.norm(v[:nrows].astype(np.float64) - ref) / rn) for k, v in outputs.items()}
+    result["source_hash"] = source_hash()
+    print(json.dumps(result), flush=True)
+
+    # reference kernel for the HBM byte counters: a plain copy of known size
+    src = torch.empty(COPY_BYTES // 4, dtype=torch.float32, device="cuda").fill_(1.0)
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    dst.copy_(src)
+    torch.cuda.synchronize()
+
+
+if __name__ == "__main__":
+    main()

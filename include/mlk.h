@@ -76,6 +76,12 @@ typedef enum {
  *   group_m    workgroup raster: tiles are visited in column bands of group_m
  *              tile-rows (1 = row-major order)
  *   xcd_remap  1: map consecutive tiles to the same XCD (shared L2)
+ *   stages     0: register-staged kernel (operands pass through registers
+ *              on their way to a double-buffered LDS tile; any shape and
+ *              alignment).  2..4: direct-to-LDS kernel (bf16 only) whose
+ *              loads go from HBM straight into a ring of `stages` LDS
+ *              buffers; needs K % bk == 0, 16-byte aligned A and B and row
+ *              pitches that are multiples of 16 bytes.
  * A zeroed struct or a NULL pointer means "choose": the tuning database
  * entry for this problem if one was loaded, else a built-in heuristic.
  */
@@ -85,6 +91,7 @@ typedef struct {
     int32_t split_k;
     int32_t group_m;
     int32_t xcd_remap;
+    int32_t stages;
 } mlk_tile_config;
 
 /*

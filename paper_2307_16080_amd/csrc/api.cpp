@@ -65,7 +65,7 @@ const std::vector<const KernelEntry*>& registry() {
     static std::vector<const KernelEntry*> all = [] {
         std::vector<const KernelEntry*> v;
         const KernelEntry* (*tables[])(int*) = {kernels_f32, kernels_bf16, kernels_i8, kernels_f8,
-                                                kernels_conv};
+                                                kernels_conv, kernels_fast};
         for (auto t : tables) {
             int n = 0;
             const KernelEntry* e = t(&n);
@@ -79,7 +79,7 @@ const std::vector<const KernelEntry*>& registry() {
 const KernelEntry* find_kernel(int dt, int conv, const mlk_tile_config& c) {
     for (const KernelEntry* e : registry())
         if (e->dt == dt && e->conv == conv && e->bm == c.bm && e->bn == c.bn && e->bk == c.bk &&
-            e->wm == c.wm && e->wn == c.wn)
+            e->wm == c.wm && e->wn == c.wn && e->stages == c.stages)
             return e;
     return nullptr;
 }
@@ -171,11 +171,20 @@ mlk_status shape_of_problem(const mlk_problem* p, Shape* s) {
 
 static int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
+// Shapes the direct-to-LDS kernels accept: whole K stages, packed rows that
+// are multiples of 16 bytes, operands below 2 GiB (32-bit buffer offsets).
+static bool fast_shape_ok(const Shape& s, int bk) {
+    return s.K > 0 && s.K % bk == 0 && (s.K * 2) % 16 == 0 && (s.N * 2) % 16 == 0 &&
+           s.M * s.K * 2 < ((int64_t)1 << 31) && s.K * s.N * 2 < ((int64_t)1 << 31);
+}
+
 mlk_status check_config(const Shape& s, int op, const mlk_tile_config& c) {
     const KernelEntry* e = find_kernel(s.dt, s.conv, c);
     if (!e)
-        return fail(MLK_ERR_CONFIG, "no compiled kernel for tile %dx%dx%d waves %dx%d (dtype %d%s)",
-                    c.bm, c.bn, c.bk, c.wm, c.wn, s.dt, s.conv ? ", conv" : "");
+        return fail(MLK_ERR_CONFIG, "no compiled kernel for tile %dx%dx%d waves %dx%d stages %d (dtype %d%s)",
+                    c.bm, c.bn, c.bk, c.wm, c.wn, c.stages, s.dt, s.conv ? ", conv" : "");
+    if (e->stages && (op == MLK_OP_BATCHED || !fast_shape_ok(s, e->bk)))
+        return fail(MLK_ERR_CONFIG, "direct-to-LDS tile needs K %% %d == 0 and 16-byte rows", e->bk);
     if (c.split_k < 1 || c.split_k > 64) return fail(MLK_ERR_CONFIG, "split_k must be in [1, 64]");
     const int64_t stages = cdiv(std::max<int64_t>(s.K, 1), c.bk);
     if (c.split_k > 1 && c.split_k > stages)
@@ -193,6 +202,7 @@ std::vector<mlk_tile_config> enumerate_configs(const mlk_problem* p, const Shape
     for (const KernelEntry* e : registry()) {
         if (e->dt != s.dt || e->conv != s.conv) continue;
         if (batched && !e->persist) continue;
+        if (e->stages && !fast_shape_ok(s, e->bk)) continue;
         // a tile at least twice the problem in a dimension only adds padding
         if (e->bm > 32 && e->bm >= 2 * s.M) continue;
         if (e->bn > 32 && e->bn >= 2 * s.N) continue;
@@ -207,7 +217,7 @@ std::vector<mlk_tile_config> enumerate_configs(const mlk_problem* p, const Shape
                 for (int xcd : {0, 1}) {
                     const int64_t nblk = tiles * sk;
                     if (xcd == 1 && (batched || nblk < 64 || nblk % 8 != 0)) continue;
-                    mlk_tile_config c{e->bm, e->bn, e->bk, e->wm, e->wn, sk, gm, xcd};
+                    mlk_tile_config c{e->bm, e->bn, e->bk, e->wm, e->wn, sk, gm, xcd, e->stages};
                     out.push_back(c);
                 }
             }
@@ -222,7 +232,7 @@ mlk_tile_config heuristic_config(const Shape& s, int op) {
     const KernelEntry* best = nullptr;
     const KernelEntry* smallest = nullptr;
     for (const KernelEntry* e : registry()) {
-        if (e->dt != s.dt || e->conv != s.conv) continue;
+        if (e->dt != s.dt || e->conv != s.conv || e->stages) continue;
         if (op == MLK_OP_BATCHED && !e->persist) continue;
         if (!smallest || e->bm * e->bn < smallest->bm * smallest->bn ||
             (e->bm * e->bn == smallest->bm * smallest->bn && e->bk > smallest->bk))
@@ -235,7 +245,7 @@ mlk_tile_config heuristic_config(const Shape& s, int op) {
             best = e;
     }
     const KernelEntry* e = best ? best : smallest;
-    mlk_tile_config c{e->bm, e->bn, e->bk, e->wm, e->wn, 1, 1, 0};
+    mlk_tile_config c{e->bm, e->bn, e->bk, e->wm, e->wn, 1, 1, 0, 0};
     if (!best && op != MLK_OP_BATCHED) {
         // too few tiles: split K while each split keeps >= 4 stages
         const int64_t tiles = cdiv(std::max<int64_t>(s.M, 1), e->bm) * cdiv(std::max<int64_t>(s.N, 1), e->bn);
@@ -355,6 +365,9 @@ mlk_status launch_dense(const Shape& s, const void* A, int64_t lda, const void* 
     g.scale_b = sb;
     g.vec_a = ((uintptr_t)A % 16 == 0) && ((lda * es) % 16 == 0);
     g.vec_b = ((uintptr_t)B % 16 == 0) && ((ldb * es) % 16 == 0);
+    if (e->stages && !(g.vec_a && g.vec_b && ((s.M - 1) * lda + s.K) * es < ((int64_t)1 << 31) &&
+                       ((s.K - 1) * ldb + s.N) * es < ((int64_t)1 << 31)))
+        return fail(MLK_ERR_CONFIG, "direct-to-LDS tile needs 16-byte aligned operands and row pitches");
     return run_gemm(e, g, s, C, s.M, s.N, ldc, st);
 }
 
@@ -465,6 +478,13 @@ mlk_status mlk_matmul(mlk_dtype in, mlk_dtype out, int64_t M, int64_t N, int64_t
     st = resolve(p, s, cfg, &c);
     if (st != MLK_OK) return st;
     if (M == 0 || N == 0) return MLK_OK;
+    if (c.stages && cfg_is_zero(cfg)) {
+        // a tuned direct-to-LDS choice needs aligned operands; otherwise use the heuristic
+        const int es = esize_in(s.dt);
+        const bool aligned = (uintptr_t)A % 16 == 0 && (uintptr_t)B % 16 == 0 &&
+                             (lda * es) % 16 == 0 && (ldb * es) % 16 == 0;
+        if (!aligned) c = heuristic_config(s, p.op);
+    }
     return launch_dense(s, A, lda, B, ldb, C, ldc, scale_a, scale_b, c, (hipStream_t)stream);
 }
 

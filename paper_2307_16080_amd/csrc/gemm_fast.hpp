@@ -1,0 +1,222 @@
+// gemm_fast.hpp -- the bf16 matmul main loop for large, aligned problems on
+// gfx950: operands go from HBM straight into LDS (buffer loads with the LDS
+// destination bit, no register staging), B stays in its row-major
+// (N-contiguous) layout in LDS and is transposed on the way out by the
+// gfx950 LDS transpose read (ds_read_b64_tr_b16), and the K loop keeps
+// STAGES-1 stages of loads in flight behind the MFMAs.
+//
+// What is computed is still linalg.matmul, C[M,N] (+)= A[M,K] * B[K,N]
+// (paper Sec. 2.1, listing "linalg-matmul"), with fp32 accumulation.
+//
+// Requirements (checked on the host): K % BK == 0, A, B 16-byte aligned with
+// row pitches that are multiples of 16 bytes, each operand < 2 GiB.  M and N
+// are arbitrary: rows past the end of an operand read as zero (buffer range
+// check) and columns past N only feed outputs that are never stored.
+//
+// LDS layout per stage: A as BM rows of BK bf16 (128 bytes for BK = 64), the
+// 16-byte chunk c of row r stored at chunk c ^ fa(r); B as BK rows of BN bf16,
+// the 16-byte chunk c of row k stored at chunk c ^ fb(k).  The XOR patterns
+// spread the lanes of one LDS read over distinct banks.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "gemm_tile.hpp"
+
+namespace mlk {
+
+typedef __bf16 bf4_t __attribute__((ext_vector_type(4)));
+typedef int32_t i32x4_t __attribute__((ext_vector_type(4)));
+
+// LLVM intrinsic: buffer load whose data goes to LDS at M0 + lane * size.
+__device__ void llvm_buffer_load_lds(i32x4_t rsrc, __attribute__((address_space(3))) uint32_t* lds,
+                                     int size, int voffset, int soffset, int offset,
+                                     int aux) __asm("llvm.amdgcn.raw.buffer.load.lds");
+
+__device__ inline i32x4_t make_rsrc(const void* base, uint32_t bytes) {
+    const uint64_t b = (uint64_t)base;
+    i32x4_t r;
+    r[0] = (int32_t)(uint32_t)(b & 0xFFFFFFFFu);
+    r[1] = (int32_t)(uint32_t)(b >> 32);  // stride 0
+    r[2] = (int32_t)bytes;                // range: larger offsets read zero
+    r[3] = 0x00020000;                    // raw buffer, 32-bit data format
+    return r;
+}
+
+// s_waitcnt with only the vector-memory counter constrained (gfx9 encoding)
+template <int N>
+__device__ inline void wait_vmcnt() {
+    static_assert(N >= 0 && N < 64, "vmcnt range");
+    __builtin_amdgcn_s_waitcnt((N & 0xF) | ((N >> 4) << 14) | 0x70 | 0xF00);
+}
+
+__device__ inline int fa(int r) { return (r & 7) ^ ((r >> 3) & 1); }
+__device__ inline int fb(int k) { return ((k & 3) << 1) | (((k >> 3) & 1) << 3); }
+
+template <int BM, int BN, int WM, int WN, int STAGES>
+struct FastBf16 {
+    static constexpr int BK = 64;                  // bf16 per A row per stage
+    static constexpr int NW = WM * WN;
+    static constexpr int NT = 64 * NW;
+    static constexpr int A_ROW = BK * 2;           // 128 bytes
+    static constexpr int B_ROW = BN * 2;
+    static constexpr int A_STAGE = BM * A_ROW;
+    static constexpr int B_STAGE = BK * B_ROW;
+    static constexpr int STAGE = A_STAGE + B_STAGE;
+    static constexpr int LDS_BYTES = STAGES * STAGE;
+    static constexpr int A_SLABS = A_STAGE / 1024;  // one wave-wide 16-byte load fills a slab
+    static constexpr int B_SLABS = B_STAGE / 1024;
+    static constexpr int NA = A_SLABS / NW;         // per wave per stage
+    static constexpr int NB = B_SLABS / NW;
+    static constexpr int LOADS = NA + NB;
+    static constexpr int WTM = BM / WM, WTN = BN / WN;
+    static constexpr int TM = WTM / 16, TN = WTN / 16;
+    static constexpr int A_ROWS_PER_SLAB = 1024 / A_ROW;  // 8
+    static constexpr int B_ROWS_PER_SLAB = 1024 / B_ROW;
+    static constexpr int B_CHUNKS = B_ROW / 16;
+
+    static_assert(A_SLABS % NW == 0 && B_SLABS % NW == 0, "slabs must divide among waves");
+    static_assert(B_CHUNKS >= 16, "B rows need at least 16 chunks for the swizzle");
+    static_assert(LDS_BYTES <= 160 * 1024, "LDS budget");
+    static_assert(WTM % 16 == 0 && WTN % 16 == 0, "wave tile");
+    static_assert(STAGES >= 2 && (STAGES - 1) * LOADS < 64, "pipeline depth");
+
+    __device__ static inline void issue_stage(const i32x4_t& ra, const i32x4_t& rb,
+                                              const int* voff_a, const int* voff_b, int64_t k0,
+                                              int64_t ldb, uint8_t* stage, int wave) {
+        typedef __attribute__((address_space(3))) uint32_t* lp;
+        const int sa = (int)(k0 * 2);
+        const int sb = (int)(k0 * ldb * 2);
+#pragma unroll
+        for (int i = 0; i < NA; ++i) {
+            const int slab = wave + i * NW;
+            llvm_buffer_load_lds(ra, (lp)(stage + slab * 1024), 16, voff_a[i], sa, 0, 0);
+        }
+#pragma unroll
+        for (int i = 0; i < NB; ++i) {
+            const int slab = wave + i * NW;
+            llvm_buffer_load_lds(rb, (lp)(stage + A_STAGE + slab * 1024), 16, voff_b[i], sb, 0, 0);
+        }
+    }
+
+    __device__ static inline void run(const GemmArgs& g, int tm, int tn, int kz, uint8_t* lds) {
+        const int tid = threadIdx.x;
+        const int lane = tid & 63, wave = tid >> 6;
+        const int wy = wave / WN, wx = wave % WN;
+        const int64_t m0 = (int64_t)tm * BM, n0 = (int64_t)tn * BN;
+        const int64_t kstages = g.K / BK;
+        const int64_t per = (kstages + g.split_k - 1) / g.split_k;
+        const int64_t s_beg = (int64_t)kz * per;
+        const int nk = (int)max<int64_t>(0, min<int64_t>(kstages, s_beg + per) - s_beg);
+
+        const i32x4_t ra = make_rsrc(g.A, (uint32_t)(((g.M - 1) * g.lda + g.K) * 2));
+        const i32x4_t rb = make_rsrc(g.B, (uint32_t)(((g.K - 1) * g.ldb + g.N) * 2));
+
+        // per-lane byte offsets of this wave's load slabs (k0 added as the scalar offset)
+        int voff_a[NA], voff_b[NB];
+#pragma unroll
+        for (int i = 0; i < NA; ++i) {
+            const int slab = wave + i * NW;
+            const int r = slab * A_ROWS_PER_SLAB + lane / 8;
+            const int c = (lane & 7) ^ fa(r);
+            int64_t row = m0 + r;
+            // rows past the operand read zero: push their offset past the range
+            voff_a[i] = row < g.M ? (int)(row * g.lda * 2 + c * 16) : 0x7FFFFFF0;
+        }
+#pragma unroll
+        for (int i = 0; i < NB; ++i) {
+            const int slab = wave + i * NW;
+            const int r = slab * B_ROWS_PER_SLAB + lane / B_CHUNKS;
+            const int c = (lane % B_CHUNKS) ^ fb(r);
+            const int64_t col = n0 + c * 8;
+            voff_b[i] = col < g.N ? (int)(r * g.ldb * 2 + col * 2) : 0x7FFFFFF0;
+        }
+
+        f4_t acc[TM][TN];
+#pragma unroll
+        for (int i = 0; i < TM; ++i)
+#pragma unroll
+            for (int j = 0; j < TN; ++j) acc[i][j] = f4_t{0.f, 0.f, 0.f, 0.f};
+
+        // prologue: STAGES-1 stages in flight
+#pragma unroll
+        for (int s = 0; s < STAGES - 1; ++s)
+            if (s < nk) issue_stage(ra, rb, voff_a, voff_b, (s_beg + s) * BK, g.ldb, lds + s * STAGE, wave);
+
+        const int lr = lane & 15, lg = lane >> 4;
+        typedef __attribute__((address_space(3))) bf4_t* tp;
+        for (int it = 0; it < nk; ++it) {
+            // stage `it` has landed once at most (stages issued after it) loads remain
+            const int later = min(STAGES - 2, nk - 1 - it);
+            if (later >= 1) {
+                if constexpr (STAGES >= 3) {
+                    if (later == 1) wait_vmcnt<LOADS>();
+                    else wait_vmcnt<(STAGES - 2) * LOADS>();
+                } else {
+                    wait_vmcnt<0>();
+                }
+            } else {
+                wait_vmcnt<0>();
+            }
+            // all of this workgroup's waves: stage `it` visible, stage it-1 fully read
+            asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
+            if (it + STAGES - 1 < nk)
+                issue_stage(ra, rb, voff_a, voff_b, (s_beg + it + STAGES - 1) * BK, g.ldb,
+                            lds + ((it + STAGES - 1) % STAGES) * STAGE, wave);
+            const uint8_t* sa = lds + (it % STAGES) * STAGE;
+            const uint8_t* sb = sa + A_STAGE;
+#pragma unroll
+            for (int ks = 0; ks < BK / 32; ++ks) {
+                u4_t af[TM];
+                bf8_t bfr[TN];
+#pragma unroll
+                for (int i = 0; i < TM; ++i) {
+                    const int r = wy * WTM + i * 16 + lr;
+                    const int c = (ks * 4 + lg) ^ fa(r);
+                    af[i] = *(const u4_t*)(sa + r * A_ROW + c * 16);
+                }
+#pragma unroll
+                for (int j = 0; j < TN; ++j) {
+                    const int nb = wx * WTN + j * 16 + 4 * (lr & 3);  // first of this lane's 4 columns
+                    bf4_t h[2];
+#pragma unroll
+                    for (int half = 0; half < 2; ++half) {
+                        const int k = ks * 32 + lg * 8 + half * 4 + (lr >> 2);
+                        const int c = (nb >> 3) ^ fb(k);
+                        const uint8_t* p = sb + k * B_ROW + c * 16 + (nb & 7) * 2;
+                        h[half] = __builtin_amdgcn_ds_read_tr16_b64_v4bf16((tp)(p));
+                    }
+                    bfr[j] = bf8_t{h[0][0], h[0][1], h[0][2], h[0][3], h[1][0], h[1][1], h[1][2], h[1][3]};
+                }
+#pragma unroll
+                for (int i = 0; i < TM; ++i)
+#pragma unroll
+                    for (int j = 0; j < TN; ++j)
+                        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                            __builtin_bit_cast(bf8_t, af[i]), bfr[j], acc[i][j], 0, 0, 0);
+            }
+        }
+
+        // epilogue: lane l, register r holds output row 4*(l/16) + r, column l % 16
+        float* C = (float*)g.C;
+#pragma unroll
+        for (int j = 0; j < TN; ++j) {
+            const int64_t n = n0 + wx * WTN + j * 16 + lr;
+            if (n >= g.N) continue;
+#pragma unroll
+            for (int i = 0; i < TM; ++i)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int64_t m = m0 + wy * WTM + i * 16 + lg * 4 + r;
+                    if (m >= g.M) continue;
+                    float* p = C + m * g.ldc + n;
+                    const float v = acc[i][j][r];
+                    if (g.atomic) atomicAdd(p, v);
+                    else *p = g.accumulate ? *p + v : v;
+                }
+        }
+    }
+};
+
+}  // namespace mlk

@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "gemm_fast.hpp"
 #include "gemm_tile.hpp"
 
 namespace mlk {
@@ -22,6 +23,7 @@ typedef hipError_t (*persist_fn)(const GemmArgs* gemms, const Task* tasks,
 struct KernelEntry {
     int dt;        // DT_*
     int conv;      // 1: implicit-GEMM convolution operand policy
+    int stages;    // 0: register-staged; >= 2: direct-to-LDS ring of that many stages
     int bm, bn, bk;
     int wm, wn;
     int lds_bytes;
@@ -56,6 +58,22 @@ __global__ __launch_bounds__(64 * WM * WN) void k_gemm_persist(const GemmArgs* g
     }
 }
 
+template <int BM, int BN, int WM, int WN, int STAGES>
+__global__ __launch_bounds__(64 * WM * WN) void k_gemm_fast_bf16(GemmArgs g) {
+    typedef FastBf16<BM, BN, WM, WN, STAGES> TL;
+    __shared__ __attribute__((aligned(1024))) uint8_t lds[TL::LDS_BYTES];
+    int tm, tn, kz;
+    tile_coords(g, blockIdx.x, gridDim.x, tm, tn, kz);
+    TL::run(g, tm, tn, kz, lds);
+}
+
+template <int BM, int BN, int WM, int WN, int STAGES>
+hipError_t launch_fast_bf16(const GemmArgs& g, int nblk, hipStream_t s) {
+    hipLaunchKernelGGL((k_gemm_fast_bf16<BM, BN, WM, WN, STAGES>), dim3(nblk), dim3(64 * WM * WN), 0,
+                       s, g);
+    return hipGetLastError();
+}
+
 template <int DT, int BM, int BN, int KB, int WM, int WN, bool CONV>
 hipError_t launch_gemm(const GemmArgs& g, int nblk, hipStream_t s) {
     hipLaunchKernelGGL((k_gemm<DT, BM, BN, KB, WM, WN, CONV>), dim3(nblk), dim3(64 * WM * WN), 0,
@@ -73,17 +91,23 @@ hipError_t launch_persist(const GemmArgs* gemms, const Task* tasks, const int32_
 
 #define MLK_ENTRY(DT, BM, BN, KB, WM, WN, CONV)                                              \
     KernelEntry {                                                                            \
-        DT, CONV, BM, BN, (KB) / Traits<DT>::ES, WM, WN,                                     \
+        DT, CONV, 0, BM, BN, (KB) / Traits<DT>::ES, WM, WN,                                  \
             Tile<DT, BM, BN, KB, WM, WN, CONV>::LDS_BYTES, 64 * (WM) * (WN),                 \
             &launch_gemm<DT, BM, BN, KB, WM, WN, CONV>, nullptr                              \
     }
 
 #define MLK_ENTRY_P(DT, BM, BN, KB, WM, WN)                                                  \
     KernelEntry {                                                                            \
-        DT, 0, BM, BN, (KB) / Traits<DT>::ES, WM, WN,                                        \
+        DT, 0, 0, BM, BN, (KB) / Traits<DT>::ES, WM, WN,                                     \
             Tile<DT, BM, BN, KB, WM, WN, false>::LDS_BYTES, 64 * (WM) * (WN),                \
             &launch_gemm<DT, BM, BN, KB, WM, WN, false>,                                     \
             &launch_persist<DT, BM, BN, KB, WM, WN>                                          \
+    }
+
+#define MLK_ENTRY_FAST(BM, BN, WM, WN, STAGES)                                               \
+    KernelEntry {                                                                            \
+        DT_BF16, 0, STAGES, BM, BN, 64, WM, WN, FastBf16<BM, BN, WM, WN, STAGES>::LDS_BYTES,    \
+            64 * (WM) * (WN), &launch_fast_bf16<BM, BN, WM, WN, STAGES>, nullptr              \
     }
 
 // Tables defined by the instantiation units (host functions: the tables hold
@@ -93,6 +117,7 @@ const KernelEntry* kernels_bf16(int* n);
 const KernelEntry* kernels_i8(int* n);
 const KernelEntry* kernels_f8(int* n);
 const KernelEntry* kernels_conv(int* n);
+const KernelEntry* kernels_fast(int* n);
 
 // Elementwise / reduction launchers (quant.hip, reduce.hip, mlp.hip).
 hipError_t launch_zero_matrix(void* C, int64_t M, int64_t N, int64_t ldc, int esize,

@@ -74,8 +74,8 @@ bool db_lookup(const char* path, const std::string& key, const std::string& dev,
         size_t ut = s.find("\"us\": ");
         if (at == std::string::npos || ut == std::string::npos) continue;
         mlk_tile_config t;
-        if (sscanf(s.c_str() + at + 8, "%d, %d, %d, %d, %d, %d, %d, %d", &t.bm, &t.bn, &t.bk,
-                   &t.wm, &t.wn, &t.split_k, &t.group_m, &t.xcd_remap) != 8)
+        if (sscanf(s.c_str() + at + 8, "%d, %d, %d, %d, %d, %d, %d, %d, %d", &t.bm, &t.bn, &t.bk,
+                   &t.wm, &t.wn, &t.split_k, &t.group_m, &t.xcd_remap, &t.stages) != 9)
             continue;
         double u = 0;
         if (sscanf(s.c_str() + ut + 6, "%lf", &u) != 1) continue;
@@ -93,10 +93,10 @@ bool db_append(const char* path, const std::string& key, const std::string& dev,
     FILE* f = fopen(path, "a");
     if (!f) return false;
     fprintf(f,
-            "{\"key\": \"%s\", \"device\": \"%s\", \"cfg\": [%d, %d, %d, %d, %d, %d, %d, %d], "
+            "{\"key\": \"%s\", \"device\": \"%s\", \"cfg\": [%d, %d, %d, %d, %d, %d, %d, %d, %d], "
             "\"us\": %.4f, \"measured\": %d, \"legal\": %d, \"strategy\": %d, \"lib\": \"%s\"}\n",
             key.c_str(), dev.c_str(), c.bm, c.bn, c.bk, c.wm, c.wn, c.split_k, c.group_m,
-            c.xcd_remap, us, n_measured, n_legal, strategy, mlk_version());
+            c.xcd_remap, c.stages, us, n_measured, n_legal, strategy, mlk_version());
     const bool ok = fflush(f) == 0;
     fclose(f);
     return ok;

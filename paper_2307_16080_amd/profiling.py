@@ -1,0 +1,72 @@
+"""Summaries of rocprofv3 output for the benchmark's kernels.
+
+    python -m paper_2307_16080_amd.profiling stats  <kernel_stats.csv>
+    python -m paper_2307_16080_amd.profiling traffic <fetch_counters.csv> <write_counters.csv>
+            <kernel-name-substring> <copy-bytes> <out.json> [source_hash] [tile]
+
+`traffic` turns the FETCH_SIZE / WRITE_SIZE counters (KiB per dispatch) of
+the kernel into bytes per launch, scaled by what the same counters read for
+the benchmark's plain device copy of `copy-bytes` bytes (the copy reads and
+writes exactly that many bytes), and writes them as JSON.
+"""
+import csv
+import json
+import sys
+
+
+def _rows(path):
+    with open(path, newline="") as f:
+        return list(csv.DictReader(f))
+
+
+def stats(path, top=12):
+    rows = _rows(path)
+    rows.sort(key=lambda r: -float(r.get("TotalDurationNs", 0) or 0))
+    out = [f"{'calls':>7} {'avg_us':>10} {'min_us':>10} {'max_us':>10} {'pct':>6}  kernel"]
+    for r in rows[:top]:
+        out.append(f"{int(r['Calls']):7d} {float(r['AverageNs']) / 1e3:10.2f} {float(r['MinNs']) / 1e3:10.2f} "
+                   f"{float(r['MaxNs']) / 1e3:10.2f} {float(r['Percentage']):6.2f}  {r['Name'][:150]}")
+    return "\n".join(out)
+
+
+def _counter_per_dispatch(path, counter, name_sub):
+    """mean counter value (summed over its instances) per dispatch of kernels matching name_sub."""
+    per = {}
+    for r in _rows(path):
+        if r.get("Counter_Name") != counter or name_sub not in r.get("Kernel_Name", ""):
+            continue
+        d = r.get("Dispatch_Id") or r.get("Correlation_Id")
+        per[d] = per.get(d, 0.0) + float(r["Counter_Value"])
+    if not per:
+        return None, 0
+    return sum(per.values()) / len(per), len(per)
+
+
+def traffic(fetch_csv, write_csv, kernel_sub, copy_bytes, copy_sub="copy"):
+    f_k, nf = _counter_per_dispatch(fetch_csv, "FETCH_SIZE", kernel_sub)
+    w_k, nw = _counter_per_dispatch(write_csv, "WRITE_SIZE", kernel_sub)
+    f_c, _ = _counter_per_dispatch(fetch_csv, "FETCH_SIZE", copy_sub)
+    w_c, _ = _counter_per_dispatch(write_csv, "WRITE_SIZE", copy_sub)
+    if None in (f_k, w_k, f_c, w_c):
+        raise SystemExit("counters missing for the kernel or the copy")
+    fetch_scale = copy_bytes / f_c      # bytes per counter unit, read side
+    write_scale = copy_bytes / w_c
+    return {"fetch_bytes": f_k * fetch_scale, "write_bytes": w_k * write_scale,
+            "bytes_per_launch": f_k * fetch_scale + w_k * write_scale,
+            "raw": {"kernel_fetch_kib": f_k, "kernel_write_kib": w_k, "copy_fetch_kib": f_c,
+                    "copy_write_kib": w_c, "dispatches": [nf, nw]},
+            "scale": {"fetch_bytes_per_unit": fetch_scale, "write_bytes_per_unit": write_scale}}
+
+
+if __name__ == "__main__":
+    if sys.argv[1] == "stats":
+        print(stats(sys.argv[2]))
+    elif sys.argv[1] == "traffic":
+        t = traffic(sys.argv[2], sys.argv[3], sys.argv[4], int(sys.argv[5]))
+        if len(sys.argv) > 7:
+            t["source_hash"] = sys.argv[7]
+        if len(sys.argv) > 8:
+            t["config"] = [int(v) for v in sys.argv[8].split(",")]
+        with open(sys.argv[6], "w") as f:
+            json.dump(t, f, indent=1)
+        print(json.dumps(t))

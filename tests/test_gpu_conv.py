@@ -46,7 +46,7 @@ def test_f32_conv_56x56x64():
 
 
 @pytest.mark.parametrize("cfg", all_tiles(L.MLK_F32, L.MLK_F32, conv=True) + all_tiles(L.MLK_BF16, L.MLK_F32, conv=True),
-                         ids=lambda c: f"{c.bm}x{c.bn}x{c.bk}_{c.wm}{c.wn}")
+                         ids=lambda c: f"{c.bm}x{c.bn}x{c.bk}_{c.wm}{c.wn}_s{c.stages}")
 def test_every_conv_tile(cfg):
     for case in CASES:
         N, C, H, W, F, KH, KW, s, p = case

@@ -55,7 +55,7 @@ def test_f32_config0_128():
     assert err <= 1e-5
 
 
-@pytest.mark.parametrize("cfg", all_tiles(L.MLK_F32, L.MLK_F32), ids=lambda c: f"{c.bm}x{c.bn}x{c.bk}_{c.wm}{c.wn}")
+@pytest.mark.parametrize("cfg", all_tiles(L.MLK_F32, L.MLK_F32), ids=lambda c: f"{c.bm}x{c.bn}x{c.bk}_{c.wm}{c.wn}_s{c.stages}")
 def test_f32_every_tile_ragged(cfg):
     for (M, N, K) in RAGGED:
         say("f32", cfg, M, N, K)
@@ -112,7 +112,7 @@ def test_i8_1024_bit_exact():
     assert np.array_equal(host(C), ref)
 
 
-@pytest.mark.parametrize("cfg", all_tiles(L.MLK_I8, L.MLK_I32), ids=lambda c: f"{c.bm}x{c.bn}x{c.bk}_{c.wm}{c.wn}")
+@pytest.mark.parametrize("cfg", all_tiles(L.MLK_I8, L.MLK_I32), ids=lambda c: f"{c.bm}x{c.bn}x{c.bk}_{c.wm}{c.wn}_s{c.stages}")
 def test_i8_every_tile_ragged(cfg):
     for (M, N, K) in RAGGED:
         say("i8", cfg, M, N, K)
@@ -173,7 +173,39 @@ def test_quantize_special_values():
 
 # ----------------------------------------------------------------------- bf16 / e4m3
 
-@pytest.mark.parametrize("cfg", all_tiles(L.MLK_BF16, L.MLK_F32), ids=lambda c: f"{c.bm}x{c.bn}x{c.bk}_{c.wm}{c.wn}")
+BF16_TILES = all_tiles(L.MLK_BF16, L.MLK_F32)
+# shapes the direct-to-LDS kernels accept (K % 64 == 0, N % 8 == 0) with ragged M and N tiles
+ALIGNED = [(1, 8, 64), (100, 136, 192), (257, 520, 640), (300, 264, 128), (512, 512, 1024), (33, 1000, 64)]
+
+
+@pytest.mark.parametrize("cfg", [c for c in BF16_TILES if c.stages], ids=lambda c: f"{c.bm}x{c.bn}x{c.bk}_{c.wm}{c.wn}_s{c.stages}")
+def test_bf16_direct_to_lds_tiles(cfg):
+    for (M, N, K) in ALIGNED:
+        say("bf16 direct", cfg, M, N, K)
+        A, B = matmul_inputs(M, N, K, seed=M + 3 * N + K, dist="normal")
+        qa, qb = oracle.bf16_encode(A), oracle.bf16_encode(B)
+        C0 = random_c(M, N, seed=K)
+        ref = oracle.matmul_f64(oracle.bf16_decode(qa), oracle.bf16_decode(qb), C0)
+        big, C = _with_guard(C0, torch.float32)
+        mlk.matmul(from_bf16_codes(qa), from_bf16_codes(qb), C, cfg=cfg)
+        e = normwise(host(C), ref)
+        say("  kernel err", e)
+        assert e <= 1e-5
+        _check_guard(big, M, N)
+        A, B = matmul_inputs(M, N, K, seed=4, dist="small_int")
+        for acc in (True, False):
+            C = torch.full((M, N), float("nan"), device="cuda") if not acc else torch.zeros(M, N, device="cuda")
+            mlk.matmul(from_bf16_codes(oracle.bf16_encode(A)), from_bf16_codes(oracle.bf16_encode(B)), C,
+                       cfg=cfg, accumulate=acc)
+            assert np.array_equal(host(C).astype(np.float64), oracle.matmul_f64(A, B)), acc
+    # unaligned operands are refused for an explicit direct-to-LDS configuration
+    A = torch.zeros(64, 65, dtype=torch.bfloat16, device="cuda")
+    with pytest.raises(mlk.MlkError, match="CONFIG"):
+        mlk.matmul(A[:, 1:], torch.zeros(64, 64, dtype=torch.bfloat16, device="cuda"),
+                   torch.zeros(64, 64, device="cuda"), cfg=cfg)
+
+
+@pytest.mark.parametrize("cfg", [c for c in BF16_TILES if not c.stages], ids=lambda c: f"{c.bm}x{c.bn}x{c.bk}_{c.wm}{c.wn}_s{c.stages}")
 def test_bf16_every_tile_ragged(cfg):
     for (M, N, K) in RAGGED:
         say("bf16", cfg, M, N, K)
@@ -194,7 +226,7 @@ def test_bf16_every_tile_ragged(cfg):
         assert np.array_equal(host(C).astype(np.float64), oracle.matmul_f64(A, B))
 
 
-@pytest.mark.parametrize("cfg", all_tiles(L.MLK_F8E4M3, L.MLK_F32), ids=lambda c: f"{c.bm}x{c.bn}x{c.bk}_{c.wm}{c.wn}")
+@pytest.mark.parametrize("cfg", all_tiles(L.MLK_F8E4M3, L.MLK_F32), ids=lambda c: f"{c.bm}x{c.bn}x{c.bk}_{c.wm}{c.wn}_s{c.stages}")
 def test_e4m3_every_tile_ragged(cfg):
     for (M, N, K) in RAGGED:
         say("e4m3", cfg, M, N, K)
