@@ -217,22 +217,42 @@ def main():
                                         "per_gemm_launches_us": round(us_loop, 1),
                                         "graph_of_launches_us": round(us_g, 1),
                                         "TFLOP/s": round(bflops / us_pg / 1e6, 1)}
-        # ResNet-18 conv stack, batch 32, bf16 (per-layer tuned, default launch uses the tuned entry)
-        stack_us, stack_flops = 0.0, 0.0
-        for shape, count in resnet18_conv_stack(32):
-            xs = torch.randn(shape.N, shape.C, shape.H, shape.W, device="cuda")
-            ws = torch.randn(shape.F, shape.C, shape.KH, shape.KW, device="cuda")
-            qx, _ = mlk.quantize(xs, "bf16")
-            qw, _ = mlk.quantize(ws, "bf16")
-            ho, wo = shape.out_hw()
-            ys = torch.zeros(shape.N, shape.F, ho, wo, device="cuda")
-            pr = mlk.conv_problem(shape.N, shape.C, shape.H, shape.W, shape.F, shape.KH, shape.KW,
-                                  shape.stride, shape.pad, L.MLK_BF16, L.MLK_F32)
-            br, _, _ = mlk.tune(pr, mlk.MLK_TUNE_EXHAUSTIVE, reps=3, warmup=1)
-            us = time_us(lambda: mlk.conv2d_nchw_fchw(qx, qw, ys, (shape.stride,) * 2, (shape.pad,) * 2, cfg=br), 10)
-            stack_us += us * count
-            stack_flops += shape.flops() * count
-        rows_out["resnet18_stack_b32_bf16"] = {"us": round(stack_us, 1), "TFLOP/s": round(stack_flops / stack_us / 1e6, 1)}
+        # ResNet-18 conv stacks (batch 1 and 32, bf16): exhaustive tile search per
+        # layer shape, the stack timed with each layer's best tile, and the learned
+        # cost model judged leave-one-problem-out against those exhaustive tables.
+        from paper_2307_16080_amd import costmodel
+        problems, shapes_all = [], []
+        for batch in (1, 32):
+            for shape, count in resnet18_conv_stack(batch):
+                problems.append(mlk.conv_problem(shape.N, shape.C, shape.H, shape.W, shape.F, shape.KH,
+                                                 shape.KW, shape.stride, shape.pad, L.MLK_BF16, L.MLK_F32))
+                shapes_all.append((shape, count))
+        t0 = time.time()
+        tables = costmodel.exhaustive_tables(problems, reps=3, warmup=1)
+        log(f"exhaustive tables for {len(problems)} conv problems in {time.time() - t0:.1f} s")
+        for batch in (1, 32):
+            stack_us, stack_flops = 0.0, 0.0
+            for (shape, count), p, t in zip(shapes_all, problems, tables):
+                if shape.N != batch:
+                    continue
+                cfg = mlk.configs(p)[int(np.argmin(np.where(t > 0, t, np.inf)))]
+                xs = torch.randn(shape.N, shape.C, shape.H, shape.W, device="cuda")
+                ws = torch.randn(shape.F, shape.C, shape.KH, shape.KW, device="cuda")
+                qx, _ = mlk.quantize(xs, "bf16")
+                qw, _ = mlk.quantize(ws, "bf16")
+                ho, wo = shape.out_hw()
+                ys = torch.zeros(shape.N, shape.F, ho, wo, device="cuda")
+                us = time_us(lambda: mlk.conv2d_nchw_fchw(qx, qw, ys, (shape.stride,) * 2, (shape.pad,) * 2,
+                                                          cfg=cfg), 20)
+                stack_us += us * count
+                stack_flops += shape.flops() * count
+            rows_out[f"resnet18_stack_b{batch}_bf16"] = {"us": round(stack_us, 1),
+                                                         "TFLOP/s": round(stack_flops / stack_us / 1e6, 2),
+                                                         "gflop": round(stack_flops / 1e9, 2)}
+        t0 = time.time()
+        ev = costmodel.leave_one_out(problems, tables, budget=0.2)
+        ev["summary"]["seconds"] = round(time.time() - t0, 1)
+        rows_out["cost_model_leave_one_out"] = ev["summary"]
     result["rows"] = rows_out
 
     # ---------------------------------------------------------------- CPU oracle baseline

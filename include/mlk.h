@@ -78,7 +78,7 @@ typedef enum {
  *   xcd_remap  1: map consecutive tiles to the same XCD (shared L2)
  *   stages     0: register-staged kernel (operands pass through registers
  *              on their way to a double-buffered LDS tile; any shape and
- *              alignment).  2..4: direct-to-LDS kernel (bf16 only) whose
+ *              alignment).  2..4: direct-to-LDS kernel (bf16, e4m3) whose
  *              loads go from HBM straight into a ring of `stages` LDS
  *              buffers; needs K % bk == 0, 16-byte aligned A and B and row
  *              pitches that are multiples of 16 bytes.

@@ -118,7 +118,7 @@ static mlk_status check_conv_dims(int64_t n, int64_t c, int64_t h, int64_t w, in
     *wo = conv_out(w, kw, sw, pw);
     if (*ho < 1 || *wo < 1)
         return fail(MLK_ERR_SHAPE, "conv2d: the filter does not fit the padded image");
-    if (n * (*ho) * (*wo) > kMaxDim || c * kh * kw > kMaxDim || c * h * w > kMaxDim)
+    if (n * (*ho) * (*wo) > kMaxDim || c * kh * kw > kMaxDim || n * c * h * w >= kMaxDim)
         return fail(MLK_ERR_SHAPE, "conv2d: problem too large for one launch");
     return MLK_OK;
 }
@@ -174,8 +174,9 @@ static int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
 // Shapes the direct-to-LDS kernels accept: whole K stages, packed rows that
 // are multiples of 16 bytes, operands below 2 GiB (32-bit buffer offsets).
 static bool fast_shape_ok(const Shape& s, int bk) {
-    return s.K > 0 && s.K % bk == 0 && (s.K * 2) % 16 == 0 && (s.N * 2) % 16 == 0 &&
-           s.M * s.K * 2 < ((int64_t)1 << 31) && s.K * s.N * 2 < ((int64_t)1 << 31);
+    const int64_t es = esize_in(s.dt);
+    return s.K > 0 && s.K % bk == 0 && (s.K * es) % 16 == 0 && (s.N * es) % 16 == 0 &&
+           s.M * s.K * es < ((int64_t)1 << 31) && s.K * s.N * es < ((int64_t)1 << 31);
 }
 
 mlk_status check_config(const Shape& s, int op, const mlk_tile_config& c) {

@@ -1,9 +1,10 @@
-// gemm_fast.hpp -- the bf16 matmul main loop for large, aligned problems on
-// gfx950: operands go from HBM straight into LDS (buffer loads with the LDS
-// destination bit, no register staging), B stays in its row-major
-// (N-contiguous) layout in LDS and is transposed on the way out by the
-// gfx950 LDS transpose read (ds_read_b64_tr_b16), and the K loop keeps
-// STAGES-1 stages of loads in flight behind the MFMAs.
+// gemm_fast.hpp -- the bf16 / e4m3 matmul main loop for large, aligned
+// problems on gfx950: operands go from HBM straight into LDS (buffer loads
+// with the LDS destination bit, no register staging), B stays in its
+// row-major (N-contiguous) layout in LDS and is transposed on the way out by
+// the gfx950 LDS transpose reads (ds_read_b64_tr_b16 for bf16,
+// ds_read_b64_tr_b8 for e4m3), and the K loop keeps STAGES-1 stages of loads
+// in flight behind the MFMAs.
 //
 // What is computed is still linalg.matmul, C[M,N] (+)= A[M,K] * B[K,N]
 // (paper Sec. 2.1, listing "linalg-matmul"), with fp32 accumulation.
@@ -13,10 +14,10 @@
 // are arbitrary: rows past the end of an operand read as zero (buffer range
 // check) and columns past N only feed outputs that are never stored.
 //
-// LDS layout per stage: A as BM rows of BK bf16 (128 bytes for BK = 64), the
-// 16-byte chunk c of row r stored at chunk c ^ fa(r); B as BK rows of BN bf16,
-// the 16-byte chunk c of row k stored at chunk c ^ fb(k).  The XOR patterns
-// spread the lanes of one LDS read over distinct banks.
+// LDS layout per stage: A as BM rows of 128 bytes (BK = 64 bf16 or 128
+// e4m3), the 16-byte chunk c of row r stored at chunk c ^ fa(r); B as BK rows
+// of BN elements, the 16-byte chunk c of row k stored at chunk c ^ fb(k).  The
+// XOR patterns spread the lanes of one LDS read over distinct banks.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -27,12 +28,23 @@
 namespace mlk {
 
 typedef __bf16 bf4_t __attribute__((ext_vector_type(4)));
+typedef int i2_t __attribute__((ext_vector_type(2)));
 typedef int32_t i32x4_t __attribute__((ext_vector_type(4)));
 
-// LLVM intrinsic: buffer load whose data goes to LDS at M0 + lane * size.
-__device__ void llvm_buffer_load_lds(i32x4_t rsrc, __attribute__((address_space(3))) uint32_t* lds,
-                                     int size, int voffset, int soffset, int offset,
-                                     int aux) __asm("llvm.amdgcn.raw.buffer.load.lds");
+// 16-byte buffer load per lane whose data goes to LDS at m0 + 16 * lane.
+// Written as inline asm so that the compiler does not treat it as a pending
+// write to every LDS location (it would otherwise wait for the whole prefetch
+// before the next LDS read); the kernel waits on vmcnt itself.  One wait
+// state separates the m0 write from the load.
+__device__ inline void dma_load16(uint32_t lds_addr, int voffset, const i32x4_t& rsrc, int soffset) {
+    asm volatile(
+        "s_mov_b32 m0, %0\n\t"
+        "s_nop 0\n\t"
+        "buffer_load_dwordx4 %1, %2, %3 offen lds"
+        :
+        : "s"(lds_addr), "v"(voffset), "s"(rsrc), "s"(soffset)
+        : "memory", "m0");
+}
 
 __device__ inline i32x4_t make_rsrc(const void* base, uint32_t bytes) {
     const uint64_t b = (uint64_t)base;
@@ -52,15 +64,17 @@ __device__ inline void wait_vmcnt() {
 }
 
 __device__ inline int fa(int r) { return (r & 7) ^ ((r >> 3) & 1); }
-__device__ inline int fb(int k) { return ((k & 3) << 1) | (((k >> 3) & 1) << 3); }
 
-template <int BM, int BN, int WM, int WN, int STAGES>
-struct FastBf16 {
-    static constexpr int BK = 64;                  // bf16 per A row per stage
+template <int DT, int BM, int BN, int WM, int WN, int STAGES>
+struct FastGemm {
+    static_assert(DT == DT_BF16 || DT == DT_F8, "direct-to-LDS kernel: bf16 or e4m3");
+    static constexpr int ES = DT == DT_BF16 ? 2 : 1;
+    static constexpr int BK = 128 / ES;            // elements per A row per stage
+    static constexpr int KSTEP = DT == DT_BF16 ? 32 : 128;  // k per MFMA
     static constexpr int NW = WM * WN;
     static constexpr int NT = 64 * NW;
-    static constexpr int A_ROW = BK * 2;           // 128 bytes
-    static constexpr int B_ROW = BN * 2;
+    static constexpr int A_ROW = BK * ES;          // 128 bytes
+    static constexpr int B_ROW = BN * ES;
     static constexpr int A_STAGE = BM * A_ROW;
     static constexpr int B_STAGE = BK * B_ROW;
     static constexpr int STAGE = A_STAGE + B_STAGE;
@@ -77,7 +91,15 @@ struct FastBf16 {
     static constexpr int B_CHUNKS = B_ROW / 16;
 
     static_assert(A_SLABS % NW == 0 && B_SLABS % NW == 0, "slabs must divide among waves");
-    static_assert(B_CHUNKS >= 16, "B rows need at least 16 chunks for the swizzle");
+    static_assert(B_CHUNKS >= (DT == DT_BF16 ? 16 : 8), "B rows too short for the swizzle");
+
+    // B swizzle: the rows read together by one transpose read land in distinct
+    // 16-byte bank groups.  bf16 reads 4 rows x 32 bytes per lane group, e4m3
+    // 8 rows x 16 bytes.
+    __device__ static inline int fb(int k) {
+        if constexpr (DT == DT_BF16) return ((k & 3) << 1) | (((k >> 3) & 1) << 3);
+        else return (k & 7) | (B_CHUNKS >= 16 ? (((k >> 5) & 1) << 3) : 0);
+    }
     static_assert(LDS_BYTES <= 160 * 1024, "LDS budget");
     static_assert(WTM % 16 == 0 && WTN % 16 == 0, "wave tile");
     static_assert(STAGES >= 2 && (STAGES - 1) * LOADS < 64, "pipeline depth");
@@ -85,18 +107,18 @@ struct FastBf16 {
     __device__ static inline void issue_stage(const i32x4_t& ra, const i32x4_t& rb,
                                               const int* voff_a, const int* voff_b, int64_t k0,
                                               int64_t ldb, uint8_t* stage, int wave) {
-        typedef __attribute__((address_space(3))) uint32_t* lp;
-        const int sa = (int)(k0 * 2);
-        const int sb = (int)(k0 * ldb * 2);
+        const int sa = __builtin_amdgcn_readfirstlane((int)(k0 * ES));
+        const int sb = __builtin_amdgcn_readfirstlane((int)(k0 * ldb * ES));
+        const uint32_t base = (uint32_t)(uintptr_t)(__attribute__((address_space(3))) uint8_t*)stage;
 #pragma unroll
         for (int i = 0; i < NA; ++i) {
             const int slab = wave + i * NW;
-            llvm_buffer_load_lds(ra, (lp)(stage + slab * 1024), 16, voff_a[i], sa, 0, 0);
+            dma_load16(__builtin_amdgcn_readfirstlane(base + slab * 1024), voff_a[i], ra, sa);
         }
 #pragma unroll
         for (int i = 0; i < NB; ++i) {
             const int slab = wave + i * NW;
-            llvm_buffer_load_lds(rb, (lp)(stage + A_STAGE + slab * 1024), 16, voff_b[i], sb, 0, 0);
+            dma_load16(__builtin_amdgcn_readfirstlane(base + A_STAGE + slab * 1024), voff_b[i], rb, sb);
         }
     }
 
@@ -110,8 +132,8 @@ struct FastBf16 {
         const int64_t s_beg = (int64_t)kz * per;
         const int nk = (int)max<int64_t>(0, min<int64_t>(kstages, s_beg + per) - s_beg);
 
-        const i32x4_t ra = make_rsrc(g.A, (uint32_t)(((g.M - 1) * g.lda + g.K) * 2));
-        const i32x4_t rb = make_rsrc(g.B, (uint32_t)(((g.K - 1) * g.ldb + g.N) * 2));
+        const i32x4_t ra = make_rsrc(g.A, (uint32_t)(((g.M - 1) * g.lda + g.K) * ES));
+        const i32x4_t rb = make_rsrc(g.B, (uint32_t)(((g.K - 1) * g.ldb + g.N) * ES));
 
         // per-lane byte offsets of this wave's load slabs (k0 added as the scalar offset)
         int voff_a[NA], voff_b[NB];
@@ -122,15 +144,15 @@ struct FastBf16 {
             const int c = (lane & 7) ^ fa(r);
             int64_t row = m0 + r;
             // rows past the operand read zero: push their offset past the range
-            voff_a[i] = row < g.M ? (int)(row * g.lda * 2 + c * 16) : 0x7FFFFFF0;
+            voff_a[i] = row < g.M ? (int)(row * g.lda * ES + c * 16) : 0x7FFFFFF0;
         }
 #pragma unroll
         for (int i = 0; i < NB; ++i) {
             const int slab = wave + i * NW;
             const int r = slab * B_ROWS_PER_SLAB + lane / B_CHUNKS;
             const int c = (lane % B_CHUNKS) ^ fb(r);
-            const int64_t col = n0 + c * 8;
-            voff_b[i] = col < g.N ? (int)(r * g.ldb * 2 + col * 2) : 0x7FFFFFF0;
+            const int64_t col = n0 + c * (16 / ES);
+            voff_b[i] = col < g.N ? (int)((r * g.ldb + col) * ES) : 0x7FFFFFF0;
         }
 
         f4_t acc[TM][TN];
@@ -146,6 +168,7 @@ struct FastBf16 {
 
         const int lr = lane & 15, lg = lane >> 4;
         typedef __attribute__((address_space(3))) bf4_t* tp;
+        typedef __attribute__((address_space(3))) i2_t* t8p;
         for (int it = 0; it < nk; ++it) {
             // stage `it` has landed once at most (stages issued after it) loads remain
             const int later = min(STAGES - 2, nk - 1 - it);
@@ -167,38 +190,78 @@ struct FastBf16 {
             const uint8_t* sa = lds + (it % STAGES) * STAGE;
             const uint8_t* sb = sa + A_STAGE;
 #pragma unroll
-            for (int ks = 0; ks < BK / 32; ++ks) {
-                u4_t af[TM];
-                bf8_t bfr[TN];
+            for (int ks = 0; ks < BK / KSTEP; ++ks) {
+                if constexpr (DT == DT_BF16) {
+                    u4_t af[TM];
+                    bf8_t bfr[TN];
 #pragma unroll
-                for (int i = 0; i < TM; ++i) {
-                    const int r = wy * WTM + i * 16 + lr;
-                    const int c = (ks * 4 + lg) ^ fa(r);
-                    af[i] = *(const u4_t*)(sa + r * A_ROW + c * 16);
-                }
-#pragma unroll
-                for (int j = 0; j < TN; ++j) {
-                    const int nb = wx * WTN + j * 16 + 4 * (lr & 3);  // first of this lane's 4 columns
-                    bf4_t h[2];
-#pragma unroll
-                    for (int half = 0; half < 2; ++half) {
-                        const int k = ks * 32 + lg * 8 + half * 4 + (lr >> 2);
-                        const int c = (nb >> 3) ^ fb(k);
-                        const uint8_t* p = sb + k * B_ROW + c * 16 + (nb & 7) * 2;
-                        h[half] = __builtin_amdgcn_ds_read_tr16_b64_v4bf16((tp)(p));
+                    for (int i = 0; i < TM; ++i) {
+                        const int r = wy * WTM + i * 16 + lr;
+                        const int c = (ks * 4 + lg) ^ fa(r);
+                        af[i] = *(const u4_t*)(sa + r * A_ROW + c * 16);
                     }
-                    bfr[j] = bf8_t{h[0][0], h[0][1], h[0][2], h[0][3], h[1][0], h[1][1], h[1][2], h[1][3]};
+#pragma unroll
+                    for (int j = 0; j < TN; ++j) {
+                        // lane lr of the group supplies row lr/4, columns 4*(lr%4)..+3 of a
+                        // 4 x 16 block; the transpose read returns column lr to it
+                        const int nb = wx * WTN + j * 16 + 4 * (lr & 3);
+                        bf4_t h[2];
+#pragma unroll
+                        for (int half = 0; half < 2; ++half) {
+                            const int k = ks * 32 + lg * 8 + half * 4 + (lr >> 2);
+                            const int c = (nb >> 3) ^ fb(k);
+                            const uint8_t* p = sb + k * B_ROW + c * 16 + (nb & 7) * 2;
+                            h[half] = __builtin_amdgcn_ds_read_tr16_b64_v4bf16((tp)(p));
+                        }
+                        bfr[j] = bf8_t{h[0][0], h[0][1], h[0][2], h[0][3], h[1][0], h[1][1], h[1][2], h[1][3]};
+                    }
+#pragma unroll
+                    for (int i = 0; i < TM; ++i)
+#pragma unroll
+                        for (int j = 0; j < TN; ++j)
+                            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                                __builtin_bit_cast(bf8_t, af[i]), bfr[j], acc[i][j], 0, 0, 0);
+                } else {
+                    i8_t af[TM], bfr[TN];
+#pragma unroll
+                    for (int i = 0; i < TM; ++i) {
+                        const int r = wy * WTM + i * 16 + lr;
+                        const u4_t lo = *(const u4_t*)(sa + r * A_ROW + ((2 * lg) ^ fa(r)) * 16);
+                        const u4_t hi = *(const u4_t*)(sa + r * A_ROW + ((2 * lg + 1) ^ fa(r)) * 16);
+                        af[i] = i8_t{(int)lo[0], (int)lo[1], (int)lo[2], (int)lo[3],
+                                     (int)hi[0], (int)hi[1], (int)hi[2], (int)hi[3]};
+                    }
+#pragma unroll
+                    for (int j = 0; j < TN; ++j) {
+                        // lane lr supplies row lr/2, bytes 8*(lr%2)..+7 of an 8 x 16 block;
+                        // the transpose read returns column lr (8 consecutive k) to it
+                        const int nb = wx * WTN + j * 16 + 8 * (lr & 1);
+                        i2_t q[4];
+#pragma unroll
+                        for (int qq = 0; qq < 4; ++qq) {
+                            const int k = lg * 32 + qq * 8 + (lr >> 1);
+                            const int c = (nb >> 4) ^ fb(k);
+                            const uint8_t* p = sb + k * B_ROW + c * 16 + (nb & 15);
+                            q[qq] = __builtin_amdgcn_ds_read_tr8_b64_v2i32((t8p)(p));
+                        }
+                        bfr[j] = i8_t{q[0][0], q[0][1], q[1][0], q[1][1], q[2][0], q[2][1], q[3][0], q[3][1]};
+                    }
+#pragma unroll
+                    for (int i = 0; i < TM; ++i)
+#pragma unroll
+                        for (int j = 0; j < TN; ++j)
+                            acc[i][j] = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(
+                                af[i], bfr[j], acc[i][j], 0, 0, 0, 127, 0, 127);
                 }
-#pragma unroll
-                for (int i = 0; i < TM; ++i)
-#pragma unroll
-                    for (int j = 0; j < TN; ++j)
-                        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
-                            __builtin_bit_cast(bf8_t, af[i]), bfr[j], acc[i][j], 0, 0, 0);
             }
         }
 
         // epilogue: lane l, register r holds output row 4*(l/16) + r, column l % 16
+        float alpha = 1.0f;
+        if constexpr (DT == DT_F8) {
+            if (g.scale_a) alpha *= *g.scale_a;
+            if (g.scale_b) alpha *= *g.scale_b;
+        }
         float* C = (float*)g.C;
 #pragma unroll
         for (int j = 0; j < TN; ++j) {
@@ -211,7 +274,7 @@ struct FastBf16 {
                     const int64_t m = m0 + wy * WTM + i * 16 + lg * 4 + r;
                     if (m >= g.M) continue;
                     float* p = C + m * g.ldc + n;
-                    const float v = acc[i][j][r];
+                    const float v = DT == DT_F8 ? alpha * acc[i][j][r] : acc[i][j][r];
                     if (g.atomic) atomicAdd(p, v);
                     else *p = g.accumulate ? *p + v : v;
                 }

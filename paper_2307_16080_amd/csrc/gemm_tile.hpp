@@ -31,6 +31,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 namespace mlk {
 
 enum : int { DT_F32 = 0, DT_BF16 = 1, DT_F8 = 2, DT_I8 = 3 };
@@ -242,8 +244,10 @@ struct Tile {
         }
     }
 
+    struct NoCols {};
+    template <class Cols>
     __device__ static inline void load_b(const GemmArgs& g, int64_t n0, int64_t k0, u4_t* rb,
-                                         int tid) {
+                                         int tid, const Cols* cols) {
 #pragma unroll
         for (int i = 0; i < NB; ++i) {
             const int blk = tid + i * NT;
@@ -266,41 +270,88 @@ struct Tile {
                     else v[e] = load_partial<ES>(row, n, nval);
                 }
             } else {
-                // implicit im2col: rows k = (c, kh, kw), columns p = (img, oh, ow)
-                // v[e] is built directly in transposed form: v[j] = column n + j
-                const int64_t P = (int64_t)g.cn * g.cho * g.cwo;
-                const int KHW = g.ckh * g.ckw;
-                int ck[EPV], ckh[EPV], ckw[EPV];
+                conv_gather(g, cols[i], kb, v);
+            }
+        }
+    }
+
+    // Implicit im2col for the conv policy.  Columns p = (img, oh, ow) of a
+    // transpose block are fixed for the whole tile, so their input offsets
+    // are computed once (ConvCols); the rows k = (c, kh, kw) of a block are
+    // decomposed once per stage and then stepped (kw fastest).  A block whose
+    // columns are all valid and whose windows lie inside the image needs no
+    // bounds checks at all.
+    struct ConvCols {
+        int cbase[EPV];  // img*C*H*W + ih0*W + iw0 (element offset of tap (0,0,0))
+        int ih0[EPV], iw0[EPV];
+        int interior;    // every column valid and its whole window inside the image
+        int any;         // at least one valid column
+    };
+
+    __device__ static inline void conv_cols(const GemmArgs& g, int64_t n0, int tid, ConvCols* cols) {
+        const int64_t P = (int64_t)g.cn * g.cho * g.cwo;
+        const int hw = g.cho * g.cwo;
 #pragma unroll
-                for (int e = 0; e < EPV; ++e) {
-                    const int64_t k = kb + e;
-                    ck[e] = k < g.K ? (int)(k / KHW) : -1;
-                    const int rem = (int)(k % KHW);
-                    ckh[e] = rem / g.ckw;
-                    ckw[e] = rem % g.ckw;
+        for (int i = 0; i < NB; ++i) {
+            const int blk = tid + i * NT;
+            const int nc = blk % (BN / EPV);
+            ConvCols& cc = cols[i];
+            cc.interior = (NBLK % NT != 0 && blk >= NBLK) ? 0 : 1;
+            cc.any = 0;
+#pragma unroll
+            for (int j = 0; j < EPV; ++j) {
+                const int64_t p = n0 + nc * EPV + j;
+                if (p < P && !(NBLK % NT != 0 && blk >= NBLK)) {
+                    const int img = (int)(p / hw), q = (int)(p % hw);
+                    cc.ih0[j] = (q / g.cwo) * g.csh - g.cph;
+                    cc.iw0[j] = (q % g.cwo) * g.csw - g.cpw;
+                    cc.cbase[j] = img * g.cc * g.ch * g.cw + cc.ih0[j] * g.cw + cc.iw0[j];
+                    cc.any = 1;
+                    if (cc.ih0[j] < 0 || cc.ih0[j] + g.ckh > g.ch || cc.iw0[j] < 0 || cc.iw0[j] + g.ckw > g.cw)
+                        cc.interior = 0;
+                } else {
+                    cc.ih0[j] = -(1 << 28);  // never inside the image
+                    cc.iw0[j] = -(1 << 28);
+                    cc.cbase[j] = 0;
+                    cc.interior = 0;
                 }
-                const uint8_t* X = (const uint8_t*)g.B;
+            }
+        }
+    }
+
+    __device__ static inline void conv_gather(const GemmArgs& g, const ConvCols& cc, int64_t kb,
+                                              u4_t* v) {
+        if (!cc.any || kb >= g.K) return;
+        const uint8_t* X = (const uint8_t*)g.B;
+        const int KHW = g.ckh * g.ckw, HW = g.ch * g.cw;
+        int c = (int)(kb / KHW);
+        const int rem = (int)(kb - (int64_t)c * KHW);
+        int kh = rem / g.ckw, kw = rem - (rem / g.ckw) * g.ckw;
+#pragma unroll
+        for (int e = 0; e < EPV; ++e) {
+            if (kb + e < g.K) {
+                const int coff = c * HW + kh * g.cw + kw;
+                const int bit = e * ES * 8;
 #pragma unroll
                 for (int j = 0; j < EPV; ++j) {
-                    const int64_t p = n + j;
-                    if (p >= P) continue;
-                    const int hw = g.cho * g.cwo;
-                    const int img = (int)(p / hw), q = (int)(p % hw);
-                    const int ih0 = (q / g.cwo) * g.csh - g.cph, iw0 = (q % g.cwo) * g.csw - g.cpw;
-                    const int64_t base = (int64_t)img * g.cc * g.ch * g.cw;
-#pragma unroll
-                    for (int e = 0; e < EPV; ++e) {
-                        if (ck[e] < 0) continue;
-                        const int ih = ih0 + ckh[e], iw = iw0 + ckw[e];
-                        if (ih < 0 || ih >= g.ch || iw < 0 || iw >= g.cw) continue;
-                        const int64_t off = base + ((int64_t)ck[e] * g.ch + ih) * g.cw + iw;
+                    const bool in = cc.interior ||
+                                    ((unsigned)(cc.ih0[j] + kh) < (unsigned)g.ch &&
+                                     (unsigned)(cc.iw0[j] + kw) < (unsigned)g.cw);
+                    if (in) {
+                        const int64_t off = (int64_t)cc.cbase[j] + coff;
                         uint32_t x;
                         if constexpr (ES == 4) x = *(const uint32_t*)(X + off * 4);
                         else if constexpr (ES == 2) x = *(const uint16_t*)(X + off * 2);
                         else x = X[off];
-                        const int bit = e * ES * 8;
                         v[j][bit >> 5] |= x << (bit & 31);
                     }
+                }
+            }
+            if (++kw == g.ckw) {
+                kw = 0;
+                if (++kh == g.ckh) {
+                    kh = 0;
+                    ++c;
                 }
             }
         }
@@ -358,9 +409,12 @@ struct Tile {
         u4_t ra[NA > 0 ? NA : 1];
         u4_t rb[NB * EPV > 0 ? NB * EPV : 1];
 
+        typedef typename std::conditional<CONV, ConvCols, NoCols>::type ColsT;
+        ColsT cols[CONV ? NB : 1];
+        if constexpr (CONV) conv_cols(g, n0, tid, cols);
         if (nk > 0) {
             load_a(g, m0, s_beg * BK, ra, tid);
-            load_b(g, n0, s_beg * BK, rb, tid);
+            load_b(g, n0, s_beg * BK, rb, tid, cols);
             store_a(lds, ra, tid);
             store_b(lds + BM * PITCH, rb, tid);
         }
@@ -371,7 +425,7 @@ struct Tile {
             const bool more = it + 1 < nk;
             if (more) {
                 load_a(g, m0, (s_beg + it + 1) * BK, ra, tid);
-                load_b(g, n0, (s_beg + it + 1) * BK, rb, tid);
+                load_b(g, n0, (s_beg + it + 1) * BK, rb, tid, cols);
             }
             const uint8_t* sa = lds + (it & 1) * STAGE;
             const uint8_t* sb = sa + BM * PITCH;

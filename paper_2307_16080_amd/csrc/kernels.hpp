@@ -58,18 +58,18 @@ __global__ __launch_bounds__(64 * WM * WN) void k_gemm_persist(const GemmArgs* g
     }
 }
 
-template <int BM, int BN, int WM, int WN, int STAGES>
-__global__ __launch_bounds__(64 * WM * WN) void k_gemm_fast_bf16(GemmArgs g) {
-    typedef FastBf16<BM, BN, WM, WN, STAGES> TL;
+template <int DT, int BM, int BN, int WM, int WN, int STAGES>
+__global__ __launch_bounds__(64 * WM * WN) void k_gemm_fast(GemmArgs g) {
+    typedef FastGemm<DT, BM, BN, WM, WN, STAGES> TL;
     __shared__ __attribute__((aligned(1024))) uint8_t lds[TL::LDS_BYTES];
     int tm, tn, kz;
     tile_coords(g, blockIdx.x, gridDim.x, tm, tn, kz);
     TL::run(g, tm, tn, kz, lds);
 }
 
-template <int BM, int BN, int WM, int WN, int STAGES>
-hipError_t launch_fast_bf16(const GemmArgs& g, int nblk, hipStream_t s) {
-    hipLaunchKernelGGL((k_gemm_fast_bf16<BM, BN, WM, WN, STAGES>), dim3(nblk), dim3(64 * WM * WN), 0,
+template <int DT, int BM, int BN, int WM, int WN, int STAGES>
+hipError_t launch_fast(const GemmArgs& g, int nblk, hipStream_t s) {
+    hipLaunchKernelGGL((k_gemm_fast<DT, BM, BN, WM, WN, STAGES>), dim3(nblk), dim3(64 * WM * WN), 0,
                        s, g);
     return hipGetLastError();
 }
@@ -104,10 +104,11 @@ hipError_t launch_persist(const GemmArgs* gemms, const Task* tasks, const int32_
             &launch_persist<DT, BM, BN, KB, WM, WN>                                          \
     }
 
-#define MLK_ENTRY_FAST(BM, BN, WM, WN, STAGES)                                               \
+#define MLK_ENTRY_FAST(DT, BM, BN, WM, WN, STAGES)                                           \
     KernelEntry {                                                                            \
-        DT_BF16, 0, STAGES, BM, BN, 64, WM, WN, FastBf16<BM, BN, WM, WN, STAGES>::LDS_BYTES,    \
-            64 * (WM) * (WN), &launch_fast_bf16<BM, BN, WM, WN, STAGES>, nullptr              \
+        DT, 0, STAGES, BM, BN, FastGemm<DT, BM, BN, WM, WN, STAGES>::BK, WM, WN,              \
+            FastGemm<DT, BM, BN, WM, WN, STAGES>::LDS_BYTES, 64 * (WM) * (WN),               \
+            &launch_fast<DT, BM, BN, WM, WN, STAGES>, nullptr                                \
     }
 
 // Tables defined by the instantiation units (host functions: the tables hold

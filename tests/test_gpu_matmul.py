@@ -226,7 +226,35 @@ def test_bf16_every_tile_ragged(cfg):
         assert np.array_equal(host(C).astype(np.float64), oracle.matmul_f64(A, B))
 
 
-@pytest.mark.parametrize("cfg", all_tiles(L.MLK_F8E4M3, L.MLK_F32), ids=lambda c: f"{c.bm}x{c.bn}x{c.bk}_{c.wm}{c.wn}_s{c.stages}")
+E4M3_TILES = all_tiles(L.MLK_F8E4M3, L.MLK_F32)
+ALIGNED8 = [(1, 16, 128), (100, 144, 256), (257, 528, 640), (300, 272, 128), (512, 512, 1024), (33, 1008, 128)]
+
+
+@pytest.mark.parametrize("cfg", [c for c in E4M3_TILES if c.stages], ids=lambda c: f"{c.bm}x{c.bn}x{c.bk}_{c.wm}{c.wn}_s{c.stages}")
+def test_e4m3_direct_to_lds_tiles(cfg):
+    for (M, N, K) in ALIGNED8:
+        say("e4m3 direct", cfg, M, N, K)
+        A, B = matmul_inputs(M, N, K, seed=M + 7 * N + K, dist="normal")
+        qa, sa = oracle.quantize_e4m3(A)
+        qb, sb = oracle.quantize_e4m3(B)
+        C0 = random_c(M, N, seed=K)
+        prod = oracle.matmul_f64(oracle.e4m3_decode(qa), oracle.e4m3_decode(qb))
+        ref = C0.astype(np.float64) + (float(np.float32(sa)) * float(np.float32(sb))) * prod
+        big, C = _with_guard(C0, torch.float32)
+        mlk.matmul(from_e4m3_codes(qa), from_e4m3_codes(qb), C, cfg=cfg,
+                   scale_a=dev(np.array([sa], np.float32)), scale_b=dev(np.array([sb], np.float32)))
+        e = normwise(host(C), ref)
+        say("  kernel err", e)
+        assert e <= E4M3_KERNEL_TOL
+        _check_guard(big, M, N)
+        A, B = matmul_inputs(M, N, K, seed=5, dist="small_int")
+        C = torch.zeros(M, N, device="cuda")
+        mlk.matmul(from_e4m3_codes(oracle.e4m3_encode(A, 1.0)), from_e4m3_codes(oracle.e4m3_encode(B, 1.0)),
+                   C, cfg=cfg)
+        assert np.array_equal(host(C).astype(np.float64), oracle.matmul_f64(A, B))
+
+
+@pytest.mark.parametrize("cfg", [c for c in E4M3_TILES if not c.stages], ids=lambda c: f"{c.bm}x{c.bn}x{c.bk}_{c.wm}{c.wn}_s{c.stages}")
 def test_e4m3_every_tile_ragged(cfg):
     for (M, N, K) in RAGGED:
         say("e4m3", cfg, M, N, K)
