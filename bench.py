@@ -123,12 +123,13 @@ def main():
 
     # traffic from committed rocprofv3 counter runs, if they match these sources
     traffic = None
-    tpath = os.path.join(ROOT, "profiles", "bf16_gemm_4096_traffic.json")
+    tpath = os.path.join(ROOT, "profiles", "bf16_gemm_4096_traffic.txt")
     if os.path.exists(tpath):
         with open(tpath) as f:
-            t = json.load(f)
+            lines = [l for l in f.read().splitlines() if l.strip() and not l.startswith("#")]
+        t = json.loads(lines[-1]) if lines else {}
         if t.get("source_hash") == source_hash() and t.get("config") == list(best.as_tuple()):
-            traffic = t.get("bytes_per_launch")
+            traffic = round(t.get("bytes_per_launch"))
 
     result = {
         "metric": "GEMM/conv TFLOP/s and % MFMA roofline; tuned vs plain fp32 at stated rel err",
