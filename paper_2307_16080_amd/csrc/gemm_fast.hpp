@@ -167,6 +167,31 @@ struct FastGemm {
             if (s < nk) issue_stage(ra, rb, voff_a, voff_b, (s_beg + s) * BK, g.ldb, lds + s * STAGE, wave);
 
         const int lr = lane & 15, lg = lane >> 4;
+        // This lane's outputs: rows wy*WTM + i*16 + lg*4 + r, columns
+        // wx*WTN + j*16 + lr of the tile whose corner is Ct (a uniform base);
+        // offsets inside the tile are 32-bit.
+        float* const Ct = (float*)g.C + m0 * g.ldc + n0;
+        const int ldc = (int)g.ldc;
+        const int row0 = wy * WTM + lg * 4, col0 = wx * WTN + lr;
+        const bool full = m0 + BM <= g.M && n0 + BN <= g.N;
+        const int mrem = (int)min<int64_t>(BM, g.M - m0), nrem = (int)min<int64_t>(BN, g.N - n0);
+        // C += A B: start the accumulators from C itself, so that its read
+        // happens here, beside the first stage's loads, instead of in a
+        // read-add-write epilogue after the last MFMA.  (e4m3 scales the
+        // product, so it keeps C apart.)
+        const bool c_in_acc = DT != DT_F8 && g.accumulate && !g.atomic;
+        if (c_in_acc) {
+#pragma unroll
+            for (int j = 0; j < TN; ++j)
+#pragma unroll
+                for (int i = 0; i < TM; ++i)
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        const int row = row0 + i * 16 + r, col = col0 + j * 16;
+                        acc[i][j][r] = (full || (row < mrem && col < nrem)) ? Ct[row * ldc + col] : 0.0f;
+                    }
+        }
+
         typedef __attribute__((address_space(3))) bf4_t* tp;
         typedef __attribute__((address_space(3))) i2_t* t8p;
         for (int it = 0; it < nk; ++it) {
@@ -193,13 +218,14 @@ struct FastGemm {
             for (int ks = 0; ks < BK / KSTEP; ++ks) {
                 if constexpr (DT == DT_BF16) {
                     u4_t af[TM];
-                    bf8_t bfr[TN];
 #pragma unroll
                     for (int i = 0; i < TM; ++i) {
                         const int r = wy * WTM + i * 16 + lr;
                         const int c = (ks * 4 + lg) ^ fa(r);
                         af[i] = *(const u4_t*)(sa + r * A_ROW + c * 16);
                     }
+                    // B fragments are consumed as soon as they arrive, column tile by
+                    // column tile, so only one or two are live at a time
 #pragma unroll
                     for (int j = 0; j < TN; ++j) {
                         // lane lr of the group supplies row lr/4, columns 4*(lr%4)..+3 of a
@@ -213,14 +239,12 @@ struct FastGemm {
                             const uint8_t* p = sb + k * B_ROW + c * 16 + (nb & 7) * 2;
                             h[half] = __builtin_amdgcn_ds_read_tr16_b64_v4bf16((tp)(p));
                         }
-                        bfr[j] = bf8_t{h[0][0], h[0][1], h[0][2], h[0][3], h[1][0], h[1][1], h[1][2], h[1][3]};
-                    }
+                        const bf8_t bj = bf8_t{h[0][0], h[0][1], h[0][2], h[0][3], h[1][0], h[1][1], h[1][2], h[1][3]};
 #pragma unroll
-                    for (int i = 0; i < TM; ++i)
-#pragma unroll
-                        for (int j = 0; j < TN; ++j)
+                        for (int i = 0; i < TM; ++i)
                             acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
-                                __builtin_bit_cast(bf8_t, af[i]), bfr[j], acc[i][j], 0, 0, 0);
+                                __builtin_bit_cast(bf8_t, af[i]), bj, acc[i][j], 0, 0, 0);
+                    }
                 } else {
                     i8_t af[TM], bfr[TN];
 #pragma unroll
@@ -262,23 +286,20 @@ struct FastGemm {
             if (g.scale_a) alpha *= *g.scale_a;
             if (g.scale_b) alpha *= *g.scale_b;
         }
-        float* C = (float*)g.C;
 #pragma unroll
-        for (int j = 0; j < TN; ++j) {
-            const int64_t n = n0 + wx * WTN + j * 16 + lr;
-            if (n >= g.N) continue;
+        for (int j = 0; j < TN; ++j)
 #pragma unroll
             for (int i = 0; i < TM; ++i)
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
-                    const int64_t m = m0 + wy * WTM + i * 16 + lg * 4 + r;
-                    if (m >= g.M) continue;
-                    float* p = C + m * g.ldc + n;
+                    const int row = row0 + i * 16 + r, col = col0 + j * 16;
+                    if (!(full || (row < mrem && col < nrem))) continue;
+                    float* p = Ct + row * ldc + col;
                     const float v = DT == DT_F8 ? alpha * acc[i][j][r] : acc[i][j][r];
                     if (g.atomic) atomicAdd(p, v);
-                    else *p = g.accumulate ? *p + v : v;
+                    else if (c_in_acc || !g.accumulate) *p = v;
+                    else *p = *p + v;
                 }
-        }
     }
 };
 

@@ -401,10 +401,32 @@ struct Tile {
         const int nk = (int)max<int64_t>(0, s_end - s_beg);
 
         acc_t acc[TM][TN];
+        const int lr = lane & 15, lg = lane >> 4;
+        out_t* C = (out_t*)g.C;
+        // C += A B: start the accumulators from C (read here, next to the first
+        // loads, rather than in a read-add-write epilogue).  e4m3 scales the
+        // product and int8 must wrap modulo 2^32 exactly, so both keep C apart.
+        const bool c_in_acc = DT != DT_F8 && DT != DT_I8 && g.accumulate && !g.atomic;
 #pragma unroll
-        for (int i = 0; i < TM; ++i)
+        for (int j = 0; j < TN; ++j) {
+            int64_t cbase = 0, rstride = 0;
+            const int64_t n = n0 + wx * WTN + j * 16 + lr;
+            if constexpr (CONV) {
+                const int64_t hw = (int64_t)g.cho * g.cwo;
+                cbase = (n / hw) * g.M * hw + n % hw;
+                rstride = hw;
+            } else {
+                cbase = n;
+                rstride = g.ldc;
+            }
 #pragma unroll
-            for (int j = 0; j < TN; ++j) acc[i][j] = acc_t{0, 0, 0, 0};
+            for (int i = 0; i < TM; ++i)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int64_t m = m0 + wy * WTM + i * 16 + lg * 4 + r;
+                    acc[i][j][r] = (c_in_acc && m < g.M && n < g.N) ? C[m * rstride + cbase] : 0;
+                }
+        }
 
         u4_t ra[NA > 0 ? NA : 1];
         u4_t rb[NB * EPV > 0 ? NB * EPV : 1];
@@ -420,7 +442,6 @@ struct Tile {
         }
         __syncthreads();
 
-        const int lr = lane & 15, lg = lane >> 4;
         for (int it = 0; it < nk; ++it) {
             const bool more = it + 1 < nk;
             if (more) {
@@ -462,7 +483,6 @@ struct Tile {
             if (g.scale_a) alpha *= *g.scale_a;
             if (g.scale_b) alpha *= *g.scale_b;
         }
-        out_t* C = (out_t*)g.C;
 #pragma unroll
         for (int j = 0; j < TN; ++j) {
             const int64_t n = n0 + wx * WTN + j * 16 + lr;
@@ -489,7 +509,8 @@ struct Tile {
                     } else {
                         const float v = (DT == DT_F8) ? alpha * acc[i][j][r] : acc[i][j][r];
                         if (g.atomic) atomicAdd(p, v);
-                        else *p = g.accumulate ? *p + v : v;
+                        else if (c_in_acc || !g.accumulate) *p = v;
+                        else *p = *p + v;
                     }
                 }
         }
