@@ -82,6 +82,12 @@ typedef enum {
  *              loads go from HBM straight into a ring of `stages` LDS
  *              buffers; needs K % bk == 0, 16-byte aligned A and B and row
  *              pitches that are multiples of 16 bytes.
+ *   layout     conv2d only.  0: the kernel gathers its operands straight from
+ *              the NCHW input (any C).  1: the input is first transposed to
+ *              channels-last (NHWC) and the filter to F x KH x KW x C in a
+ *              stream-ordered workspace, so every operand load is one aligned
+ *              16-byte read; needs C a multiple of 8 (bf16) or 4 (fp32) and
+ *              16-byte aligned x and w.  Must be 0 for matmul.
  * A zeroed struct or a NULL pointer means "choose": the tuning database
  * entry for this problem if one was loaded, else a built-in heuristic.
  */
@@ -92,6 +98,7 @@ typedef struct {
     int32_t group_m;
     int32_t xcd_remap;
     int32_t stages;
+    int32_t layout;
 } mlk_tile_config;
 
 /*

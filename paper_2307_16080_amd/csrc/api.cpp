@@ -147,6 +147,7 @@ mlk_status shape_of_problem(const mlk_problem* p, Shape* s) {
         s->M = p->f;
         s->N = p->n * ho * wo;
         s->K = p->c * p->kh * p->kw;
+        s->conv_c = p->c;
     } else {
         if (p->count < 1) return fail(MLK_ERR_SHAPE, "batched: count must be >= 1");
         if (!p->descs) return fail(MLK_ERR_NULL, "batched: descs is NULL");
@@ -192,6 +193,10 @@ mlk_status check_config(const Shape& s, int op, const mlk_tile_config& c) {
         return fail(MLK_ERR_CONFIG, "split_k %d exceeds the %lld K stages", c.split_k, (long long)stages);
     if (c.group_m < 0 || c.group_m > 64) return fail(MLK_ERR_CONFIG, "group_m must be in [0, 64]");
     if (c.xcd_remap != 0 && c.xcd_remap != 1) return fail(MLK_ERR_CONFIG, "xcd_remap must be 0 or 1");
+    if (c.layout != 0 && !(s.conv && c.layout == 1))
+        return fail(MLK_ERR_CONFIG, "layout must be 0, or 1 for conv2d");
+    if (c.layout == 1 && (!e->launch_nhwc || s.conv_c % (16 / esize_in(s.dt)) != 0))
+        return fail(MLK_ERR_CONFIG, "channels-last layout needs C a multiple of %d", 16 / esize_in(s.dt));
     const int64_t tiles = cdiv(s.M, c.bm) * cdiv(s.N, c.bn) * c.split_k;
     if (tiles > ((int64_t)1 << 31) - 1) return fail(MLK_ERR_CONFIG, "too many workgroups");
     return MLK_OK;
@@ -218,8 +223,12 @@ std::vector<mlk_tile_config> enumerate_configs(const mlk_problem* p, const Shape
                 for (int xcd : {0, 1}) {
                     const int64_t nblk = tiles * sk;
                     if (xcd == 1 && (batched || nblk < 64 || nblk % 8 != 0)) continue;
-                    mlk_tile_config c{e->bm, e->bn, e->bk, e->wm, e->wn, sk, gm, xcd, e->stages};
-                    out.push_back(c);
+                    for (int lay = 0; lay < 2; ++lay) {
+                        if (lay == 1 && !(s.conv && e->launch_nhwc && s.conv_c % (16 / esize_in(s.dt)) == 0))
+                            continue;
+                        mlk_tile_config c{e->bm, e->bn, e->bk, e->wm, e->wn, sk, gm, xcd, e->stages, lay};
+                        out.push_back(c);
+                    }
                 }
             }
         }
@@ -246,7 +255,9 @@ mlk_tile_config heuristic_config(const Shape& s, int op) {
             best = e;
     }
     const KernelEntry* e = best ? best : smallest;
-    mlk_tile_config c{e->bm, e->bn, e->bk, e->wm, e->wn, 1, 1, 0, 0};
+    mlk_tile_config c{e->bm, e->bn, e->bk, e->wm, e->wn, 1, 1, 0, 0, 0};
+    // channels-last pays a transpose of the input: worth it for large images
+    if (s.conv && e->launch_nhwc && s.conv_c % (16 / esize_in(s.dt)) == 0 && s.N >= 16384) c.layout = 1;
     if (!best && op != MLK_OP_BATCHED) {
         // too few tiles: split K while each split keeps >= 4 stages
         const int64_t tiles = cdiv(std::max<int64_t>(s.M, 1), e->bm) * cdiv(std::max<int64_t>(s.N, 1), e->bn);
@@ -405,6 +416,34 @@ mlk_status launch_conv(const Shape& s, int64_t n, int64_t c, int64_t h, int64_t 
         if (z != hipSuccess) return hip_fail(z, "zero output");
     }
     const int64_t nblk = (int64_t)g.tiles_m * g.tiles_n * g.split_k;
+    // Channels-last route: with C a multiple of the 16-byte vector, transpose
+    // x to NHWC and the filter to F x KH x KW x C in a stream-ordered
+    // workspace, so every operand load of the tile kernel is one aligned
+    // 16-byte read.
+    const int epv = 16 / es;
+    if (cfg.layout == 1) {
+        if (!(e->launch_nhwc && c % epv == 0 && (uintptr_t)x % 16 == 0 && (uintptr_t)wt % 16 == 0 &&
+              n <= 65535 && f <= 65535))
+            return fail(MLK_ERR_CONFIG, "channels-last layout needs C %% %d == 0, aligned x and w, N, F <= 65535", epv);
+        const size_t xb = ((size_t)(n * c * h * w) * es + 255) & ~(size_t)255;
+        const size_t wb = (size_t)(f * c * kh * kw) * es;
+        void* ws = nullptr;
+        hipError_t err = hipMallocAsync(&ws, xb + wb, st);
+        if (err != hipSuccess) return hip_fail(err, "conv workspace");
+        uint8_t* xn = (uint8_t*)ws;
+        uint8_t* wn = xn + xb;
+        if ((err = launch_transpose_batched(x, xn, n, c, h * w, es, st)) == hipSuccess &&
+            (err = launch_transpose_batched(wt, wn, f, c, kh * kw, es, st)) == hipSuccess) {
+            g.A = wn;
+            g.B = xn;
+            g.vec_a = 1;
+            err = e->launch_nhwc(g, (int)nblk, st);
+        }
+        hipError_t e2 = hipFreeAsync(ws, st);
+        if (err != hipSuccess) return hip_fail(err, "conv launch");
+        if (e2 != hipSuccess) return hip_fail(e2, "conv workspace free");
+        return MLK_OK;
+    }
     hipError_t err = e->launch(g, (int)nblk, st);
     if (err != hipSuccess) return hip_fail(err, "kernel launch");
     return MLK_OK;
@@ -523,6 +562,9 @@ mlk_status mlk_conv2d_nchw_fchw(mlk_dtype in, mlk_dtype out, int64_t N, int64_t 
     mlk_tile_config c;
     st = resolve(p, s, cfg, &c);
     if (st != MLK_OK) return st;
+    if (c.layout == 1 && cfg_is_zero(cfg) &&
+        ((uintptr_t)x % 16 != 0 || (uintptr_t)w % 16 != 0 || N > 65535 || F > 65535))
+        c.layout = 0;
     return launch_conv(s, N, C, H, W, F, KH, KW, sh, sw, ph, pw, ho, wo, x, w, y, c,
                        (hipStream_t)stream);
 }

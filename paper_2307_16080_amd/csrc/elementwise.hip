@@ -192,6 +192,30 @@ __global__ __launch_bounds__(kThreads) void k_fill_random(uint8_t* p, int64_t n,
     }
 }
 
+// ------------------------------------------------------------------ layout transform
+
+// out[b][c][r] = in[b][r][c] for a batch of rows x cols matrices, through a
+// 32 x 32 LDS tile (one padding column keeps the column reads conflict-free).
+template <typename T>
+__global__ __launch_bounds__(256) void k_transpose(const T* __restrict__ in, T* __restrict__ out,
+                                                   int64_t rows, int64_t cols) {
+    __shared__ T tile[32][33];
+    const int64_t b = blockIdx.z;
+    const T* src = in + b * rows * cols;
+    T* dst = out + b * rows * cols;
+    const int64_t c0 = (int64_t)blockIdx.x * 32, r0 = (int64_t)blockIdx.y * 32;
+    const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+    for (int i = ty; i < 32; i += 8) {
+        const int64_t r = r0 + i, c = c0 + tx;
+        if (r < rows && c < cols) tile[i][tx] = src[r * cols + c];
+    }
+    __syncthreads();
+    for (int i = ty; i < 32; i += 8) {
+        const int64_t c = c0 + i, r = r0 + tx;
+        if (c < cols && r < rows) dst[c * rows + r] = tile[tx][i];
+    }
+}
+
 // ------------------------------------------------------------------ error statistics
 
 constexpr int kErrBlocks = 1024;
@@ -288,6 +312,23 @@ hipError_t launch_quant_e4m3(const float* x, int64_t n, uint8_t* q, float* scale
         }
     }
     hipLaunchKernelGGL(k_amax_to_scale, dim3(1), dim3(1), 0, s, bits);
+    return hipGetLastError();
+}
+
+hipError_t launch_transpose_batched(const void* in, void* out, int64_t batch, int64_t rows,
+                                    int64_t cols, int esize, hipStream_t s) {
+    if (batch <= 0 || rows <= 0 || cols <= 0) return hipSuccess;
+    if (batch > 65535 || (rows + 31) / 32 > 65535) return hipErrorInvalidValue;
+    const dim3 grid((unsigned)((cols + 31) / 32), (unsigned)((rows + 31) / 32), (unsigned)batch);
+    if (esize == 4)
+        hipLaunchKernelGGL(k_transpose<uint32_t>, grid, dim3(256), 0, s, (const uint32_t*)in,
+                           (uint32_t*)out, rows, cols);
+    else if (esize == 2)
+        hipLaunchKernelGGL(k_transpose<uint16_t>, grid, dim3(256), 0, s, (const uint16_t*)in,
+                           (uint16_t*)out, rows, cols);
+    else
+        hipLaunchKernelGGL(k_transpose<uint8_t>, grid, dim3(256), 0, s, (const uint8_t*)in,
+                           (uint8_t*)out, rows, cols);
     return hipGetLastError();
 }
 

@@ -197,10 +197,14 @@ __device__ inline void tile_coords(const GemmArgs& g, int bid, int nblk, int& tm
 
 // ---------------------------------------------------------------- the tile
 
-// CONV = false: dense row-major A, B, C.  CONV = true: A = filter (F x CKK,
-// row-major, lda = CKK), B = implicit im2col of the NCHW input, C = NFHW
-// output.
-template <int DT, int BM, int BN, int KB, int WM, int WN, bool CONV>
+// Operand policies.  CONV = 0: dense row-major A, B, C.  CONV = 1: A = filter
+// (F x C*KH*KW, row-major), B = implicit im2col of the NCHW input, k ordered
+// (c, kh, kw), C = NFHW output.  CONV = 2: the channels-last form: A = filter
+// laid out F x KH x KW x C, B gathered from an NHWC copy of the input, k
+// ordered (kh, kw, c); with C a multiple of the 16-byte vector, every B load
+// is one aligned 16-byte read of consecutive channels, stored into LDS as is
+// (no transpose).  The output is NFHW in both conv policies.
+template <int DT, int BM, int BN, int KB, int WM, int WN, int CONV>
 struct Tile {
     typedef Traits<DT> T;
     typedef typename T::acc_t acc_t;
@@ -218,7 +222,8 @@ struct Tile {
     static constexpr int CPR = KB / 16;          // 16-byte chunks per row
     static constexpr int NA = (BM * CPR + NT - 1) / NT;      // A chunks per thread
     static constexpr int NBLK = (BK / EPV) * (BN / EPV);     // B transpose blocks
-    static constexpr int NB = (NBLK + NT - 1) / NT;          // B blocks per thread
+    static constexpr int NB = CONV == 2 ? 0 : (NBLK + NT - 1) / NT;  // B blocks per thread
+    static constexpr int NB2 = CONV == 2 ? (BN * CPR + NT - 1) / NT : 0;  // channels-last B chunks
     static constexpr int KV = KS / 64;                       // 16-byte regs per MFMA operand
 
     static_assert(KB % KS == 0, "stage depth must hold whole K steps");
@@ -248,6 +253,10 @@ struct Tile {
     template <class Cols>
     __device__ static inline void load_b(const GemmArgs& g, int64_t n0, int64_t k0, u4_t* rb,
                                          int tid, const Cols* cols) {
+        if constexpr (CONV == 2) {
+            nhwc_gather(g, k0, rb, tid, cols);
+            return;
+        }
 #pragma unroll
         for (int i = 0; i < NB; ++i) {
             const int blk = tid + i * NT;
@@ -257,7 +266,7 @@ struct Tile {
             if (NBLK % NT != 0 && blk >= NBLK) continue;
             const int kr = blk / (BN / EPV), nc = blk % (BN / EPV);
             const int64_t kb = k0 + kr * EPV, n = n0 + nc * EPV;
-            if constexpr (!CONV) {
+            if constexpr (CONV == 0) {
                 if (n >= g.N) continue;
                 const uint8_t* B = (const uint8_t*)g.B;
                 const int nval = (int)min<int64_t>(EPV, g.N - n);
@@ -269,7 +278,7 @@ struct Tile {
                     if (g.vec_b && nval == EPV) v[e] = *(const u4_t*)(row + n * ES);
                     else v[e] = load_partial<ES>(row, n, nval);
                 }
-            } else {
+            } else if constexpr (CONV == 1) {
                 conv_gather(g, cols[i], kb, v);
             }
         }
@@ -357,6 +366,58 @@ struct Tile {
         }
     }
 
+    // Channels-last gather (CONV = 2): chunk i of this thread covers column
+    // n = n0 + c / CPR and k-chunk c % CPR; its pixel window origin is fixed
+    // for the tile.
+    struct NhwcCols {
+        int pbase[NB2 > 0 ? NB2 : 1];  // img * H * W
+        int ih0[NB2 > 0 ? NB2 : 1], iw0[NB2 > 0 ? NB2 : 1];
+    };
+
+    __device__ static inline void nhwc_cols(const GemmArgs& g, int64_t n0, int tid, NhwcCols* nc) {
+        const int64_t P = (int64_t)g.cn * g.cho * g.cwo;
+        const int hw = g.cho * g.cwo;
+#pragma unroll
+        for (int i = 0; i < NB2; ++i) {
+            const int c = tid + i * NT;
+            const int64_t p = n0 + c / CPR;
+            if ((BN * CPR) % NT == 0 || c < BN * CPR) {
+                if (p < P) {
+                    const int img = (int)(p / hw), q = (int)(p % hw);
+                    nc->pbase[i] = img * g.ch * g.cw;
+                    nc->ih0[i] = (q / g.cwo) * g.csh - g.cph;
+                    nc->iw0[i] = (q % g.cwo) * g.csw - g.cpw;
+                    continue;
+                }
+            }
+            nc->pbase[i] = 0;
+            nc->ih0[i] = -(1 << 28);  // never inside the image
+            nc->iw0[i] = -(1 << 28);
+        }
+    }
+
+    template <class Cols>
+    __device__ static inline void nhwc_gather(const GemmArgs& g, int64_t k0, u4_t* rb, int tid,
+                                              const Cols* cols) {
+        if constexpr (CONV == 2) {
+            const NhwcCols& nc = cols[0];
+            const uint8_t* X = (const uint8_t*)g.B;
+#pragma unroll
+            for (int i = 0; i < NB2; ++i) {
+                const int c = tid + i * NT;
+                rb[i] = u4_t{0u, 0u, 0u, 0u};
+                const int64_t k = k0 + (c % CPR) * EPV;
+                if (k >= g.K) continue;
+                const int tap = (int)(k / g.cc), ch = (int)(k - (int64_t)tap * g.cc);
+                const int kh = tap / g.ckw, kw = tap - (tap / g.ckw) * g.ckw;
+                const int ih = nc.ih0[i] + kh, iw = nc.iw0[i] + kw;
+                if ((unsigned)ih >= (unsigned)g.ch || (unsigned)iw >= (unsigned)g.cw) continue;
+                const int64_t off = ((int64_t)nc.pbase[i] + ih * g.cw + iw) * g.cc + ch;
+                rb[i] = *(const u4_t*)(X + off * ES);
+            }
+        }
+    }
+
     // ---- registers -> LDS
     __device__ static inline void store_a(uint8_t* sa, const u4_t* ra, int tid) {
 #pragma unroll
@@ -369,13 +430,22 @@ struct Tile {
     }
 
     __device__ static inline void store_b(uint8_t* sb, const u4_t* rb, int tid) {
+        if constexpr (CONV == 2) {
+#pragma unroll
+            for (int i = 0; i < NB2; ++i) {
+                const int c = tid + i * NT;
+                if ((BN * CPR) % NT != 0 && c >= BN * CPR) continue;
+                *(u4_t*)(sb + (c / CPR) * PITCH + (c % CPR) * 16) = rb[i];
+            }
+            return;
+        }
 #pragma unroll
         for (int i = 0; i < NB; ++i) {
             const int blk = tid + i * NT;
             if (NBLK % NT != 0 && blk >= NBLK) continue;
             const int kr = blk / (BN / EPV), nc = blk % (BN / EPV);
             u4_t t[EPV];
-            if constexpr (!CONV) transpose_block<ES>(rb + i * EPV, t);
+            if constexpr (CONV == 0) transpose_block<ES>(rb + i * EPV, t);
             else {
 #pragma unroll
                 for (int e = 0; e < EPV; ++e) t[e] = rb[i * EPV + e];
@@ -411,7 +481,7 @@ struct Tile {
         for (int j = 0; j < TN; ++j) {
             int64_t cbase = 0, rstride = 0;
             const int64_t n = n0 + wx * WTN + j * 16 + lr;
-            if constexpr (CONV) {
+            if constexpr (CONV != 0) {
                 const int64_t hw = (int64_t)g.cho * g.cwo;
                 cbase = (n / hw) * g.M * hw + n % hw;
                 rstride = hw;
@@ -429,11 +499,13 @@ struct Tile {
         }
 
         u4_t ra[NA > 0 ? NA : 1];
-        u4_t rb[NB * EPV > 0 ? NB * EPV : 1];
+        u4_t rb[(NB * EPV > NB2 ? NB * EPV : NB2) > 0 ? (NB * EPV > NB2 ? NB * EPV : NB2) : 1];
 
-        typedef typename std::conditional<CONV, ConvCols, NoCols>::type ColsT;
-        ColsT cols[CONV ? NB : 1];
-        if constexpr (CONV) conv_cols(g, n0, tid, cols);
+        typedef typename std::conditional<CONV == 1, ConvCols,
+                typename std::conditional<CONV == 2, NhwcCols, NoCols>::type>::type ColsT;
+        ColsT cols[CONV == 1 ? NB : 1];
+        if constexpr (CONV == 1) conv_cols(g, n0, tid, cols);
+        if constexpr (CONV == 2) nhwc_cols(g, n0, tid, cols);
         if (nk > 0) {
             load_a(g, m0, s_beg * BK, ra, tid);
             load_b(g, n0, s_beg * BK, rb, tid, cols);
@@ -489,7 +561,7 @@ struct Tile {
             if (n >= g.N) continue;
             int64_t cbase = n;   // offset of column n (row 0)
             int64_t rstride = g.ldc;
-            if constexpr (CONV) {
+            if constexpr (CONV != 0) {
                 const int64_t hw = (int64_t)g.cho * g.cwo;
                 const int64_t img = n / hw, q = n % hw;
                 cbase = img * g.M * hw + q;

@@ -27,6 +27,7 @@ struct Shape {
     int conv = 0;
     int64_t M = 0, N = 0, K = 0;
     int accumulate = 1;
+    int64_t conv_c = 0;  // conv: input channels
 };
 
 // registry of compiled kernels

@@ -30,9 +30,10 @@ struct KernelEntry {
     int threads;
     launch_fn launch;
     persist_fn persist;  // null where no persistent variant is built
+    launch_fn launch_nhwc;  // conv entries: the channels-last variant (CONV = 2)
 };
 
-template <int DT, int BM, int BN, int KB, int WM, int WN, bool CONV>
+template <int DT, int BM, int BN, int KB, int WM, int WN, int CONV>
 __global__ __launch_bounds__(64 * WM * WN) void k_gemm(GemmArgs g) {
     typedef Tile<DT, BM, BN, KB, WM, WN, CONV> TL;
     __shared__ __attribute__((aligned(16))) uint8_t lds[TL::LDS_BYTES];
@@ -46,7 +47,7 @@ template <int DT, int BM, int BN, int KB, int WM, int WN>
 __global__ __launch_bounds__(64 * WM * WN) void k_gemm_persist(const GemmArgs* gemms,
                                                                const Task* tasks,
                                                                const int32_t* bounds) {
-    typedef Tile<DT, BM, BN, KB, WM, WN, false> TL;
+    typedef Tile<DT, BM, BN, KB, WM, WN, 0> TL;
     __shared__ __attribute__((aligned(16))) uint8_t lds[TL::LDS_BYTES];
     const int b = blockIdx.x;
     const int t0 = bounds[b], t1 = bounds[b + 1];
@@ -74,7 +75,7 @@ hipError_t launch_fast(const GemmArgs& g, int nblk, hipStream_t s) {
     return hipGetLastError();
 }
 
-template <int DT, int BM, int BN, int KB, int WM, int WN, bool CONV>
+template <int DT, int BM, int BN, int KB, int WM, int WN, int CONV>
 hipError_t launch_gemm(const GemmArgs& g, int nblk, hipStream_t s) {
     hipLaunchKernelGGL((k_gemm<DT, BM, BN, KB, WM, WN, CONV>), dim3(nblk), dim3(64 * WM * WN), 0,
                        s, g);
@@ -91,24 +92,25 @@ hipError_t launch_persist(const GemmArgs* gemms, const Task* tasks, const int32_
 
 #define MLK_ENTRY(DT, BM, BN, KB, WM, WN, CONV)                                              \
     KernelEntry {                                                                            \
-        DT, CONV, 0, BM, BN, (KB) / Traits<DT>::ES, WM, WN,                                  \
-            Tile<DT, BM, BN, KB, WM, WN, CONV>::LDS_BYTES, 64 * (WM) * (WN),                 \
-            &launch_gemm<DT, BM, BN, KB, WM, WN, CONV>, nullptr                              \
+        DT, (CONV) ? 1 : 0, 0, BM, BN, (KB) / Traits<DT>::ES, WM, WN,                          \
+            Tile<DT, BM, BN, KB, WM, WN, (CONV) ? 1 : 0>::LDS_BYTES, 64 * (WM) * (WN),         \
+            &launch_gemm<DT, BM, BN, KB, WM, WN, (CONV) ? 1 : 0>, nullptr,                     \
+            (CONV) ? &launch_gemm<DT, BM, BN, KB, WM, WN, 2> : nullptr                        \
     }
 
 #define MLK_ENTRY_P(DT, BM, BN, KB, WM, WN)                                                  \
     KernelEntry {                                                                            \
         DT, 0, 0, BM, BN, (KB) / Traits<DT>::ES, WM, WN,                                     \
-            Tile<DT, BM, BN, KB, WM, WN, false>::LDS_BYTES, 64 * (WM) * (WN),                \
-            &launch_gemm<DT, BM, BN, KB, WM, WN, false>,                                     \
-            &launch_persist<DT, BM, BN, KB, WM, WN>                                          \
+            Tile<DT, BM, BN, KB, WM, WN, 0>::LDS_BYTES, 64 * (WM) * (WN),                    \
+            &launch_gemm<DT, BM, BN, KB, WM, WN, 0>, &launch_persist<DT, BM, BN, KB, WM, WN>,  \
+            nullptr                                                                          \
     }
 
 #define MLK_ENTRY_FAST(DT, BM, BN, WM, WN, STAGES)                                           \
     KernelEntry {                                                                            \
         DT, 0, STAGES, BM, BN, FastGemm<DT, BM, BN, WM, WN, STAGES>::BK, WM, WN,              \
             FastGemm<DT, BM, BN, WM, WN, STAGES>::LDS_BYTES, 64 * (WM) * (WN),               \
-            &launch_fast<DT, BM, BN, WM, WN, STAGES>, nullptr                                \
+            &launch_fast<DT, BM, BN, WM, WN, STAGES>, nullptr, nullptr                       \
     }
 
 // Tables defined by the instantiation units (host functions: the tables hold
@@ -129,6 +131,9 @@ hipError_t launch_quant_e4m3(const float* x, int64_t n, uint8_t* q, float* scale
 hipError_t launch_err_stats(int c_is_int, int64_t n, const void* c, const double* r,
                             const double* bound, double* out, hipStream_t s);
 hipError_t launch_fill_random(void* p, int64_t n, int dt, uint64_t seed, hipStream_t s);
+// batch of [rows x cols] matrices -> [cols x rows] (NCHW -> NHWC, FCHW -> FHWC)
+hipError_t launch_transpose_batched(const void* in, void* out, int64_t batch, int64_t rows,
+                                    int64_t cols, int esize, hipStream_t s);
 hipError_t launch_mlp_forward(int64_t B, int64_t D0, int64_t H1, int64_t H2, const float* p,
                               const float* X, float* y, hipStream_t s);
 hipError_t launch_mlp_loss_grad(int64_t B, int64_t D0, int64_t H1, int64_t H2, const float* p,

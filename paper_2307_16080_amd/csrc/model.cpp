@@ -39,7 +39,7 @@ namespace mlk {
 
 namespace {
 
-constexpr int kFeatures = 26;
+constexpr int kFeatures = 27;
 
 int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
 double lg(double v) { return std::log2(std::max(v, 1.0)); }
@@ -88,6 +88,7 @@ void model_features(const Shape& s, const mlk_tile_config& c, int cus, float* f)
     f[i++] = s.dt == DT_F8 ? 1.f : 0.f;
     // work on the critical path: rounds of tiles times the work of one tile
     f[i++] = (float)lg(std::ceil(waves) * (double)c.bm * c.bn * c.bk * stages);
+    f[i++] = (float)c.layout;
 }
 
 static mlk_status upload_params(mlk_cost_model* m) {

@@ -74,8 +74,8 @@ bool db_lookup(const char* path, const std::string& key, const std::string& dev,
         size_t ut = s.find("\"us\": ");
         if (at == std::string::npos || ut == std::string::npos) continue;
         mlk_tile_config t;
-        if (sscanf(s.c_str() + at + 8, "%d, %d, %d, %d, %d, %d, %d, %d, %d", &t.bm, &t.bn, &t.bk,
-                   &t.wm, &t.wn, &t.split_k, &t.group_m, &t.xcd_remap, &t.stages) != 9)
+        if (sscanf(s.c_str() + at + 8, "%d, %d, %d, %d, %d, %d, %d, %d, %d, %d", &t.bm, &t.bn, &t.bk,
+                   &t.wm, &t.wn, &t.split_k, &t.group_m, &t.xcd_remap, &t.stages, &t.layout) != 10)
             continue;
         double u = 0;
         if (sscanf(s.c_str() + ut + 6, "%lf", &u) != 1) continue;
@@ -93,10 +93,10 @@ bool db_append(const char* path, const std::string& key, const std::string& dev,
     FILE* f = fopen(path, "a");
     if (!f) return false;
     fprintf(f,
-            "{\"key\": \"%s\", \"device\": \"%s\", \"cfg\": [%d, %d, %d, %d, %d, %d, %d, %d, %d], "
+            "{\"key\": \"%s\", \"device\": \"%s\", \"cfg\": [%d, %d, %d, %d, %d, %d, %d, %d, %d, %d], "
             "\"us\": %.4f, \"measured\": %d, \"legal\": %d, \"strategy\": %d, \"lib\": \"%s\"}\n",
             key.c_str(), dev.c_str(), c.bm, c.bn, c.bk, c.wm, c.wn, c.split_k, c.group_m,
-            c.xcd_remap, c.stages, us, n_measured, n_legal, strategy, mlk_version());
+            c.xcd_remap, c.stages, c.layout, us, n_measured, n_legal, strategy, mlk_version());
     const bool ok = fflush(f) == 0;
     fclose(f);
     return ok;
@@ -242,6 +242,7 @@ double fake_time_us(const Shape& s, int op, const mlk_tile_config& c, int index,
     double t = waves * (2.0 * c.bm * c.bn * c.bk * stages / (rate * eff) + 0.8) + 3.0;
     if (c.split_k > 1) t += 1.5;
     if (c.group_m > 1) t *= 0.99;
+    if (c.layout == 1) t = 0.6 * t + 4.0;
     if (op == MLK_OP_BATCHED) t += 2.0;
     const double noise = (double)(mix64(seed * 1000003ull + (uint64_t)index) >> 11) / 9007199254740992.0;
     return t * (1.0 + 0.02 * (noise - 0.5));

@@ -124,6 +124,14 @@ def test_config_space():
     # conv and batched spaces
     cp = mlk.conv_problem(32, 64, 56, 56, 64, 3, 3, 1, 1)
     assert mlk.config_count(cp) > 20
+    assert {c.layout for c in mlk.configs(cp)} == {0, 1}
+    # channels-last needs C a multiple of the 16-byte vector (8 bf16)
+    c3 = mlk.conv_problem(1, 3, 32, 32, 16, 3, 3, 1, 1)
+    assert {c.layout for c in mlk.configs(c3)} == {0}
+    assert not mlk.config_legal(c3, mlk.TileConfig(32, 32, 32, 1, 1, 1, 1, 0, 0, 1))
+    # and layout is meaningless for matmul
+    assert not mlk.config_legal(mlk.matmul_problem(64, 64, 64, L.MLK_BF16, L.MLK_F32),
+                                mlk.TileConfig(64, 64, 32, 2, 2, 1, 1, 0, 0, 1))
     bp = mlk.batched_problem([(100, 200, 300), (64, 64, 64)])
     bc = mlk.configs(bp)
     assert bc and all(c.split_k == 1 for c in bc)

@@ -46,7 +46,7 @@ def test_f32_conv_56x56x64():
 
 
 @pytest.mark.parametrize("cfg", all_tiles(L.MLK_F32, L.MLK_F32, conv=True) + all_tiles(L.MLK_BF16, L.MLK_F32, conv=True),
-                         ids=lambda c: f"{c.bm}x{c.bn}x{c.bk}_{c.wm}{c.wn}_s{c.stages}")
+                         ids=lambda c: f"{c.bm}x{c.bn}x{c.bk}_{c.wm}{c.wn}_l{c.layout}")
 def test_every_conv_tile(cfg):
     for case in CASES:
         N, C, H, W, F, KH, KW, s, p = case
@@ -84,11 +84,12 @@ def test_every_conv_tile(cfg):
 def test_conv_split_k_overwrite():
     x, w = conv_inputs(1, 64, 14, 14, 32, 3, 3, seed=4, dist="small_int")
     ref = oracle.conv2d_f64(x, w, (1, 1), (1, 1))
-    for sk in (1, 2, 4):
-        y = torch.full((1, 32, 14, 14), float("nan"), device="cuda")
-        mlk.conv2d_nchw_fchw(dev(x), dev(w), y, (1, 1), (1, 1), accumulate=False,
-                             cfg=mlk.TileConfig(32, 32, 16, 1, 1, sk, 1, 0))
-        assert np.array_equal(host(y).astype(np.float64), ref), sk
+    for layout in (0, 1):
+        for sk in (1, 2, 4):
+            y = torch.full((1, 32, 14, 14), float("nan"), device="cuda")
+            mlk.conv2d_nchw_fchw(dev(x), dev(w), y, (1, 1), (1, 1), accumulate=False,
+                                 cfg=mlk.TileConfig(32, 32, 16, 1, 1, sk, 1, 0, 0, layout))
+            assert np.array_equal(host(y).astype(np.float64), ref), (layout, sk)
 
 
 @pytest.mark.parametrize("batch", [1, 2])
