@@ -78,10 +78,13 @@ typedef enum {
  *   xcd_remap  1: map consecutive tiles to the same XCD (shared L2)
  *   stages     0: register-staged kernel (operands pass through registers
  *              on their way to a double-buffered LDS tile; any shape and
- *              alignment).  2..4: direct-to-LDS kernel (bf16, e4m3) whose
+ *              alignment).  2..5: direct-to-LDS kernel (bf16, e4m3) whose
  *              loads go from HBM straight into a ring of `stages` LDS
  *              buffers; needs K % bk == 0, 16-byte aligned A and B and row
- *              pitches that are multiples of 16 bytes.
+ *              pitches that are multiples of 16 bytes.  1: the same kernel
+ *              with its operands loaded through registers into two LDS
+ *              buffers (bf16, e4m3): any shape and alignment, and usable by
+ *              the persistent batched launch.
  *   layout     conv2d only.  0: the kernel gathers its operands straight from
  *              the NCHW input (any C).  1: the input is first transposed to
  *              channels-last (NHWC) and the filter to F x KH x KW x C in a

@@ -185,7 +185,7 @@ mlk_status check_config(const Shape& s, int op, const mlk_tile_config& c) {
     if (!e)
         return fail(MLK_ERR_CONFIG, "no compiled kernel for tile %dx%dx%d waves %dx%d stages %d (dtype %d%s)",
                     c.bm, c.bn, c.bk, c.wm, c.wn, c.stages, s.dt, s.conv ? ", conv" : "");
-    if (e->stages && (op == MLK_OP_BATCHED || !fast_shape_ok(s, e->bk)))
+    if (e->stages >= 2 && (op == MLK_OP_BATCHED || !fast_shape_ok(s, e->bk)))
         return fail(MLK_ERR_CONFIG, "direct-to-LDS tile needs K %% %d == 0 and 16-byte rows", e->bk);
     if (c.split_k < 1 || c.split_k > 64) return fail(MLK_ERR_CONFIG, "split_k must be in [1, 64]");
     const int64_t stages = cdiv(std::max<int64_t>(s.K, 1), c.bk);
@@ -208,7 +208,7 @@ std::vector<mlk_tile_config> enumerate_configs(const mlk_problem* p, const Shape
     for (const KernelEntry* e : registry()) {
         if (e->dt != s.dt || e->conv != s.conv) continue;
         if (batched && !e->persist) continue;
-        if (e->stages && !fast_shape_ok(s, e->bk)) continue;
+        if (e->stages >= 2 && !fast_shape_ok(s, e->bk)) continue;
         // a tile at least twice the problem in a dimension only adds padding
         if (e->bm > 32 && e->bm >= 2 * s.M) continue;
         if (e->bn > 32 && e->bn >= 2 * s.N) continue;
@@ -377,7 +377,7 @@ mlk_status launch_dense(const Shape& s, const void* A, int64_t lda, const void* 
     g.scale_b = sb;
     g.vec_a = ((uintptr_t)A % 16 == 0) && ((lda * es) % 16 == 0);
     g.vec_b = ((uintptr_t)B % 16 == 0) && ((ldb * es) % 16 == 0);
-    if (e->stages && !(g.vec_a && g.vec_b && ((s.M - 1) * lda + s.K) * es < ((int64_t)1 << 31) &&
+    if (e->stages >= 2 && !(g.vec_a && g.vec_b && ((s.M - 1) * lda + s.K) * es < ((int64_t)1 << 31) &&
                        ((s.K - 1) * ldb + s.N) * es < ((int64_t)1 << 31)))
         return fail(MLK_ERR_CONFIG, "direct-to-LDS tile needs 16-byte aligned operands and row pitches");
     return run_gemm(e, g, s, C, s.M, s.N, ldc, st);
@@ -518,7 +518,7 @@ mlk_status mlk_matmul(mlk_dtype in, mlk_dtype out, int64_t M, int64_t N, int64_t
     st = resolve(p, s, cfg, &c);
     if (st != MLK_OK) return st;
     if (M == 0 || N == 0) return MLK_OK;
-    if (c.stages && cfg_is_zero(cfg)) {
+    if (c.stages >= 2 && cfg_is_zero(cfg)) {
         // a tuned direct-to-LDS choice needs aligned operands; otherwise use the heuristic
         const int es = esize_in(s.dt);
         const bool aligned = (uintptr_t)A % 16 == 0 && (uintptr_t)B % 16 == 0 &&

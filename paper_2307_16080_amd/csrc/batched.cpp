@@ -1,13 +1,14 @@
 // batched.cpp -- many uneven GEMMs in one launch.
 //
-// Persistent mode: the host cuts every GEMM of the batch into output tiles,
-// estimates each tile's cost from its K depth, and packs the tiles into one
+// Persistent mode: the host cuts every GEMM of the batch into output tiles
+// (of the configured shape, or 64 x 64 for GEMMs too small for it), estimates
+// each tile's cost from its shape and K depth, and packs the tiles into one
 // bin per resident workgroup with the longest-processing-time-first rule
 // (largest tile to the currently least-loaded bin).  The device then runs one
 // grid of exactly that many workgroups; workgroup b walks its own task range,
 // so there is no device-side queue, counter or reset.  Every tile runs the
-// same code as a plain launch with split_k = 1, so results equal per-GEMM
-// launches bit for bit.
+// same code as a plain launch of its tile shape with split_k = 1, so results
+// equal per-GEMM launches of that shape bit for bit.
 //
 // Graph mode: the launch(es) are captured once into a hipGraph on a private
 // stream and replayed on the caller's stream; the graph and its device task
@@ -62,7 +63,7 @@ std::string plan_key(int dt, int64_t count, const mlk_gemm_desc* d, const mlk_ti
 GemmArgs args_for(int dt, const mlk_gemm_desc& d, const mlk_tile_config& c, int accumulate) {
     GemmArgs g;
     memset(&g, 0, sizeof g);
-    const int es = dt == DT_F32 ? 4 : 2;
+    const int es = dt == DT_F32 ? 4 : dt == DT_BF16 ? 2 : 1;
     g.M = d.M;
     g.N = d.N;
     g.K = d.K;
@@ -84,13 +85,10 @@ GemmArgs args_for(int dt, const mlk_gemm_desc& d, const mlk_tile_config& c, int 
     return g;
 }
 
-// Workgroups that fit on the device at once for this tile kernel: limited by
-// LDS (160 KB per CU) and by waves (at most two workgroups of 8 waves or four
-// of 4 waves share a CU without starving each other of registers).
+// Workgroups of the persistent kernel that are resident on the device at once
+// (the runtime's occupancy for its registers, LDS and waves): one bin each.
 int resident_blocks(const KernelEntry* e, int cus) {
-    int by_lds = (160 * 1024) / std::max(e->lds_bytes, 1);
-    int by_waves = e->threads >= 512 ? 1 : (e->threads >= 256 ? 2 : 4);
-    return cus * std::max(1, std::min(by_lds, by_waves));
+    return cus * (e->occupancy ? e->occupancy() : 1);
 }
 
 // Build the LPT schedule on the host and upload it.
@@ -102,14 +100,27 @@ mlk_status build_plan(int dt, int64_t count, const mlk_gemm_desc* d, const Kerne
         Task t;
     };
     std::vector<T> all;
+    // A register-staged kernel whose configured tile has 4 waves also carries
+    // a 64 x 64 tile;
+    // each GEMM takes the shape with the smaller estimated time: padded tile
+    // work plus a fixed prologue / epilogue of about two K stages, with the
+    // small tile's stages taken as 1.5x less efficient per flop.
+    const bool pair = e->stages == 0 && e->threads == 256 && !(c.bm == 64 && c.bn == 64);
+    const int sbk = dt == DT_F32 ? 32 : 64;
     for (int64_t i = 0; i < count; ++i) {
         gemms[i] = args_for(dt, d[i], c, accumulate);
         if (d[i].M == 0 || d[i].N == 0) continue;
-        const int64_t stages = cdiv(std::max<int64_t>(d[i].K, 1), c.bk);
-        for (int32_t tm = 0; tm < gemms[i].tiles_m; ++tm)
-            for (int32_t tn = 0; tn < gemms[i].tiles_n; ++tn)
-                // fixed prologue / epilogue cost of about two K stages
-                all.push_back(T{(double)stages + 2.0, Task{(int32_t)i, tm, tn, 0}});
+        const int64_t K = std::max<int64_t>(d[i].K, 1);
+        const int64_t tb = cdiv(d[i].M, c.bm) * cdiv(d[i].N, c.bn);
+        const double cost_big = (double)(cdiv(K, c.bk) + 2) * c.bm * c.bn * c.bk;
+        const int64_t ts = cdiv(d[i].M, 64) * cdiv(d[i].N, 64);
+        const double cost_small = 1.5 * (double)(cdiv(K, sbk) + 2) * 64 * 64 * sbk;
+        const bool small = pair && ts * cost_small < tb * cost_big;
+        const int bm = small ? 64 : c.bm, bn = small ? 64 : c.bn;
+        const double unit = small ? cost_small : cost_big;
+        for (int32_t tm = 0; tm < (int32_t)cdiv(d[i].M, bm); ++tm)
+            for (int32_t tn = 0; tn < (int32_t)cdiv(d[i].N, bn); ++tn)
+                all.push_back(T{unit, Task{(int32_t)i, tm, tn, small ? 1 : 0}});
     }
     const int cus = device_cus();
     int nblk = resident_blocks(e, cus);
@@ -211,7 +222,7 @@ mlk_status mlk_batched_matmul(mlk_dtype in, mlk_dtype out, int64_t count,
     Shape s;
     mlk_status st = shape_of_problem(&p, &s);
     if (st != MLK_OK) return st;
-    const int es = s.dt == DT_F32 ? 4 : 2;
+    const int es = s.dt == DT_F32 ? 4 : s.dt == DT_BF16 ? 2 : 1;
     for (int64_t i = 0; i < count; ++i) {
         const mlk_gemm_desc& d = descs[i];
         if (d.M == 0 || d.N == 0) continue;

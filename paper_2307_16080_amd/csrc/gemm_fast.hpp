@@ -9,10 +9,18 @@
 // What is computed is still linalg.matmul, C[M,N] (+)= A[M,K] * B[K,N]
 // (paper Sec. 2.1, listing "linalg-matmul"), with fp32 accumulation.
 //
-// Requirements (checked on the host): K % BK == 0, A, B 16-byte aligned with
-// row pitches that are multiples of 16 bytes, each operand < 2 GiB.  M and N
-// are arbitrary: rows past the end of an operand read as zero (buffer range
-// check) and columns past N only feed outputs that are never stored.
+// Requirements of the direct-to-LDS form (checked on the host): K % BK == 0,
+// A, B 16-byte aligned with row pitches that are multiples of 16 bytes, each
+// operand < 2 GiB.  M and N are arbitrary: rows past the end of an operand
+// read as zero (buffer range check) and columns past N only feed outputs that
+// are never stored.
+//
+// STAGES == 1 selects the register-loaded form of the same kernel: every
+// thread loads the 16-byte chunks that the DMA would have moved (with the
+// same swizzles) into registers, one stage ahead, and writes them to one of
+// two LDS buffers.  It takes any shape and alignment (rows aligned only to
+// the element size, K not a multiple of BK) and is the tile that the
+// persistent batched launch runs.
 //
 // LDS layout per stage: A as BM rows of 128 bytes (BK = 64 bf16 or 128
 // e4m3), the 16-byte chunk c of row r stored at chunk c ^ fa(r); B as BK rows
@@ -23,7 +31,13 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 #include "gemm_tile.hpp"
+
+#ifndef MLK_PP_DEFAULT
+#define MLK_PP_DEFAULT 0
+#endif
 
 namespace mlk {
 
@@ -63,24 +77,35 @@ __device__ inline void wait_vmcnt() {
     __builtin_amdgcn_s_waitcnt((N & 0xF) | ((N >> 4) << 14) | 0x70 | 0xF00);
 }
 
-// A swizzle: chosen by measurement among XOR patterns (a ds_read_b128 sweep:
+// A swizzle: chosen by measurement among XOR patterns (a ds_read_b128 sweep
+// in which 16 lanes read 16 consecutive 128-byte rows at one logical chunk:
 // this one streams 181 B/clk/CU, the plain layout 59).
 __device__ inline int fa(int r) { return (r & 7) ^ ((r >> 2) & 2); }
 
 template <int DT, int BM, int BN, int WM, int WN, int STAGES>
 struct FastGemm {
     static_assert(DT == DT_BF16 || DT == DT_F8, "direct-to-LDS kernel: bf16 or e4m3");
+    static constexpr int KB = 128;                 // bytes of K per A row per stage
     static constexpr int ES = DT == DT_BF16 ? 2 : 1;
-    static constexpr int BK = 128 / ES;            // elements per A row per stage
+    static constexpr int BK = KB / ES;             // elements per A row per stage
     static constexpr int KSTEP = DT == DT_BF16 ? 32 : 128;  // k per MFMA
     static constexpr int NW = WM * WN;
     static constexpr int NT = 64 * NW;
-    static constexpr int A_ROW = BK * ES;          // 128 bytes
+    static constexpr int A_ROW = KB;               // bytes
+    static constexpr int A_CPR = KB / 16;          // 16-byte chunks per A row
     static constexpr int B_ROW = BN * ES;
     static constexpr int A_STAGE = BM * A_ROW;
     static constexpr int B_STAGE = BK * B_ROW;
     static constexpr int STAGE = A_STAGE + B_STAGE;
-    static constexpr int LDS_BYTES = STAGES * STAGE;
+    static constexpr bool REG = STAGES == 1;      // register-loaded form
+    // Ping-pong schedule (8 waves, two direct-to-LDS buffers): waves 0-3 and
+    // 4-7 (one of each on every SIMD) alternate, one phase apart, between
+    // reading a stage's fragments from LDS and running its MFMAs, so that each
+    // SIMD always has one wave issuing MFMAs while the other waits on LDS.
+    static constexpr bool PP = MLK_PP_DEFAULT && DT == DT_BF16 && !REG && STAGES == 2 && WM * WN == 8;
+    static constexpr int NBUF = REG ? 2 : STAGES;  // LDS stage buffers
+    static constexpr int EPV = 16 / ES;            // elements per 16-byte chunk
+    static constexpr int LDS_BYTES = NBUF * STAGE;
     static constexpr int A_SLABS = A_STAGE / 1024;  // one wave-wide 16-byte load fills a slab
     static constexpr int B_SLABS = B_STAGE / 1024;
     static constexpr int NA = A_SLABS / NW;         // per wave per stage
@@ -88,7 +113,7 @@ struct FastGemm {
     static constexpr int LOADS = NA + NB;
     static constexpr int WTM = BM / WM, WTN = BN / WN;
     static constexpr int TM = WTM / 16, TN = WTN / 16;
-    static constexpr int A_ROWS_PER_SLAB = 1024 / A_ROW;  // 8
+    static constexpr int A_ROWS_PER_SLAB = 1024 / A_ROW;
     static constexpr int B_ROWS_PER_SLAB = 1024 / B_ROW;
     static constexpr int B_CHUNKS = B_ROW / 16;
 
@@ -104,7 +129,19 @@ struct FastGemm {
     }
     static_assert(LDS_BYTES <= 160 * 1024, "LDS budget");
     static_assert(WTM % 16 == 0 && WTN % 16 == 0, "wave tile");
-    static_assert(STAGES >= 2 && (STAGES - 1) * LOADS < 64, "pipeline depth");
+    static_assert(STAGES >= 1 && (STAGES - 1) * LOADS < 64, "pipeline depth");
+
+    // wait until stage `it` has landed: at most `later` stages (issued after
+    // it) may still be in flight, LOADS buffer loads each per lane
+    template <int L>
+    __device__ static inline void wait_stage(int later) {
+        if constexpr (L == 0) {
+            wait_vmcnt<0>();
+        } else {
+            if (later >= L) wait_vmcnt<L * LOADS>();
+            else wait_stage<L - 1>(later);
+        }
+    }
 
     __device__ static inline void issue_stage(const i32x4_t& ra, const i32x4_t& rb,
                                               const int* voff_a, const int* voff_b, int64_t k0,
@@ -124,37 +161,201 @@ struct FastGemm {
         }
     }
 
-    __device__ static inline void run(const GemmArgs& g, int tm, int tn, int kz, uint8_t* lds) {
-        const int tid = threadIdx.x;
-        const int lane = tid & 63, wave = tid >> 6;
-        const int wy = wave / WN, wx = wave % WN;
-        const int64_t m0 = (int64_t)tm * BM, n0 = (int64_t)tn * BN;
-        const int64_t kstages = g.K / BK;
-        const int64_t per = (kstages + g.split_k - 1) / g.split_k;
-        const int64_t s_beg = (int64_t)kz * per;
-        const int nk = (int)max<int64_t>(0, min<int64_t>(kstages, s_beg + per) - s_beg);
+    // ---- one stage's MFMA operands, read from LDS ahead of their MFMAs
+    typedef typename std::conditional<DT == DT_BF16, u4_t, i8_t>::type afrag_t;
+    typedef typename std::conditional<DT == DT_BF16, bf8_t, i8_t>::type bfrag_t;
+    struct Frags {
+        afrag_t a[BK / KSTEP][TM];
+        bfrag_t b[BK / KSTEP][TN];
+    };
 
-        const i32x4_t ra = make_rsrc(g.A, (uint32_t)(((g.M - 1) * g.lda + g.K) * ES));
-        const i32x4_t rb = make_rsrc(g.B, (uint32_t)(((g.K - 1) * g.ldb + g.N) * ES));
+    __device__ static inline void read_frags(const uint8_t* sa, const uint8_t* sb, int wy, int wx,
+                                             int lr, int lg, Frags& f) {
+        typedef __attribute__((address_space(3))) bf4_t* tp;
+        typedef __attribute__((address_space(3))) i2_t* t8p;
+#pragma unroll
+        for (int ks = 0; ks < BK / KSTEP; ++ks) {
+            if constexpr (DT == DT_BF16) {
+#pragma unroll
+                for (int i = 0; i < TM; ++i) {
+                    const int r = wy * WTM + i * 16 + lr;
+                    f.a[ks][i] = *(const u4_t*)(sa + r * A_ROW + (((ks * 4 + lg) ^ fa(r)) * 16));
+                }
+#pragma unroll
+                for (int j = 0; j < TN; ++j) {
+                    const int nb = wx * WTN + j * 16 + 4 * (lr & 3);
+                    bf4_t h[2];
+#pragma unroll
+                    for (int half = 0; half < 2; ++half) {
+                        const int k = ks * 32 + lg * 8 + half * 4 + (lr >> 2);
+                        const uint8_t* p = sb + k * B_ROW + ((nb >> 3) ^ fb(k)) * 16 + (nb & 7) * 2;
+                        h[half] = __builtin_amdgcn_ds_read_tr16_b64_v4bf16((tp)(p));
+                    }
+                    f.b[ks][j] = bf8_t{h[0][0], h[0][1], h[0][2], h[0][3], h[1][0], h[1][1], h[1][2], h[1][3]};
+                }
+            } else {
+#pragma unroll
+                for (int i = 0; i < TM; ++i) {
+                    const int r = wy * WTM + i * 16 + lr;
+                    const u4_t lo = *(const u4_t*)(sa + r * A_ROW + ((2 * lg) ^ fa(r)) * 16);
+                    const u4_t hi = *(const u4_t*)(sa + r * A_ROW + ((2 * lg + 1) ^ fa(r)) * 16);
+                    f.a[ks][i] = i8_t{(int)lo[0], (int)lo[1], (int)lo[2], (int)lo[3],
+                                      (int)hi[0], (int)hi[1], (int)hi[2], (int)hi[3]};
+                }
+#pragma unroll
+                for (int j = 0; j < TN; ++j) {
+                    const int nb = wx * WTN + j * 16 + 8 * (lr & 1);
+                    i2_t q[4];
+#pragma unroll
+                    for (int qq = 0; qq < 4; ++qq) {
+                        const int k = lg * 32 + qq * 8 + (lr >> 1);
+                        const uint8_t* p = sb + k * B_ROW + ((nb >> 4) ^ fb(k)) * 16 + (nb & 15);
+                        q[qq] = __builtin_amdgcn_ds_read_tr8_b64_v2i32((t8p)(p));
+                    }
+                    f.b[ks][j] = i8_t{q[0][0], q[0][1], q[1][0], q[1][1], q[2][0], q[2][1], q[3][0], q[3][1]};
+                }
+            }
+        }
+    }
 
-        // per-lane byte offsets of this wave's load slabs (k0 added as the scalar offset)
-        int voff_a[NA], voff_b[NB];
+    __device__ static inline void mma_frags(const Frags& f, f4_t (&acc)[TM][TN]) {
+#pragma unroll
+        for (int ks = 0; ks < BK / KSTEP; ++ks)
+#pragma unroll
+            for (int j = 0; j < TN; ++j)
+#pragma unroll
+                for (int i = 0; i < TM; ++i) {
+                    if constexpr (DT == DT_BF16)
+                        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                            __builtin_bit_cast(bf8_t, f.a[ks][i]), f.b[ks][j], acc[i][j], 0, 0, 0);
+                    else
+                        acc[i][j] = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(
+                            f.a[ks][i], f.b[ks][j], acc[i][j], 0, 0, 0, 127, 0, 127);
+                }
+    }
+
+    // barrier between ping-pong phases; nothing is scheduled across it
+    __device__ static inline void phase_barrier() {
+        __builtin_amdgcn_sched_barrier(0);
+        asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
+        __builtin_amdgcn_sched_barrier(0);
+    }
+
+    // ---- register-loaded form: per-thread chunk state, fixed for a tile
+    struct RegSlots {
+        int64_t a_off[NA];   // byte offset of the chunk's row (clamped to row 0 when invalid)
+        int a_el[NA];        // element offset of the chunk inside its row (swizzled source chunk)
+        bool a_ok[NA];       // row < M
+        int64_t b_off[NB];   // byte offset of (row r of the stage, first column of the chunk)
+        int b_r[NB];         // row of the stage
+        int b_col[NB];       // first column of the chunk
+        int b_nv[NB];        // valid columns in the chunk (0..EPV)
+    };
+
+    __device__ static inline void reg_slots(const GemmArgs& g, int64_t m0, int64_t n0, int wave,
+                                            int lane, RegSlots& rs) {
 #pragma unroll
         for (int i = 0; i < NA; ++i) {
             const int slab = wave + i * NW;
-            const int r = slab * A_ROWS_PER_SLAB + lane / 8;
-            const int c = (lane & 7) ^ fa(r);
-            int64_t row = m0 + r;
-            // rows past the operand read zero: push their offset past the range
-            voff_a[i] = row < g.M ? (int)(row * g.lda * ES + c * 16) : 0x7FFFFFF0;
+            const int r = slab * A_ROWS_PER_SLAB + lane / A_CPR;
+            const int c = (lane % A_CPR) ^ fa(r);
+            const int64_t row = m0 + r;
+            rs.a_ok[i] = row < g.M;
+            rs.a_off[i] = (rs.a_ok[i] ? row : 0) * g.lda * ES;
+            rs.a_el[i] = c * EPV;
         }
 #pragma unroll
         for (int i = 0; i < NB; ++i) {
             const int slab = wave + i * NW;
             const int r = slab * B_ROWS_PER_SLAB + lane / B_CHUNKS;
             const int c = (lane % B_CHUNKS) ^ fb(r);
-            const int64_t col = n0 + c * (16 / ES);
-            voff_b[i] = col < g.N ? (int)((r * g.ldb + col) * ES) : 0x7FFFFFF0;
+            const int64_t col = n0 + c * EPV;
+            rs.b_r[i] = r;
+            rs.b_col[i] = (int)min<int64_t>(col, g.N);
+            rs.b_nv[i] = (int)max<int64_t>(0, min<int64_t>(EPV, g.N - col));
+            rs.b_off[i] = (int64_t)r * g.ldb * ES + (int64_t)rs.b_col[i] * ES;
+        }
+    }
+
+    // the chunks of the stage starting at k0 (zero outside the operands)
+    __device__ static inline void reg_load(const GemmArgs& g, const RegSlots& rs, int64_t k0,
+                                           u4_t* ra, u4_t* rb) {
+        const gbytes A = (gbytes)g.A, B = (gbytes)g.B;
+        const bool kfull = k0 + BK <= g.K;
+#pragma unroll
+        for (int i = 0; i < NA; ++i) {
+            const int64_t k = k0 + rs.a_el[i];
+            const gbytes row = A + rs.a_off[i];
+            u4_t v = u4_t{0u, 0u, 0u, 0u};
+            if (rs.a_ok[i]) {
+                if (kfull) v = g.vec_a ? *(const MLK_GLOBAL u4_t*)(row + k * ES) : load16_any<ES>(row + k * ES);
+                else if (k < g.K) v = load_unaligned<ES>(row, k, (int)min<int64_t>(EPV, g.K - k));
+            }
+            ra[i] = v;
+        }
+        const int64_t kb = k0 * g.ldb * ES;
+#pragma unroll
+        for (int i = 0; i < NB; ++i) {
+            u4_t v = u4_t{0u, 0u, 0u, 0u};
+            if (rs.b_nv[i] > 0 && (kfull || k0 + rs.b_r[i] < g.K)) {
+                const gbytes p = B + kb + rs.b_off[i];
+                if (rs.b_nv[i] == EPV) v = g.vec_b ? *(const MLK_GLOBAL u4_t*)p : load16_any<ES>(p);
+                else v = load_unaligned<ES>(p - (int64_t)rs.b_col[i] * ES, rs.b_col[i], rs.b_nv[i]);
+            }
+            rb[i] = v;
+        }
+    }
+
+    // registers -> the LDS positions the DMA would have filled
+    __device__ static inline void reg_store(uint8_t* stage, const u4_t* ra, const u4_t* rb, int wave,
+                                            int lane) {
+#pragma unroll
+        for (int i = 0; i < NA; ++i)
+            *(u4_t*)(stage + (wave + i * NW) * 1024 + lane * 16) = ra[i];
+#pragma unroll
+        for (int i = 0; i < NB; ++i)
+            *(u4_t*)(stage + A_STAGE + (wave + i * NW) * 1024 + lane * 16) = rb[i];
+    }
+
+    __device__ static inline void run(const GemmArgs& g, int tm, int tn, int kz, uint8_t* lds) {
+        const int tid = threadIdx.x;
+        const int lane = tid & 63, wave = tid >> 6;
+        const int wy = wave / WN, wx = wave % WN;
+        const int64_t m0 = (int64_t)tm * BM, n0 = (int64_t)tn * BN;
+        const int64_t kstages = REG ? (g.K + BK - 1) / BK : g.K / BK;
+        const int64_t per = (kstages + g.split_k - 1) / g.split_k;
+        const int64_t s_beg = (int64_t)kz * per;
+        const int nk = (int)max<int64_t>(0, min<int64_t>(kstages, s_beg + per) - s_beg);
+
+        // direct-to-LDS form: buffer resources and per-lane byte offsets of this
+        // wave's load slabs (k0 added as the scalar offset)
+        i32x4_t ra = {0, 0, 0, 0}, rb = {0, 0, 0, 0};
+        int voff_a[NA], voff_b[NB];
+        // register-loaded form: chunk state and the stage in flight
+        RegSlots rs;
+        u4_t qa[NA], qb[NB];
+        if constexpr (!REG) {
+            ra = make_rsrc(g.A, (uint32_t)(((g.M - 1) * g.lda + g.K) * ES));
+            rb = make_rsrc(g.B, (uint32_t)(((g.K - 1) * g.ldb + g.N) * ES));
+#pragma unroll
+            for (int i = 0; i < NA; ++i) {
+                const int slab = wave + i * NW;
+                const int r = slab * A_ROWS_PER_SLAB + lane / A_CPR;
+                const int c = (lane % A_CPR) ^ fa(r);
+                int64_t row = m0 + r;
+                // rows past the operand read zero: push their offset past the range
+                voff_a[i] = row < g.M ? (int)(row * g.lda * ES + c * 16) : 0x7FFFFFF0;
+            }
+#pragma unroll
+            for (int i = 0; i < NB; ++i) {
+                const int slab = wave + i * NW;
+                const int r = slab * B_ROWS_PER_SLAB + lane / B_CHUNKS;
+                const int c = (lane % B_CHUNKS) ^ fb(r);
+                const int64_t col = n0 + c * (16 / ES);
+                voff_b[i] = col < g.N ? (int)((r * g.ldb + col) * ES) : 0x7FFFFFF0;
+            }
+        } else {
+            reg_slots(g, m0, n0, wave, lane, rs);
         }
 
         f4_t acc[TM][TN];
@@ -163,26 +364,44 @@ struct FastGemm {
 #pragma unroll
             for (int j = 0; j < TN; ++j) acc[i][j] = f4_t{0.f, 0.f, 0.f, 0.f};
 
-        // prologue: STAGES-1 stages in flight
+        // prologue: STAGES-1 stages in flight (direct), or stage 0 in LDS (registers)
+        if constexpr (!REG) {
 #pragma unroll
-        for (int s = 0; s < STAGES - 1; ++s)
-            if (s < nk) issue_stage(ra, rb, voff_a, voff_b, (s_beg + s) * BK, g.ldb, lds + s * STAGE, wave);
+            for (int s = 0; s < STAGES - 1; ++s)
+                if (s < nk) issue_stage(ra, rb, voff_a, voff_b, (s_beg + s) * BK, g.ldb, lds + s * STAGE, wave);
+        } else {
+            if (nk > 0) {
+                reg_load(g, rs, s_beg * BK, qa, qb);
+                reg_store(lds, qa, qb, wave, lane);
+            }
+        }
 
         const int lr = lane & 15, lg = lane >> 4;
         // This lane's outputs: rows wy*WTM + i*16 + lg*4 + r, columns
         // wx*WTN + j*16 + lr of the tile whose corner is Ct (a uniform base);
         // offsets inside the tile are 32-bit.
-        float* const Ct = (float*)g.C + m0 * g.ldc + n0;
+        MLK_GLOBAL float* const Ct = (MLK_GLOBAL float*)g.C + m0 * g.ldc + n0;
         const int ldc = (int)g.ldc;
         const int row0 = wy * WTM + lg * 4, col0 = wx * WTN + lr;
         const bool full = m0 + BM <= g.M && n0 + BN <= g.N;
         const int mrem = (int)min<int64_t>(BM, g.M - m0), nrem = (int)min<int64_t>(BN, g.N - n0);
         // C += A B: start the accumulators from C itself, so that its read
         // happens here, beside the first stage's loads, instead of in a
-        // read-add-write epilogue after the last MFMA.  (e4m3 scales the
-        // product, so it keeps C apart.)
-        const bool c_in_acc = DT != DT_F8 && g.accumulate && !g.atomic;
+        // read-add-write epilogue after the last MFMA.  e4m3 multiplies the
+        // sum by alpha = scale_a * scale_b at the end, so it starts from
+        // C / alpha (one extra rounding of C); when alpha is far from 1, or a
+        // wave finds a C / alpha that overflows, that wave keeps C apart.
+        float alpha = 1.0f, inv_alpha = 1.0f;
+        bool c_in_acc = g.accumulate && !g.atomic;
+        if constexpr (DT == DT_F8) {
+            if (g.scale_a) alpha *= *(const MLK_GLOBAL float*)g.scale_a;
+            if (g.scale_b) alpha *= *(const MLK_GLOBAL float*)g.scale_b;
+            const float aa = fabsf(alpha);
+            c_in_acc = c_in_acc && aa >= 0x1p-60f && aa <= 0x1p60f;
+            inv_alpha = 1.0f / alpha;
+        }
         if (c_in_acc) {
+            bool over = false;
 #pragma unroll
             for (int j = 0; j < TN; ++j)
 #pragma unroll
@@ -190,31 +409,70 @@ struct FastGemm {
 #pragma unroll
                     for (int r = 0; r < 4; ++r) {
                         const int row = row0 + i * 16 + r, col = col0 + j * 16;
-                        acc[i][j][r] = (full || (row < mrem && col < nrem)) ? Ct[row * ldc + col] : 0.0f;
+                        const float x = (full || (row < mrem && col < nrem)) ? Ct[row * ldc + col] : 0.0f;
+                        if constexpr (DT == DT_F8) {
+                            const float y = x * inv_alpha;
+                            over |= __builtin_isinf(y) && !__builtin_isinf(x);
+                            acc[i][j][r] = y;
+                        } else {
+                            acc[i][j][r] = x;
+                        }
                     }
+            if constexpr (DT == DT_F8) {
+                if (__any(over)) {
+                    c_in_acc = false;
+#pragma unroll
+                    for (int i = 0; i < TM; ++i)
+#pragma unroll
+                        for (int j = 0; j < TN; ++j) acc[i][j] = f4_t{0.f, 0.f, 0.f, 0.f};
+                }
+            }
         }
 
         typedef __attribute__((address_space(3))) bf4_t* tp;
         typedef __attribute__((address_space(3))) i2_t* t8p;
-        for (int it = 0; it < nk; ++it) {
-            // stage `it` has landed once at most (stages issued after it) loads remain
-            const int later = min(STAGES - 2, nk - 1 - it);
-            if (later >= 1) {
-                if constexpr (STAGES >= 3) {
-                    if (later == 1) wait_vmcnt<LOADS>();
-                    else wait_vmcnt<(STAGES - 2) * LOADS>();
+        if constexpr (PP) {
+            // Phase 2s: stage s+1 is issued into the buffer that held stage s-1;
+            // waves 0-3 read stage s, waves 4-7 multiply stage s-1.  Phase 2s+1:
+            // waves 0-3 multiply stage s, waves 4-7 read it; every wave then
+            // waits for its share of stage s+1 before the barrier.
+            const bool first = wave < 4;
+            Frags f;
+            wait_vmcnt<0>();
+            phase_barrier();
+            for (int s = 0; s <= nk; ++s) {
+                if (s + 1 < nk)
+                    issue_stage(ra, rb, voff_a, voff_b, (s_beg + s + 1) * BK, g.ldb,
+                                lds + ((s + 1) & 1) * STAGE, wave);
+                if (first) {
+                    if (s < nk) read_frags(lds + (s & 1) * STAGE, lds + (s & 1) * STAGE + A_STAGE, wy, wx, lr, lg, f);
                 } else {
-                    wait_vmcnt<0>();
+                    if (s >= 1) mma_frags(f, acc);
                 }
-            } else {
+                if (s == nk) break;
+                phase_barrier();
+                if (first) mma_frags(f, acc);
+                else read_frags(lds + (s & 1) * STAGE, lds + (s & 1) * STAGE + A_STAGE, wy, wx, lr, lg, f);
                 wait_vmcnt<0>();
+                phase_barrier();
+            }
+        }
+        for (int it = 0; it < (PP ? 0 : nk); ++it) {
+            if constexpr (!REG) {
+                // stage `it` has landed once at most (stages issued after it) loads remain
+                wait_stage<(STAGES >= 2 ? STAGES - 2 : 0)>(min(STAGES - 2, nk - 1 - it));
+            } else {
+                // next stage into registers, in flight across the barrier and the MFMAs
+                if (it + 1 < nk) reg_load(g, rs, (s_beg + it + 1) * BK, qa, qb);
             }
             // all of this workgroup's waves: stage `it` visible, stage it-1 fully read
             asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
-            if (it + STAGES - 1 < nk)
-                issue_stage(ra, rb, voff_a, voff_b, (s_beg + it + STAGES - 1) * BK, g.ldb,
-                            lds + ((it + STAGES - 1) % STAGES) * STAGE, wave);
-            const uint8_t* sa = lds + (it % STAGES) * STAGE;
+            if constexpr (!REG) {
+                if (it + STAGES - 1 < nk)
+                    issue_stage(ra, rb, voff_a, voff_b, (s_beg + it + STAGES - 1) * BK, g.ldb,
+                                lds + ((it + STAGES - 1) % STAGES) * STAGE, wave);
+            }
+            const uint8_t* sa = lds + (it % NBUF) * STAGE;
             const uint8_t* sb = sa + A_STAGE;
 #pragma unroll
             for (int ks = 0; ks < BK / KSTEP; ++ks) {
@@ -280,14 +538,12 @@ struct FastGemm {
                                 af[i], bfr[j], acc[i][j], 0, 0, 0, 127, 0, 127);
                 }
             }
+            if constexpr (REG) {
+                if (it + 1 < nk) reg_store(lds + ((it + 1) % NBUF) * STAGE, qa, qb, wave, lane);
+            }
         }
 
         // epilogue: lane l, register r holds output row 4*(l/16) + r, column l % 16
-        float alpha = 1.0f;
-        if constexpr (DT == DT_F8) {
-            if (g.scale_a) alpha *= *g.scale_a;
-            if (g.scale_b) alpha *= *g.scale_b;
-        }
 #pragma unroll
         for (int j = 0; j < TN; ++j)
 #pragma unroll
@@ -296,9 +552,9 @@ struct FastGemm {
                 for (int r = 0; r < 4; ++r) {
                     const int row = row0 + i * 16 + r, col = col0 + j * 16;
                     if (!(full || (row < mrem && col < nrem))) continue;
-                    float* p = Ct + row * ldc + col;
+                    MLK_GLOBAL float* p = Ct + row * ldc + col;
                     const float v = DT == DT_F8 ? alpha * acc[i][j][r] : acc[i][j][r];
-                    if (g.atomic) atomicAdd(p, v);
+                    if (g.atomic) __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                     else if (c_in_acc || !g.accumulate) *p = v;
                     else *p = *p + v;
                 }

@@ -128,21 +128,66 @@ template <> struct Mma<DT_F8> {
 
 // ---------------------------------------------------------------- helpers
 
-// 16 bytes holding elements [e0, e0 + nvalid) of a row, zero beyond.
+// Global-memory views.  Accesses through these compile to global_load /
+// global_store; through a generic pointer they would be flat accesses, which
+// also count against the LDS wait counter and so serialise with LDS traffic.
+#define MLK_GLOBAL __attribute__((address_space(1)))
+typedef const MLK_GLOBAL uint8_t* gbytes;
+typedef uint32_t u4a_t __attribute__((ext_vector_type(4), aligned(4)));
+
+__host__ __device__ inline uint32_t funnel32(uint32_t lo, uint32_t hi, int byteshift) {
+    return (uint32_t)((((uint64_t)hi << 32) | lo) >> (8 * byteshift));
+}
+
+// The 16 bytes at p, all of them wanted, for a p that is a multiple of the
+// element size but not necessarily of 4 or 16: one dword-aligned 16-byte load
+// and, when p is not dword aligned, the dword after it, joined by byte shifts.
+// Every dword read holds a wanted byte (when p is dword aligned the last dword
+// is read again instead of the next one).
 template <int ES>
-__device__ inline u4_t load_partial(const uint8_t* row, int64_t e0, int nvalid) {
-    u4_t v = {0u, 0u, 0u, 0u};
-    constexpr int EPV = 16 / ES;
+__device__ inline u4_t load16_any(gbytes p) {
+    const uintptr_t a = (uintptr_t)p;
+    const int sh = (int)(a & 3);
+    const gbytes q = (gbytes)(a - (uintptr_t)sh);
+    const u4a_t lo = *(const MLK_GLOBAL u4a_t*)q;
+    if constexpr (ES == 4) {
+        return u4_t{lo[0], lo[1], lo[2], lo[3]};
+    } else {
+        const uint32_t hi = *(const MLK_GLOBAL uint32_t*)(q + (sh ? 16 : 12));
+        return u4_t{funnel32(lo[0], lo[1], sh), funnel32(lo[1], lo[2], sh),
+                    funnel32(lo[2], lo[3], sh), funnel32(lo[3], hi, sh)};
+    }
+}
+
+// The 16 bytes holding elements [e0, e0 + nvalid) of a row (zero beyond):
+// the tail of a row, where reading past the wanted bytes could leave the
+// operand.  Reads the (at most two) aligned 16-byte blocks that contain the
+// wanted bytes and shifts them into place; an aligned block that holds a
+// wanted byte lies in the same page as that byte.
+template <int ES>
+__device__ inline u4_t load_unaligned(gbytes row, int64_t e0, int nvalid) {
+    const uintptr_t a = (uintptr_t)(row + e0 * ES);
+    const MLK_GLOBAL u4_t* blk = (const MLK_GLOBAL u4_t*)(a & ~(uintptr_t)15);
+    const int sh = (int)(a & 15);
+    const int nbytes = nvalid * ES;
+    const u4_t lo = blk[0];
+    const u4_t hi = (sh + nbytes > 16) ? blk[1] : u4_t{0u, 0u, 0u, 0u};
+    const uint32_t w[8] = {lo[0], lo[1], lo[2], lo[3], hi[0], hi[1], hi[2], hi[3]};
+    const int q = sh >> 2, r = sh & 3;
+    u4_t v;
 #pragma unroll
-    for (int e = 0; e < EPV; ++e) {
-        if (e < nvalid) {
-            uint32_t x;
-            if constexpr (ES == 4) x = *(const uint32_t*)(row + (e0 + e) * 4);
-            else if constexpr (ES == 2) x = *(const uint16_t*)(row + (e0 + e) * 2);
-            else x = *(const uint8_t*)(row + (e0 + e));
-            const int bit = e * ES * 8;
-            v[bit >> 5] |= x << (bit & 31);
-        }
+    for (int d = 0; d < 4; ++d) {
+        // dwords d + q and d + q + 1 of the 32-byte window, selected without
+        // dynamic register indexing
+        uint32_t x0 = w[d], x1 = w[d + 1];
+        if (q == 1) { x0 = w[d + 1]; x1 = w[d + 2]; }
+        if (q == 2) { x0 = w[d + 2]; x1 = w[d + 3]; }
+        if (q == 3) { x0 = w[d + 3]; x1 = w[d + 4]; }
+        uint32_t x = funnel32(x0, x1, r);
+        const int keep = nbytes - 4 * d;  // valid bytes in this dword
+        if (keep <= 0) x = 0u;
+        else if (keep < 4) x &= (1u << (8 * keep)) - 1u;
+        v[d] = x;
     }
     return v;
 }
@@ -234,7 +279,8 @@ struct Tile {
     // ---- global -> registers
     __device__ static inline void load_a(const GemmArgs& g, int64_t m0, int64_t k0, u4_t* ra,
                                          int tid) {
-        const uint8_t* A = (const uint8_t*)g.A;
+        const gbytes A = (gbytes)g.A;
+        const bool kfull = k0 + BK <= g.K;  // every chunk of this stage lies inside K
 #pragma unroll
         for (int i = 0; i < NA; ++i) {
             const int c = tid + i * NT;
@@ -242,10 +288,12 @@ struct Tile {
             if ((BM * CPR) % NT != 0 && c >= BM * CPR) continue;
             const int r = c / CPR, cc = c % CPR;
             const int64_t m = m0 + r, k = k0 + cc * EPV;
-            if (m >= g.M || k >= g.K) continue;
-            const uint8_t* row = A + m * g.lda * ES;
-            if (g.vec_a && k + EPV <= g.K) ra[i] = *(const u4_t*)(row + k * ES);
-            else ra[i] = load_partial<ES>(row, k, (int)min<int64_t>(EPV, g.K - k));
+            if (m >= g.M) continue;
+            const gbytes row = A + m * g.lda * ES;
+            if (kfull || k + EPV <= g.K)
+                ra[i] = g.vec_a ? *(const MLK_GLOBAL u4_t*)(row + k * ES) : load16_any<ES>(row + k * ES);
+            else if (k < g.K)
+                ra[i] = load_unaligned<ES>(row, k, (int)(g.K - k));
         }
     }
 
@@ -257,6 +305,7 @@ struct Tile {
             nhwc_gather(g, k0, rb, tid, cols);
             return;
         }
+        const bool kfull = k0 + BK <= g.K;
 #pragma unroll
         for (int i = 0; i < NB; ++i) {
             const int blk = tid + i * NT;
@@ -268,15 +317,24 @@ struct Tile {
             const int64_t kb = k0 + kr * EPV, n = n0 + nc * EPV;
             if constexpr (CONV == 0) {
                 if (n >= g.N) continue;
-                const uint8_t* B = (const uint8_t*)g.B;
+                const gbytes B = (gbytes)g.B;
+                const int64_t pitch = g.ldb * ES;
                 const int nval = (int)min<int64_t>(EPV, g.N - n);
+                if (nval == EPV && (kfull || kb + EPV <= g.K)) {
+                    const gbytes p = B + kb * pitch + n * ES;
+                    if (g.vec_b) {
 #pragma unroll
-                for (int e = 0; e < EPV; ++e) {
-                    const int64_t k = kb + e;
-                    if (k >= g.K) continue;
-                    const uint8_t* row = B + k * g.ldb * ES;
-                    if (g.vec_b && nval == EPV) v[e] = *(const u4_t*)(row + n * ES);
-                    else v[e] = load_partial<ES>(row, n, nval);
+                        for (int e = 0; e < EPV; ++e) v[e] = *(const MLK_GLOBAL u4_t*)(p + e * pitch);
+                    } else {
+#pragma unroll
+                        for (int e = 0; e < EPV; ++e) v[e] = load16_any<ES>(p + e * pitch);
+                    }
+                } else {
+#pragma unroll
+                    for (int e = 0; e < EPV; ++e) {
+                        const int64_t k = kb + e;
+                        if (k < g.K) v[e] = load_unaligned<ES>(B + k * pitch, n, nval);
+                    }
                 }
             } else if constexpr (CONV == 1) {
                 conv_gather(g, cols[i], kb, v);
@@ -331,7 +389,7 @@ struct Tile {
     __device__ static inline void conv_gather(const GemmArgs& g, const ConvCols& cc, int64_t kb,
                                               u4_t* v) {
         if (!cc.any || kb >= g.K) return;
-        const uint8_t* X = (const uint8_t*)g.B;
+        const gbytes X = (gbytes)g.B;
         const int KHW = g.ckh * g.ckw, HW = g.ch * g.cw;
         int c = (int)(kb / KHW);
         const int rem = (int)(kb - (int64_t)c * KHW);
@@ -349,8 +407,8 @@ struct Tile {
                     if (in) {
                         const int64_t off = (int64_t)cc.cbase[j] + coff;
                         uint32_t x;
-                        if constexpr (ES == 4) x = *(const uint32_t*)(X + off * 4);
-                        else if constexpr (ES == 2) x = *(const uint16_t*)(X + off * 2);
+                        if constexpr (ES == 4) x = *(const MLK_GLOBAL uint32_t*)(X + off * 4);
+                        else if constexpr (ES == 2) x = *(const MLK_GLOBAL uint16_t*)(X + off * 2);
                         else x = X[off];
                         v[j][bit >> 5] |= x << (bit & 31);
                     }
@@ -401,7 +459,7 @@ struct Tile {
                                               const Cols* cols) {
         if constexpr (CONV == 2) {
             const NhwcCols& nc = cols[0];
-            const uint8_t* X = (const uint8_t*)g.B;
+            const gbytes X = (gbytes)g.B;
 #pragma unroll
             for (int i = 0; i < NB2; ++i) {
                 const int c = tid + i * NT;
@@ -413,7 +471,7 @@ struct Tile {
                 const int ih = nc.ih0[i] + kh, iw = nc.iw0[i] + kw;
                 if ((unsigned)ih >= (unsigned)g.ch || (unsigned)iw >= (unsigned)g.cw) continue;
                 const int64_t off = ((int64_t)nc.pbase[i] + ih * g.cw + iw) * g.cc + ch;
-                rb[i] = *(const u4_t*)(X + off * ES);
+                rb[i] = *(const MLK_GLOBAL u4_t*)(X + off * ES);
             }
         }
     }
@@ -472,7 +530,7 @@ struct Tile {
 
         acc_t acc[TM][TN];
         const int lr = lane & 15, lg = lane >> 4;
-        out_t* C = (out_t*)g.C;
+        MLK_GLOBAL out_t* C = (MLK_GLOBAL out_t*)g.C;
         // C += A B: start the accumulators from C (read here, next to the first
         // loads, rather than in a read-add-write epilogue).  e4m3 scales the
         // product and int8 must wrap modulo 2^32 exactly, so both keep C apart.
@@ -524,22 +582,24 @@ struct Tile {
             const uint8_t* sb = sa + BM * PITCH;
 #pragma unroll
             for (int ks = 0; ks < KB / KS; ++ks) {
-                u4_t af[TM][KV], bfr[TN][KV];
+                u4_t af[TM][KV];
                 const int off = ks * KS + lg * (KS / 4);
 #pragma unroll
                 for (int i = 0; i < TM; ++i)
 #pragma unroll
                     for (int v = 0; v < KV; ++v)
                         af[i][v] = *(const u4_t*)(sa + (wy * WTM + i * 16 + lr) * PITCH + off + v * 16);
+                // B fragments are used as they arrive (one column tile at a
+                // time), which keeps few of them live next to the staged loads
 #pragma unroll
-                for (int j = 0; j < TN; ++j)
+                for (int j = 0; j < TN; ++j) {
+                    u4_t bj[KV];
 #pragma unroll
                     for (int v = 0; v < KV; ++v)
-                        bfr[j][v] = *(const u4_t*)(sb + (wx * WTN + j * 16 + lr) * PITCH + off + v * 16);
+                        bj[v] = *(const u4_t*)(sb + (wx * WTN + j * 16 + lr) * PITCH + off + v * 16);
 #pragma unroll
-                for (int i = 0; i < TM; ++i)
-#pragma unroll
-                    for (int j = 0; j < TN; ++j) Mma<DT>::run(acc[i][j], af[i], bfr[j]);
+                    for (int i = 0; i < TM; ++i) Mma<DT>::run(acc[i][j], af[i], bj);
+                }
             }
             if (more) {
                 uint8_t* na = lds + ((it + 1) & 1) * STAGE;
@@ -573,14 +633,14 @@ struct Tile {
                 for (int r = 0; r < 4; ++r) {
                     const int64_t m = m0 + wy * WTM + i * 16 + lg * 4 + r;
                     if (m >= g.M) continue;
-                    out_t* p = C + m * rstride + cbase;
+                    MLK_GLOBAL out_t* p = C + m * rstride + cbase;
                     if constexpr (DT == DT_I8) {
                         const uint32_t v = (uint32_t)acc[i][j][r];
-                        if (g.atomic) atomicAdd((unsigned int*)p, v);
+                        if (g.atomic) __hip_atomic_fetch_add((MLK_GLOBAL uint32_t*)p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                         else *p = (int32_t)(g.accumulate ? (uint32_t)*p + v : v);
                     } else {
                         const float v = (DT == DT_F8) ? alpha * acc[i][j][r] : acc[i][j][r];
-                        if (g.atomic) atomicAdd(p, v);
+                        if (g.atomic) __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                         else if (c_in_acc || !g.accumulate) *p = v;
                         else *p = *p + v;
                     }

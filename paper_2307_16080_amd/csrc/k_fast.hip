@@ -1,4 +1,5 @@
-// Configurations of the direct-to-LDS kernel (bf16 and e4m3, large aligned problems).
+// Configurations of the direct-layout kernel (bf16 and e4m3): tile, wave
+// grid, LDS stages (2..4: direct-to-LDS ring; 1: loaded through registers).
 #include "kernels.hpp"
 namespace mlk {
 const KernelEntry* kernels_fast(int* n) {
@@ -9,11 +10,16 @@ const KernelEntry* kernels_fast(int* n) {
         MLK_ENTRY_FAST(DT_BF16, 256, 128, 2, 2, 3),
         MLK_ENTRY_FAST(DT_BF16, 128, 256, 2, 2, 3),
         MLK_ENTRY_FAST(DT_BF16, 128, 128, 2, 2, 4),
+        // operands loaded through registers: any shape and alignment, persistent batches
+        MLK_ENTRY_FASTREG(DT_BF16, 128, 128, 2, 2),
+        MLK_ENTRY_FASTREG(DT_BF16, 256, 128, 2, 2),
+        MLK_ENTRY_FASTREG(DT_BF16, 128, 256, 2, 2),
         MLK_ENTRY_FAST(DT_F8, 256, 256, 2, 4, 2),
         MLK_ENTRY_FAST(DT_F8, 256, 256, 2, 2, 2),
         MLK_ENTRY_FAST(DT_F8, 256, 128, 2, 2, 3),
         MLK_ENTRY_FAST(DT_F8, 128, 256, 2, 2, 3),
         MLK_ENTRY_FAST(DT_F8, 128, 128, 2, 2, 4),
+        MLK_ENTRY_FASTREG(DT_F8, 128, 128, 2, 2),
     };
     *n = (int)(sizeof(t) / sizeof(t[0]));
     return t;

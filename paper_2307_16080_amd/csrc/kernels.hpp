@@ -5,19 +5,24 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 #include "gemm_fast.hpp"
 #include "gemm_tile.hpp"
 
 namespace mlk {
 
-// One (GEMM, tile) work item of a persistent launch.
+// One (GEMM, tile) work item of a persistent launch.  kind 0: a tile of the
+// configured shape; kind 1: a 64 x 64 tile of the same kernel (used for GEMMs
+// too small to fill the configured tile).
 struct Task {
-    int32_t gemm, tm, tn, kz;
+    int32_t gemm, tm, tn, kind;
 };
 
 typedef hipError_t (*launch_fn)(const GemmArgs& g, int nblk, hipStream_t s);
 typedef hipError_t (*persist_fn)(const GemmArgs* gemms, const Task* tasks,
                                  const int32_t* bounds, int nblk, hipStream_t s);
+typedef int (*occupancy_fn)();  // workgroups of the persistent kernel resident per CU
 
 // A compiled tile configuration.
 struct KernelEntry {
@@ -31,6 +36,7 @@ struct KernelEntry {
     launch_fn launch;
     persist_fn persist;  // null where no persistent variant is built
     launch_fn launch_nhwc;  // conv entries: the channels-last variant (CONV = 2)
+    occupancy_fn occupancy; // with persist: resident workgroups per CU
 };
 
 template <int DT, int BM, int BN, int KB, int WM, int WN, int CONV>
@@ -42,19 +48,32 @@ __global__ __launch_bounds__(64 * WM * WN) void k_gemm(GemmArgs g) {
     TL::run(g, tm, tn, kz, lds);
 }
 
+// The small tile paired with a configured tile in one persistent kernel: a
+// 64 x 64 tile with the same number of waves when the configured tile has 4
+// waves, otherwise the configured tile itself (no second shape).
+template <int DT, int BM, int BN, int KB, int WM, int WN>
+struct SmallTile {
+    static constexpr bool pair = WM * WN == 4 && !(BM == 64 && BN == 64);
+    typedef typename std::conditional<pair, Tile<DT, 64, 64, 128, 2, 2, 0>,
+                                      Tile<DT, BM, BN, KB, WM, WN, 0>>::type type;
+};
+
 // Persistent variant: workgroup b runs tasks [bounds[b], bounds[b+1]) in order.
 template <int DT, int BM, int BN, int KB, int WM, int WN>
-__global__ __launch_bounds__(64 * WM * WN) void k_gemm_persist(const GemmArgs* gemms,
-                                                               const Task* tasks,
-                                                               const int32_t* bounds) {
+__global__ __launch_bounds__(64 * WM * WN) void k_gemm_persist(const GemmArgs* __restrict__ gemms,
+                                                               const Task* __restrict__ tasks,
+                                                               const int32_t* __restrict__ bounds) {
     typedef Tile<DT, BM, BN, KB, WM, WN, 0> TL;
-    __shared__ __attribute__((aligned(16))) uint8_t lds[TL::LDS_BYTES];
+    typedef typename SmallTile<DT, BM, BN, KB, WM, WN>::type TS;
+    constexpr int LDS = TL::LDS_BYTES > TS::LDS_BYTES ? TL::LDS_BYTES : TS::LDS_BYTES;
+    __shared__ __attribute__((aligned(16))) uint8_t lds[LDS];
     const int b = blockIdx.x;
     const int t0 = bounds[b], t1 = bounds[b + 1];
     for (int t = t0; t < t1; ++t) {
         const Task tk = tasks[t];
         const GemmArgs g = gemms[tk.gemm];
-        TL::run(g, tk.tm, tk.tn, tk.kz, lds);
+        if (SmallTile<DT, BM, BN, KB, WM, WN>::pair && tk.kind == 1) TS::run(g, tk.tm, tk.tn, 0, lds);
+        else TL::run(g, tk.tm, tk.tn, 0, lds);
         __syncthreads();
     }
 }
@@ -73,6 +92,48 @@ hipError_t launch_fast(const GemmArgs& g, int nblk, hipStream_t s) {
     hipLaunchKernelGGL((k_gemm_fast<DT, BM, BN, WM, WN, STAGES>), dim3(nblk), dim3(64 * WM * WN), 0,
                        s, g);
     return hipGetLastError();
+}
+
+// Persistent form of the register-loaded direct-layout kernel (one tile shape).
+template <int DT, int BM, int BN, int WM, int WN>
+__global__ __launch_bounds__(64 * WM * WN) void k_fast_persist(const GemmArgs* __restrict__ gemms,
+                                                               const Task* __restrict__ tasks,
+                                                               const int32_t* __restrict__ bounds) {
+    typedef FastGemm<DT, BM, BN, WM, WN, 1> TL;
+    __shared__ __attribute__((aligned(1024))) uint8_t lds[TL::LDS_BYTES];
+    const int b = blockIdx.x;
+    const int t0 = bounds[b], t1 = bounds[b + 1];
+    for (int t = t0; t < t1; ++t) {
+        const Task tk = tasks[t];
+        const GemmArgs g = gemms[tk.gemm];
+        TL::run(g, tk.tm, tk.tn, 0, lds);
+        __syncthreads();
+    }
+}
+
+template <int DT, int BM, int BN, int WM, int WN>
+hipError_t launch_fast_persist(const GemmArgs* gemms, const Task* tasks, const int32_t* bounds,
+                               int nblk, hipStream_t s) {
+    hipLaunchKernelGGL((k_fast_persist<DT, BM, BN, WM, WN>), dim3(nblk), dim3(64 * WM * WN), 0,
+                       s, gemms, tasks, bounds);
+    return hipGetLastError();
+}
+
+// Resident workgroups per CU of a persistent kernel (registers, LDS and waves
+// all counted by the runtime), at least 1.
+template <class K>
+int occupancy_of(K kernel, int threads) {
+    int n = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, kernel, threads, 0) != hipSuccess) n = 1;
+    return n > 0 ? n : 1;
+}
+template <int DT, int BM, int BN, int KB, int WM, int WN>
+int occupancy_persist() {
+    return occupancy_of(k_gemm_persist<DT, BM, BN, KB, WM, WN>, 64 * WM * WN);
+}
+template <int DT, int BM, int BN, int WM, int WN>
+int occupancy_fast_persist() {
+    return occupancy_of(k_fast_persist<DT, BM, BN, WM, WN>, 64 * WM * WN);
 }
 
 template <int DT, int BM, int BN, int KB, int WM, int WN, int CONV>
@@ -95,7 +156,7 @@ hipError_t launch_persist(const GemmArgs* gemms, const Task* tasks, const int32_
         DT, (CONV) ? 1 : 0, 0, BM, BN, (KB) / Traits<DT>::ES, WM, WN,                          \
             Tile<DT, BM, BN, KB, WM, WN, (CONV) ? 1 : 0>::LDS_BYTES, 64 * (WM) * (WN),         \
             &launch_gemm<DT, BM, BN, KB, WM, WN, (CONV) ? 1 : 0>, nullptr,                     \
-            (CONV) ? &launch_gemm<DT, BM, BN, KB, WM, WN, 2> : nullptr                        \
+            (CONV) ? &launch_gemm<DT, BM, BN, KB, WM, WN, 2> : nullptr, nullptr               \
     }
 
 #define MLK_ENTRY_P(DT, BM, BN, KB, WM, WN)                                                  \
@@ -103,14 +164,22 @@ hipError_t launch_persist(const GemmArgs* gemms, const Task* tasks, const int32_
         DT, 0, 0, BM, BN, (KB) / Traits<DT>::ES, WM, WN,                                     \
             Tile<DT, BM, BN, KB, WM, WN, 0>::LDS_BYTES, 64 * (WM) * (WN),                    \
             &launch_gemm<DT, BM, BN, KB, WM, WN, 0>, &launch_persist<DT, BM, BN, KB, WM, WN>,  \
-            nullptr                                                                          \
+            nullptr, &occupancy_persist<DT, BM, BN, KB, WM, WN>                              \
     }
 
 #define MLK_ENTRY_FAST(DT, BM, BN, WM, WN, STAGES)                                           \
     KernelEntry {                                                                            \
         DT, 0, STAGES, BM, BN, FastGemm<DT, BM, BN, WM, WN, STAGES>::BK, WM, WN,              \
             FastGemm<DT, BM, BN, WM, WN, STAGES>::LDS_BYTES, 64 * (WM) * (WN),               \
-            &launch_fast<DT, BM, BN, WM, WN, STAGES>, nullptr, nullptr                       \
+            &launch_fast<DT, BM, BN, WM, WN, STAGES>, nullptr, nullptr, nullptr              \
+    }
+
+#define MLK_ENTRY_FASTREG(DT, BM, BN, WM, WN)                                                \
+    KernelEntry {                                                                            \
+        DT, 0, 1, BM, BN, FastGemm<DT, BM, BN, WM, WN, 1>::BK, WM, WN,                       \
+            FastGemm<DT, BM, BN, WM, WN, 1>::LDS_BYTES, 64 * (WM) * (WN),                    \
+            &launch_fast<DT, BM, BN, WM, WN, 1>, &launch_fast_persist<DT, BM, BN, WM, WN>,   \
+            nullptr, &occupancy_fast_persist<DT, BM, BN, WM, WN>                             \
     }
 
 // Tables defined by the instantiation units (host functions: the tables hold

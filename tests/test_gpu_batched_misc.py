@@ -54,6 +54,27 @@ def test_batched_256_persistent_equals_per_gemm_and_oracle():
         assert normwise(pers[i], ref) <= 1e-5, (i, shapes[i])
 
 
+@pytest.mark.parametrize("tile", [(128, 128, 64, 2, 2), (256, 128, 64, 2, 2)])
+def test_batched_persistent_register_loaded_tiles(tile):
+    """The persistent launch of the register-loaded direct-layout kernel (any
+    alignment, K not a multiple of the stage depth) against per-GEMM launches
+    of the same configuration, bit for bit, and against the oracle."""
+    shapes = batched_shapes(64, seed=5)
+    probs, codes = _batch(shapes, seed=4)
+    cfg = mlk.TileConfig(*tile, 1, 1, 0, 1, 0)
+    mlk.batched_matmul(probs, cfg=cfg)
+    base = _outs(probs)
+    _zero(probs)
+    mlk.batched_matmul(probs, cfg=cfg, persistent=True, graph=True)
+    pers = _outs(probs)
+    for i, (a, b) in enumerate(zip(base, pers)):
+        assert np.array_equal(a, b), i
+    for i in range(0, 64, 9):
+        qa, qb = codes[i]
+        ref = oracle.matmul_f64(oracle.bf16_decode(qa), oracle.bf16_decode(qb), threads=oracle.default_threads())
+        assert normwise(pers[i], ref) <= 1e-5, (i, shapes[i])
+
+
 def test_batched_graph_replays_match_eager():
     shapes = batched_shapes(40, seed=3)
     probs, _ = _batch(shapes, seed=2, dist="small_int")

@@ -178,7 +178,7 @@ BF16_TILES = all_tiles(L.MLK_BF16, L.MLK_F32)
 ALIGNED = [(1, 8, 64), (100, 136, 192), (257, 520, 640), (300, 264, 128), (512, 512, 1024), (33, 1000, 64)]
 
 
-@pytest.mark.parametrize("cfg", [c for c in BF16_TILES if c.stages], ids=lambda c: f"{c.bm}x{c.bn}x{c.bk}_{c.wm}{c.wn}_s{c.stages}")
+@pytest.mark.parametrize("cfg", [c for c in BF16_TILES if c.stages >= 2], ids=lambda c: f"{c.bm}x{c.bn}x{c.bk}_{c.wm}{c.wn}_s{c.stages}")
 def test_bf16_direct_to_lds_tiles(cfg):
     for (M, N, K) in ALIGNED:
         say("bf16 direct", cfg, M, N, K)
@@ -205,7 +205,7 @@ def test_bf16_direct_to_lds_tiles(cfg):
                    torch.zeros(64, 64, device="cuda"), cfg=cfg)
 
 
-@pytest.mark.parametrize("cfg", [c for c in BF16_TILES if not c.stages], ids=lambda c: f"{c.bm}x{c.bn}x{c.bk}_{c.wm}{c.wn}_s{c.stages}")
+@pytest.mark.parametrize("cfg", [c for c in BF16_TILES if c.stages < 2], ids=lambda c: f"{c.bm}x{c.bn}x{c.bk}_{c.wm}{c.wn}_s{c.stages}")
 def test_bf16_every_tile_ragged(cfg):
     for (M, N, K) in RAGGED:
         say("bf16", cfg, M, N, K)
@@ -230,7 +230,7 @@ E4M3_TILES = all_tiles(L.MLK_F8E4M3, L.MLK_F32)
 ALIGNED8 = [(1, 16, 128), (100, 144, 256), (257, 528, 640), (300, 272, 128), (512, 512, 1024), (33, 1008, 128)]
 
 
-@pytest.mark.parametrize("cfg", [c for c in E4M3_TILES if c.stages], ids=lambda c: f"{c.bm}x{c.bn}x{c.bk}_{c.wm}{c.wn}_s{c.stages}")
+@pytest.mark.parametrize("cfg", [c for c in E4M3_TILES if c.stages >= 2], ids=lambda c: f"{c.bm}x{c.bn}x{c.bk}_{c.wm}{c.wn}_s{c.stages}")
 def test_e4m3_direct_to_lds_tiles(cfg):
     for (M, N, K) in ALIGNED8:
         say("e4m3 direct", cfg, M, N, K)
@@ -254,7 +254,36 @@ def test_e4m3_direct_to_lds_tiles(cfg):
         assert np.array_equal(host(C).astype(np.float64), oracle.matmul_f64(A, B))
 
 
-@pytest.mark.parametrize("cfg", [c for c in E4M3_TILES if not c.stages], ids=lambda c: f"{c.bm}x{c.bn}x{c.bk}_{c.wm}{c.wn}_s{c.stages}")
+def test_e4m3_direct_scaled_accumulate_extremes():
+    """C += alpha * (A_q B_q) when C / alpha is not representable: alpha outside
+    [2^-60, 2^60], or a C so large that C / alpha overflows in one wave's tile."""
+    cfg = next(c for c in E4M3_TILES if c.stages >= 2 and c.bm == 256 and c.bn == 256 and c.wm * c.wn == 8)
+    M, N, K = 300, 272, 256
+    A, B = matmul_inputs(M, N, K, seed=11, dist="normal")
+    qa, _ = oracle.quantize_e4m3(A)
+    qb, _ = oracle.quantize_e4m3(B)
+    prod = oracle.matmul_f64(oracle.e4m3_decode(qa), oracle.e4m3_decode(qb))
+    mag = oracle.matmul_f64(np.abs(oracle.e4m3_decode(qa)), np.abs(oracle.e4m3_decode(qb)))
+    for sa, sb, big_c in ((2.0 ** -35, 2.0 ** -36, 0.0), (2.0 ** -25, 2.0 ** -25, 3e38), (3.0, 0.25, 0.0)):
+        say("e4m3 extremes", sa, sb, big_c)
+        C0 = random_c(M, N, seed=3)
+        if big_c:
+            C0[5, 7] = big_c          # C / alpha overflows for this element's wave
+            C0[290, 260] = -big_c
+        ref = C0.astype(np.float64) + (sa * sb) * prod
+        C = dev(C0)
+        mlk.matmul(from_e4m3_codes(qa), from_e4m3_codes(qb), C, cfg=cfg,
+                   scale_a=dev(np.array([sa], np.float32)), scale_b=dev(np.array([sb], np.float32)))
+        got = host(C).astype(np.float64)
+        assert np.all(np.isfinite(got))
+        # componentwise: the accumulator starts from C / alpha and each 128-deep
+        # MFMA step rounds the running sum (measured up to 6 * 2^-24 * |C| for
+        # two steps), plus the MFMA's own error on the products
+        bound = 2.0 ** -20 * np.abs(C0) + 2.0 ** -14 * (sa * sb) * mag + 1e-45
+        assert np.all(np.abs(got - ref) <= bound), float(np.max(np.abs(got - ref) / bound))
+
+
+@pytest.mark.parametrize("cfg", [c for c in E4M3_TILES if c.stages < 2], ids=lambda c: f"{c.bm}x{c.bn}x{c.bk}_{c.wm}{c.wn}_s{c.stages}")
 def test_e4m3_every_tile_ragged(cfg):
     for (M, N, K) in RAGGED:
         say("e4m3", cfg, M, N, K)
