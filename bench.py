@@ -211,13 +211,16 @@ def main():
         pb = mlk.batched_problem(shapes, L.MLK_BF16, L.MLK_F32)
         bb, _, _ = mlk.tune(pb, mlk.MLK_TUNE_EXHAUSTIVE, reps=5, warmup=1)
         us_pg = time_us(lambda: mlk.batched_matmul(probs, cfg=bb, persistent=True, graph=True), 10)
-        us_loop = time_us(lambda: mlk.batched_matmul(probs, cfg=bb), 5)
-        us_g = time_us(lambda: mlk.batched_matmul(probs, cfg=bb, graph=True), 5)
+        # the same GEMMs as 256 separate launches (register-loaded tile: any alignment)
+        bl = mlk.TileConfig(128, 128, 64, 2, 2, 1, 1, 0, 1, 0)
+        us_loop = time_us(lambda: mlk.batched_matmul(probs, cfg=bl), 3)
+        us_g = time_us(lambda: mlk.batched_matmul(probs, cfg=bl, graph=True), 3)
         rows_out["batched_256_bf16"] = {"gflop": round(bflops / 1e9, 2), "tile": list(bb.as_tuple()),
                                         "persistent_graph_us": round(us_pg, 1),
+                                        "TFLOP/s": round(bflops / us_pg / 1e6, 1),
+                                        "per_gemm_tile": list(bl.as_tuple()),
                                         "per_gemm_launches_us": round(us_loop, 1),
-                                        "graph_of_launches_us": round(us_g, 1),
-                                        "TFLOP/s": round(bflops / us_pg / 1e6, 1)}
+                                        "graph_of_launches_us": round(us_g, 1)}
         # ResNet-18 conv stacks (batch 1 and 32, bf16): exhaustive tile search per
         # layer shape, the stack timed with each layer's best tile, and the learned
         # cost model judged leave-one-problem-out against those exhaustive tables.

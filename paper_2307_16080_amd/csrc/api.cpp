@@ -185,7 +185,8 @@ mlk_status check_config(const Shape& s, int op, const mlk_tile_config& c) {
     if (!e)
         return fail(MLK_ERR_CONFIG, "no compiled kernel for tile %dx%dx%d waves %dx%d stages %d (dtype %d%s)",
                     c.bm, c.bn, c.bk, c.wm, c.wn, c.stages, s.dt, s.conv ? ", conv" : "");
-    if (e->stages >= 2 && (op == MLK_OP_BATCHED || !fast_shape_ok(s, e->bk)))
+    // (a batch packs its operands for these tiles, so any batch shape is fine)
+    if (e->stages >= 2 && op != MLK_OP_BATCHED && !fast_shape_ok(s, e->bk))
         return fail(MLK_ERR_CONFIG, "direct-to-LDS tile needs K %% %d == 0 and 16-byte rows", e->bk);
     if (c.split_k < 1 || c.split_k > 64) return fail(MLK_ERR_CONFIG, "split_k must be in [1, 64]");
     const int64_t stages = cdiv(std::max<int64_t>(s.K, 1), c.bk);
@@ -208,7 +209,7 @@ std::vector<mlk_tile_config> enumerate_configs(const mlk_problem* p, const Shape
     for (const KernelEntry* e : registry()) {
         if (e->dt != s.dt || e->conv != s.conv) continue;
         if (batched && !e->persist) continue;
-        if (e->stages >= 2 && !fast_shape_ok(s, e->bk)) continue;
+        if (e->stages >= 2 && !batched && !fast_shape_ok(s, e->bk)) continue;
         // a tile at least twice the problem in a dimension only adds padding
         if (e->bm > 32 && e->bm >= 2 * s.M) continue;
         if (e->bn > 32 && e->bn >= 2 * s.N) continue;

@@ -4,7 +4,9 @@
 // (of the configured shape, or 64 x 64 for GEMMs too small for it), estimates
 // each tile's cost from its shape and K depth, and packs the tiles into one
 // bin per resident workgroup with the longest-processing-time-first rule
-// (largest tile to the currently least-loaded bin).  The device then runs one
+// (largest tile to the currently least-loaded bin).  With a direct-to-LDS
+// tile, one copy kernel first packs the operands into aligned, zero-padded
+// buffers (one launch for the whole batch).  The device then runs one
 // grid of exactly that many workgroups; workgroup b walks its own task range,
 // so there is no device-side queue, counter or reset.  Every tile runs the
 // same code as a plain launch of its tile shape with split_k = 1, so results
@@ -32,11 +34,18 @@ namespace mlk {
 namespace {
 
 struct Plan {
-    void* dev = nullptr;     // GemmArgs[count] | Task[ntasks] | int32 bounds[nblk + 1]
+    // GemmArgs[count] | Task[ntasks] | int32 bounds[nblk + 1] | PackJob[njobs] |
+    // int64 row_start[njobs + 1] | packed operands
+    void* dev = nullptr;
     GemmArgs* gemms = nullptr;
     Task* tasks = nullptr;
     int32_t* bounds = nullptr;
     int nblk = 0;
+    PackJob* jobs = nullptr;
+    int64_t* row_start = nullptr;
+    int njobs = 0;
+    int64_t pack_rows = 0;
+    int esize = 0;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     int device = 0;
@@ -91,10 +100,27 @@ int resident_blocks(const KernelEntry* e, int cus) {
     return cus * (e->occupancy ? e->occupancy() : 1);
 }
 
-// Build the LPT schedule on the host and upload it.
+int64_t round_up(int64_t a, int64_t b) { return cdiv(a, b) * b; }
+
+// Build the LPT schedule on the host and upload it.  For a direct-to-LDS tile
+// every operand that is not already in its form (16-byte rows, K a multiple of
+// the stage depth) gets a zero-padded copy: A as M x Kp, B as Kp x Np, with Kp
+// K rounded up to the stage depth and Np N rounded up to 16 bytes.  The padded
+// K columns of A and rows of B are zero, so they add nothing.
 mlk_status build_plan(int dt, int64_t count, const mlk_gemm_desc* d, const KernelEntry* e,
                       const mlk_tile_config& c, int accumulate, Plan* plan) {
     std::vector<GemmArgs> gemms((size_t)count);
+    const int es = dt == DT_F32 ? 4 : dt == DT_BF16 ? 2 : 1;
+    const bool pack = e->stages >= 2;
+    std::vector<PackJob> jobs;
+    std::vector<int64_t> dst_off;  // byte offset of each job's block in the packed area
+    int64_t packed_bytes = 0;
+    struct Fix {
+        int64_t gemm;
+        int which;  // 0: A, 1: B
+        int64_t job;
+    };
+    std::vector<Fix> fixes;
     struct T {
         double cost;
         Task t;
@@ -110,6 +136,33 @@ mlk_status build_plan(int dt, int64_t count, const mlk_gemm_desc* d, const Kerne
     for (int64_t i = 0; i < count; ++i) {
         gemms[i] = args_for(dt, d[i], c, accumulate);
         if (d[i].M == 0 || d[i].N == 0) continue;
+        if (pack && d[i].K > 0) {
+            GemmArgs& g = gemms[i];
+            const int64_t Kp = round_up(d[i].K, e->bk), Np = round_up(d[i].N, 16 / es);
+            const bool kfit = d[i].K % e->bk == 0;
+            if (!(kfit && g.vec_a)) {
+                jobs.push_back(PackJob{d[i].A, nullptr, d[i].lda, Kp, (int32_t)d[i].M, (int32_t)d[i].K,
+                                       (int32_t)d[i].M, 0});
+                dst_off.push_back(packed_bytes);
+                packed_bytes += round_up(d[i].M * Kp * es, 256);
+                fixes.push_back(Fix{i, 0, (int64_t)jobs.size() - 1});
+                g.lda = Kp;
+            }
+            if (!(kfit && g.vec_b)) {
+                jobs.push_back(PackJob{d[i].B, nullptr, d[i].ldb, Np, (int32_t)d[i].K, (int32_t)d[i].N,
+                                       (int32_t)Kp, 0});
+                dst_off.push_back(packed_bytes);
+                packed_bytes += round_up(Kp * Np * es, 256);
+                fixes.push_back(Fix{i, 1, (int64_t)jobs.size() - 1});
+                g.ldb = Np;
+            }
+            g.K = Kp;
+            g.vec_a = g.vec_b = 1;
+            if (((d[i].M - 1) * g.lda + Kp) * es >= ((int64_t)1 << 31) ||
+                ((Kp - 1) * g.ldb + d[i].N) * es >= ((int64_t)1 << 31))
+                return fail(MLK_ERR_CONFIG, "batched: operand of desc %lld exceeds 2 GiB for a direct-to-LDS tile",
+                            (long long)i);
+        }
         const int64_t K = std::max<int64_t>(d[i].K, 1);
         const int64_t tb = cdiv(d[i].M, c.bm) * cdiv(d[i].N, c.bn);
         const double cost_big = (double)(cdiv(K, c.bk) + 2) * c.bm * c.bn * c.bk;
@@ -145,27 +198,47 @@ mlk_status build_plan(int dt, int64_t count, const mlk_gemm_desc* d, const Kerne
     }
     bounds[nblk] = (int32_t)tasks.size();
 
+    // pack job table: destination rows counted over all jobs
+    std::vector<int64_t> row_start(jobs.size() + 1, 0);
+    for (size_t j = 0; j < jobs.size(); ++j) row_start[j + 1] = row_start[j] + jobs[j].rows_dst;
+
     const size_t gb = sizeof(GemmArgs) * gemms.size();
     const size_t tb = sizeof(Task) * std::max<size_t>(tasks.size(), 1);
     const size_t bb = sizeof(int32_t) * bounds.size();
-    const size_t total = gb + tb + bb;
+    const size_t jb = sizeof(PackJob) * jobs.size();
+    const size_t rb = sizeof(int64_t) * row_start.size();
+    const size_t head = (size_t)round_up((int64_t)(gb + tb + bb + jb + rb), 256);
+    const size_t total = head + (size_t)packed_bytes;
     void* dev = nullptr;
     hipError_t err = hipMalloc(&dev, total);
     if (err != hipSuccess) return hip_fail(err, "batched plan allocation");
-    std::vector<char> host(total, 0);
+    char* base = (char*)dev;
+    for (size_t j = 0; j < jobs.size(); ++j) jobs[j].dst = base + head + dst_off[j];
+    for (const Fix& f : fixes) {
+        if (f.which == 0) gemms[f.gemm].A = jobs[f.job].dst;
+        else gemms[f.gemm].B = jobs[f.job].dst;
+    }
+    std::vector<char> host(head, 0);
     memcpy(host.data(), gemms.data(), gb);
     if (!tasks.empty()) memcpy(host.data() + gb, tasks.data(), sizeof(Task) * tasks.size());
     memcpy(host.data() + gb + tb, bounds.data(), bb);
-    err = hipMemcpy(dev, host.data(), total, hipMemcpyHostToDevice);
+    if (!jobs.empty()) memcpy(host.data() + gb + tb + bb, jobs.data(), jb);
+    memcpy(host.data() + gb + tb + bb + jb, row_start.data(), rb);
+    err = hipMemcpy(dev, host.data(), head, hipMemcpyHostToDevice);
     if (err != hipSuccess) {
         (void)hipFree(dev);
         return hip_fail(err, "batched plan upload");
     }
     plan->dev = dev;
-    plan->gemms = (GemmArgs*)dev;
-    plan->tasks = (Task*)((char*)dev + gb);
-    plan->bounds = (int32_t*)((char*)dev + gb + tb);
+    plan->gemms = (GemmArgs*)base;
+    plan->tasks = (Task*)(base + gb);
+    plan->bounds = (int32_t*)(base + gb + tb);
     plan->nblk = nblk;
+    plan->jobs = (PackJob*)(base + gb + tb + bb);
+    plan->row_start = (int64_t*)(base + gb + tb + bb + jb);
+    plan->njobs = (int)jobs.size();
+    plan->pack_rows = row_start.back();
+    plan->esize = es;
     return MLK_OK;
 }
 
@@ -174,7 +247,9 @@ mlk_status launch_batch(int dt, int64_t count, const mlk_gemm_desc* d, const Ker
                         hipStream_t st) {
     if (flags & MLK_BATCH_PERSISTENT) {
         if (plan->nblk == 0) return MLK_OK;
-        hipError_t err = e->persist(plan->gemms, plan->tasks, plan->bounds, plan->nblk, st);
+        hipError_t err = launch_pack(plan->jobs, plan->row_start, plan->njobs, plan->pack_rows, plan->esize, st);
+        if (err != hipSuccess) return hip_fail(err, "operand packing");
+        err = e->persist(plan->gemms, plan->tasks, plan->bounds, plan->nblk, st);
         if (err != hipSuccess) return hip_fail(err, "persistent launch");
         return MLK_OK;
     }
@@ -251,6 +326,8 @@ mlk_status mlk_batched_matmul(mlk_dtype in, mlk_dtype out, int64_t count,
     if (!e) return fail(MLK_ERR_CONFIG, "batched: no kernel for configuration");
     if ((flags & MLK_BATCH_PERSISTENT) && !e->persist)
         return fail(MLK_ERR_CONFIG, "batched: tile %dx%dx%d has no persistent variant", c.bm, c.bn, c.bk);
+    if (e->stages >= 2 && !(flags & MLK_BATCH_PERSISTENT))
+        return fail(MLK_ERR_CONFIG, "batched: direct-to-LDS tiles (stages >= 2) run only in the persistent mode");
     hipStream_t user = (hipStream_t)stream;
     int dev = 0;
     hipError_t herr = hipGetDevice(&dev);

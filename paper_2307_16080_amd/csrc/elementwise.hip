@@ -192,6 +192,35 @@ __global__ __launch_bounds__(kThreads) void k_fill_random(uint8_t* p, int64_t n,
     }
 }
 
+// ------------------------------------------------------------------ operand packing
+
+// One wave per destination row (grid-stride over the rows of all jobs): the
+// row's first `cols` elements come from the source row, the rest of the pitch
+// (and every row past `rows`) is zero.  Lanes take consecutive elements, so
+// each wave-wide load and store is one contiguous run.
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_pack(const PackJob* __restrict__ jobs,
+                                                   const int64_t* __restrict__ row_start, int njobs,
+                                                   int64_t total_rows) {
+    const int lane = threadIdx.x & 63;
+    const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+    for (int64_t R = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6; R < total_rows; R += nwaves) {
+        // the job holding row R: the last j with row_start[j] <= R
+        int lo = 0, hi = njobs - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (row_start[mid] <= R) lo = mid;
+            else hi = mid - 1;
+        }
+        const PackJob jb = jobs[lo];
+        const int64_t r = R - row_start[lo];
+        const T* src = (const T*)jb.src + r * jb.ld_src;
+        T* dst = (T*)jb.dst + r * jb.ld_dst;
+        const int64_t valid = r < jb.rows ? jb.cols : 0;
+        for (int64_t c = lane; c < jb.ld_dst; c += 64) dst[c] = c < valid ? src[c] : (T)0;
+    }
+}
+
 // ------------------------------------------------------------------ layout transform
 
 // out[b][c][r] = in[b][r][c] for a batch of rows x cols matrices, through a
@@ -329,6 +358,19 @@ hipError_t launch_transpose_batched(const void* in, void* out, int64_t batch, in
     else
         hipLaunchKernelGGL(k_transpose<uint8_t>, grid, dim3(256), 0, s, (const uint8_t*)in,
                            (uint8_t*)out, rows, cols);
+    return hipGetLastError();
+}
+
+hipError_t launch_pack(const PackJob* jobs, const int64_t* row_start, int njobs, int64_t total_rows,
+                       int esize, hipStream_t s) {
+    if (njobs <= 0 || total_rows <= 0) return hipSuccess;
+    const int grid = grid_for(total_rows, kThreads / 64);
+    if (esize == 4)
+        hipLaunchKernelGGL(k_pack<uint32_t>, dim3(grid), dim3(kThreads), 0, s, jobs, row_start, njobs, total_rows);
+    else if (esize == 2)
+        hipLaunchKernelGGL(k_pack<uint16_t>, dim3(grid), dim3(kThreads), 0, s, jobs, row_start, njobs, total_rows);
+    else
+        hipLaunchKernelGGL(k_pack<uint8_t>, dim3(grid), dim3(kThreads), 0, s, jobs, row_start, njobs, total_rows);
     return hipGetLastError();
 }
 

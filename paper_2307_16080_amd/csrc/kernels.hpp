@@ -19,6 +19,16 @@ struct Task {
     int32_t gemm, tm, tn, kind;
 };
 
+// One operand copied into a zero-padded, 16-byte-pitched buffer: rows x cols
+// elements from src (pitch ld_src) to dst (pitch ld_dst elements, rows_dst
+// rows); every other element of the dst block is written as zero.
+struct PackJob {
+    const void* src;
+    void* dst;
+    int64_t ld_src, ld_dst;
+    int32_t rows, cols, rows_dst, pad_;
+};
+
 typedef hipError_t (*launch_fn)(const GemmArgs& g, int nblk, hipStream_t s);
 typedef hipError_t (*persist_fn)(const GemmArgs* gemms, const Task* tasks,
                                  const int32_t* bounds, int nblk, hipStream_t s);
@@ -94,12 +104,14 @@ hipError_t launch_fast(const GemmArgs& g, int nblk, hipStream_t s) {
     return hipGetLastError();
 }
 
-// Persistent form of the register-loaded direct-layout kernel (one tile shape).
-template <int DT, int BM, int BN, int WM, int WN>
+// Persistent form of the direct-layout kernel (one tile shape).  The
+// direct-to-LDS form (STAGES >= 2) runs batches whose operands were packed
+// into aligned, zero-padded buffers first.
+template <int DT, int BM, int BN, int WM, int WN, int STAGES>
 __global__ __launch_bounds__(64 * WM * WN) void k_fast_persist(const GemmArgs* __restrict__ gemms,
                                                                const Task* __restrict__ tasks,
                                                                const int32_t* __restrict__ bounds) {
-    typedef FastGemm<DT, BM, BN, WM, WN, 1> TL;
+    typedef FastGemm<DT, BM, BN, WM, WN, STAGES> TL;
     __shared__ __attribute__((aligned(1024))) uint8_t lds[TL::LDS_BYTES];
     const int b = blockIdx.x;
     const int t0 = bounds[b], t1 = bounds[b + 1];
@@ -111,10 +123,10 @@ __global__ __launch_bounds__(64 * WM * WN) void k_fast_persist(const GemmArgs* _
     }
 }
 
-template <int DT, int BM, int BN, int WM, int WN>
+template <int DT, int BM, int BN, int WM, int WN, int STAGES>
 hipError_t launch_fast_persist(const GemmArgs* gemms, const Task* tasks, const int32_t* bounds,
                                int nblk, hipStream_t s) {
-    hipLaunchKernelGGL((k_fast_persist<DT, BM, BN, WM, WN>), dim3(nblk), dim3(64 * WM * WN), 0,
+    hipLaunchKernelGGL((k_fast_persist<DT, BM, BN, WM, WN, STAGES>), dim3(nblk), dim3(64 * WM * WN), 0,
                        s, gemms, tasks, bounds);
     return hipGetLastError();
 }
@@ -131,9 +143,9 @@ template <int DT, int BM, int BN, int KB, int WM, int WN>
 int occupancy_persist() {
     return occupancy_of(k_gemm_persist<DT, BM, BN, KB, WM, WN>, 64 * WM * WN);
 }
-template <int DT, int BM, int BN, int WM, int WN>
+template <int DT, int BM, int BN, int WM, int WN, int STAGES>
 int occupancy_fast_persist() {
-    return occupancy_of(k_fast_persist<DT, BM, BN, WM, WN>, 64 * WM * WN);
+    return occupancy_of(k_fast_persist<DT, BM, BN, WM, WN, STAGES>, 64 * WM * WN);
 }
 
 template <int DT, int BM, int BN, int KB, int WM, int WN, int CONV>
@@ -171,15 +183,9 @@ hipError_t launch_persist(const GemmArgs* gemms, const Task* tasks, const int32_
     KernelEntry {                                                                            \
         DT, 0, STAGES, BM, BN, FastGemm<DT, BM, BN, WM, WN, STAGES>::BK, WM, WN,              \
             FastGemm<DT, BM, BN, WM, WN, STAGES>::LDS_BYTES, 64 * (WM) * (WN),               \
-            &launch_fast<DT, BM, BN, WM, WN, STAGES>, nullptr, nullptr, nullptr              \
-    }
-
-#define MLK_ENTRY_FASTREG(DT, BM, BN, WM, WN)                                                \
-    KernelEntry {                                                                            \
-        DT, 0, 1, BM, BN, FastGemm<DT, BM, BN, WM, WN, 1>::BK, WM, WN,                       \
-            FastGemm<DT, BM, BN, WM, WN, 1>::LDS_BYTES, 64 * (WM) * (WN),                    \
-            &launch_fast<DT, BM, BN, WM, WN, 1>, &launch_fast_persist<DT, BM, BN, WM, WN>,   \
-            nullptr, &occupancy_fast_persist<DT, BM, BN, WM, WN>                             \
+            &launch_fast<DT, BM, BN, WM, WN, STAGES>,                                        \
+            &launch_fast_persist<DT, BM, BN, WM, WN, STAGES>, nullptr,                       \
+            &occupancy_fast_persist<DT, BM, BN, WM, WN, STAGES>                              \
     }
 
 // Tables defined by the instantiation units (host functions: the tables hold
@@ -200,6 +206,10 @@ hipError_t launch_quant_e4m3(const float* x, int64_t n, uint8_t* q, float* scale
 hipError_t launch_err_stats(int c_is_int, int64_t n, const void* c, const double* r,
                             const double* bound, double* out, hipStream_t s);
 hipError_t launch_fill_random(void* p, int64_t n, int dt, uint64_t seed, hipStream_t s);
+// copy operands into zero-padded buffers; row_start[j] = first destination row
+// of job j in a running count over all jobs (njobs + 1 entries, device memory)
+hipError_t launch_pack(const PackJob* jobs, const int64_t* row_start, int njobs, int64_t total_rows,
+                       int esize, hipStream_t s);
 // batch of [rows x cols] matrices -> [cols x rows] (NCHW -> NHWC, FCHW -> FHWC)
 hipError_t launch_transpose_batched(const void* in, void* out, int64_t batch, int64_t rows,
                                     int64_t cols, int esize, hipStream_t s);

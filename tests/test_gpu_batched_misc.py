@@ -75,6 +75,34 @@ def test_batched_persistent_register_loaded_tiles(tile):
         assert normwise(pers[i], ref) <= 1e-5, (i, shapes[i])
 
 
+@pytest.mark.parametrize("tile", [(256, 256, 64, 2, 4, 2), (128, 128, 64, 2, 2, 4), (256, 128, 64, 2, 2, 3)])
+def test_batched_persistent_direct_tiles_with_packing(tile):
+    """Direct-to-LDS tiles on a batch with odd K and N: the operands are packed
+    into zero-padded copies inside the launch (and its graph); the result must
+    equal per-GEMM launches of the register-loaded kernel bit for bit (same
+    MFMA sequence over the same 32-deep k chunks) on every graph replay."""
+    shapes = batched_shapes(48, seed=6) + [(64, 128, 128), (1, 1, 1), (300, 8, 64)]
+    probs, codes = _batch(shapes, seed=7)
+    ref_cfg = mlk.TileConfig(128, 128, 64, 2, 2, 1, 1, 0, 1, 0)
+    mlk.batched_matmul(probs, cfg=ref_cfg)
+    base = _outs(probs)
+    cfg = mlk.TileConfig(*tile[:5], 1, 1, 0, tile[5], 0)
+    with pytest.raises(mlk.MlkError, match="CONFIG"):
+        mlk.batched_matmul(probs, cfg=cfg)                  # per-GEMM launches: not for these tiles
+    for rep in range(3):
+        _zero(probs)
+        junk = torch.randn(1000, device="cuda").sum()       # eager work between replays
+        mlk.batched_matmul(probs, cfg=cfg, persistent=True, graph=rep > 0)
+        got = _outs(probs)
+        for i, (a, b) in enumerate(zip(base, got)):
+            assert np.array_equal(a, b), (rep, i, shapes[i])
+        del junk
+    for i in (0, 17, 48, 49, 50):
+        qa, qb = codes[i]
+        ref = oracle.matmul_f64(oracle.bf16_decode(qa), oracle.bf16_decode(qb), threads=oracle.default_threads())
+        assert normwise(got[i], ref) <= 1e-5, (i, shapes[i])
+
+
 def test_batched_graph_replays_match_eager():
     shapes = batched_shapes(40, seed=3)
     probs, _ = _batch(shapes, seed=2, dist="small_int")
