@@ -39,10 +39,14 @@ def parse():
     return ap.parse_args()
 
 
+# the sources that define the headline GEMM kernel (its code and its launch)
+KERNEL_SOURCES = ["gemm_fast.hpp", "gemm_tile.hpp", "kernels.hpp", "k_fast.hip"]
+
+
 def source_hash():
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2307_16080_amd", "csrc")
-    for name in sorted(os.listdir(csrc)):
+    for name in KERNEL_SOURCES:
         with open(os.path.join(csrc, name), "rb") as f:
             h.update(name.encode() + f.read())
     return h.hexdigest()[:16]
@@ -125,11 +129,13 @@ def main():
     traffic = None
     tpath = os.path.join(ROOT, "profiles", "bf16_gemm_4096_traffic.txt")
     if os.path.exists(tpath):
+        # one JSON line per profiled tile configuration
         with open(tpath) as f:
             lines = [l for l in f.read().splitlines() if l.strip() and not l.startswith("#")]
-        t = json.loads(lines[-1]) if lines else {}
-        if t.get("source_hash") == source_hash() and t.get("config") == list(best.as_tuple()):
-            traffic = round(t.get("bytes_per_launch"))
+        for line in lines:
+            t = json.loads(line)
+            if t.get("source_hash") == source_hash() and t.get("config") == list(best.as_tuple()):
+                traffic = round(t.get("bytes_per_launch"))
 
     result = {
         "metric": "GEMM/conv TFLOP/s and % MFMA roofline; tuned vs plain fp32 at stated rel err",

@@ -172,12 +172,13 @@ mlk_status shape_of_problem(const mlk_problem* p, Shape* s) {
 
 static int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
-// Shapes the direct-to-LDS kernels accept: whole K stages, packed rows that
-// are multiples of 16 bytes, operands below 2 GiB (32-bit buffer offsets).
+// Shapes the direct-to-LDS kernels take: after packing (K rounded up to the
+// stage depth, rows to 16 bytes) each operand stays below 2 GiB (32-bit buffer
+// offsets).
 static bool fast_shape_ok(const Shape& s, int bk) {
     const int64_t es = esize_in(s.dt);
-    return s.K > 0 && s.K % bk == 0 && (s.K * es) % 16 == 0 && (s.N * es) % 16 == 0 &&
-           s.M * s.K * es < ((int64_t)1 << 31) && s.K * s.N * es < ((int64_t)1 << 31);
+    const int64_t Kp = cdiv(std::max<int64_t>(s.K, 1), bk) * bk, Np = cdiv(s.N, 16 / es) * (16 / es);
+    return s.M * Kp * es < ((int64_t)1 << 31) && Kp * Np * es < ((int64_t)1 << 31);
 }
 
 mlk_status check_config(const Shape& s, int op, const mlk_tile_config& c) {
@@ -185,9 +186,9 @@ mlk_status check_config(const Shape& s, int op, const mlk_tile_config& c) {
     if (!e)
         return fail(MLK_ERR_CONFIG, "no compiled kernel for tile %dx%dx%d waves %dx%d stages %d (dtype %d%s)",
                     c.bm, c.bn, c.bk, c.wm, c.wn, c.stages, s.dt, s.conv ? ", conv" : "");
-    // (a batch packs its operands for these tiles, so any batch shape is fine)
+    // (operands that do not fit these tiles are packed, so any shape is fine)
     if (e->stages >= 2 && op != MLK_OP_BATCHED && !fast_shape_ok(s, e->bk))
-        return fail(MLK_ERR_CONFIG, "direct-to-LDS tile needs K %% %d == 0 and 16-byte rows", e->bk);
+        return fail(MLK_ERR_CONFIG, "direct-to-LDS tile: an operand exceeds 2 GiB");
     if (c.split_k < 1 || c.split_k > 64) return fail(MLK_ERR_CONFIG, "split_k must be in [1, 64]");
     const int64_t stages = cdiv(std::max<int64_t>(s.K, 1), c.bk);
     if (c.split_k > 1 && c.split_k > stages)
@@ -257,6 +258,16 @@ mlk_tile_config heuristic_config(const Shape& s, int op) {
     }
     const KernelEntry* e = best ? best : smallest;
     mlk_tile_config c{e->bm, e->bn, e->bk, e->wm, e->wn, 1, 1, 0, 0, 0};
+    // large bf16 / e4m3 matmuls: the 8-wave direct-to-LDS tile, grouped raster
+    if (op == MLK_OP_MATMUL && (s.dt == DT_BF16 || s.dt == DT_F8) &&
+        cdiv(s.M, 256) * cdiv(s.N, 256) >= cus && s.K >= 256) {
+        for (const KernelEntry* f : registry())
+            if (f->dt == s.dt && !f->conv && f->stages == 2 && f->bm == 256 && f->bn == 256 &&
+                f->wm == 2 && f->wn == 4 && fast_shape_ok(s, f->bk)) {
+                const int64_t tiles = cdiv(s.M, 256) * cdiv(s.N, 256);
+                return mlk_tile_config{256, 256, f->bk, 2, 4, 1, 8, tiles % 8 == 0 ? 1 : 0, 2, 0};
+            }
+    }
     // channels-last pays a transpose of the input: worth it for large images
     if (s.conv && e->launch_nhwc && s.conv_c % (16 / esize_in(s.dt)) == 0 && s.N >= 16384) c.layout = 1;
     if (!best && op != MLK_OP_BATCHED) {
@@ -378,10 +389,43 @@ mlk_status launch_dense(const Shape& s, const void* A, int64_t lda, const void* 
     g.scale_b = sb;
     g.vec_a = ((uintptr_t)A % 16 == 0) && ((lda * es) % 16 == 0);
     g.vec_b = ((uintptr_t)B % 16 == 0) && ((ldb * es) % 16 == 0);
-    if (e->stages >= 2 && !(g.vec_a && g.vec_b && ((s.M - 1) * lda + s.K) * es < ((int64_t)1 << 31) &&
-                       ((s.K - 1) * ldb + s.N) * es < ((int64_t)1 << 31)))
-        return fail(MLK_ERR_CONFIG, "direct-to-LDS tile needs 16-byte aligned operands and row pitches");
-    return run_gemm(e, g, s, C, s.M, s.N, ldc, st);
+    if (e->stages < 2 || s.K == 0) return run_gemm(e, g, s, C, s.M, s.N, ldc, st);
+    // Direct-to-LDS tile: an operand without 16-byte rows, or with K not a
+    // multiple of the stage depth, is first copied into a zero-padded buffer
+    // (A as M x Kp, B as Kp x Np; Kp = K rounded up to the stage depth, Np = N
+    // rounded up to 16 bytes) in a stream-ordered workspace.
+    const bool kfit = s.K % e->bk == 0;
+    const bool pa = !(g.vec_a && kfit), pb = !(g.vec_b && kfit);
+    const int64_t Kp = cdiv(s.K, e->bk) * e->bk, Np = cdiv(s.N, 16 / es) * (16 / es);
+    const int64_t lda2 = pa ? Kp : lda, ldb2 = pb ? Np : ldb;
+    if (((s.M - 1) * lda2 + Kp) * es >= ((int64_t)1 << 31) || ((Kp - 1) * ldb2 + s.N) * es >= ((int64_t)1 << 31))
+        return fail(MLK_ERR_CONFIG, "direct-to-LDS tile: an operand exceeds 2 GiB");
+    if (!pa && !pb) return run_gemm(e, g, s, C, s.M, s.N, ldc, st);
+    const int64_t abytes = pa ? cdiv(s.M * Kp * es, 256) * 256 : 0;
+    const int64_t bbytes = pb ? Kp * Np * es : 0;
+    void* ws = nullptr;
+    hipError_t err = hipMallocAsync(&ws, (size_t)(abytes + bbytes), st);
+    if (err != hipSuccess) return hip_fail(err, "packing workspace");
+    PackJob jobs[2];
+    int nj = 0;
+    if (pa) {
+        jobs[nj++] = PackJob{A, ws, lda, Kp, (int32_t)s.M, (int32_t)s.K, (int32_t)s.M, 0};
+        g.A = ws;
+    }
+    if (pb) {
+        void* wb = (char*)ws + abytes;
+        jobs[nj++] = PackJob{B, wb, ldb, Np, (int32_t)s.K, (int32_t)s.N, (int32_t)Kp, 0};
+        g.B = wb;
+    }
+    g.lda = lda2;
+    g.ldb = ldb2;
+    g.K = Kp;
+    g.vec_a = g.vec_b = 1;
+    err = launch_pack_pair(jobs, nj, es, st);
+    mlk_status r = err == hipSuccess ? run_gemm(e, g, s, C, s.M, s.N, ldc, st) : hip_fail(err, "operand packing");
+    const hipError_t ferr = hipFreeAsync(ws, st);
+    if (r == MLK_OK && ferr != hipSuccess) return hip_fail(ferr, "packing workspace release");
+    return r;
 }
 
 mlk_status launch_conv(const Shape& s, int64_t n, int64_t c, int64_t h, int64_t w, int64_t f,
@@ -519,13 +563,6 @@ mlk_status mlk_matmul(mlk_dtype in, mlk_dtype out, int64_t M, int64_t N, int64_t
     st = resolve(p, s, cfg, &c);
     if (st != MLK_OK) return st;
     if (M == 0 || N == 0) return MLK_OK;
-    if (c.stages >= 2 && cfg_is_zero(cfg)) {
-        // a tuned direct-to-LDS choice needs aligned operands; otherwise use the heuristic
-        const int es = esize_in(s.dt);
-        const bool aligned = (uintptr_t)A % 16 == 0 && (uintptr_t)B % 16 == 0 &&
-                             (lda * es) % 16 == 0 && (ldb * es) % 16 == 0;
-        if (!aligned) c = heuristic_config(s, p.op);
-    }
     return launch_dense(s, A, lda, B, ldb, C, ldc, scale_a, scale_b, c, (hipStream_t)stream);
 }
 

@@ -35,16 +35,16 @@ namespace {
 
 struct Plan {
     // GemmArgs[count] | Task[ntasks] | int32 bounds[nblk + 1] | PackJob[njobs] |
-    // int64 row_start[njobs + 1] | packed operands
+    // int64 seg_start[njobs + 1] | packed operands
     void* dev = nullptr;
     GemmArgs* gemms = nullptr;
     Task* tasks = nullptr;
     int32_t* bounds = nullptr;
     int nblk = 0;
     PackJob* jobs = nullptr;
-    int64_t* row_start = nullptr;
+    int64_t* seg_start = nullptr;
     int njobs = 0;
-    int64_t pack_rows = 0;
+    int64_t pack_segs = 0;
     int esize = 0;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
@@ -178,17 +178,59 @@ mlk_status build_plan(int dt, int64_t count, const mlk_gemm_desc* d, const Kerne
     const int cus = device_cus();
     int nblk = resident_blocks(e, cus);
     if ((int64_t)nblk > (int64_t)all.size()) nblk = std::max<int>(1, (int)all.size());
-    std::stable_sort(all.begin(), all.end(), [](const T& a, const T& b) { return a.cost > b.cost; });
-    // min-heap of (load, bin)
-    typedef std::pair<double, int> LB;
-    std::priority_queue<LB, std::vector<LB>, std::greater<LB>> heap;
-    for (int b = 0; b < nblk; ++b) heap.push(LB(0.0, b));
     std::vector<std::vector<Task>> bins((size_t)nblk);
-    for (const T& x : all) {
-        LB top = heap.top();
-        heap.pop();
-        bins[top.second].push_back(x.t);
-        heap.push(LB(top.first + x.cost, top.second));
+    // Two-level longest-processing-time-first.  Workgroup b runs on XCD b % 8
+    // (workgroups are dealt to the eight XCDs in turn), and each XCD has its
+    // own L2: so whole GEMMs -- or, for a GEMM heavier than a quarter of an
+    // XCD's share, bands of consecutive tile rows, which share A's row panels
+    // -- are first dealt to the XCDs, largest first to the least-loaded one;
+    // then each XCD's tiles go to its own workgroups, largest first to the
+    // least-loaded one.
+    const int nx = nblk >= 8 && nblk % 8 == 0 ? 8 : 1;
+    double work = 0.0;
+    for (const T& x : all) work += x.cost;
+    const double cap = work / (4.0 * nx);
+    struct Unit {
+        double cost;
+        std::vector<int64_t> tiles;  // indices into `all`
+    };
+    std::vector<Unit> units;
+    for (size_t a = 0; a < all.size();) {
+        // `all` holds each GEMM's tiles together, row by row
+        size_t z = a;
+        double gc = 0.0;
+        while (z < all.size() && all[z].t.gemm == all[a].t.gemm) gc += all[z++].cost;
+        const int32_t rows = all[z - 1].t.tm + 1;
+        const int32_t band = gc <= cap ? rows : std::max<int32_t>(1, (int32_t)std::floor(rows * cap / gc));
+        for (size_t k = a; k < z; ++k) {
+            if (k == a || all[k].t.tm / band != all[k - 1].t.tm / band) units.push_back(Unit{0.0, {}});
+            units.back().cost += all[k].cost;
+            units.back().tiles.push_back((int64_t)k);
+        }
+        a = z;
+    }
+    std::stable_sort(units.begin(), units.end(), [](const Unit& u, const Unit& v) { return u.cost > v.cost; });
+    typedef std::pair<double, int> LB;  // (load, index), smallest load on top
+    std::priority_queue<LB, std::vector<LB>, std::greater<LB>> xh;
+    for (int x = 0; x < nx; ++x) xh.push(LB(0.0, x));
+    std::vector<std::vector<int64_t>> per_x((size_t)nx);
+    for (const Unit& u : units) {
+        LB top = xh.top();
+        xh.pop();
+        per_x[top.second].insert(per_x[top.second].end(), u.tiles.begin(), u.tiles.end());
+        xh.push(LB(top.first + u.cost, top.second));
+    }
+    for (int x = 0; x < nx; ++x) {
+        std::vector<int64_t>& tl = per_x[x];
+        std::stable_sort(tl.begin(), tl.end(), [&](int64_t u, int64_t v) { return all[u].cost > all[v].cost; });
+        std::priority_queue<LB, std::vector<LB>, std::greater<LB>> heap;
+        for (int b = x; b < nblk; b += nx) heap.push(LB(0.0, b));
+        for (int64_t k : tl) {
+            LB top = heap.top();
+            heap.pop();
+            bins[top.second].push_back(all[k].t);
+            heap.push(LB(top.first + all[k].cost, top.second));
+        }
     }
     std::vector<Task> tasks;
     std::vector<int32_t> bounds((size_t)nblk + 1, 0);
@@ -198,15 +240,15 @@ mlk_status build_plan(int dt, int64_t count, const mlk_gemm_desc* d, const Kerne
     }
     bounds[nblk] = (int32_t)tasks.size();
 
-    // pack job table: destination rows counted over all jobs
-    std::vector<int64_t> row_start(jobs.size() + 1, 0);
-    for (size_t j = 0; j < jobs.size(); ++j) row_start[j + 1] = row_start[j] + jobs[j].rows_dst;
+    // pack job table: destination segments counted over all jobs
+    std::vector<int64_t> seg_start(jobs.size() + 1, 0);
+    for (size_t j = 0; j < jobs.size(); ++j) seg_start[j + 1] = seg_start[j] + pack_segments(jobs[j]);
 
     const size_t gb = sizeof(GemmArgs) * gemms.size();
     const size_t tb = sizeof(Task) * std::max<size_t>(tasks.size(), 1);
     const size_t bb = sizeof(int32_t) * bounds.size();
     const size_t jb = sizeof(PackJob) * jobs.size();
-    const size_t rb = sizeof(int64_t) * row_start.size();
+    const size_t rb = sizeof(int64_t) * seg_start.size();
     const size_t head = (size_t)round_up((int64_t)(gb + tb + bb + jb + rb), 256);
     const size_t total = head + (size_t)packed_bytes;
     void* dev = nullptr;
@@ -223,7 +265,7 @@ mlk_status build_plan(int dt, int64_t count, const mlk_gemm_desc* d, const Kerne
     if (!tasks.empty()) memcpy(host.data() + gb, tasks.data(), sizeof(Task) * tasks.size());
     memcpy(host.data() + gb + tb, bounds.data(), bb);
     if (!jobs.empty()) memcpy(host.data() + gb + tb + bb, jobs.data(), jb);
-    memcpy(host.data() + gb + tb + bb + jb, row_start.data(), rb);
+    memcpy(host.data() + gb + tb + bb + jb, seg_start.data(), rb);
     err = hipMemcpy(dev, host.data(), head, hipMemcpyHostToDevice);
     if (err != hipSuccess) {
         (void)hipFree(dev);
@@ -235,9 +277,9 @@ mlk_status build_plan(int dt, int64_t count, const mlk_gemm_desc* d, const Kerne
     plan->bounds = (int32_t*)(base + gb + tb);
     plan->nblk = nblk;
     plan->jobs = (PackJob*)(base + gb + tb + bb);
-    plan->row_start = (int64_t*)(base + gb + tb + bb + jb);
+    plan->seg_start = (int64_t*)(base + gb + tb + bb + jb);
     plan->njobs = (int)jobs.size();
-    plan->pack_rows = row_start.back();
+    plan->pack_segs = seg_start.back();
     plan->esize = es;
     return MLK_OK;
 }
@@ -247,7 +289,7 @@ mlk_status launch_batch(int dt, int64_t count, const mlk_gemm_desc* d, const Ker
                         hipStream_t st) {
     if (flags & MLK_BATCH_PERSISTENT) {
         if (plan->nblk == 0) return MLK_OK;
-        hipError_t err = launch_pack(plan->jobs, plan->row_start, plan->njobs, plan->pack_rows, plan->esize, st);
+        hipError_t err = launch_pack(plan->jobs, plan->seg_start, plan->njobs, plan->pack_segs, plan->esize, st);
         if (err != hipSuccess) return hip_fail(err, "operand packing");
         err = e->persist(plan->gemms, plan->tasks, plan->bounds, plan->nblk, st);
         if (err != hipSuccess) return hip_fail(err, "persistent launch");
@@ -326,8 +368,6 @@ mlk_status mlk_batched_matmul(mlk_dtype in, mlk_dtype out, int64_t count,
     if (!e) return fail(MLK_ERR_CONFIG, "batched: no kernel for configuration");
     if ((flags & MLK_BATCH_PERSISTENT) && !e->persist)
         return fail(MLK_ERR_CONFIG, "batched: tile %dx%dx%d has no persistent variant", c.bm, c.bn, c.bk);
-    if (e->stages >= 2 && !(flags & MLK_BATCH_PERSISTENT))
-        return fail(MLK_ERR_CONFIG, "batched: direct-to-LDS tiles (stages >= 2) run only in the persistent mode");
     hipStream_t user = (hipStream_t)stream;
     int dev = 0;
     hipError_t herr = hipGetDevice(&dev);

@@ -8,6 +8,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <cstring>
+
 #include "kernels.hpp"
 
 namespace mlk {
@@ -194,30 +196,88 @@ __global__ __launch_bounds__(kThreads) void k_fill_random(uint8_t* p, int64_t n,
 
 // ------------------------------------------------------------------ operand packing
 
-// One wave per destination row (grid-stride over the rows of all jobs): the
-// row's first `cols` elements come from the source row, the rest of the pitch
-// (and every row past `rows`) is zero.  Lanes take consecutive elements, so
-// each wave-wide load and store is one contiguous run.
+// Every job's destination block (rows_dst x ld_dst elements, contiguous) is
+// cut into segments of kPackSeg consecutive elements, across row ends, so a
+// narrow operand moves as much per wave as a wide one; seg_start[j] counts the
+// segments of the jobs before j.  One wave per segment: lane l moves elements
+// l, l + 64, l + 128, ... of the segment, so each wave-wide load (within a
+// row) and store is one contiguous run, and all of the segment's loads are
+// issued before its stores.  Elements outside the copied block are zero.
+template <typename T>
+__device__ inline void pack_segment(const PackJob& jb, int64_t q, int lane) {
+    constexpr int U = kPackSeg / 64;
+    const uint32_t n = (uint32_t)jb.rows_dst * (uint32_t)jb.ld_dst;  // < 2^31 (2 GiB operands)
+    const uint32_t ld = (uint32_t)jb.ld_dst;
+    const uint32_t e0 = (uint32_t)q * kPackSeg + lane;
+    // (row, column) of this lane's first element; each later element is 64
+    // further on: 64 = q64 * ld + r64
+    uint32_t r = e0 / ld, c = e0 - r * ld;
+    const uint32_t q64 = 64 / ld, r64 = 64 - q64 * ld;
+    const T* src = (const T*)jb.src;
+    T* dst = (T*)jb.dst;
+    T v[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        const uint32_t e = e0 + u * 64;
+        v[u] = (e < n && r < (uint32_t)jb.rows && c < (uint32_t)jb.cols) ? src[(int64_t)r * jb.ld_src + c] : (T)0;
+        c += r64;
+        r += q64;
+        if (c >= ld) {
+            c -= ld;
+            ++r;
+        }
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        const uint32_t e = e0 + u * 64;
+        if (e < n) dst[e] = v[u];
+    }
+}
+
 template <typename T>
 __global__ __launch_bounds__(kThreads) void k_pack(const PackJob* __restrict__ jobs,
-                                                   const int64_t* __restrict__ row_start, int njobs,
-                                                   int64_t total_rows) {
+                                                   const int64_t* __restrict__ seg_start, int njobs,
+                                                   int64_t total) {
+    // wave w takes the contiguous segments [q0, q1): one search for its first
+    // job, then the job index only moves forward
     const int lane = threadIdx.x & 63;
     const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
-    for (int64_t R = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6; R < total_rows; R += nwaves) {
-        // the job holding row R: the last j with row_start[j] <= R
-        int lo = 0, hi = njobs - 1;
-        while (lo < hi) {
-            const int mid = (lo + hi + 1) >> 1;
-            if (row_start[mid] <= R) lo = mid;
-            else hi = mid - 1;
+    const int64_t w = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int64_t per = (total + nwaves - 1) / nwaves;
+    const int64_t q0 = w * per, q1 = min(total, q0 + per);
+    if (q0 >= q1) return;
+    int j = 0, hi = njobs - 1;  // the last j with seg_start[j] <= q0
+    while (j < hi) {
+        const int mid = (j + hi + 1) >> 1;
+        if (seg_start[mid] <= q0) j = mid;
+        else hi = mid - 1;
+    }
+    int64_t s0 = seg_start[j], s1 = seg_start[j + 1];
+    PackJob jb = jobs[j];
+    for (int64_t q = q0; q < q1; ++q) {
+        while (q >= s1) {
+            ++j;
+            s0 = s1;
+            s1 = seg_start[j + 1];
+            jb = jobs[j];
         }
-        const PackJob jb = jobs[lo];
-        const int64_t r = R - row_start[lo];
-        const T* src = (const T*)jb.src + r * jb.ld_src;
-        T* dst = (T*)jb.dst + r * jb.ld_dst;
-        const int64_t valid = r < jb.rows ? jb.cols : 0;
-        for (int64_t c = lane; c < jb.ld_dst; c += 64) dst[c] = c < valid ? src[c] : (T)0;
+        pack_segment<T>(jb, q - s0, lane);
+    }
+}
+
+// the same for at most two jobs passed by value (one GEMM's A and B)
+struct PackPair {
+    PackJob job[2];
+    int64_t segs0, total;  // segments of job 0, of both
+};
+
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_pack_pair(PackPair pp) {
+    const int lane = threadIdx.x & 63;
+    const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+    for (int64_t q = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6; q < pp.total; q += nwaves) {
+        if (q < pp.segs0) pack_segment<T>(pp.job[0], q, lane);
+        else pack_segment<T>(pp.job[1], q - pp.segs0, lane);
     }
 }
 
@@ -361,16 +421,32 @@ hipError_t launch_transpose_batched(const void* in, void* out, int64_t batch, in
     return hipGetLastError();
 }
 
-hipError_t launch_pack(const PackJob* jobs, const int64_t* row_start, int njobs, int64_t total_rows,
+hipError_t launch_pack(const PackJob* jobs, const int64_t* seg_start, int njobs, int64_t total_segs,
                        int esize, hipStream_t s) {
-    if (njobs <= 0 || total_rows <= 0) return hipSuccess;
-    const int grid = grid_for(total_rows, kThreads / 64);
+    if (njobs <= 0 || total_segs <= 0) return hipSuccess;
+    const int grid = grid_for(total_segs, kThreads / 64);
     if (esize == 4)
-        hipLaunchKernelGGL(k_pack<uint32_t>, dim3(grid), dim3(kThreads), 0, s, jobs, row_start, njobs, total_rows);
+        hipLaunchKernelGGL(k_pack<uint32_t>, dim3(grid), dim3(kThreads), 0, s, jobs, seg_start, njobs, total_segs);
     else if (esize == 2)
-        hipLaunchKernelGGL(k_pack<uint16_t>, dim3(grid), dim3(kThreads), 0, s, jobs, row_start, njobs, total_rows);
+        hipLaunchKernelGGL(k_pack<uint16_t>, dim3(grid), dim3(kThreads), 0, s, jobs, seg_start, njobs, total_segs);
     else
-        hipLaunchKernelGGL(k_pack<uint8_t>, dim3(grid), dim3(kThreads), 0, s, jobs, row_start, njobs, total_rows);
+        hipLaunchKernelGGL(k_pack<uint8_t>, dim3(grid), dim3(kThreads), 0, s, jobs, seg_start, njobs, total_segs);
+    return hipGetLastError();
+}
+
+hipError_t launch_pack_pair(const PackJob* jobs, int njobs, int esize, hipStream_t s) {
+    if (njobs <= 0) return hipSuccess;
+    PackPair pp;
+    memset(&pp, 0, sizeof pp);
+    pp.job[0] = jobs[0];
+    if (njobs > 1) pp.job[1] = jobs[1];
+    pp.segs0 = pack_segments(jobs[0]);
+    pp.total = pp.segs0 + (njobs > 1 ? pack_segments(jobs[1]) : 0);
+    if (pp.total <= 0) return hipSuccess;
+    const int grid = grid_for(pp.total, kThreads / 64);
+    if (esize == 4) hipLaunchKernelGGL(k_pack_pair<uint32_t>, dim3(grid), dim3(kThreads), 0, s, pp);
+    else if (esize == 2) hipLaunchKernelGGL(k_pack_pair<uint16_t>, dim3(grid), dim3(kThreads), 0, s, pp);
+    else hipLaunchKernelGGL(k_pack_pair<uint8_t>, dim3(grid), dim3(kThreads), 0, s, pp);
     return hipGetLastError();
 }
 

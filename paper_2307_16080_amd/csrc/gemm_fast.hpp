@@ -31,13 +31,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
-#include <type_traits>
-
 #include "gemm_tile.hpp"
 
-#ifndef MLK_PP_DEFAULT
-#define MLK_PP_DEFAULT 0
-#endif
 
 namespace mlk {
 
@@ -98,11 +93,6 @@ struct FastGemm {
     static constexpr int B_STAGE = BK * B_ROW;
     static constexpr int STAGE = A_STAGE + B_STAGE;
     static constexpr bool REG = STAGES == 1;      // register-loaded form
-    // Ping-pong schedule (8 waves, two direct-to-LDS buffers): waves 0-3 and
-    // 4-7 (one of each on every SIMD) alternate, one phase apart, between
-    // reading a stage's fragments from LDS and running its MFMAs, so that each
-    // SIMD always has one wave issuing MFMAs while the other waits on LDS.
-    static constexpr bool PP = MLK_PP_DEFAULT && DT == DT_BF16 && !REG && STAGES == 2 && WM * WN == 8;
     static constexpr int NBUF = REG ? 2 : STAGES;  // LDS stage buffers
     static constexpr int EPV = 16 / ES;            // elements per 16-byte chunk
     static constexpr int LDS_BYTES = NBUF * STAGE;
@@ -159,86 +149,6 @@ struct FastGemm {
             const int slab = wave + i * NW;
             dma_load16(__builtin_amdgcn_readfirstlane(base + A_STAGE + slab * 1024), voff_b[i], rb, sb);
         }
-    }
-
-    // ---- one stage's MFMA operands, read from LDS ahead of their MFMAs
-    typedef typename std::conditional<DT == DT_BF16, u4_t, i8_t>::type afrag_t;
-    typedef typename std::conditional<DT == DT_BF16, bf8_t, i8_t>::type bfrag_t;
-    struct Frags {
-        afrag_t a[BK / KSTEP][TM];
-        bfrag_t b[BK / KSTEP][TN];
-    };
-
-    __device__ static inline void read_frags(const uint8_t* sa, const uint8_t* sb, int wy, int wx,
-                                             int lr, int lg, Frags& f) {
-        typedef __attribute__((address_space(3))) bf4_t* tp;
-        typedef __attribute__((address_space(3))) i2_t* t8p;
-#pragma unroll
-        for (int ks = 0; ks < BK / KSTEP; ++ks) {
-            if constexpr (DT == DT_BF16) {
-#pragma unroll
-                for (int i = 0; i < TM; ++i) {
-                    const int r = wy * WTM + i * 16 + lr;
-                    f.a[ks][i] = *(const u4_t*)(sa + r * A_ROW + (((ks * 4 + lg) ^ fa(r)) * 16));
-                }
-#pragma unroll
-                for (int j = 0; j < TN; ++j) {
-                    const int nb = wx * WTN + j * 16 + 4 * (lr & 3);
-                    bf4_t h[2];
-#pragma unroll
-                    for (int half = 0; half < 2; ++half) {
-                        const int k = ks * 32 + lg * 8 + half * 4 + (lr >> 2);
-                        const uint8_t* p = sb + k * B_ROW + ((nb >> 3) ^ fb(k)) * 16 + (nb & 7) * 2;
-                        h[half] = __builtin_amdgcn_ds_read_tr16_b64_v4bf16((tp)(p));
-                    }
-                    f.b[ks][j] = bf8_t{h[0][0], h[0][1], h[0][2], h[0][3], h[1][0], h[1][1], h[1][2], h[1][3]};
-                }
-            } else {
-#pragma unroll
-                for (int i = 0; i < TM; ++i) {
-                    const int r = wy * WTM + i * 16 + lr;
-                    const u4_t lo = *(const u4_t*)(sa + r * A_ROW + ((2 * lg) ^ fa(r)) * 16);
-                    const u4_t hi = *(const u4_t*)(sa + r * A_ROW + ((2 * lg + 1) ^ fa(r)) * 16);
-                    f.a[ks][i] = i8_t{(int)lo[0], (int)lo[1], (int)lo[2], (int)lo[3],
-                                      (int)hi[0], (int)hi[1], (int)hi[2], (int)hi[3]};
-                }
-#pragma unroll
-                for (int j = 0; j < TN; ++j) {
-                    const int nb = wx * WTN + j * 16 + 8 * (lr & 1);
-                    i2_t q[4];
-#pragma unroll
-                    for (int qq = 0; qq < 4; ++qq) {
-                        const int k = lg * 32 + qq * 8 + (lr >> 1);
-                        const uint8_t* p = sb + k * B_ROW + ((nb >> 4) ^ fb(k)) * 16 + (nb & 15);
-                        q[qq] = __builtin_amdgcn_ds_read_tr8_b64_v2i32((t8p)(p));
-                    }
-                    f.b[ks][j] = i8_t{q[0][0], q[0][1], q[1][0], q[1][1], q[2][0], q[2][1], q[3][0], q[3][1]};
-                }
-            }
-        }
-    }
-
-    __device__ static inline void mma_frags(const Frags& f, f4_t (&acc)[TM][TN]) {
-#pragma unroll
-        for (int ks = 0; ks < BK / KSTEP; ++ks)
-#pragma unroll
-            for (int j = 0; j < TN; ++j)
-#pragma unroll
-                for (int i = 0; i < TM; ++i) {
-                    if constexpr (DT == DT_BF16)
-                        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
-                            __builtin_bit_cast(bf8_t, f.a[ks][i]), f.b[ks][j], acc[i][j], 0, 0, 0);
-                    else
-                        acc[i][j] = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(
-                            f.a[ks][i], f.b[ks][j], acc[i][j], 0, 0, 0, 127, 0, 127);
-                }
-    }
-
-    // barrier between ping-pong phases; nothing is scheduled across it
-    __device__ static inline void phase_barrier() {
-        __builtin_amdgcn_sched_barrier(0);
-        asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
-        __builtin_amdgcn_sched_barrier(0);
     }
 
     // ---- register-loaded form: per-thread chunk state, fixed for a tile
@@ -431,33 +341,7 @@ struct FastGemm {
 
         typedef __attribute__((address_space(3))) bf4_t* tp;
         typedef __attribute__((address_space(3))) i2_t* t8p;
-        if constexpr (PP) {
-            // Phase 2s: stage s+1 is issued into the buffer that held stage s-1;
-            // waves 0-3 read stage s, waves 4-7 multiply stage s-1.  Phase 2s+1:
-            // waves 0-3 multiply stage s, waves 4-7 read it; every wave then
-            // waits for its share of stage s+1 before the barrier.
-            const bool first = wave < 4;
-            Frags f;
-            wait_vmcnt<0>();
-            phase_barrier();
-            for (int s = 0; s <= nk; ++s) {
-                if (s + 1 < nk)
-                    issue_stage(ra, rb, voff_a, voff_b, (s_beg + s + 1) * BK, g.ldb,
-                                lds + ((s + 1) & 1) * STAGE, wave);
-                if (first) {
-                    if (s < nk) read_frags(lds + (s & 1) * STAGE, lds + (s & 1) * STAGE + A_STAGE, wy, wx, lr, lg, f);
-                } else {
-                    if (s >= 1) mma_frags(f, acc);
-                }
-                if (s == nk) break;
-                phase_barrier();
-                if (first) mma_frags(f, acc);
-                else read_frags(lds + (s & 1) * STAGE, lds + (s & 1) * STAGE + A_STAGE, wy, wx, lr, lg, f);
-                wait_vmcnt<0>();
-                phase_barrier();
-            }
-        }
-        for (int it = 0; it < (PP ? 0 : nk); ++it) {
+        for (int it = 0; it < nk; ++it) {
             if constexpr (!REG) {
                 // stage `it` has landed once at most (stages issued after it) loads remain
                 wait_stage<(STAGES >= 2 ? STAGES - 2 : 0)>(min(STAGES - 2, nk - 1 - it));

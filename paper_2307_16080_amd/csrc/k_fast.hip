@@ -10,6 +10,8 @@ const KernelEntry* kernels_fast(int* n) {
         MLK_ENTRY_FAST(DT_BF16, 256, 128, 2, 2, 3),
         MLK_ENTRY_FAST(DT_BF16, 128, 256, 2, 2, 3),
         MLK_ENTRY_FAST(DT_BF16, 128, 128, 2, 2, 4),
+        MLK_ENTRY_FAST(DT_BF16, 128, 128, 2, 2, 2),  // 64 KB of LDS: two workgroups per CU
+        MLK_ENTRY_FAST(DT_BF16, 64, 128, 2, 2, 2),   // 48 KB: three per CU
         // operands loaded through registers: any shape and alignment, persistent batches
         MLK_ENTRY_FAST(DT_BF16, 128, 128, 2, 2, 1),
         MLK_ENTRY_FAST(DT_BF16, 256, 128, 2, 2, 1),
@@ -19,6 +21,7 @@ const KernelEntry* kernels_fast(int* n) {
         MLK_ENTRY_FAST(DT_F8, 256, 128, 2, 2, 3),
         MLK_ENTRY_FAST(DT_F8, 128, 256, 2, 2, 3),
         MLK_ENTRY_FAST(DT_F8, 128, 128, 2, 2, 4),
+        MLK_ENTRY_FAST(DT_F8, 128, 128, 2, 2, 2),
         MLK_ENTRY_FAST(DT_F8, 128, 128, 2, 2, 1),
     };
     *n = (int)(sizeof(t) / sizeof(t[0]));

@@ -206,10 +206,17 @@ hipError_t launch_quant_e4m3(const float* x, int64_t n, uint8_t* q, float* scale
 hipError_t launch_err_stats(int c_is_int, int64_t n, const void* c, const double* r,
                             const double* bound, double* out, hipStream_t s);
 hipError_t launch_fill_random(void* p, int64_t n, int dt, uint64_t seed, hipStream_t s);
-// copy operands into zero-padded buffers; row_start[j] = first destination row
-// of job j in a running count over all jobs (njobs + 1 entries, device memory)
-hipError_t launch_pack(const PackJob* jobs, const int64_t* row_start, int njobs, int64_t total_rows,
+// copy operands into zero-padded buffers, one wave per segment of kPackSeg
+// consecutive destination elements; seg_start[j] = first segment of job j in
+// a running count over all jobs (njobs + 1 entries, device memory)
+constexpr int kPackSeg = 1024;
+inline int64_t pack_segments(const PackJob& j) {
+    return ((int64_t)j.rows_dst * j.ld_dst + kPackSeg - 1) / kPackSeg;
+}
+hipError_t launch_pack(const PackJob* jobs, const int64_t* seg_start, int njobs, int64_t total_segs,
                        int esize, hipStream_t s);
+// the same for one or two jobs given in host memory (passed by value)
+hipError_t launch_pack_pair(const PackJob* jobs, int njobs, int esize, hipStream_t s);
 // batch of [rows x cols] matrices -> [cols x rows] (NCHW -> NHWC, FCHW -> FHWC)
 hipError_t launch_transpose_batched(const void* in, void* out, int64_t batch, int64_t rows,
                                     int64_t cols, int esize, hipStream_t s);

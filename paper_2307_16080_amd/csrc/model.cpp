@@ -39,7 +39,7 @@ namespace mlk {
 
 namespace {
 
-constexpr int kFeatures = 27;
+constexpr int kFeatures = 29;
 
 int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
 double lg(double v) { return std::log2(std::max(v, 1.0)); }
@@ -89,6 +89,10 @@ void model_features(const Shape& s, const mlk_tile_config& c, int cus, float* f)
     // work on the critical path: rounds of tiles times the work of one tile
     f[i++] = (float)lg(std::ceil(waves) * (double)c.bm * c.bn * c.bk * stages);
     f[i++] = (float)c.layout;
+    // kernel family: register-staged (0), register-loaded direct layout (1),
+    // direct-to-LDS ring (its depth)
+    f[i++] = c.stages == 1 ? 1.f : 0.f;
+    f[i++] = c.stages >= 2 ? (float)c.stages : 0.f;
 }
 
 static mlk_status upload_params(mlk_cost_model* m) {

@@ -198,11 +198,28 @@ def test_bf16_direct_to_lds_tiles(cfg):
             mlk.matmul(from_bf16_codes(oracle.bf16_encode(A)), from_bf16_codes(oracle.bf16_encode(B)), C,
                        cfg=cfg, accumulate=acc)
             assert np.array_equal(host(C).astype(np.float64), oracle.matmul_f64(A, B)), acc
-    # unaligned operands are refused for an explicit direct-to-LDS configuration
-    A = torch.zeros(64, 65, dtype=torch.bfloat16, device="cuda")
-    with pytest.raises(mlk.MlkError, match="CONFIG"):
-        mlk.matmul(A[:, 1:], torch.zeros(64, 64, dtype=torch.bfloat16, device="cuda"),
-                   torch.zeros(64, 64, device="cuda"), cfg=cfg)
+    # ragged shapes and unaligned operands: packed into zero-padded copies first
+    for (M, N, K) in RAGGED:
+        say("bf16 direct ragged", cfg, M, N, K)
+        A, B = matmul_inputs(M, N, K, seed=M + 5 * N + K, dist="normal")
+        qa, qb = oracle.bf16_encode(A), oracle.bf16_encode(B)
+        C0 = random_c(M, N, seed=K + 1)
+        ref = oracle.matmul_f64(oracle.bf16_decode(qa), oracle.bf16_decode(qb), C0)
+        big, C = _with_guard(C0, torch.float32)
+        mlk.matmul(from_bf16_codes(qa), from_bf16_codes(qb), C, cfg=cfg)
+        assert normwise(host(C), ref) <= 1e-5
+        _check_guard(big, M, N)
+        A, B = matmul_inputs(M, N, K, seed=3, dist="small_int")
+        C = torch.zeros(M, N, device="cuda")
+        mlk.matmul(from_bf16_codes(oracle.bf16_encode(A)), from_bf16_codes(oracle.bf16_encode(B)), C, cfg=cfg)
+        assert np.array_equal(host(C).astype(np.float64), oracle.matmul_f64(A, B))
+    # an operand view whose rows start 2 bytes past 16-byte alignment
+    A, B = matmul_inputs(64, 72, 64, seed=9, dist="small_int")
+    wide = torch.zeros(64, 65, dtype=torch.bfloat16, device="cuda")
+    wide[:, 1:] = from_bf16_codes(oracle.bf16_encode(A))
+    C = torch.zeros(64, 72, device="cuda")
+    mlk.matmul(wide[:, 1:], from_bf16_codes(oracle.bf16_encode(B)), C, cfg=cfg)
+    assert np.array_equal(host(C).astype(np.float64), oracle.matmul_f64(A, B))
 
 
 @pytest.mark.parametrize("cfg", [c for c in BF16_TILES if c.stages < 2], ids=lambda c: f"{c.bm}x{c.bn}x{c.bk}_{c.wm}{c.wn}_s{c.stages}")
@@ -252,6 +269,15 @@ def test_e4m3_direct_to_lds_tiles(cfg):
         mlk.matmul(from_e4m3_codes(oracle.e4m3_encode(A, 1.0)), from_e4m3_codes(oracle.e4m3_encode(B, 1.0)),
                    C, cfg=cfg)
         assert np.array_equal(host(C).astype(np.float64), oracle.matmul_f64(A, B))
+    # ragged shapes (packed into zero-padded copies first)
+    for (M, N, K) in RAGGED:
+        say("e4m3 direct ragged", cfg, M, N, K)
+        A, B = matmul_inputs(M, N, K, seed=6, dist="small_int")
+        big, C = _with_guard(np.zeros((M, N), np.float32), torch.float32)
+        mlk.matmul(from_e4m3_codes(oracle.e4m3_encode(A, 1.0)), from_e4m3_codes(oracle.e4m3_encode(B, 1.0)),
+                   C, cfg=cfg)
+        assert np.array_equal(host(C).astype(np.float64), oracle.matmul_f64(A, B))
+        _check_guard(big, M, N)
 
 
 def test_e4m3_direct_scaled_accumulate_extremes():
