@@ -1,8 +1,14 @@
-"""Summaries of rocprofv3 output for the benchmark's kernels.
+"""Summaries of rocprofv3 output for the benchmark's kernels, and a driver
+for the batched workload to run under the profiler.
 
     python -m paper_2307_16080_amd.profiling stats  <kernel_stats.csv>
     python -m paper_2307_16080_amd.profiling traffic <fetch_counters.csv> <write_counters.csv>
             <kernel-name-substring> <copy-bytes> <out.json> [source_hash] [tile]
+    python -m paper_2307_16080_amd.profiling batched <tile> <launches>
+
+`batched` runs the 256 uneven bf16 GEMMs of the benchmark (seeded shapes and
+inputs) as persistent launches, replayed from a hipGraph, with the given tile
+(ten comma-separated configuration fields).
 
 `traffic` turns the FETCH_SIZE / WRITE_SIZE counters (KiB per dispatch) of
 the kernel into bytes per launch, scaled by what the same counters read for
@@ -58,8 +64,32 @@ def traffic(fetch_csv, write_csv, kernel_sub, copy_bytes, copy_sub="copy"):
             "scale": {"fetch_bytes_per_unit": fetch_scale, "write_bytes_per_unit": write_scale}}
 
 
+def run_batched(tile, launches):
+    import os
+
+    import torch
+
+    sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+    import paper_2307_16080_amd as mlk
+    from workloads import batched_inputs, batched_shapes
+
+    shapes = batched_shapes(256, seed=0)
+    probs = []
+    for (a, b), (m, n, k) in zip(batched_inputs(shapes, seed=1), shapes):
+        qa, _ = mlk.quantize(torch.from_numpy(a).cuda(), "bf16")
+        qb, _ = mlk.quantize(torch.from_numpy(b).cuda(), "bf16")
+        probs.append((qa, qb, torch.zeros(m, n, device="cuda")))
+    cfg = mlk.TileConfig(*[int(v) for v in tile.split(",")])
+    for _ in range(launches):
+        mlk.batched_matmul(probs, cfg=cfg, persistent=True, graph=True)
+    torch.cuda.synchronize()
+    print(f"batched: {launches} persistent launches of {len(shapes)} GEMMs, tile {tile}", flush=True)
+
+
 if __name__ == "__main__":
-    if sys.argv[1] == "stats":
+    if sys.argv[1] == "batched":
+        run_batched(sys.argv[2], int(sys.argv[3]))
+    elif sys.argv[1] == "stats":
         print(stats(sys.argv[2]))
     elif sys.argv[1] == "traffic":
         t = traffic(sys.argv[2], sys.argv[3], sys.argv[4], int(sys.argv[5]))
