@@ -197,6 +197,8 @@ mlk_status check_config(const Shape& s, int op, const mlk_tile_config& c) {
     if (c.xcd_remap != 0 && c.xcd_remap != 1) return fail(MLK_ERR_CONFIG, "xcd_remap must be 0 or 1");
     if (c.layout != 0 && !(s.conv && c.layout == 1))
         return fail(MLK_ERR_CONFIG, "layout must be 0, or 1 for conv2d");
+    if (s.conv && !e->launch && c.layout != 1)
+        return fail(MLK_ERR_CONFIG, "this conv tile runs only the channels-last layout (layout 1)");
     if (c.layout == 1 && (!e->launch_nhwc || s.conv_c % (16 / esize_in(s.dt)) != 0))
         return fail(MLK_ERR_CONFIG, "channels-last layout needs C a multiple of %d", 16 / esize_in(s.dt));
     const int64_t tiles = cdiv(s.M, c.bm) * cdiv(s.N, c.bn) * c.split_k;
@@ -228,6 +230,7 @@ std::vector<mlk_tile_config> enumerate_configs(const mlk_problem* p, const Shape
                     for (int lay = 0; lay < 2; ++lay) {
                         if (lay == 1 && !(s.conv && e->launch_nhwc && s.conv_c % (16 / esize_in(s.dt)) == 0))
                             continue;
+                        if (lay == 0 && !e->launch) continue;
                         mlk_tile_config c{e->bm, e->bn, e->bk, e->wm, e->wn, sk, gm, xcd, e->stages, lay};
                         out.push_back(c);
                     }
@@ -366,6 +369,7 @@ static mlk_status run_gemm(const KernelEntry* e, GemmArgs& g, const Shape& s, vo
         if (z != hipSuccess) return hip_fail(z, "zero output");
     }
     const int64_t nblk = (int64_t)g.tiles_m * g.tiles_n * g.split_k;
+    if (!e->launch) return fail(MLK_ERR_CONFIG, "this conv tile runs only the channels-last layout (layout 1)");
     hipError_t err = e->launch(g, (int)nblk, st);
     if (err != hipSuccess) return hip_fail(err, "kernel launch");
     return MLK_OK;
@@ -489,6 +493,7 @@ mlk_status launch_conv(const Shape& s, int64_t n, int64_t c, int64_t h, int64_t 
         if (e2 != hipSuccess) return hip_fail(e2, "conv workspace free");
         return MLK_OK;
     }
+    if (!e->launch) return fail(MLK_ERR_CONFIG, "this conv tile runs only the channels-last layout (layout 1)");
     hipError_t err = e->launch(g, (int)nblk, st);
     if (err != hipSuccess) return hip_fail(err, "kernel launch");
     return MLK_OK;

@@ -77,9 +77,17 @@ __device__ inline void wait_vmcnt() {
 // this one streams 181 B/clk/CU, the plain layout 59).
 __device__ inline int fa(int r) { return (r & 7) ^ ((r >> 2) & 2); }
 
-template <int DT, int BM, int BN, int WM, int WN, int STAGES>
+// CONV = 2: the channels-last implicit-GEMM convolution (register-loaded form
+// only): A is the filter as F x (KH*KW*C), C contiguous; B is never formed:
+// its transpose -- one row per output pixel n = (img, oh, ow), columns k =
+// (kh, kw, c) -- is gathered from the NHWC input in 16-byte chunks of 8
+// channels (C a multiple of 8) and kept in LDS like A (rows of BK k), so the
+// MFMA's B operand is read as A's is.  The output is NFHW.
+template <int DT, int BM, int BN, int WM, int WN, int STAGES, int CONV = 0>
 struct FastGemm {
     static_assert(DT == DT_BF16 || DT == DT_F8, "direct-to-LDS kernel: bf16 or e4m3");
+    static_assert(CONV == 0 || (CONV == 2 && STAGES == 1 && DT == DT_BF16),
+                  "implicit convolution: bf16, register-loaded form");
     static constexpr int KB = 128;                 // bytes of K per A row per stage
     static constexpr int ES = DT == DT_BF16 ? 2 : 1;
     static constexpr int BK = KB / ES;             // elements per A row per stage
@@ -88,9 +96,9 @@ struct FastGemm {
     static constexpr int NT = 64 * NW;
     static constexpr int A_ROW = KB;               // bytes
     static constexpr int A_CPR = KB / 16;          // 16-byte chunks per A row
-    static constexpr int B_ROW = BN * ES;
+    static constexpr int B_ROW = CONV ? KB : BN * ES;  // B^T rows of BK k for conv
     static constexpr int A_STAGE = BM * A_ROW;
-    static constexpr int B_STAGE = BK * B_ROW;
+    static constexpr int B_STAGE = CONV ? BN * B_ROW : BK * B_ROW;
     static constexpr int STAGE = A_STAGE + B_STAGE;
     static constexpr bool REG = STAGES == 1;      // register-loaded form
     static constexpr int NBUF = REG ? 2 : STAGES;  // LDS stage buffers
@@ -108,7 +116,7 @@ struct FastGemm {
     static constexpr int B_CHUNKS = B_ROW / 16;
 
     static_assert(A_SLABS % NW == 0 && B_SLABS % NW == 0, "slabs must divide among waves");
-    static_assert(B_CHUNKS >= (DT == DT_BF16 ? 16 : 8), "B rows too short for the swizzle");
+    static_assert(CONV || B_CHUNKS >= (DT == DT_BF16 ? 16 : 8), "B rows too short for the swizzle");
 
     // B swizzle: the rows read together by one transpose read land in distinct
     // 16-byte bank groups.  bf16 reads 4 rows x 32 bytes per lane group, e4m3
@@ -160,6 +168,10 @@ struct FastGemm {
         int b_r[NB];         // row of the stage
         int b_col[NB];       // first column of the chunk
         int b_nv[NB];        // valid columns in the chunk (0..EPV)
+        // conv: the pixel of B^T row r (base of its image in NHWC, window origin)
+        int64_t p_img[NB];
+        int p_ih0[NB], p_iw0[NB];
+        int p_ok[NB];
     };
 
     __device__ static inline void reg_slots(const GemmArgs& g, int64_t m0, int64_t n0, int wave,
@@ -177,13 +189,29 @@ struct FastGemm {
 #pragma unroll
         for (int i = 0; i < NB; ++i) {
             const int slab = wave + i * NW;
-            const int r = slab * B_ROWS_PER_SLAB + lane / B_CHUNKS;
-            const int c = (lane % B_CHUNKS) ^ fb(r);
-            const int64_t col = n0 + c * EPV;
-            rs.b_r[i] = r;
-            rs.b_col[i] = (int)min<int64_t>(col, g.N);
-            rs.b_nv[i] = (int)max<int64_t>(0, min<int64_t>(EPV, g.N - col));
-            rs.b_off[i] = (int64_t)r * g.ldb * ES + (int64_t)rs.b_col[i] * ES;
+            if constexpr (CONV) {
+                // B^T row r = output pixel n0 + r, chunk c of its k range
+                const int r = slab * A_ROWS_PER_SLAB + lane / A_CPR;
+                const int c = (lane % A_CPR) ^ fa(r);
+                const int64_t p = n0 + r;
+                const int hw = g.cho * g.cwo;
+                rs.b_r[i] = r;
+                rs.b_col[i] = c * EPV;  // element offset of the chunk in the stage's k range
+                rs.p_ok[i] = p < g.N;
+                const int img = rs.p_ok[i] ? (int)(p / hw) : 0;
+                const int q = rs.p_ok[i] ? (int)(p - (int64_t)img * hw) : 0;
+                rs.p_img[i] = (int64_t)img * g.ch * g.cw;
+                rs.p_ih0[i] = (q / g.cwo) * g.csh - g.cph;
+                rs.p_iw0[i] = (q % g.cwo) * g.csw - g.cpw;
+            } else {
+                const int r = slab * B_ROWS_PER_SLAB + lane / B_CHUNKS;
+                const int c = (lane % B_CHUNKS) ^ fb(r);
+                const int64_t col = n0 + c * EPV;
+                rs.b_r[i] = r;
+                rs.b_col[i] = (int)min<int64_t>(col, g.N);
+                rs.b_nv[i] = (int)max<int64_t>(0, min<int64_t>(EPV, g.N - col));
+                rs.b_off[i] = (int64_t)r * g.ldb * ES + (int64_t)rs.b_col[i] * ES;
+            }
         }
     }
 
@@ -202,6 +230,24 @@ struct FastGemm {
                 else if (k < g.K) v = load_unaligned<ES>(row, k, (int)min<int64_t>(EPV, g.K - k));
             }
             ra[i] = v;
+        }
+        if constexpr (CONV) {
+            // chunk k..k+7 lies in one filter tap (C is a multiple of 8): channels
+            // ci..ci+7 of input pixel (ih, iw), zero outside the image
+#pragma unroll
+            for (int i = 0; i < NB; ++i) {
+                u4_t v = u4_t{0u, 0u, 0u, 0u};
+                const int64_t k = k0 + rs.b_col[i];
+                if (rs.p_ok[i] && k < g.K) {
+                    const int tap = (int)(k / g.cc), ci = (int)(k - (int64_t)tap * g.cc);
+                    const int kh = tap / g.ckw, kw = tap - kh * g.ckw;
+                    const int ih = rs.p_ih0[i] + kh, iw = rs.p_iw0[i] + kw;
+                    if ((unsigned)ih < (unsigned)g.ch && (unsigned)iw < (unsigned)g.cw)
+                        v = *(const MLK_GLOBAL u4_t*)(B + ((rs.p_img[i] + (int64_t)ih * g.cw + iw) * g.cc + ci) * ES);
+                }
+                rb[i] = v;
+            }
+            return;
         }
         const int64_t kb = k0 * g.ldb * ES;
 #pragma unroll
@@ -290,11 +336,23 @@ struct FastGemm {
         // This lane's outputs: rows wy*WTM + i*16 + lg*4 + r, columns
         // wx*WTN + j*16 + lr of the tile whose corner is Ct (a uniform base);
         // offsets inside the tile are 32-bit.
-        MLK_GLOBAL float* const Ct = (MLK_GLOBAL float*)g.C + m0 * g.ldc + n0;
+        MLK_GLOBAL float* const Ct = (MLK_GLOBAL float*)g.C + (CONV ? 0 : m0 * g.ldc + n0);
         const int ldc = (int)g.ldc;
         const int row0 = wy * WTM + lg * 4, col0 = wx * WTN + lr;
         const bool full = m0 + BM <= g.M && n0 + BN <= g.N;
         const int mrem = (int)min<int64_t>(BM, g.M - m0), nrem = (int)min<int64_t>(BN, g.N - n0);
+        // conv: output (f, n) of NFHW lives at img(n)*F*HW + f*HW + pix(n); this
+        // lane's column tiles j start at cbase[j] (row f = 0), rows step by HW
+        int64_t cbase[CONV ? TN : 1];
+        const int64_t hw = CONV ? (int64_t)g.cho * g.cwo : 0;
+        if constexpr (CONV) {
+#pragma unroll
+            for (int j = 0; j < TN; ++j) {
+                const int64_t n = n0 + col0 + j * 16;
+                const int64_t img = n / hw;
+                cbase[j] = img * g.M * hw + (n - img * hw) + m0 * hw;
+            }
+        }
         // C += A B: start the accumulators from C itself, so that its read
         // happens here, beside the first stage's loads, instead of in a
         // read-add-write epilogue after the last MFMA.  e4m3 multiplies the
@@ -319,7 +377,13 @@ struct FastGemm {
 #pragma unroll
                     for (int r = 0; r < 4; ++r) {
                         const int row = row0 + i * 16 + r, col = col0 + j * 16;
-                        const float x = (full || (row < mrem && col < nrem)) ? Ct[row * ldc + col] : 0.0f;
+                        const bool in = full || (row < mrem && col < nrem);
+                        float x = 0.0f;
+                        if constexpr (CONV) {
+                            if (in) x = Ct[cbase[j] + row * hw];
+                        } else {
+                            x = in ? Ct[row * ldc + col] : 0.0f;
+                        }
                         if constexpr (DT == DT_F8) {
                             const float y = x * inv_alpha;
                             over |= __builtin_isinf(y) && !__builtin_isinf(x);
@@ -374,16 +438,23 @@ struct FastGemm {
                     for (int j = 0; j < TN; ++j) {
                         // lane lr of the group supplies row lr/4, columns 4*(lr%4)..+3 of a
                         // 4 x 16 block; the transpose read returns column lr to it
-                        const int nb = wx * WTN + j * 16 + 4 * (lr & 3);
-                        bf4_t h[2];
+                        bf8_t bj;
+                        if constexpr (CONV) {
+                            // B^T rows hold k contiguous: read like A
+                            const int r = wx * WTN + j * 16 + lr;
+                            bj = __builtin_bit_cast(bf8_t, *(const u4_t*)(sb + r * B_ROW + (((ks * 4 + lg) ^ fa(r)) * 16)));
+                        } else {
+                            const int nb = wx * WTN + j * 16 + 4 * (lr & 3);
+                            bf4_t h[2];
 #pragma unroll
-                        for (int half = 0; half < 2; ++half) {
-                            const int k = ks * 32 + lg * 8 + half * 4 + (lr >> 2);
-                            const int c = (nb >> 3) ^ fb(k);
-                            const uint8_t* p = sb + k * B_ROW + c * 16 + (nb & 7) * 2;
-                            h[half] = __builtin_amdgcn_ds_read_tr16_b64_v4bf16((tp)(p));
+                            for (int half = 0; half < 2; ++half) {
+                                const int k = ks * 32 + lg * 8 + half * 4 + (lr >> 2);
+                                const int c = (nb >> 3) ^ fb(k);
+                                const uint8_t* p = sb + k * B_ROW + c * 16 + (nb & 7) * 2;
+                                h[half] = __builtin_amdgcn_ds_read_tr16_b64_v4bf16((tp)(p));
+                            }
+                            bj = bf8_t{h[0][0], h[0][1], h[0][2], h[0][3], h[1][0], h[1][1], h[1][2], h[1][3]};
                         }
-                        const bf8_t bj = bf8_t{h[0][0], h[0][1], h[0][2], h[0][3], h[1][0], h[1][1], h[1][2], h[1][3]};
 #pragma unroll
                         for (int i = 0; i < TM; ++i)
                             acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
@@ -436,7 +507,7 @@ struct FastGemm {
                 for (int r = 0; r < 4; ++r) {
                     const int row = row0 + i * 16 + r, col = col0 + j * 16;
                     if (!(full || (row < mrem && col < nrem))) continue;
-                    MLK_GLOBAL float* p = Ct + row * ldc + col;
+                    MLK_GLOBAL float* p = CONV ? Ct + cbase[j] + row * hw : Ct + row * ldc + col;
                     const float v = DT == DT_F8 ? alpha * acc[i][j][r] : acc[i][j][r];
                     if (g.atomic) __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                     else if (c_in_acc || !g.accumulate) *p = v;

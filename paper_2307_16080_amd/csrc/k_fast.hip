@@ -1,5 +1,6 @@
 // Configurations of the direct-layout kernel (bf16 and e4m3): tile, wave
-// grid, LDS stages (2..4: direct-to-LDS ring; 1: loaded through registers).
+// grid, LDS stages (2..4: direct-to-LDS ring; 1: loaded through registers),
+// and its channels-last convolution form.
 #include "kernels.hpp"
 namespace mlk {
 const KernelEntry* kernels_fast(int* n) {
@@ -23,6 +24,11 @@ const KernelEntry* kernels_fast(int* n) {
         MLK_ENTRY_FAST(DT_F8, 128, 128, 2, 2, 4),
         MLK_ENTRY_FAST(DT_F8, 128, 128, 2, 2, 2),
         MLK_ENTRY_FAST(DT_F8, 128, 128, 2, 2, 1),
+        // channels-last implicit-GEMM convolution (bf16, C a multiple of 8)
+        MLK_ENTRY_FASTCONV(DT_BF16, 128, 128, 2, 2),
+        MLK_ENTRY_FASTCONV(DT_BF16, 64, 128, 2, 2),
+        MLK_ENTRY_FASTCONV(DT_BF16, 128, 256, 2, 2),
+        MLK_ENTRY_FASTCONV(DT_BF16, 256, 128, 2, 2),
     };
     *n = (int)(sizeof(t) / sizeof(t[0]));
     return t;

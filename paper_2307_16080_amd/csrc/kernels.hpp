@@ -97,6 +97,22 @@ __global__ __launch_bounds__(64 * WM * WN) void k_gemm_fast(GemmArgs g) {
     TL::run(g, tm, tn, kz, lds);
 }
 
+// The channels-last implicit-GEMM convolution form of the direct-layout kernel.
+template <int DT, int BM, int BN, int WM, int WN>
+__global__ __launch_bounds__(64 * WM * WN) void k_fast_conv(GemmArgs g) {
+    typedef FastGemm<DT, BM, BN, WM, WN, 1, 2> TL;
+    __shared__ __attribute__((aligned(1024))) uint8_t lds[TL::LDS_BYTES];
+    int tm, tn, kz;
+    tile_coords(g, blockIdx.x, gridDim.x, tm, tn, kz);
+    TL::run(g, tm, tn, kz, lds);
+}
+
+template <int DT, int BM, int BN, int WM, int WN>
+hipError_t launch_fast_conv(const GemmArgs& g, int nblk, hipStream_t s) {
+    hipLaunchKernelGGL((k_fast_conv<DT, BM, BN, WM, WN>), dim3(nblk), dim3(64 * WM * WN), 0, s, g);
+    return hipGetLastError();
+}
+
 template <int DT, int BM, int BN, int WM, int WN, int STAGES>
 hipError_t launch_fast(const GemmArgs& g, int nblk, hipStream_t s) {
     hipLaunchKernelGGL((k_gemm_fast<DT, BM, BN, WM, WN, STAGES>), dim3(nblk), dim3(64 * WM * WN), 0,
@@ -186,6 +202,14 @@ hipError_t launch_persist(const GemmArgs* gemms, const Task* tasks, const int32_
             &launch_fast<DT, BM, BN, WM, WN, STAGES>,                                        \
             &launch_fast_persist<DT, BM, BN, WM, WN, STAGES>, nullptr,                       \
             &occupancy_fast_persist<DT, BM, BN, WM, WN, STAGES>                              \
+    }
+
+// conv entry: channels-last layout only (launch_nhwc); no NCHW form, no persistent form
+#define MLK_ENTRY_FASTCONV(DT, BM, BN, WM, WN)                                               \
+    KernelEntry {                                                                            \
+        DT, 1, 1, BM, BN, FastGemm<DT, BM, BN, WM, WN, 1, 2>::BK, WM, WN,                    \
+            FastGemm<DT, BM, BN, WM, WN, 1, 2>::LDS_BYTES, 64 * (WM) * (WN), nullptr,        \
+            nullptr, &launch_fast_conv<DT, BM, BN, WM, WN>, nullptr                          \
     }
 
 // Tables defined by the instantiation units (host functions: the tables hold

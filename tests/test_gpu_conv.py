@@ -81,6 +81,46 @@ def test_every_conv_tile(cfg):
             assert np.array_equal(host(y).astype(np.float64), oracle.conv2d_f64(x, w, (s, s), (p, p))), case
 
 
+FAST_CONV = [c for c in all_tiles(L.MLK_BF16, L.MLK_F32, conv=True) if c.stages == 1]
+# channels-last shapes (C a multiple of 8): strides, padding, K = C*KH*KW not a
+# multiple of the 64-deep stage, tiles that span images, ragged F and pixels
+FAST_CASES = [
+    (1, 8, 9, 9, 5, 3, 3, 1, 1),
+    (3, 16, 13, 11, 40, 3, 3, 2, 1),
+    (2, 64, 14, 14, 65, 3, 3, 1, 1),
+    (5, 24, 7, 7, 130, 1, 1, 1, 0),
+    (2, 32, 20, 20, 64, 5, 5, 2, 2),
+]
+
+
+@pytest.mark.parametrize("cfg", FAST_CONV, ids=lambda c: f"{c.bm}x{c.bn}x{c.bk}_{c.wm}{c.wn}")
+def test_fast_conv_tiles(cfg):
+    assert cfg.layout == 1
+    with pytest.raises(mlk.MlkError, match="CONFIG"):    # no NCHW form of this tile
+        x = torch.zeros(1, 8, 4, 4, dtype=torch.bfloat16, device="cuda")
+        mlk.conv2d_nchw_fchw(x, torch.zeros(8, 8, 3, 3, dtype=torch.bfloat16, device="cuda"),
+                             torch.zeros(1, 8, 2, 2, device="cuda"), (1, 1), (0, 0),
+                             cfg=mlk.TileConfig(*list(cfg.as_tuple())[:9], 0))
+    for case in FAST_CASES:
+        N, C, H, W, F, KH, KW, s, p = case
+        say("fast conv", cfg, case)
+        x, w = conv_inputs(N, C, H, W, F, KH, KW, seed=sum(case) + 1)
+        ho, wo = (H + 2 * p - KH) // s + 1, (W + 2 * p - KW) // s + 1
+        y0 = np.random.default_rng(2).uniform(-1, 1, (N, F, ho, wo)).astype(np.float32)
+        qx, qw = oracle.bf16_encode(x), oracle.bf16_encode(w)
+        ref = oracle.conv2d_f64(oracle.bf16_decode(qx), oracle.bf16_decode(qw), (s, s), (p, p), y=y0)
+        y = dev(y0)
+        mlk.conv2d_nchw_fchw(from_bf16_codes(qx), from_bf16_codes(qw), y, (s, s), (p, p), cfg=cfg)
+        assert normwise(host(y), ref) <= 1e-5, case
+        x, w = conv_inputs(N, C, H, W, F, KH, KW, seed=4, dist="small_int")
+        for acc in (True, False):
+            y = torch.full((N, F, ho, wo), float("nan"), device="cuda") if not acc else \
+                torch.zeros(N, F, ho, wo, device="cuda")
+            mlk.conv2d_nchw_fchw(from_bf16_codes(oracle.bf16_encode(x)), from_bf16_codes(oracle.bf16_encode(w)),
+                                 y, (s, s), (p, p), cfg=cfg, accumulate=acc)
+            assert np.array_equal(host(y).astype(np.float64), oracle.conv2d_f64(x, w, (s, s), (p, p))), (case, acc)
+
+
 def test_conv_split_k_overwrite():
     x, w = conv_inputs(1, 64, 14, 14, 32, 3, 3, seed=4, dist="small_int")
     ref = oracle.conv2d_f64(x, w, (1, 1), (1, 1))
