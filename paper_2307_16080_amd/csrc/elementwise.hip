@@ -8,6 +8,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <algorithm>
 #include <cstring>
 
 #include "kernels.hpp"
@@ -87,23 +88,36 @@ __device__ inline uint32_t e4m3_rne_sat(float v) {
     return sign | code;                               // < 448 never reaches 0x7F
 }
 
-__global__ __launch_bounds__(kThreads) void k_amax_init(uint32_t* amax_bits) { *amax_bits = 0u; }
+// Two passes.  k_amax writes one maximum |x| per workgroup (kAmaxBlocks of
+// them, as non-negative floats); k_quant_e4m3 has every workgroup reduce those
+// partials to amax first (a few KB from L2: no atomics, no device-wide
+// counter), derive the scale, and workgroup 0 stores it.
+constexpr int kAmaxBlocks = 512;
 
-// max |x| as the bit pattern of a non-negative float (ordered like unsigned ints)
 template <bool VEC>
 __global__ __launch_bounds__(kThreads) void k_amax(const float* __restrict__ x, int64_t n,
-                                                   uint32_t* amax_bits) {
+                                                   float* __restrict__ part) {
     float m = 0.0f;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     const int64_t first = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if constexpr (VEC) {
         const int64_t nvec = n / 4;
-        for (int64_t i = first; i < nvec; i += stride) {
+        int64_t i = first;
+        // eight independent 16-byte loads in flight per thread
+        for (; i + 7 * stride < nvec; i += 8 * stride) {
+            f4_t a[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) a[u] = *(const f4_t*)(x + 4 * (i + u * stride));
+#pragma unroll
+            for (int u = 0; u < 8; ++u)
+                m = fmaxf(m, fmaxf(fmaxf(fabsf(a[u][0]), fabsf(a[u][1])), fmaxf(fabsf(a[u][2]), fabsf(a[u][3]))));
+        }
+        for (; i < nvec; i += stride) {
             const f4_t a = *(const f4_t*)(x + 4 * i);
             m = fmaxf(m, fmaxf(fmaxf(fabsf(a[0]), fabsf(a[1])), fmaxf(fabsf(a[2]), fabsf(a[3]))));
         }
         if (blockIdx.x == 0)
-            for (int64_t i = nvec * 4 + threadIdx.x; i < n; i += blockDim.x) m = fmaxf(m, fabsf(x[i]));
+            for (int64_t j = nvec * 4 + threadIdx.x; j < n; j += blockDim.x) m = fmaxf(m, fabsf(x[j]));
     } else {
         for (int64_t i = first; i < n; i += stride) m = fmaxf(m, fabsf(x[i]));
     }
@@ -114,20 +128,56 @@ __global__ __launch_bounds__(kThreads) void k_amax(const float* __restrict__ x, 
     __syncthreads();
     if (threadIdx.x == 0) {
         for (int w = 1; w < kThreads / 64; ++w) m = fmaxf(m, wmax[w]);
-        atomicMax(amax_bits, __float_as_uint(m));
+        part[blockIdx.x] = m;
     }
 }
 
-__device__ inline float e4m3_scale_from_amax(uint32_t bits) {
-    const float amax = __uint_as_float(bits);
-    if (!(amax > 0.0f) || bits >= 0x7F800000u) return 1.0f;
+__device__ inline float e4m3_scale_from_amax(float amax) {
+    if (!(amax > 0.0f) || !__builtin_isfinite(amax)) return 1.0f;
     return __fdiv_rn(amax, 448.0f);
 }
 
+// amax over the partials of k_amax, by the whole workgroup; thread 0 of
+// workgroup 0 also stores the scale
+__device__ inline float e4m3_block_scale(const float* __restrict__ part, int nparts, float* scale) {
+    float m = 0.0f;
+    for (int i = threadIdx.x; i < nparts; i += blockDim.x) m = fmaxf(m, part[i]);
+    for (int off = 32; off > 0; off >>= 1) m = fmaxf(m, __shfl_xor(m, off, 64));
+    __shared__ float wmax[kThreads / 64];
+    if ((threadIdx.x & 63) == 0) wmax[threadIdx.x >> 6] = m;
+    __syncthreads();
+    m = wmax[0];
+    for (int w = 1; w < kThreads / 64; ++w) m = fmaxf(m, wmax[w]);
+    const float s = e4m3_scale_from_amax(m);
+    if (blockIdx.x == 0 && threadIdx.x == 0) *scale = s;
+    return s;
+}
+
+// e4m3 code of RN(x / s) without a division for almost every element: y =
+// x * RN(1/s) is within 2.5 fp32 ulps of RN(x / s) (two roundings of 2^-24
+// relative each, plus the quotient's own half ulp), and the e4m3 code is a
+// step function of its input whose steps in the normal range sit where the
+// 20 fraction bits below the kept three equal 0x80000.  So when y is a normal
+// e4m3 input (2^-6 <= |y| < 448) at least 5 ulps from such a step, y and
+// RN(x / s) give the same code; otherwise (near a step, subnormal,
+// saturating, non-finite, or 1/s not finite) the quotient is formed exactly.
+__device__ inline uint32_t e4m3_of_quotient(float x, float s, float r, bool fast) {
+    if (fast) {
+        const float y = x * r;
+        const uint32_t mag = __float_as_uint(y) & 0x7FFFFFFFu;
+        const uint32_t rest = mag & 0xFFFFFu;
+        const uint32_t d = rest > 0x80000u ? rest - 0x80000u : 0x80000u - rest;
+        if (mag >= 0x3C800000u && mag < 0x43E00000u && d > 4u) return e4m3_rne_sat(y);
+    }
+    return e4m3_rne_sat(__fdiv_rn(x, s));
+}
+
 __global__ __launch_bounds__(kThreads) void k_quant_e4m3(const float* __restrict__ x, int64_t n,
-                                                         const uint32_t* amax_bits,
-                                                         uint8_t* __restrict__ q) {
-    const float s = e4m3_scale_from_amax(*amax_bits);
+                                                         const float* __restrict__ part, int nparts,
+                                                         uint8_t* __restrict__ q, float* scale) {
+    const float s = e4m3_block_scale(part, nparts, scale);
+    const float r = __frcp_rn(s);
+    const bool fast = __builtin_isfinite(r) && r > 0.0f;
     const int64_t nvec = n / 16;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nvec; i += stride) {
@@ -135,30 +185,28 @@ __global__ __launch_bounds__(kThreads) void k_quant_e4m3(const float* __restrict
 #pragma unroll
         for (int w = 0; w < 4; ++w) {
             const f4_t a = *(const f4_t*)(x + 16 * i + 4 * w);
-            o[w] = e4m3_rne_sat(__fdiv_rn(a[0], s)) | (e4m3_rne_sat(__fdiv_rn(a[1], s)) << 8) |
-                   (e4m3_rne_sat(__fdiv_rn(a[2], s)) << 16) | (e4m3_rne_sat(__fdiv_rn(a[3], s)) << 24);
+            o[w] = e4m3_of_quotient(a[0], s, r, fast) | (e4m3_of_quotient(a[1], s, r, fast) << 8) |
+                   (e4m3_of_quotient(a[2], s, r, fast) << 16) | (e4m3_of_quotient(a[3], s, r, fast) << 24);
         }
         *(u4_t*)(q + 16 * i) = o;
     }
     if (blockIdx.x == 0)
         for (int64_t i = nvec * 16 + threadIdx.x; i < n; i += blockDim.x)
-            q[i] = (uint8_t)e4m3_rne_sat(__fdiv_rn(x[i], s));
+            q[i] = (uint8_t)e4m3_of_quotient(x[i], s, r, fast);
 }
 
-__global__ __launch_bounds__(kThreads) void k_quant_e4m3_scalar(const float* __restrict__ x,
-                                                                int64_t n, const uint32_t* amax_bits,
-                                                                uint8_t* __restrict__ q) {
-    const float s = e4m3_scale_from_amax(*amax_bits);
+__global__ __launch_bounds__(kThreads) void k_quant_e4m3_scalar(const float* __restrict__ x, int64_t n,
+                                                                const float* __restrict__ part, int nparts,
+                                                                uint8_t* __restrict__ q, float* scale) {
+    const float s = e4m3_block_scale(part, nparts, scale);
+    const float r = __frcp_rn(s);
+    const bool fast = __builtin_isfinite(r) && r > 0.0f;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride)
-        q[i] = (uint8_t)e4m3_rne_sat(__fdiv_rn(x[i], s));
+        q[i] = (uint8_t)e4m3_of_quotient(x[i], s, r, fast);
 }
 
-// scale <- amax / 448 (runs after every block of k_quant_e4m3 has read amax)
-__global__ __launch_bounds__(kThreads) void k_amax_to_scale(uint32_t* amax_bits) {
-    const float s = e4m3_scale_from_amax(*amax_bits);
-    *(float*)amax_bits = s;
-}
+__global__ __launch_bounds__(kThreads) void k_scale_one(float* scale) { *scale = 1.0f; }
 
 // ------------------------------------------------------------------ fills
 
@@ -384,24 +432,27 @@ hipError_t launch_quant_bf16(const float* x, int64_t n, uint16_t* q, hipStream_t
 
 hipError_t launch_quant_e4m3(const float* x, int64_t n, uint8_t* q, float* scale,
                              hipStream_t s) {
-    uint32_t* bits = (uint32_t*)scale;  // holds amax bits until the last kernel
-    hipLaunchKernelGGL(k_amax_init, dim3(1), dim3(1), 0, s, bits);
-    if (n > 0) {
-        const bool vec = ((uintptr_t)x % 16 == 0) && ((uintptr_t)q % 16 == 0);
-        if (vec) {
-            hipLaunchKernelGGL(k_amax<true>, dim3(grid_for(n / 4 + 1, kThreads * 8)), dim3(kThreads),
-                               0, s, x, n, bits);
-            hipLaunchKernelGGL(k_quant_e4m3, dim3(grid_for(n / 16 + 1, kThreads * 2)), dim3(kThreads),
-                               0, s, x, n, (const uint32_t*)bits, q);
-        } else {
-            hipLaunchKernelGGL(k_amax<false>, dim3(grid_for(n, kThreads * 16)), dim3(kThreads), 0, s,
-                               x, n, bits);
-            hipLaunchKernelGGL(k_quant_e4m3_scalar, dim3(grid_for(n, kThreads * 8)), dim3(kThreads), 0,
-                               s, x, n, (const uint32_t*)bits, q);
-        }
+    if (n <= 0) {
+        hipLaunchKernelGGL(k_scale_one, dim3(1), dim3(1), 0, s, scale);
+        return hipGetLastError();
     }
-    hipLaunchKernelGGL(k_amax_to_scale, dim3(1), dim3(1), 0, s, bits);
-    return hipGetLastError();
+    float* part = nullptr;
+    hipError_t err = hipMallocAsync((void**)&part, sizeof(float) * kAmaxBlocks, s);
+    if (err != hipSuccess) return err;
+    const bool vec = ((uintptr_t)x % 16 == 0) && ((uintptr_t)q % 16 == 0);
+    const int nparts = (int)std::min<int64_t>(kAmaxBlocks, grid_for(vec ? n / 4 + 1 : n, kThreads));
+    if (vec) {
+        hipLaunchKernelGGL(k_amax<true>, dim3(nparts), dim3(kThreads), 0, s, x, n, part);
+        hipLaunchKernelGGL(k_quant_e4m3, dim3(grid_for(n / 16 + 1, kThreads * 2)), dim3(kThreads), 0, s, x,
+                           n, (const float*)part, nparts, q, scale);
+    } else {
+        hipLaunchKernelGGL(k_amax<false>, dim3(nparts), dim3(kThreads), 0, s, x, n, part);
+        hipLaunchKernelGGL(k_quant_e4m3_scalar, dim3(grid_for(n, kThreads * 8)), dim3(kThreads), 0, s, x, n,
+                           (const float*)part, nparts, q, scale);
+    }
+    err = hipGetLastError();
+    const hipError_t e2 = hipFreeAsync(part, s);
+    return err != hipSuccess ? err : e2;
 }
 
 hipError_t launch_transpose_batched(const void* in, void* out, int64_t batch, int64_t rows,

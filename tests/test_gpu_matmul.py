@@ -171,6 +171,35 @@ def test_quantize_special_values():
     assert host(s)[0] == np.float32(scale) and np.array_equal(bits8(q8), codes)
 
 
+@pytest.mark.parametrize("scale", [0.37, 1.0, 3.1e-5, 2.0 ** -20])
+def test_quantize_e4m3_rounding_steps(scale):
+    """Inputs within a few fp32 ulps of every e4m3 rounding step (after
+    division by the scale), of the subnormal range and of saturation, both
+    signs, in the vector (16 per thread) and the scalar kernels: codes and
+    scale equal the oracle's bit for bit."""
+    vals = oracle.e4m3_decode(np.arange(0, 127, dtype=np.uint8)).astype(np.float64)
+    steps = np.concatenate([(vals[:-1] + vals[1:]) / 2, vals, [448.0, 464.0, 2.0 ** -6, 2.0 ** -9]])
+    x = (steps * scale).astype(np.float32)
+    around = [x]
+    up, dn = x.copy(), x.copy()
+    for _ in range(8):
+        up = np.nextafter(up, np.float32(np.inf))
+        dn = np.nextafter(dn, np.float32(0))
+        around += [up.copy(), dn.copy()]
+    x = np.concatenate(around)
+    x = np.concatenate([x, -x, [np.float32(448.0 * scale)]]).astype(np.float32)
+    x = x[np.abs(x) <= np.float32(448.0 * scale)]          # keep amax = 448 * scale
+    for data in (x, np.concatenate([x, x[:7]])):             # length 16k and 16k + 7
+        codes, sc = oracle.quantize_e4m3(data)
+        q8, s = mlk.quantize(dev(data), "e4m3")
+        assert host(s)[0] == np.float32(sc)
+        assert np.array_equal(bits8(q8), codes)
+    base = dev(np.concatenate([[0.0], x]).astype(np.float32))  # unaligned view: scalar kernel
+    q8, s = mlk.quantize(base[1:], "e4m3")
+    codes, sc = oracle.quantize_e4m3(x)
+    assert np.array_equal(bits8(q8), codes)
+
+
 # ----------------------------------------------------------------------- bf16 / e4m3
 
 BF16_TILES = all_tiles(L.MLK_BF16, L.MLK_F32)
