@@ -253,32 +253,30 @@ __global__ __launch_bounds__(kThreads) void k_fill_random(uint8_t* p, int64_t n,
 // issued before its stores.  Elements outside the copied block are zero.
 template <typename T>
 __device__ inline void pack_segment(const PackJob& jb, int64_t q, int lane) {
-    constexpr int U = kPackSeg / 64;
+    // lane l moves the 16-byte destination chunks l, l + 64, ... of the segment
+    // (a chunk never crosses a destination row: ld_dst is a whole number of
+    // chunks); the source row is read with dword-aligned 16-byte loads
+    constexpr int EPV = 16 / (int)sizeof(T);
+    constexpr int U = kPackSeg / (64 * EPV);
     const uint32_t n = (uint32_t)jb.rows_dst * (uint32_t)jb.ld_dst;  // < 2^31 (2 GiB operands)
     const uint32_t ld = (uint32_t)jb.ld_dst;
-    const uint32_t e0 = (uint32_t)q * kPackSeg + lane;
-    // (row, column) of this lane's first element; each later element is 64
-    // further on: 64 = q64 * ld + r64
-    uint32_t r = e0 / ld, c = e0 - r * ld;
-    const uint32_t q64 = 64 / ld, r64 = 64 - q64 * ld;
-    const T* src = (const T*)jb.src;
-    T* dst = (T*)jb.dst;
-    T v[U];
+    const gbytes src = (gbytes)jb.src;
+    u4_t v[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-        const uint32_t e = e0 + u * 64;
-        v[u] = (e < n && r < (uint32_t)jb.rows && c < (uint32_t)jb.cols) ? src[(int64_t)r * jb.ld_src + c] : (T)0;
-        c += r64;
-        r += q64;
-        if (c >= ld) {
-            c -= ld;
-            ++r;
+        const uint32_t e = (uint32_t)q * kPackSeg + (uint32_t)(u * 64 + lane) * EPV;
+        const uint32_t r = e / ld, c = e - r * ld;
+        v[u] = u4_t{0u, 0u, 0u, 0u};
+        if (e < n && r < (uint32_t)jb.rows && c < (uint32_t)jb.cols) {
+            const gbytes row = src + (int64_t)r * jb.ld_src * (int64_t)sizeof(T);
+            if (c + EPV <= (uint32_t)jb.cols) v[u] = load16_any<(int)sizeof(T)>(row + (int64_t)c * sizeof(T));
+            else v[u] = load_unaligned<(int)sizeof(T)>(row, c, (int)(jb.cols - c));
         }
     }
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-        const uint32_t e = e0 + u * 64;
-        if (e < n) dst[e] = v[u];
+        const uint32_t e = (uint32_t)q * kPackSeg + (uint32_t)(u * 64 + lane) * EPV;
+        if (e < n) *(u4_t*)((T*)jb.dst + e) = v[u];
     }
 }
 

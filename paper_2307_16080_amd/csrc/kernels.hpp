@@ -233,7 +233,7 @@ hipError_t launch_fill_random(void* p, int64_t n, int dt, uint64_t seed, hipStre
 // copy operands into zero-padded buffers, one wave per segment of kPackSeg
 // consecutive destination elements; seg_start[j] = first segment of job j in
 // a running count over all jobs (njobs + 1 entries, device memory)
-constexpr int kPackSeg = 1024;
+constexpr int kPackSeg = 2048;
 inline int64_t pack_segments(const PackJob& j) {
     return ((int64_t)j.rows_dst * j.ld_dst + kPackSeg - 1) / kPackSeg;
 }
