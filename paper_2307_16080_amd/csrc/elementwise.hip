@@ -351,6 +351,41 @@ __global__ __launch_bounds__(256) void k_transpose(const T* __restrict__ in, T* 
     }
 }
 
+// 2-byte elements with rows and cols multiples of 8 (16-byte rows on both
+// sides): 64 x 64 tiles, 16-byte loads along the input rows and 16-byte stores
+// along the output rows; the LDS tile row pitch (144 bytes) keeps the column
+// gathers of the transposed read on distinct banks.
+__global__ __launch_bounds__(256) void k_transpose16(const uint16_t* __restrict__ in,
+                                                     uint16_t* __restrict__ out, int64_t rows,
+                                                     int64_t cols) {
+    __shared__ __attribute__((aligned(16))) uint16_t tile[64][72];
+    const int64_t b = blockIdx.z;
+    const uint16_t* src = in + b * rows * cols;
+    uint16_t* dst = out + b * rows * cols;
+    const int64_t c0 = (int64_t)blockIdx.x * 64, r0 = (int64_t)blockIdx.y * 64;
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+        const int k = threadIdx.x + 256 * i;
+        const int r = k >> 3, cc = (k & 7) * 8;
+        u4_t v = u4_t{0u, 0u, 0u, 0u};
+        if (r0 + r < rows && c0 + cc < cols) v = *(const u4_t*)(src + (r0 + r) * cols + c0 + cc);
+        *(u4_t*)&tile[r][cc] = v;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+        const int k = threadIdx.x + 256 * i;
+        const int oc = k >> 3, rc = (k & 7) * 8;
+        if (c0 + oc < cols && r0 + rc < rows) {
+            u4_t v;
+#pragma unroll
+            for (int t = 0; t < 4; ++t)
+                v[t] = (uint32_t)tile[rc + 2 * t][oc] | ((uint32_t)tile[rc + 2 * t + 1][oc] << 16);
+            *(u4_t*)(dst + (c0 + oc) * rows + r0 + rc) = v;
+        }
+    }
+}
+
 // ------------------------------------------------------------------ error statistics
 
 constexpr int kErrBlocks = 1024;
@@ -461,6 +496,11 @@ hipError_t launch_transpose_batched(const void* in, void* out, int64_t batch, in
     if (esize == 4)
         hipLaunchKernelGGL(k_transpose<uint32_t>, grid, dim3(256), 0, s, (const uint32_t*)in,
                            (uint32_t*)out, rows, cols);
+    else if (esize == 2 && rows % 8 == 0 && cols % 8 == 0 && (uintptr_t)in % 16 == 0 &&
+             (uintptr_t)out % 16 == 0 && batch <= 65535)
+        hipLaunchKernelGGL(k_transpose16, dim3((unsigned)((cols + 63) / 64), (unsigned)((rows + 63) / 64),
+                                               (unsigned)batch),
+                           dim3(256), 0, s, (const uint16_t*)in, (uint16_t*)out, rows, cols);
     else if (esize == 2)
         hipLaunchKernelGGL(k_transpose<uint16_t>, grid, dim3(256), 0, s, (const uint16_t*)in,
                            (uint16_t*)out, rows, cols);

@@ -168,14 +168,16 @@ struct FastGemm {
         int b_r[NB];         // row of the stage
         int b_col[NB];       // first column of the chunk
         int b_nv[NB];        // valid columns in the chunk (0..EPV)
-        // conv: the pixel of B^T row r (base of its image in NHWC, window origin)
+        // conv: the pixel of B^T row r (base of its image in NHWC, window origin),
+        // and the chunk's current k = (kh, kw, ci), stepped by BK per stage
         int64_t p_img[NB];
         int p_ih0[NB], p_iw0[NB];
         int p_ok[NB];
+        int k_ci[NB], k_kh[NB], k_kw[NB];
     };
 
-    __device__ static inline void reg_slots(const GemmArgs& g, int64_t m0, int64_t n0, int wave,
-                                            int lane, RegSlots& rs) {
+    __device__ static inline void reg_slots(const GemmArgs& g, int64_t m0, int64_t n0, int64_t kfirst,
+                                            int wave, int lane, RegSlots& rs) {
 #pragma unroll
         for (int i = 0; i < NA; ++i) {
             const int slab = wave + i * NW;
@@ -203,6 +205,11 @@ struct FastGemm {
                 rs.p_img[i] = (int64_t)img * g.ch * g.cw;
                 rs.p_ih0[i] = (q / g.cwo) * g.csh - g.cph;
                 rs.p_iw0[i] = (q % g.cwo) * g.csw - g.cpw;
+                const int64_t k = kfirst + rs.b_col[i];
+                const int tap = (int)(k / g.cc);
+                rs.k_ci[i] = (int)(k - (int64_t)tap * g.cc);
+                rs.k_kh[i] = tap / g.ckw;
+                rs.k_kw[i] = tap - rs.k_kh[i] * g.ckw;
             } else {
                 const int r = slab * B_ROWS_PER_SLAB + lane / B_CHUNKS;
                 const int c = (lane % B_CHUNKS) ^ fb(r);
@@ -216,7 +223,7 @@ struct FastGemm {
     }
 
     // the chunks of the stage starting at k0 (zero outside the operands)
-    __device__ static inline void reg_load(const GemmArgs& g, const RegSlots& rs, int64_t k0,
+    __device__ static inline void reg_load(const GemmArgs& g, RegSlots& rs, int64_t k0,
                                            u4_t* ra, u4_t* rb) {
         const gbytes A = (gbytes)g.A, B = (gbytes)g.B;
         const bool kfull = k0 + BK <= g.K;
@@ -234,18 +241,26 @@ struct FastGemm {
         if constexpr (CONV) {
             // chunk k..k+7 lies in one filter tap (C is a multiple of 8): channels
             // ci..ci+7 of input pixel (ih, iw), zero outside the image
+            // (stages are loaded in order, so each call steps every chunk by BK)
 #pragma unroll
             for (int i = 0; i < NB; ++i) {
                 u4_t v = u4_t{0u, 0u, 0u, 0u};
                 const int64_t k = k0 + rs.b_col[i];
                 if (rs.p_ok[i] && k < g.K) {
-                    const int tap = (int)(k / g.cc), ci = (int)(k - (int64_t)tap * g.cc);
-                    const int kh = tap / g.ckw, kw = tap - kh * g.ckw;
-                    const int ih = rs.p_ih0[i] + kh, iw = rs.p_iw0[i] + kw;
+                    const int ih = rs.p_ih0[i] + rs.k_kh[i], iw = rs.p_iw0[i] + rs.k_kw[i];
                     if ((unsigned)ih < (unsigned)g.ch && (unsigned)iw < (unsigned)g.cw)
-                        v = *(const MLK_GLOBAL u4_t*)(B + ((rs.p_img[i] + (int64_t)ih * g.cw + iw) * g.cc + ci) * ES);
+                        v = *(const MLK_GLOBAL u4_t*)(B + ((rs.p_img[i] + (int64_t)ih * g.cw + iw) * g.cc +
+                                                           rs.k_ci[i]) * ES);
                 }
                 rb[i] = v;
+                rs.k_ci[i] += BK;
+                while (rs.k_ci[i] >= g.cc) {
+                    rs.k_ci[i] -= g.cc;
+                    if (++rs.k_kw[i] == g.ckw) {
+                        rs.k_kw[i] = 0;
+                        ++rs.k_kh[i];
+                    }
+                }
             }
             return;
         }
@@ -273,6 +288,84 @@ struct FastGemm {
             *(u4_t*)(stage + A_STAGE + (wave + i * NW) * 1024 + lane * 16) = rb[i];
     }
 
+    // the MFMAs of one LDS stage (sa: A rows, sb: B rows or, for conv, B^T rows)
+    __device__ static inline void mma_stage(const uint8_t* sa, const uint8_t* sb, f4_t (&acc)[TM][TN], int wy,
+                                            int wx, int lr, int lg) {
+        typedef __attribute__((address_space(3))) bf4_t* tp;
+        typedef __attribute__((address_space(3))) i2_t* t8p;
+#pragma unroll
+        for (int ks = 0; ks < BK / KSTEP; ++ks) {
+            if constexpr (DT == DT_BF16) {
+                u4_t af[TM];
+#pragma unroll
+                for (int i = 0; i < TM; ++i) {
+                    const int r = wy * WTM + i * 16 + lr;
+                    const int c = (ks * 4 + lg) ^ fa(r);
+                    af[i] = *(const u4_t*)(sa + r * A_ROW + c * 16);
+                }
+                // B fragments are consumed as soon as they arrive, column tile by
+                // column tile, so only one or two are live at a time
+#pragma unroll
+                for (int j = 0; j < TN; ++j) {
+                    // lane lr of the group supplies row lr/4, columns 4*(lr%4)..+3 of a
+                    // 4 x 16 block; the transpose read returns column lr to it
+                    bf8_t bj;
+                    if constexpr (CONV) {
+                        // B^T rows hold k contiguous: read like A
+                        const int r = wx * WTN + j * 16 + lr;
+                        bj = __builtin_bit_cast(bf8_t, *(const u4_t*)(sb + r * B_ROW + (((ks * 4 + lg) ^ fa(r)) * 16)));
+                    } else {
+                        const int nb = wx * WTN + j * 16 + 4 * (lr & 3);
+                        bf4_t h[2];
+#pragma unroll
+                        for (int half = 0; half < 2; ++half) {
+                            const int k = ks * 32 + lg * 8 + half * 4 + (lr >> 2);
+                            const int c = (nb >> 3) ^ fb(k);
+                            const uint8_t* p = sb + k * B_ROW + c * 16 + (nb & 7) * 2;
+                            h[half] = __builtin_amdgcn_ds_read_tr16_b64_v4bf16((tp)(p));
+                        }
+                        bj = bf8_t{h[0][0], h[0][1], h[0][2], h[0][3], h[1][0], h[1][1], h[1][2], h[1][3]};
+                    }
+#pragma unroll
+                    for (int i = 0; i < TM; ++i)
+                        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                            __builtin_bit_cast(bf8_t, af[i]), bj, acc[i][j], 0, 0, 0);
+                }
+            } else {
+                i8_t af[TM], bfr[TN];
+#pragma unroll
+                for (int i = 0; i < TM; ++i) {
+                    const int r = wy * WTM + i * 16 + lr;
+                    const u4_t lo = *(const u4_t*)(sa + r * A_ROW + ((2 * lg) ^ fa(r)) * 16);
+                    const u4_t hi = *(const u4_t*)(sa + r * A_ROW + ((2 * lg + 1) ^ fa(r)) * 16);
+                    af[i] = i8_t{(int)lo[0], (int)lo[1], (int)lo[2], (int)lo[3],
+                                 (int)hi[0], (int)hi[1], (int)hi[2], (int)hi[3]};
+                }
+#pragma unroll
+                for (int j = 0; j < TN; ++j) {
+                    // lane lr supplies row lr/2, bytes 8*(lr%2)..+7 of an 8 x 16 block;
+                    // the transpose read returns column lr (8 consecutive k) to it
+                    const int nb = wx * WTN + j * 16 + 8 * (lr & 1);
+                    i2_t q[4];
+#pragma unroll
+                    for (int qq = 0; qq < 4; ++qq) {
+                        const int k = lg * 32 + qq * 8 + (lr >> 1);
+                        const int c = (nb >> 4) ^ fb(k);
+                        const uint8_t* p = sb + k * B_ROW + c * 16 + (nb & 15);
+                        q[qq] = __builtin_amdgcn_ds_read_tr8_b64_v2i32((t8p)(p));
+                    }
+                    bfr[j] = i8_t{q[0][0], q[0][1], q[1][0], q[1][1], q[2][0], q[2][1], q[3][0], q[3][1]};
+                }
+#pragma unroll
+                for (int i = 0; i < TM; ++i)
+#pragma unroll
+                    for (int j = 0; j < TN; ++j)
+                        acc[i][j] = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(
+                            af[i], bfr[j], acc[i][j], 0, 0, 0, 127, 0, 127);
+            }
+        }
+    }
+
     __device__ static inline void run(const GemmArgs& g, int tm, int tn, int kz, uint8_t* lds) {
         const int tid = threadIdx.x;
         const int lane = tid & 63, wave = tid >> 6;
@@ -289,7 +382,7 @@ struct FastGemm {
         int voff_a[NA], voff_b[NB];
         // register-loaded form: chunk state and the stage in flight
         RegSlots rs;
-        u4_t qa[NA], qb[NB];
+        u4_t qa[NA], qb[NB], qa2[NA], qb2[NB];
         if constexpr (!REG) {
             ra = make_rsrc(g.A, (uint32_t)(((g.M - 1) * g.lda + g.K) * ES));
             rb = make_rsrc(g.B, (uint32_t)(((g.K - 1) * g.ldb + g.N) * ES));
@@ -311,7 +404,7 @@ struct FastGemm {
                 voff_b[i] = col < g.N ? (int)((r * g.ldb + col) * ES) : 0x7FFFFFF0;
             }
         } else {
-            reg_slots(g, m0, n0, wave, lane, rs);
+            reg_slots(g, m0, n0, s_beg * BK, wave, lane, rs);
         }
 
         f4_t acc[TM][TN];
@@ -330,6 +423,7 @@ struct FastGemm {
                 reg_load(g, rs, s_beg * BK, qa, qb);
                 reg_store(lds, qa, qb, wave, lane);
             }
+            if (nk > 1) reg_load(g, rs, (s_beg + 1) * BK, qa2, qb2);
         }
 
         const int lr = lane & 15, lg = lane >> 4;
@@ -405,99 +499,34 @@ struct FastGemm {
 
         typedef __attribute__((address_space(3))) bf4_t* tp;
         typedef __attribute__((address_space(3))) i2_t* t8p;
-        for (int it = 0; it < nk; ++it) {
-            if constexpr (!REG) {
+        if constexpr (!REG) {
+            for (int it = 0; it < nk; ++it) {
                 // stage `it` has landed once at most (stages issued after it) loads remain
                 wait_stage<(STAGES >= 2 ? STAGES - 2 : 0)>(min(STAGES - 2, nk - 1 - it));
-            } else {
-                // next stage into registers, in flight across the barrier and the MFMAs
-                if (it + 1 < nk) reg_load(g, rs, (s_beg + it + 1) * BK, qa, qb);
-            }
-            // all of this workgroup's waves: stage `it` visible, stage it-1 fully read
-            asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
-            if constexpr (!REG) {
+                // all of this workgroup's waves: stage `it` visible, stage it-1 fully read
+                asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
                 if (it + STAGES - 1 < nk)
                     issue_stage(ra, rb, voff_a, voff_b, (s_beg + it + STAGES - 1) * BK, g.ldb,
                                 lds + ((it + STAGES - 1) % STAGES) * STAGE, wave);
+                const uint8_t* sa = lds + (it % NBUF) * STAGE;
+                mma_stage(sa, sa + A_STAGE, acc, wy, wx, lr, lg);
             }
-            const uint8_t* sa = lds + (it % NBUF) * STAGE;
-            const uint8_t* sb = sa + A_STAGE;
-#pragma unroll
-            for (int ks = 0; ks < BK / KSTEP; ++ks) {
-                if constexpr (DT == DT_BF16) {
-                    u4_t af[TM];
-#pragma unroll
-                    for (int i = 0; i < TM; ++i) {
-                        const int r = wy * WTM + i * 16 + lr;
-                        const int c = (ks * 4 + lg) ^ fa(r);
-                        af[i] = *(const u4_t*)(sa + r * A_ROW + c * 16);
-                    }
-                    // B fragments are consumed as soon as they arrive, column tile by
-                    // column tile, so only one or two are live at a time
-#pragma unroll
-                    for (int j = 0; j < TN; ++j) {
-                        // lane lr of the group supplies row lr/4, columns 4*(lr%4)..+3 of a
-                        // 4 x 16 block; the transpose read returns column lr to it
-                        bf8_t bj;
-                        if constexpr (CONV) {
-                            // B^T rows hold k contiguous: read like A
-                            const int r = wx * WTN + j * 16 + lr;
-                            bj = __builtin_bit_cast(bf8_t, *(const u4_t*)(sb + r * B_ROW + (((ks * 4 + lg) ^ fa(r)) * 16)));
-                        } else {
-                            const int nb = wx * WTN + j * 16 + 4 * (lr & 3);
-                            bf4_t h[2];
-#pragma unroll
-                            for (int half = 0; half < 2; ++half) {
-                                const int k = ks * 32 + lg * 8 + half * 4 + (lr >> 2);
-                                const int c = (nb >> 3) ^ fb(k);
-                                const uint8_t* p = sb + k * B_ROW + c * 16 + (nb & 7) * 2;
-                                h[half] = __builtin_amdgcn_ds_read_tr16_b64_v4bf16((tp)(p));
-                            }
-                            bj = bf8_t{h[0][0], h[0][1], h[0][2], h[0][3], h[1][0], h[1][1], h[1][2], h[1][3]};
-                        }
-#pragma unroll
-                        for (int i = 0; i < TM; ++i)
-                            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
-                                __builtin_bit_cast(bf8_t, af[i]), bj, acc[i][j], 0, 0, 0);
-                    }
-                } else {
-                    i8_t af[TM], bfr[TN];
-#pragma unroll
-                    for (int i = 0; i < TM; ++i) {
-                        const int r = wy * WTM + i * 16 + lr;
-                        const u4_t lo = *(const u4_t*)(sa + r * A_ROW + ((2 * lg) ^ fa(r)) * 16);
-                        const u4_t hi = *(const u4_t*)(sa + r * A_ROW + ((2 * lg + 1) ^ fa(r)) * 16);
-                        af[i] = i8_t{(int)lo[0], (int)lo[1], (int)lo[2], (int)lo[3],
-                                     (int)hi[0], (int)hi[1], (int)hi[2], (int)hi[3]};
-                    }
-#pragma unroll
-                    for (int j = 0; j < TN; ++j) {
-                        // lane lr supplies row lr/2, bytes 8*(lr%2)..+7 of an 8 x 16 block;
-                        // the transpose read returns column lr (8 consecutive k) to it
-                        const int nb = wx * WTN + j * 16 + 8 * (lr & 1);
-                        i2_t q[4];
-#pragma unroll
-                        for (int qq = 0; qq < 4; ++qq) {
-                            const int k = lg * 32 + qq * 8 + (lr >> 1);
-                            const int c = (nb >> 4) ^ fb(k);
-                            const uint8_t* p = sb + k * B_ROW + c * 16 + (nb & 15);
-                            q[qq] = __builtin_amdgcn_ds_read_tr8_b64_v2i32((t8p)(p));
-                        }
-                        bfr[j] = i8_t{q[0][0], q[0][1], q[1][0], q[1][1], q[2][0], q[2][1], q[3][0], q[3][1]};
-                    }
-#pragma unroll
-                    for (int i = 0; i < TM; ++i)
-#pragma unroll
-                        for (int j = 0; j < TN; ++j)
-                            acc[i][j] = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(
-                                af[i], bfr[j], acc[i][j], 0, 0, 0, 127, 0, 127);
-                }
-            }
-            if constexpr (REG) {
-                if (it + 1 < nk) reg_store(lds + ((it + 1) % NBUF) * STAGE, qa, qb, wave, lane);
+        } else {
+            // Two register sets, two stages ahead: iteration it loads stage it+2
+            // into one set while the other (stage it+1, loaded one iteration
+            // earlier) is written to the LDS buffer that stage it-1 used.
+            auto step = [&](int it, u4_t* la, u4_t* lb, const u4_t* sa_, const u4_t* sb_) {
+                if (it + 2 < nk) reg_load(g, rs, (s_beg + it + 2) * BK, la, lb);
+                asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
+                const uint8_t* sa = lds + (it & 1) * STAGE;
+                mma_stage(sa, sa + A_STAGE, acc, wy, wx, lr, lg);
+                if (it + 1 < nk) reg_store(lds + ((it + 1) & 1) * STAGE, sa_, sb_, wave, lane);
+            };
+            for (int it = 0; it < nk; it += 2) {
+                step(it, qa, qb, qa2, qb2);
+                if (it + 1 < nk) step(it + 1, qa2, qb2, qa, qb);
             }
         }
-
         // epilogue: lane l, register r holds output row 4*(l/16) + r, column l % 16
 #pragma unroll
         for (int j = 0; j < TN; ++j)

@@ -391,8 +391,9 @@ struct Tile {
         if (!cc.any || kb >= g.K) return;
         const gbytes X = (gbytes)g.B;
         const int KHW = g.ckh * g.ckw, HW = g.ch * g.cw;
-        int c = (int)(kb / KHW);
-        const int rem = (int)(kb - (int64_t)c * KHW);
+        // (K = C*KH*KW < 2^31: 32-bit divisions)
+        int c = (int)kb / KHW;
+        const int rem = (int)kb - c * KHW;
         int kh = rem / g.ckw, kw = rem - (rem / g.ckw) * g.ckw;
 #pragma unroll
         for (int e = 0; e < EPV; ++e) {
@@ -466,7 +467,7 @@ struct Tile {
                 rb[i] = u4_t{0u, 0u, 0u, 0u};
                 const int64_t k = k0 + (c % CPR) * EPV;
                 if (k >= g.K) continue;
-                const int tap = (int)(k / g.cc), ch = (int)(k - (int64_t)tap * g.cc);
+                const int tap = (int)k / g.cc, ch = (int)k - tap * g.cc;  // K < 2^31
                 const int kh = tap / g.ckw, kw = tap - (tap / g.ckw) * g.ckw;
                 const int ih = nc.ih0[i] + kh, iw = nc.iw0[i] + kw;
                 if ((unsigned)ih >= (unsigned)g.ch || (unsigned)iw >= (unsigned)g.cw) continue;

@@ -16,7 +16,6 @@ const KernelEntry* kernels_fast(int* n) {
         // operands loaded through registers: any shape and alignment, persistent batches
         MLK_ENTRY_FAST(DT_BF16, 128, 128, 2, 2, 1),
         MLK_ENTRY_FAST(DT_BF16, 256, 128, 2, 2, 1),
-        MLK_ENTRY_FAST(DT_BF16, 128, 256, 2, 2, 1),
         MLK_ENTRY_FAST(DT_F8, 256, 256, 2, 4, 2),
         MLK_ENTRY_FAST(DT_F8, 256, 256, 2, 2, 2),
         MLK_ENTRY_FAST(DT_F8, 256, 128, 2, 2, 3),

@@ -90,6 +90,9 @@ FAST_CASES = [
     (2, 64, 14, 14, 65, 3, 3, 1, 1),
     (5, 24, 7, 7, 130, 1, 1, 1, 0),
     (2, 32, 20, 20, 64, 5, 5, 2, 2),
+    # H*W and C multiples of 8 (the 16-byte transpose), ragged against its 64 x 64 tiles
+    (2, 72, 10, 20, 24, 3, 3, 1, 1),
+    (1, 128, 16, 16, 64, 1, 1, 1, 0),
 ]
 
 
