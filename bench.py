@@ -93,14 +93,27 @@ def main():
     qb, _ = mlk.quantize(Bd, "bf16")
     C = torch.zeros(M, N, dtype=torch.float32, device="cuda")
 
-    # tile configuration: exhaustive search over the legal space (not timed as a step)
+    def tune_sustained(problem, run, finalists=6, iters=30, **kw):
+        """Exhaustive search (the library's tuner: short timed bursts), then the
+        fastest few configurations re-timed over `iters` back-to-back launches,
+        the way the benchmark runs them; returns the best of those."""
+        best, rep, times = mlk.tune(problem, mlk.MLK_TUNE_EXHAUSTIVE, want_times=True, **kw)
+        cfgs = mlk.configs(problem)
+        order = sorted((t, i) for i, t in enumerate(times) if t > 0)[:finalists]
+        timed = [(time_us(lambda: run(cfgs[i]), iters), i) for _, i in order]
+        us, i = min(timed)
+        return cfgs[i], rep, us
+
+    # tile configuration: exhaustive search over the legal space, finalists
+    # re-timed under sustained load (not timed as a step)
     t0 = time.time()
     prob = mlk.matmul_problem(M, N, K, L.MLK_BF16, L.MLK_F32, accumulate=True)
     if args.tile:
         best = mlk.TileConfig(*[int(v) for v in args.tile.split(",")])
     else:
-        best, rep, _ = mlk.tune(prob, mlk.MLK_TUNE_EXHAUSTIVE, reps=5, warmup=2)
-        log(f"tuned bf16 {M}^3: {best} {rep.best_us:.1f} us over {rep.n_legal} configs in {time.time() - t0:.1f} s")
+        best, rep, us_best = tune_sustained(prob, lambda c: mlk.matmul(qa, qb, C, cfg=c), reps=5, warmup=2)
+        log(f"tuned bf16 {M}^3: {best} {us_best:.1f} us (sustained) over {rep.n_legal} configs in "
+            f"{time.time() - t0:.1f} s")
 
     # ---------------------------------------------------------------- timed region
     for _ in range(args.warmup):
@@ -173,7 +186,8 @@ def main():
         qa8, sa = mlk.quantize(Ad, "e4m3")
         qb8, sb = mlk.quantize(Bd, "e4m3")
         p8 = mlk.matmul_problem(M, N, K, L.MLK_F8E4M3, L.MLK_F32)
-        b8, _, _ = mlk.tune(p8, mlk.MLK_TUNE_EXHAUSTIVE, reps=5, warmup=2)
+        b8, _, _ = tune_sustained(p8, lambda c: mlk.matmul(qa8, qb8, C, cfg=c, scale_a=sa, scale_b=sb),
+                                  reps=5, warmup=2)
         us = time_us(lambda: mlk.matmul(qa8, qb8, C, cfg=b8, scale_a=sa, scale_b=sb), 20)
         C.zero_()
         mlk.matmul(qa8, qb8, C, cfg=b8, scale_a=sa, scale_b=sb)

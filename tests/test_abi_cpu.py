@@ -132,9 +132,24 @@ def test_config_space():
     # and layout is meaningless for matmul
     assert not mlk.config_legal(mlk.matmul_problem(64, 64, 64, L.MLK_BF16, L.MLK_F32),
                                 mlk.TileConfig(64, 64, 32, 2, 2, 1, 1, 0, 0, 1))
+    # the direct-layout conv form (stages 1) exists only channels-last
+    fast_conv = [c for c in mlk.configs(cp) if c.stages == 1]
+    assert fast_conv and all(c.layout == 1 for c in fast_conv)
+    f0 = fast_conv[0]
+    assert not mlk.config_legal(cp, mlk.TileConfig(*list(f0.as_tuple())[:9], 0))
+    assert not any(c.stages == 1 for c in mlk.configs(c3))
+    # direct-to-LDS tiles take any matmul shape (operands are packed as needed)
+    odd = mlk.matmul_problem(1000, 1001, 999, L.MLK_BF16, L.MLK_F32)
+    assert any(c.stages >= 2 for c in mlk.configs(odd))
+    assert mlk.config_legal(odd, mlk.TileConfig(256, 256, 64, 2, 4, 1, 8, 0, 2, 0))
+    # but not fp32 or int8 problems
+    assert not any(c.stages for c in mlk.configs(mlk.matmul_problem(999, 999, 999, L.MLK_F32, L.MLK_F32)))
+    assert not any(c.stages for c in mlk.configs(mlk.matmul_problem(999, 999, 999, L.MLK_I8, L.MLK_I32)))
     bp = mlk.batched_problem([(100, 200, 300), (64, 64, 64)])
     bc = mlk.configs(bp)
     assert bc and all(c.split_k == 1 for c in bc)
+    # batches take every persistent tile family, direct-to-LDS ones included
+    assert {c.stages for c in bc} >= {0, 1, 2}
     # invalid problems count as -1
     bad = mlk.matmul_problem(4, 4, 4, L.MLK_I8, L.MLK_F32)
     assert L.lib().mlk_config_count(ctypes.byref(bad)) == -1
