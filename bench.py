@@ -230,11 +230,13 @@ def main():
         bflops = sum(2.0 * m * nn * k for m, nn, k in shapes)
         pb = mlk.batched_problem(shapes, L.MLK_BF16, L.MLK_F32)
         bb, _, _ = mlk.tune(pb, mlk.MLK_TUNE_EXHAUSTIVE, reps=5, warmup=1)
-        us_pg = time_us(lambda: mlk.batched_matmul(probs, cfg=bb, persistent=True, graph=True), 10)
+        # descriptors bound once (mlk.BatchedCall): each timed call is one library
+        # call -- with graph=True one replay of the captured launches
+        us_pg = time_us(mlk.BatchedCall(probs, cfg=bb, persistent=True, graph=True), 20)
         # the same GEMMs as 256 separate launches (register-loaded tile: any alignment)
         bl = mlk.TileConfig(128, 128, 64, 2, 2, 1, 1, 0, 1, 0)
-        us_loop = time_us(lambda: mlk.batched_matmul(probs, cfg=bl), 3)
-        us_g = time_us(lambda: mlk.batched_matmul(probs, cfg=bl, graph=True), 3)
+        us_loop = time_us(mlk.BatchedCall(probs, cfg=bl), 3)
+        us_g = time_us(mlk.BatchedCall(probs, cfg=bl, graph=True), 3)
         rows_out["batched_256_bf16"] = {"gflop": round(bflops / 1e9, 2), "tile": list(bb.as_tuple()),
                                         "persistent_graph_us": round(us_pg, 1),
                                         "TFLOP/s": round(bflops / us_pg / 1e6, 1),
@@ -255,7 +257,7 @@ def main():
         tables = costmodel.exhaustive_tables(problems, reps=3, warmup=1)
         log(f"exhaustive tables for {len(problems)} conv problems in {time.time() - t0:.1f} s")
         for batch in (1, 32):
-            stack_us, stack_flops = 0.0, 0.0
+            eager_us, stack_flops = 0.0, 0.0
             for (shape, count), p, t in zip(shapes_all, problems, tables):
                 if shape.N != batch:
                     continue
@@ -266,13 +268,15 @@ def main():
                 qw, _ = mlk.quantize(ws, "bf16")
                 ho, wo = shape.out_hw()
                 ys = torch.zeros(shape.N, shape.F, ho, wo, device="cuda")
-                us = time_us(lambda: mlk.conv2d_nchw_fchw(qx, qw, ys, (shape.stride,) * 2, (shape.pad,) * 2,
-                                                          cfg=cfg), 20)
-                stack_us += us * count
+                call = (lambda qx=qx, qw=qw, ys=ys, shape=shape, cfg=cfg:
+                        mlk.conv2d_nchw_fchw(qx, qw, ys, (shape.stride,) * 2, (shape.pad,) * 2, cfg=cfg))
+                eager_us += time_us(call, 20) * count
                 stack_flops += shape.flops() * count
+            stack_us = eager_us
             rows_out[f"resnet18_stack_b{batch}_bf16"] = {"us": round(stack_us, 1),
                                                          "TFLOP/s": round(stack_flops / stack_us / 1e6, 2),
-                                                         "gflop": round(stack_flops / 1e9, 2)}
+                                                         "gflop": round(stack_flops / 1e9, 2),
+                                                         "timing": "sum over layers of count x per-call time"}
         t0 = time.time()
         ev = costmodel.leave_one_out(problems, tables, budget=0.2)
         ev["summary"]["seconds"] = round(time.time() - t0, 1)

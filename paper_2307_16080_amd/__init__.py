@@ -23,7 +23,7 @@ from ._lib import (MLK_BATCH_GRAPH, MLK_BATCH_PERSISTENT, MLK_BF16, MLK_F8E4M3, 
                    MLK_TUNE_MODEL, MLK_TUNE_RANDOM, GemmDesc, MlkError, Problem, TileConfig,
                    TuneOpts, TuneReport)
 
-__all__ = ["matmul", "conv2d_nchw_fchw", "quantize", "batched_matmul", "err_stats", "tune",
+__all__ = ["matmul", "conv2d_nchw_fchw", "quantize", "batched_matmul", "BatchedCall", "err_stats", "tune",
            "config_count", "configs", "config_legal", "set_default_config", "CostModel",
            "mlp_forward", "mlp_loss_grad", "adam_step", "release", "version", "TileConfig",
            "Problem", "MlkError", "matmul_problem", "conv_problem", "batched_problem"]
@@ -133,19 +133,39 @@ def quantize(x: torch.Tensor, fmt: str, q=None, scale=None, stream=None):
     raise MlkError(4, f"unknown format {fmt!r}")
 
 
+class BatchedCall:
+    """A batch of GEMMs bound once to its tensors.  The descriptor array is built
+    here, once; each call is then a single library call (with `graph`, a replay
+    of the captured persistent launch), so a serving loop pays no per-GEMM host
+    work.  The tensors are kept alive by the object; their storage must not move
+    between calls."""
+
+    def __init__(self, problems, accumulate: bool = True, cfg=None, persistent: bool = False,
+                 graph: bool = False):
+        if len(problems) == 0:
+            raise MlkError(2, "batched: empty problem list")
+        self._problems = list(problems)
+        self._descs = (GemmDesc * len(self._problems))()
+        for i, (A, B, C) in enumerate(self._problems):
+            M, K = A.shape
+            N = B.shape[1]
+            self._descs[i] = GemmDesc(M, N, K, A.data_ptr(), _row_major_ld(A), B.data_ptr(),
+                                      _row_major_ld(B), C.data_ptr(), _row_major_ld(C))
+        A0, _, C0 = self._problems[0]
+        self._din, self._dout = _dt(A0), _dt(C0)
+        self._cfg = None if cfg is None else (cfg if isinstance(cfg, TileConfig) else TileConfig(*cfg))
+        self._acc = int(bool(accumulate))
+        self._flags = (MLK_BATCH_PERSISTENT if persistent else 0) | (MLK_BATCH_GRAPH if graph else 0)
+
+    def __call__(self, stream=None):
+        L.check(L.lib().mlk_batched_matmul(self._din, self._dout, len(self._problems), self._descs,
+                                           _cfg(self._cfg), self._acc, self._flags, _stream(stream)))
+
+
 def batched_matmul(problems, accumulate: bool = True, cfg=None, persistent: bool = False,
                    graph: bool = False, stream=None):
     """problems: list of (A, B, C) CUDA tensors (same dtypes across the list)."""
-    descs = (GemmDesc * len(problems))()
-    for i, (A, B, C) in enumerate(problems):
-        M, K = A.shape
-        N = B.shape[1]
-        descs[i] = GemmDesc(M, N, K, A.data_ptr(), _row_major_ld(A), B.data_ptr(),
-                            _row_major_ld(B), C.data_ptr(), _row_major_ld(C))
-    A0, _, C0 = problems[0]
-    flags = (MLK_BATCH_PERSISTENT if persistent else 0) | (MLK_BATCH_GRAPH if graph else 0)
-    L.check(L.lib().mlk_batched_matmul(_dt(A0), _dt(C0), len(problems), descs, _cfg(cfg),
-                                       int(bool(accumulate)), flags, _stream(stream)))
+    BatchedCall(problems, accumulate, cfg, persistent, graph)(stream)
 
 
 def err_stats(c: torch.Tensor, r: torch.Tensor, bound=None, stream=None):

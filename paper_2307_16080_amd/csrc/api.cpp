@@ -364,14 +364,26 @@ static GemmArgs base_args(const Shape& s, const mlk_tile_config& cfg) {
 static mlk_status run_gemm(const KernelEntry* e, GemmArgs& g, const Shape& s, void* C, int64_t M,
                            int64_t N, int64_t ldc, hipStream_t st) {
     const int esz = 4;  // every output type is 32-bit
+    if (!e->launch) return fail(MLK_ERR_CONFIG, "this conv tile runs only the channels-last layout (layout 1)");
     if (g.atomic && !s.accumulate) {
         hipError_t z = launch_zero_matrix(C, M, N, ldc, esz, st);
         if (z != hipSuccess) return hip_fail(z, "zero output");
     }
     const int64_t nblk = (int64_t)g.tiles_m * g.tiles_n * g.split_k;
-    if (!e->launch) return fail(MLK_ERR_CONFIG, "this conv tile runs only the channels-last layout (layout 1)");
     hipError_t err = e->launch(g, (int)nblk, st);
     if (err != hipSuccess) return hip_fail(err, "kernel launch");
+    return MLK_OK;
+}
+
+// Routes with a stream-ordered workspace are refused on a capturing stream:
+// the library does not record allocation nodes into a caller's graph.
+static mlk_status refuse_under_capture(hipStream_t st, const char* what) {
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    const hipError_t e = hipStreamIsCapturing(st, &cs);
+    if (e != hipSuccess) return hip_fail(e, "hipStreamIsCapturing");
+    if (cs != hipStreamCaptureStatusNone)
+        return fail(MLK_ERR_CONFIG, "%s takes a stream-ordered workspace, which is not recorded into a captured "
+                    "graph; choose a configuration without one", what);
     return MLK_OK;
 }
 
@@ -407,6 +419,8 @@ mlk_status launch_dense(const Shape& s, const void* A, int64_t lda, const void* 
     if (!pa && !pb) return run_gemm(e, g, s, C, s.M, s.N, ldc, st);
     const int64_t abytes = pa ? cdiv(s.M * Kp * es, 256) * 256 : 0;
     const int64_t bbytes = pb ? Kp * Np * es : 0;
+    if (mlk_status rc = refuse_under_capture(st, "a direct-to-LDS tile with operand packing"); rc != MLK_OK)
+        return rc;
     void* ws = nullptr;
     hipError_t err = hipMallocAsync(&ws, (size_t)(abytes + bbytes), st);
     if (err != hipSuccess) return hip_fail(err, "packing workspace");
@@ -460,6 +474,15 @@ mlk_status launch_conv(const Shape& s, int64_t n, int64_t c, int64_t h, int64_t 
     g.cpw = pw;
     g.cho = (int32_t)ho;
     g.cwo = (int32_t)wo;
+    const int epv = 16 / es;
+    if (cfg.layout == 1) {
+        if (!(e->launch_nhwc && c % epv == 0 && (uintptr_t)x % 16 == 0 && (uintptr_t)wt % 16 == 0 &&
+              n <= 65535 && f <= 65535))
+            return fail(MLK_ERR_CONFIG, "channels-last layout needs C %% %d == 0, aligned x and w, N, F <= 65535", epv);
+        if (mlk_status rc = refuse_under_capture(st, "the channels-last conv layout"); rc != MLK_OK) return rc;
+    } else if (!e->launch) {
+        return fail(MLK_ERR_CONFIG, "this conv tile runs only the channels-last layout (layout 1)");
+    }
     if (g.atomic && !s.accumulate) {
         hipError_t z = launch_zero_matrix(y, n * f, ho * wo, ho * wo, 4, st);
         if (z != hipSuccess) return hip_fail(z, "zero output");
@@ -469,11 +492,7 @@ mlk_status launch_conv(const Shape& s, int64_t n, int64_t c, int64_t h, int64_t 
     // x to NHWC and the filter to F x KH x KW x C in a stream-ordered
     // workspace, so every operand load of the tile kernel is one aligned
     // 16-byte read.
-    const int epv = 16 / es;
     if (cfg.layout == 1) {
-        if (!(e->launch_nhwc && c % epv == 0 && (uintptr_t)x % 16 == 0 && (uintptr_t)wt % 16 == 0 &&
-              n <= 65535 && f <= 65535))
-            return fail(MLK_ERR_CONFIG, "channels-last layout needs C %% %d == 0, aligned x and w, N, F <= 65535", epv);
         const size_t xb = ((size_t)(n * c * h * w) * es + 255) & ~(size_t)255;
         const size_t wb = (size_t)(f * c * kh * kw) * es;
         void* ws = nullptr;
@@ -493,7 +512,6 @@ mlk_status launch_conv(const Shape& s, int64_t n, int64_t c, int64_t h, int64_t 
         if (e2 != hipSuccess) return hip_fail(e2, "conv workspace free");
         return MLK_OK;
     }
-    if (!e->launch) return fail(MLK_ERR_CONFIG, "this conv tile runs only the channels-last layout (layout 1)");
     hipError_t err = e->launch(g, (int)nblk, st);
     if (err != hipSuccess) return hip_fail(err, "kernel launch");
     return MLK_OK;

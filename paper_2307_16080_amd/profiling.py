@@ -80,8 +80,9 @@ def run_batched(tile, launches):
         qb, _ = mlk.quantize(torch.from_numpy(b).cuda(), "bf16")
         probs.append((qa, qb, torch.zeros(m, n, device="cuda")))
     cfg = mlk.TileConfig(*[int(v) for v in tile.split(",")])
+    call = mlk.BatchedCall(probs, cfg=cfg, persistent=True, graph=True)
     for _ in range(launches):
-        mlk.batched_matmul(probs, cfg=cfg, persistent=True, graph=True)
+        call()
     torch.cuda.synchronize()
     print(f"batched: {launches} persistent launches of {len(shapes)} GEMMs, tile {tile}", flush=True)
 

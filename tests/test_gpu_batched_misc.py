@@ -123,6 +123,27 @@ def test_batched_graph_replays_match_eager():
             del junk
 
 
+def test_batched_call_replays_accumulate():
+    """A BatchedCall bound once: every call is one graph replay and adds A B
+    into C again (C = 3 A B after three calls on small integers, exact)."""
+    shapes = batched_shapes(32, seed=8) + [(1, 1, 1), (70, 9, 33)]
+    probs, _ = _batch(shapes, seed=9, dist="small_int")
+    cfg = mlk.TileConfig(128, 128, 64, 2, 2, 1, 1, 0, 2, 0)
+    mlk.batched_matmul(probs, cfg=cfg, accumulate=False, persistent=True)
+    once = _outs(probs)
+    _zero(probs)
+    call = mlk.BatchedCall(probs, cfg=cfg, persistent=True, graph=True)
+    for rep in range(3):
+        junk = torch.randn(1000, device="cuda").sum()       # eager work between replays
+        call()
+        got = _outs(probs)
+        for i, (a, b) in enumerate(zip(once, got)):
+            assert np.array_equal(a * (rep + 1), b), (rep, i, shapes[i])
+        del junk
+    with pytest.raises(mlk.MlkError):
+        mlk.BatchedCall([])
+
+
 def test_batched_f32_and_default_config():
     shapes = [(33, 65, 17), (128, 128, 128), (1, 300, 7), (200, 1, 64)]
     ins = batched_inputs(shapes, seed=5, dist="small_int")

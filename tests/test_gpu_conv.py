@@ -11,7 +11,7 @@ import torch
 import oracle
 import paper_2307_16080_amd as mlk
 from paper_2307_16080_amd import _lib as L
-from workloads import CFG_CONV_F32, conv_inputs, resnet18_conv_stack
+from workloads import CFG_CONV_F32, conv_inputs, matmul_inputs, resnet18_conv_stack
 
 from gpu_util import all_tiles, dev, from_bf16_codes, host, normwise, say
 
@@ -156,3 +156,85 @@ def test_paper_conv_shape_f32():
     y = torch.zeros(1, 3, 1278, 1278, device="cuda")
     mlk.conv2d_nchw_fchw(dev(x), dev(w), y)
     assert normwise(host(y), ref) <= 1e-5
+
+
+def test_workspace_routes_refused_under_capture():
+    """On a capturing stream the routes that take a stream-ordered workspace
+    (channels-last conv, packed direct-to-LDS matmul) return MLK_ERR_CONFIG
+    and record nothing; the capture itself stays valid."""
+    x = torch.zeros(1, 64, 8, 8, dtype=torch.bfloat16, device="cuda")
+    w = torch.zeros(64, 64, 3, 3, dtype=torch.bfloat16, device="cuda")
+    y = torch.zeros(1, 64, 8, 8, device="cuda")
+    A = torch.zeros(40, 72, dtype=torch.bfloat16, device="cuda")
+    B = torch.zeros(72, 24, dtype=torch.bfloat16, device="cuda")
+    C = torch.zeros(40, 24, device="cuda")
+    t = torch.zeros(16, device="cuda")
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        t.add_(1.0)
+        with pytest.raises(mlk.MlkError, match="CONFIG"):
+            mlk.conv2d_nchw_fchw(x, w, y, (1, 1), (1, 1), cfg=mlk.TileConfig(128, 128, 64, 2, 2, 1, 1, 0, 1, 1))
+        with pytest.raises(mlk.MlkError, match="CONFIG"):
+            mlk.matmul(A, B, C, cfg=mlk.TileConfig(128, 128, 64, 2, 2, 1, 1, 0, 2, 0))
+    del graph
+    torch.cuda.synchronize()
+
+
+@pytest.mark.skip(reason="records stream-ordered workspace allocations into a captured graph; a replay of a "
+                         "larger capture of that kind (the ResNet-18 stack) hit a GPU memory fault in the "
+                         "weight transpose, with no cause found in this library; those routes now refuse "
+                         "a capturing stream")
+def test_conv_stack_graph_capture_replays():
+    """Library calls recorded into one HIP graph (torch's capture of the current
+    stream): the channels-last route's stream-ordered workspace, its
+    transposes and the tile kernel, the NCHW route and a GEMM, each layer
+    twice (C += twice).  Every replay, from zeroed outputs and with eager work
+    and synchronisations between replays, equals the eager calls bit for bit."""
+    layers = [((2, 64, 14, 14, 64, 3, 3, 1, 1), mlk.TileConfig(128, 128, 64, 2, 2, 1, 1, 0, 1, 1)),
+              ((2, 32, 9, 11, 16, 3, 3, 2, 1), mlk.TileConfig(64, 64, 32, 2, 2, 1, 1, 0, 0, 0)),
+              ((1, 128, 7, 7, 256, 1, 1, 1, 0), mlk.TileConfig(64, 128, 64, 2, 2, 1, 1, 0, 1, 1))]
+    ops = []
+    for i, (case, cfg) in enumerate(layers):
+        N, C, H, W, F, KH, KW, s, p = case
+        x, w = conv_inputs(N, C, H, W, F, KH, KW, seed=30 + i)
+        qx, qw = from_bf16_codes(oracle.bf16_encode(x)), from_bf16_codes(oracle.bf16_encode(w))
+        y = torch.zeros(N, F, (H + 2 * p - KH) // s + 1, (W + 2 * p - KW) // s + 1, device="cuda")
+        ops.append(lambda qx=qx, qw=qw, y=y, s=s, p=p, cfg=cfg:
+                   mlk.conv2d_nchw_fchw(qx, qw, y, (s, s), (p, p), cfg=cfg))
+        ops.append(ops[-1])
+        layers[i] = y
+    A, B = (from_bf16_codes(oracle.bf16_encode(m)) for m in matmul_inputs(200, 136, 72, seed=5))
+    Cm = torch.zeros(200, 136, device="cuda")
+    ops.append(lambda: mlk.matmul(A, B, Cm, cfg=mlk.TileConfig(128, 128, 64, 2, 2, 1, 1, 0, 1, 0)))
+    outs = layers + [Cm]
+
+    def zero():
+        for t in outs:
+            t.zero_()
+
+    zero()
+    for op in ops:
+        op()
+    torch.cuda.synchronize()
+    want = [t.cpu().clone() for t in outs]
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):                           # warm-up on a side stream
+        for op in ops:
+            op()
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        for op in ops:
+            op()
+    for rep in range(3):
+        zero()
+        junk = torch.randn(4096, device="cuda").sum()        # eager work between replays
+        torch.cuda.synchronize()
+        graph.replay()
+        torch.cuda.synchronize()
+        for i, (t, ref) in enumerate(zip(outs, want)):
+            assert torch.equal(t.cpu(), ref), (rep, i)
+        del junk
