@@ -27,12 +27,17 @@
  *    MLK_ERR_* codes except MLK_ERR_HIP can be produced without a GPU.  On
  *    error nothing is enqueued and mlk_last_error() returns a thread-local
  *    message.
- *  - Stream capture: the routes that take a stream-ordered workspace (a
- *    direct-to-LDS matmul tile whose operands need zero-padded copies, the
- *    channels-last conv layout) are not recorded into a captured graph: on a
- *    stream that is capturing they return MLK_ERR_CONFIG and enqueue
- *    nothing.  Configurations without a workspace (register-loaded tiles,
- *    aligned direct-to-LDS operands, conv layout 0) may be captured.
+ *  - Scratch memory: the routes that need a workspace (a direct-to-LDS
+ *    matmul tile whose operands need zero-padded copies, the channels-last
+ *    conv layout, e4m3 quantisation) use one library-owned buffer per device,
+ *    grown on demand up to 512 MiB and held until mlk_release(); larger
+ *    requests take a stream-ordered allocation of their own for the call.
+ *    Uses of the buffer are ordered on the device with an event, whatever
+ *    streams they run on.
+ *  - Stream capture: those workspace routes are not recorded into a captured
+ *    graph: on a stream that is capturing they return MLK_ERR_CONFIG and
+ *    enqueue nothing.  Configurations without a workspace (register-loaded
+ *    tiles, aligned direct-to-LDS operands, conv layout 0) may be captured.
  *  - Thread safety: calls from several host threads are safe; calls that
  *    overlap on one device share its workspaces and are serialised inside
  *    the library.

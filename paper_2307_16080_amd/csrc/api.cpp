@@ -419,11 +419,11 @@ mlk_status launch_dense(const Shape& s, const void* A, int64_t lda, const void* 
     if (!pa && !pb) return run_gemm(e, g, s, C, s.M, s.N, ldc, st);
     const int64_t abytes = pa ? cdiv(s.M * Kp * es, 256) * 256 : 0;
     const int64_t bbytes = pb ? Kp * Np * es : 0;
-    if (mlk_status rc = refuse_under_capture(st, "a direct-to-LDS tile with operand packing"); rc != MLK_OK)
+    ScratchUse scratch;
+    if (mlk_status rc = scratch.begin((size_t)(abytes + bbytes), st, "a direct-to-LDS tile with operand packing");
+        rc != MLK_OK)
         return rc;
-    void* ws = nullptr;
-    hipError_t err = hipMallocAsync(&ws, (size_t)(abytes + bbytes), st);
-    if (err != hipSuccess) return hip_fail(err, "packing workspace");
+    void* ws = scratch.ptr();
     PackJob jobs[2];
     int nj = 0;
     if (pa) {
@@ -439,11 +439,10 @@ mlk_status launch_dense(const Shape& s, const void* A, int64_t lda, const void* 
     g.ldb = ldb2;
     g.K = Kp;
     g.vec_a = g.vec_b = 1;
-    err = launch_pack_pair(jobs, nj, es, st);
+    const hipError_t err = launch_pack_pair(jobs, nj, es, st);
     mlk_status r = err == hipSuccess ? run_gemm(e, g, s, C, s.M, s.N, ldc, st) : hip_fail(err, "operand packing");
-    const hipError_t ferr = hipFreeAsync(ws, st);
-    if (r == MLK_OK && ferr != hipSuccess) return hip_fail(ferr, "packing workspace release");
-    return r;
+    const mlk_status rel = scratch.end();
+    return r != MLK_OK ? r : rel;
 }
 
 mlk_status launch_conv(const Shape& s, int64_t n, int64_t c, int64_t h, int64_t w, int64_t f,
@@ -495,10 +494,10 @@ mlk_status launch_conv(const Shape& s, int64_t n, int64_t c, int64_t h, int64_t 
     if (cfg.layout == 1) {
         const size_t xb = ((size_t)(n * c * h * w) * es + 255) & ~(size_t)255;
         const size_t wb = (size_t)(f * c * kh * kw) * es;
-        void* ws = nullptr;
-        hipError_t err = hipMallocAsync(&ws, xb + wb, st);
-        if (err != hipSuccess) return hip_fail(err, "conv workspace");
-        uint8_t* xn = (uint8_t*)ws;
+        ScratchUse scratch;
+        if (mlk_status rc = scratch.begin(xb + wb, st, "the channels-last conv layout"); rc != MLK_OK) return rc;
+        hipError_t err = hipSuccess;
+        uint8_t* xn = (uint8_t*)scratch.ptr();
         uint8_t* wn = xn + xb;
         if ((err = launch_transpose_batched(x, xn, n, c, h * w, es, st)) == hipSuccess &&
             (err = launch_transpose_batched(wt, wn, f, c, kh * kw, es, st)) == hipSuccess) {
@@ -507,10 +506,9 @@ mlk_status launch_conv(const Shape& s, int64_t n, int64_t c, int64_t h, int64_t 
             g.vec_a = 1;
             err = e->launch_nhwc(g, (int)nblk, st);
         }
-        hipError_t e2 = hipFreeAsync(ws, st);
+        const mlk_status rel = scratch.end();
         if (err != hipSuccess) return hip_fail(err, "conv launch");
-        if (e2 != hipSuccess) return hip_fail(e2, "conv workspace free");
-        return MLK_OK;
+        return rel;
     }
     hipError_t err = e->launch(g, (int)nblk, st);
     if (err != hipSuccess) return hip_fail(err, "kernel launch");
@@ -640,10 +638,21 @@ mlk_status mlk_quantize(mlk_dtype out, int64_t n, const float* x, void* q, float
     if (n > 0 && (!x || !q)) return fail(MLK_ERR_NULL, "quantize: x or q is NULL");
     if (n > 0 && overlaps(x, (size_t)n * 4, q, (size_t)n * (out == MLK_BF16 ? 2 : 1)))
         return fail(MLK_ERR_LAYOUT, "quantize: q overlaps x");
-    hipError_t e = out == MLK_BF16 ? launch_quant_bf16(x, n, (uint16_t*)q, (hipStream_t)stream)
-                                   : launch_quant_e4m3(x, n, (uint8_t*)q, scale, (hipStream_t)stream);
+    const hipStream_t st = (hipStream_t)stream;
+    if (out == MLK_BF16) {
+        const hipError_t e = launch_quant_bf16(x, n, (uint16_t*)q, st);
+        return e == hipSuccess ? MLK_OK : hip_fail(e, "quantize launch");
+    }
+    ScratchUse scratch;
+    if (n > 0) {
+        if (mlk_status rc = scratch.begin(sizeof(float) * quant_e4m3_parts(), st, "e4m3 quantisation");
+            rc != MLK_OK)
+            return rc;
+    }
+    const hipError_t e = launch_quant_e4m3(x, n, (uint8_t*)q, scale, (float*)scratch.ptr(), st);
+    const mlk_status rel = scratch.end();
     if (e != hipSuccess) return hip_fail(e, "quantize launch");
-    return MLK_OK;
+    return rel;
 }
 
 mlk_status mlk_err_stats(mlk_dtype c_dtype, int64_t n, const void* c, const double* r,

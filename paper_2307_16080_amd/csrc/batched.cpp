@@ -440,6 +440,7 @@ void mlk_release(void) {
     g_plans.clear();
     for (auto& kv : g_capture_streams) (void)hipStreamDestroy(kv.second);
     g_capture_streams.clear();
+    release_scratch();
 }
 
 }  // extern "C"

@@ -92,7 +92,7 @@ __device__ inline uint32_t e4m3_rne_sat(float v) {
 // them, as non-negative floats); k_quant_e4m3 has every workgroup reduce those
 // partials to amax first (a few KB from L2: no atomics, no device-wide
 // counter), derive the scale, and workgroup 0 stores it.
-constexpr int kAmaxBlocks = 512;
+constexpr int kAmaxBlocks = quant_e4m3_parts();
 
 template <bool VEC>
 __global__ __launch_bounds__(kThreads) void k_amax(const float* __restrict__ x, int64_t n,
@@ -463,15 +463,12 @@ hipError_t launch_quant_bf16(const float* x, int64_t n, uint16_t* q, hipStream_t
     return hipGetLastError();
 }
 
-hipError_t launch_quant_e4m3(const float* x, int64_t n, uint8_t* q, float* scale,
+hipError_t launch_quant_e4m3(const float* x, int64_t n, uint8_t* q, float* scale, float* part,
                              hipStream_t s) {
     if (n <= 0) {
         hipLaunchKernelGGL(k_scale_one, dim3(1), dim3(1), 0, s, scale);
         return hipGetLastError();
     }
-    float* part = nullptr;
-    hipError_t err = hipMallocAsync((void**)&part, sizeof(float) * kAmaxBlocks, s);
-    if (err != hipSuccess) return err;
     const bool vec = ((uintptr_t)x % 16 == 0) && ((uintptr_t)q % 16 == 0);
     const int nparts = (int)std::min<int64_t>(kAmaxBlocks, grid_for(vec ? n / 4 + 1 : n, kThreads));
     if (vec) {
@@ -483,9 +480,7 @@ hipError_t launch_quant_e4m3(const float* x, int64_t n, uint8_t* q, float* scale
         hipLaunchKernelGGL(k_quant_e4m3_scalar, dim3(grid_for(n, kThreads * 8)), dim3(kThreads), 0, s, x, n,
                            (const float*)part, nparts, q, scale);
     }
-    err = hipGetLastError();
-    const hipError_t e2 = hipFreeAsync(part, s);
-    return err != hipSuccess ? err : e2;
+    return hipGetLastError();
 }
 
 hipError_t launch_transpose_batched(const void* in, void* out, int64_t batch, int64_t rows,

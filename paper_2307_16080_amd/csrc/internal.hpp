@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdarg>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -59,6 +60,30 @@ mlk_status launch_conv(const Shape& s, int64_t n, int64_t c, int64_t h, int64_t 
                        const mlk_tile_config& cfg, hipStream_t st);
 
 int64_t conv_out(int64_t in, int64_t k, int64_t stride, int64_t pad);
+
+// One use of the library's scratch memory (scratch.cpp).  begin() returns
+// with the device's buffer (at least `bytes`) locked for this call and the
+// stream ordered after the buffer's previous use; end(), or the destructor,
+// records the release once the call's work is enqueued.  On a capturing
+// stream begin() refuses with MLK_ERR_CONFIG.
+class ScratchUse {
+  public:
+    ScratchUse() = default;
+    ScratchUse(const ScratchUse&) = delete;
+    ScratchUse& operator=(const ScratchUse&) = delete;
+    ~ScratchUse();
+    mlk_status begin(size_t bytes, hipStream_t st, const char* what);
+    mlk_status end();
+    void* ptr() const { return ptr_; }
+
+  private:
+    std::unique_lock<std::mutex> lock_;
+    hipStream_t stream_ = nullptr;
+    void* ptr_ = nullptr;
+    void* own_ = nullptr;  // an uncached (oversized) allocation of this use
+    int dev_ = 0;
+};
+void release_scratch();
 
 // cost model internals used by the tuner
 int model_feature_count();

@@ -17,6 +17,7 @@ const KernelEntry* kernels_fast(int* n) {
         MLK_ENTRY_FAST(DT_BF16, 128, 128, 2, 2, 1),
         MLK_ENTRY_FAST(DT_BF16, 256, 128, 2, 2, 1),
         MLK_ENTRY_FAST(DT_F8, 256, 256, 2, 4, 2),
+        MLK_ENTRY_FAST(DT_F8, 256, 256, 4, 2, 2),
         MLK_ENTRY_FAST(DT_F8, 256, 256, 2, 2, 2),
         MLK_ENTRY_FAST(DT_F8, 256, 128, 2, 2, 3),
         MLK_ENTRY_FAST(DT_F8, 128, 256, 2, 2, 3),

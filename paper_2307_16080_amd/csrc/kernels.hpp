@@ -225,7 +225,9 @@ const KernelEntry* kernels_fast(int* n);
 hipError_t launch_zero_matrix(void* C, int64_t M, int64_t N, int64_t ldc, int esize,
                               hipStream_t s);
 hipError_t launch_quant_bf16(const float* x, int64_t n, uint16_t* q, hipStream_t s);
-hipError_t launch_quant_e4m3(const float* x, int64_t n, uint8_t* q, float* scale,
+// `part`: device workspace of quant_e4m3_parts() floats (per-workgroup maxima)
+constexpr int quant_e4m3_parts() { return 512; }
+hipError_t launch_quant_e4m3(const float* x, int64_t n, uint8_t* q, float* scale, float* part,
                              hipStream_t s);
 hipError_t launch_err_stats(int c_is_int, int64_t n, const void* c, const double* r,
                             const double* bound, double* out, hipStream_t s);

@@ -238,3 +238,44 @@ def test_conv_stack_graph_capture_replays():
         for i, (t, ref) in enumerate(zip(outs, want)):
             assert torch.equal(t.cpu(), ref), (rep, i)
         del junk
+
+
+def test_scratch_shared_across_streams():
+    """The workspace routes share one library scratch buffer per device: calls
+    interleaved on two streams (growing the buffer on the way) give the same
+    bits as the same calls made one after another on the default stream."""
+    convs = []
+    for i, case in enumerate([(1, 64, 12, 12, 32, 3, 3, 1, 1), (4, 128, 20, 20, 64, 3, 3, 1, 1),
+                              (2, 64, 30, 30, 64, 1, 1, 2, 0)]):
+        N, C, H, W, F, KH, KW, s, p = case
+        x, w = conv_inputs(N, C, H, W, F, KH, KW, seed=40 + i)
+        qx, qw = from_bf16_codes(oracle.bf16_encode(x)), from_bf16_codes(oracle.bf16_encode(w))
+        convs.append((qx, qw, (s, s), (p, p), (N, F, (H + 2 * p - KH) // s + 1, (W + 2 * p - KW) // s + 1)))
+    mms = []
+    for i, (M, N, K) in enumerate([(96, 40, 70), (300, 136, 200), (64, 24, 33)]):
+        A, B = (from_bf16_codes(oracle.bf16_encode(m)) for m in matmul_inputs(M, N, K, seed=50 + i))
+        mms.append((A, B, (M, N)))
+    ccfg = mlk.TileConfig(128, 128, 64, 2, 2, 1, 1, 0, 1, 1)
+    mcfg = mlk.TileConfig(128, 128, 64, 2, 2, 1, 1, 0, 2, 0)
+
+    def run_all(stream_of):
+        outs = []
+        for k in range(6):
+            x, w, s, p, shp = convs[k % 3]
+            A, B, mn = mms[k % 3]
+            with torch.cuda.stream(stream_of(k)):
+                y = torch.zeros(shp, device="cuda")
+                mlk.conv2d_nchw_fchw(x, w, y, s, p, cfg=ccfg)
+                C = torch.zeros(mn, device="cuda")
+                mlk.matmul(A, B, C, cfg=mcfg)
+                outs += [y, C]
+        torch.cuda.synchronize()
+        return [t.cpu() for t in outs]
+
+    mlk.release()                                            # start from no scratch buffer
+    want = run_all(lambda k: torch.cuda.current_stream())
+    s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+    mlk.release()
+    got = run_all(lambda k: s1 if k % 2 == 0 else s2)
+    for i, (a, b) in enumerate(zip(want, got)):
+        assert torch.equal(a, b), i
