@@ -148,6 +148,7 @@ mlk_status shape_of_problem(const mlk_problem* p, Shape* s) {
         s->N = p->n * ho * wo;
         s->K = p->c * p->kh * p->kw;
         s->conv_c = p->c;
+        s->conv_in = p->n * p->c * p->h * p->w;
     } else {
         if (p->count < 1) return fail(MLK_ERR_SHAPE, "batched: count must be >= 1");
         if (!p->descs) return fail(MLK_ERR_NULL, "batched: descs is NULL");
@@ -177,6 +178,9 @@ static int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
 // offsets).
 static bool fast_shape_ok(const Shape& s, int bk) {
     const int64_t es = esize_in(s.dt);
+    // conv: the filter (F x C*KH*KW) and the NHWC input are read in place, the
+    // depth in whole stages
+    if (s.conv) return s.K % bk == 0 && s.M * s.K * es < ((int64_t)1 << 31) && s.conv_in * es < ((int64_t)1 << 31);
     const int64_t Kp = cdiv(std::max<int64_t>(s.K, 1), bk) * bk, Np = cdiv(s.N, 16 / es) * (16 / es);
     return s.M * Kp * es < ((int64_t)1 << 31) && Kp * Np * es < ((int64_t)1 << 31);
 }
@@ -186,9 +190,13 @@ mlk_status check_config(const Shape& s, int op, const mlk_tile_config& c) {
     if (!e)
         return fail(MLK_ERR_CONFIG, "no compiled kernel for tile %dx%dx%d waves %dx%d stages %d (dtype %d%s)",
                     c.bm, c.bn, c.bk, c.wm, c.wn, c.stages, s.dt, s.conv ? ", conv" : "");
-    // (operands that do not fit these tiles are packed, so any shape is fine)
-    if (e->stages >= 2 && op != MLK_OP_BATCHED && !fast_shape_ok(s, e->bk))
+    // (matmul operands that do not fit these tiles are packed, so any shape is fine)
+    if (e->stages >= 2 && op != MLK_OP_BATCHED && !fast_shape_ok(s, e->bk)) {
+        if (s.conv)
+            return fail(MLK_ERR_CONFIG, "direct-to-LDS conv tile: needs C*KH*KW a multiple of %d and operands "
+                        "below 2 GiB", e->bk);
         return fail(MLK_ERR_CONFIG, "direct-to-LDS tile: an operand exceeds 2 GiB");
+    }
     if (c.split_k < 1 || c.split_k > 64) return fail(MLK_ERR_CONFIG, "split_k must be in [1, 64]");
     const int64_t stages = cdiv(std::max<int64_t>(s.K, 1), c.bk);
     if (c.split_k > 1 && c.split_k > stages)

@@ -86,8 +86,7 @@ __device__ inline int fa(int r) { return (r & 7) ^ ((r >> 2) & 2); }
 template <int DT, int BM, int BN, int WM, int WN, int STAGES, int CONV = 0>
 struct FastGemm {
     static_assert(DT == DT_BF16 || DT == DT_F8, "direct-to-LDS kernel: bf16 or e4m3");
-    static_assert(CONV == 0 || (CONV == 2 && STAGES == 1 && DT == DT_BF16),
-                  "implicit convolution: bf16, register-loaded form");
+    static_assert(CONV == 0 || (CONV == 2 && DT == DT_BF16), "implicit convolution: bf16");
     static constexpr int KB = 128;                 // bytes of K per A row per stage
     static constexpr int ES = DT == DT_BF16 ? 2 : 1;
     static constexpr int BK = KB / ES;             // elements per A row per stage
@@ -156,6 +155,44 @@ struct FastGemm {
         for (int i = 0; i < NB; ++i) {
             const int slab = wave + i * NW;
             dma_load16(__builtin_amdgcn_readfirstlane(base + A_STAGE + slab * 1024), voff_b[i], rb, sb);
+        }
+    }
+
+    // conv, direct-to-LDS form: A as issue_stage; each B^T slab is gathered
+    // from the NHWC input, one 16-byte chunk per lane (8 channels of one pixel
+    // and filter tap) landing where the register-loaded form would store it;
+    // chunks outside the image or past the last pixel read zero (offset past
+    // the buffer's range).  Stages are issued in order and every call steps the
+    // chunks' k by BK (C * KH * KW is a multiple of BK for this form).
+    template <typename Slots>
+    __device__ static inline void issue_stage_conv(const GemmArgs& g, const i32x4_t& ra, const i32x4_t& rb,
+                                                   const int* voff_a, Slots& rs, int64_t k0, uint8_t* stage,
+                                                   int wave) {
+        const int sa = __builtin_amdgcn_readfirstlane((int)(k0 * ES));
+        const uint32_t base = (uint32_t)(uintptr_t)(__attribute__((address_space(3))) uint8_t*)stage;
+#pragma unroll
+        for (int i = 0; i < NA; ++i) {
+            const int slab = wave + i * NW;
+            dma_load16(__builtin_amdgcn_readfirstlane(base + slab * 1024), voff_a[i], ra, sa);
+        }
+#pragma unroll
+        for (int i = 0; i < NB; ++i) {
+            const int slab = wave + i * NW;
+            int off = 0x7FFFFFF0;
+            if (rs.p_ok[i]) {
+                const int ih = rs.p_ih0[i] + rs.k_kh[i], iw = rs.p_iw0[i] + rs.k_kw[i];
+                if ((unsigned)ih < (unsigned)g.ch && (unsigned)iw < (unsigned)g.cw)
+                    off = (int)(((rs.p_img[i] + (int64_t)ih * g.cw + iw) * g.cc + rs.k_ci[i]) * ES);
+            }
+            dma_load16(__builtin_amdgcn_readfirstlane(base + A_STAGE + slab * 1024), off, rb, 0);
+            rs.k_ci[i] += BK;
+            while (rs.k_ci[i] >= g.cc) {
+                rs.k_ci[i] -= g.cc;
+                if (++rs.k_kw[i] == g.ckw) {
+                    rs.k_kw[i] = 0;
+                    ++rs.k_kh[i];
+                }
+            }
         }
     }
 
@@ -393,7 +430,12 @@ struct FastGemm {
         u4_t qa[NA], qb[NB], qa2[NA], qb2[NB];
         if constexpr (!REG) {
             ra = make_rsrc(g.A, (uint32_t)(((g.M - 1) * g.lda + g.K) * ES));
-            rb = make_rsrc(g.B, (uint32_t)(((g.K - 1) * g.ldb + g.N) * ES));
+            if constexpr (CONV) {
+                rb = make_rsrc(g.B, (uint32_t)((int64_t)g.cn * g.ch * g.cw * g.cc * ES));
+                reg_slots(g, m0, n0, s_beg * BK, wave, lane, rs);
+            } else {
+                rb = make_rsrc(g.B, (uint32_t)(((g.K - 1) * g.ldb + g.N) * ES));
+            }
 #pragma unroll
             for (int i = 0; i < NA; ++i) {
                 const int slab = wave + i * NW;
@@ -405,11 +447,15 @@ struct FastGemm {
             }
 #pragma unroll
             for (int i = 0; i < NB; ++i) {
-                const int slab = wave + i * NW;
-                const int r = slab * B_ROWS_PER_SLAB + lane / B_CHUNKS;
-                const int c = (lane % B_CHUNKS) ^ fb(r);
-                const int64_t col = n0 + c * (16 / ES);
-                voff_b[i] = col < g.N ? (int)((r * g.ldb + col) * ES) : 0x7FFFFFF0;
+                if constexpr (CONV) {
+                    voff_b[i] = 0;
+                } else {
+                    const int slab = wave + i * NW;
+                    const int r = slab * B_ROWS_PER_SLAB + lane / B_CHUNKS;
+                    const int c = (lane % B_CHUNKS) ^ fb(r);
+                    const int64_t col = n0 + c * (16 / ES);
+                    voff_b[i] = col < g.N ? (int)((r * g.ldb + col) * ES) : 0x7FFFFFF0;
+                }
             }
         } else {
             reg_slots(g, m0, n0, s_beg * BK, wave, lane, rs);
@@ -424,8 +470,11 @@ struct FastGemm {
         // prologue: STAGES-1 stages in flight (direct), or stage 0 in LDS (registers)
         if constexpr (!REG) {
 #pragma unroll
-            for (int s = 0; s < STAGES - 1; ++s)
-                if (s < nk) issue_stage(ra, rb, voff_a, voff_b, (s_beg + s) * BK, g.ldb, lds + s * STAGE, wave);
+            for (int s = 0; s < STAGES - 1; ++s) {
+                if (s >= nk) continue;
+                if constexpr (CONV) issue_stage_conv(g, ra, rb, voff_a, rs, (s_beg + s) * BK, lds + s * STAGE, wave);
+                else issue_stage(ra, rb, voff_a, voff_b, (s_beg + s) * BK, g.ldb, lds + s * STAGE, wave);
+            }
         } else {
             if (nk > 0) {
                 reg_load(g, rs, s_beg * BK, qa, qb);
@@ -515,9 +564,12 @@ struct FastGemm {
                 asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
                 const uint8_t* sa = lds + (it % NBUF) * STAGE;
                 mma_stage(sa, sa + A_STAGE, acc, wy, wx, lr, lg, [&] {
-                    if (it + STAGES - 1 < nk)
-                        issue_stage(ra, rb, voff_a, voff_b, (s_beg + it + STAGES - 1) * BK, g.ldb,
-                                    lds + ((it + STAGES - 1) % STAGES) * STAGE, wave);
+                    if (it + STAGES - 1 >= nk) return;
+                    uint8_t* dst = lds + ((it + STAGES - 1) % STAGES) * STAGE;
+                    if constexpr (CONV)
+                        issue_stage_conv(g, ra, rb, voff_a, rs, (s_beg + it + STAGES - 1) * BK, dst, wave);
+                    else
+                        issue_stage(ra, rb, voff_a, voff_b, (s_beg + it + STAGES - 1) * BK, g.ldb, dst, wave);
                 });
             }
         } else {

@@ -28,7 +28,8 @@ struct Shape {
     int conv = 0;
     int64_t M = 0, N = 0, K = 0;
     int accumulate = 1;
-    int64_t conv_c = 0;  // conv: input channels
+    int64_t conv_c = 0;   // conv: input channels
+    int64_t conv_in = 0;  // conv: input elements N*C*H*W
 };
 
 // registry of compiled kernels

@@ -25,10 +25,16 @@ const KernelEntry* kernels_fast(int* n) {
         MLK_ENTRY_FAST(DT_F8, 128, 128, 2, 2, 2),
         MLK_ENTRY_FAST(DT_F8, 128, 128, 2, 2, 1),
         // channels-last implicit-GEMM convolution (bf16, C a multiple of 8)
-        MLK_ENTRY_FASTCONV(DT_BF16, 128, 128, 2, 2),
-        MLK_ENTRY_FASTCONV(DT_BF16, 64, 128, 2, 2),
-        MLK_ENTRY_FASTCONV(DT_BF16, 128, 256, 2, 2),
-        MLK_ENTRY_FASTCONV(DT_BF16, 256, 128, 2, 2),
+        MLK_ENTRY_FASTCONV(DT_BF16, 128, 128, 2, 2, 1),
+        MLK_ENTRY_FASTCONV(DT_BF16, 64, 128, 2, 2, 1),
+        MLK_ENTRY_FASTCONV(DT_BF16, 128, 256, 2, 2, 1),
+        MLK_ENTRY_FASTCONV(DT_BF16, 256, 128, 2, 2, 1),
+        // the same gather issued as direct-to-LDS copies: C * KH * KW a multiple of 64
+        MLK_ENTRY_FASTCONV(DT_BF16, 64, 128, 2, 2, 3),
+        MLK_ENTRY_FASTCONV(DT_BF16, 64, 128, 2, 2, 4),
+        MLK_ENTRY_FASTCONV(DT_BF16, 128, 128, 2, 2, 3),
+        MLK_ENTRY_FASTCONV(DT_BF16, 128, 128, 2, 2, 4),
+        MLK_ENTRY_FASTCONV(DT_BF16, 256, 128, 2, 2, 3),
     };
     *n = (int)(sizeof(t) / sizeof(t[0]));
     return t;

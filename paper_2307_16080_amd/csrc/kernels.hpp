@@ -98,18 +98,18 @@ __global__ __launch_bounds__(64 * WM * WN) void k_gemm_fast(GemmArgs g) {
 }
 
 // The channels-last implicit-GEMM convolution form of the direct-layout kernel.
-template <int DT, int BM, int BN, int WM, int WN>
+template <int DT, int BM, int BN, int WM, int WN, int STAGES>
 __global__ __launch_bounds__(64 * WM * WN) void k_fast_conv(GemmArgs g) {
-    typedef FastGemm<DT, BM, BN, WM, WN, 1, 2> TL;
+    typedef FastGemm<DT, BM, BN, WM, WN, STAGES, 2> TL;
     __shared__ __attribute__((aligned(1024))) uint8_t lds[TL::LDS_BYTES];
     int tm, tn, kz;
     tile_coords(g, blockIdx.x, gridDim.x, tm, tn, kz);
     TL::run(g, tm, tn, kz, lds);
 }
 
-template <int DT, int BM, int BN, int WM, int WN>
+template <int DT, int BM, int BN, int WM, int WN, int STAGES>
 hipError_t launch_fast_conv(const GemmArgs& g, int nblk, hipStream_t s) {
-    hipLaunchKernelGGL((k_fast_conv<DT, BM, BN, WM, WN>), dim3(nblk), dim3(64 * WM * WN), 0, s, g);
+    hipLaunchKernelGGL((k_fast_conv<DT, BM, BN, WM, WN, STAGES>), dim3(nblk), dim3(64 * WM * WN), 0, s, g);
     return hipGetLastError();
 }
 
@@ -205,11 +205,11 @@ hipError_t launch_persist(const GemmArgs* gemms, const Task* tasks, const int32_
     }
 
 // conv entry: channels-last layout only (launch_nhwc); no NCHW form, no persistent form
-#define MLK_ENTRY_FASTCONV(DT, BM, BN, WM, WN)                                               \
+#define MLK_ENTRY_FASTCONV(DT, BM, BN, WM, WN, STAGES)                                       \
     KernelEntry {                                                                            \
-        DT, 1, 1, BM, BN, FastGemm<DT, BM, BN, WM, WN, 1, 2>::BK, WM, WN,                    \
-            FastGemm<DT, BM, BN, WM, WN, 1, 2>::LDS_BYTES, 64 * (WM) * (WN), nullptr,        \
-            nullptr, &launch_fast_conv<DT, BM, BN, WM, WN>, nullptr                          \
+        DT, 1, STAGES, BM, BN, FastGemm<DT, BM, BN, WM, WN, STAGES, 2>::BK, WM, WN,          \
+            FastGemm<DT, BM, BN, WM, WN, STAGES, 2>::LDS_BYTES, 64 * (WM) * (WN), nullptr,   \
+            nullptr, &launch_fast_conv<DT, BM, BN, WM, WN, STAGES>, nullptr                  \
     }
 
 // Tables defined by the instantiation units (host functions: the tables hold

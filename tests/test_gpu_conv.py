@@ -124,6 +124,45 @@ def test_fast_conv_tiles(cfg):
             assert np.array_equal(host(y).astype(np.float64), oracle.conv2d_f64(x, w, (s, s), (p, p))), (case, acc)
 
 
+FAST_CONV_DMA = [c for c in all_tiles(L.MLK_BF16, L.MLK_F32, conv=True) if c.stages >= 2]
+# channels-last shapes with C*KH*KW a multiple of the 64-deep stage: C below,
+# equal to and above the stage (several taps per stage, one tap, one tap over
+# several stages), strides, padding, ragged F and pixels, tiles across images
+DMA_CASES = [
+    (1, 8, 16, 16, 5, 4, 2, 1, 0),
+    (2, 16, 9, 9, 33, 2, 2, 1, 1),
+    (2, 64, 14, 14, 65, 3, 3, 1, 1),
+    (3, 64, 13, 11, 40, 3, 3, 2, 1),
+    (1, 128, 16, 16, 64, 1, 1, 1, 0),
+    (4, 128, 7, 7, 130, 3, 3, 1, 1),
+]
+
+
+@pytest.mark.parametrize("cfg", FAST_CONV_DMA, ids=lambda c: f"{c.bm}x{c.bn}x{c.bk}_{c.wm}{c.wn}_s{c.stages}")
+def test_fast_conv_dma_tiles(cfg):
+    assert cfg.layout == 1 and FAST_CONV_DMA
+    # depth not a multiple of the stage: refused
+    assert not mlk.config_legal(mlk.conv_problem(1, 24, 8, 8, 16, 3, 3, 1, 1, L.MLK_BF16, L.MLK_F32), cfg)
+    for case in DMA_CASES:
+        N, C, H, W, F, KH, KW, s, p = case
+        say("dma conv", cfg, case)
+        x, w = conv_inputs(N, C, H, W, F, KH, KW, seed=sum(case) + 7)
+        ho, wo = (H + 2 * p - KH) // s + 1, (W + 2 * p - KW) // s + 1
+        y0 = np.random.default_rng(3).uniform(-1, 1, (N, F, ho, wo)).astype(np.float32)
+        qx, qw = oracle.bf16_encode(x), oracle.bf16_encode(w)
+        ref = oracle.conv2d_f64(oracle.bf16_decode(qx), oracle.bf16_decode(qw), (s, s), (p, p), y=y0)
+        y = dev(y0)
+        mlk.conv2d_nchw_fchw(from_bf16_codes(qx), from_bf16_codes(qw), y, (s, s), (p, p), cfg=cfg)
+        assert normwise(host(y), ref) <= 1e-5, case
+        x, w = conv_inputs(N, C, H, W, F, KH, KW, seed=5, dist="small_int")
+        for acc in (True, False):
+            y = torch.full((N, F, ho, wo), float("nan"), device="cuda") if not acc else \
+                torch.zeros(N, F, ho, wo, device="cuda")
+            mlk.conv2d_nchw_fchw(from_bf16_codes(oracle.bf16_encode(x)), from_bf16_codes(oracle.bf16_encode(w)),
+                                 y, (s, s), (p, p), cfg=cfg, accumulate=acc)
+            assert np.array_equal(host(y).astype(np.float64), oracle.conv2d_f64(x, w, (s, s), (p, p))), (case, acc)
+
+
 def test_conv_split_k_overwrite():
     x, w = conv_inputs(1, 64, 14, 14, 32, 3, 3, seed=4, dist="small_int")
     ref = oracle.conv2d_f64(x, w, (1, 1), (1, 1))
