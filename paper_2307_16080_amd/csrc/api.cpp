@@ -496,9 +496,9 @@ mlk_status launch_conv(const Shape& s, int64_t n, int64_t c, int64_t h, int64_t 
     }
     const int64_t nblk = (int64_t)g.tiles_m * g.tiles_n * g.split_k;
     // Channels-last route: with C a multiple of the 16-byte vector, transpose
-    // x to NHWC and the filter to F x KH x KW x C in a stream-ordered
-    // workspace, so every operand load of the tile kernel is one aligned
-    // 16-byte read.
+    // x to NHWC and the filter to F x KH x KW x C in the library's scratch
+    // buffer, so every operand load of the tile kernel is one aligned 16-byte
+    // read.
     if (cfg.layout == 1) {
         const size_t xb = ((size_t)(n * c * h * w) * es + 255) & ~(size_t)255;
         const size_t wb = (size_t)(f * c * kh * kw) * es;
@@ -507,9 +507,13 @@ mlk_status launch_conv(const Shape& s, int64_t n, int64_t c, int64_t h, int64_t 
         hipError_t err = hipSuccess;
         uint8_t* xn = (uint8_t*)scratch.ptr();
         uint8_t* wn = xn + xb;
-        if ((err = launch_transpose_batched(x, xn, n, c, h * w, es, st)) == hipSuccess &&
-            (err = launch_transpose_batched(wt, wn, f, c, kh * kw, es, st)) == hipSuccess) {
-            g.A = wn;
+        // a 1 x 1 filter is already F x C; otherwise FCHW -> F x KH x KW x C
+        // in the same launch as the input
+        const bool w_as_is = kh * kw == 1;
+        if ((err = launch_transpose_pair(x, xn, n, c, h * w, wt, wn, w_as_is ? 0 : f, c, kh * kw, es, st)) ==
+            hipSuccess) {
+            if (!w_as_is) wt = wn;
+            g.A = wt;
             g.B = xn;
             g.vec_a = 1;
             err = e->launch_nhwc(g, (int)nblk, st);

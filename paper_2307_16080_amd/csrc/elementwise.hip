@@ -329,16 +329,14 @@ __global__ __launch_bounds__(kThreads) void k_pack_pair(PackPair pp) {
 
 // ------------------------------------------------------------------ layout transform
 
-// out[b][c][r] = in[b][r][c] for a batch of rows x cols matrices, through a
-// 32 x 32 LDS tile (one padding column keeps the column reads conflict-free).
+// out[b][c][r] = in[b][r][c] for a batch of rows x cols matrices.  One tile
+// of one batch entry per workgroup.  Generic form: a 32 x 32 LDS tile (one
+// padding column keeps the column reads conflict-free).
 template <typename T>
-__global__ __launch_bounds__(256) void k_transpose(const T* __restrict__ in, T* __restrict__ out,
-                                                   int64_t rows, int64_t cols) {
-    __shared__ T tile[32][33];
-    const int64_t b = blockIdx.z;
-    const T* src = in + b * rows * cols;
-    T* dst = out + b * rows * cols;
-    const int64_t c0 = (int64_t)blockIdx.x * 32, r0 = (int64_t)blockIdx.y * 32;
+__device__ inline void transpose_tile32(const T* __restrict__ src, T* __restrict__ dst, int64_t rows,
+                                        int64_t cols, int64_t bx, int64_t by, uint8_t* lds) {
+    T (*tile)[33] = (T (*)[33])lds;
+    const int64_t c0 = bx * 32, r0 = by * 32;
     const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
     for (int i = ty; i < 32; i += 8) {
         const int64_t r = r0 + i, c = c0 + tx;
@@ -355,14 +353,10 @@ __global__ __launch_bounds__(256) void k_transpose(const T* __restrict__ in, T* 
 // sides): 64 x 64 tiles, 16-byte loads along the input rows and 16-byte stores
 // along the output rows; the LDS tile row pitch (144 bytes) keeps the column
 // gathers of the transposed read on distinct banks.
-__global__ __launch_bounds__(256) void k_transpose16(const uint16_t* __restrict__ in,
-                                                     uint16_t* __restrict__ out, int64_t rows,
-                                                     int64_t cols) {
-    __shared__ __attribute__((aligned(16))) uint16_t tile[64][72];
-    const int64_t b = blockIdx.z;
-    const uint16_t* src = in + b * rows * cols;
-    uint16_t* dst = out + b * rows * cols;
-    const int64_t c0 = (int64_t)blockIdx.x * 64, r0 = (int64_t)blockIdx.y * 64;
+__device__ inline void transpose_tile64_16(const uint16_t* __restrict__ src, uint16_t* __restrict__ dst,
+                                           int64_t rows, int64_t cols, int64_t bx, int64_t by, uint8_t* lds) {
+    uint16_t (*tile)[72] = (uint16_t (*)[72])lds;
+    const int64_t c0 = bx * 64, r0 = by * 64;
 #pragma unroll
     for (int i = 0; i < 2; ++i) {
         const int k = threadIdx.x + 256 * i;
@@ -384,6 +378,38 @@ __global__ __launch_bounds__(256) void k_transpose16(const uint16_t* __restrict_
             *(u4_t*)(dst + (c0 + oc) * rows + r0 + rc) = v;
         }
     }
+}
+
+// One batched transpose: tiles x-major, then y, then batch entry.
+struct TransposeJob {
+    const void* in;
+    void* out;
+    int64_t rows, cols;
+    int64_t tiles_x, tiles_y;
+    int64_t blocks;  // tiles_x * tiles_y * batch
+    int wide;        // 2-byte elements in the 64 x 64 16-byte form
+};
+
+// Two batched transposes in one launch (the conv's input and filter to
+// channels-last): workgroups [0, j0.blocks) take the first job, the rest the
+// second.  The job choice is uniform per workgroup.
+template <typename T>
+__global__ __launch_bounds__(256) void k_transpose_pair(TransposeJob j0, TransposeJob j1) {
+    __shared__ __attribute__((aligned(16))) uint8_t lds[64 * 72 * 2 > 32 * 33 * sizeof(T) ? 64 * 72 * 2
+                                                                                           : 32 * 33 * sizeof(T)];
+    int64_t id = blockIdx.x;
+    const bool second = id >= j0.blocks;
+    const TransposeJob j = second ? j1 : j0;
+    if (second) id -= j0.blocks;
+    const int64_t bx = id % j.tiles_x, by = (id / j.tiles_x) % j.tiles_y, bz = id / (j.tiles_x * j.tiles_y);
+    const int64_t off = bz * j.rows * j.cols;
+    if constexpr (sizeof(T) == 2) {
+        if (j.wide) {
+            transpose_tile64_16((const uint16_t*)j.in + off, (uint16_t*)j.out + off, j.rows, j.cols, bx, by, lds);
+            return;
+        }
+    }
+    transpose_tile32<T>((const T*)j.in + off, (T*)j.out + off, j.rows, j.cols, bx, by, lds);
 }
 
 // ------------------------------------------------------------------ error statistics
@@ -483,25 +509,33 @@ hipError_t launch_quant_e4m3(const float* x, int64_t n, uint8_t* q, float* scale
     return hipGetLastError();
 }
 
-hipError_t launch_transpose_batched(const void* in, void* out, int64_t batch, int64_t rows,
-                                    int64_t cols, int esize, hipStream_t s) {
-    if (batch <= 0 || rows <= 0 || cols <= 0) return hipSuccess;
-    if (batch > 65535 || (rows + 31) / 32 > 65535) return hipErrorInvalidValue;
-    const dim3 grid((unsigned)((cols + 31) / 32), (unsigned)((rows + 31) / 32), (unsigned)batch);
+static TransposeJob transpose_job(const void* in, void* out, int64_t batch, int64_t rows, int64_t cols,
+                                  int esize) {
+    TransposeJob j{in, out, rows, cols, 0, 0, 0, 0};
+    if (batch <= 0 || rows <= 0 || cols <= 0) return j;
+    j.wide = esize == 2 && rows % 8 == 0 && cols % 8 == 0 && (uintptr_t)in % 16 == 0 && (uintptr_t)out % 16 == 0;
+    const int t = j.wide ? 64 : 32;
+    j.tiles_x = (cols + t - 1) / t;
+    j.tiles_y = (rows + t - 1) / t;
+    j.blocks = j.tiles_x * j.tiles_y * batch;
+    return j;
+}
+
+hipError_t launch_transpose_pair(const void* in0, void* out0, int64_t batch0, int64_t rows0, int64_t cols0,
+                                 const void* in1, void* out1, int64_t batch1, int64_t rows1, int64_t cols1,
+                                 int esize, hipStream_t s) {
+    const TransposeJob j0 = transpose_job(in0, out0, batch0, rows0, cols0, esize);
+    const TransposeJob j1 = transpose_job(in1, out1, batch1, rows1, cols1, esize);
+    const int64_t blocks = j0.blocks + j1.blocks;
+    if (blocks == 0) return hipSuccess;
+    if (blocks > 0x7FFFFFFF) return hipErrorInvalidValue;
+    const dim3 grid((unsigned)blocks);
     if (esize == 4)
-        hipLaunchKernelGGL(k_transpose<uint32_t>, grid, dim3(256), 0, s, (const uint32_t*)in,
-                           (uint32_t*)out, rows, cols);
-    else if (esize == 2 && rows % 8 == 0 && cols % 8 == 0 && (uintptr_t)in % 16 == 0 &&
-             (uintptr_t)out % 16 == 0 && batch <= 65535)
-        hipLaunchKernelGGL(k_transpose16, dim3((unsigned)((cols + 63) / 64), (unsigned)((rows + 63) / 64),
-                                               (unsigned)batch),
-                           dim3(256), 0, s, (const uint16_t*)in, (uint16_t*)out, rows, cols);
+        hipLaunchKernelGGL(k_transpose_pair<uint32_t>, grid, dim3(256), 0, s, j0, j1);
     else if (esize == 2)
-        hipLaunchKernelGGL(k_transpose<uint16_t>, grid, dim3(256), 0, s, (const uint16_t*)in,
-                           (uint16_t*)out, rows, cols);
+        hipLaunchKernelGGL(k_transpose_pair<uint16_t>, grid, dim3(256), 0, s, j0, j1);
     else
-        hipLaunchKernelGGL(k_transpose<uint8_t>, grid, dim3(256), 0, s, (const uint8_t*)in,
-                           (uint8_t*)out, rows, cols);
+        hipLaunchKernelGGL(k_transpose_pair<uint8_t>, grid, dim3(256), 0, s, j0, j1);
     return hipGetLastError();
 }
 

@@ -35,6 +35,8 @@ const KernelEntry* kernels_fast(int* n) {
         MLK_ENTRY_FASTCONV(DT_BF16, 128, 128, 2, 2, 3),
         MLK_ENTRY_FASTCONV(DT_BF16, 128, 128, 2, 2, 4),
         MLK_ENTRY_FASTCONV(DT_BF16, 256, 128, 2, 2, 3),
+        MLK_ENTRY_FASTCONV(DT_BF16, 64, 256, 2, 2, 3),   // few filters, many pixels
+        MLK_ENTRY_FASTCONV(DT_BF16, 128, 256, 2, 2, 3),
     };
     *n = (int)(sizeof(t) / sizeof(t[0]));
     return t;

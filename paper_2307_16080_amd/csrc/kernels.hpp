@@ -243,9 +243,11 @@ hipError_t launch_pack(const PackJob* jobs, const int64_t* seg_start, int njobs,
                        int esize, hipStream_t s);
 // the same for one or two jobs given in host memory (passed by value)
 hipError_t launch_pack_pair(const PackJob* jobs, int njobs, int esize, hipStream_t s);
-// batch of [rows x cols] matrices -> [cols x rows] (NCHW -> NHWC, FCHW -> FHWC)
-hipError_t launch_transpose_batched(const void* in, void* out, int64_t batch, int64_t rows,
-                                    int64_t cols, int esize, hipStream_t s);
+// two batches of [rows x cols] matrices -> [cols x rows] in one launch
+// (NCHW -> NHWC and FCHW -> FHWC); a job with batch 0 is skipped
+hipError_t launch_transpose_pair(const void* in0, void* out0, int64_t batch0, int64_t rows0, int64_t cols0,
+                                 const void* in1, void* out1, int64_t batch1, int64_t rows1, int64_t cols1,
+                                 int esize, hipStream_t s);
 hipError_t launch_mlp_forward(int64_t B, int64_t D0, int64_t H1, int64_t H2, const float* p,
                               const float* X, float* y, hipStream_t s);
 hipError_t launch_mlp_loss_grad(int64_t B, int64_t D0, int64_t H1, int64_t H2, const float* p,
