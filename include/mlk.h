@@ -29,7 +29,8 @@
  *    message.
  *  - Scratch memory: the routes that need a workspace (a direct-to-LDS
  *    matmul tile whose operands need zero-padded copies, the channels-last
- *    conv layout, e4m3 quantisation) use one library-owned buffer per device,
+ *    conv layout, e4m3 quantisation, the error statistics and the MLP
+ *    kernels' activations) use one library-owned buffer per device,
  *    grown on demand up to 512 MiB and held until mlk_release(); larger
  *    requests take a stream-ordered allocation of their own for the call.
  *    Uses of the buffer are ordered on the device with an event, whatever
@@ -90,18 +91,22 @@ typedef enum {
  *   stages     0: register-staged kernel (operands pass through registers
  *              on their way to a double-buffered LDS tile; any shape and
  *              alignment).  2..5: direct-to-LDS kernel (bf16, e4m3) whose
- *              loads go from HBM straight into a ring of `stages` LDS
- *              buffers; needs K % bk == 0, 16-byte aligned A and B and row
- *              pitches that are multiples of 16 bytes.  1: the same kernel
- *              with its operands loaded through registers into two LDS
- *              buffers (bf16, e4m3): any shape and alignment, and usable by
- *              the persistent batched launch.
+ *              loads go from memory straight into a ring of `stages` LDS
+ *              buffers; matmul operands without 16-byte rows, or with K not
+ *              a multiple of bk, are first copied into zero-padded buffers
+ *              (library scratch memory); the bf16 conv tiles of this form
+ *              (channels-last layout) need C*KH*KW a multiple of bk.  1: the
+ *              same kernel with its operands loaded through registers into
+ *              two LDS buffers (bf16, e4m3; bf16 channels-last conv): any
+ *              shape and alignment, and usable by the persistent batched
+ *              launch.
  *   layout     conv2d only.  0: the kernel gathers its operands straight from
  *              the NCHW input (any C).  1: the input is first transposed to
- *              channels-last (NHWC) and the filter to F x KH x KW x C in a
- *              stream-ordered workspace, so every operand load is one aligned
- *              16-byte read; needs C a multiple of 8 (bf16) or 4 (fp32) and
- *              16-byte aligned x and w.  Must be 0 for matmul.
+ *              channels-last (NHWC) and the filter to F x KH x KW x C in the
+ *              library's scratch memory (one launch for both), so every
+ *              operand load is one aligned 16-byte read; needs C a multiple
+ *              of 8 (bf16) or 4 (fp32) and 16-byte aligned x and w.  Must be
+ *              0 for matmul.
  * A zeroed struct or a NULL pointer means "choose": the tuning database
  * entry for this problem if one was loaded, else a built-in heuristic.
  */

@@ -383,15 +383,15 @@ static mlk_status run_gemm(const KernelEntry* e, GemmArgs& g, const Shape& s, vo
     return MLK_OK;
 }
 
-// Routes with a stream-ordered workspace are refused on a capturing stream:
-// the library does not record allocation nodes into a caller's graph.
+// Routes that use the library's scratch memory are refused on a capturing
+// stream (checked before anything is enqueued).
 static mlk_status refuse_under_capture(hipStream_t st, const char* what) {
     hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
     const hipError_t e = hipStreamIsCapturing(st, &cs);
     if (e != hipSuccess) return hip_fail(e, "hipStreamIsCapturing");
     if (cs != hipStreamCaptureStatusNone)
-        return fail(MLK_ERR_CONFIG, "%s takes a stream-ordered workspace, which is not recorded into a captured "
-                    "graph; choose a configuration without one", what);
+        return fail(MLK_ERR_CONFIG, "%s needs library scratch memory, which is not used under stream capture; "
+                    "choose a configuration without it", what);
     return MLK_OK;
 }
 
@@ -417,7 +417,7 @@ mlk_status launch_dense(const Shape& s, const void* A, int64_t lda, const void* 
     // Direct-to-LDS tile: an operand without 16-byte rows, or with K not a
     // multiple of the stage depth, is first copied into a zero-padded buffer
     // (A as M x Kp, B as Kp x Np; Kp = K rounded up to the stage depth, Np = N
-    // rounded up to 16 bytes) in a stream-ordered workspace.
+    // rounded up to 16 bytes) in the library's scratch buffer.
     const bool kfit = s.K % e->bk == 0;
     const bool pa = !(g.vec_a && kfit), pb = !(g.vec_b && kfit);
     const int64_t Kp = cdiv(s.K, e->bk) * e->bk, Np = cdiv(s.N, 16 / es) * (16 / es);
@@ -674,9 +674,14 @@ mlk_status mlk_err_stats(mlk_dtype c_dtype, int64_t n, const void* c, const doub
         return fail(MLK_ERR_DTYPE, "err_stats: c must be MLK_F32 or MLK_I32");
     if (n < 0) return fail(MLK_ERR_SHAPE, "err_stats: n < 0");
     if (!out || (n > 0 && (!c || !r))) return fail(MLK_ERR_NULL, "err_stats: NULL pointer");
-    hipError_t e = launch_err_stats(c_dtype == MLK_I32, n, c, r, bound, out, (hipStream_t)stream);
+    const hipStream_t st = (hipStream_t)stream;
+    ScratchUse scratch;
+    if (mlk_status rc = scratch.begin(sizeof(double) * 4 * err_stats_parts(), st, "err_stats"); rc != MLK_OK)
+        return rc;
+    const hipError_t e = launch_err_stats(c_dtype == MLK_I32, n, c, r, bound, out, (double*)scratch.ptr(), st);
+    const mlk_status rel = scratch.end();
     if (e != hipSuccess) return hip_fail(e, "err_stats launch");
-    return MLK_OK;
+    return rel;
 }
 
 mlk_status mlk_mlp_forward(int64_t B, int64_t D0, int64_t H1, int64_t H2, const float* params,
@@ -685,9 +690,15 @@ mlk_status mlk_mlp_forward(int64_t B, int64_t D0, int64_t H1, int64_t H2, const 
     if (B < 0 || D0 < 1 || H1 < 1 || H2 < 1 || D0 > 4096 || H1 > 4096 || H2 > 4096)
         return fail(MLK_ERR_SHAPE, "mlp: bad sizes");
     if (B > 0 && (!params || !X || !y)) return fail(MLK_ERR_NULL, "mlp: NULL pointer");
-    hipError_t e = launch_mlp_forward(B, D0, H1, H2, params, X, y, (hipStream_t)stream);
+    if (B == 0) return MLK_OK;
+    const hipStream_t st = (hipStream_t)stream;
+    ScratchUse scratch;
+    if (mlk_status rc = scratch.begin(sizeof(float) * mlp_forward_words(B, H1, H2), st, "mlp forward"); rc != MLK_OK)
+        return rc;
+    const hipError_t e = launch_mlp_forward(B, D0, H1, H2, params, X, y, (float*)scratch.ptr(), st);
+    const mlk_status rel = scratch.end();
     if (e != hipSuccess) return hip_fail(e, "mlp forward");
-    return MLK_OK;
+    return rel;
 }
 
 mlk_status mlk_mlp_loss_grad(int64_t B, int64_t D0, int64_t H1, int64_t H2,
@@ -697,9 +708,15 @@ mlk_status mlk_mlp_loss_grad(int64_t B, int64_t D0, int64_t H1, int64_t H2,
     if (B < 1 || D0 < 1 || H1 < 1 || H2 < 1 || D0 > 4096 || H1 > 4096 || H2 > 4096)
         return fail(MLK_ERR_SHAPE, "mlp: bad sizes");
     if (!params || !X || !t || !grad || !loss) return fail(MLK_ERR_NULL, "mlp: NULL pointer");
-    hipError_t e = launch_mlp_loss_grad(B, D0, H1, H2, params, X, t, grad, loss, (hipStream_t)stream);
+    const hipStream_t st = (hipStream_t)stream;
+    ScratchUse scratch;
+    if (mlk_status rc = scratch.begin(sizeof(float) * mlp_loss_grad_words(B, H1, H2), st, "mlp loss/grad");
+        rc != MLK_OK)
+        return rc;
+    const hipError_t e = launch_mlp_loss_grad(B, D0, H1, H2, params, X, t, grad, loss, (float*)scratch.ptr(), st);
+    const mlk_status rel = scratch.end();
     if (e != hipSuccess) return hip_fail(e, "mlp loss/grad");
-    return MLK_OK;
+    return rel;
 }
 
 mlk_status mlk_adam_step(int64_t n, float* params, const float* grad, float* m, float* v,

@@ -414,7 +414,7 @@ __global__ __launch_bounds__(256) void k_transpose_pair(TransposeJob j0, Transpo
 
 // ------------------------------------------------------------------ error statistics
 
-constexpr int kErrBlocks = 1024;
+constexpr int kErrBlocks = err_stats_parts();
 
 // per-block partials: [sum d^2, sum r^2, max |d|, max |d|/bound]
 __global__ __launch_bounds__(kThreads) void k_err_partial(int c_is_int, int64_t n,
@@ -576,16 +576,11 @@ hipError_t launch_fill_random(void* p, int64_t n, int dt, uint64_t seed, hipStre
 }
 
 hipError_t launch_err_stats(int c_is_int, int64_t n, const void* c, const double* r,
-                            const double* bound, double* out, hipStream_t s) {
-    double* part = nullptr;
-    hipError_t e = hipMallocAsync((void**)&part, sizeof(double) * 4 * kErrBlocks, s);
-    if (e != hipSuccess) return e;
+                            const double* bound, double* out, double* part, hipStream_t s) {
     hipLaunchKernelGGL(k_err_partial, dim3(kErrBlocks), dim3(kThreads), 0, s, c_is_int, n, c, r,
                        bound, part);
     hipLaunchKernelGGL(k_err_final, dim3(1), dim3(64), 0, s, (const double*)part, kErrBlocks, out);
-    e = hipGetLastError();
-    hipError_t e2 = hipFreeAsync(part, s);
-    return e != hipSuccess ? e : e2;
+    return hipGetLastError();
 }
 
 }  // namespace mlk

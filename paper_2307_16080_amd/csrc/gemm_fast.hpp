@@ -77,11 +77,12 @@ __device__ inline void wait_vmcnt() {
 // this one streams 181 B/clk/CU, the plain layout 59).
 __device__ inline int fa(int r) { return (r & 7) ^ ((r >> 2) & 2); }
 
-// CONV = 2: the channels-last implicit-GEMM convolution (register-loaded form
-// only): A is the filter as F x (KH*KW*C), C contiguous; B is never formed:
-// its transpose -- one row per output pixel n = (img, oh, ow), columns k =
-// (kh, kw, c) -- is gathered from the NHWC input in 16-byte chunks of 8
-// channels (C a multiple of 8) and kept in LDS like A (rows of BK k), so the
+// CONV = 2: the channels-last implicit-GEMM convolution (bf16): A is the
+// filter as F x (KH*KW*C), C contiguous; B is never formed: its transpose --
+// one row per output pixel n = (img, oh, ow), columns k = (kh, kw, c) -- is
+// gathered from the NHWC input in 16-byte chunks of 8 channels (C a multiple
+// of 8), through registers (STAGES = 1) or as direct-to-LDS copies (STAGES >=
+// 2, C*KH*KW a multiple of BK), and kept in LDS like A (rows of BK k), so the
 // MFMA's B operand is read as A's is.  The output is NFHW.
 template <int DT, int BM, int BN, int WM, int WN, int STAGES, int CONV = 0>
 struct FastGemm {

@@ -229,8 +229,10 @@ hipError_t launch_quant_bf16(const float* x, int64_t n, uint16_t* q, hipStream_t
 constexpr int quant_e4m3_parts() { return 512; }
 hipError_t launch_quant_e4m3(const float* x, int64_t n, uint8_t* q, float* scale, float* part,
                              hipStream_t s);
+// `part`: device workspace of err_stats_parts() x 4 doubles (per-workgroup partials)
+constexpr int err_stats_parts() { return 1024; }
 hipError_t launch_err_stats(int c_is_int, int64_t n, const void* c, const double* r,
-                            const double* bound, double* out, hipStream_t s);
+                            const double* bound, double* out, double* part, hipStream_t s);
 hipError_t launch_fill_random(void* p, int64_t n, int dt, uint64_t seed, hipStream_t s);
 // copy operands into zero-padded buffers, one wave per segment of kPackSeg
 // consecutive destination elements; seg_start[j] = first segment of job j in
@@ -248,10 +250,14 @@ hipError_t launch_pack_pair(const PackJob* jobs, int njobs, int esize, hipStream
 hipError_t launch_transpose_pair(const void* in0, void* out0, int64_t batch0, int64_t rows0, int64_t cols0,
                                  const void* in1, void* out1, int64_t batch1, int64_t rows1, int64_t cols1,
                                  int esize, hipStream_t s);
+// `ws`: device workspace of mlp_forward_words() / mlp_loss_grad_words() floats
+// (the hidden activations, pre-activations and deltas of the batch)
+inline int64_t mlp_forward_words(int64_t B, int64_t H1, int64_t H2) { return B * (H1 + H2); }
+inline int64_t mlp_loss_grad_words(int64_t B, int64_t H1, int64_t H2) { return B * (3 * H1 + 3 * H2 + 2); }
 hipError_t launch_mlp_forward(int64_t B, int64_t D0, int64_t H1, int64_t H2, const float* p,
-                              const float* X, float* y, hipStream_t s);
+                              const float* X, float* y, float* ws, hipStream_t s);
 hipError_t launch_mlp_loss_grad(int64_t B, int64_t D0, int64_t H1, int64_t H2, const float* p,
-                                const float* X, const float* t, float* grad, float* loss,
+                                const float* X, const float* t, float* grad, float* loss, float* ws,
                                 hipStream_t s);
 hipError_t launch_adam(int64_t n, float* p, const float* g, float* m, float* v, float lr,
                        float b1, float b2, float eps, int64_t t, hipStream_t s);

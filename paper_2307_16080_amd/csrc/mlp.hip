@@ -120,12 +120,9 @@ Offsets offsets(int64_t D0, int64_t H1, int64_t H2) {
 }  // namespace
 
 hipError_t launch_mlp_forward(int64_t B, int64_t D0, int64_t H1, int64_t H2, const float* p,
-                              const float* X, float* y, hipStream_t s) {
+                              const float* X, float* y, float* ws, hipStream_t s) {
     if (B <= 0) return hipSuccess;
     const Offsets o = offsets(D0, H1, H2);
-    float* ws = nullptr;
-    hipError_t e = hipMallocAsync((void**)&ws, sizeof(float) * B * (H1 + H2), s);
-    if (e != hipSuccess) return e;
     float* a1 = ws;
     float* a2 = ws + B * H1;
     hipLaunchKernelGGL(k_layer, dim3(blocks(B * H1)), dim3(kT), 0, s, X, B, D0, p + o.W1, p + o.b1,
@@ -135,20 +132,14 @@ hipError_t launch_mlp_forward(int64_t B, int64_t D0, int64_t H1, int64_t H2, con
     // output layer: linear, no activation
     hipLaunchKernelGGL(k_layer, dim3(blocks(B)), dim3(kT), 0, s, (const float*)a2, B, H2, p + o.W3,
                        p + o.b3, (int64_t)1, y, (float*)nullptr);
-    e = hipGetLastError();
-    hipError_t e2 = hipFreeAsync(ws, s);
-    return e != hipSuccess ? e : e2;
+    return hipGetLastError();
 }
 
 hipError_t launch_mlp_loss_grad(int64_t B, int64_t D0, int64_t H1, int64_t H2, const float* p,
-                                const float* X, const float* t, float* grad, float* loss,
+                                const float* X, const float* t, float* grad, float* loss, float* ws,
                                 hipStream_t s) {
     if (B <= 0) return hipErrorInvalidValue;
     const Offsets o = offsets(D0, H1, H2);
-    float* ws = nullptr;
-    const int64_t words = B * (3 * H1 + 3 * H2 + 2);
-    hipError_t e = hipMallocAsync((void**)&ws, sizeof(float) * words, s);
-    if (e != hipSuccess) return e;
     float* z1 = ws;
     float* a1 = z1 + B * H1;
     float* d1 = a1 + B * H1;
@@ -178,9 +169,7 @@ hipError_t launch_mlp_loss_grad(int64_t B, int64_t D0, int64_t H1, int64_t H2, c
                        (const float*)d2, H2, B, grad + o.W2, grad + o.b2);
     hipLaunchKernelGGL(k_weight_grad, dim3(blocks(D0 * H1)), dim3(kT), 0, s, X, D0,
                        (const float*)d1, H1, B, grad + o.W1, grad + o.b1);
-    e = hipGetLastError();
-    hipError_t e2 = hipFreeAsync(ws, s);
-    return e != hipSuccess ? e : e2;
+    return hipGetLastError();
 }
 
 hipError_t launch_adam(int64_t n, float* p, const float* g, float* m, float* v, float lr,

@@ -139,10 +139,19 @@ mlk_status model_predict_shape(mlk_cost_model* m, const Shape& s,
     mlk_status st = MLK_OK;
     if ((e = hipMemcpy(dX, X.data(), sizeof(float) * X.size(), hipMemcpyHostToDevice)) != hipSuccess)
         st = hip_fail(e, "predict upload");
-    else if ((e = launch_mlp_forward(n, D0, m->hidden, m->hidden, m->d_params, dX, dy, 0)) != hipSuccess)
-        st = hip_fail(e, "predict forward");
-    else if ((e = hipMemcpy(us->data(), dy, sizeof(float) * n, hipMemcpyDeviceToHost)) != hipSuccess)
-        st = hip_fail(e, "predict download");
+    else {
+        ScratchUse scratch;
+        if ((st = scratch.begin(sizeof(float) * mlp_forward_words(n, m->hidden, m->hidden), 0, "model predict")) ==
+            MLK_OK) {
+            e = launch_mlp_forward(n, D0, m->hidden, m->hidden, m->d_params, dX, dy, (float*)scratch.ptr(), 0);
+            st = scratch.end();
+            if (e != hipSuccess) st = hip_fail(e, "predict forward");
+        }
+    }
+    if (st == MLK_OK && e == hipSuccess) {
+        if ((e = hipMemcpy(us->data(), dy, sizeof(float) * n, hipMemcpyDeviceToHost)) != hipSuccess)
+            st = hip_fail(e, "predict download");
+    }
     (void)hipFree(dX);
     (void)hipFree(dy);
     if (st != MLK_OK) return st;
@@ -270,6 +279,14 @@ mlk_status mlk_model_train(mlk_cost_model* m, int32_t epochs, int32_t batch, flo
         (void)hipFree(dX);
         return hip_fail(e, "train alloc");
     }
+    // one workspace for every step (the full-batch loss at the end is the largest)
+    ScratchUse scratch;
+    if ((st = scratch.begin(sizeof(float) * mlp_loss_grad_words(n, H, H), 0, "model training")) != MLK_OK) {
+        (void)hipFree(dX);
+        (void)hipFree(dy);
+        return st;
+    }
+    float* ws = (float*)scratch.ptr();
     std::vector<int64_t> perm((size_t)n);
     std::iota(perm.begin(), perm.end(), 0);
     std::mt19937_64 rng(m->seed ^ 0xA5A5A5A5ull);
@@ -290,7 +307,7 @@ mlk_status mlk_model_train(mlk_cost_model* m, int32_t epochs, int32_t batch, flo
         for (int64_t off = 0; off < n; off += batch) {
             const int64_t B = std::min<int64_t>(batch, n - off);
             if ((e = launch_mlp_loss_grad(B, D0, H, H, m->d_params, dX + off * D0, dy + off, m->d_g,
-                                          m->d_loss, 0)) != hipSuccess ||
+                                          m->d_loss, ws, 0)) != hipSuccess ||
                 (e = launch_adam(P, m->d_params, m->d_g, m->d_m, m->d_v, lr, 0.9f, 0.999f, 1e-8f,
                                  ++m->step, 0)) != hipSuccess) {
                 st = hip_fail(e, "train step");
@@ -302,10 +319,12 @@ mlk_status mlk_model_train(mlk_cost_model* m, int32_t epochs, int32_t batch, flo
         // full-batch loss of the final parameters
         if ((e = hipMemcpy(dX, Xn.data(), sizeof(float) * Xn.size(), hipMemcpyHostToDevice)) != hipSuccess ||
             (e = hipMemcpy(dy, yn.data(), sizeof(float) * yn.size(), hipMemcpyHostToDevice)) != hipSuccess ||
-            (e = launch_mlp_loss_grad(n, D0, H, H, m->d_params, dX, dy, m->d_g, m->d_loss, 0)) != hipSuccess ||
+            (e = launch_mlp_loss_grad(n, D0, H, H, m->d_params, dX, dy, m->d_g, m->d_loss, ws, 0)) != hipSuccess ||
             (e = hipMemcpy(&loss, m->d_loss, sizeof(float), hipMemcpyDeviceToHost)) != hipSuccess)
             st = hip_fail(e, "train final loss");
     }
+    const mlk_status rel = scratch.end();
+    if (st == MLK_OK) st = rel;
     (void)hipFree(dX);
     (void)hipFree(dy);
     if (st != MLK_OK) return st;
