@@ -51,6 +51,13 @@ struct Plan {
     int device = 0;
 };
 
+void free_plan(Plan& p) {
+    if (p.exec) (void)hipGraphExecDestroy(p.exec);
+    if (p.graph) (void)hipGraphDestroy(p.graph);
+    if (p.dev) (void)hipFree(p.dev);
+    p = Plan();
+}
+
 std::mutex g_mu;
 std::map<std::string, Plan> g_plans;
 std::map<int, hipStream_t> g_capture_streams;
@@ -394,28 +401,36 @@ mlk_status mlk_batched_matmul(mlk_dtype in, mlk_dtype out, int64_t count,
             auto cs = g_capture_streams.find(dev);
             if (cs == g_capture_streams.end()) {
                 herr = hipStreamCreateWithFlags(&cap, hipStreamNonBlocking);
-                if (herr != hipSuccess) return hip_fail(herr, "capture stream");
+                if (herr != hipSuccess) {
+                    free_plan(plan);
+                    return hip_fail(herr, "capture stream");
+                }
                 g_capture_streams[dev] = cap;
             } else {
                 cap = cs->second;
             }
             herr = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
-            if (herr != hipSuccess) return hip_fail(herr, "hipStreamBeginCapture");
+            if (herr != hipSuccess) {
+                free_plan(plan);
+                return hip_fail(herr, "hipStreamBeginCapture");
+            }
             st = launch_batch(s.dt, count, descs, e, c, p.accumulate, flags, &plan, cap);
             hipGraph_t gr = nullptr;
             hipError_t endc = hipStreamEndCapture(cap, &gr);
+            plan.graph = gr;
             if (st != MLK_OK) {
-                if (gr) (void)hipGraphDestroy(gr);
-                if (plan.dev) (void)hipFree(plan.dev);
+                free_plan(plan);
                 return st;
             }
-            if (endc != hipSuccess) return hip_fail(endc, "hipStreamEndCapture");
+            if (endc != hipSuccess) {
+                free_plan(plan);
+                return hip_fail(endc, "hipStreamEndCapture");
+            }
             herr = hipGraphInstantiate(&plan.exec, gr, nullptr, nullptr, 0);
             if (herr != hipSuccess) {
-                (void)hipGraphDestroy(gr);
+                free_plan(plan);
                 return hip_fail(herr, "hipGraphInstantiate");
             }
-            plan.graph = gr;
         }
         it = g_plans.emplace(key, plan).first;
     }
@@ -431,12 +446,7 @@ mlk_status mlk_batched_matmul(mlk_dtype in, mlk_dtype out, int64_t count,
 void mlk_release(void) {
     std::lock_guard<std::mutex> g(g_mu);
     (void)hipDeviceSynchronize();
-    for (auto& kv : g_plans) {
-        Plan& p = kv.second;
-        if (p.exec) (void)hipGraphExecDestroy(p.exec);
-        if (p.graph) (void)hipGraphDestroy(p.graph);
-        if (p.dev) (void)hipFree(p.dev);
-    }
+    for (auto& kv : g_plans) free_plan(kv.second);
     g_plans.clear();
     for (auto& kv : g_capture_streams) (void)hipStreamDestroy(kv.second);
     g_capture_streams.clear();
