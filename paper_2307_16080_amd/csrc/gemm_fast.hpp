@@ -44,7 +44,9 @@ typedef int32_t i32x4_t __attribute__((ext_vector_type(4)));
 // Written as inline asm so that the compiler does not treat it as a pending
 // write to every LDS location (it would otherwise wait for the whole prefetch
 // before the next LDS read); the kernel waits on vmcnt itself.  One wait
-// state separates the m0 write from the load.
+// state separates the m0 write from the load.  m0 is listed as clobbered
+// (the compiler warns that it is a reserved register); in these kernels
+// nothing else keeps a value in m0 (the generated code writes m0 only here).
 __device__ inline void dma_load16(uint32_t lds_addr, int voffset, const i32x4_t& rsrc, int soffset) {
     asm volatile(
         "s_mov_b32 m0, %0\n\t"
@@ -555,8 +557,6 @@ struct FastGemm {
             }
         }
 
-        typedef __attribute__((address_space(3))) bf4_t* tp;
-        typedef __attribute__((address_space(3))) i2_t* t8p;
         if constexpr (!REG) {
             for (int it = 0; it < nk; ++it) {
                 // stage `it` has landed once at most (stages issued after it) loads remain
