@@ -30,6 +30,9 @@ const KernelEntry* kernels_fast(int* n) {
         MLK_ENTRY_FASTCONV(DT_BF16, 128, 256, 2, 2, 1),
         MLK_ENTRY_FASTCONV(DT_BF16, 256, 128, 2, 2, 1),
         // the same gather issued as direct-to-LDS copies: C * KH * KW a multiple of 64
+        MLK_ENTRY_FASTCONV(DT_BF16, 64, 64, 2, 2, 2),    // 32 KB of LDS: five workgroups per CU
+        MLK_ENTRY_FASTCONV(DT_BF16, 64, 64, 2, 2, 3),
+        MLK_ENTRY_FASTCONV(DT_BF16, 64, 128, 2, 2, 2),
         MLK_ENTRY_FASTCONV(DT_BF16, 64, 128, 2, 2, 3),
         MLK_ENTRY_FASTCONV(DT_BF16, 64, 128, 2, 2, 4),
         MLK_ENTRY_FASTCONV(DT_BF16, 128, 128, 2, 2, 3),
