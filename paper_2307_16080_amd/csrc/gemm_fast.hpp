@@ -240,14 +240,16 @@ struct FastGemm {
                 rs.b_r[i] = r;
                 rs.b_col[i] = c * EPV;  // element offset of the chunk in the stage's k range
                 rs.p_ok[i] = p < g.N;
-                const int img = rs.p_ok[i] ? (int)(p / hw) : 0;
-                const int q = rs.p_ok[i] ? (int)(p - (int64_t)img * hw) : 0;
+                // pixel and depth indices fit 32 bits (N*HO*WO and C*KH*KW are
+                // below 2^31): 32-bit divisions
+                const int img = rs.p_ok[i] ? (int)((uint32_t)p / (uint32_t)hw) : 0;
+                const int q = rs.p_ok[i] ? (int)p - img * hw : 0;
                 rs.p_img[i] = (int64_t)img * g.ch * g.cw;
                 rs.p_ih0[i] = (q / g.cwo) * g.csh - g.cph;
                 rs.p_iw0[i] = (q % g.cwo) * g.csw - g.cpw;
-                const int64_t k = kfirst + rs.b_col[i];
-                const int tap = (int)(k / g.cc);
-                rs.k_ci[i] = (int)(k - (int64_t)tap * g.cc);
+                const int k = (int)kfirst + rs.b_col[i];
+                const int tap = (int)((uint32_t)k / (uint32_t)g.cc);
+                rs.k_ci[i] = k - tap * g.cc;
                 rs.k_kh[i] = tap / g.ckw;
                 rs.k_kw[i] = tap - rs.k_kh[i] * g.ckw;
             } else {
@@ -503,7 +505,7 @@ struct FastGemm {
 #pragma unroll
             for (int j = 0; j < TN; ++j) {
                 const int64_t n = n0 + col0 + j * 16;
-                const int64_t img = n / hw;
+                const int64_t img = (uint32_t)n / (uint32_t)hw;  // n < N*HO*WO < 2^31
                 cbase[j] = img * g.M * hw + (n - img * hw) + m0 * hw;
             }
         }

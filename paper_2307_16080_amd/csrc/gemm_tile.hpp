@@ -542,7 +542,8 @@ struct Tile {
             const int64_t n = n0 + wx * WTN + j * 16 + lr;
             if constexpr (CONV != 0) {
                 const int64_t hw = (int64_t)g.cho * g.cwo;
-                cbase = (n / hw) * g.M * hw + n % hw;
+                const int64_t img = (uint32_t)n / (uint32_t)hw;  // n < N*HO*WO + tile < 2^32
+                cbase = img * g.M * hw + (n - img * hw);
                 rstride = hw;
             } else {
                 cbase = n;
@@ -624,7 +625,7 @@ struct Tile {
             int64_t rstride = g.ldc;
             if constexpr (CONV != 0) {
                 const int64_t hw = (int64_t)g.cho * g.cwo;
-                const int64_t img = n / hw, q = n % hw;
+                const int64_t img = (uint32_t)n / (uint32_t)hw, q = n - img * hw;
                 cbase = img * g.M * hw + q;
                 rstride = hw;
             }
