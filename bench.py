@@ -24,7 +24,8 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-PEAK = {"bf16": 2516.6, "fp8": 5033.2, "i8": 5033.2, "f32": 157.3}  # dense TFLOP/s (TOPS)
+PEAK = {"bf16": 2516.6, "fp8": 5033.2, "i8": 5033.2, "f32": 157.3,  # dense TFLOP/s (TOPS)
+        "hbm_gbs": 8000.0}  # HBM3E GB/s
 COPY_BYTES = 256 << 20  # the reference copy: bytes read (and written)
 
 
@@ -219,6 +220,19 @@ def main():
         us = time_us(lambda: mlk.conv2d_nchw_fchw(xd, wd, y, (1, 1), (1, 1), cfg=bc), 50)
         rows_out["conv_f32_56x56x64"] = {"us": round(us, 2), "TFLOP/s": round(cs.flops() / us / 1e6, 2),
                                          "tile": list(bc.as_tuple())}
+        # the paper's measured workload: one 1280 x 1280 image, 3 filters 3x3,
+        # valid, fp32 (y += conv): HBM-bound, reported against 8 TB/s with the
+        # algorithmic bytes (x, w read; y read and written)
+        xp, wp = conv_inputs(1, 1, 1280, 1280, 3, 3, 3, seed=0)
+        xpd, wpd = torch.from_numpy(xp).cuda(), torch.from_numpy(wp).cuda()
+        yp = torch.zeros(1, 3, 1278, 1278, device="cuda")
+        pp = mlk.conv_problem(1, 1, 1280, 1280, 3, 3, 3, 1, 0, L.MLK_F32, L.MLK_F32)
+        bp, _, _ = mlk.tune(pp, mlk.MLK_TUNE_EXHAUSTIVE, reps=10, warmup=2)
+        us = time_us(lambda: mlk.conv2d_nchw_fchw(xpd, wpd, yp, (1, 1), (0, 0), cfg=bp), 50)
+        pbytes = 4 * (1280 * 1280 + 3 * 9 + 2 * 3 * 1278 * 1278)
+        rows_out["conv_f32_paper_1280x1280x3"] = {"us": round(us, 2), "GB/s": round(pbytes / us / 1e3, 1),
+                                                  "frac_hbm": round(pbytes / us / 1e3 / PEAK["hbm_gbs"], 3),
+                                                  "bytes": pbytes, "tile": list(bp.as_tuple())}
         # 256 uneven bf16 GEMMs
         shapes = batched_shapes(256, seed=0)
         ins = batched_inputs(shapes, seed=1)

@@ -247,17 +247,21 @@ typedef struct {
 typedef enum {
     MLK_TUNE_EXHAUSTIVE = 0, /* measure every legal configuration */
     MLK_TUNE_RANDOM = 1,     /* measure a uniform random sample of the budget */
-    MLK_TUNE_MODEL = 2       /* rank all by the cost model, measure the top budget */
+    MLK_TUNE_MODEL = 2,      /* rank all by the cost model, measure the top budget */
+    MLK_TUNE_ES = 3          /* (1+1) evolution strategy over the configuration's
+                                fields: mutate the best so far, keep the child if it
+                                is faster, adapt the mutation strength by the 1/5
+                                success rule; stops at the budget */
 } mlk_tune_strategy;
 
 typedef struct mlk_cost_model mlk_cost_model; /* opaque, see mlk_model_* */
 
 typedef struct {
     int32_t strategy;       /* mlk_tune_strategy */
-    double budget_frac;     /* RANDOM / MODEL: measure ceil(budget_frac * n_legal) configs */
+    double budget_frac;     /* RANDOM / MODEL / ES: measure ceil(budget_frac * n_legal) configs */
     int32_t reps;           /* timed runs per configuration (median taken); 0 = 20 */
     int32_t warmup;         /* untimed runs first; 0 = 3 */
-    uint64_t seed;          /* RANDOM sampling seed; also seeds the scratch inputs */
+    uint64_t seed;          /* RANDOM / ES seed; also seeds the scratch inputs */
     const char* db_path;    /* NULL = no database; else JSON-lines file, appended */
     int32_t use_db;         /* 1: if the database holds this problem, return it unmeasured */
     mlk_cost_model* model;  /* MLK_TUNE_MODEL: the trained model (else ignored) */
@@ -265,6 +269,10 @@ typedef struct {
                                legal config in enumeration order, -1 if not measured */
     int32_t fake_timer;     /* 1: replace GPU timing by a deterministic analytic cost
                                (host-only; for testing the search logic) */
+    const double* table_us; /* optional HOST array [mlk_config_count]: times to use
+                               instead of measuring (<= 0: the configuration fails),
+                               for replaying a strategy offline on a measured table;
+                               host-only, like fake_timer (which it overrides) */
 } mlk_tune_opts;
 
 typedef struct {

@@ -20,7 +20,7 @@ import torch
 from . import _lib as L
 from ._lib import (MLK_BATCH_GRAPH, MLK_BATCH_PERSISTENT, MLK_BF16, MLK_F8E4M3, MLK_F32, MLK_I8,
                    MLK_I32, MLK_OP_BATCHED, MLK_OP_CONV2D, MLK_OP_MATMUL, MLK_TUNE_EXHAUSTIVE,
-                   MLK_TUNE_MODEL, MLK_TUNE_RANDOM, GemmDesc, MlkError, Problem, TileConfig,
+                   MLK_TUNE_ES, MLK_TUNE_MODEL, MLK_TUNE_RANDOM, GemmDesc, MlkError, Problem, TileConfig,
                    TuneOpts, TuneReport)
 
 __all__ = ["matmul", "conv2d_nchw_fchw", "quantize", "batched_matmul", "BatchedCall", "err_stats", "tune",
@@ -235,10 +235,16 @@ def set_default_config(problem, cfg):
 
 
 def tune(problem, strategy=MLK_TUNE_EXHAUSTIVE, budget_frac=1.0, reps=0, warmup=0, seed=0,
-         db_path=None, use_db=False, model=None, want_times=False, fake_timer=False):
-    """Returns (best TileConfig, TuneReport, times_us list or None)."""
+         db_path=None, use_db=False, model=None, want_times=False, fake_timer=False, table=None):
+    """Returns (best TileConfig, TuneReport, times_us list or None).  `table`: one time per
+    legal configuration (enumeration order) to replay the search on instead of measuring."""
     n = config_count(problem)
     times = (ctypes.c_double * max(n, 1))() if want_times else None
+    tab = None
+    if table is not None:
+        if len(table) != n:
+            raise MlkError(9, f"tune: table has {len(table)} entries for {n} configurations")
+        tab = (ctypes.c_double * n)(*[float(v) for v in table])
     o = TuneOpts()
     o.strategy, o.budget_frac, o.reps, o.warmup, o.seed = strategy, budget_frac, reps, warmup, seed
     o.db_path = db_path.encode() if db_path else None
@@ -246,6 +252,7 @@ def tune(problem, strategy=MLK_TUNE_EXHAUSTIVE, budget_frac=1.0, reps=0, warmup=
     o.model = model.handle if model is not None else None
     o.times_us = ctypes.cast(times, ctypes.POINTER(ctypes.c_double)) if times is not None else None
     o.fake_timer = int(bool(fake_timer))
+    o.table_us = ctypes.cast(tab, ctypes.POINTER(ctypes.c_double)) if tab is not None else None
     best, rep = TileConfig(), TuneReport()
     L.check(L.lib().mlk_tune(ctypes.byref(problem), ctypes.byref(o), ctypes.byref(best),
                              ctypes.byref(rep)))

@@ -20,7 +20,7 @@ STATUS_NAMES = ["MLK_OK", "MLK_ERR_NULL", "MLK_ERR_SHAPE", "MLK_ERR_LAYOUT", "ML
 MLK_F32, MLK_BF16, MLK_F8E4M3, MLK_I8, MLK_I32 = 0, 1, 2, 3, 4
 # ops / strategies / flags
 MLK_OP_MATMUL, MLK_OP_CONV2D, MLK_OP_BATCHED = 0, 1, 2
-MLK_TUNE_EXHAUSTIVE, MLK_TUNE_RANDOM, MLK_TUNE_MODEL = 0, 1, 2
+MLK_TUNE_EXHAUSTIVE, MLK_TUNE_RANDOM, MLK_TUNE_MODEL, MLK_TUNE_ES = 0, 1, 2, 3
 MLK_BATCH_PERSISTENT, MLK_BATCH_GRAPH = 1, 2
 
 
@@ -61,7 +61,7 @@ class TuneOpts(ctypes.Structure):
                 ("reps", ctypes.c_int32), ("warmup", ctypes.c_int32), ("seed", ctypes.c_uint64),
                 ("db_path", ctypes.c_char_p), ("use_db", ctypes.c_int32),
                 ("model", ctypes.c_void_p), ("times_us", ctypes.POINTER(ctypes.c_double)),
-                ("fake_timer", ctypes.c_int32)]
+                ("fake_timer", ctypes.c_int32), ("table_us", ctypes.POINTER(ctypes.c_double))]
 
 
 class TuneReport(ctypes.Structure):

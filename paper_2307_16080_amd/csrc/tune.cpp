@@ -5,7 +5,9 @@
 // Strategies: EXHAUSTIVE measures every legal configuration (the ground
 // truth); RANDOM measures a seeded uniform sample of the budget; MODEL ranks
 // every configuration with the learned cost model and measures only the top
-// of the ranking.  The objective is the median of `reps` timed samples after
+// of the ranking; ES is a (1+1) evolution strategy, the derivative-free
+// black-box search of the kind the paper runs through an external optimiser
+// library, written here over the configuration's fields.  The objective is the median of `reps` timed samples after
 // `warmup` untimed launches; each sample times enough back-to-back launches
 // (hipEvents on the tuning stream) to last about 0.2 ms.
 //
@@ -228,6 +230,86 @@ double measure(const mlk_problem* p, const Shape& s, const Scratch& sc, const ml
     return t.size() % 2 ? t[t.size() / 2] : 0.5 * (t[t.size() / 2 - 1] + t[t.size() / 2]);
 }
 
+// The fields of a configuration as the evolution strategy mutates them: the
+// kernel (tile shape, waves and stages together), split_k, group_m,
+// xcd_remap and layout.
+constexpr int kGenes = 5;
+
+int gene_distance(const mlk_tile_config& a, const mlk_tile_config& b) {
+    const bool kernel = a.bm == b.bm && a.bn == b.bn && a.bk == b.bk && a.wm == b.wm && a.wn == b.wn &&
+                        a.stages == b.stages;
+    return (kernel ? 0 : 1) + (a.split_k != b.split_k) + (a.group_m != b.group_m) + (a.xcd_remap != b.xcd_remap) +
+           (a.layout != b.layout);
+}
+
+// (1+1) evolution strategy over the legal configurations.  The parent starts
+// at `start` when that configuration is legal here (else a seeded random one);
+// each step measures one unmeasured child that differs from the parent in m
+// fields (the nearest other distance when none is left at m) and keeps it if
+// it is faster.  The mutation strength m follows the 1/5 success rule over
+// windows of five children: more than one success in five widens the steps,
+// fewer narrows them.  After three windows without a success the search
+// restarts from a seeded random unmeasured configuration (the fastest
+// measured so far is kept by the caller).  Stops after `budget` measurements
+// or when every configuration has been measured.
+template <typename Eval>
+void es_search(const std::vector<mlk_tile_config>& cfgs, int budget, uint64_t seed, const mlk_tile_config& start,
+               Eval&& eval) {
+    const int S = (int)cfgs.size();
+    std::mt19937_64 rng(seed);
+    std::vector<char> visited(S, 0);
+    int parent = -1;
+    for (int i = 0; i < S && parent < 0; ++i)
+        if (!memcmp(&cfgs[i], &start, sizeof start)) parent = i;
+    if (parent < 0) parent = std::uniform_int_distribution<int>(0, S - 1)(rng);
+    visited[parent] = 1;
+    double tp = eval(parent);
+    int used = 1, m = 1, succ = 0, tries = 0, dry = 0;
+    std::vector<int> cand;
+    while (used < budget) {
+        if (dry >= 15) {
+            // stagnation: restart from an unmeasured configuration
+            cand.clear();
+            for (int i = 0; i < S; ++i)
+                if (!visited[i]) cand.push_back(i);
+            if (cand.empty()) break;
+            parent = cand[std::uniform_int_distribution<int>(0, (int)cand.size() - 1)(rng)];
+            visited[parent] = 1;
+            tp = eval(parent);
+            ++used;
+            m = 1;
+            succ = tries = dry = 0;
+            continue;
+        }
+        cand.clear();
+        for (int d = 0; d <= kGenes && cand.empty(); ++d)
+            for (int dist : {m - d, m + d}) {
+                if (dist < 1 || dist > kGenes || (d == 0 && dist != m) || !cand.empty()) continue;
+                for (int i = 0; i < S; ++i)
+                    if (!visited[i] && gene_distance(cfgs[i], cfgs[parent]) == dist) cand.push_back(i);
+            }
+        if (cand.empty()) break;
+        const int child = cand[std::uniform_int_distribution<int>(0, (int)cand.size() - 1)(rng)];
+        visited[child] = 1;
+        const double tc = eval(child);
+        ++used;
+        ++tries;
+        if (tc > 0 && (tp <= 0 || tc < tp)) {
+            parent = child;
+            tp = tc;
+            ++succ;
+            dry = 0;
+        } else {
+            ++dry;
+        }
+        if (tries == 5) {
+            if (succ * 5 > tries) m = std::min(m + 1, kGenes);
+            else if (succ * 5 < tries) m = std::max(m - 1, 1);
+            tries = succ = 0;
+        }
+    }
+}
+
 }  // namespace
 
 double fake_time_us(const Shape& s, int op, const mlk_tile_config& c, int index, uint64_t seed) {
@@ -259,7 +341,7 @@ extern "C" mlk_status mlk_tune(const mlk_problem* p, const mlk_tune_opts* o, mlk
     Shape s;
     mlk_status st = shape_of_problem(p, &s);
     if (st != MLK_OK) return st;
-    if (o->strategy < MLK_TUNE_EXHAUSTIVE || o->strategy > MLK_TUNE_MODEL)
+    if (o->strategy < MLK_TUNE_EXHAUSTIVE || o->strategy > MLK_TUNE_ES)
         return fail(MLK_ERR_ARG, "tune: unknown strategy %d", o->strategy);
     if (o->strategy != MLK_TUNE_EXHAUSTIVE && !(o->budget_frac > 0.0 && o->budget_frac <= 1.0))
         return fail(MLK_ERR_ARG, "tune: budget_frac must be in (0, 1]");
@@ -302,34 +384,17 @@ extern "C" mlk_status mlk_tune(const mlk_problem* p, const mlk_tune_opts* o, mlk
         if (unreadable) return fail(MLK_ERR_DB, "tune: database %s is not readable", o->db_path);
     }
 
-    // which configurations to measure, in order
-    int budget = S;
-    if (o->strategy != MLK_TUNE_EXHAUSTIVE)
-        budget = std::max(1, std::min(S, (int)std::ceil(o->budget_frac * S - 1e-9)));
-    std::vector<int> order(S);
-    std::iota(order.begin(), order.end(), 0);
-    if (o->strategy == MLK_TUNE_RANDOM) {
-        std::mt19937_64 rng(o->seed);
-        for (int i = 0; i < budget; ++i) {
-            std::uniform_int_distribution<int> pick(i, S - 1);
-            std::swap(order[i], order[pick(rng)]);
-        }
-    } else if (o->strategy == MLK_TUNE_MODEL) {
-        std::vector<float> pred;
-        st = model_predict_shape(o->model, s, cfgs, &pred);
-        if (st != MLK_OK) return st;
-        std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return pred[a] < pred[b]; });
-    }
-    order.resize(budget);
-
+    // measurement of one configuration (cached), on the GPU or, for testing
+    // and offline replays, from the analytic cost or a given table
+    const bool host_timer = o->table_us || o->fake_timer;
     std::vector<double> t(S, -1.0);
-    if (o->fake_timer) {
-        for (int i : order) t[i] = fake_time_us(s, p->op, cfgs[i], i, o->seed);
-    } else {
-        Scratch sc;
+    std::vector<char> seen(S, 0);
+    std::vector<int> order;  // configurations measured, in measurement order
+    Scratch sc;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (!host_timer) {
         st = make_scratch(p, s, o->seed ^ 0x5EEDull, &sc);
         if (st != MLK_OK) return st;
-        hipEvent_t e0, e1;
         hipError_t he = hipEventCreate(&e0);
         if (he != hipSuccess) return hip_fail(he, "tune: event");
         he = hipEventCreate(&e1);
@@ -337,14 +402,51 @@ extern "C" mlk_status mlk_tune(const mlk_problem* p, const mlk_tune_opts* o, mlk
             (void)hipEventDestroy(e0);
             return hip_fail(he, "tune: event");
         }
-        he = hipDeviceSynchronize();
-        for (int i : order) t[i] = measure(p, s, sc, cfgs[i], warmup, reps, 0, e0, e1);
+        (void)hipDeviceSynchronize();
+    }
+    auto eval = [&](int i) {
+        if (seen[i]) return t[i];
+        seen[i] = 1;
+        order.push_back(i);
+        if (o->table_us) t[i] = o->table_us[i] > 0 ? o->table_us[i] : -1.0;
+        else if (o->fake_timer) t[i] = fake_time_us(s, p->op, cfgs[i], i, o->seed);
+        else t[i] = measure(p, s, sc, cfgs[i], warmup, reps, 0, e0, e1);
+        return t[i];
+    };
+
+    int budget = S;
+    if (o->strategy != MLK_TUNE_EXHAUSTIVE)
+        budget = std::max(1, std::min(S, (int)std::ceil(o->budget_frac * S - 1e-9)));
+    if (o->strategy == MLK_TUNE_ES) {
+        es_search(cfgs, budget, o->seed, heuristic_config(s, p->op), eval);
+    } else {
+        std::vector<int> plan(S);
+        std::iota(plan.begin(), plan.end(), 0);
+        if (o->strategy == MLK_TUNE_RANDOM) {
+            std::mt19937_64 rng(o->seed);
+            for (int i = 0; i < budget; ++i) {
+                std::uniform_int_distribution<int> pick(i, S - 1);
+                std::swap(plan[i], plan[pick(rng)]);
+            }
+        } else if (o->strategy == MLK_TUNE_MODEL) {
+            std::vector<float> pred;
+            st = model_predict_shape(o->model, s, cfgs, &pred);
+            if (st != MLK_OK) {
+                if (e0) (void)hipEventDestroy(e0);
+                if (e1) (void)hipEventDestroy(e1);
+                return st;
+            }
+            std::stable_sort(plan.begin(), plan.end(), [&](int a, int b) { return pred[a] < pred[b]; });
+        }
+        for (int k = 0; k < budget; ++k) eval(plan[k]);
+    }
+    if (!host_timer) {
         (void)hipDeviceSynchronize();
         (void)hipEventDestroy(e0);
         (void)hipEventDestroy(e1);
         clear_error();
     }
-    r.n_measured = budget;
+    r.n_measured = (int)order.size();
 
     // fastest, with configurations within 1% counted as tied: smaller LDS
     // footprint first, then the lower enumeration index

@@ -188,6 +188,73 @@ def test_tune_random_budget_and_determinism():
     assert [i for i, t in enumerate(t3) if t > 0] != measured
 
 
+def _table(p, seed=3):
+    _, _, times = mlk.tune(p, mlk.MLK_TUNE_EXHAUSTIVE, fake_timer=True, want_times=True, seed=seed)
+    return times
+
+
+def test_tune_es_budget_determinism_and_neighbourhood():
+    """ES measures exactly its budget of distinct configurations, reads its
+    times from the replayed table, and is a function of its seed."""
+    p = mlk.conv_problem(32, 64, 56, 56, 64, 3, 3, 1, 1, L.MLK_BF16, L.MLK_F32)
+    S = mlk.config_count(p)
+    tab = _table(p)
+    b1, r1, t1 = mlk.tune(p, mlk.MLK_TUNE_ES, budget_frac=0.2, seed=5, table=tab, want_times=True)
+    b2, r2, t2 = mlk.tune(p, mlk.MLK_TUNE_ES, budget_frac=0.2, seed=5, table=tab, want_times=True)
+    measured = [i for i, t in enumerate(t1) if t > 0]
+    assert r1.n_measured == len(measured) == -(-S * 2 // 10)
+    assert b1.as_tuple() == b2.as_tuple() and t1 == t2
+    assert all(t1[i] == tab[i] for i in measured)               # the table, not a measurement
+    assert rep_best_is_measured_min(r1, t1)
+    _, _, t3 = mlk.tune(p, mlk.MLK_TUNE_ES, budget_frac=0.2, seed=6, table=tab, want_times=True)
+    assert [i for i, t in enumerate(t3) if t > 0] != measured
+
+
+def rep_best_is_measured_min(rep, times):
+    tmin = min(t for t in times if t > 0)
+    return times[rep.best_index] <= 1.01 * tmin
+
+
+def test_tune_es_full_budget_and_failed_configurations():
+    """With the whole budget ES visits every configuration (restarts included)
+    and returns the table's fastest; configurations whose time is <= 0 count
+    as failed launches and are never returned."""
+    p = mlk.matmul_problem(1000, 300, 2000, L.MLK_F32, L.MLK_F32)
+    S = mlk.config_count(p)
+    tab = _table(p, seed=1)
+    fastest = min(range(S), key=lambda i: tab[i])
+    _, rep, _ = mlk.tune(p, mlk.MLK_TUNE_ES, budget_frac=1.0, seed=2, table=tab)
+    assert rep.n_measured == S and rep_best_is_measured_min(rep, tab)
+    failed = list(tab)
+    failed[fastest] = -1.0                                      # the fastest cannot launch
+    best, rep, times = mlk.tune(p, mlk.MLK_TUNE_ES, budget_frac=1.0, seed=2, table=failed, want_times=True)
+    assert rep.best_index != fastest and times[rep.best_index] > 0
+    with pytest.raises(mlk.MlkError):
+        mlk.tune(p, mlk.MLK_TUNE_ES, budget_frac=0.5, table=tab[:-1])
+
+
+def test_tune_es_beats_random_on_replayed_tables():
+    """On the analytic timer's tables ES's median regret over 40 seeds is no
+    worse than random sampling's at the same 20% budget on each problem, and
+    better on their sum."""
+    import numpy as np
+    probs = [mlk.conv_problem(1, 256, 14, 14, 512, 3, 3, 2, 1, L.MLK_BF16, L.MLK_F32),
+             mlk.conv_problem(32, 128, 28, 28, 256, 3, 3, 2, 1, L.MLK_BF16, L.MLK_F32),
+             mlk.matmul_problem(4096, 4096, 4096, L.MLK_BF16, L.MLK_F32)]
+    es_tot = rnd_tot = 0.0
+    for p in probs:
+        tab = _table(p, seed=0)
+        best = min(tab)
+        es = [mlk.tune(p, mlk.MLK_TUNE_ES, budget_frac=0.2, seed=s, table=tab)[1].best_us / best - 1
+              for s in range(40)]
+        rnd = [mlk.tune(p, mlk.MLK_TUNE_RANDOM, budget_frac=0.2, seed=s, table=tab)[1].best_us / best - 1
+               for s in range(40)]
+        assert np.median(es) <= np.median(rnd) + 1e-12
+        es_tot += float(np.median(es))
+        rnd_tot += float(np.median(rnd))
+    assert es_tot < rnd_tot
+
+
 def test_tune_database_append_and_resume(tmp_path):
     db = str(tmp_path / "tune.jsonl")
     p = mlk.matmul_problem(512, 512, 512, L.MLK_BF16, L.MLK_F32)
