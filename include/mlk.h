@@ -105,8 +105,12 @@ typedef enum {
  *              channels-last (NHWC) and the filter to F x KH x KW x C in the
  *              library's scratch memory (one launch for both), so every
  *              operand load is one aligned 16-byte read; needs C a multiple
- *              of 8 (bf16) or 4 (fp32) and 16-byte aligned x and w.  Must be
- *              0 for matmul.
+ *              of 8 (bf16) or 4 (fp32) and 16-byte aligned x and w.  2: the
+ *              direct (stencil) conv, no GEMM tiling: a workgroup computes a
+ *              bm x bn block of output pixels (bn = 64) for all F filters
+ *              from the input window staged in LDS; its configurations have
+ *              bk = 1, wm = wn = 0, split_k = 1, and it needs F <= 16,
+ *              strides <= 2 and filters up to 7 x 7.  Must be 0 for matmul.
  * A zeroed struct or a NULL pointer means "choose": the tuning database
  * entry for this problem if one was loaded, else a built-in heuristic.
  */

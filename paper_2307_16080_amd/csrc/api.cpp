@@ -65,7 +65,7 @@ const std::vector<const KernelEntry*>& registry() {
     static std::vector<const KernelEntry*> all = [] {
         std::vector<const KernelEntry*> v;
         const KernelEntry* (*tables[])(int*) = {kernels_f32, kernels_bf16, kernels_i8, kernels_f8,
-                                                kernels_conv, kernels_fast};
+                                                kernels_conv, kernels_fast, kernels_direct};
         for (auto t : tables) {
             int n = 0;
             const KernelEntry* e = t(&n);
@@ -149,6 +149,10 @@ mlk_status shape_of_problem(const mlk_problem* p, Shape* s) {
         s->K = p->c * p->kh * p->kw;
         s->conv_c = p->c;
         s->conv_in = p->n * p->c * p->h * p->w;
+        s->conv_kh = (int)p->kh;
+        s->conv_kw = (int)p->kw;
+        s->conv_sh = p->sh;
+        s->conv_sw = p->sw;
     } else {
         if (p->count < 1) return fail(MLK_ERR_SHAPE, "batched: count must be >= 1");
         if (!p->descs) return fail(MLK_ERR_NULL, "batched: descs is NULL");
@@ -185,6 +189,14 @@ static bool fast_shape_ok(const Shape& s, int bk) {
     return s.M * Kp * es < ((int64_t)1 << 31) && Kp * Np * es < ((int64_t)1 << 31);
 }
 
+static bool is_direct(const KernelEntry* e) { return e->conv && e->wm == 0; }
+
+// the direct (stencil) conv covers few filters, small strides and taps
+static bool direct_ok(const Shape& s) {
+    return s.conv && s.M <= kDirectMaxF && s.conv_sh <= kDirectMaxStride && s.conv_sw <= kDirectMaxStride &&
+           s.conv_kh <= kDirectMaxTap && s.conv_kw <= kDirectMaxTap;
+}
+
 mlk_status check_config(const Shape& s, int op, const mlk_tile_config& c) {
     const KernelEntry* e = find_kernel(s.dt, s.conv, c);
     if (!e)
@@ -203,8 +215,16 @@ mlk_status check_config(const Shape& s, int op, const mlk_tile_config& c) {
         return fail(MLK_ERR_CONFIG, "split_k %d exceeds the %lld K stages", c.split_k, (long long)stages);
     if (c.group_m < 0 || c.group_m > 64) return fail(MLK_ERR_CONFIG, "group_m must be in [0, 64]");
     if (c.xcd_remap != 0 && c.xcd_remap != 1) return fail(MLK_ERR_CONFIG, "xcd_remap must be 0 or 1");
+    if (is_direct(e)) {
+        if (c.layout != 2 || c.split_k != 1)
+            return fail(MLK_ERR_CONFIG, "the direct conv tile runs as layout 2 with split_k 1");
+        if (!direct_ok(s))
+            return fail(MLK_ERR_CONFIG, "direct conv: needs F <= %d, strides <= %d and filters up to %dx%d",
+                        kDirectMaxF, kDirectMaxStride, kDirectMaxTap, kDirectMaxTap);
+        return MLK_OK;
+    }
     if (c.layout != 0 && !(s.conv && c.layout == 1))
-        return fail(MLK_ERR_CONFIG, "layout must be 0, or 1 for conv2d");
+        return fail(MLK_ERR_CONFIG, "layout must be 0, or 1 for conv2d (2 only for the direct conv tiles)");
     if (s.conv && !e->launch && c.layout != 1)
         return fail(MLK_ERR_CONFIG, "this conv tile runs only the channels-last layout (layout 1)");
     if (c.layout == 1 && (!e->launch_nhwc || s.conv_c % (16 / esize_in(s.dt)) != 0))
@@ -220,6 +240,10 @@ std::vector<mlk_tile_config> enumerate_configs(const mlk_problem* p, const Shape
     for (const KernelEntry* e : registry()) {
         if (e->dt != s.dt || e->conv != s.conv) continue;
         if (batched && !e->persist) continue;
+        if (is_direct(e)) {
+            if (direct_ok(s)) out.push_back(mlk_tile_config{e->bm, e->bn, e->bk, 0, 0, 1, 1, 0, 0, 2});
+            continue;
+        }
         if (e->stages >= 2 && !batched && !fast_shape_ok(s, e->bk)) continue;
         // a tile at least twice the problem in a dimension only adds padding
         if (e->bm > 32 && e->bm >= 2 * s.M) continue;
@@ -255,7 +279,7 @@ mlk_tile_config heuristic_config(const Shape& s, int op) {
     const KernelEntry* best = nullptr;
     const KernelEntry* smallest = nullptr;
     for (const KernelEntry* e : registry()) {
-        if (e->dt != s.dt || e->conv != s.conv || e->stages) continue;
+        if (e->dt != s.dt || e->conv != s.conv || e->stages || is_direct(e)) continue;
         if (op == MLK_OP_BATCHED && !e->persist) continue;
         if (!smallest || e->bm * e->bn < smallest->bm * smallest->bn ||
             (e->bm * e->bn == smallest->bm * smallest->bn && e->bk > smallest->bk))
@@ -278,6 +302,13 @@ mlk_tile_config heuristic_config(const Shape& s, int op) {
                 const int64_t tiles = cdiv(s.M, 256) * cdiv(s.N, 256);
                 return mlk_tile_config{256, 256, f->bk, 2, 4, 1, 8, tiles % 8 == 0 ? 1 : 0, 2, 0};
             }
+    }
+    // few filters over a shallow depth: the direct (stencil) conv, whose MFMA
+    // tile would be mostly padding rows
+    if (s.conv && direct_ok(s) && (s.dt == DT_F32 || s.K <= 64)) {
+        for (const KernelEntry* d : registry())
+            if (is_direct(d) && d->dt == s.dt && d->bm == 16)
+                return mlk_tile_config{d->bm, d->bn, d->bk, 0, 0, 1, 1, 0, 0, 2};
     }
     // channels-last pays a transpose of the input: worth it for large images
     if (s.conv && e->launch_nhwc && s.conv_c % (16 / esize_in(s.dt)) == 0 && s.N >= 16384) c.layout = 1;
@@ -481,6 +512,11 @@ mlk_status launch_conv(const Shape& s, int64_t n, int64_t c, int64_t h, int64_t 
     g.cpw = pw;
     g.cho = (int32_t)ho;
     g.cwo = (int32_t)wo;
+    if (is_direct(e)) {
+        if (cfg.layout != 2) return fail(MLK_ERR_CONFIG, "the direct conv tile runs as layout 2");
+        const hipError_t err = e->launch(g, 0, st);
+        return err == hipSuccess ? MLK_OK : hip_fail(err, "direct conv launch");
+    }
     const int epv = 16 / es;
     if (cfg.layout == 1) {
         if (!(e->launch_nhwc && c % epv == 0 && (uintptr_t)x % 16 == 0 && (uintptr_t)wt % 16 == 0 &&

@@ -30,6 +30,7 @@ struct Shape {
     int accumulate = 1;
     int64_t conv_c = 0;   // conv: input channels
     int64_t conv_in = 0;  // conv: input elements N*C*H*W
+    int conv_kh = 0, conv_kw = 0, conv_sh = 0, conv_sw = 0;  // conv: filter taps and strides
 };
 
 // registry of compiled kernels

@@ -221,6 +221,14 @@ const KernelEntry* kernels_f8(int* n);
 const KernelEntry* kernels_conv(int* n);
 const KernelEntry* kernels_fast(int* n);
 
+// Direct (stencil) convolution (k_direct.hip): a few filters (F <=
+// kDirectMaxF), strides up to kDirectMaxStride, filter taps up to
+// kDirectMaxTap per side.  Its entries have bk = 1 and wm = wn = 0 and run as
+// conv layout 2; the LDS window is sized for the largest tile (16 x 64).
+constexpr int kDirectMaxF = 16, kDirectMaxStride = 2, kDirectMaxTap = 7;
+constexpr int kDirectPatch = ((16 - 1) * kDirectMaxStride + kDirectMaxTap) * ((64 - 1) * kDirectMaxStride + kDirectMaxTap);
+const KernelEntry* kernels_direct(int* n);
+
 // Elementwise / reduction launchers (quant.hip, reduce.hip, mlp.hip).
 hipError_t launch_zero_matrix(void* C, int64_t M, int64_t N, int64_t ldc, int esize,
                               hipStream_t s);

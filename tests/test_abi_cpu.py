@@ -125,10 +125,21 @@ def test_config_space():
     cp = mlk.conv_problem(32, 64, 56, 56, 64, 3, 3, 1, 1)
     assert mlk.config_count(cp) > 20
     assert {c.layout for c in mlk.configs(cp)} == {0, 1}
-    # channels-last needs C a multiple of the 16-byte vector (8 bf16)
+    # channels-last needs C a multiple of the 16-byte vector (8 bf16); with
+    # F <= 16 the direct (stencil) conv adds its layout-2 tiles
     c3 = mlk.conv_problem(1, 3, 32, 32, 16, 3, 3, 1, 1)
-    assert {c.layout for c in mlk.configs(c3)} == {0}
+    assert {c.layout for c in mlk.configs(c3)} == {0, 2}
     assert not mlk.config_legal(c3, mlk.TileConfig(32, 32, 32, 1, 1, 1, 1, 0, 0, 1))
+    direct = [c for c in mlk.configs(c3) if c.layout == 2]
+    assert direct and all(c.wm == 0 and c.wn == 0 and c.split_k == 1 and c.bk == 1 for c in direct)
+    d0 = direct[0]
+    assert not mlk.config_legal(c3, mlk.TileConfig(*list(d0.as_tuple())[:9], 0))      # only as layout 2
+    assert not mlk.config_legal(c3, mlk.TileConfig(d0.bm, d0.bn, 1, 0, 0, 2, 1, 0, 0, 2))  # no split K
+    # beyond its limits: 17 filters, stride 3, a 9x9 filter
+    for q in (mlk.conv_problem(1, 3, 32, 32, 17, 3, 3, 1, 1), mlk.conv_problem(1, 3, 32, 32, 8, 3, 3, 3, 1),
+              mlk.conv_problem(1, 3, 32, 32, 8, 9, 9, 1, 4)):
+        assert not any(c.layout == 2 for c in mlk.configs(q))
+        assert not mlk.config_legal(q, d0)
     # and layout is meaningless for matmul
     assert not mlk.config_legal(mlk.matmul_problem(64, 64, 64, L.MLK_BF16, L.MLK_F32),
                                 mlk.TileConfig(64, 64, 32, 2, 2, 1, 1, 0, 0, 1))

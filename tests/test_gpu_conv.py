@@ -318,3 +318,65 @@ def test_scratch_shared_across_streams():
     got = run_all(lambda k: s1 if k % 2 == 0 else s2)
     for i, (a, b) in enumerate(zip(want, got)):
         assert torch.equal(a, b), i
+
+
+DIRECT_CASES = [
+    # N, C, H, W, F, KH, KW, stride, pad: few filters, odd sizes, strides 1-2, taps up to 7x7,
+    # images narrower and wider than one 64-pixel row segment, several channels and images
+    (1, 1, 37, 70, 3, 3, 3, 1, 0),
+    (2, 3, 33, 129, 16, 3, 3, 2, 1),
+    (1, 5, 20, 20, 1, 5, 5, 1, 2),
+    (3, 2, 11, 9, 7, 7, 7, 1, 3),
+    (1, 4, 66, 65, 8, 1, 1, 2, 0),
+    (2, 16, 17, 30, 12, 3, 1, 1, 1),
+]
+
+
+@pytest.mark.parametrize("dt", ["f32", "bf16"])
+def test_direct_conv_tiles(dt):
+    """The direct (stencil) conv, every compiled tile height, against the
+    oracle: normwise <= 1e-5 from a random y (C += conv), bit-exact on small
+    integers, and with y overwritten (NaN-filled before)."""
+    in_dt = L.MLK_F32 if dt == "f32" else L.MLK_BF16
+    for case in DIRECT_CASES:
+        N, C, H, W, F, KH, KW, s, p = case
+        tiles = [c for c in mlk.configs(mlk.conv_problem(N, C, H, W, F, KH, KW, s, p, in_dt, L.MLK_F32))
+                 if c.layout == 2]
+        assert len(tiles) == 3, case
+        x, w = conv_inputs(N, C, H, W, F, KH, KW, seed=sum(case))
+        ho, wo = (H + 2 * p - KH) // s + 1, (W + 2 * p - KW) // s + 1
+        y0 = np.random.default_rng(5).uniform(-1, 1, (N, F, ho, wo)).astype(np.float32)
+        if dt == "bf16":
+            qx, qw = oracle.bf16_encode(x), oracle.bf16_encode(w)
+            xv, wv = oracle.bf16_decode(qx), oracle.bf16_decode(qw)
+            xd, wd = from_bf16_codes(qx), from_bf16_codes(qw)
+        else:
+            xv, wv, xd, wd = x, w, dev(x), dev(w)
+        ref = oracle.conv2d_f64(xv, wv, (s, s), (p, p), y=y0)
+        xi, wi = conv_inputs(N, C, H, W, F, KH, KW, seed=6, dist="small_int")
+        exact = oracle.conv2d_f64(xi, wi, (s, s), (p, p))
+        xid = dev(xi) if dt == "f32" else from_bf16_codes(oracle.bf16_encode(xi))
+        wid = dev(wi) if dt == "f32" else from_bf16_codes(oracle.bf16_encode(wi))
+        for cfg in tiles:
+            say("direct conv", dt, cfg, case)
+            y = dev(y0)
+            mlk.conv2d_nchw_fchw(xd, wd, y, (s, s), (p, p), cfg=cfg)
+            assert normwise(host(y), ref) <= 1e-5, (case, cfg)
+            for acc in (True, False):
+                y = torch.zeros(N, F, ho, wo, device="cuda") if acc else \
+                    torch.full((N, F, ho, wo), float("nan"), device="cuda")
+                mlk.conv2d_nchw_fchw(xid, wid, y, (s, s), (p, p), cfg=cfg, accumulate=acc)
+                assert np.array_equal(host(y).astype(np.float64), exact), (case, cfg, acc)
+
+
+def test_paper_conv_shape_tuned():
+    """The paper's one-channel, three-filter 3x3 layer with the tile the
+    exhaustive search picks (direct conv tiles included), against the oracle."""
+    p = mlk.conv_problem(1, 1, 1280, 1280, 3, 3, 3, 1, 0, L.MLK_F32, L.MLK_F32)
+    best, _, _ = mlk.tune(p, mlk.MLK_TUNE_EXHAUSTIVE, reps=3, warmup=1)
+    assert mlk.config_legal(p, best)
+    x, w = conv_inputs(1, 1, 1280, 1280, 3, 3, 3, seed=1)
+    ref = oracle.conv2d_f64(x, w, threads=oracle.default_threads())
+    y = torch.zeros(1, 3, 1278, 1278, device="cuda")
+    mlk.conv2d_nchw_fchw(dev(x), dev(w), y, cfg=best)
+    assert normwise(host(y), ref) <= 1e-5
