@@ -43,6 +43,7 @@ def _load():
     sig = {
         "orc_matmul_f64": (None, [_i64, _i64, _i64, _vp, _i64, _vp, _i64, _vp, _i64, _int]),
         "orc_matmul_f32": (None, [_i64, _i64, _i64, _vp, _i64, _vp, _i64, _vp, _i64]),
+        "orc_bias_rows_f64": (None, [_i64, _i64, _vp, _vp, _i64]),
         "orc_matmul_i8": (None, [_i64, _i64, _i64, _vp, _i64, _vp, _i64, _vp, _i64, _int]),
         "orc_conv_out_size": (_i64, [_i64, _i64, _i64, _i64]),
         "orc_conv2d_f64": (None, [_i64] * 11 + [_vp, _vp, _vp, _int]),
@@ -97,6 +98,20 @@ def matmul_f64(A, B, C=None, threads: int = 1):
     C = np.zeros((M, N), np.float64) if C is None else _c(C, np.float64).copy()
     _load().orc_matmul_f64(M, N, K, _p(A), K, _p(B), N, _p(C), N, threads)
     return C
+
+
+def linear_f64(A, B, bias, C=None, threads: int = 1):
+    """REF64 of the Linear layer (Sec. 2.1, listing "listing1"): the product A @ B
+    into a zeroed buffer, then the bias nest adding bias[j] to every row; with C,
+    the result is added to C (the library's accumulate mode: C += A B + bias)."""
+    T = matmul_f64(A, B, threads=threads)
+    M, N = T.shape
+    b = _c(np.asarray(bias).reshape(-1), np.float64)
+    assert b.shape[0] == N
+    _load().orc_bias_rows_f64(M, N, _p(b), _p(T), N)
+    if C is not None:
+        T = _c(C, np.float64) + T
+    return T
 
 
 def matmul_f32(A, B, C=None):

@@ -16,6 +16,9 @@
  *            "linalg-matmul" (linalg.generic with maps (d0,d2),(d2,d1),
  *            (d0,d1), iterators parallel/parallel/reduction, body mulf then
  *            addf into the output).  Naming here: C[M,N] += A[M,K] * B[K,N].
+ *   linear   Sec. 2.1 (MLIR), listing "listing1" (torch.nn.Linear lowered to
+ *            scf loops): the matmul nest into a zeroed buffer, then a
+ *            separate nest adding bias[j] to every row.
  *   conv2d   Sec. 4.1 (End-to-end GPU), listing "2dnchwconv": output[n,co,ho,wo] +=
  *            input[n,ci,ho+ki,wo+kj] * kernel[co,ci,ki,kj]; outer four loops
  *            parallel, ci/ki/kj sequential in that order.  Generalised to
@@ -131,6 +134,14 @@ void orc_matmul_f64(int64_t M, int64_t N, int64_t K, const double* A, int64_t ld
                     const double* B, int64_t ldb, double* C, int64_t ldc, int threads) {
     struct mm_f64 a = {N, K, lda, ldb, ldc, A, B, C};
     parallel_range(M, threads, mm_f64_rows, &a);
+}
+
+/* The bias nest of the Linear layer (Sec. 2.1, listing "listing1": after the
+ * product nest into a zeroed buffer, a second i/j nest loads the product and
+ * bias[j], adds them and stores): C[i,j] = C[i,j] + bias[j], in double. */
+void orc_bias_rows_f64(int64_t M, int64_t N, const double* bias, double* C, int64_t ldc) {
+    for (int64_t i = 0; i < M; ++i)
+        for (int64_t j = 0; j < N; ++j) C[i * ldc + j] = C[i * ldc + j] + bias[j];
 }
 
 /* C[i,j] = (C[i,j] + (A[i,k] * B[k,j])) in float, one rounding after the
