@@ -65,7 +65,7 @@ def main():
 
     import paper_2307_16080_amd as mlk
     from paper_2307_16080_amd import _lib as L
-    from workloads import (CFG_CONV_F32, batched_inputs, batched_shapes, conv_inputs, matmul_inputs,
+    from workloads import (CFG_CONV_F32, batched_inputs, batched_shapes, conv_inputs, linear_bias, matmul_inputs,
                            resnet18_conv_stack)
 
     torch.cuda.set_device(0)
@@ -195,6 +195,14 @@ def main():
         outputs["e4m3"] = C.cpu().numpy()
         rows_out["matmul_e4m3_4096"] = {"us": round(us, 1), "TFLOP/s": round(flops / us / 1e6, 1),
                                         "frac_peak": round(flops / us / 1e6 / PEAK["fp8"], 3), "tile": list(b8.as_tuple())}
+        # Linear: the same product with the bias add fused into its output stage
+        # (C = A B + bias), beside the plain product in overwrite mode (C = A B),
+        # both in the timed tile: the difference is the cost of the fusion
+        bias = torch.from_numpy(linear_bias(N, seed=0)).cuda()
+        us_lin = time_us(lambda: mlk.matmul_bias(qa, qb, bias, C, accumulate=False, cfg=best), 20)
+        us_ow = time_us(lambda: mlk.matmul(qa, qb, C, accumulate=False, cfg=best), 20)
+        rows_out["linear_bf16_4096"] = {"us": round(us_lin, 1), "TFLOP/s": round(flops / us_lin / 1e6, 1),
+                                        "matmul_overwrite_us": round(us_ow, 1), "tile": list(best.as_tuple())}
         # quantisation (HBM-bound)
         us_q16 = time_us(lambda: mlk.quantize(Ad, "bf16", q=qa), 20)
         us_q8 = time_us(lambda: mlk.quantize(Ad, "e4m3", q=qa8, scale=sa), 20)

@@ -137,6 +137,13 @@ typedef struct {
  *                          is multiplied by (*scale_a) * (*scale_b)
  *   (MLK_I8,     MLK_I32)  sign-extended int8 products, int32 sums that
  *                          wrap modulo 2^32; bit-exact
+ *   (MLK_BF16,   MLK_BF16) bf16 output: the fp32 result (with accumulate, the
+ *   (MLK_F8E4M3, MLK_BF16) bf16 C read back and added in fp32) is rounded
+ *                          once to bf16, to nearest even, in the kernel's
+ *                          output stage; C is M x N bf16 with row stride ldc
+ *                          (elements).  A result rounded once from the whole
+ *                          sum cannot be split over K: split_k must be 1; the
+ *                          register-loaded fast tiles (stages 1) are refused.
  * accumulate = 1: C += product (the linalg "outs" semantics);
  * accumulate = 0: C = product (C is not read).
  * scale_a / scale_b: device pointers to one float each (MLK_F8E4M3 only; NULL
@@ -150,6 +157,27 @@ mlk_status mlk_matmul(mlk_dtype in, mlk_dtype out, int64_t M, int64_t N, int64_t
                       const void* A, int64_t lda, const void* B, int64_t ldb, void* C,
                       int64_t ldc, const float* scale_a, const float* scale_b, int accumulate,
                       const mlk_tile_config* cfg, void* stream);
+
+/*
+ * The Linear layer: C[i,j] (+)= sum_k A[i,k] * B[k,j] + bias[j]  -- the
+ * product nest followed by the bias nest that adds bias[j] to every row
+ * (Sec. 2.1, listing "listing1"), with the bias add fused into the product's
+ * output stage instead of a second pass over C.
+ * Same arguments, dtypes and conventions as mlk_matmul, plus
+ * bias: device pointer to N floats (must not overlap C).  Float outputs only:
+ * (MLK_I8, MLK_I32) returns MLK_ERR_DTYPE.  For MLK_F8E4M3 the bias is added
+ * after the scale: C (+)= scale_a * scale_b * (A B) + bias.  With a bf16
+ * output the bias is added in fp32 before the one rounding.
+ * accumulate = 1: C += A B + bias; accumulate = 0: C = A B + bias.
+ * K == 0 gives C (+)= bias.  bias == NULL with M, N > 0 is MLK_ERR_NULL.
+ * The tile configuration is chosen (and tuned) as for mlk_matmul of the same
+ * shape.
+ */
+mlk_status mlk_matmul_bias(mlk_dtype in, mlk_dtype out, int64_t M, int64_t N, int64_t K,
+                           const void* A, int64_t lda, const void* B, int64_t ldb,
+                           const float* bias, void* C, int64_t ldc, const float* scale_a,
+                           const float* scale_b, int accumulate, const mlk_tile_config* cfg,
+                           void* stream);
 
 /*
  * y[n,f,oh,ow] (+)= sum_{c,kh,kw} x[n,c,oh*sh-ph+kh, ow*sw-pw+kw] * w[f,c,kh,kw]

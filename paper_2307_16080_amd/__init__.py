@@ -23,7 +23,7 @@ from ._lib import (MLK_BATCH_GRAPH, MLK_BATCH_PERSISTENT, MLK_BF16, MLK_F8E4M3, 
                    MLK_TUNE_ES, MLK_TUNE_MODEL, MLK_TUNE_RANDOM, GemmDesc, MlkError, Problem, TileConfig,
                    TuneOpts, TuneReport)
 
-__all__ = ["matmul", "conv2d_nchw_fchw", "quantize", "batched_matmul", "BatchedCall", "err_stats", "tune",
+__all__ = ["matmul", "matmul_bias", "conv2d_nchw_fchw", "quantize", "batched_matmul", "BatchedCall", "err_stats", "tune",
            "config_count", "configs", "config_legal", "set_default_config", "CostModel",
            "mlp_forward", "mlp_loss_grad", "adam_step", "release", "version", "TileConfig",
            "Problem", "MlkError", "matmul_problem", "conv_problem", "batched_problem"]
@@ -82,7 +82,8 @@ def matmul(A, B, C, accumulate: bool = True, cfg=None, scale_a=None, scale_b=Non
     """C (+)= A @ B.  A: (M, K), B: (K, N), C: (M, N), row-major CUDA tensors.
 
     (float32, float32), (bfloat16, float32), (float8_e4m3fn, float32) with optional
-    device scale tensors, (int8, int32)."""
+    device scale tensors, (int8, int32); bfloat16 C with bfloat16 or float8_e4m3fn
+    inputs (the fp32 result rounded once to bf16; split_k 1)."""
     M, K = A.shape
     K2, N = B.shape
     if K2 != K or tuple(C.shape) != (M, N):
@@ -90,6 +91,24 @@ def matmul(A, B, C, accumulate: bool = True, cfg=None, scale_a=None, scale_b=Non
     L.check(L.lib().mlk_matmul(_dt(A), _dt(C), M, N, K, _ptr(A), _row_major_ld(A), _ptr(B),
                                _row_major_ld(B), _ptr(C), _row_major_ld(C), _ptr(scale_a),
                                _ptr(scale_b), int(bool(accumulate)), _cfg(cfg), _stream(stream)))
+    return C
+
+
+def matmul_bias(A, B, bias, C, accumulate: bool = False, cfg=None, scale_a=None, scale_b=None,
+                stream=None):
+    """The Linear layer: C (+)= A @ B + bias, the bias add fused into the product's output.
+
+    bias: float32 CUDA tensor of N elements.  Float outputs only (the float pairs of matmul)."""
+    M, K = A.shape
+    K2, N = B.shape
+    if K2 != K or tuple(C.shape) != (M, N):
+        raise MlkError(2, f"shape mismatch: A {tuple(A.shape)}, B {tuple(B.shape)}, C {tuple(C.shape)}")
+    if bias.dtype != torch.float32 or bias.numel() != N or not bias.is_contiguous():
+        raise MlkError(2, f"bias must be {N} contiguous float32 values")
+    L.check(L.lib().mlk_matmul_bias(_dt(A), _dt(C), M, N, K, _ptr(A), _row_major_ld(A), _ptr(B),
+                                    _row_major_ld(B), _ptr(bias), _ptr(C), _row_major_ld(C),
+                                    _ptr(scale_a), _ptr(scale_b), int(bool(accumulate)), _cfg(cfg),
+                                    _stream(stream)))
     return C
 
 

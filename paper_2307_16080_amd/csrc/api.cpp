@@ -89,6 +89,9 @@ int dt_of(mlk_dtype in, mlk_dtype out, int conv, bool* ok) {
     if (in == MLK_F32 && out == MLK_F32) return DT_F32;
     if (in == MLK_BF16 && out == MLK_F32) return DT_BF16;
     if (!conv && in == MLK_F8E4M3 && out == MLK_F32) return DT_F8;
+    // bf16 results (matmul only): the input type picks the kernel
+    if (!conv && in == MLK_BF16 && out == MLK_BF16) return DT_BF16;
+    if (!conv && in == MLK_F8E4M3 && out == MLK_BF16) return DT_F8;
     if (!conv && in == MLK_I8 && out == MLK_I32) return DT_I8;
     *ok = false;
     return -1;
@@ -132,6 +135,7 @@ mlk_status shape_of_problem(const mlk_problem* p, Shape* s) {
         return fail(MLK_ERR_ARG, "unknown op %d", p->op);
     s->dt = dt_of((mlk_dtype)p->in, (mlk_dtype)p->out, s->conv, &ok);
     if (!ok) return fail(MLK_ERR_DTYPE, "unsupported dtype pair (%d, %d) for op %d", p->in, p->out, p->op);
+    s->out16 = p->out == MLK_BF16 ? 1 : 0;
     if (p->op == MLK_OP_MATMUL) {
         if (p->M < 0 || p->N < 0 || p->K < 0) return fail(MLK_ERR_SHAPE, "negative matmul dimension");
         if (p->M > kMaxDim || p->N > kMaxDim || p->K > kMaxDim)
@@ -156,8 +160,8 @@ mlk_status shape_of_problem(const mlk_problem* p, Shape* s) {
     } else {
         if (p->count < 1) return fail(MLK_ERR_SHAPE, "batched: count must be >= 1");
         if (!p->descs) return fail(MLK_ERR_NULL, "batched: descs is NULL");
-        if (s->dt != DT_BF16 && s->dt != DT_F32)
-            return fail(MLK_ERR_DTYPE, "batched: only bf16 and f32 inputs are supported");
+        if ((s->dt != DT_BF16 && s->dt != DT_F32) || s->out16)
+            return fail(MLK_ERR_DTYPE, "batched: only bf16 and f32 inputs with fp32 outputs are supported");
         int64_t mm = 0, nn = 0, kk = 0;
         for (int64_t i = 0; i < p->count; ++i) {
             const mlk_gemm_desc& d = p->descs[i];
@@ -213,6 +217,11 @@ mlk_status check_config(const Shape& s, int op, const mlk_tile_config& c) {
     const int64_t stages = cdiv(std::max<int64_t>(s.K, 1), c.bk);
     if (c.split_k > 1 && c.split_k > stages)
         return fail(MLK_ERR_CONFIG, "split_k %d exceeds the %lld K stages", c.split_k, (long long)stages);
+    if (c.split_k > 1 && s.out16)
+        return fail(MLK_ERR_CONFIG, "a bf16 output is rounded once from the whole sum: split_k must be 1");
+    if (s.out16 && e->stages == 1)
+        return fail(MLK_ERR_CONFIG, "a bf16 output is written by the direct-to-LDS (stages >= 2) and plain "
+                    "(stages 0) tiles, not the register-loaded fast tiles");
     if (c.group_m < 0 || c.group_m > 64) return fail(MLK_ERR_CONFIG, "group_m must be in [0, 64]");
     if (c.xcd_remap != 0 && c.xcd_remap != 1) return fail(MLK_ERR_CONFIG, "xcd_remap must be 0 or 1");
     if (is_direct(e)) {
@@ -245,6 +254,7 @@ std::vector<mlk_tile_config> enumerate_configs(const mlk_problem* p, const Shape
             continue;
         }
         if (e->stages >= 2 && !batched && !fast_shape_ok(s, e->bk)) continue;
+        if (s.out16 && e->stages == 1) continue;
         // a tile at least twice the problem in a dimension only adds padding
         if (e->bm > 32 && e->bm >= 2 * s.M) continue;
         if (e->bn > 32 && e->bn >= 2 * s.N) continue;
@@ -252,7 +262,7 @@ std::vector<mlk_tile_config> enumerate_configs(const mlk_problem* p, const Shape
         const int64_t tiles = cdiv(std::max<int64_t>(s.M, 1), e->bm) * cdiv(std::max<int64_t>(s.N, 1), e->bn);
         const int64_t tm = cdiv(std::max<int64_t>(s.M, 1), e->bm);
         for (int sk : {1, 2, 4, 8}) {
-            if (batched && sk > 1) break;
+            if ((batched || s.out16) && sk > 1) break;
             if (sk > 1 && stages < 2 * sk) break;
             for (int gm : {1, 8}) {
                 if (gm == 8 && (batched || tm < 16)) continue;
@@ -312,7 +322,7 @@ mlk_tile_config heuristic_config(const Shape& s, int op) {
     }
     // channels-last pays a transpose of the input: worth it for large images
     if (s.conv && e->launch_nhwc && s.conv_c % (16 / esize_in(s.dt)) == 0 && s.N >= 16384) c.layout = 1;
-    if (!best && op != MLK_OP_BATCHED) {
+    if (!best && op != MLK_OP_BATCHED && !s.out16) {
         // too few tiles: split K while each split keeps >= 4 stages
         const int64_t tiles = cdiv(std::max<int64_t>(s.M, 1), e->bm) * cdiv(std::max<int64_t>(s.N, 1), e->bn);
         const int64_t stages = cdiv(std::max<int64_t>(s.K, 1), e->bk);
@@ -397,19 +407,23 @@ static GemmArgs base_args(const Shape& s, const mlk_tile_config& cfg) {
     g.tiles_n = (int32_t)cdiv(s.N, cfg.bn);
     g.group_m = cfg.group_m < 1 ? 1 : cfg.group_m;
     g.xcd_remap = cfg.xcd_remap;
+    g.out_bf16 = s.out16;
     return g;
 }
 
 static mlk_status run_gemm(const KernelEntry* e, GemmArgs& g, const Shape& s, void* C, int64_t M,
                            int64_t N, int64_t ldc, hipStream_t st) {
-    const int esz = 4;  // every output type is 32-bit
+    const int esz = 4;  // split K (the only zeroing route) has 32-bit outputs
     if (!e->launch) return fail(MLK_ERR_CONFIG, "this conv tile runs only the channels-last layout (layout 1)");
     if (g.atomic && !s.accumulate) {
         hipError_t z = launch_zero_matrix(C, M, N, ldc, esz, st);
         if (z != hipSuccess) return hip_fail(z, "zero output");
     }
+    // a bias or a bf16 C takes the entry's extended-epilogue variant
+    const launch_fn fn = (g.bias || g.out_bf16) ? e->launch_epi : e->launch;
+    if (!fn) return fail(MLK_ERR_CONFIG, "this tile has no bias / bf16-output variant");
     const int64_t nblk = (int64_t)g.tiles_m * g.tiles_n * g.split_k;
-    hipError_t err = e->launch(g, (int)nblk, st);
+    hipError_t err = fn(g, (int)nblk, st);
     if (err != hipSuccess) return hip_fail(err, "kernel launch");
     return MLK_OK;
 }
@@ -428,7 +442,7 @@ static mlk_status refuse_under_capture(hipStream_t st, const char* what) {
 
 mlk_status launch_dense(const Shape& s, const void* A, int64_t lda, const void* B, int64_t ldb,
                         void* C, int64_t ldc, const float* sa, const float* sb,
-                        const mlk_tile_config& cfg, hipStream_t st) {
+                        const mlk_tile_config& cfg, hipStream_t st, const float* bias) {
     const KernelEntry* e = find_kernel(s.dt, 0, cfg);
     if (!e) return fail(MLK_ERR_CONFIG, "no kernel for configuration");
     if (s.M == 0 || s.N == 0) return MLK_OK;
@@ -442,6 +456,7 @@ mlk_status launch_dense(const Shape& s, const void* A, int64_t lda, const void* 
     g.ldc = ldc;
     g.scale_a = sa;
     g.scale_b = sb;
+    g.bias = bias;
     g.vec_a = ((uintptr_t)A % 16 == 0) && ((lda * es) % 16 == 0);
     g.vec_b = ((uintptr_t)B % 16 == 0) && ((ldb * es) % 16 == 0);
     if (e->stages < 2 || s.K == 0) return run_gemm(e, g, s, C, s.M, s.N, ldc, st);
@@ -594,11 +609,11 @@ const char* mlk_last_error(void) { return t_err.c_str(); }
 
 const char* mlk_version(void) { return "mlk 0.1 (gfx950)"; }
 
-mlk_status mlk_matmul(mlk_dtype in, mlk_dtype out, int64_t M, int64_t N, int64_t K,
-                      const void* A, int64_t lda, const void* B, int64_t ldb, void* C,
-                      int64_t ldc, const float* scale_a, const float* scale_b, int accumulate,
-                      const mlk_tile_config* cfg, void* stream) {
-    clear_error();
+static mlk_status matmul_impl(mlk_dtype in, mlk_dtype out, int64_t M, int64_t N, int64_t K,
+                              const void* A, int64_t lda, const void* B, int64_t ldb, void* C,
+                              int64_t ldc, const float* scale_a, const float* scale_b,
+                              const float* bias, int accumulate, const mlk_tile_config* cfg,
+                              void* stream) {
     mlk_problem p;
     memset(&p, 0, sizeof p);
     p.op = MLK_OP_MATMUL;
@@ -618,9 +633,10 @@ mlk_status mlk_matmul(mlk_dtype in, mlk_dtype out, int64_t M, int64_t N, int64_t
     if (lda < std::max<int64_t>(K, 1) || ldb < std::max<int64_t>(N, 1) || ldc < std::max<int64_t>(N, 1))
         return fail(MLK_ERR_LAYOUT, "matmul: leading dimension too small (lda %lld >= K %lld, ldb %lld >= N, ldc %lld >= N %lld)",
                     (long long)lda, (long long)K, (long long)ldb, (long long)ldc, (long long)N);
+    const int cs = s.out16 ? 2 : 4;  // bytes per element of C
     if (M > 0 && N > 0 && K > 0) {
         const int es = esize_in(s.dt);
-        const size_t cb = (size_t)((M - 1) * ldc + N) * 4;
+        const size_t cb = (size_t)((M - 1) * ldc + N) * cs;
         const size_t ab = (size_t)((M - 1) * lda + K) * es;
         const size_t bb = (size_t)((K - 1) * ldb + N) * es;
         if (overlaps(C, cb, A, ab) || overlaps(C, cb, B, bb))
@@ -628,11 +644,36 @@ mlk_status mlk_matmul(mlk_dtype in, mlk_dtype out, int64_t M, int64_t N, int64_t
     }
     if ((scale_a || scale_b) && s.dt != DT_F8)
         return fail(MLK_ERR_ARG, "matmul: scales apply to MLK_F8E4M3 inputs only");
+    if (bias && M > 0 && N > 0) {
+        if (s.dt == DT_I8) return fail(MLK_ERR_DTYPE, "matmul_bias: the bias applies to float outputs only");
+        if (overlaps(C, (size_t)((M - 1) * ldc + N) * cs, bias, (size_t)N * 4))
+            return fail(MLK_ERR_LAYOUT, "matmul_bias: C overlaps bias");
+    }
     mlk_tile_config c;
     st = resolve(p, s, cfg, &c);
     if (st != MLK_OK) return st;
     if (M == 0 || N == 0) return MLK_OK;
-    return launch_dense(s, A, lda, B, ldb, C, ldc, scale_a, scale_b, c, (hipStream_t)stream);
+    return launch_dense(s, A, lda, B, ldb, C, ldc, scale_a, scale_b, c, (hipStream_t)stream, bias);
+}
+
+mlk_status mlk_matmul(mlk_dtype in, mlk_dtype out, int64_t M, int64_t N, int64_t K,
+                      const void* A, int64_t lda, const void* B, int64_t ldb, void* C,
+                      int64_t ldc, const float* scale_a, const float* scale_b, int accumulate,
+                      const mlk_tile_config* cfg, void* stream) {
+    clear_error();
+    return matmul_impl(in, out, M, N, K, A, lda, B, ldb, C, ldc, scale_a, scale_b, nullptr,
+                       accumulate, cfg, stream);
+}
+
+mlk_status mlk_matmul_bias(mlk_dtype in, mlk_dtype out, int64_t M, int64_t N, int64_t K,
+                           const void* A, int64_t lda, const void* B, int64_t ldb,
+                           const float* bias, void* C, int64_t ldc, const float* scale_a,
+                           const float* scale_b, int accumulate, const mlk_tile_config* cfg,
+                           void* stream) {
+    clear_error();
+    if (!bias && M > 0 && N > 0) return fail(MLK_ERR_NULL, "matmul_bias: bias is NULL");
+    return matmul_impl(in, out, M, N, K, A, lda, B, ldb, C, ldc, scale_a, scale_b, bias,
+                       accumulate, cfg, stream);
 }
 
 mlk_status mlk_conv2d_nchw_fchw(mlk_dtype in, mlk_dtype out, int64_t N, int64_t C, int64_t H,

@@ -27,16 +27,7 @@ inline int grid_for(int64_t items, int per_block_items) {
 }
 
 // ------------------------------------------------------------------ bf16
-
-__device__ inline uint16_t bf16_rne(float f) {
-    const uint32_t u = __float_as_uint(f);
-    if ((u & 0x7F800000u) == 0x7F800000u && (u & 0x007FFFFFu) != 0)
-        return (uint16_t)(((u >> 16) & 0x8000u) | 0x7FC0u);  // quiet NaN, sign kept
-    // add half an ulp of the kept part (minus one when the kept lsb is even),
-    // then truncate: round to nearest, ties to even; overflow carries to inf
-    const uint32_t r = u + 0x7FFFu + ((u >> 16) & 1u);
-    return (uint16_t)(r >> 16);
-}
+// (bf16_rne, the rounding shared with the GEMM epilogues, is in gemm_tile.hpp)
 
 __global__ __launch_bounds__(kThreads) void k_quant_bf16(const float* __restrict__ x, int64_t n,
                                                          uint16_t* __restrict__ q) {

@@ -43,6 +43,19 @@ typedef int i8_t __attribute__((ext_vector_type(8)));
 typedef __bf16 bf8_t __attribute__((ext_vector_type(8)));
 typedef uint32_t u4_t __attribute__((ext_vector_type(4)));
 
+// fp32 -> bf16 code: round to nearest, ties to even; a NaN stays a quiet NaN
+// with its sign, overflow rounds to inf.  Adding 0x7FFF plus the kept part's
+// lowest bit and truncating rounds half-way cases to the even neighbour.
+__device__ inline uint16_t bf16_rne(float f) {
+    const uint32_t u = __float_as_uint(f);
+    if ((u & 0x7F800000u) == 0x7F800000u && (u & 0x007FFFFFu) != 0)
+        return (uint16_t)(((u >> 16) & 0x8000u) | 0x7FC0u);
+    const uint32_t r = u + 0x7FFFu + ((u >> 16) & 1u);
+    return (uint16_t)(r >> 16);
+}
+// bf16 code -> its (exact) fp32 value
+__device__ inline float bf16_value(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
+
 template <int DT> struct Traits;
 template <> struct Traits<DT_F32> {
     static constexpr int ES = 4;   // element size (bytes)
@@ -89,6 +102,13 @@ struct GemmArgs {
     int32_t group_m, xcd_remap;
     // convolution view (conv policy only)
     int32_t cn, cc, ch, cw, ckh, ckw, csh, csw, cph, cpw, cho, cwo;
+    // Linear layer: bias[n] added to every row of the product (float outputs,
+    // GEMM policy only); null for a plain product.  Under split K only the
+    // first split adds it.
+    const float* bias;
+    // 1: C holds bf16 codes (float results rounded once, to nearest even;
+    // GEMM policy only, split_k 1); accumulate reads them back as fp32
+    int32_t out_bf16;
 };
 
 // ---------------------------------------------------------------- MFMA step
@@ -249,7 +269,9 @@ __device__ inline void tile_coords(const GemmArgs& g, int bid, int nblk, int& tm
 // ordered (kh, kw, c); with C a multiple of the 16-byte vector, every B load
 // is one aligned 16-byte read of consecutive channels, stored into LDS as is
 // (no transpose).  The output is NFHW in both conv policies.
-template <int DT, int BM, int BN, int KB, int WM, int WN, int CONV>
+// EPI = 1 builds the Linear / bf16-output epilogue (bias add, bf16 C); the
+// plain product (EPI = 0) compiles without either.
+template <int DT, int BM, int BN, int KB, int WM, int WN, int CONV, int EPI = 0>
 struct Tile {
     typedef Traits<DT> T;
     typedef typename T::acc_t acc_t;
@@ -535,7 +557,8 @@ struct Tile {
         // C += A B: start the accumulators from C (read here, next to the first
         // loads, rather than in a read-add-write epilogue).  e4m3 scales the
         // product and int8 must wrap modulo 2^32 exactly, so both keep C apart.
-        const bool c_in_acc = DT != DT_F8 && DT != DT_I8 && g.accumulate && !g.atomic;
+        // (a bf16 C is read in the epilogue instead)
+        const bool c_in_acc = DT != DT_F8 && DT != DT_I8 && g.accumulate && !g.atomic && !(EPI && g.out_bf16);
 #pragma unroll
         for (int j = 0; j < TN; ++j) {
             int64_t cbase = 0, rstride = 0;
@@ -617,10 +640,37 @@ struct Tile {
             if (g.scale_a) alpha *= *g.scale_a;
             if (g.scale_b) alpha *= *g.scale_b;
         }
+        if constexpr (EPI && DT != DT_I8 && CONV == 0) {
+            if (g.out_bf16) {
+                // bf16 C (never split): fp32 result, plus the bf16 C when
+                // accumulating, rounded once
+                MLK_GLOBAL uint16_t* const Cb = (MLK_GLOBAL uint16_t*)g.C;
+#pragma unroll
+                for (int j = 0; j < TN; ++j) {
+                    const int64_t n = n0 + wx * WTN + j * 16 + lr;
+                    if (n >= g.N) continue;
+                    const float bn = g.bias && kz == 0 ? g.bias[n] : 0.0f;
+#pragma unroll
+                    for (int i = 0; i < TM; ++i)
+#pragma unroll
+                        for (int r = 0; r < 4; ++r) {
+                            const int64_t m = m0 + wy * WTM + i * 16 + lg * 4 + r;
+                            if (m >= g.M) continue;
+                            MLK_GLOBAL uint16_t* q = Cb + m * g.ldc + n;
+                            const float v = ((DT == DT_F8) ? alpha * acc[i][j][r] : acc[i][j][r]) + bn;
+                            *q = bf16_rne(g.accumulate ? bf16_value(*q) + v : v);
+                        }
+                }
+                return;
+            }
+        }
 #pragma unroll
         for (int j = 0; j < TN; ++j) {
             const int64_t n = n0 + wx * WTN + j * 16 + lr;
             if (n >= g.N) continue;
+            float bn = 0.0f;
+            if constexpr (EPI && DT != DT_I8 && CONV == 0)
+                if (g.bias && kz == 0) bn = g.bias[n];
             int64_t cbase = n;   // offset of column n (row 0)
             int64_t rstride = g.ldc;
             if constexpr (CONV != 0) {
@@ -641,7 +691,8 @@ struct Tile {
                         if (g.atomic) __hip_atomic_fetch_add((MLK_GLOBAL uint32_t*)p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                         else *p = (int32_t)(g.accumulate ? (uint32_t)*p + v : v);
                     } else {
-                        const float v = (DT == DT_F8) ? alpha * acc[i][j][r] : acc[i][j][r];
+                        const float v0 = (DT == DT_F8) ? alpha * acc[i][j][r] : acc[i][j][r];
+                        const float v = EPI ? v0 + bn : v0;
                         if (g.atomic) __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                         else if (c_in_acc || !g.accumulate) *p = v;
                         else *p = *p + v;

@@ -28,6 +28,7 @@ struct Shape {
     int conv = 0;
     int64_t M = 0, N = 0, K = 0;
     int accumulate = 1;
+    int out16 = 0;        // 1: C holds bf16 (matmul only)
     int64_t conv_c = 0;   // conv: input channels
     int64_t conv_in = 0;  // conv: input elements N*C*H*W
     int conv_kh = 0, conv_kw = 0, conv_sh = 0, conv_sw = 0;  // conv: filter taps and strides
@@ -55,7 +56,7 @@ void store_default(const std::string& key, const mlk_tile_config& c);
 // launch one contraction with a resolved configuration
 mlk_status launch_dense(const Shape& s, const void* A, int64_t lda, const void* B, int64_t ldb,
                         void* C, int64_t ldc, const float* sa, const float* sb,
-                        const mlk_tile_config& cfg, hipStream_t st);
+                        const mlk_tile_config& cfg, hipStream_t st, const float* bias = nullptr);
 mlk_status launch_conv(const Shape& s, int64_t n, int64_t c, int64_t h, int64_t w, int64_t f,
                        int64_t kh, int64_t kw, int sh, int sw, int ph, int pw, int64_t ho,
                        int64_t wo, const void* x, const void* wt, void* y,

@@ -47,11 +47,12 @@ struct KernelEntry {
     persist_fn persist;  // null where no persistent variant is built
     launch_fn launch_nhwc;  // conv entries: the channels-last variant (CONV = 2)
     occupancy_fn occupancy; // with persist: resident workgroups per CU
+    launch_fn launch_epi;   // GEMM entries: the bias / bf16-output epilogue variant (EPI = 1)
 };
 
-template <int DT, int BM, int BN, int KB, int WM, int WN, int CONV>
+template <int DT, int BM, int BN, int KB, int WM, int WN, int CONV, int EPI = 0>
 __global__ __launch_bounds__(64 * WM * WN) void k_gemm(GemmArgs g) {
-    typedef Tile<DT, BM, BN, KB, WM, WN, CONV> TL;
+    typedef Tile<DT, BM, BN, KB, WM, WN, CONV, EPI> TL;
     __shared__ __attribute__((aligned(16))) uint8_t lds[TL::LDS_BYTES];
     int tm, tn, kz;
     tile_coords(g, blockIdx.x, gridDim.x, tm, tn, kz);
@@ -88,9 +89,9 @@ __global__ __launch_bounds__(64 * WM * WN) void k_gemm_persist(const GemmArgs* _
     }
 }
 
-template <int DT, int BM, int BN, int WM, int WN, int STAGES>
+template <int DT, int BM, int BN, int WM, int WN, int STAGES, int EPI = 0>
 __global__ __launch_bounds__(64 * WM * WN) void k_gemm_fast(GemmArgs g) {
-    typedef FastGemm<DT, BM, BN, WM, WN, STAGES> TL;
+    typedef FastGemm<DT, BM, BN, WM, WN, STAGES, 0, EPI> TL;
     __shared__ __attribute__((aligned(1024))) uint8_t lds[TL::LDS_BYTES];
     int tm, tn, kz;
     tile_coords(g, blockIdx.x, gridDim.x, tm, tn, kz);
@@ -113,9 +114,9 @@ hipError_t launch_fast_conv(const GemmArgs& g, int nblk, hipStream_t s) {
     return hipGetLastError();
 }
 
-template <int DT, int BM, int BN, int WM, int WN, int STAGES>
+template <int DT, int BM, int BN, int WM, int WN, int STAGES, int EPI = 0>
 hipError_t launch_fast(const GemmArgs& g, int nblk, hipStream_t s) {
-    hipLaunchKernelGGL((k_gemm_fast<DT, BM, BN, WM, WN, STAGES>), dim3(nblk), dim3(64 * WM * WN), 0,
+    hipLaunchKernelGGL((k_gemm_fast<DT, BM, BN, WM, WN, STAGES, EPI>), dim3(nblk), dim3(64 * WM * WN), 0,
                        s, g);
     return hipGetLastError();
 }
@@ -164,9 +165,9 @@ int occupancy_fast_persist() {
     return occupancy_of(k_fast_persist<DT, BM, BN, WM, WN, STAGES>, 64 * WM * WN);
 }
 
-template <int DT, int BM, int BN, int KB, int WM, int WN, int CONV>
+template <int DT, int BM, int BN, int KB, int WM, int WN, int CONV, int EPI = 0>
 hipError_t launch_gemm(const GemmArgs& g, int nblk, hipStream_t s) {
-    hipLaunchKernelGGL((k_gemm<DT, BM, BN, KB, WM, WN, CONV>), dim3(nblk), dim3(64 * WM * WN), 0,
+    hipLaunchKernelGGL((k_gemm<DT, BM, BN, KB, WM, WN, CONV, EPI>), dim3(nblk), dim3(64 * WM * WN), 0,
                        s, g);
     return hipGetLastError();
 }
@@ -184,7 +185,8 @@ hipError_t launch_persist(const GemmArgs* gemms, const Task* tasks, const int32_
         DT, (CONV) ? 1 : 0, 0, BM, BN, (KB) / Traits<DT>::ES, WM, WN,                          \
             Tile<DT, BM, BN, KB, WM, WN, (CONV) ? 1 : 0>::LDS_BYTES, 64 * (WM) * (WN),         \
             &launch_gemm<DT, BM, BN, KB, WM, WN, (CONV) ? 1 : 0>, nullptr,                     \
-            (CONV) ? &launch_gemm<DT, BM, BN, KB, WM, WN, 2> : nullptr, nullptr               \
+            (CONV) ? &launch_gemm<DT, BM, BN, KB, WM, WN, 2> : nullptr, nullptr,              \
+            (CONV) ? nullptr : &launch_gemm<DT, BM, BN, KB, WM, WN, 0, 1>                      \
     }
 
 #define MLK_ENTRY_P(DT, BM, BN, KB, WM, WN)                                                  \
@@ -192,7 +194,8 @@ hipError_t launch_persist(const GemmArgs* gemms, const Task* tasks, const int32_
         DT, 0, 0, BM, BN, (KB) / Traits<DT>::ES, WM, WN,                                     \
             Tile<DT, BM, BN, KB, WM, WN, 0>::LDS_BYTES, 64 * (WM) * (WN),                    \
             &launch_gemm<DT, BM, BN, KB, WM, WN, 0>, &launch_persist<DT, BM, BN, KB, WM, WN>,  \
-            nullptr, &occupancy_persist<DT, BM, BN, KB, WM, WN>                              \
+            nullptr, &occupancy_persist<DT, BM, BN, KB, WM, WN>,                             \
+            &launch_gemm<DT, BM, BN, KB, WM, WN, 0, 1>                                       \
     }
 
 #define MLK_ENTRY_FAST(DT, BM, BN, WM, WN, STAGES)                                           \
@@ -201,7 +204,8 @@ hipError_t launch_persist(const GemmArgs* gemms, const Task* tasks, const int32_
             FastGemm<DT, BM, BN, WM, WN, STAGES>::LDS_BYTES, 64 * (WM) * (WN),               \
             &launch_fast<DT, BM, BN, WM, WN, STAGES>,                                        \
             &launch_fast_persist<DT, BM, BN, WM, WN, STAGES>, nullptr,                       \
-            &occupancy_fast_persist<DT, BM, BN, WM, WN, STAGES>                              \
+            &occupancy_fast_persist<DT, BM, BN, WM, WN, STAGES>,                             \
+            &launch_fast<DT, BM, BN, WM, WN, STAGES, 1>                                      \
     }
 
 // conv entry: channels-last layout only (launch_nhwc); no NCHW form, no persistent form

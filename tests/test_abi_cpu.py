@@ -75,6 +75,46 @@ def test_matmul_validation():
     assert _mm(K=32, lda=32, cfg=ctypes.byref(bad))[0] == 5
 
 
+def _mmb(**kw):
+    args = dict(inp=L.MLK_F32, out=L.MLK_F32, M=4, N=4, K=4, A=0x1000, lda=4, B=0x2000, ldb=4,
+                bias=0x4000, C=0x3000, ldc=4, sa=NULL, sb=NULL, acc=0, cfg=NULL)
+    args.update(kw)
+    st = L.lib().mlk_matmul_bias(args["inp"], args["out"], args["M"], args["N"], args["K"], args["A"],
+                                 args["lda"], args["B"], args["ldb"], args["bias"], args["C"], args["ldc"],
+                                 args["sa"], args["sb"], args["acc"], args["cfg"], NULL)
+    return st, L.lib().mlk_last_error().decode()
+
+
+def test_matmul_bias_validation():
+    assert _mmb(bias=NULL)[0] == 1
+    assert _mmb(M=-1)[0] == 2
+    assert _mmb(ldc=2)[0] == 3
+    assert _mmb(inp=L.MLK_I8, out=L.MLK_I32)[0] == 4   # integer outputs take no bias
+    st, msg = _mmb(bias=0x3008)                         # bias inside C
+    assert st == 3 and "bias" in msg
+    assert _mmb(sa=0x5000)[0] == 9
+    # M == 0 (nothing to write) accepts a NULL bias, as mlk_matmul accepts NULL operands
+    assert _mmb(M=0, bias=NULL)[0] == 0
+
+
+def test_bf16_output_pairs_and_split_rule():
+    # bf16 C from bf16 or e4m3 inputs (matmul only); a bf16 result is not split over K
+    assert _mm(inp=L.MLK_BF16, out=L.MLK_BF16, acc=0, A=0x10000, B=0x20000, C=0x30000)[0] != 4
+    for inp in (L.MLK_BF16, L.MLK_F8E4M3):
+        p = mlk.matmul_problem(256, 256, 4096, inp, L.MLK_BF16)
+        cfgs = mlk.configs(p)
+        assert cfgs and all(c.split_k == 1 and c.stages != 1 for c in cfgs)
+        c = cfgs[0]
+        split = mlk.TileConfig(c.bm, c.bn, c.bk, c.wm, c.wn, 2, 1, 0, c.stages, c.layout)
+        assert not mlk.config_legal(p, split)
+        assert mlk.config_legal(mlk.matmul_problem(256, 256, 4096, inp, L.MLK_F32), split)
+    assert _mm(inp=L.MLK_F32, out=L.MLK_BF16)[0] == 4
+    assert _mm(inp=L.MLK_I8, out=L.MLK_BF16)[0] == 4
+    # C overlap is measured in bf16 elements: 4 x 4 bf16 C at 0x3000 ends at 0x3020
+    assert _mm(inp=L.MLK_BF16, out=L.MLK_BF16, A=0x3020, B=0x6000)[0] != 3
+    assert _mm(inp=L.MLK_BF16, out=L.MLK_BF16, A=0x301E, B=0x6000)[0] == 3
+
+
 def test_conv_quant_err_validation():
     lib = L.lib()
     conv = lambda **k: lib.mlk_conv2d_nchw_fchw(
@@ -86,6 +126,7 @@ def test_conv_quant_err_validation():
     assert conv(KH=9) == 2            # filter larger than the padded image
     assert conv(x=NULL) == 1
     assert conv(inp=L.MLK_I8, out=L.MLK_I32) == 4
+    assert conv(inp=L.MLK_BF16, out=L.MLK_BF16) == 4   # bf16 outputs: matmul only
     assert conv(y=0x1004) == 3        # y overlapping x
     assert lib.mlk_quantize(L.MLK_F32, 4, 0x1000, 0x2000, 0x3000, NULL) == 4
     assert lib.mlk_quantize(L.MLK_F8E4M3, 4, 0x1000, 0x2000, NULL, NULL) == 1

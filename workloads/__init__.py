@@ -56,6 +56,17 @@ def random_c(M: int, N: int, seed: int, dtype=np.float32):
     return rng.uniform(-1.0, 1.0, (M, N)).astype(dtype)
 
 
+def linear_bias(N: int, seed: int, dist: str = "normal"):
+    """The bias vector of a Linear layer (N float32 values).
+
+    dist: "normal" standard normal; "small_int" integers uniform in [-8, 8]
+    (sums with small-integer products stay exact in fp32)."""
+    rng = np.random.default_rng(seed + 104729)
+    if dist == "small_int":
+        return rng.integers(-8, 9, N).astype(np.float32)
+    return rng.standard_normal(N).astype(np.float32)
+
+
 # --------------------------------------------------------------------------- conv
 
 def conv_inputs(N: int, C: int, H: int, W: int, F: int, KH: int, KW: int, seed: int = 0,
