@@ -238,9 +238,13 @@ def main():
         bp, _, _ = mlk.tune(pp, mlk.MLK_TUNE_EXHAUSTIVE, reps=10, warmup=2)
         us = time_us(lambda: mlk.conv2d_nchw_fchw(xpd, wpd, yp, (1, 1), (0, 0), cfg=bp), 50)
         pbytes = 4 * (1280 * 1280 + 3 * 9 + 2 * 3 * 1278 * 1278)
+        # context, as the paper set its kernel beside the framework's: PyTorch's own
+        # fp32 conv of the same tensors on this GPU (MIOpen; a new output each call)
+        us_torch = time_us(lambda: torch.nn.functional.conv2d(xpd, wpd), 50)
         rows_out["conv_f32_paper_1280x1280x3"] = {"us": round(us, 2), "GB/s": round(pbytes / us / 1e3, 1),
                                                   "frac_hbm": round(pbytes / us / 1e3 / PEAK["hbm_gbs"], 3),
-                                                  "bytes": pbytes, "tile": list(bp.as_tuple())}
+                                                  "bytes": pbytes, "tile": list(bp.as_tuple()),
+                                                  "torch_conv2d_us_context": round(us_torch, 2)}
         # 256 uneven bf16 GEMMs
         shapes = batched_shapes(256, seed=0)
         ins = batched_inputs(shapes, seed=1)
