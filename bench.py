@@ -133,6 +133,18 @@ def main():
     value = flops / (ms_per_step * 1e-3) / 1e12
     achieved = flops / (kernel_us * 1e-6) / 1e12
     log(f"bf16 GEMM: {kernel_us:.1f} us/launch (events), {ms_per_step * 1e3:.1f} us/step (wall)")
+    # spread of single launches (after the timed region, not part of it): each
+    # launch between its own pair of events, back to back
+    evs = [torch.cuda.Event(enable_timing=True) for _ in range(2 * args.steps)]
+    for i in range(args.steps):
+        evs[2 * i].record(stream)
+        mlk.matmul(qa, qb, C, cfg=best)
+        evs[2 * i + 1].record(stream)
+    torch.cuda.synchronize()
+    per = sorted(evs[2 * i].elapsed_time(evs[2 * i + 1]) * 1e3 for i in range(args.steps))
+    pct = lambda q: per[min(len(per) - 1, int(q * (len(per) - 1) + 0.5))]
+    launch_pcts = {"p10": round(pct(0.1), 1), "median": round(pct(0.5), 1), "p90": round(pct(0.9), 1),
+                   "n": len(per)}
 
     # one clean launch of the timed configuration, kept for the error report
     C.zero_()
@@ -168,6 +180,7 @@ def main():
                    "tile": list(best.as_tuple()), "global_batch": 1, "parallelism": "none (1 GPU)"},
         "roofline": {"bound": "mfma", "achieved": round(achieved, 2), "peak": PEAK["bf16"],
                      "unit": "TFLOP/s", "frac": round(achieved / PEAK["bf16"], 4), "traffic": traffic},
+        "launch_us": launch_pcts,
     }
 
     # ---------------------------------------------------------------- other rows
@@ -201,8 +214,13 @@ def main():
         bias = torch.from_numpy(linear_bias(N, seed=0)).cuda()
         us_lin = time_us(lambda: mlk.matmul_bias(qa, qb, bias, C, accumulate=False, cfg=best), 20)
         us_ow = time_us(lambda: mlk.matmul(qa, qb, C, accumulate=False, cfg=best), 20)
+        # the same Linear writing a bf16 output (rounded once from the fp32 sum)
+        Y16 = torch.empty(M, N, dtype=torch.bfloat16, device="cuda")
+        us_lin16 = time_us(lambda: mlk.matmul_bias(qa, qb, bias, Y16, accumulate=False, cfg=best), 20)
+        del Y16
         rows_out["linear_bf16_4096"] = {"us": round(us_lin, 1), "TFLOP/s": round(flops / us_lin / 1e6, 1),
-                                        "matmul_overwrite_us": round(us_ow, 1), "tile": list(best.as_tuple())}
+                                        "matmul_overwrite_us": round(us_ow, 1),
+                                        "bf16_output_us": round(us_lin16, 1), "tile": list(best.as_tuple())}
         # quantisation (HBM-bound)
         us_q16 = time_us(lambda: mlk.quantize(Ad, "bf16", q=qa), 20)
         us_q8 = time_us(lambda: mlk.quantize(Ad, "e4m3", q=qa8, scale=sa), 20)

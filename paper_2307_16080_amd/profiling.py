@@ -13,7 +13,9 @@ inputs) as persistent launches, replayed from a hipGraph, with the given tile
 `traffic` turns the FETCH_SIZE / WRITE_SIZE counters (KiB per dispatch) of
 the kernel into bytes per launch, scaled by what the same counters read for
 the benchmark's plain device copy of `copy-bytes` bytes (the copy reads and
-writes exactly that many bytes), and writes them as JSON.
+writes exactly that many bytes), and writes them as JSON.  The reference copy
+is the largest copy dispatch of the run: the runtime may also move host
+transfers through small staging copies of the same kernel, which are not it.
 """
 import csv
 import json
@@ -35,8 +37,9 @@ def stats(path, top=12):
     return "\n".join(out)
 
 
-def _counter_per_dispatch(path, counter, name_sub):
-    """mean counter value (summed over its instances) per dispatch of kernels matching name_sub."""
+def _counter_per_dispatch(path, counter, name_sub, largest=False):
+    """Counter value (summed over its instances) per dispatch of kernels matching
+    name_sub: the mean over those dispatches, or with largest=True the largest one."""
     per = {}
     for r in _rows(path):
         if r.get("Counter_Name") != counter or name_sub not in r.get("Kernel_Name", ""):
@@ -45,14 +48,16 @@ def _counter_per_dispatch(path, counter, name_sub):
         per[d] = per.get(d, 0.0) + float(r["Counter_Value"])
     if not per:
         return None, 0
+    if largest:
+        return max(per.values()), len(per)
     return sum(per.values()) / len(per), len(per)
 
 
 def traffic(fetch_csv, write_csv, kernel_sub, copy_bytes, copy_sub="copy"):
     f_k, nf = _counter_per_dispatch(fetch_csv, "FETCH_SIZE", kernel_sub)
     w_k, nw = _counter_per_dispatch(write_csv, "WRITE_SIZE", kernel_sub)
-    f_c, _ = _counter_per_dispatch(fetch_csv, "FETCH_SIZE", copy_sub)
-    w_c, _ = _counter_per_dispatch(write_csv, "WRITE_SIZE", copy_sub)
+    f_c, _ = _counter_per_dispatch(fetch_csv, "FETCH_SIZE", copy_sub, largest=True)
+    w_c, _ = _counter_per_dispatch(write_csv, "WRITE_SIZE", copy_sub, largest=True)
     if None in (f_k, w_k, f_c, w_c):
         raise SystemExit("counters missing for the kernel or the copy")
     fetch_scale = copy_bytes / f_c      # bytes per counter unit, read side

@@ -132,7 +132,7 @@ def test_bf16_out_e4m3_scaled():
         assert np.all(np.abs(got - exact) <= bound), float(np.max(np.abs(got - exact) / bound))
 
 
-def test_bf16_out_refuses_split_k_and_conv():
+def test_bf16_out_refuses_split_k_and_register_loaded_tiles():
     M, N, K = 64, 64, 1024
     A = torch.zeros(M, K, dtype=torch.bfloat16, device="cuda")
     B = torch.zeros(K, N, dtype=torch.bfloat16, device="cuda")
