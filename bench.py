@@ -225,7 +225,20 @@ def main():
         us_q16 = time_us(lambda: mlk.quantize(Ad, "bf16", q=qa), 20)
         us_q8 = time_us(lambda: mlk.quantize(Ad, "e4m3", q=qa8, scale=sa), 20)
         n = M * K
-        rows_out["quantize_bf16"] = {"us": round(us_q16, 2), "GB/s": round(6 * n / us_q16 / 1e3, 1)}
+        # the same with 8 input/output pairs rotated (800 MB, past the 256 MB
+        # Infinity Cache): each call reads from HBM
+        xs = [torch.empty_like(Ad).copy_(Ad) for _ in range(8)]
+        qs = [torch.empty_like(qa) for _ in range(8)]
+        rot = {"i": 0}
+
+        def quant_rot():
+            i = rot["i"] = (rot["i"] + 1) % 8
+            mlk.quantize(xs[i], "bf16", q=qs[i])
+        us_q16_rot = time_us(quant_rot, 24)
+        del xs, qs
+        rows_out["quantize_bf16"] = {"us": round(us_q16, 2), "GB/s": round(6 * n / us_q16 / 1e3, 1),
+                                     "rotated_us": round(us_q16_rot, 2),
+                                     "rotated_GB/s": round(6 * n / us_q16_rot / 1e3, 1)}
         rows_out["quantize_e4m3"] = {"us": round(us_q8, 2), "GB/s": round(9 * n / us_q8 / 1e3, 1)}
         # int8 1024^3, bit-exact
         A8, B8 = matmul_inputs(1024, 1024, 1024, seed=0, dist="int8")
@@ -259,9 +272,22 @@ def main():
         # context, as the paper set its kernel beside the framework's: PyTorch's own
         # fp32 conv of the same tensors on this GPU (MIOpen; a new output each call)
         us_torch = time_us(lambda: torch.nn.functional.conv2d(xpd, wpd), 50)
+        # the layer is 45.8 MB, so back-to-back calls run from the 256 MB Infinity
+        # Cache: also timed with 16 (x, y) pairs rotated (420 MB), each call from HBM
+        xr = [torch.empty_like(xpd).copy_(xpd) for _ in range(16)]
+        yr = [torch.zeros_like(yp) for _ in range(16)]
+        rotc = {"i": 0}
+
+        def conv_rot():
+            i = rotc["i"] = (rotc["i"] + 1) % 16
+            mlk.conv2d_nchw_fchw(xr[i], wpd, yr[i], (1, 1), (0, 0), cfg=bp)
+        us_rot = time_us(conv_rot, 48)
+        del xr, yr
         rows_out["conv_f32_paper_1280x1280x3"] = {"us": round(us, 2), "GB/s": round(pbytes / us / 1e3, 1),
                                                   "frac_hbm": round(pbytes / us / 1e3 / PEAK["hbm_gbs"], 3),
                                                   "bytes": pbytes, "tile": list(bp.as_tuple()),
+                                                  "rotated_us": round(us_rot, 2),
+                                                  "rotated_frac_hbm": round(pbytes / us_rot / 1e3 / PEAK["hbm_gbs"], 3),
                                                   "torch_conv2d_us_context": round(us_torch, 2)}
         # 256 uneven bf16 GEMMs
         shapes = batched_shapes(256, seed=0)

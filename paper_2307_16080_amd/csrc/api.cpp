@@ -219,7 +219,7 @@ mlk_status check_config(const Shape& s, int op, const mlk_tile_config& c) {
         return fail(MLK_ERR_CONFIG, "split_k %d exceeds the %lld K stages", c.split_k, (long long)stages);
     if (c.split_k > 1 && s.out16)
         return fail(MLK_ERR_CONFIG, "a bf16 output is rounded once from the whole sum: split_k must be 1");
-    if (s.out16 && e->stages == 1)
+    if (s.out16 && !e->launch_epi16)
         return fail(MLK_ERR_CONFIG, "a bf16 output is written by the direct-to-LDS (stages >= 2) and plain "
                     "(stages 0) tiles, not the register-loaded fast tiles");
     if (c.group_m < 0 || c.group_m > 64) return fail(MLK_ERR_CONFIG, "group_m must be in [0, 64]");
@@ -254,7 +254,7 @@ std::vector<mlk_tile_config> enumerate_configs(const mlk_problem* p, const Shape
             continue;
         }
         if (e->stages >= 2 && !batched && !fast_shape_ok(s, e->bk)) continue;
-        if (s.out16 && e->stages == 1) continue;
+        if (s.out16 && !e->launch_epi16) continue;
         // a tile at least twice the problem in a dimension only adds padding
         if (e->bm > 32 && e->bm >= 2 * s.M) continue;
         if (e->bn > 32 && e->bn >= 2 * s.N) continue;
@@ -419,8 +419,8 @@ static mlk_status run_gemm(const KernelEntry* e, GemmArgs& g, const Shape& s, vo
         hipError_t z = launch_zero_matrix(C, M, N, ldc, esz, st);
         if (z != hipSuccess) return hip_fail(z, "zero output");
     }
-    // a bias or a bf16 C takes the entry's extended-epilogue variant
-    const launch_fn fn = (g.bias || g.out_bf16) ? e->launch_epi : e->launch;
+    // a bf16 C, or a bias, takes the entry's variant with that output stage
+    const launch_fn fn = g.out_bf16 ? e->launch_epi16 : g.bias ? e->launch_epi : e->launch;
     if (!fn) return fail(MLK_ERR_CONFIG, "this tile has no bias / bf16-output variant");
     const int64_t nblk = (int64_t)g.tiles_m * g.tiles_n * g.split_k;
     hipError_t err = fn(g, (int)nblk, st);

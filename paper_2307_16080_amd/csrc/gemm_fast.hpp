@@ -86,8 +86,9 @@ __device__ inline int fa(int r) { return (r & 7) ^ ((r >> 2) & 2); }
 // of 8), through registers (STAGES = 1) or as direct-to-LDS copies (STAGES >=
 // 2, C*KH*KW a multiple of BK), and kept in LDS like A (rows of BK k), so the
 // MFMA's B operand is read as A's is.  The output is NFHW.
-// EPI = 1 builds the Linear / bf16-output epilogue (bias add, bf16 C); the
-// plain product (EPI = 0) compiles without either.
+// Output stage: EPI = 0 the plain product; 1 adds the Linear layer's bias to
+// an fp32 C; 2 writes a bf16 C (bias optional).  Each is its own instantiation,
+// so no kernel carries a branch between them.
 template <int DT, int BM, int BN, int WM, int WN, int STAGES, int CONV = 0, int EPI = 0>
 struct FastGemm {
     static_assert(DT == DT_BF16 || DT == DT_F8, "direct-to-LDS kernel: bf16 or e4m3");
@@ -520,7 +521,7 @@ struct FastGemm {
         // C / alpha (one extra rounding of C); when alpha is far from 1, or a
         // wave finds a C / alpha that overflows, that wave keeps C apart.
         float alpha = 1.0f, inv_alpha = 1.0f;
-        bool c_in_acc = g.accumulate && !g.atomic && !(EPI && g.out_bf16);  // a bf16 C is read in the epilogue
+        bool c_in_acc = g.accumulate && !g.atomic && EPI != 2;  // a bf16 C is read in the epilogue
         if constexpr (DT == DT_F8) {
             if (g.scale_a) alpha *= *(const MLK_GLOBAL float*)g.scale_a;
             if (g.scale_b) alpha *= *(const MLK_GLOBAL float*)g.scale_b;
@@ -599,7 +600,7 @@ struct FastGemm {
         const MLK_GLOBAL float* const bias = !EPI || CONV || kz != 0 ? nullptr : (const MLK_GLOBAL float*)g.bias;
         // a bf16 C (direct-to-LDS forms only; never split) is read back, added in
         // fp32 and rounded once; the register-loaded form has no registers to spare
-        constexpr bool OUT16 = EPI && !CONV && !REG;
+        constexpr bool OUT16 = EPI == 2 && !CONV && !REG;
 #pragma unroll
         for (int j = 0; j < TN; ++j) {
             const int col = col0 + j * 16;
@@ -613,12 +614,14 @@ struct FastGemm {
                     MLK_GLOBAL float* p = CONV ? Ct + cbase[j] + row * hw : Ct + row * ldc + col;
                     const float v0 = DT == DT_F8 ? alpha * acc[i][j][r] : acc[i][j][r];
                     const float v = EPI ? v0 + bn : v0;
-                    if (OUT16 && g.out_bf16) {
+                    if constexpr (OUT16) {
                         MLK_GLOBAL uint16_t* q = Cb + row * ldc + col;
                         *q = bf16_rne(g.accumulate ? bf16_value(*q) + v : v);
-                    } else if (g.atomic) __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                    else if (c_in_acc || !g.accumulate) *p = v;
-                    else *p = *p + v;
+                    } else {
+                        if (g.atomic) __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                        else if (c_in_acc || !g.accumulate) *p = v;
+                        else *p = *p + v;
+                    }
                 }
         }
     }

@@ -269,8 +269,8 @@ __device__ inline void tile_coords(const GemmArgs& g, int bid, int nblk, int& tm
 // ordered (kh, kw, c); with C a multiple of the 16-byte vector, every B load
 // is one aligned 16-byte read of consecutive channels, stored into LDS as is
 // (no transpose).  The output is NFHW in both conv policies.
-// EPI = 1 builds the Linear / bf16-output epilogue (bias add, bf16 C); the
-// plain product (EPI = 0) compiles without either.
+// Output stage: EPI = 0 the plain product; 1 adds the Linear layer's bias to
+// an fp32 C; 2 writes a bf16 C (bias optional).  Each is its own instantiation.
 template <int DT, int BM, int BN, int KB, int WM, int WN, int CONV, int EPI = 0>
 struct Tile {
     typedef Traits<DT> T;
@@ -558,7 +558,7 @@ struct Tile {
         // loads, rather than in a read-add-write epilogue).  e4m3 scales the
         // product and int8 must wrap modulo 2^32 exactly, so both keep C apart.
         // (a bf16 C is read in the epilogue instead)
-        const bool c_in_acc = DT != DT_F8 && DT != DT_I8 && g.accumulate && !g.atomic && !(EPI && g.out_bf16);
+        const bool c_in_acc = DT != DT_F8 && DT != DT_I8 && g.accumulate && !g.atomic && EPI != 2;
 #pragma unroll
         for (int j = 0; j < TN; ++j) {
             int64_t cbase = 0, rstride = 0;
@@ -640,29 +640,27 @@ struct Tile {
             if (g.scale_a) alpha *= *g.scale_a;
             if (g.scale_b) alpha *= *g.scale_b;
         }
-        if constexpr (EPI && DT != DT_I8 && CONV == 0) {
-            if (g.out_bf16) {
-                // bf16 C (never split): fp32 result, plus the bf16 C when
-                // accumulating, rounded once
-                MLK_GLOBAL uint16_t* const Cb = (MLK_GLOBAL uint16_t*)g.C;
+        if constexpr (EPI == 2 && DT != DT_I8 && CONV == 0) {
+            // bf16 C (never split): fp32 result, plus the bf16 C when
+            // accumulating, rounded once
+            MLK_GLOBAL uint16_t* const Cb = (MLK_GLOBAL uint16_t*)g.C;
 #pragma unroll
-                for (int j = 0; j < TN; ++j) {
-                    const int64_t n = n0 + wx * WTN + j * 16 + lr;
-                    if (n >= g.N) continue;
-                    const float bn = g.bias && kz == 0 ? g.bias[n] : 0.0f;
+            for (int j = 0; j < TN; ++j) {
+                const int64_t n = n0 + wx * WTN + j * 16 + lr;
+                if (n >= g.N) continue;
+                const float bn = g.bias && kz == 0 ? g.bias[n] : 0.0f;
 #pragma unroll
-                    for (int i = 0; i < TM; ++i)
+                for (int i = 0; i < TM; ++i)
 #pragma unroll
-                        for (int r = 0; r < 4; ++r) {
-                            const int64_t m = m0 + wy * WTM + i * 16 + lg * 4 + r;
-                            if (m >= g.M) continue;
-                            MLK_GLOBAL uint16_t* q = Cb + m * g.ldc + n;
-                            const float v = ((DT == DT_F8) ? alpha * acc[i][j][r] : acc[i][j][r]) + bn;
-                            *q = bf16_rne(g.accumulate ? bf16_value(*q) + v : v);
-                        }
-                }
-                return;
+                    for (int r = 0; r < 4; ++r) {
+                        const int64_t m = m0 + wy * WTM + i * 16 + lg * 4 + r;
+                        if (m >= g.M) continue;
+                        MLK_GLOBAL uint16_t* q = Cb + m * g.ldc + n;
+                        const float v = ((DT == DT_F8) ? alpha * acc[i][j][r] : acc[i][j][r]) + bn;
+                        *q = bf16_rne(g.accumulate ? bf16_value(*q) + v : v);
+                    }
             }
+            return;
         }
 #pragma unroll
         for (int j = 0; j < TN; ++j) {

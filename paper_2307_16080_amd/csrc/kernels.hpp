@@ -47,7 +47,8 @@ struct KernelEntry {
     persist_fn persist;  // null where no persistent variant is built
     launch_fn launch_nhwc;  // conv entries: the channels-last variant (CONV = 2)
     occupancy_fn occupancy; // with persist: resident workgroups per CU
-    launch_fn launch_epi;   // GEMM entries: the bias / bf16-output epilogue variant (EPI = 1)
+    launch_fn launch_epi;   // GEMM entries: the Linear variant, bias added to an fp32 C (EPI = 1)
+    launch_fn launch_epi16; // GEMM entries that write a bf16 C (EPI = 2); null where not built
 };
 
 template <int DT, int BM, int BN, int KB, int WM, int WN, int CONV, int EPI = 0>
@@ -180,13 +181,29 @@ hipError_t launch_persist(const GemmArgs* gemms, const Task* tasks, const int32_
     return hipGetLastError();
 }
 
+// Output-stage variants of a GEMM entry: the Linear variant (EPI = 1) for the
+// float outputs, the bf16-output variant (EPI = 2) for bf16 and e4m3 inputs
+// and, in the fast kernel, only its direct-to-LDS forms (the register-loaded
+// form has no registers to spare for it).  Conv entries have neither.
+template <int DT, int BM, int BN, int KB, int WM, int WN, int CONV, int EPI>
+launch_fn tile_epi() {
+    if constexpr (CONV != 0 || DT == DT_I8 || (EPI == 2 && DT == DT_F32)) return nullptr;
+    else return &launch_gemm<DT, BM, BN, KB, WM, WN, 0, EPI>;
+}
+template <int DT, int BM, int BN, int WM, int WN, int STAGES>
+launch_fn fast_epi16() {
+    if constexpr (STAGES >= 2) return &launch_fast<DT, BM, BN, WM, WN, STAGES, 2>;
+    else return nullptr;
+}
+
 #define MLK_ENTRY(DT, BM, BN, KB, WM, WN, CONV)                                              \
     KernelEntry {                                                                            \
         DT, (CONV) ? 1 : 0, 0, BM, BN, (KB) / Traits<DT>::ES, WM, WN,                          \
             Tile<DT, BM, BN, KB, WM, WN, (CONV) ? 1 : 0>::LDS_BYTES, 64 * (WM) * (WN),         \
             &launch_gemm<DT, BM, BN, KB, WM, WN, (CONV) ? 1 : 0>, nullptr,                     \
             (CONV) ? &launch_gemm<DT, BM, BN, KB, WM, WN, 2> : nullptr, nullptr,              \
-            (CONV) ? nullptr : &launch_gemm<DT, BM, BN, KB, WM, WN, 0, 1>                      \
+            tile_epi<DT, BM, BN, KB, WM, WN, (CONV) ? 1 : 0, 1>(),                             \
+            tile_epi<DT, BM, BN, KB, WM, WN, (CONV) ? 1 : 0, 2>()                              \
     }
 
 #define MLK_ENTRY_P(DT, BM, BN, KB, WM, WN)                                                  \
@@ -195,7 +212,7 @@ hipError_t launch_persist(const GemmArgs* gemms, const Task* tasks, const int32_
             Tile<DT, BM, BN, KB, WM, WN, 0>::LDS_BYTES, 64 * (WM) * (WN),                    \
             &launch_gemm<DT, BM, BN, KB, WM, WN, 0>, &launch_persist<DT, BM, BN, KB, WM, WN>,  \
             nullptr, &occupancy_persist<DT, BM, BN, KB, WM, WN>,                             \
-            &launch_gemm<DT, BM, BN, KB, WM, WN, 0, 1>                                       \
+            tile_epi<DT, BM, BN, KB, WM, WN, 0, 1>(), tile_epi<DT, BM, BN, KB, WM, WN, 0, 2>()   \
     }
 
 #define MLK_ENTRY_FAST(DT, BM, BN, WM, WN, STAGES)                                           \
@@ -205,7 +222,7 @@ hipError_t launch_persist(const GemmArgs* gemms, const Task* tasks, const int32_
             &launch_fast<DT, BM, BN, WM, WN, STAGES>,                                        \
             &launch_fast_persist<DT, BM, BN, WM, WN, STAGES>, nullptr,                       \
             &occupancy_fast_persist<DT, BM, BN, WM, WN, STAGES>,                             \
-            &launch_fast<DT, BM, BN, WM, WN, STAGES, 1>                                      \
+            &launch_fast<DT, BM, BN, WM, WN, STAGES, 1>, fast_epi16<DT, BM, BN, WM, WN, STAGES>() \
     }
 
 // conv entry: channels-last layout only (launch_nhwc); no NCHW form, no persistent form
