@@ -601,28 +601,70 @@ struct FastGemm {
         // a bf16 C (direct-to-LDS forms only; never split) is read back, added in
         // fp32 and rounded once; the register-loaded form has no registers to spare
         constexpr bool OUT16 = EPI == 2 && !CONV && !REG;
+        if constexpr (OUT16) {
+            // Lanes l and l ^ 1 hold columns c and c + 1 (c even) of the same
+            // four rows: they swap two values (DPP quad permute [1,0,3,2]) so that
+            // the even lane writes rows 0-1 and the odd lane rows 2-3 of the
+            // pair, each as one 32-bit store of two bf16 codes.  A pair cut by the
+            // edge of C, or not 4-byte aligned (odd ldc), is written per element.
+            const bool odd = (lr & 1) != 0;
+            const bool al = (ldc & 1) == 0 && ((uintptr_t)g.C & 3) == 0;
 #pragma unroll
-        for (int j = 0; j < TN; ++j) {
-            const int col = col0 + j * 16;
-            const float bn = bias && (full || col < nrem) ? bias[n0 + col] : 0.0f;
+            for (int j = 0; j < TN; ++j) {
+                const int col = col0 + j * 16, cp = col & ~1;
+                const float bn = bias && (full || col < nrem) ? bias[n0 + col] : 0.0f;
 #pragma unroll
-            for (int i = 0; i < TM; ++i)
+                for (int i = 0; i < TM; ++i) {
+                    float v[4];
 #pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    const int row = row0 + i * 16 + r;
-                    if (!(full || (row < mrem && col < nrem))) continue;
-                    MLK_GLOBAL float* p = CONV ? Ct + cbase[j] + row * hw : Ct + row * ldc + col;
-                    const float v0 = DT == DT_F8 ? alpha * acc[i][j][r] : acc[i][j][r];
-                    const float v = EPI ? v0 + bn : v0;
-                    if constexpr (OUT16) {
-                        MLK_GLOBAL uint16_t* q = Cb + row * ldc + col;
-                        *q = bf16_rne(g.accumulate ? bf16_value(*q) + v : v);
-                    } else {
+                    for (int r = 0; r < 4; ++r) v[r] = (DT == DT_F8 ? alpha * acc[i][j][r] : acc[i][j][r]) + bn;
+                    const float x0 = __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(odd ? v[0] : v[2]), 0xB1, 0xF, 0xF, true));
+                    const float x1 = __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(odd ? v[1] : v[3]), 0xB1, 0xF, 0xF, true));
+#pragma unroll
+                    for (int h = 0; h < 2; ++h) {
+                        const int row = row0 + i * 16 + (odd ? 2 + h : h);
+                        const float xh = h ? x1 : x0;
+                        const float lo = odd ? xh : v[h];          // column cp
+                        const float hi = odd ? v[2 + h] : xh;      // column cp + 1
+                        const bool in_lo = full || (row < mrem && cp < nrem);
+                        const bool in_hi = full || (row < mrem && cp + 1 < nrem);
+                        if (!in_lo) continue;
+                        MLK_GLOBAL uint16_t* q = Cb + row * ldc + cp;
+                        if (in_hi && al) {
+                            MLK_GLOBAL uint32_t* qd = (MLK_GLOBAL uint32_t*)q;
+                            float a = lo, b = hi;
+                            if (g.accumulate) {
+                                const uint32_t c = *qd;
+                                a = bf16_value((uint16_t)(c & 0xFFFFu)) + a;
+                                b = bf16_value((uint16_t)(c >> 16)) + b;
+                            }
+                            *qd = (uint32_t)bf16_rne(a) | ((uint32_t)bf16_rne(b) << 16);
+                        } else {
+                            q[0] = bf16_rne(g.accumulate ? bf16_value(q[0]) + lo : lo);
+                            if (in_hi) q[1] = bf16_rne(g.accumulate ? bf16_value(q[1]) + hi : hi);
+                        }
+                    }
+                }
+            }
+        } else {
+#pragma unroll
+            for (int j = 0; j < TN; ++j) {
+                const int col = col0 + j * 16;
+                const float bn = bias && (full || col < nrem) ? bias[n0 + col] : 0.0f;
+#pragma unroll
+                for (int i = 0; i < TM; ++i)
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        const int row = row0 + i * 16 + r;
+                        if (!(full || (row < mrem && col < nrem))) continue;
+                        MLK_GLOBAL float* p = CONV ? Ct + cbase[j] + row * hw : Ct + row * ldc + col;
+                        const float v0 = DT == DT_F8 ? alpha * acc[i][j][r] : acc[i][j][r];
+                        const float v = EPI ? v0 + bn : v0;
                         if (g.atomic) __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                         else if (c_in_acc || !g.accumulate) *p = v;
                         else *p = *p + v;
                     }
-                }
+            }
         }
     }
 };

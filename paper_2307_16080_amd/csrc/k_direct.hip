@@ -12,7 +12,8 @@
 // taps (the taps are LDS broadcasts: every lane reads the same word).  Sums
 // run over c, then kh, then kw, in the order of the definition, in fp32,
 // starting from y (C += conv).  Output rows are written by consecutive lanes
-// along ow.
+// along ow.  Each pixel's sums are held for a bucket of 4, 8 or 16 filters,
+// the smallest that holds F, picked at launch.
 #include <hip/hip_runtime.h>
 
 #include "kernels.hpp"
@@ -24,12 +25,15 @@ namespace {
 __device__ inline float load_val(const float* p, int64_t i) { return p[i]; }
 __device__ inline float load_val(const uint16_t* p, int64_t i) { return __uint_as_float((uint32_t)p[i] << 16); }
 
-template <typename T, int TH, int TW>
+// FB: filters held per pixel (a bucket of 4, 8 or 16 at least F): the sums and
+// the taps of filters past F are not formed at all.
+template <typename T, int TH, int TW, int FB>
 __global__ __launch_bounds__(256) void k_conv_direct(GemmArgs g) {
     static_assert(TW == 64 && TH % 4 == 0, "one wave per output row segment of 64 pixels");
+    static_assert(FB <= kDirectMaxF, "filter bucket");
     constexpr int P = TH * TW / 256;  // output pixels per thread (rows tid/64 + 4q)
-    __shared__ float patch[kDirectPatch];
-    __shared__ float taps[kDirectMaxF * kDirectMaxTap * kDirectMaxTap];
+    __shared__ float patch[direct_patch(TH, TW)];
+    __shared__ float taps[FB * kDirectMaxTap * kDirectMaxTap];
     const T* __restrict__ x = (const T*)g.B;
     const T* __restrict__ w = (const T*)g.A;
     float* __restrict__ y = (float*)g.C;
@@ -41,7 +45,7 @@ __global__ __launch_bounds__(256) void k_conv_direct(GemmArgs g) {
     const int ih0 = oh0 * SH - g.cph, iw0 = ow0 * SW - g.cpw;
     const int tid = threadIdx.x, col = tid & 63, row = tid >> 6;
 
-    float acc[P][kDirectMaxF];
+    float acc[P][FB];
     const int64_t hw_out = (int64_t)HO * WO;
     float* ybase = y + (int64_t)img * F * hw_out;
 #pragma unroll
@@ -49,7 +53,7 @@ __global__ __launch_bounds__(256) void k_conv_direct(GemmArgs g) {
         const int oh = oh0 + row + 4 * q, ow = ow0 + col;
         const bool in = oh < HO && ow < WO;
 #pragma unroll
-        for (int f = 0; f < kDirectMaxF; ++f)
+        for (int f = 0; f < FB; ++f)
             acc[q][f] = (in && f < F && g.accumulate) ? ybase[f * hw_out + (int64_t)oh * WO + ow] : 0.0f;
     }
 
@@ -63,24 +67,24 @@ __global__ __launch_bounds__(256) void k_conv_direct(GemmArgs g) {
             patch[i] = ((unsigned)ih < (unsigned)H && (unsigned)iw < (unsigned)W) ? load_val(xc, (int64_t)ih * W + iw)
                                                                                   : 0.0f;
         }
-        // taps[(kh * KW + kw) * kDirectMaxF + f] = w[f][c][kh][kw] (0 past F)
+        // taps[(kh * KW + kw) * FB + f] = w[f][c][kh][kw] (0 past F)
         const int KK = KH * KW;
-        for (int i = tid; i < KK * kDirectMaxF; i += 256) {
-            const int f = i % kDirectMaxF, t = i / kDirectMaxF;
+        for (int i = tid; i < KK * FB; i += 256) {
+            const int f = i % FB, t = i / FB;
             taps[i] = f < F ? load_val(w, ((int64_t)f * C + c) * KK + t) : 0.0f;
         }
         __syncthreads();
         for (int kh = 0; kh < KH; ++kh)
             for (int kw = 0; kw < KW; ++kw) {
-                float wt[kDirectMaxF];
-                const float* tk = taps + (kh * KW + kw) * kDirectMaxF;
+                float wt[FB];
+                const float* tk = taps + (kh * KW + kw) * FB;
 #pragma unroll
-                for (int f = 0; f < kDirectMaxF; ++f) wt[f] = tk[f];
+                for (int f = 0; f < FB; ++f) wt[f] = tk[f];
 #pragma unroll
                 for (int q = 0; q < P; ++q) {
                     const float xv = patch[((row + 4 * q) * SH + kh) * PW + col * SW + kw];
 #pragma unroll
-                    for (int f = 0; f < kDirectMaxF; ++f) acc[q][f] = __builtin_fmaf(xv, wt[f], acc[q][f]);
+                    for (int f = 0; f < FB; ++f) acc[q][f] = __builtin_fmaf(xv, wt[f], acc[q][f]);
                 }
             }
     }
@@ -90,7 +94,7 @@ __global__ __launch_bounds__(256) void k_conv_direct(GemmArgs g) {
         const int oh = oh0 + row + 4 * q, ow = ow0 + col;
         if (oh >= HO || ow >= WO) continue;
 #pragma unroll
-        for (int f = 0; f < kDirectMaxF; ++f)
+        for (int f = 0; f < FB; ++f)
             if (f < F) ybase[f * hw_out + (int64_t)oh * WO + ow] = acc[q][f];
     }
 }
@@ -98,7 +102,13 @@ __global__ __launch_bounds__(256) void k_conv_direct(GemmArgs g) {
 template <typename T, int TH, int TW>
 hipError_t launch_conv_direct(const GemmArgs& g, int, hipStream_t s) {
     const dim3 grid((unsigned)((g.cwo + TW - 1) / TW), (unsigned)((g.cho + TH - 1) / TH), (unsigned)g.cn);
-    hipLaunchKernelGGL((k_conv_direct<T, TH, TW>), grid, dim3(256), 0, s, g);
+    // F <= kDirectMaxF is checked by the host before any launch
+    if (g.M <= 4)
+        hipLaunchKernelGGL((k_conv_direct<T, TH, TW, 4>), grid, dim3(256), 0, s, g);
+    else if (g.M <= 8)
+        hipLaunchKernelGGL((k_conv_direct<T, TH, TW, 8>), grid, dim3(256), 0, s, g);
+    else
+        hipLaunchKernelGGL((k_conv_direct<T, TH, TW, 16>), grid, dim3(256), 0, s, g);
     return hipGetLastError();
 }
 
@@ -106,7 +116,7 @@ hipError_t launch_conv_direct(const GemmArgs& g, int, hipStream_t s) {
 
 #define MLK_ENTRY_DIRECT(DT, T, TH, TW)                                                                  \
     KernelEntry {                                                                                        \
-        DT, 1, 0, TH, TW, 1, 0, 0, (int)(sizeof(float) * (kDirectPatch + kDirectMaxF * kDirectMaxTap * kDirectMaxTap)), \
+        DT, 1, 0, TH, TW, 1, 0, 0, (int)(sizeof(float) * (direct_patch(TH, TW) + kDirectMaxF * kDirectMaxTap * kDirectMaxTap)), \
             256, &launch_conv_direct<T, TH, TW>,                                                         \
             nullptr, nullptr, nullptr                                                                    \
     }
@@ -116,9 +126,11 @@ const KernelEntry* kernels_direct(int* n) {
         MLK_ENTRY_DIRECT(DT_F32, float, 4, 64),
         MLK_ENTRY_DIRECT(DT_F32, float, 8, 64),
         MLK_ENTRY_DIRECT(DT_F32, float, 16, 64),
+        MLK_ENTRY_DIRECT(DT_F32, float, 32, 64),
         MLK_ENTRY_DIRECT(DT_BF16, uint16_t, 4, 64),
         MLK_ENTRY_DIRECT(DT_BF16, uint16_t, 8, 64),
         MLK_ENTRY_DIRECT(DT_BF16, uint16_t, 16, 64),
+        MLK_ENTRY_DIRECT(DT_BF16, uint16_t, 32, 64),
     };
     *n = (int)(sizeof t / sizeof t[0]);
     return t;

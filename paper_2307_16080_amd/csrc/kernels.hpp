@@ -245,9 +245,12 @@ const KernelEntry* kernels_fast(int* n);
 // Direct (stencil) convolution (k_direct.hip): a few filters (F <=
 // kDirectMaxF), strides up to kDirectMaxStride, filter taps up to
 // kDirectMaxTap per side.  Its entries have bk = 1 and wm = wn = 0 and run as
-// conv layout 2; the LDS window is sized for the largest tile (16 x 64).
+// conv layout 2; a TH x TW tile stages an input window of
+// direct_patch(TH, TW) floats in LDS.
 constexpr int kDirectMaxF = 16, kDirectMaxStride = 2, kDirectMaxTap = 7;
-constexpr int kDirectPatch = ((16 - 1) * kDirectMaxStride + kDirectMaxTap) * ((64 - 1) * kDirectMaxStride + kDirectMaxTap);
+constexpr int direct_patch(int th, int tw) {
+    return ((th - 1) * kDirectMaxStride + kDirectMaxTap) * ((tw - 1) * kDirectMaxStride + kDirectMaxTap);
+}
 const KernelEntry* kernels_direct(int* n);
 
 // Elementwise / reduction launchers (quant.hip, reduce.hip, mlp.hip).
