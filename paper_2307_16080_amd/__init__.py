@@ -44,8 +44,16 @@ def _dt(t: torch.Tensor) -> int:
         raise MlkError(4, f"unsupported tensor dtype {t.dtype}") from None
 
 
+def _on_device(t):
+    """The library takes device memory only: a host tensor is refused here,
+    before its address could reach a kernel."""
+    if isinstance(t, torch.Tensor) and not t.is_cuda:
+        raise MlkError(9, f"expected a tensor in GPU memory, got one on {t.device}")
+    return t
+
+
 def _ptr(t):
-    return None if t is None else ctypes.c_void_p(t.data_ptr())
+    return None if t is None else ctypes.c_void_p(_on_device(t).data_ptr())
 
 
 def _stream(stream=None):
@@ -168,8 +176,9 @@ class BatchedCall:
         for i, (A, B, C) in enumerate(self._problems):
             M, K = A.shape
             N = B.shape[1]
-            self._descs[i] = GemmDesc(M, N, K, A.data_ptr(), _row_major_ld(A), B.data_ptr(),
-                                      _row_major_ld(B), C.data_ptr(), _row_major_ld(C))
+            self._descs[i] = GemmDesc(M, N, K, _on_device(A).data_ptr(), _row_major_ld(A),
+                                      _on_device(B).data_ptr(), _row_major_ld(B), _on_device(C).data_ptr(),
+                                      _row_major_ld(C))
         A0, _, C0 = self._problems[0]
         self._din, self._dout = _dt(A0), _dt(C0)
         self._cfg = None if cfg is None else (cfg if isinstance(cfg, TileConfig) else TileConfig(*cfg))

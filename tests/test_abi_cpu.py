@@ -115,6 +115,24 @@ def test_bf16_output_pairs_and_split_rule():
     assert _mm(inp=L.MLK_BF16, out=L.MLK_BF16, A=0x301E, B=0x6000)[0] == 3
 
 
+def test_binding_refuses_host_tensors():
+    """The binding passes device pointers only: torch tensors in host memory are
+    refused before the library is called (a host address must never reach a kernel)."""
+    import torch
+    A, B, C = torch.zeros(4, 4), torch.zeros(4, 4), torch.zeros(4, 4)
+    with pytest.raises(mlk.MlkError, match="GPU memory"):
+        mlk.matmul(A, B, C)
+    with pytest.raises(mlk.MlkError, match="GPU memory"):
+        mlk.matmul_bias(A, B, torch.zeros(4), C)
+    x, w, y = torch.zeros(1, 1, 5, 5), torch.zeros(2, 1, 3, 3), torch.zeros(1, 2, 3, 3)
+    with pytest.raises(mlk.MlkError, match="GPU memory"):
+        mlk.conv2d_nchw_fchw(x, w, y)
+    with pytest.raises(mlk.MlkError, match="GPU memory"):
+        mlk.quantize(torch.zeros(8), "bf16", q=torch.zeros(8, dtype=torch.bfloat16))
+    with pytest.raises(mlk.MlkError, match="GPU memory"):
+        mlk.BatchedCall([(A, B, C)])
+
+
 def test_conv_quant_err_validation():
     lib = L.lib()
     conv = lambda **k: lib.mlk_conv2d_nchw_fchw(
