@@ -164,3 +164,21 @@ def test_bf16_out_headline_shape_sampled():
     mag = oracle.matmul_f64(np.abs(va), np.abs(vb), threads=8) + np.abs(bias)[None, :]
     bound = 2.0 ** -8 * np.abs(exact) + 2.0 ** -16 * mag
     assert np.all(np.abs(got[rows] - exact) <= bound)
+
+
+def test_bf16_out_k_zero():
+    """K = 0 with a bf16 C: the Linear writes the bias rounded to bf16; the plain
+    product leaves C (accumulate) or writes +0 (overwrite)."""
+    M, N = 37, 70
+    A = torch.zeros(M, 0, dtype=torch.bfloat16, device="cuda")
+    B = torch.zeros(0, N, dtype=torch.bfloat16, device="cuda")
+    bias = linear_bias(N, 1, "normal")
+    C = from_bf16_codes(np.full((M, N), 0x7FC0, np.uint16))
+    mlk.matmul_bias(A, B, dev(bias), C, accumulate=False)
+    assert np.array_equal(bits16(C), oracle.bf16_encode(np.broadcast_to(bias, (M, N))))
+    c0 = oracle.bf16_encode(random_c(M, N, seed=3))
+    C = from_bf16_codes(c0)
+    mlk.matmul(A, B, C, accumulate=True)
+    assert np.array_equal(bits16(C), c0)
+    mlk.matmul(A, B, C, accumulate=False)
+    assert np.all(bits16(C) == 0)
