@@ -169,21 +169,26 @@ __global__ __launch_bounds__(kThreads) void k_quant_e4m3(const float* __restrict
     const float s = e4m3_block_scale(part, nparts, scale);
     const float r = __frcp_rn(s);
     const bool fast = __builtin_isfinite(r) && r > 0.0f;
-    const int64_t nvec = n / 16;
+    // consecutive lanes take consecutive groups of 4 values (each load and store
+    // instruction of a wave covers one contiguous block), four groups in flight
+    const int64_t n4 = n / 4;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nvec; i += stride) {
-        u4_t o;
+    auto encode4 = [&](const f4_t& a) {
+        return e4m3_of_quotient(a[0], s, r, fast) | (e4m3_of_quotient(a[1], s, r, fast) << 8) |
+               (e4m3_of_quotient(a[2], s, r, fast) << 16) | (e4m3_of_quotient(a[3], s, r, fast) << 24);
+    };
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    for (; i + 3 * stride < n4; i += 4 * stride) {
+        f4_t a[4];
 #pragma unroll
-        for (int w = 0; w < 4; ++w) {
-            const f4_t a = *(const f4_t*)(x + 16 * i + 4 * w);
-            o[w] = e4m3_of_quotient(a[0], s, r, fast) | (e4m3_of_quotient(a[1], s, r, fast) << 8) |
-                   (e4m3_of_quotient(a[2], s, r, fast) << 16) | (e4m3_of_quotient(a[3], s, r, fast) << 24);
-        }
-        *(u4_t*)(q + 16 * i) = o;
+        for (int u = 0; u < 4; ++u) a[u] = *(const f4_t*)(x + 4 * (i + u * stride));
+#pragma unroll
+        for (int u = 0; u < 4; ++u) *(uint32_t*)(q + 4 * (i + u * stride)) = encode4(a[u]);
     }
+    for (; i < n4; i += stride) *(uint32_t*)(q + 4 * i) = encode4(*(const f4_t*)(x + 4 * i));
     if (blockIdx.x == 0)
-        for (int64_t i = nvec * 16 + threadIdx.x; i < n; i += blockDim.x)
-            q[i] = (uint8_t)e4m3_of_quotient(x[i], s, r, fast);
+        for (int64_t j = n4 * 4 + threadIdx.x; j < n; j += blockDim.x)
+            q[j] = (uint8_t)e4m3_of_quotient(x[j], s, r, fast);
 }
 
 __global__ __launch_bounds__(kThreads) void k_quant_e4m3_scalar(const float* __restrict__ x, int64_t n,
