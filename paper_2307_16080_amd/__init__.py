@@ -52,6 +52,17 @@ def _on_device(t):
     return t
 
 
+def _need(cond, status, msg):
+    if not cond:
+        raise MlkError(status, msg)
+
+
+def _check_scale(t, what):
+    if t is not None:
+        _need(isinstance(t, torch.Tensor) and t.dtype == torch.float32 and t.numel() >= 1, 9,
+              f"{what} must be a float32 tensor of at least one element")
+
+
 def _ptr(t):
     return None if t is None else ctypes.c_void_p(_on_device(t).data_ptr())
 
@@ -92,10 +103,14 @@ def matmul(A, B, C, accumulate: bool = True, cfg=None, scale_a=None, scale_b=Non
     (float32, float32), (bfloat16, float32), (float8_e4m3fn, float32) with optional
     device scale tensors, (int8, int32); bfloat16 C with bfloat16 or float8_e4m3fn
     inputs (the fp32 result rounded once to bf16; split_k 1)."""
+    _need(A.dim() == 2 and B.dim() == 2 and C.dim() == 2, 2, "matmul operands must be 2-D")
     M, K = A.shape
     K2, N = B.shape
     if K2 != K or tuple(C.shape) != (M, N):
         raise MlkError(2, f"shape mismatch: A {tuple(A.shape)}, B {tuple(B.shape)}, C {tuple(C.shape)}")
+    _need(B.dtype == A.dtype, 4, f"A and B must have one dtype (got {A.dtype}, {B.dtype})")
+    _check_scale(scale_a, "scale_a")
+    _check_scale(scale_b, "scale_b")
     L.check(L.lib().mlk_matmul(_dt(A), _dt(C), M, N, K, _ptr(A), _row_major_ld(A), _ptr(B),
                                _row_major_ld(B), _ptr(C), _row_major_ld(C), _ptr(scale_a),
                                _ptr(scale_b), int(bool(accumulate)), _cfg(cfg), _stream(stream)))
@@ -107,10 +122,14 @@ def matmul_bias(A, B, bias, C, accumulate: bool = False, cfg=None, scale_a=None,
     """The Linear layer: C (+)= A @ B + bias, the bias add fused into the product's output.
 
     bias: float32 CUDA tensor of N elements.  Float outputs only (the float pairs of matmul)."""
+    _need(A.dim() == 2 and B.dim() == 2 and C.dim() == 2, 2, "matmul operands must be 2-D")
     M, K = A.shape
     K2, N = B.shape
     if K2 != K or tuple(C.shape) != (M, N):
         raise MlkError(2, f"shape mismatch: A {tuple(A.shape)}, B {tuple(B.shape)}, C {tuple(C.shape)}")
+    _need(B.dtype == A.dtype, 4, f"A and B must have one dtype (got {A.dtype}, {B.dtype})")
+    _check_scale(scale_a, "scale_a")
+    _check_scale(scale_b, "scale_b")
     if bias.dtype != torch.float32 or bias.numel() != N or not bias.is_contiguous():
         raise MlkError(2, f"bias must be {N} contiguous float32 values")
     L.check(L.lib().mlk_matmul_bias(_dt(A), _dt(C), M, N, K, _ptr(A), _row_major_ld(A), _ptr(B),
@@ -126,12 +145,19 @@ def conv2d_nchw_fchw(x, w, y, stride=(1, 1), pad=(0, 0), accumulate: bool = True
     for t in (x, w, y):
         if not t.is_contiguous():
             raise MlkError(3, "conv2d tensors must be contiguous")
+    _need(x.dim() == 4 and w.dim() == 4 and y.dim() == 4, 2, "conv2d tensors must be 4-D")
     N, C, H, W = x.shape
     F, C2, KH, KW = w.shape
     if C2 != C:
         raise MlkError(2, "channel mismatch")
+    _need(w.dtype == x.dtype, 4, f"x and w must have one dtype (got {x.dtype}, {w.dtype})")
     sh, sw = stride
     ph, pw = pad
+    if sh > 0 and sw > 0:
+        HO, WO = conv_out_hw(H, W, KH, KW, stride, pad)
+        if HO > 0 and WO > 0:
+            _need(tuple(y.shape) == (N, F, HO, WO), 2,
+                  f"y must be {(N, F, HO, WO)} for these inputs, got {tuple(y.shape)}")
     L.check(L.lib().mlk_conv2d_nchw_fchw(_dt(x), _dt(y), N, C, H, W, F, KH, KW, sh, sw, ph, pw,
                                          _ptr(x), _ptr(w), _ptr(y), int(bool(accumulate)),
                                          _cfg(cfg), _stream(stream)))
@@ -147,13 +173,19 @@ def quantize(x: torch.Tensor, fmt: str, q=None, scale=None, stream=None):
     with scale a one-element float32 device tensor (amax / 448)."""
     if x.dtype != torch.float32 or not x.is_contiguous():
         raise MlkError(4, "quantize expects a contiguous float32 tensor")
+    def _out(t, dtype):
+        _need(t.dtype == dtype and t.is_contiguous() and t.numel() >= x.numel(), 2,
+              f"q must be a contiguous {dtype} tensor of at least {x.numel()} elements")
     if fmt == "bf16":
         q = torch.empty(x.shape, dtype=torch.bfloat16, device=x.device) if q is None else q
+        _out(q, torch.bfloat16)
         L.check(L.lib().mlk_quantize(MLK_BF16, x.numel(), _ptr(x), _ptr(q), None, _stream(stream)))
         return q, None
     if fmt == "e4m3":
         q = torch.empty(x.shape, dtype=torch.float8_e4m3fn, device=x.device) if q is None else q
         scale = torch.empty(1, dtype=torch.float32, device=x.device) if scale is None else scale
+        _out(q, torch.float8_e4m3fn)
+        _check_scale(scale, "scale")
         L.check(L.lib().mlk_quantize(MLK_F8E4M3, x.numel(), _ptr(x), _ptr(q), _ptr(scale),
                                      _stream(stream)))
         return q, scale
@@ -173,13 +205,19 @@ class BatchedCall:
             raise MlkError(2, "batched: empty problem list")
         self._problems = list(problems)
         self._descs = (GemmDesc * len(self._problems))()
+        A0, B0, C0 = self._problems[0]
+        for i, (A, B, C) in enumerate(self._problems):
+            _need(A.dim() == 2 and B.dim() == 2 and C.dim() == 2, 2, f"batched: GEMM {i}: operands must be 2-D")
+            _need(B.shape[0] == A.shape[1] and tuple(C.shape) == (A.shape[0], B.shape[1]), 2,
+                  f"batched: GEMM {i}: shapes A {tuple(A.shape)}, B {tuple(B.shape)}, C {tuple(C.shape)}")
+            _need(A.dtype == A0.dtype and B.dtype == A0.dtype and C.dtype == C0.dtype, 4,
+                  f"batched: GEMM {i}: every A and B must be {A0.dtype} and every C {C0.dtype}")
         for i, (A, B, C) in enumerate(self._problems):
             M, K = A.shape
             N = B.shape[1]
             self._descs[i] = GemmDesc(M, N, K, _on_device(A).data_ptr(), _row_major_ld(A),
                                       _on_device(B).data_ptr(), _row_major_ld(B), _on_device(C).data_ptr(),
                                       _row_major_ld(C))
-        A0, _, C0 = self._problems[0]
         self._din, self._dout = _dt(A0), _dt(C0)
         self._cfg = None if cfg is None else (cfg if isinstance(cfg, TileConfig) else TileConfig(*cfg))
         self._acc = int(bool(accumulate))
@@ -201,6 +239,9 @@ def err_stats(c: torch.Tensor, r: torch.Tensor, bound=None, stream=None):
     out = torch.empty(4, dtype=torch.float64, device=c.device)
     if r.dtype != torch.float64 or (bound is not None and bound.dtype != torch.float64):
         raise MlkError(4, "reference and bound must be float64")
+    _need(c.is_contiguous() and r.is_contiguous() and r.numel() == c.numel() and
+          (bound is None or (bound.is_contiguous() and bound.numel() == c.numel())), 2,
+          "err_stats: c, r (and bound) must be contiguous with one element count")
     L.check(L.lib().mlk_err_stats(_dt(c), c.numel(), _ptr(c), _ptr(r), _ptr(bound), _ptr(out),
                                   _stream(stream)))
     return out
@@ -327,7 +368,20 @@ def features(problem, cfg):
 
 # --------------------------------------------------------------------------- cost-model kernels
 
+def mlp_param_count(D0, H1, H2):
+    """Length of the flat parameter vector: W1, b1, W2, b2, W3, b3."""
+    return D0 * H1 + H1 + H1 * H2 + H2 + H2 + 1
+
+
+def _check_mlp(params, X, H1, H2):
+    _need(X.dim() == 2 and X.dtype == torch.float32 and X.is_contiguous(), 2, "X must be a contiguous 2-D float32 tensor")
+    _need(params.dtype == torch.float32 and params.is_contiguous() and
+          params.numel() == mlp_param_count(X.shape[1], H1, H2), 2,
+          f"params must hold {mlp_param_count(X.shape[1], H1, H2)} contiguous float32 values")
+
+
 def mlp_forward(params, X, H1, H2, stream=None):
+    _check_mlp(params, X, H1, H2)
     B, D0 = X.shape
     y = torch.empty(B, dtype=torch.float32, device=X.device)
     L.check(L.lib().mlk_mlp_forward(B, D0, H1, H2, _ptr(params), _ptr(X), _ptr(y), _stream(stream)))
@@ -335,6 +389,9 @@ def mlp_forward(params, X, H1, H2, stream=None):
 
 
 def mlp_loss_grad(params, X, t, H1, H2, stream=None):
+    _check_mlp(params, X, H1, H2)
+    _need(t.dtype == torch.float32 and t.is_contiguous() and t.numel() == X.shape[0], 2,
+          "t must hold one contiguous float32 target per row of X")
     B, D0 = X.shape
     g = torch.empty_like(params)
     loss = torch.empty(1, dtype=torch.float32, device=X.device)
@@ -344,5 +401,8 @@ def mlp_loss_grad(params, X, t, H1, H2, stream=None):
 
 
 def adam_step(params, grad, m, v, lr, beta1, beta2, eps, t, stream=None):
+    for a in (params, grad, m, v):
+        _need(a.dtype == torch.float32 and a.is_contiguous() and a.numel() == params.numel(), 2,
+              "adam_step: params, grad, m and v must be contiguous float32 tensors of one length")
     L.check(L.lib().mlk_adam_step(params.numel(), _ptr(params), _ptr(grad), _ptr(m), _ptr(v), lr,
                                   beta1, beta2, eps, t, _stream(stream)))

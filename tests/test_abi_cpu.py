@@ -133,6 +133,39 @@ def test_binding_refuses_host_tensors():
         mlk.BatchedCall([(A, B, C)])
 
 
+def test_binding_checks_shapes_and_dtypes():
+    """The C ABI sees pointers only, so the binding checks what it can of each
+    tensor (shape, dtype, element count) before any pointer is taken: a short
+    output or a wider operand type would otherwise be read or written past its
+    allocation."""
+    import torch
+    A, B, C = torch.zeros(4, 8), torch.zeros(8, 4), torch.zeros(4, 4)
+    with pytest.raises(mlk.MlkError, match="one dtype"):
+        mlk.matmul(A.to(torch.bfloat16), B, C)
+    with pytest.raises(mlk.MlkError, match="scale_a"):
+        mlk.matmul(A, B, C, scale_a=torch.zeros(1, dtype=torch.float16))
+    with pytest.raises(mlk.MlkError, match="one dtype"):
+        mlk.matmul_bias(A, B.to(torch.bfloat16), torch.zeros(4), C)
+    x, w = torch.zeros(1, 2, 5, 5), torch.zeros(3, 2, 3, 3)
+    with pytest.raises(mlk.MlkError, match="y must be"):
+        mlk.conv2d_nchw_fchw(x, w, torch.zeros(1, 3, 2, 3))
+    with pytest.raises(mlk.MlkError, match="one dtype"):
+        mlk.conv2d_nchw_fchw(x, w.to(torch.bfloat16), torch.zeros(1, 3, 3, 3))
+    with pytest.raises(mlk.MlkError, match="q must be"):
+        mlk.quantize(torch.zeros(8), "bf16", q=torch.zeros(4, dtype=torch.bfloat16))
+    with pytest.raises(mlk.MlkError, match="q must be"):
+        mlk.quantize(torch.zeros(8), "e4m3", q=torch.zeros(8, dtype=torch.bfloat16))
+    with pytest.raises(mlk.MlkError, match="batched"):
+        mlk.BatchedCall([(A, B, torch.zeros(4, 5))])
+    with pytest.raises(mlk.MlkError, match="batched"):
+        mlk.BatchedCall([(A, B, C), (A.to(torch.bfloat16), B.to(torch.bfloat16), C)])
+    with pytest.raises(mlk.MlkError, match="params"):
+        mlk.mlp_forward(torch.zeros(10), torch.zeros(2, 3), 4, 4)
+    assert mlk.mlp_param_count(3, 4, 4) == 3 * 4 + 4 + 4 * 4 + 4 + 4 + 1
+    with pytest.raises(mlk.MlkError, match="element count"):
+        mlk.err_stats(torch.zeros(4), torch.zeros(5, dtype=torch.float64))
+
+
 def test_conv_quant_err_validation():
     lib = L.lib()
     conv = lambda **k: lib.mlk_conv2d_nchw_fchw(
