@@ -23,7 +23,7 @@ from ._lib import (MLK_BATCH_GRAPH, MLK_BATCH_PERSISTENT, MLK_BF16, MLK_F8E4M3, 
                    MLK_TUNE_ES, MLK_TUNE_MODEL, MLK_TUNE_RANDOM, GemmDesc, MlkError, Problem, TileConfig,
                    TuneOpts, TuneReport)
 
-__all__ = ["matmul", "matmul_bias", "conv2d_nchw_fchw", "quantize", "batched_matmul", "BatchedCall", "err_stats", "tune",
+__all__ = ["matmul", "matmul_bias", "conv2d_nchw_fchw", "ConvCall", "quantize", "batched_matmul", "BatchedCall", "err_stats", "tune",
            "config_count", "configs", "config_legal", "set_default_config", "CostModel",
            "mlp_forward", "mlp_loss_grad", "adam_step", "release", "version", "TileConfig",
            "Problem", "MlkError", "matmul_problem", "conv_problem", "batched_problem"]
@@ -139,9 +139,8 @@ def matmul_bias(A, B, bias, C, accumulate: bool = False, cfg=None, scale_a=None,
     return C
 
 
-def conv2d_nchw_fchw(x, w, y, stride=(1, 1), pad=(0, 0), accumulate: bool = True, cfg=None,
-                     stream=None):
-    """y (+)= conv(x, w): x (N,C,H,W), w (F,C,KH,KW), y (N,F,HO,WO), contiguous."""
+def _conv_args(x, w, y, stride, pad, accumulate):
+    """Checked arguments of mlk_conv2d_nchw_fchw up to (not including) cfg and stream."""
     for t in (x, w, y):
         if not t.is_contiguous():
             raise MlkError(3, "conv2d tensors must be contiguous")
@@ -158,10 +157,41 @@ def conv2d_nchw_fchw(x, w, y, stride=(1, 1), pad=(0, 0), accumulate: bool = True
         if HO > 0 and WO > 0:
             _need(tuple(y.shape) == (N, F, HO, WO), 2,
                   f"y must be {(N, F, HO, WO)} for these inputs, got {tuple(y.shape)}")
-    L.check(L.lib().mlk_conv2d_nchw_fchw(_dt(x), _dt(y), N, C, H, W, F, KH, KW, sh, sw, ph, pw,
-                                         _ptr(x), _ptr(w), _ptr(y), int(bool(accumulate)),
-                                         _cfg(cfg), _stream(stream)))
+    return (_dt(x), _dt(y), N, C, H, W, F, KH, KW, sh, sw, ph, pw, _ptr(x), _ptr(w), _ptr(y),
+            int(bool(accumulate)))
+
+
+def conv2d_nchw_fchw(x, w, y, stride=(1, 1), pad=(0, 0), accumulate: bool = True, cfg=None,
+                     stream=None):
+    """y (+)= conv(x, w): x (N,C,H,W), w (F,C,KH,KW), y (N,F,HO,WO), contiguous."""
+    L.check(L.lib().mlk_conv2d_nchw_fchw(*_conv_args(x, w, y, stride, pad, accumulate), _cfg(cfg),
+                                         _stream(stream)))
     return y
+
+
+class ConvCall:
+    """One convolution bound once to its tensors: shapes, dtypes, pointers and
+    the configuration are checked and marshalled here, so each call is a single
+    library call (a layer in a serving loop pays no per-call Python work beyond
+    it).  The tensors are kept alive by the object; their storage must not move
+    between calls.  `stream`, if given here, is the default for every call."""
+
+    def __init__(self, x, w, y, stride=(1, 1), pad=(0, 0), accumulate: bool = True, cfg=None,
+                 stream=None):
+        self._args = _conv_args(x, w, y, stride, pad, accumulate)
+        self._keep = (x, w, y)
+        self._cfg = None if cfg is None else (cfg if isinstance(cfg, TileConfig) else TileConfig(*cfg))
+        self._cfgp = _cfg(self._cfg)
+        self._fn = L.lib().mlk_conv2d_nchw_fchw
+        self._stream = None if stream is None else _stream(stream)
+
+    def __call__(self, stream=None):
+        if stream is not None:
+            st = _stream(stream)
+        else:
+            st = self._stream if self._stream is not None else _stream(None)
+        L.check(self._fn(*self._args, self._cfgp, st))
+        return self._keep[2]
 
 
 def conv_out_hw(H, W, KH, KW, stride=(1, 1), pad=(0, 0)):

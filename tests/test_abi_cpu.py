@@ -151,6 +151,10 @@ def test_binding_checks_shapes_and_dtypes():
         mlk.conv2d_nchw_fchw(x, w, torch.zeros(1, 3, 2, 3))
     with pytest.raises(mlk.MlkError, match="one dtype"):
         mlk.conv2d_nchw_fchw(x, w.to(torch.bfloat16), torch.zeros(1, 3, 3, 3))
+    with pytest.raises(mlk.MlkError, match="y must be"):
+        mlk.ConvCall(x, w, torch.zeros(1, 3, 2, 3))
+    with pytest.raises(mlk.MlkError, match="GPU memory"):
+        mlk.ConvCall(x, w, torch.zeros(1, 3, 3, 3))
     with pytest.raises(mlk.MlkError, match="q must be"):
         mlk.quantize(torch.zeros(8), "bf16", q=torch.zeros(4, dtype=torch.bfloat16))
     with pytest.raises(mlk.MlkError, match="q must be"):

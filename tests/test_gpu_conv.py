@@ -380,3 +380,25 @@ def test_paper_conv_shape_tuned():
     y = torch.zeros(1, 3, 1278, 1278, device="cuda")
     mlk.conv2d_nchw_fchw(dev(x), dev(w), y, cfg=best)
     assert normwise(host(y), ref) <= 1e-5
+
+
+def test_conv_call_matches_per_call_api():
+    """A layer bound once (mlk.ConvCall) gives what the per-call API gives, bit
+    for bit, over repeated accumulating calls, on the default and a side stream."""
+    x, w = conv_inputs(2, 16, 14, 14, 32, 3, 3, seed=4)
+    qx = from_bf16_codes(oracle.bf16_encode(x))
+    qw = from_bf16_codes(oracle.bf16_encode(w))
+    y1 = torch.zeros(2, 32, 14, 14, device="cuda")
+    y2 = torch.zeros_like(y1)
+    call = mlk.ConvCall(qx, qw, y1, (1, 1), (1, 1))
+    side = torch.cuda.Stream()
+    for k in range(3):
+        if k == 1:
+            torch.cuda.synchronize()
+            call(stream=side)
+            side.synchronize()
+        else:
+            call()
+        mlk.conv2d_nchw_fchw(qx, qw, y2, (1, 1), (1, 1))
+    torch.cuda.synchronize()
+    assert torch.equal(y1, y2)
