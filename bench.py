@@ -370,8 +370,9 @@ def main():
             nrows = min(4096, max(nrows * 2, int(nrows * 10.0 / max(dt, 1e-3))))
         result["cpu_baseline"] = {"value": round(2.0 * nrows * N * K / dt / 1e12, 6), "unit": "TFLOP/s",
                                   "cores": threads, "kind": "oracle",
-                                  "sample": f"REF64 (double) oracle matmul of the first {nrows} rows of the "
-                                            f"4096x4096x4096 workload, {dt:.1f} s on {threads} threads"}
+                                  "sample": ("REF64 (double) oracle matmul of "
+                                             + ("the whole" if nrows >= M else f"the first {nrows} rows of the")
+                                             + f" 4096x4096x4096 workload, {dt:.1f} s on {threads} threads")}
         rn = np.linalg.norm(ref)
         result["errors_vs_ref64_fp32_inputs"] = {
             k: float(np.linalg.norm(v[:nrows].astype(np.float64) - ref) / rn) for k, v in outputs.items()}
