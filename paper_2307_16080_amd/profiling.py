@@ -5,6 +5,7 @@ for the batched workload to run under the profiler.
     python -m paper_2307_16080_amd.profiling traffic <fetch_counters.csv> <write_counters.csv>
             <kernel-name-substring> <copy-bytes> <out.json> [source_hash] [tile]
     python -m paper_2307_16080_amd.profiling batched <tile> <launches>
+    python -m paper_2307_16080_amd.profiling paperconv <tile> <launches>
 
 `batched` runs the 256 uneven bf16 GEMMs of the benchmark (seeded shapes and
 inputs) as persistent launches, replayed from a hipGraph, with the given tile
@@ -92,9 +93,37 @@ def run_batched(tile, launches):
     print(f"batched: {launches} persistent launches of {len(shapes)} GEMMs, tile {tile}", flush=True)
 
 
+def run_paper_conv(tile, launches):
+    """The paper's measured layer (one 1280 x 1280 image, three 3 x 3 filters,
+    valid, fp32, y += conv) launched back to back with the given tile, then one
+    plain 256 MiB device copy (the reference for the HBM byte counters)."""
+    import os
+
+    import torch
+
+    sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+    import paper_2307_16080_amd as mlk
+    from workloads import conv_inputs
+
+    x, w = conv_inputs(1, 1, 1280, 1280, 3, 3, 3, seed=0)
+    xd, wd = torch.from_numpy(x).cuda(), torch.from_numpy(w).cuda()
+    y = torch.zeros(1, 3, 1278, 1278, device="cuda")
+    cfg = mlk.TileConfig(*[int(v) for v in tile.split(",")])
+    call = mlk.ConvCall(xd, wd, y, (1, 1), (0, 0), cfg=cfg)
+    for _ in range(launches):
+        call()
+    src = torch.empty(256 << 20, dtype=torch.uint8, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    print(f"paper conv: {launches} launches, tile {tile}; one 256 MiB copy", flush=True)
+
+
 if __name__ == "__main__":
     if sys.argv[1] == "batched":
         run_batched(sys.argv[2], int(sys.argv[3]))
+    elif sys.argv[1] == "paperconv":
+        run_paper_conv(sys.argv[2], int(sys.argv[3]))
     elif sys.argv[1] == "stats":
         print(stats(sys.argv[2]))
     elif sys.argv[1] == "traffic":
