@@ -195,6 +195,13 @@ static bool fast_shape_ok(const Shape& s, int bk) {
 
 static bool is_direct(const KernelEntry* e) { return e->conv && e->wm == 0; }
 
+// The direct-layout matmul tiles address their output tile with 32-bit
+// offsets from its corner; with ldc >= N the rows of a tile span at least
+// (bm - 1) * N + bn elements.
+static bool fast_ldc_ok(const Shape& s, const KernelEntry* e) {
+    return s.conv || e->stages < 1 || (int64_t)(e->bm - 1) * std::max<int64_t>(s.N, 1) + e->bn < ((int64_t)1 << 31);
+}
+
 // the direct (stencil) conv covers few filters, small strides and taps
 static bool direct_ok(const Shape& s) {
     return s.conv && s.M <= kDirectMaxF && s.conv_sh <= kDirectMaxStride && s.conv_sw <= kDirectMaxStride &&
@@ -206,6 +213,9 @@ mlk_status check_config(const Shape& s, int op, const mlk_tile_config& c) {
     if (!e)
         return fail(MLK_ERR_CONFIG, "no compiled kernel for tile %dx%dx%d waves %dx%d stages %d (dtype %d%s)",
                     c.bm, c.bn, c.bk, c.wm, c.wn, c.stages, s.dt, s.conv ? ", conv" : "");
+    if (!fast_ldc_ok(s, e))
+        return fail(MLK_ERR_CONFIG, "direct-layout tile: N too large for its %d-row tile (32-bit output offsets)",
+                    e->bm);
     // (matmul operands that do not fit these tiles are packed, so any shape is fine)
     if (e->stages >= 2 && op != MLK_OP_BATCHED && !fast_shape_ok(s, e->bk)) {
         if (s.conv)
@@ -254,6 +264,7 @@ std::vector<mlk_tile_config> enumerate_configs(const mlk_problem* p, const Shape
             continue;
         }
         if (e->stages >= 2 && !batched && !fast_shape_ok(s, e->bk)) continue;
+        if (!fast_ldc_ok(s, e)) continue;
         if (s.out16 && !e->launch_epi16) continue;
         // a tile at least twice the problem in a dimension only adds padding
         if (e->bm > 32 && e->bm >= 2 * s.M) continue;
@@ -308,7 +319,7 @@ mlk_tile_config heuristic_config(const Shape& s, int op) {
         cdiv(s.M, 256) * cdiv(s.N, 256) >= cus && s.K >= 256) {
         for (const KernelEntry* f : registry())
             if (f->dt == s.dt && !f->conv && f->stages == 2 && f->bm == 256 && f->bn == 256 &&
-                f->wm == 2 && f->wn == 4 && fast_shape_ok(s, f->bk)) {
+                f->wm == 2 && f->wn == 4 && fast_shape_ok(s, f->bk) && fast_ldc_ok(s, f)) {
                 const int64_t tiles = cdiv(s.M, 256) * cdiv(s.N, 256);
                 return mlk_tile_config{256, 256, f->bk, 2, 4, 1, 8, tiles % 8 == 0 ? 1 : 0, 2, 0};
             }
@@ -440,12 +451,57 @@ static mlk_status refuse_under_capture(hipStream_t st, const char* what) {
     return MLK_OK;
 }
 
+// How a direct-to-LDS launch takes its operands: an operand without 16-byte
+// rows, or with K not a multiple of the stage depth, is first copied into a
+// zero-padded buffer (A as M x Kp, B as Kp x Np; Kp = K rounded up to the
+// stage depth, Np = N rounded up to 16 bytes).
+struct PackPlan {
+    bool pa = false, pb = false;
+    int64_t Kp = 0, Np = 0, lda2 = 0, ldb2 = 0;
+    int64_t abytes = 0, bbytes = 0;  // workspace bytes of each packed copy
+};
+
+static PackPlan pack_plan(const Shape& s, const KernelEntry* e, const void* A, int64_t lda, const void* B,
+                          int64_t ldb) {
+    PackPlan pp;
+    const int es = esize_in(s.dt);
+    pp.lda2 = lda;
+    pp.ldb2 = ldb;
+    if (e->stages < 2 || s.K == 0 || s.M == 0 || s.N == 0) return pp;
+    const bool vec_a = ((uintptr_t)A % 16 == 0) && ((lda * es) % 16 == 0);
+    const bool vec_b = ((uintptr_t)B % 16 == 0) && ((ldb * es) % 16 == 0);
+    const bool kfit = s.K % e->bk == 0;
+    pp.pa = !(vec_a && kfit);
+    pp.pb = !(vec_b && kfit);
+    pp.Kp = cdiv(s.K, e->bk) * e->bk;
+    pp.Np = cdiv(s.N, 16 / es) * (16 / es);
+    pp.lda2 = pp.pa ? pp.Kp : lda;
+    pp.ldb2 = pp.pb ? pp.Np : ldb;
+    pp.abytes = pp.pa ? cdiv(s.M * pp.Kp * es, 256) * 256 : 0;
+    pp.bbytes = pp.pb ? pp.Kp * pp.Np * es : 0;
+    return pp;
+}
+
+int64_t dense_workspace_bytes(const Shape& s, const void* A, int64_t lda, const void* B, int64_t ldb,
+                              const mlk_tile_config& cfg) {
+    const KernelEntry* e = find_kernel(s.dt, 0, cfg);
+    if (!e) return 0;
+    const PackPlan pp = pack_plan(s, e, A, lda, B, ldb);
+    return pp.abytes + pp.bbytes;
+}
+
 mlk_status launch_dense(const Shape& s, const void* A, int64_t lda, const void* B, int64_t ldb,
                         void* C, int64_t ldc, const float* sa, const float* sb,
-                        const mlk_tile_config& cfg, hipStream_t st, const float* bias) {
+                        const mlk_tile_config& cfg, hipStream_t st, const float* bias, void* ext_ws,
+                        size_t ext_bytes) {
     const KernelEntry* e = find_kernel(s.dt, 0, cfg);
     if (!e) return fail(MLK_ERR_CONFIG, "no kernel for configuration");
     if (s.M == 0 || s.N == 0) return MLK_OK;
+    // the direct-layout kernel addresses its output tile with 32-bit offsets
+    // from the tile corner: rows up to bm - 1 apart at pitch ldc
+    if (e->stages >= 1 && (int64_t)(e->bm - 1) * ldc + e->bn >= ((int64_t)1 << 31))
+        return fail(MLK_ERR_CONFIG, "direct-layout tile: ldc %lld too large for its %d-row tile (32-bit offsets)",
+                    (long long)ldc, e->bm);
     GemmArgs g = base_args(s, cfg);
     const int es = esize_in(s.dt);
     g.A = A;
@@ -460,38 +516,40 @@ mlk_status launch_dense(const Shape& s, const void* A, int64_t lda, const void* 
     g.vec_a = ((uintptr_t)A % 16 == 0) && ((lda * es) % 16 == 0);
     g.vec_b = ((uintptr_t)B % 16 == 0) && ((ldb * es) % 16 == 0);
     if (e->stages < 2 || s.K == 0) return run_gemm(e, g, s, C, s.M, s.N, ldc, st);
-    // Direct-to-LDS tile: an operand without 16-byte rows, or with K not a
-    // multiple of the stage depth, is first copied into a zero-padded buffer
-    // (A as M x Kp, B as Kp x Np; Kp = K rounded up to the stage depth, Np = N
-    // rounded up to 16 bytes) in the library's scratch buffer.
-    const bool kfit = s.K % e->bk == 0;
-    const bool pa = !(g.vec_a && kfit), pb = !(g.vec_b && kfit);
-    const int64_t Kp = cdiv(s.K, e->bk) * e->bk, Np = cdiv(s.N, 16 / es) * (16 / es);
-    const int64_t lda2 = pa ? Kp : lda, ldb2 = pb ? Np : ldb;
-    if (((s.M - 1) * lda2 + Kp) * es >= ((int64_t)1 << 31) || ((Kp - 1) * ldb2 + s.N) * es >= ((int64_t)1 << 31))
+    const PackPlan pp = pack_plan(s, e, A, lda, B, ldb);
+    if (((s.M - 1) * pp.lda2 + pp.Kp) * es >= ((int64_t)1 << 31) ||
+        ((pp.Kp - 1) * pp.ldb2 + s.N) * es >= ((int64_t)1 << 31))
         return fail(MLK_ERR_CONFIG, "direct-to-LDS tile: an operand exceeds 2 GiB");
-    if (!pa && !pb) return run_gemm(e, g, s, C, s.M, s.N, ldc, st);
-    const int64_t abytes = pa ? cdiv(s.M * Kp * es, 256) * 256 : 0;
-    const int64_t bbytes = pb ? Kp * Np * es : 0;
+    if (!pp.pa && !pp.pb) return run_gemm(e, g, s, C, s.M, s.N, ldc, st);
+    // the packed copies go to the caller's workspace when one is given (no
+    // allocation, no scratch lock, capturable), else to the library's scratch
     ScratchUse scratch;
-    if (mlk_status rc = scratch.begin((size_t)(abytes + bbytes), st, "a direct-to-LDS tile with operand packing");
-        rc != MLK_OK)
-        return rc;
-    void* ws = scratch.ptr();
+    void* ws = ext_ws;
+    if (ext_ws) {
+        if ((size_t)(pp.abytes + pp.bbytes) > ext_bytes)
+            return fail(MLK_ERR_SHAPE, "operand packing needs %lld bytes of workspace, %zu available",
+                        (long long)(pp.abytes + pp.bbytes), ext_bytes);
+    } else {
+        if (mlk_status rc = scratch.begin((size_t)(pp.abytes + pp.bbytes), st,
+                                          "a direct-to-LDS tile with operand packing");
+            rc != MLK_OK)
+            return rc;
+        ws = scratch.ptr();
+    }
     PackJob jobs[2];
     int nj = 0;
-    if (pa) {
-        jobs[nj++] = PackJob{A, ws, lda, Kp, (int32_t)s.M, (int32_t)s.K, (int32_t)s.M, 0};
+    if (pp.pa) {
+        jobs[nj++] = PackJob{A, ws, lda, pp.Kp, (int32_t)s.M, (int32_t)s.K, (int32_t)s.M, 0};
         g.A = ws;
     }
-    if (pb) {
-        void* wb = (char*)ws + abytes;
-        jobs[nj++] = PackJob{B, wb, ldb, Np, (int32_t)s.K, (int32_t)s.N, (int32_t)Kp, 0};
+    if (pp.pb) {
+        void* wb = (char*)ws + pp.abytes;
+        jobs[nj++] = PackJob{B, wb, ldb, pp.Np, (int32_t)s.K, (int32_t)s.N, (int32_t)pp.Kp, 0};
         g.B = wb;
     }
-    g.lda = lda2;
-    g.ldb = ldb2;
-    g.K = Kp;
+    g.lda = pp.lda2;
+    g.ldb = pp.ldb2;
+    g.K = pp.Kp;
     g.vec_a = g.vec_b = 1;
     const hipError_t err = launch_pack_pair(jobs, nj, es, st);
     mlk_status r = err == hipSuccess ? run_gemm(e, g, s, C, s.M, s.N, ldc, st) : hip_fail(err, "operand packing");

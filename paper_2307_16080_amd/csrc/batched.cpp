@@ -375,6 +375,11 @@ mlk_status mlk_batched_matmul(mlk_dtype in, mlk_dtype out, int64_t count,
     if (!e) return fail(MLK_ERR_CONFIG, "batched: no kernel for configuration");
     if ((flags & MLK_BATCH_PERSISTENT) && !e->persist)
         return fail(MLK_ERR_CONFIG, "batched: tile %dx%dx%d has no persistent variant", c.bm, c.bn, c.bk);
+    // the direct-layout tiles address their output tile with 32-bit offsets
+    for (int64_t i = 0; e->stages >= 1 && i < count; ++i)
+        if ((int64_t)(e->bm - 1) * descs[i].ldc + e->bn >= ((int64_t)1 << 31))
+            return fail(MLK_ERR_CONFIG, "batched: ldc of desc %lld too large for a %d-row direct-layout tile",
+                        (long long)i, e->bm);
     hipStream_t user = (hipStream_t)stream;
     int dev = 0;
     hipError_t herr = hipGetDevice(&dev);

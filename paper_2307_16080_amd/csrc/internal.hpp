@@ -56,7 +56,11 @@ void store_default(const std::string& key, const mlk_tile_config& c);
 // launch one contraction with a resolved configuration
 mlk_status launch_dense(const Shape& s, const void* A, int64_t lda, const void* B, int64_t ldb,
                         void* C, int64_t ldc, const float* sa, const float* sb,
-                        const mlk_tile_config& cfg, hipStream_t st, const float* bias = nullptr);
+                        const mlk_tile_config& cfg, hipStream_t st, const float* bias = nullptr,
+                        void* ext_ws = nullptr, size_t ext_bytes = 0);
+// bytes of packed operand copies launch_dense needs for this launch (0: none)
+int64_t dense_workspace_bytes(const Shape& s, const void* A, int64_t lda, const void* B, int64_t ldb,
+                              const mlk_tile_config& cfg);
 mlk_status launch_conv(const Shape& s, int64_t n, int64_t c, int64_t h, int64_t w, int64_t f,
                        int64_t kh, int64_t kw, int sh, int sw, int ph, int pw, int64_t ho,
                        int64_t wo, const void* x, const void* wt, void* y,
