@@ -390,3 +390,19 @@ def test_tune_bad_arguments(tmp_path):
     with pytest.raises(mlk.MlkError, match="MLK_ERR_DB"):
         mlk.tune(p, mlk.MLK_TUNE_EXHAUSTIVE, fake_timer=True,
                  db_path=str(tmp_path / "no_such_dir" / "db.jsonl"))
+
+
+def test_direct_layout_tiles_refuse_overflowing_output_offsets():
+    """The direct-layout tiles address their output tile with 32-bit offsets: an
+    ldc that would overflow them is refused before anything is enqueued, and
+    such tiles are not offered for a problem whose N alone would overflow."""
+    fast = L.TileConfig(256, 256, 64, 2, 4, 1, 1, 0, 2, 0)
+    big_ldc = (1 << 31) // 255 + 1
+    st = L.lib().mlk_matmul(L.MLK_BF16, L.MLK_F32, 256, 256, 64, 0x10000000, 64, 0x20000000, 256,
+                            0x100000000, big_ldc, NULL, NULL, 1, ctypes.byref(fast), NULL)
+    assert st == 5 and "32-bit" in L.lib().mlk_last_error().decode()
+    p = mlk.matmul_problem(256, (1 << 31) // 255 + 1, 64, L.MLK_BF16, L.MLK_F32)
+    assert not mlk.config_legal(p, fast)
+    N = p.N
+    assert all(c.stages == 0 or (c.bm - 1) * N + c.bn < (1 << 31) for c in mlk.configs(p))
+    assert any(c.stages >= 1 for c in mlk.configs(p))   # the smaller direct-layout tiles stay
