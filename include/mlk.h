@@ -92,9 +92,9 @@ typedef enum {
  *              on their way to a double-buffered LDS tile; any shape and
  *              alignment).  2..5: direct-to-LDS kernel (bf16, e4m3) whose
  *              loads go from memory straight into a ring of `stages` LDS
- *              buffers; matmul operands without 16-byte rows, or with K not
- *              a multiple of bk, are first copied into zero-padded buffers
- *              (library scratch memory); the bf16 conv tiles of this form
+ *              buffers; matmul operands without 16-byte rows, with K not
+ *              a multiple of bk, or (B) with N not a multiple of 16 bytes, are
+ *              first copied into zero-padded buffers (library scratch memory); the bf16 conv tiles of this form
  *              (channels-last layout) need C*KH*KW a multiple of bk.  1: the
  *              same kernel with its operands loaded through registers into
  *              two LDS buffers (bf16, e4m3; bf16 channels-last conv): any
@@ -336,7 +336,8 @@ int32_t mlk_config_count(const mlk_problem* p);
 mlk_status mlk_config_get(const mlk_problem* p, int32_t i, mlk_tile_config* cfg);
 
 /* Record cfg as the tuned choice for p in the in-memory table consulted when
- * a launch gets cfg == NULL (mlk_tune does this for its result). */
+ * a launch gets cfg == NULL (mlk_tune does this for a measured result; its
+ * table_us and fake_timer replays leave the table alone). */
 mlk_status mlk_config_set_default(const mlk_problem* p, const mlk_tile_config* cfg);
 
 /* ------------------------------------------------------------------------ */

@@ -472,7 +472,8 @@ static PackPlan pack_plan(const Shape& s, const KernelEntry* e, const void* A, i
     const bool vec_b = ((uintptr_t)B % 16 == 0) && ((ldb * es) % 16 == 0);
     const bool kfit = s.K % e->bk == 0;
     pp.pa = !(vec_a && kfit);
-    pp.pb = !(vec_b && kfit);
+    // B is read in whole 16-byte chunks up to its last row's padded end
+    pp.pb = !(vec_b && kfit && s.N % (16 / es) == 0);
     pp.Kp = cdiv(s.K, e->bk) * e->bk;
     pp.Np = cdiv(s.N, 16 / es) * (16 / es);
     pp.lda2 = pp.pa ? pp.Kp : lda;

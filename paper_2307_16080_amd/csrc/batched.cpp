@@ -111,7 +111,7 @@ int64_t round_up(int64_t a, int64_t b) { return cdiv(a, b) * b; }
 
 // Build the LPT schedule on the host and upload it.  For a direct-to-LDS tile
 // every operand that is not already in its form (16-byte rows, K a multiple of
-// the stage depth) gets a zero-padded copy: A as M x Kp, B as Kp x Np, with Kp
+// the stage depth; for B also N a multiple of 16 bytes) gets a zero-padded copy: A as M x Kp, B as Kp x Np, with Kp
 // K rounded up to the stage depth and Np N rounded up to 16 bytes.  The padded
 // K columns of A and rows of B are zero, so they add nothing.
 mlk_status build_plan(int dt, int64_t count, const mlk_gemm_desc* d, const KernelEntry* e,
@@ -155,7 +155,8 @@ mlk_status build_plan(int dt, int64_t count, const mlk_gemm_desc* d, const Kerne
                 fixes.push_back(Fix{i, 0, (int64_t)jobs.size() - 1});
                 g.lda = Kp;
             }
-            if (!(kfit && g.vec_b)) {
+            // B is read in whole 16-byte chunks up to its last row's padded end
+            if (!(kfit && g.vec_b && d[i].N % (16 / es) == 0)) {
                 jobs.push_back(PackJob{d[i].B, nullptr, d[i].ldb, Np, (int32_t)d[i].K, (int32_t)d[i].N,
                                        (int32_t)Kp, 0});
                 dst_off.push_back(packed_bytes);

@@ -1,19 +1,21 @@
-// gemm_fast.hpp -- the bf16 / e4m3 matmul main loop for large, aligned
+// gemm_fast.hpp -- the bf16 / e4m3 / int8 matmul main loop for large, aligned
 // problems on gfx950: operands go from HBM straight into LDS (buffer loads
 // with the LDS destination bit, no register staging), B stays in its
 // row-major (N-contiguous) layout in LDS and is transposed on the way out by
 // the gfx950 LDS transpose reads (ds_read_b64_tr_b16 for bf16,
-// ds_read_b64_tr_b8 for e4m3), and the K loop keeps STAGES-1 stages of loads
-// in flight behind the MFMAs.
+// ds_read_b64_tr_b8 for e4m3 and int8), and the K loop keeps STAGES-1 stages
+// of loads in flight behind the MFMAs.
 //
 // What is computed is still linalg.matmul, C[M,N] (+)= A[M,K] * B[K,N]
-// (paper Sec. 2.1, listing "linalg-matmul"), with fp32 accumulation.
+// (paper Sec. 2.1, listing "linalg-matmul"), with fp32 accumulation (int8:
+// sign-extended products summed in int32, wrapping modulo 2^32).
 //
 // Requirements of the direct-to-LDS form (checked on the host): K % BK == 0,
-// A, B 16-byte aligned with row pitches that are multiples of 16 bytes, each
-// operand < 2 GiB.  M and N are arbitrary: rows past the end of an operand
-// read as zero (buffer range check) and columns past N only feed outputs that
-// are never stored.
+// A, B 16-byte aligned with row pitches that are multiples of 16 bytes, N a
+// multiple of the 16-byte chunk (B's rows are read in whole chunks up to the
+// last row's padded end), each operand < 2 GiB.  M is arbitrary: rows past the
+// end of A read as zero (buffer range check); columns past N only feed outputs
+// that are never stored.
 //
 // STAGES == 1 selects the register-loaded form of the same kernel: every
 // thread loads the 16-byte chunks that the DMA would have moved (with the
@@ -22,8 +24,8 @@
 // the element size, K not a multiple of BK) and is the tile that the
 // persistent batched launch runs.
 //
-// LDS layout per stage: A as BM rows of 128 bytes (BK = 64 bf16 or 128
-// e4m3), the 16-byte chunk c of row r stored at chunk c ^ fa(r); B as BK rows
+// LDS layout per stage: A as BM rows of 128 bytes (BK = 64 bf16, or 128
+// e4m3 or int8), the 16-byte chunk c of row r stored at chunk c ^ fa(r); B as BK rows
 // of BN elements, the 16-byte chunk c of row k stored at chunk c ^ fb(k).  The
 // XOR patterns spread the lanes of one LDS read over distinct banks.
 #pragma once
@@ -91,12 +93,17 @@ __device__ inline int fa(int r) { return (r & 7) ^ ((r >> 2) & 2); }
 // so no kernel carries a branch between them.
 template <int DT, int BM, int BN, int WM, int WN, int STAGES, int CONV = 0, int EPI = 0>
 struct FastGemm {
-    static_assert(DT == DT_BF16 || DT == DT_F8, "direct-to-LDS kernel: bf16 or e4m3");
+    static_assert(DT == DT_BF16 || DT == DT_F8 || DT == DT_I8, "direct-layout kernel: bf16, e4m3 or int8");
     static_assert(CONV == 0 || (CONV == 2 && DT == DT_BF16), "implicit convolution: bf16");
+    static_assert(DT != DT_I8 || EPI == 0, "int8: plain int32 output stage only");
     static constexpr int KB = 128;                 // bytes of K per A row per stage
     static constexpr int ES = DT == DT_BF16 ? 2 : 1;
     static constexpr int BK = KB / ES;             // elements per A row per stage
-    static constexpr int KSTEP = DT == DT_BF16 ? 32 : 128;  // k per MFMA
+    // k per MFMA: 16x16x32 bf16, 16x16x128 f8f6f4, 16x16x64 i8
+    static constexpr int KSTEP = DT == DT_BF16 ? 32 : DT == DT_F8 ? 128 : 64;
+    // int8: int32 accumulators and output (sums wrap modulo 2^32)
+    typedef typename std::conditional<DT == DT_I8, i4_t, f4_t>::type acc_t;
+    typedef typename std::conditional<DT == DT_I8, int32_t, float>::type out_t;
     static constexpr int NW = WM * WN;
     static constexpr int NT = 64 * NW;
     static constexpr int A_ROW = KB;               // bytes
@@ -121,14 +128,21 @@ struct FastGemm {
     static constexpr int B_CHUNKS = B_ROW / 16;
 
     static_assert(A_SLABS % NW == 0 && B_SLABS % NW == 0, "slabs must divide among waves");
-    static_assert(CONV || B_CHUNKS >= (DT == DT_BF16 ? 16 : 8), "B rows too short for the swizzle");
+    static_assert(CONV || B_CHUNKS >= (DT == DT_BF16 ? 16 : DT == DT_F8 ? 8 : 4), "B rows too short for the swizzle");
 
     // B swizzle: the rows read together by one transpose read land in distinct
     // 16-byte bank groups.  bf16 reads 4 rows x 32 bytes per lane group, e4m3
-    // 8 rows x 16 bytes.
+    // 8 rows x 16 bytes.  int8 reads 8 rows x 16 bytes per lane group, the
+    // groups 16 rows apart, so the 16 rows a half-wave reads are k = 0..7 and
+    // 16..23 (plus a multiple of 8): with 64 banks of 4 bytes a row pitch of 256
+    // bytes maps every row to the same banks (chunks 0..15 must differ), 128
+    // bytes alternates two halves by k & 1, 64 bytes four quarters by k & 3.
     __device__ static inline int fb(int k) {
         if constexpr (DT == DT_BF16) return ((k & 3) << 1) | (((k >> 3) & 1) << 3);
-        else return (k & 7) | (B_CHUNKS >= 16 ? (((k >> 5) & 1) << 3) : 0);
+        else if constexpr (DT == DT_F8) return (k & 7) | (B_CHUNKS >= 16 ? (((k >> 5) & 1) << 3) : 0);
+        else if constexpr (B_CHUNKS >= 16) return (k & 7) | (((k >> 4) & 1) << 3);
+        else if constexpr (B_CHUNKS == 8) return ((k >> 1) & 3) | (((k >> 4) & 1) << 2);
+        else return ((k >> 2) & 1) | (((k >> 4) & 1) << 1);
     }
     static_assert(LDS_BYTES <= 160 * 1024, "LDS budget");
     static_assert(WTM % 16 == 0 && WTN % 16 == 0, "wave tile");
@@ -339,10 +353,10 @@ struct FastGemm {
     // before the first); e4m3 stages hold one k-step and issue before it (an
     // issue after any of its MFMAs measured ~20% slower).
     template <typename Mid>
-    __device__ static inline void mma_stage(const uint8_t* sa, const uint8_t* sb, f4_t (&acc)[TM][TN], int wy,
+    __device__ static inline void mma_stage(const uint8_t* sa, const uint8_t* sb, acc_t (&acc)[TM][TN], int wy,
                                             int wx, int lr, int lg, Mid&& mid) {
         constexpr int KSTEPS = BK / KSTEP;
-        constexpr int MID_AT = (DT == DT_BF16 && KSTEPS >= 2) ? KSTEPS / 2 : 0;
+        constexpr int MID_AT = (DT != DT_F8 && KSTEPS >= 2) ? KSTEPS / 2 : 0;
         typedef __attribute__((address_space(3))) bf4_t* tp;
         typedef __attribute__((address_space(3))) i2_t* t8p;
 #pragma unroll
@@ -383,6 +397,34 @@ struct FastGemm {
                     for (int i = 0; i < TM; ++i)
                         acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
                             __builtin_bit_cast(bf8_t, af[i]), bj, acc[i][j], 0, 0, 0);
+                }
+            } else if constexpr (DT == DT_I8) {
+                // lane (lr, lg) supplies row / column lr and k bytes
+                // ks*64 + lg*16 .. +15 of the stage, as the 16x16x64 i8 MFMA takes them
+                u4_t af[TM];
+#pragma unroll
+                for (int i = 0; i < TM; ++i) {
+                    const int r = wy * WTM + i * 16 + lr;
+                    af[i] = *(const u4_t*)(sa + r * A_ROW + (((ks * 4 + lg) ^ fa(r)) * 16));
+                }
+#pragma unroll
+                for (int j = 0; j < TN; ++j) {
+                    // two transpose reads: lane lr supplies row lr/2, bytes
+                    // 8*(lr%2)..+7 of an 8 x 16 block and gets column lr (8 k) back
+                    const int nb = wx * WTN + j * 16 + 8 * (lr & 1);
+                    i2_t q[2];
+#pragma unroll
+                    for (int qq = 0; qq < 2; ++qq) {
+                        const int k = ks * 64 + lg * 16 + qq * 8 + (lr >> 1);
+                        const int c = (nb >> 4) ^ fb(k);
+                        const uint8_t* p = sb + k * B_ROW + c * 16 + (nb & 15);
+                        q[qq] = __builtin_amdgcn_ds_read_tr8_b64_v2i32((t8p)(p));
+                    }
+                    const i4_t bj = i4_t{q[0][0], q[0][1], q[1][0], q[1][1]};
+#pragma unroll
+                    for (int i = 0; i < TM; ++i)
+                        acc[i][j] = __builtin_amdgcn_mfma_i32_16x16x64_i8(__builtin_bit_cast(i4_t, af[i]), bj,
+                                                                           acc[i][j], 0, 0, 0);
                 }
             } else {
                 i8_t af[TM], bfr[TN];
@@ -442,7 +484,12 @@ struct FastGemm {
                 rb = make_rsrc(g.B, (uint32_t)((int64_t)g.cn * g.ch * g.cw * g.cc * ES));
                 reg_slots(g, m0, n0, s_beg * BK, wave, lane, rs);
             } else {
-                rb = make_rsrc(g.B, (uint32_t)(((g.K - 1) * g.ldb + g.N) * ES));
+                // B rows are read in whole 16-byte chunks, so the range ends at the
+                // last row's chunk-padded end: the host packs B whenever N is not a
+                // multiple of the chunk (a 16-byte load that crosses the range end
+                // would read back as zero, dropping the last row's products)
+                const int64_t np = (g.N + EPV - 1) / EPV * EPV;
+                rb = make_rsrc(g.B, (uint32_t)(((g.K - 1) * g.ldb + np) * ES));
             }
 #pragma unroll
             for (int i = 0; i < NA; ++i) {
@@ -469,11 +516,11 @@ struct FastGemm {
             reg_slots(g, m0, n0, s_beg * BK, wave, lane, rs);
         }
 
-        f4_t acc[TM][TN];
+        acc_t acc[TM][TN];
 #pragma unroll
         for (int i = 0; i < TM; ++i)
 #pragma unroll
-            for (int j = 0; j < TN; ++j) acc[i][j] = f4_t{0.f, 0.f, 0.f, 0.f};
+            for (int j = 0; j < TN; ++j) acc[i][j] = acc_t{0, 0, 0, 0};
 
         // prologue: STAGES-1 stages in flight (direct), or stage 0 in LDS (registers)
         if constexpr (!REG) {
@@ -495,7 +542,7 @@ struct FastGemm {
         // This lane's outputs: rows wy*WTM + i*16 + lg*4 + r, columns
         // wx*WTN + j*16 + lr of the tile whose corner is Ct (a uniform base);
         // offsets inside the tile are 32-bit.
-        MLK_GLOBAL float* const Ct = (MLK_GLOBAL float*)g.C + (CONV ? 0 : m0 * g.ldc + n0);
+        MLK_GLOBAL out_t* const Ct = (MLK_GLOBAL out_t*)g.C + (CONV ? 0 : m0 * g.ldc + n0);
         // bf16 output (GEMM policy only): the same tile of C as 16-bit codes
         MLK_GLOBAL uint16_t* const Cb = (MLK_GLOBAL uint16_t*)g.C + (CONV ? 0 : m0 * g.ldc + n0);
         const int ldc = (int)g.ldc;
@@ -539,11 +586,11 @@ struct FastGemm {
                     for (int r = 0; r < 4; ++r) {
                         const int row = row0 + i * 16 + r, col = col0 + j * 16;
                         const bool in = full || (row < mrem && col < nrem);
-                        float x = 0.0f;
+                        out_t x = 0;
                         if constexpr (CONV) {
                             if (in) x = Ct[cbase[j] + row * hw];
                         } else {
-                            x = in ? Ct[row * ldc + col] : 0.0f;
+                            x = in ? Ct[row * ldc + col] : (out_t)0;
                         }
                         if constexpr (DT == DT_F8) {
                             const float y = x * inv_alpha;
@@ -559,7 +606,7 @@ struct FastGemm {
 #pragma unroll
                     for (int i = 0; i < TM; ++i)
 #pragma unroll
-                        for (int j = 0; j < TN; ++j) acc[i][j] = f4_t{0.f, 0.f, 0.f, 0.f};
+                        for (int j = 0; j < TN; ++j) acc[i][j] = acc_t{0, 0, 0, 0};
                 }
             }
         }
@@ -597,7 +644,8 @@ struct FastGemm {
             }
         }
         // epilogue: lane l, register r holds output row 4*(l/16) + r, column l % 16
-        const MLK_GLOBAL float* const bias = !EPI || CONV || kz != 0 ? nullptr : (const MLK_GLOBAL float*)g.bias;
+        const MLK_GLOBAL float* const bias =
+            !EPI || CONV || DT == DT_I8 || kz != 0 ? nullptr : (const MLK_GLOBAL float*)g.bias;
         // a bf16 C (direct-to-LDS forms only; never split) is read back, added in
         // fp32 and rounded once; the register-loaded form has no registers to spare
         constexpr bool OUT16 = EPI == 2 && !CONV && !REG;
@@ -657,12 +705,17 @@ struct FastGemm {
                     for (int r = 0; r < 4; ++r) {
                         const int row = row0 + i * 16 + r;
                         if (!(full || (row < mrem && col < nrem))) continue;
-                        MLK_GLOBAL float* p = CONV ? Ct + cbase[j] + row * hw : Ct + row * ldc + col;
-                        const float v0 = DT == DT_F8 ? alpha * acc[i][j][r] : acc[i][j][r];
-                        const float v = EPI ? v0 + bn : v0;
+                        MLK_GLOBAL out_t* p = CONV ? Ct + cbase[j] + row * hw : Ct + row * ldc + col;
+                        out_t v;
+                        if constexpr (DT == DT_I8) {
+                            v = acc[i][j][r];
+                        } else {
+                            const float v0 = DT == DT_F8 ? alpha * acc[i][j][r] : acc[i][j][r];
+                            v = EPI ? v0 + bn : v0;
+                        }
                         if (g.atomic) __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                         else if (c_in_acc || !g.accumulate) *p = v;
-                        else *p = *p + v;
+                        else *p = (out_t)((DT == DT_I8) ? (int32_t)((uint32_t)*p + (uint32_t)v) : *p + v);
                     }
             }
         }

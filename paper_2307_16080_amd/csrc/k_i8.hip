@@ -1,4 +1,5 @@
-// int8 x int8 -> int32 matmul tile configurations (MFMA 16x16x64 i8).
+// int8 x int8 -> int32 matmul tile configurations (MFMA 16x16x64 i8): the
+// register-staged tile and the direct-layout kernel.
 #include "kernels.hpp"
 namespace mlk {
 const KernelEntry* kernels_i8(int* n) {
@@ -12,6 +13,18 @@ const KernelEntry* kernels_i8(int* n) {
         MLK_ENTRY(DT_I8, 128, 128, 128, 2, 2, false),
         MLK_ENTRY(DT_I8, 256, 128, 128, 2, 2, false),
         MLK_ENTRY(DT_I8, 256, 256, 128, 2, 2, false),
+        // direct-layout kernel (MFMA 16x16x64 i8, B transposed by ds_read_b64_tr_b8):
+        // direct-to-LDS rings of 2-4 stages, and the register-loaded form (any alignment)
+        MLK_ENTRY_FAST_I8(64, 64, 2, 2, 2),
+        MLK_ENTRY_FAST_I8(64, 64, 2, 2, 3),
+        MLK_ENTRY_FAST_I8(64, 64, 2, 2, 4),
+        MLK_ENTRY_FAST_I8(128, 64, 2, 2, 3),
+        MLK_ENTRY_FAST_I8(64, 128, 2, 2, 3),
+        MLK_ENTRY_FAST_I8(128, 128, 2, 2, 2),
+        MLK_ENTRY_FAST_I8(128, 128, 2, 2, 4),
+        MLK_ENTRY_FAST_I8(256, 128, 2, 2, 3),
+        MLK_ENTRY_FAST_I8(256, 256, 2, 4, 2),
+        MLK_ENTRY_FAST_I8(128, 128, 2, 2, 1),
     };
     *n = (int)(sizeof(t) / sizeof(t[0]));
     return t;

@@ -225,6 +225,15 @@ launch_fn fast_epi16() {
             &launch_fast<DT, BM, BN, WM, WN, STAGES, 1>, fast_epi16<DT, BM, BN, WM, WN, STAGES>() \
     }
 
+// int8 direct-layout entry: the plain int32 output stage only (no Linear or
+// bf16-output variant, no persistent form: batches are bf16 / fp32)
+#define MLK_ENTRY_FAST_I8(BM, BN, WM, WN, STAGES)                                            \
+    KernelEntry {                                                                            \
+        DT_I8, 0, STAGES, BM, BN, FastGemm<DT_I8, BM, BN, WM, WN, STAGES>::BK, WM, WN,        \
+            FastGemm<DT_I8, BM, BN, WM, WN, STAGES>::LDS_BYTES, 64 * (WM) * (WN),            \
+            &launch_fast<DT_I8, BM, BN, WM, WN, STAGES>, nullptr, nullptr, nullptr, nullptr, nullptr \
+    }
+
 // conv entry: channels-last layout only (launch_nhwc); no NCHW form, no persistent form
 #define MLK_ENTRY_FASTCONV(DT, BM, BN, WM, WN, STAGES)                                       \
     KernelEntry {                                                                            \

@@ -470,7 +470,9 @@ extern "C" mlk_status mlk_tune(const mlk_problem* p, const mlk_tune_opts* o, mlk
     r.best_us = t[pick];
     if (o->times_us)
         for (int i = 0; i < S; ++i) o->times_us[i] = t[i];
-    store_default(key, *best);
+    // a measured result becomes the default for launches that pass no
+    // configuration; replays of a table or of the analytic timer do not
+    if (!host_timer) store_default(key, *best);
     if (o->db_path && !db_append(o->db_path, key, dev, *best, r.best_us, r.n_measured, S, o->strategy)) {
         if (rep) *rep = r;
         return fail(MLK_ERR_DB, "tune: cannot append to database %s", o->db_path);

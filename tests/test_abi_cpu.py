@@ -249,9 +249,12 @@ def test_config_space():
     odd = mlk.matmul_problem(1000, 1001, 999, L.MLK_BF16, L.MLK_F32)
     assert any(c.stages >= 2 for c in mlk.configs(odd))
     assert mlk.config_legal(odd, mlk.TileConfig(256, 256, 64, 2, 4, 1, 8, 0, 2, 0))
-    # but not fp32 or int8 problems
+    # int8 has its own direct-layout tiles (int32 output stage only); fp32 has none
     assert not any(c.stages for c in mlk.configs(mlk.matmul_problem(999, 999, 999, L.MLK_F32, L.MLK_F32)))
-    assert not any(c.stages for c in mlk.configs(mlk.matmul_problem(999, 999, 999, L.MLK_I8, L.MLK_I32)))
+    i8 = mlk.matmul_problem(999, 999, 999, L.MLK_I8, L.MLK_I32)
+    assert {c.stages for c in mlk.configs(i8)} >= {0, 1, 2, 3, 4}
+    assert all(c.bk == 128 for c in mlk.configs(i8) if c.stages)
+    assert mlk.config_legal(i8, mlk.TileConfig(64, 64, 128, 2, 2, 4, 1, 0, 3, 0))
     bp = mlk.batched_problem([(100, 200, 300), (64, 64, 64)])
     bc = mlk.configs(bp)
     assert bc and all(c.split_k == 1 for c in bc)
@@ -406,3 +409,4 @@ def test_direct_layout_tiles_refuse_overflowing_output_offsets():
     N = p.N
     assert all(c.stages == 0 or (c.bm - 1) * N + c.bn < (1 << 31) for c in mlk.configs(p))
     assert any(c.stages >= 1 for c in mlk.configs(p))   # the smaller direct-layout tiles stay
+

@@ -133,6 +133,10 @@ def test_i8_split_k_and_wraparound():
         C = dev(C0)
         mlk.matmul(dev(A), dev(B), C, cfg=mlk.TileConfig(64, 64, 64, 2, 2, sk, 1, 0))
         assert np.array_equal(host(C), oracle.matmul_i8(A, B, C0)), sk
+        # the direct-to-LDS int8 tile: int32 atomics under split K wrap the same way
+        C = dev(C0)
+        mlk.matmul(dev(A), dev(B), C, cfg=mlk.TileConfig(64, 64, 128, 2, 2, sk, 1, 0, 3, 0))
+        assert np.array_equal(host(C), oracle.matmul_i8(A, B, C0)), ("direct", sk)
 
 
 # ----------------------------------------------------------------------- quantisation
@@ -408,3 +412,43 @@ def test_precision_4096_sampled_rows():
     e = normwise(host(C)[rows], exact)
     say("f32 4096 err", e)
     assert e <= 1e-5
+
+
+# ----------------------------------------------------------------------- direct-layout edge
+
+@pytest.mark.parametrize("kind", ["bf16", "e4m3", "i8"])
+def test_direct_tiles_last_k_row_with_unaligned_n(kind):
+    """K a whole number of stages and N not a multiple of the 16-byte chunk:
+    the last K row of B ends inside a chunk.  Every direct-to-LDS tile, with B
+    as a plain (M, N) tensor and as a view whose 16-byte-aligned row pitch
+    exceeds N, must still sum that row's products (bit-exact on small
+    integers; the oracle in double elsewhere)."""
+    din = {"bf16": L.MLK_BF16, "e4m3": L.MLK_F8E4M3, "i8": L.MLK_I8}[kind]
+    dout = L.MLK_I32 if kind == "i8" else L.MLK_F32
+    tiles = [c for c in all_tiles(din, dout) if c.stages >= 2]
+    assert tiles
+    for (M, N, K) in ((519, 625, 64), (37, 13, 128), (130, 255, 256)):
+        Kk = K if kind == "bf16" else 2 * K          # a whole number of 128-deep stages for 1-byte inputs
+        P = (N + 15) // 16 * 16 + 16                 # a 16-byte-aligned row pitch beyond N
+        if kind == "i8":
+            A, B = matmul_inputs(M, N, Kk, seed=M + N, dist="int8")
+            ref = oracle.matmul_i8(A, B)
+            a, b_full = dev(A), torch.zeros(Kk, P, dtype=torch.int8, device="cuda")
+            b_full[:, :N] = dev(B)
+            cdt = torch.int32
+        else:
+            A, B = matmul_inputs(M, N, Kk, seed=M + N, dist="small_int")
+            ref = oracle.matmul_f64(A, B)
+            enc = (lambda x: from_bf16_codes(oracle.bf16_encode(x))) if kind == "bf16" else \
+                  (lambda x: from_e4m3_codes(oracle.e4m3_encode(x, 1.0)))
+            a = enc(A)
+            Bw = np.zeros((Kk, P), np.float32)
+            Bw[:, :N] = B
+            b_full = enc(Bw)
+            cdt = torch.float32
+        for b in (b_full[:, :N].contiguous(), b_full[:, :N]):   # plain, and a pitched view
+            for c in tiles:
+                C = torch.zeros(M, N, dtype=cdt, device="cuda")
+                mlk.matmul(a, b, C, cfg=c)
+                got = host(C)
+                assert np.array_equal(got.astype(ref.dtype), ref), (kind, (M, N, Kk), c, b.stride())
