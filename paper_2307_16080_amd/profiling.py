@@ -6,6 +6,8 @@ for the batched workload to run under the profiler.
             <kernel-name-substring> <copy-bytes> <out.json> [source_hash] [tile]
     python -m paper_2307_16080_amd.profiling batched <tile> <launches>
     python -m paper_2307_16080_amd.profiling paperconv <tile> <launches>
+    python -m paper_2307_16080_amd.profiling gemm <bf16|e4m3|f32|i8> <tile> <launches> [size]
+    python -m paper_2307_16080_amd.profiling resnet <batch> <launches>
 
 `batched` runs the 256 uneven bf16 GEMMs of the benchmark (seeded shapes and
 inputs) as persistent launches, replayed from a hipGraph, with the given tile
@@ -119,8 +121,94 @@ def run_paper_conv(tile, launches):
     print(f"paper conv: {launches} launches, tile {tile}; one 256 MiB copy", flush=True)
 
 
+def _copy_reference():
+    """One plain 256 MiB device copy: the reference dispatch for the HBM byte counters."""
+    import torch
+
+    src = torch.empty(256 << 20, dtype=torch.uint8, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+
+
+def run_gemm(kind, tile, launches, size=4096):
+    """The benchmark's square GEMM (C += A B, inputs seeded as the benchmark
+    draws them) launched back to back with one fixed tile, then the reference
+    copy.  kind: bf16 | e4m3 | f32 (size^3) or i8 (1024^3 by default)."""
+    import os
+
+    import torch
+
+    sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+    import paper_2307_16080_amd as mlk
+    from workloads import matmul_inputs
+
+    n = size
+    A, B = matmul_inputs(n, n, n, seed=0, dist="int8" if kind == "i8" else "normal")
+    Ad, Bd = torch.from_numpy(A).cuda(), torch.from_numpy(B).cuda()
+    kw = {}
+    if kind == "bf16":
+        a, _ = mlk.quantize(Ad, "bf16")
+        b, _ = mlk.quantize(Bd, "bf16")
+        C = torch.zeros(n, n, device="cuda")
+    elif kind == "e4m3":
+        a, sa = mlk.quantize(Ad, "e4m3")
+        b, sb = mlk.quantize(Bd, "e4m3")
+        kw = dict(scale_a=sa, scale_b=sb)
+        C = torch.zeros(n, n, device="cuda")
+    elif kind == "i8":
+        a, b = Ad, Bd
+        C = torch.zeros(n, n, dtype=torch.int32, device="cuda")
+    else:
+        a, b = Ad, Bd
+        C = torch.zeros(n, n, device="cuda")
+    cfg = mlk.TileConfig(*[int(v) for v in tile.split(",")])
+    for _ in range(launches):
+        mlk.matmul(a, b, C, cfg=cfg, **kw)
+    torch.cuda.synchronize()
+    _copy_reference()
+    print(f"gemm {kind} {n}^3: {launches} launches, tile {tile}; one 256 MiB copy", flush=True)
+
+
+def run_resnet(batch, launches):
+    """The ResNet-18 conv stack (bf16, seeded inputs) at one batch size: each
+    layer shape tuned exhaustively (as the benchmark does), then every layer of
+    the stack launched `launches` times in stack order with its tuned tile."""
+    import os
+
+    import torch
+
+    sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+    import paper_2307_16080_amd as mlk
+    from paper_2307_16080_amd import _lib as L
+    from workloads import resnet18_conv_stack
+
+    calls = []
+    for shape, count in resnet18_conv_stack(batch):
+        p = mlk.conv_problem(shape.N, shape.C, shape.H, shape.W, shape.F, shape.KH, shape.KW, shape.stride,
+                             shape.pad, L.MLK_BF16, L.MLK_F32)
+        best, _, _ = mlk.tune(p, mlk.MLK_TUNE_EXHAUSTIVE, reps=3, warmup=1)
+        qx, _ = mlk.quantize(torch.randn(shape.N, shape.C, shape.H, shape.W, device="cuda"), "bf16")
+        qw, _ = mlk.quantize(torch.randn(shape.F, shape.C, shape.KH, shape.KW, device="cuda"), "bf16")
+        ho, wo = shape.out_hw()
+        y = torch.zeros(shape.N, shape.F, ho, wo, device="cuda")
+        call = mlk.ConvCall(qx, qw, y, (shape.stride,) * 2, (shape.pad,) * 2, cfg=best)
+        calls += [call] * count
+        print(f"layer {shape}: tile {list(best.as_tuple())}", flush=True)
+    torch.cuda.synchronize()
+    for _ in range(launches):
+        for call in calls:
+            call()
+    torch.cuda.synchronize()
+    print(f"resnet18 b{batch}: {launches} passes over {len(calls)} layers", flush=True)
+
+
 if __name__ == "__main__":
-    if sys.argv[1] == "batched":
+    if sys.argv[1] == "gemm":
+        run_gemm(sys.argv[2], sys.argv[3], int(sys.argv[4]), *(int(v) for v in sys.argv[5:6]))
+    elif sys.argv[1] == "resnet":
+        run_resnet(int(sys.argv[2]), int(sys.argv[3]))
+    elif sys.argv[1] == "batched":
         run_batched(sys.argv[2], int(sys.argv[3]))
     elif sys.argv[1] == "paperconv":
         run_paper_conv(sys.argv[2], int(sys.argv[3]))
