@@ -159,6 +159,30 @@ mlk_status mlk_matmul(mlk_dtype in, mlk_dtype out, int64_t M, int64_t N, int64_t
                       const mlk_tile_config* cfg, void* stream);
 
 /*
+ * mlk_matmul for callers that cannot allocate device memory: code recorded
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc.  Same arguments, dtypes, results and errors as mlk_matmul, and
+ * the same kernels; the only difference is where a direct-to-LDS tile's
+ * zero-padded operand copies go (needed when A or B lacks 16-byte rows, K
+ * is not a multiple of the tile depth, or B's N is not a multiple of 16
+ * bytes): into a fixed device array of
+ * MLK_NOALLOC_WORKSPACE_BYTES (64 MiB), one per device, held by the library
+ * until the process ends, instead of the library's growable scratch buffer.
+ * The call allocates nothing, takes no scratch lock, and may be captured.
+ * A shape and tile whose packed copies exceed the array return
+ * MLK_ERR_SHAPE before anything is enqueued.
+ * Every call on one device shares that device's array: calls that overlap
+ * in time on one device (different streams, or several host threads) race on
+ * it; order them on one stream.  The packing kernel writes every byte the
+ * GEMM reads, so nothing carries over from an earlier call.
+ */
+#define MLK_NOALLOC_WORKSPACE_BYTES ((size_t)64 << 20)
+mlk_status mlk_matmul_noalloc(mlk_dtype in, mlk_dtype out, int64_t M, int64_t N, int64_t K,
+                              const void* A, int64_t lda, const void* B, int64_t ldb, void* C,
+                              int64_t ldc, const float* scale_a, const float* scale_b, int accumulate,
+                              const mlk_tile_config* cfg, void* stream);
+
+/*
  * The Linear layer: C[i,j] (+)= sum_k A[i,k] * B[k,j] + bias[j]  -- the
  * product nest followed by the bias nest that adds bias[j] to every row
  * (Sec. 2.1, listing "listing1"), with the bias add fused into the product's

@@ -23,7 +23,7 @@ from ._lib import (MLK_BATCH_GRAPH, MLK_BATCH_PERSISTENT, MLK_BF16, MLK_F8E4M3, 
                    MLK_TUNE_ES, MLK_TUNE_MODEL, MLK_TUNE_RANDOM, GemmDesc, MlkError, Problem, TileConfig,
                    TuneOpts, TuneReport)
 
-__all__ = ["matmul", "matmul_bias", "conv2d_nchw_fchw", "ConvCall", "quantize", "batched_matmul", "BatchedCall", "err_stats", "tune",
+__all__ = ["matmul", "matmul_noalloc", "matmul_bias", "conv2d_nchw_fchw", "ConvCall", "quantize", "batched_matmul", "BatchedCall", "err_stats", "tune",
            "config_count", "configs", "config_legal", "set_default_config", "CostModel",
            "mlp_forward", "mlp_loss_grad", "adam_step", "release", "version", "TileConfig",
            "Problem", "MlkError", "matmul_problem", "conv_problem", "batched_problem"]
@@ -114,6 +114,24 @@ def matmul(A, B, C, accumulate: bool = True, cfg=None, scale_a=None, scale_b=Non
     L.check(L.lib().mlk_matmul(_dt(A), _dt(C), M, N, K, _ptr(A), _row_major_ld(A), _ptr(B),
                                _row_major_ld(B), _ptr(C), _row_major_ld(C), _ptr(scale_a),
                                _ptr(scale_b), int(bool(accumulate)), _cfg(cfg), _stream(stream)))
+    return C
+
+
+def matmul_noalloc(A, B, C, accumulate: bool = True, cfg=None, scale_a=None, scale_b=None, stream=None):
+    """matmul through mlk_matmul_noalloc: operand packing (when the tile needs it)
+    uses the library's fixed per-device array, so the call allocates nothing
+    (usable under graph capture).  Calls overlapping on one device race on it."""
+    _need(A.dim() == 2 and B.dim() == 2 and C.dim() == 2, 2, "matmul operands must be 2-D")
+    M, K = A.shape
+    K2, N = B.shape
+    if K2 != K or tuple(C.shape) != (M, N):
+        raise MlkError(2, f"shape mismatch: A {tuple(A.shape)}, B {tuple(B.shape)}, C {tuple(C.shape)}")
+    _need(B.dtype == A.dtype, 4, f"A and B must have one dtype (got {A.dtype}, {B.dtype})")
+    _check_scale(scale_a, "scale_a")
+    _check_scale(scale_b, "scale_b")
+    L.check(L.lib().mlk_matmul_noalloc(_dt(A), _dt(C), M, N, K, _ptr(A), _row_major_ld(A), _ptr(B),
+                                       _row_major_ld(B), _ptr(C), _row_major_ld(C), _ptr(scale_a),
+                                       _ptr(scale_b), int(bool(accumulate)), _cfg(cfg), _stream(stream)))
     return C
 
 

@@ -79,6 +79,8 @@ _probp = ctypes.POINTER(Problem)
 SIGNATURES = {
     "mlk_matmul": (_st, [_int, _int, _i64, _i64, _i64, _vp, _i64, _vp, _i64, _vp, _i64, _vp, _vp,
                          _int, _cfgp, _vp]),
+    "mlk_matmul_noalloc": (_st, [_int, _int, _i64, _i64, _i64, _vp, _i64, _vp, _i64, _vp, _i64, _vp,
+                                 _vp, _int, _cfgp, _vp]),
     "mlk_matmul_bias": (_st, [_int, _int, _i64, _i64, _i64, _vp, _i64, _vp, _i64, _vp, _vp, _i64,
                               _vp, _vp, _int, _cfgp, _vp]),
     "mlk_conv2d_nchw_fchw": (_st, [_int, _int, _i64, _i64, _i64, _i64, _i64, _i64, _i64, _i32,

@@ -637,6 +637,35 @@ mlk_status launch_conv(const Shape& s, int64_t n, int64_t c, int64_t h, int64_t 
     return MLK_OK;
 }
 
+// ------------------------------------------------------------------ no-alloc workspace
+
+// The workspace of mlk_matmul_noalloc: a fixed device array, one copy per
+// device that loads the library, held until the process ends.  Host code
+// never passes the array's name as an address: each device's copy is looked
+// up once (hipGetSymbolAddress with that device current) and its address kept.
+constexpr size_t kNoallocBytes = MLK_NOALLOC_WORKSPACE_BYTES;
+static __device__ __align__(256) uint8_t noalloc_scratch[kNoallocBytes];
+
+static std::mutex g_noalloc_mu;
+static std::map<int, void*> g_noalloc_ptr;
+
+static mlk_status noalloc_workspace(void** out) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    std::lock_guard<std::mutex> g(g_noalloc_mu);
+    auto it = g_noalloc_ptr.find(dev);
+    if (it == g_noalloc_ptr.end()) {
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(noalloc_scratch));
+        if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress(no-alloc workspace)");
+        if (!p) return fail(MLK_ERR_HIP, "hipGetSymbolAddress(no-alloc workspace) returned NULL");
+        it = g_noalloc_ptr.emplace(dev, p).first;
+    }
+    *out = it->second;
+    return MLK_OK;
+}
+
 static bool overlaps(const void* a, size_t na, const void* b, size_t nb) {
     const uintptr_t x = (uintptr_t)a, y = (uintptr_t)b;
     return x < y + nb && y < x + na;
@@ -672,7 +701,7 @@ static mlk_status matmul_impl(mlk_dtype in, mlk_dtype out, int64_t M, int64_t N,
                               const void* A, int64_t lda, const void* B, int64_t ldb, void* C,
                               int64_t ldc, const float* scale_a, const float* scale_b,
                               const float* bias, int accumulate, const mlk_tile_config* cfg,
-                              void* stream) {
+                              void* stream, bool noalloc = false) {
     mlk_problem p;
     memset(&p, 0, sizeof p);
     p.op = MLK_OP_MATMUL;
@@ -712,6 +741,21 @@ static mlk_status matmul_impl(mlk_dtype in, mlk_dtype out, int64_t M, int64_t N,
     st = resolve(p, s, cfg, &c);
     if (st != MLK_OK) return st;
     if (M == 0 || N == 0) return MLK_OK;
+    if (noalloc) {
+        // packed operand copies go to the fixed device array: refuse what it cannot hold
+        const int64_t need = dense_workspace_bytes(s, A, lda, B, ldb, c);
+        if (need > (int64_t)kNoallocBytes)
+            return fail(MLK_ERR_SHAPE,
+                        "matmul_noalloc: operand packing for this shape and tile needs %lld bytes, more than "
+                        "the %zu-byte no-alloc workspace; use operands with 16-byte rows and K a multiple of "
+                        "the tile depth, or a tile without packing (stages 0 or 1)",
+                        (long long)need, kNoallocBytes);
+        void* ws = nullptr;
+        if (need > 0)
+            if (mlk_status r = noalloc_workspace(&ws); r != MLK_OK) return r;
+        return launch_dense(s, A, lda, B, ldb, C, ldc, scale_a, scale_b, c, (hipStream_t)stream, bias, ws,
+                            kNoallocBytes);
+    }
     return launch_dense(s, A, lda, B, ldb, C, ldc, scale_a, scale_b, c, (hipStream_t)stream, bias);
 }
 
@@ -722,6 +766,15 @@ mlk_status mlk_matmul(mlk_dtype in, mlk_dtype out, int64_t M, int64_t N, int64_t
     clear_error();
     return matmul_impl(in, out, M, N, K, A, lda, B, ldb, C, ldc, scale_a, scale_b, nullptr,
                        accumulate, cfg, stream);
+}
+
+mlk_status mlk_matmul_noalloc(mlk_dtype in, mlk_dtype out, int64_t M, int64_t N, int64_t K,
+                              const void* A, int64_t lda, const void* B, int64_t ldb, void* C,
+                              int64_t ldc, const float* scale_a, const float* scale_b, int accumulate,
+                              const mlk_tile_config* cfg, void* stream) {
+    clear_error();
+    return matmul_impl(in, out, M, N, K, A, lda, B, ldb, C, ldc, scale_a, scale_b, nullptr,
+                       accumulate, cfg, stream, true);
 }
 
 mlk_status mlk_matmul_bias(mlk_dtype in, mlk_dtype out, int64_t M, int64_t N, int64_t K,

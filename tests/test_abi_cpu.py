@@ -410,3 +410,22 @@ def test_direct_layout_tiles_refuse_overflowing_output_offsets():
     assert all(c.stages == 0 or (c.bm - 1) * N + c.bn < (1 << 31) for c in mlk.configs(p))
     assert any(c.stages >= 1 for c in mlk.configs(p))   # the smaller direct-layout tiles stay
 
+
+def test_matmul_noalloc_validation():
+    """mlk_matmul_noalloc checks its arguments like mlk_matmul and refuses a
+    shape whose packed operand copies exceed its fixed workspace, all before
+    any HIP call (no GPU here)."""
+    lib = L.lib()
+
+    def call(M, N, K, A, lda, B, ldb, C, ldc, cfg):
+        return lib.mlk_matmul_noalloc(L.MLK_BF16, L.MLK_F32, M, N, K, A, lda, B, ldb, C, ldc, NULL, NULL, 1,
+                                      cfg, NULL)
+
+    packed = L.TileConfig(128, 128, 64, 2, 2, 1, 1, 0, 4, 0)
+    assert call(-1, 4, 4, 0x1000, 4, 0x2000, 4, 0x3000, 4, NULL) == 2
+    assert call(4, 4, 4, NULL, 4, 0x2000, 4, 0x3000, 4, NULL) == 1
+    assert call(4, 4, 4, 0x1000, 3, 0x2000, 4, 0x3000, 4, NULL) == 3
+    # 4096 x 8193 bf16 A packed to 4096 x 8256: more than the 64 MiB workspace
+    st = call(4096, 64, 8193, 0x10000000, 8193, 0x20000000, 64, 0x30000000, 64, ctypes.byref(packed))
+    msg = lib.mlk_last_error().decode()
+    assert st == 2 and "no-alloc workspace" in msg, msg
