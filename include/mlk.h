@@ -38,7 +38,9 @@
  *  - Stream capture: those workspace routes are not recorded into a captured
  *    graph: on a stream that is capturing they return MLK_ERR_CONFIG and
  *    enqueue nothing.  Configurations without a workspace (register-loaded
- *    tiles, aligned direct-to-LDS operands, conv layout 0) may be captured.
+ *    tiles, aligned direct-to-LDS operands, conv layout 0) may be captured;
+ *    so may every run of a bound convolution (mlk_conv2d_plan_run, whose
+ *    buffers are allocated when the plan is created) and mlk_matmul_noalloc.
  *  - Thread safety: calls from several host threads are safe; calls that
  *    overlap on one device share its workspaces and are serialised inside
  *    the library.
@@ -221,6 +223,42 @@ mlk_status mlk_conv2d_nchw_fchw(mlk_dtype in, mlk_dtype out, int64_t N, int64_t 
                                 void* y, int accumulate, const mlk_tile_config* cfg, void* stream);
 
 /*
+ * A convolution bound once to its shape, tile configuration and filter, for
+ * callers that run the same layer many times (a network's layers in a
+ * serving loop), including under HIP graph capture.  Same operation, dtypes
+ * and results as mlk_conv2d_nchw_fchw (Sec. 4.1, listing "2dnchwconv").
+ *
+ * mlk_conv2d_plan_create validates the problem, resolves the configuration
+ * (cfg NULL or zeroed: the tuned default or the heuristic, as for
+ * mlk_conv2d_nchw_fchw), and, for the channels-last layout (layout 1),
+ * allocates the plan's own buffers (an NHWC copy of the input and, for
+ * filters larger than 1 x 1, the filter as F x KH x KW x C) and enqueues the
+ * filter's transpose on `stream`.  It must not be called on a capturing
+ * stream (MLK_ERR_CONFIG).  `w` (device, FCHW) is bound to the plan: runs use
+ * its values as of creation (or of the last mlk_conv2d_plan_update_filter,
+ * which re-reads it, stream-ordered); it must stay allocated while the plan
+ * exists.  `accumulate` is fixed per plan.  On success *plan owns the
+ * buffers; free with mlk_conv2d_plan_destroy (which waits for the device).
+ *
+ * mlk_conv2d_plan_run computes y (+)= conv(x, w) on `stream`: x (N,C,H,W) and
+ * y (N,F,HO,WO) contiguous device buffers (x 16-byte aligned for layout 1);
+ * it allocates nothing, takes no library lock and may be recorded into a
+ * captured graph.  Runs of one plan that overlap in time (several streams)
+ * race on its input copy; different plans are independent.  The plan must be
+ * run on the device it was created on.
+ * mlk_conv2d_plan_config returns the configuration the plan resolved.
+ */
+typedef struct mlk_conv_plan mlk_conv_plan;
+mlk_status mlk_conv2d_plan_create(mlk_dtype in, mlk_dtype out, int64_t N, int64_t C, int64_t H, int64_t W,
+                                  int64_t F, int64_t KH, int64_t KW, int32_t sh, int32_t sw, int32_t ph,
+                                  int32_t pw, const void* w, int accumulate, const mlk_tile_config* cfg,
+                                  void* stream, mlk_conv_plan** plan);
+mlk_status mlk_conv2d_plan_run(const mlk_conv_plan* plan, const void* x, void* y, void* stream);
+mlk_status mlk_conv2d_plan_update_filter(mlk_conv_plan* plan, void* stream);
+mlk_status mlk_conv2d_plan_config(const mlk_conv_plan* plan, mlk_tile_config* cfg);
+void mlk_conv2d_plan_destroy(mlk_conv_plan* plan);
+
+/*
  * Quantise n fp32 values for the low-precision paths.
  *   out = MLK_BF16:   q[i] = bf16 round-to-nearest-even of x[i]; scale unused
  *                     (may be NULL).  NaN becomes a quiet NaN, overflow inf.
@@ -365,15 +403,19 @@ mlk_status mlk_config_get(const mlk_problem* p, int32_t i, mlk_tile_config* cfg)
 mlk_status mlk_config_set_default(const mlk_problem* p, const mlk_tile_config* cfg);
 
 /* ------------------------------------------------------------------------ */
-/* Learned cost model: an MLP  features(problem, config) -> log(time in us),
- * trained on the GPU by the library's own forward / backward / Adam kernels. */
+/* Learned cost model: MLPs  features(problem, config) -> log(time in us),
+ * trained on the GPU by the library's own forward / backward / Adam kernels.
+ * A model holds three networks of the same shape, initialised and trained
+ * from different seeds on the same samples; its prediction is the mean of
+ * their log-time predictions. */
 
 /* Feature vector length and the features of (p, cfg) (host computation). */
 int32_t mlk_model_feature_count(void);
 mlk_status mlk_model_features(const mlk_problem* p, const mlk_tile_config* cfg, float* out);
 
-/* hidden: width of both hidden layers (1..256).  Weights are initialised on
- * the host from `seed` and uploaded; the model owns device buffers. */
+/* hidden: width of both hidden layers of each network (1..256).  Weights
+ * are initialised on the host from `seed` and uploaded; the model owns
+ * device buffers. */
 mlk_status mlk_model_create(int32_t hidden, uint64_t seed, mlk_cost_model** out);
 void mlk_model_destroy(mlk_cost_model* m);
 /* Add one training sample (a measured median time, microseconds > 0). */
@@ -381,8 +423,9 @@ mlk_status mlk_model_add_sample(mlk_cost_model* m, const mlk_problem* p,
                                 const mlk_tile_config* cfg, double time_us);
 int64_t mlk_model_sample_count(const mlk_cost_model* m);
 /* Normalise features over the current samples, then run `epochs` passes of
- * minibatch Adam (batch rows, learning rate lr) on the GPU.  *final_loss
- * (may be NULL) receives the last epoch's mean squared error in log space. */
+ * minibatch Adam (batch rows, learning rate lr) on the GPU for each network.
+ * *final_loss (may be NULL) receives the networks' mean full-batch squared
+ * error in normalised log space. */
 mlk_status mlk_model_train(mlk_cost_model* m, int32_t epochs, int32_t batch, float lr,
                            float* final_loss);
 /* Predicted time (microseconds) of n configurations of p (host arrays). */

@@ -188,28 +188,52 @@ def conv2d_nchw_fchw(x, w, y, stride=(1, 1), pad=(0, 0), accumulate: bool = True
 
 
 class ConvCall:
-    """One convolution bound once to its tensors: shapes, dtypes, pointers and
-    the configuration are checked and marshalled here, so each call is a single
-    library call (a layer in a serving loop pays no per-call Python work beyond
-    it).  The tensors are kept alive by the object; their storage must not move
-    between calls.  `stream`, if given here, is the default for every call."""
+    """One convolution bound once to its tensors (mlk_conv2d_plan_*): shape,
+    configuration and filter are checked, resolved and bound here, so each
+    call is a single library call that allocates nothing and may be recorded
+    into a captured graph.  The filter's values are those at binding (or at
+    the last update_filter()).  The tensors are kept alive by the object; their
+    storage must not move between calls.  `stream`, if given here, orders the
+    binding's own work (the channels-last filter transpose) and is the default
+    for every call."""
 
     def __init__(self, x, w, y, stride=(1, 1), pad=(0, 0), accumulate: bool = True, cfg=None,
                  stream=None):
-        self._args = _conv_args(x, w, y, stride, pad, accumulate)
+        a = _conv_args(x, w, y, stride, pad, accumulate)
         self._keep = (x, w, y)
         self._cfg = None if cfg is None else (cfg if isinstance(cfg, TileConfig) else TileConfig(*cfg))
-        self._cfgp = _cfg(self._cfg)
-        self._fn = L.lib().mlk_conv2d_nchw_fchw
         self._stream = None if stream is None else _stream(stream)
+        h = ctypes.c_void_p()
+        # (din, dout, N, C, H, W, F, KH, KW, sh, sw, ph, pw, x, w, y, accumulate)
+        L.check(L.lib().mlk_conv2d_plan_create(*a[:13], a[14], a[16], _cfg(self._cfg),
+                                               self._stream if self._stream is not None else _stream(None),
+                                               ctypes.byref(h)))
+        self._plan = h.value
+        self._x, self._y = a[13], a[15]
+        self._run = L.lib().mlk_conv2d_plan_run
+
+    @property
+    def config(self):
+        c = TileConfig()
+        L.check(L.lib().mlk_conv2d_plan_config(self._plan, ctypes.byref(c)))
+        return c
+
+    def update_filter(self, stream=None):
+        L.check(L.lib().mlk_conv2d_plan_update_filter(self._plan, _stream(stream) if stream is not None
+                                                      else (self._stream or _stream(None))))
 
     def __call__(self, stream=None):
         if stream is not None:
             st = _stream(stream)
         else:
             st = self._stream if self._stream is not None else _stream(None)
-        L.check(self._fn(*self._args, self._cfgp, st))
+        L.check(self._run(self._plan, self._x, self._y, st))
         return self._keep[2]
+
+    def __del__(self):
+        if getattr(self, "_plan", None) and L._lib is not None:
+            L.lib().mlk_conv2d_plan_destroy(self._plan)
+            self._plan = None
 
 
 def conv_out_hw(H, W, KH, KW, stride=(1, 1), pad=(0, 0)):

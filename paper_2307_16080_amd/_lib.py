@@ -85,6 +85,12 @@ SIGNATURES = {
                               _vp, _vp, _int, _cfgp, _vp]),
     "mlk_conv2d_nchw_fchw": (_st, [_int, _int, _i64, _i64, _i64, _i64, _i64, _i64, _i64, _i32,
                                    _i32, _i32, _i32, _vp, _vp, _vp, _int, _cfgp, _vp]),
+    "mlk_conv2d_plan_create": (_st, [_int, _int, _i64, _i64, _i64, _i64, _i64, _i64, _i64, _i32, _i32, _i32,
+                                     _i32, _vp, _int, _cfgp, _vp, ctypes.POINTER(_vp)]),
+    "mlk_conv2d_plan_run": (_st, [_vp, _vp, _vp, _vp]),
+    "mlk_conv2d_plan_update_filter": (_st, [_vp, _vp]),
+    "mlk_conv2d_plan_config": (_st, [_vp, _cfgp]),
+    "mlk_conv2d_plan_destroy": (None, [_vp]),
     "mlk_quantize": (_st, [_int, _i64, _vp, _vp, _vp, _vp]),
     "mlk_batched_matmul": (_st, [_int, _int, _i64, ctypes.POINTER(GemmDesc), _cfgp, _int, _u32,
                                  _vp]),

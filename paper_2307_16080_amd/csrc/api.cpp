@@ -561,7 +561,7 @@ mlk_status launch_dense(const Shape& s, const void* A, int64_t lda, const void* 
 mlk_status launch_conv(const Shape& s, int64_t n, int64_t c, int64_t h, int64_t w, int64_t f,
                        int64_t kh, int64_t kw, int sh, int sw, int ph, int pw, int64_t ho,
                        int64_t wo, const void* x, const void* wt, void* y,
-                       const mlk_tile_config& cfg, hipStream_t st) {
+                       const mlk_tile_config& cfg, hipStream_t st, const ConvPrep* prep) {
     const KernelEntry* e = find_kernel(s.dt, 1, cfg);
     if (!e) return fail(MLK_ERR_CONFIG, "no kernel for configuration");
     GemmArgs g = base_args(s, cfg);
@@ -596,7 +596,8 @@ mlk_status launch_conv(const Shape& s, int64_t n, int64_t c, int64_t h, int64_t 
         if (!(e->launch_nhwc && c % epv == 0 && (uintptr_t)x % 16 == 0 && (uintptr_t)wt % 16 == 0 &&
               n <= 65535 && f <= 65535))
             return fail(MLK_ERR_CONFIG, "channels-last layout needs C %% %d == 0, aligned x and w, N, F <= 65535", epv);
-        if (mlk_status rc = refuse_under_capture(st, "the channels-last conv layout"); rc != MLK_OK) return rc;
+        if (!prep)
+            if (mlk_status rc = refuse_under_capture(st, "the channels-last conv layout"); rc != MLK_OK) return rc;
     } else if (!e->launch) {
         return fail(MLK_ERR_CONFIG, "this conv tile runs only the channels-last layout (layout 1)");
     }
@@ -609,6 +610,17 @@ mlk_status launch_conv(const Shape& s, int64_t n, int64_t c, int64_t h, int64_t 
     // x to NHWC and the filter to F x KH x KW x C in the library's scratch
     // buffer, so every operand load of the tile kernel is one aligned 16-byte
     // read.
+    if (cfg.layout == 1 && prep) {
+        // a bound convolution: its own NHWC buffer, its filter already transposed
+        hipError_t err = launch_transpose_pair(x, prep->xn, n, c, h * w, nullptr, nullptr, 0, 0, 0, es, st);
+        if (err == hipSuccess) {
+            g.A = prep->w_cl;
+            g.B = prep->xn;
+            g.vec_a = 1;
+            err = e->launch_nhwc(g, (int)nblk, st);
+        }
+        return err == hipSuccess ? MLK_OK : hip_fail(err, "conv launch");
+    }
     if (cfg.layout == 1) {
         const size_t xb = ((size_t)(n * c * h * w) * es + 255) & ~(size_t)255;
         const size_t wb = (size_t)(f * c * kh * kw) * es;
@@ -827,6 +839,160 @@ mlk_status mlk_conv2d_nchw_fchw(mlk_dtype in, mlk_dtype out, int64_t N, int64_t 
         c.layout = 0;
     return launch_conv(s, N, C, H, W, F, KH, KW, sh, sw, ph, pw, ho, wo, x, w, y, c,
                        (hipStream_t)stream);
+}
+
+}  // extern "C"
+
+// A convolution bound to its shape, configuration and filter.
+struct mlk_conv_plan {
+    mlk::Shape s;
+    int64_t n = 0, c = 0, h = 0, w = 0, f = 0, kh = 0, kw = 0, ho = 0, wo = 0;
+    int32_t sh = 1, sw = 1, ph = 0, pw = 0;
+    mlk_tile_config cfg{};
+    const void* filter = nullptr;  // the caller's FCHW filter
+    void* buf = nullptr;           // channels-last layout: NHWC input copy, then the transposed filter
+    size_t xb = 0;                 // bytes of the input copy (256-byte multiple)
+    int device = 0;
+};
+
+namespace {
+
+// the filter in F x KH x KW x C for a channels-last plan (a 1 x 1 filter is
+// used as it is)
+mlk_status plan_transpose_filter(const mlk_conv_plan* pl, hipStream_t st) {
+    if (pl->cfg.layout != 1 || pl->kh * pl->kw == 1) return MLK_OK;
+    const int es = esize_in(pl->s.dt);
+    const hipError_t e = launch_transpose_pair(nullptr, nullptr, 0, 0, 0, pl->filter, (char*)pl->buf + pl->xb,
+                                               pl->f, pl->c, pl->kh * pl->kw, es, st);
+    return e == hipSuccess ? MLK_OK : hip_fail(e, "conv plan filter transpose");
+}
+
+}  // namespace
+
+extern "C" {
+
+mlk_status mlk_conv2d_plan_create(mlk_dtype in, mlk_dtype out, int64_t N, int64_t C, int64_t H, int64_t W,
+                                  int64_t F, int64_t KH, int64_t KW, int32_t sh, int32_t sw, int32_t ph,
+                                  int32_t pw, const void* w, int accumulate, const mlk_tile_config* cfg,
+                                  void* stream, mlk_conv_plan** plan) {
+    clear_error();
+    if (!plan) return fail(MLK_ERR_NULL, "conv plan: plan is NULL");
+    *plan = nullptr;
+    mlk_problem p;
+    memset(&p, 0, sizeof p);
+    p.op = MLK_OP_CONV2D;
+    p.in = in;
+    p.out = out;
+    p.accumulate = accumulate ? 1 : 0;
+    p.n = N;
+    p.c = C;
+    p.h = H;
+    p.w = W;
+    p.f = F;
+    p.kh = KH;
+    p.kw = KW;
+    p.sh = sh;
+    p.sw = sw;
+    p.ph = ph;
+    p.pw = pw;
+    Shape s;
+    mlk_status st = shape_of_problem(&p, &s);
+    if (st != MLK_OK) return st;
+    if (!w) return fail(MLK_ERR_NULL, "conv plan: w is NULL");
+    mlk_tile_config c;
+    st = resolve(p, s, cfg, &c);
+    if (st != MLK_OK) return st;
+    if (c.layout == 1 && (uintptr_t)w % 16 != 0) {
+        if (!cfg_is_zero(cfg)) return fail(MLK_ERR_CONFIG, "conv plan: the channels-last layout needs an aligned w");
+        c.layout = 0;
+    }
+    if (c.layout == 1 && (N > 65535 || F > 65535)) {
+        if (!cfg_is_zero(cfg)) return fail(MLK_ERR_CONFIG, "conv plan: the channels-last layout needs N, F <= 65535");
+        c.layout = 0;
+    }
+    const hipStream_t hs = (hipStream_t)stream;
+    // the plan's buffers are allocated here, so creation cannot be captured
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    hipError_t e = hipStreamIsCapturing(hs, &cs);
+    if (e != hipSuccess) return hip_fail(e, "hipStreamIsCapturing");
+    if (cs != hipStreamCaptureStatusNone)
+        return fail(MLK_ERR_CONFIG, "conv plan: create plans outside stream capture (runs may be captured)");
+    mlk_conv_plan* pl = new mlk_conv_plan();
+    pl->s = s;
+    pl->n = N;
+    pl->c = C;
+    pl->h = H;
+    pl->w = W;
+    pl->f = F;
+    pl->kh = KH;
+    pl->kw = KW;
+    pl->ho = conv_out(H, KH, sh, ph);
+    pl->wo = conv_out(W, KW, sw, pw);
+    pl->sh = sh;
+    pl->sw = sw;
+    pl->ph = ph;
+    pl->pw = pw;
+    pl->cfg = c;
+    pl->filter = w;
+    if ((e = hipGetDevice(&pl->device)) != hipSuccess) {
+        delete pl;
+        return hip_fail(e, "hipGetDevice");
+    }
+    if (c.layout == 1) {
+        const int es = esize_in(s.dt);
+        pl->xb = ((size_t)(N * C * H * W) * es + 255) & ~(size_t)255;
+        const size_t wb = KH * KW == 1 ? 0 : (size_t)(F * C * KH * KW) * es;
+        if ((e = hipMalloc(&pl->buf, pl->xb + wb)) != hipSuccess) {
+            delete pl;
+            return hip_fail(e, "conv plan buffers");
+        }
+        if ((st = plan_transpose_filter(pl, hs)) != MLK_OK) {
+            mlk_conv2d_plan_destroy(pl);
+            return st;
+        }
+    }
+    *plan = pl;
+    return MLK_OK;
+}
+
+mlk_status mlk_conv2d_plan_update_filter(mlk_conv_plan* plan, void* stream) {
+    clear_error();
+    if (!plan) return fail(MLK_ERR_NULL, "conv plan is NULL");
+    return plan_transpose_filter(plan, (hipStream_t)stream);
+}
+
+mlk_status mlk_conv2d_plan_run(const mlk_conv_plan* plan, const void* x, void* y, void* stream) {
+    clear_error();
+    if (!plan) return fail(MLK_ERR_NULL, "conv plan is NULL");
+    if (!x || !y) return fail(MLK_ERR_NULL, "conv plan: x or y is NULL");
+    const mlk_conv_plan& pl = *plan;
+    const int es = esize_in(pl.s.dt);
+    const size_t yb = (size_t)(pl.n * pl.f * pl.ho * pl.wo) * 4;
+    if (overlaps(y, yb, x, (size_t)(pl.n * pl.c * pl.h * pl.w) * es) ||
+        overlaps(y, yb, pl.filter, (size_t)(pl.f * pl.c * pl.kh * pl.kw) * es))
+        return fail(MLK_ERR_LAYOUT, "conv plan: y overlaps x or w");
+    if (pl.cfg.layout == 1 && (uintptr_t)x % 16 != 0)
+        return fail(MLK_ERR_LAYOUT, "conv plan: its channels-last layout needs a 16-byte aligned x");
+    int dev = 0;
+    const hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    if (dev != pl.device) return fail(MLK_ERR_ARG, "conv plan: created on device %d, run on device %d", pl.device, dev);
+    ConvPrep prep{pl.buf, pl.kh * pl.kw == 1 ? pl.filter : (const void*)((const char*)pl.buf + pl.xb)};
+    return launch_conv(pl.s, pl.n, pl.c, pl.h, pl.w, pl.f, pl.kh, pl.kw, pl.sh, pl.sw, pl.ph, pl.pw, pl.ho, pl.wo, x,
+                       pl.filter, y, pl.cfg, (hipStream_t)stream, pl.cfg.layout == 1 ? &prep : nullptr);
+}
+
+mlk_status mlk_conv2d_plan_config(const mlk_conv_plan* plan, mlk_tile_config* cfg) {
+    clear_error();
+    if (!plan || !cfg) return fail(MLK_ERR_NULL, "conv plan: NULL pointer");
+    *cfg = plan->cfg;
+    return MLK_OK;
+}
+
+void mlk_conv2d_plan_destroy(mlk_conv_plan* plan) {
+    if (!plan) return;
+    if (plan->buf) (void)hipFree(plan->buf);
+    delete plan;
 }
 
 mlk_status mlk_quantize(mlk_dtype out, int64_t n, const float* x, void* q, float* scale,

@@ -61,10 +61,17 @@ mlk_status launch_dense(const Shape& s, const void* A, int64_t lda, const void* 
 // bytes of packed operand copies launch_dense needs for this launch (0: none)
 int64_t dense_workspace_bytes(const Shape& s, const void* A, int64_t lda, const void* B, int64_t ldb,
                               const mlk_tile_config& cfg);
+// Buffers a bound convolution owns for the channels-last layout: the NHWC
+// copy of the input (written by each call) and the filter already laid out
+// F x KH x KW x C.  With them launch_conv takes no scratch memory.
+struct ConvPrep {
+    void* xn;
+    const void* w_cl;
+};
 mlk_status launch_conv(const Shape& s, int64_t n, int64_t c, int64_t h, int64_t w, int64_t f,
                        int64_t kh, int64_t kw, int sh, int sw, int ph, int pw, int64_t ho,
                        int64_t wo, const void* x, const void* wt, void* y,
-                       const mlk_tile_config& cfg, hipStream_t st);
+                       const mlk_tile_config& cfg, hipStream_t st, const ConvPrep* prep = nullptr);
 
 int64_t conv_out(int64_t in, int64_t k, int64_t stride, int64_t pad);
 

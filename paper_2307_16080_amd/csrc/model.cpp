@@ -24,8 +24,8 @@ struct mlk_cost_model {
     std::vector<float> y;   // log(time in us)
     std::vector<float> mu, sd;  // feature normalisation
     float ymu = 0.f, ysd = 1.f;
-    std::vector<float> params;  // host copy of the initial parameters
-    float* d_params = nullptr;
+    std::vector<float> params;  // host copy of the initial parameters, kMembers networks
+    float* d_params = nullptr;  // kMembers parameter vectors back to back (as are d_m, d_v)
     float* d_m = nullptr;
     float* d_v = nullptr;
     float* d_g = nullptr;
@@ -39,7 +39,12 @@ namespace mlk {
 
 namespace {
 
-constexpr int kFeatures = 29;
+constexpr int kFeatures = 36;
+// The model is a small ensemble: kMembers networks of the same shape, started
+// from different initial weights and batch orders, whose log-time predictions
+// are averaged (one network's ranking of close configurations varies with its
+// initialisation more than the measurements it was trained on).
+constexpr int kMembers = 3;
 
 int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
 double lg(double v) { return std::log2(std::max(v, 1.0)); }
@@ -93,10 +98,22 @@ void model_features(const Shape& s, const mlk_tile_config& c, int cus, float* f)
     // direct-to-LDS ring (its depth)
     f[i++] = c.stages == 1 ? 1.f : 0.f;
     f[i++] = c.stages >= 2 ? (float)c.stages : 0.f;
+    // convolution view (zero for a matmul): channels, filter taps and stride,
+    // and the sizes the channels-last layout transposes before its GEMM (input,
+    // and the filter unless it is 1 x 1)
+    const double taps = s.conv ? (double)s.conv_kh * s.conv_kw : 0.0;
+    const double in_el = s.conv ? (double)std::max<int64_t>(s.conv_in, 1) : 0.0;
+    f[i++] = s.conv ? (float)lg((double)s.conv_c) : 0.f;
+    f[i++] = (float)taps;
+    f[i++] = s.conv ? (float)s.conv_sh : 0.f;
+    f[i++] = (float)lg(in_el);
+    f[i++] = c.layout == 1 ? (float)lg(in_el) : 0.f;
+    f[i++] = c.layout == 1 && taps > 1 ? (float)lg((double)M * K) : 0.f;
+    f[i++] = c.layout == 2 ? 1.f : 0.f;
 }
 
 static mlk_status upload_params(mlk_cost_model* m) {
-    const int64_t P = param_count(m->D0, m->hidden);
+    const int64_t P = param_count(m->D0, m->hidden) * kMembers;
     hipError_t e = hipSuccess;
     if (!m->d_params) {
         if ((e = hipMalloc((void**)&m->d_params, sizeof(float) * P)) != hipSuccess ||
@@ -132,10 +149,11 @@ mlk_status model_predict_shape(mlk_cost_model* m, const Shape& s,
     float *dX = nullptr, *dy = nullptr;
     hipError_t e;
     if ((e = hipMalloc((void**)&dX, sizeof(float) * X.size())) != hipSuccess) return hip_fail(e, "predict alloc");
-    if ((e = hipMalloc((void**)&dy, sizeof(float) * n)) != hipSuccess) {
+    if ((e = hipMalloc((void**)&dy, sizeof(float) * n * kMembers)) != hipSuccess) {
         (void)hipFree(dX);
         return hip_fail(e, "predict alloc");
     }
+    const int64_t P = param_count(D0, m->hidden);
     mlk_status st = MLK_OK;
     if ((e = hipMemcpy(dX, X.data(), sizeof(float) * X.size(), hipMemcpyHostToDevice)) != hipSuccess)
         st = hip_fail(e, "predict upload");
@@ -143,19 +161,27 @@ mlk_status model_predict_shape(mlk_cost_model* m, const Shape& s,
         ScratchUse scratch;
         if ((st = scratch.begin(sizeof(float) * mlp_forward_words(n, m->hidden, m->hidden), 0, "model predict")) ==
             MLK_OK) {
-            e = launch_mlp_forward(n, D0, m->hidden, m->hidden, m->d_params, dX, dy, (float*)scratch.ptr(), 0);
+            for (int k = 0; k < kMembers && e == hipSuccess; ++k)
+                e = launch_mlp_forward(n, D0, m->hidden, m->hidden, m->d_params + k * P, dX, dy + (int64_t)k * n,
+                                       (float*)scratch.ptr(), 0);
             st = scratch.end();
             if (e != hipSuccess) st = hip_fail(e, "predict forward");
         }
     }
+    std::vector<float> all((size_t)n * kMembers);
     if (st == MLK_OK && e == hipSuccess) {
-        if ((e = hipMemcpy(us->data(), dy, sizeof(float) * n, hipMemcpyDeviceToHost)) != hipSuccess)
+        if ((e = hipMemcpy(all.data(), dy, sizeof(float) * all.size(), hipMemcpyDeviceToHost)) != hipSuccess)
             st = hip_fail(e, "predict download");
     }
     (void)hipFree(dX);
     (void)hipFree(dy);
     if (st != MLK_OK) return st;
-    for (int i = 0; i < n; ++i) (*us)[i] = std::exp((*us)[i] * m->ysd + m->ymu);
+    // the members' normalised log-time predictions averaged, then back to microseconds
+    for (int i = 0; i < n; ++i) {
+        double a = 0.0;
+        for (int k = 0; k < kMembers; ++k) a += all[(size_t)k * n + i];
+        (*us)[i] = std::exp((float)(a / kMembers) * m->ysd + m->ymu);
+    }
     return MLK_OK;
 }
 
@@ -185,19 +211,21 @@ mlk_status mlk_model_create(int32_t hidden, uint64_t seed, mlk_cost_model** out)
     m->hidden = hidden;
     m->D0 = kFeatures;
     m->seed = seed;
-    // He-uniform initialisation of the weights, zero biases
+    // He-uniform initialisation of every member's weights, zero biases
     const int64_t P = param_count(m->D0, hidden);
-    m->params.assign((size_t)P, 0.f);
+    m->params.assign((size_t)(P * kMembers), 0.f);
     std::mt19937_64 rng(seed);
-    auto fill = [&](int64_t off, int64_t fan_in, int64_t count) {
-        const float lim = std::sqrt(6.0f / (float)fan_in);
-        std::uniform_real_distribution<float> u(-lim, lim);
-        for (int64_t i = 0; i < count; ++i) m->params[(size_t)(off + i)] = u(rng);
-    };
     const int64_t D0 = m->D0, H = hidden;
-    fill(0, D0, D0 * H);
-    fill(D0 * H + H, H, H * H);
-    fill(D0 * H + H + H * H + H, H, H);
+    for (int k = 0; k < kMembers; ++k) {
+        auto fill = [&](int64_t off, int64_t fan_in, int64_t count) {
+            const float lim = std::sqrt(6.0f / (float)fan_in);
+            std::uniform_real_distribution<float> u(-lim, lim);
+            for (int64_t i = 0; i < count; ++i) m->params[(size_t)(k * P + off + i)] = u(rng);
+        };
+        fill(0, D0, D0 * H);
+        fill(D0 * H + H, H, H * H);
+        fill(D0 * H + H + H * H + H, H, H);
+    }
     mlk_status st = upload_params(m);
     if (st != MLK_OK) {
         mlk_model_destroy(m);
@@ -288,40 +316,53 @@ mlk_status mlk_model_train(mlk_cost_model* m, int32_t epochs, int32_t batch, flo
     }
     float* ws = (float*)scratch.ptr();
     std::vector<int64_t> perm((size_t)n);
-    std::iota(perm.begin(), perm.end(), 0);
-    std::mt19937_64 rng(m->seed ^ 0xA5A5A5A5ull);
     std::vector<float> Xs(Xn.size()), ys(yn.size());
     float loss = 0.f;
     st = MLK_OK;
-    for (int ep = 0; ep < epochs && st == MLK_OK; ++ep) {
-        std::shuffle(perm.begin(), perm.end(), rng);
-        for (int64_t i = 0; i < n; ++i) {
-            memcpy(&Xs[(size_t)(i * D0)], &Xn[(size_t)(perm[i] * D0)], sizeof(float) * D0);
-            ys[(size_t)i] = yn[(size_t)perm[i]];
-        }
-        if ((e = hipMemcpy(dX, Xs.data(), sizeof(float) * Xs.size(), hipMemcpyHostToDevice)) != hipSuccess ||
-            (e = hipMemcpy(dy, ys.data(), sizeof(float) * ys.size(), hipMemcpyHostToDevice)) != hipSuccess) {
-            st = hip_fail(e, "train upload");
-            break;
-        }
-        for (int64_t off = 0; off < n; off += batch) {
-            const int64_t B = std::min<int64_t>(batch, n - off);
-            if ((e = launch_mlp_loss_grad(B, D0, H, H, m->d_params, dX + off * D0, dy + off, m->d_g,
-                                          m->d_loss, ws, 0)) != hipSuccess ||
-                (e = launch_adam(P, m->d_params, m->d_g, m->d_m, m->d_v, lr, 0.9f, 0.999f, 1e-8f,
-                                 ++m->step, 0)) != hipSuccess) {
-                st = hip_fail(e, "train step");
+    // each member: its own initial weights, Adam state and batch order
+    for (int k = 0; k < kMembers && st == MLK_OK; ++k) {
+        float* pk = m->d_params + k * P;
+        float* mk = m->d_m + k * P;
+        float* vk = m->d_v + k * P;
+        std::iota(perm.begin(), perm.end(), 0);
+        std::mt19937_64 rng((m->seed + 0x9E37ull * k) ^ 0xA5A5A5A5ull);
+        int64_t step = 0;
+        for (int ep = 0; ep < epochs && st == MLK_OK; ++ep) {
+            std::shuffle(perm.begin(), perm.end(), rng);
+            for (int64_t i = 0; i < n; ++i) {
+                memcpy(&Xs[(size_t)(i * D0)], &Xn[(size_t)(perm[i] * D0)], sizeof(float) * D0);
+                ys[(size_t)i] = yn[(size_t)perm[i]];
+            }
+            if ((e = hipMemcpy(dX, Xs.data(), sizeof(float) * Xs.size(), hipMemcpyHostToDevice)) != hipSuccess ||
+                (e = hipMemcpy(dy, ys.data(), sizeof(float) * ys.size(), hipMemcpyHostToDevice)) != hipSuccess) {
+                st = hip_fail(e, "train upload");
                 break;
             }
+            for (int64_t off = 0; off < n; off += batch) {
+                const int64_t B = std::min<int64_t>(batch, n - off);
+                if ((e = launch_mlp_loss_grad(B, D0, H, H, pk, dX + off * D0, dy + off, m->d_g, m->d_loss, ws,
+                                              0)) != hipSuccess ||
+                    (e = launch_adam(P, pk, m->d_g, mk, vk, lr, 0.9f, 0.999f, 1e-8f, ++step, 0)) != hipSuccess) {
+                    st = hip_fail(e, "train step");
+                    break;
+                }
+            }
         }
+        m->step += step;
     }
     if (st == MLK_OK) {
-        // full-batch loss of the final parameters
+        // full-batch loss of the final parameters, averaged over the members
         if ((e = hipMemcpy(dX, Xn.data(), sizeof(float) * Xn.size(), hipMemcpyHostToDevice)) != hipSuccess ||
-            (e = hipMemcpy(dy, yn.data(), sizeof(float) * yn.size(), hipMemcpyHostToDevice)) != hipSuccess ||
-            (e = launch_mlp_loss_grad(n, D0, H, H, m->d_params, dX, dy, m->d_g, m->d_loss, ws, 0)) != hipSuccess ||
-            (e = hipMemcpy(&loss, m->d_loss, sizeof(float), hipMemcpyDeviceToHost)) != hipSuccess)
+            (e = hipMemcpy(dy, yn.data(), sizeof(float) * yn.size(), hipMemcpyHostToDevice)) != hipSuccess)
             st = hip_fail(e, "train final loss");
+        for (int k = 0; k < kMembers && st == MLK_OK; ++k) {
+            float lk = 0.f;
+            if ((e = launch_mlp_loss_grad(n, D0, H, H, m->d_params + k * P, dX, dy, m->d_g, m->d_loss, ws, 0)) !=
+                    hipSuccess ||
+                (e = hipMemcpy(&lk, m->d_loss, sizeof(float), hipMemcpyDeviceToHost)) != hipSuccess)
+                st = hip_fail(e, "train final loss");
+            loss += lk / kMembers;
+        }
     }
     const mlk_status rel = scratch.end();
     if (st == MLK_OK) st = rel;

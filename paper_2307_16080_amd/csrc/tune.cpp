@@ -9,7 +9,9 @@
 // black-box search of the kind the paper runs through an external optimiser
 // library, written here over the configuration's fields.  The objective is the median of `reps` timed samples after
 // `warmup` untimed launches; each sample times enough back-to-back launches
-// (hipEvents on the tuning stream) to last about 0.2 ms.
+// (hipEvents on the tuning stream) to last about 0.2 ms.  Before the best is
+// declared, the three fastest measured configurations are timed again,
+// interleaved, three times each, and their medians replace their first times.
 //
 // Results are appended to a JSON-lines database keyed by the problem and the
 // device, and recorded as the default configuration for later launches that
@@ -440,13 +442,32 @@ extern "C" mlk_status mlk_tune(const mlk_problem* p, const mlk_tune_opts* o, mlk
         }
         for (int k = 0; k < budget; ++k) eval(plan[k]);
     }
+    r.n_measured = (int)order.size();
     if (!host_timer) {
+        // The fastest few are timed again, interleaved, before one is declared
+        // the best: a single short burst of a latency-bound kernel can read a
+        // few percent fast or slow, and the ranking of close configurations
+        // with it.  No new configuration is measured here.
+        std::vector<int> top;
+        for (int i : order)
+            if (t[i] > 0) top.push_back(i);
+        std::stable_sort(top.begin(), top.end(), [&](int a, int b) { return t[a] < t[b]; });
+        if (top.size() > 3) top.resize(3);
+        if (top.size() > 1) {
+            std::vector<std::vector<double>> again(top.size());
+            for (int round = 0; round < 3; ++round)
+                for (size_t j = 0; j < top.size(); ++j) again[j].push_back(measure(p, s, sc, cfgs[top[j]], 1, reps, 0, e0, e1));
+            for (size_t j = 0; j < top.size(); ++j) {
+                std::vector<double>& v = again[j];
+                std::sort(v.begin(), v.end());
+                if (v[1] > 0) t[top[j]] = v[1];  // median of the three re-timings
+            }
+        }
         (void)hipDeviceSynchronize();
         (void)hipEventDestroy(e0);
         (void)hipEventDestroy(e1);
         clear_error();
     }
-    r.n_measured = (int)order.size();
 
     // fastest, with configurations within 1% counted as tied: smaller LDS
     // footprint first, then the lower enumeration index

@@ -220,33 +220,38 @@ def test_workspace_routes_refused_under_capture():
     torch.cuda.synchronize()
 
 
-@pytest.mark.skip(reason="records stream-ordered workspace allocations into a captured graph; a replay of a "
-                         "larger capture of that kind (the ResNet-18 stack) hit a GPU memory fault in the "
-                         "weight transpose, with no cause found in this library; those routes now refuse "
-                         "a capturing stream")
 def test_conv_stack_graph_capture_replays():
-    """Library calls recorded into one HIP graph (torch's capture of the current
-    stream): the channels-last route's stream-ordered workspace, its
-    transposes and the tile kernel, the NCHW route and a GEMM, each layer
-    twice (C += twice).  Every replay, from zeroed outputs and with eager work
-    and synchronisations between replays, equals the eager calls bit for bit."""
+    """Bound convolutions (mlk.ConvCall: plans whose buffers are allocated when
+    they are created) recorded into one HIP graph with torch's capture of the
+    current stream: channels-last layers (3 x 3 and 1 x 1, their NHWC copies
+    in the plans' own buffers, filters transposed once), an NCHW layer, a
+    direct-conv layer, and a packed direct-to-LDS matmul through
+    mlk_matmul_noalloc; each layer twice (y += twice).  Every replay, from
+    zeroed outputs and with eager work and synchronisations between replays,
+    equals the eager calls bit for bit, and the first layer matches the
+    oracle."""
     layers = [((2, 64, 14, 14, 64, 3, 3, 1, 1), mlk.TileConfig(128, 128, 64, 2, 2, 1, 1, 0, 1, 1)),
               ((2, 32, 9, 11, 16, 3, 3, 2, 1), mlk.TileConfig(64, 64, 32, 2, 2, 1, 1, 0, 0, 0)),
-              ((1, 128, 7, 7, 256, 1, 1, 1, 0), mlk.TileConfig(64, 128, 64, 2, 2, 1, 1, 0, 1, 1))]
-    ops = []
+              ((1, 128, 7, 7, 256, 1, 1, 1, 0), mlk.TileConfig(64, 128, 64, 2, 2, 1, 1, 0, 1, 1)),
+              ((1, 64, 56, 56, 64, 3, 3, 1, 1), mlk.TileConfig(64, 64, 64, 2, 2, 1, 1, 0, 3, 1)),
+              ((1, 8, 40, 40, 3, 3, 3, 1, 0), None)]
+    ops, outs, first = [], [], None
     for i, (case, cfg) in enumerate(layers):
         N, C, H, W, F, KH, KW, s, p = case
         x, w = conv_inputs(N, C, H, W, F, KH, KW, seed=30 + i)
         qx, qw = from_bf16_codes(oracle.bf16_encode(x)), from_bf16_codes(oracle.bf16_encode(w))
+        if i == 4:   # fp32 few-filter layer: the direct conv
+            qx, qw = dev(x), dev(w)
         y = torch.zeros(N, F, (H + 2 * p - KH) // s + 1, (W + 2 * p - KW) // s + 1, device="cuda")
-        ops.append(lambda qx=qx, qw=qw, y=y, s=s, p=p, cfg=cfg:
-                   mlk.conv2d_nchw_fchw(qx, qw, y, (s, s), (p, p), cfg=cfg))
-        ops.append(ops[-1])
-        layers[i] = y
+        call = mlk.ConvCall(qx, qw, y, (s, s), (p, p), cfg=cfg)
+        if i == 0:
+            first = (x, w, s, p, y)
+        ops += [call, call]
+        outs.append(y)
     A, B = (from_bf16_codes(oracle.bf16_encode(m)) for m in matmul_inputs(200, 136, 72, seed=5))
     Cm = torch.zeros(200, 136, device="cuda")
-    ops.append(lambda: mlk.matmul(A, B, Cm, cfg=mlk.TileConfig(128, 128, 64, 2, 2, 1, 1, 0, 1, 0)))
-    outs = layers + [Cm]
+    ops.append(lambda: mlk.matmul_noalloc(A, B, Cm, cfg=mlk.TileConfig(128, 128, 64, 2, 2, 1, 1, 0, 4, 0)))
+    outs.append(Cm)
 
     def zero():
         for t in outs:
@@ -257,6 +262,10 @@ def test_conv_stack_graph_capture_replays():
         op()
     torch.cuda.synchronize()
     want = [t.cpu().clone() for t in outs]
+    x, w, s, p, _ = first
+    ref = 2.0 * oracle.conv2d_f64(oracle.bf16_decode(oracle.bf16_encode(x)),
+                                  oracle.bf16_decode(oracle.bf16_encode(w)), (s, s), (p, p))
+    assert normwise(want[0].numpy(), ref) <= 1e-5
     side = torch.cuda.Stream()
     side.wait_stream(torch.cuda.current_stream())
     with torch.cuda.stream(side):                           # warm-up on a side stream
@@ -274,9 +283,52 @@ def test_conv_stack_graph_capture_replays():
         torch.cuda.synchronize()
         graph.replay()
         torch.cuda.synchronize()
-        for i, (t, ref) in enumerate(zip(outs, want)):
-            assert torch.equal(t.cpu(), ref), (rep, i)
+        for i, (t, r) in enumerate(zip(outs, want)):
+            assert torch.equal(t.cpu(), r), (rep, i)
         del junk
+    del graph
+
+
+@pytest.mark.parametrize("case", [(2, 64, 14, 14, 64, 3, 3, 1, 1), (1, 128, 7, 7, 256, 1, 1, 2, 0),
+                                  (3, 16, 9, 13, 24, 3, 3, 2, 1)])
+def test_conv_plan_every_config(case):
+    """Every legal configuration of a layer, bound as a plan, equals the per-call
+    API bit for bit over two accumulating runs and matches the oracle; the
+    filter's values are the ones at binding until update_filter()."""
+    N, C, H, W, F, KH, KW, s, p = case
+    x, w = conv_inputs(N, C, H, W, F, KH, KW, seed=N + C + F)
+    qx, qw = from_bf16_codes(oracle.bf16_encode(x)), from_bf16_codes(oracle.bf16_encode(w))
+    ref = oracle.conv2d_f64(oracle.bf16_decode(oracle.bf16_encode(x)), oracle.bf16_decode(oracle.bf16_encode(w)),
+                            (s, s), (p, p))
+    ho, wo = (H + 2 * p - KH) // s + 1, (W + 2 * p - KW) // s + 1
+    prob = mlk.conv_problem(N, C, H, W, F, KH, KW, s, p, L.MLK_BF16, L.MLK_F32)
+    for cfg in mlk.configs(prob):
+        y1 = torch.zeros(N, F, ho, wo, device="cuda")
+        y2 = torch.zeros_like(y1)
+        call = mlk.ConvCall(qx, qw, y1, (s, s), (p, p), cfg=cfg)
+        assert call.config.as_tuple() == cfg.as_tuple()
+        for _ in range(2):
+            call()
+            mlk.conv2d_nchw_fchw(qx, qw, y2, (s, s), (p, p), cfg=cfg)
+        torch.cuda.synchronize()
+        if cfg.split_k == 1:   # (split K adds partials with atomics: equal within rounding only)
+            assert torch.equal(y1, y2), cfg
+        assert normwise(host(y1), 2.0 * ref) <= 1e-5, cfg
+        assert normwise(host(y2), 2.0 * ref) <= 1e-5, cfg
+    # the bound filter: changed values reach the plan only through update_filter
+    call = mlk.ConvCall(qx, qw, y1, (s, s), (p, p), cfg=mlk.configs(prob)[-1])
+    w_saved = qw.clone()
+    qw.zero_()
+    y1.zero_()
+    call.update_filter()
+    call()
+    assert torch.count_nonzero(y1).item() == 0
+    qw.copy_(w_saved)
+    call.update_filter()
+    y1.zero_()
+    call()
+    assert normwise(host(y1), ref) <= 1e-5
+
 
 
 def test_scratch_shared_across_streams():

@@ -1,0 +1,128 @@
+"""The learned cost model as the library runs it, measuring live.
+
+Exhaustive tables of the ResNet-18 conv problems (batch 1 and 32) are
+measured on the GPU; for each held-out layer, a model is trained on the GPU
+(the library's own MLP kernels) on the tables of every OTHER layer (both batch
+sizes of the held-out layer excluded), and the library's model-guided search
+(mlk_tune, MLK_TUNE_MODEL) then tunes each batch variant of the held-out
+layer by timing configurations live.  Its choice is judged on the held-out
+problem's exhaustive table: regret = t(chosen) / t(exhaustive best) - 1,
+with at most ceil(0.2 S) configurations measured, against the library's
+random search at the same budget (replayed on the same table, 21 seeds).
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import paper_2307_16080_amd as mlk
+from paper_2307_16080_amd import _lib as L
+from paper_2307_16080_amd import costmodel
+from workloads import resnet18_conv_stack
+
+from gpu_util import say
+
+pytestmark = pytest.mark.gpu
+
+BUDGET = 0.2
+
+
+def _problems():
+    out = []
+    for batch in (1, 32):
+        for shape, _count in resnet18_conv_stack(batch):
+            out.append(mlk.conv_problem(shape.N, shape.C, shape.H, shape.W, shape.F, shape.KH, shape.KW,
+                                        shape.stride, shape.pad, L.MLK_BF16, L.MLK_F32))
+    return out
+
+
+def _time_us(fn, iters):
+    fn()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(iters):
+        fn()
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) * 1e3 / iters
+
+
+def paired_regret(p, chosen, best, rounds=7, iters=30):
+    """t(chosen) / t(best) - 1 with both configurations timed under the same
+    conditions: alternating bursts, median of each."""
+    qx, _ = mlk.quantize(torch.randn(p.n, p.c, p.h, p.w, device="cuda"), "bf16")
+    qw, _ = mlk.quantize(torch.randn(p.f, p.c, p.kh, p.kw, device="cuda"), "bf16")
+    ho, wo = mlk.conv_out_hw(p.h, p.w, p.kh, p.kw, (p.sh, p.sw), (p.ph, p.pw))
+    y = torch.zeros(p.n, p.f, ho, wo, device="cuda")
+    calls = [mlk.ConvCall(qx, qw, y, (p.sh, p.sw), (p.ph, p.pw), cfg=c) for c in (chosen, best)]
+    t = [[], []]
+    for _ in range(rounds):
+        for j in (0, 1):
+            t[j].append(_time_us(calls[j], iters))
+    return float(np.median(t[0]) / np.median(t[1]) - 1.0)
+
+
+@pytest.fixture(scope="module")
+def measured():
+    problems = _problems()
+    tables = costmodel.exhaustive_tables(problems, reps=5, warmup=2)
+    say("exhaustive tables:", [len(t) for t in tables])
+    return problems, tables
+
+
+def test_model_guided_search_live_on_held_out_layers(measured):
+    problems, tables = measured
+    # two layers held out in turn: the 64-channel 3x3 layer (largest space) and
+    # the 256-channel stride-1 layer
+    held = [costmodel.layer_key(problems[0]), costmodel.layer_key(problems[6])]
+    model_r, random_r = [], []
+    for key in held:
+        model, loss = costmodel.train_model(problems, tables, skip_key=key, seed=3)
+        say("held-out layer", key, "model trained on", model.sample_count(), "samples, loss", loss)
+        for p, t in zip(problems, tables):
+            if costmodel.layer_key(p) != key:
+                continue
+            t = np.asarray(t)
+            S = len(t)
+            best = float(t[t > 0].min())
+            _, rep, seen = mlk.tune(p, mlk.MLK_TUNE_MODEL, budget_frac=BUDGET, model=model, reps=5, warmup=2,
+                                    want_times=True)
+            assert rep.n_measured <= math.ceil(BUDGET * S - 1e-9), (rep.n_measured, S)
+            assert sum(1 for v in seen if v > 0) == rep.n_measured
+            regret = float(t[rep.best_index] / best - 1.0)
+            cfgs = mlk.configs(p)
+            paired = paired_regret(p, cfgs[rep.best_index], cfgs[int(np.argmin(np.where(t > 0, t, np.inf)))])
+            rand = []
+            for s in range(21):
+                _, rr, _ = mlk.tune(p, mlk.MLK_TUNE_RANDOM, budget_frac=BUDGET, seed=100 + s, table=list(t))
+                rand.append(float(t[rr.best_index] / best - 1.0))
+            say(f"  batch {p.n}: S={S} measured {rep.n_measured}, model regret {regret:.4f} on the table, "
+                f"{paired:.4f} re-timed beside the exhaustive best; random median {np.median(rand):.4f}")
+            model_r.append(regret)
+            random_r.append(float(np.median(rand)))
+            # within 5% of the exhaustive best, both timed under the same conditions
+            assert paired <= 0.05, (key, p.n, regret, paired)
+    # what the network gains over the method without it, at the same budget
+    assert np.mean(model_r) < np.mean(random_r), (model_r, random_r)
+
+
+def test_es_search_live(measured):
+    """The (1+1) evolution strategy measuring live on one layer at the same
+    budget, judged on that layer's exhaustive table."""
+    problems, tables = measured
+    p, t = problems[10], np.asarray(tables[10])   # 64 -> 64 at 56 x 56, batch 32
+    S = len(t)
+    best = float(t[t > 0].min())
+    cfgs = mlk.configs(p)
+    ibest = int(np.argmin(np.where(t > 0, t, np.inf)))
+    regrets, paired = [], []
+    for seed in range(3):
+        _, rep, _ = mlk.tune(p, mlk.MLK_TUNE_ES, budget_frac=BUDGET, seed=seed, reps=5, warmup=2)
+        assert rep.n_measured <= math.ceil(BUDGET * S - 1e-9)
+        regrets.append(float(t[rep.best_index] / best - 1.0))
+        paired.append(paired_regret(p, cfgs[rep.best_index], cfgs[ibest]))
+    say("ES live regrets on the table", regrets, "re-timed", paired, "S", S)
+    # stated bound: the median of three seeded runs within 10% of the exhaustive best
+    assert float(np.median(paired)) <= 0.10, (regrets, paired)
