@@ -54,12 +54,13 @@ def source_hash():
 
 
 def host_facts():
-    """CPU model and core count of this host, and the GPU clocks as rocm-smi
-    reports them right after the benchmark (null where a tool is missing)."""
-    import subprocess
+    """CPU model and core count of this host, and the GPU's engine / memory
+    clock levels as the driver lists them in sysfs (the current level marked
+    with *), read as files: no tool is started."""
+    import glob
 
     facts = {"nproc": os.cpu_count(), "affinity": len(os.sched_getaffinity(0)), "cpu_model": None,
-             "gpu_clocks": None}
+             "gpu_sclk_levels": None, "gpu_mclk_levels": None}
     try:
         with open("/proc/cpuinfo") as f:
             for line in f:
@@ -68,11 +69,14 @@ def host_facts():
                     break
     except OSError:
         pass
-    try:
-        r = subprocess.run(["rocm-smi", "--showclocks"], capture_output=True, text=True, timeout=20)
-        facts["gpu_clocks"] = [l.strip() for l in r.stdout.splitlines() if "clk" in l.lower() and "GPU[" in l]
-    except (OSError, subprocess.SubprocessError):
-        pass
+    for key, name in (("gpu_sclk_levels", "pp_dpm_sclk"), ("gpu_mclk_levels", "pp_dpm_mclk")):
+        for path in sorted(glob.glob(f"/sys/class/drm/card*/device/{name}")):
+            try:
+                with open(path) as f:
+                    facts[key] = [l.strip() for l in f if l.strip()]
+                break
+            except OSError:
+                continue
     return facts
 
 
@@ -108,6 +112,23 @@ def main():
         e1.record(stream)
         torch.cuda.synchronize()
         return e0.elapsed_time(e1) * 1e3 / iters
+
+    def graph_us(fn, calls=20, replays=10):
+        """Device time of one fn() call: `calls` calls captured in one graph,
+        replayed back to back (no host time per call)."""
+        side = torch.cuda.Stream()
+        side.wait_stream(stream)
+        with torch.cuda.stream(side):
+            fn()
+        stream.wait_stream(side)
+        torch.cuda.synchronize()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            for _ in range(calls):
+                fn()
+        us = time_us(lambda: g.replay(), replays, warm=2) / calls
+        del g
+        return us
 
     M = N = K = 4096
     flops = 2.0 * M * N * K
@@ -174,9 +195,10 @@ def main():
     mlk.matmul(qa, qb, C, cfg=best)
     outputs = {"bf16": C.cpu().numpy()}
 
-    # traffic from committed rocprofv3 counter runs, if they match these sources
-    traffic = None
-    tpath = os.path.join(ROOT, "profiles", "bf16_gemm_4096_traffic.txt")
+    # HBM traffic and MFMA utilisation of the timed tile from the committed
+    # rocprofv3 counter runs, if they were taken on these kernel sources
+    traffic, counters = None, None
+    tpath = os.path.join(ROOT, "profiles", "bf16_gemm_4096_counters.txt")
     if os.path.exists(tpath):
         # one JSON line per profiled tile configuration
         with open(tpath) as f:
@@ -184,7 +206,9 @@ def main():
         for line in lines:
             t = json.loads(line)
             if t.get("source_hash") == source_hash() and t.get("config") == list(best.as_tuple()):
-                traffic = round(t.get("bytes_per_launch"))
+                traffic = round(t["bytes_per_launch"])
+                counters = {"mfma_util_pct": t["mfma_util_pct"], "trace_avg_us": t["trace"]["avg_us"],
+                            "source": "profiles/bf16_gemm_4096_counters.txt"}
 
     result = {
         "metric": "GEMM/conv TFLOP/s and % MFMA roofline; tuned vs plain fp32 at stated rel err",
@@ -202,7 +226,8 @@ def main():
         "config": {"workload": "linalg.matmul M=N=K=4096, bf16 inputs, fp32 accumulate into C (C += A B), tuned tile",
                    "tile": list(best.as_tuple()), "global_batch": 1, "parallelism": "none (1 GPU)"},
         "roofline": {"bound": "mfma", "achieved": round(achieved, 2), "peak": PEAK["bf16"],
-                     "unit": "TFLOP/s", "frac": round(achieved / PEAK["bf16"], 4), "traffic": traffic},
+                     "unit": "TFLOP/s", "frac": round(achieved / PEAK["bf16"], 4), "traffic": traffic,
+                     "counters": counters},
         "launch_us": launch_pcts,
     }
 
@@ -269,8 +294,12 @@ def main():
         c8 = torch.zeros(1024, 1024, dtype=torch.int32, device="cuda")
         pi = mlk.matmul_problem(1024, 1024, 1024, L.MLK_I8, L.MLK_I32)
         bi, _, _ = mlk.tune(pi, mlk.MLK_TUNE_EXHAUSTIVE, reps=10, warmup=2)
-        us = time_us(lambda: mlk.matmul(a8, b8_, c8, cfg=bi), 50)
+        us_host = time_us(lambda: mlk.matmul(a8, b8_, c8, cfg=bi), 50)
+        us = graph_us(lambda: mlk.matmul(a8, b8_, c8, cfg=bi), 50)
         rows_out["matmul_i8_1024"] = {"us": round(us, 2), "TOPS": round(2 * 1024 ** 3 / us / 1e6, 1),
+                                      # A and B (1 MiB each), C read and written (4 MiB each)
+                                      "frac_hbm": round(1024 * 1024 * (1 + 1 + 4 + 4) / us / 1e3 / PEAK["hbm_gbs"], 3),
+                                      "timing": "graph of 50 launches", "per_call_us": round(us_host, 2),
                                       "tile": list(bi.as_tuple())}
         # fp32 conv 1x64x56x56, 64 3x3 filters, s1 p1
         cs = CFG_CONV_F32
@@ -279,8 +308,10 @@ def main():
         y = torch.zeros(1, 64, 56, 56, device="cuda")
         pc = mlk.conv_problem(1, 64, 56, 56, 64, 3, 3, 1, 1, L.MLK_F32, L.MLK_F32)
         bc, _, _ = mlk.tune(pc, mlk.MLK_TUNE_EXHAUSTIVE, reps=10, warmup=2)
-        us = time_us(lambda: mlk.conv2d_nchw_fchw(xd, wd, y, (1, 1), (1, 1), cfg=bc), 50)
+        us_host = time_us(lambda: mlk.conv2d_nchw_fchw(xd, wd, y, (1, 1), (1, 1), cfg=bc), 50)
+        us = graph_us(mlk.ConvCall(xd, wd, y, (1, 1), (1, 1), cfg=bc), 50)
         rows_out["conv_f32_56x56x64"] = {"us": round(us, 2), "TFLOP/s": round(cs.flops() / us / 1e6, 2),
+                                         "timing": "graph of 50 bound calls", "per_call_us": round(us_host, 2),
                                          "tile": list(bc.as_tuple())}
         # the paper's measured workload: one 1280 x 1280 image, 3 filters 3x3,
         # valid, fp32 (y += conv): HBM-bound, reported against 8 TB/s with the
@@ -326,16 +357,33 @@ def main():
         # descriptors bound once (mlk.BatchedCall): each timed call is one library
         # call -- with graph=True one replay of the captured launches
         us_pg = time_us(mlk.BatchedCall(probs, cfg=bb, persistent=True, graph=True), 20)
-        # the same GEMMs as 256 separate launches (register-loaded tile: any alignment)
-        bl = mlk.TileConfig(128, 128, 64, 2, 2, 1, 1, 0, 1, 0)
-        us_loop = time_us(mlk.BatchedCall(probs, cfg=bl), 3)
-        us_g = time_us(mlk.BatchedCall(probs, cfg=bl, graph=True), 3)
+        # each GEMM tuned alone as a matmul (exhaustive over its own legal space,
+        # split K included): the per-GEMM comparator, 256 launches from the host
+        # and the same launches replayed from one graph
+        t0 = time.time()
+        per = [mlk.tune(mlk.matmul_problem(m, nn, k, L.MLK_BF16, L.MLK_F32), mlk.MLK_TUNE_EXHAUSTIVE, reps=2,
+                        warmup=1)[0] for m, nn, k in shapes]
+        tune_s = time.time() - t0
+        us_loop = time_us(mlk.BatchedCall(probs, cfg=per), 3)
+        us_g = time_us(mlk.BatchedCall(probs, cfg=per, graph=True), 5)
+        # persistent launches with per-GEMM tiles: each GEMM's own tuned tile where
+        # that kernel has a persistent form (else the batch's tuned tile), the
+        # GEMMs grouped by kernel, one persistent launch per group
+        pers = []
+        for c, (m, nn, k) in zip(per, shapes):
+            cands = {x.as_tuple() for x in mlk.configs(mlk.batched_problem([(m, nn, k)], L.MLK_BF16, L.MLK_F32))}
+            c1 = mlk.TileConfig(*(list(c.as_tuple())[:5] + [1, 1, 0] + list(c.as_tuple())[8:]))
+            pers.append(c1 if c1.as_tuple() in cands else bb)
+        us_pp = time_us(mlk.BatchedCall(probs, cfg=pers, persistent=True, graph=True), 20)
+        kernels = len({(c.bm, c.bn, c.bk, c.wm, c.wn, c.stages) for c in pers})
         rows_out["batched_256_bf16"] = {"gflop": round(bflops / 1e9, 2), "tile": list(bb.as_tuple()),
                                         "persistent_graph_us": round(us_pg, 1),
                                         "TFLOP/s": round(bflops / us_pg / 1e6, 1),
-                                        "per_gemm_tile": list(bl.as_tuple()),
-                                        "per_gemm_launches_us": round(us_loop, 1),
-                                        "graph_of_launches_us": round(us_g, 1)}
+                                        "per_gemm_tiles_persistent_graph_us": round(us_pp, 1),
+                                        "per_gemm_tiles_kernel_groups": kernels,
+                                        "per_gemm_tuned_launches_us": round(us_loop, 1),
+                                        "per_gemm_tuned_graph_of_launches_us": round(us_g, 1),
+                                        "per_gemm_tuning_s": round(tune_s, 1)}
         # ResNet-18 conv stacks (batch 1 and 32, bf16): exhaustive tile search per
         # layer shape, the stack timed with each layer's best tile, and the learned
         # cost model judged leave-one-problem-out against those exhaustive tables.
@@ -351,25 +399,38 @@ def main():
         log(f"exhaustive tables for {len(problems)} conv problems in {time.time() - t0:.1f} s")
         for batch in (1, 32):
             eager_us, stack_flops = 0.0, 0.0
+            stack_calls, layer_tiles = [], []
             for (shape, count), p, t in zip(shapes_all, problems, tables):
                 if shape.N != batch:
                     continue
-                cfg = mlk.configs(p)[int(np.argmin(np.where(t > 0, t, np.inf)))]
                 xs = torch.randn(shape.N, shape.C, shape.H, shape.W, device="cuda")
                 ws = torch.randn(shape.F, shape.C, shape.KH, shape.KW, device="cuda")
                 qx, _ = mlk.quantize(xs, "bf16")
                 qw, _ = mlk.quantize(ws, "bf16")
                 ho, wo = shape.out_hw()
                 ys = torch.zeros(shape.N, shape.F, ho, wo, device="cuda")
-                # the layer bound once (mlk.ConvCall): each timed call is one library call
-                call = mlk.ConvCall(qx, qw, ys, (shape.stride,) * 2, (shape.pad,) * 2, cfg=cfg, stream=stream)
+                # the layer bound once (mlk.ConvCall: a plan whose filter is transposed
+                # once): the exhaustive table's six fastest re-timed as bound calls, in
+                # graphs of 10 calls (no host time), and the fastest kept
+                cfgs = mlk.configs(p)
+                order = [i for _, i in sorted((v, i) for i, v in enumerate(t) if v > 0)[:6]]
+                cands = [mlk.ConvCall(qx, qw, ys, (shape.stride,) * 2, (shape.pad,) * 2, cfg=cfgs[i])
+                         for i in order]
+                us_c = [graph_us(c, 10) for c in cands]
+                k = int(np.argmin(us_c))
+                call = cands[k]
+                layer_tiles.append(list(cfgs[order[k]].as_tuple()))
                 eager_us += time_us(call, 20) * count
                 stack_flops += shape.flops() * count
-            stack_us = eager_us
+                stack_calls += [call] * count
+            # the whole stack (every layer, in order) as one captured graph
+            stack_us = graph_us(lambda: [c() for c in stack_calls], 1, replays=20)
             rows_out[f"resnet18_stack_b{batch}_bf16"] = {"us": round(stack_us, 1),
                                                          "TFLOP/s": round(stack_flops / stack_us / 1e6, 2),
                                                          "gflop": round(stack_flops / 1e9, 2),
-                                                         "timing": "sum over layers of count x per-call time (mlk.ConvCall)"}
+                                                         "timing": "one replay of the captured stack of bound layers",
+                                                         "eager_sum_us": round(eager_us, 1),
+                                                         "layer_tiles": layer_tiles}
         t0 = time.time()
         ev = costmodel.leave_one_out(problems, tables, budget=0.2)
         ev["summary"]["seconds"] = round(time.time() - t0, 1)
@@ -383,10 +444,23 @@ def main():
             for p, t in zip(problems, tables):
                 if costmodel.layer_key(p) != key:
                     continue
-                _, rep, _ = mlk.tune(p, mlk.MLK_TUNE_MODEL, budget_frac=0.2, model=model, reps=3, warmup=1)
+                _, rep, _ = mlk.tune(p, mlk.MLK_TUNE_MODEL, budget_frac=0.2, model=model, reps=5, warmup=2)
+                # the chosen and the exhaustive-best configuration re-timed side by
+                # side (alternating graphs of bound calls), so that both times come
+                # from the same conditions
+                cf = mlk.configs(p)
+                qx, _ = mlk.quantize(torch.randn(p.n, p.c, p.h, p.w, device="cuda"), "bf16")
+                qw, _ = mlk.quantize(torch.randn(p.f, p.c, p.kh, p.kw, device="cuda"), "bf16")
+                ho_, wo_ = mlk.conv_out_hw(p.h, p.w, p.kh, p.kw, (p.sh, p.sw), (p.ph, p.pw))
+                yq = torch.zeros(p.n, p.f, ho_, wo_, device="cuda")
+                pair = [mlk.ConvCall(qx, qw, yq, (p.sh, p.sw), (p.ph, p.pw), cfg=cf[i])
+                        for i in (rep.best_index, int(np.argmin(np.where(t > 0, t, np.inf))))]
+                tt = [[graph_us(c, 10) for c in pair] for _ in range(5)]
                 live.append({"layer": f"{p.c}->{p.f}@{p.h} k{p.kh} s{p.sh} b{p.n}", "configs": len(t),
                              "measured": rep.n_measured,
-                             "regret": round(float(t[rep.best_index] / t[t > 0].min() - 1.0), 4)})
+                             "regret_table": round(float(t[rep.best_index] / t[t > 0].min() - 1.0), 4),
+                             "regret_retimed": round(float(np.median([a for a, _ in tt]) /
+                                                           np.median([b for _, b in tt]) - 1.0), 4)})
         rows_out["cost_model_live"] = live
         # the small case: fp32 matmul 128^3 (uniform[-1, 1], C = 0), latency-bound:
         # single launches between their own events (median of 200), and 100

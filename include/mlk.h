@@ -291,18 +291,32 @@ typedef struct {
  * Many independent matmuls of different shapes (the extension that batches
  * uneven GEMMs into one launch).  descs: HOST array of `count` descriptors
  * (device A/B/C pointers inside).  Supported (in, out): (MLK_BF16, MLK_F32),
- * (MLK_F32, MLK_F32).  cfg: one tile configuration for every GEMM of the
- * batch (NULL = choose); its split_k is ignored in persistent mode, where
- * the library splits K per GEMM from its own cost estimate.
- * flags: 0 = one launch per GEMM; MLK_BATCH_PERSISTENT = one launch whose
- * workgroups walk a precomputed, load-balanced list of (GEMM, tile) tasks;
+ * (MLK_F32, MLK_F32).
+ * cfgs / ncfgs: the tile configurations (HOST array).
+ *   ncfgs = 0 (cfgs ignored): one configuration for the whole batch, its
+ *     tuned choice (mlk_tune on the MLK_OP_BATCHED problem) else a heuristic;
+ *   ncfgs = 1: cfgs[0] for every GEMM;
+ *   ncfgs = count: cfgs[i] for GEMM i; a zeroed entry leaves GEMM i to choose:
+ *     per-GEMM launches take its own tuned matmul configuration (else the
+ *     heuristic for its shape), persistent launches the batch's choice.
+ * Other ncfgs values return MLK_ERR_ARG.
+ * flags: 0 = one launch per GEMM, each with its configuration (split_k
+ * honoured); MLK_BATCH_PERSISTENT = one persistent launch per kernel used by
+ * the batch (GEMMs whose configurations share a kernel form one group; the
+ * groups run one after another), whose workgroups walk a precomputed,
+ * load-balanced list of (GEMM, tile) tasks, split_k ignored;
  * MLK_BATCH_GRAPH = replay a hipGraph captured on the first call with the
- * same descriptors, configuration and flags (the graph bakes in the device
- * pointers, so a changed pointer is a new batch).
- * Results equal per-GEMM mlk_matmul calls with the same configuration.
+ * same descriptors, configurations and flags (the graph bakes in the device
+ * pointers, so a changed pointer is a new batch; a graph of per-GEMM launches
+ * takes its packed operand copies from a workspace the cached batch owns,
+ * not from scratch memory).  Persistent task lists, workspaces and graphs are
+ * cached per batch, at most 16 (the least recently used is freed first, after
+ * a device synchronisation), and freed by mlk_release().
+ * Results equal per-GEMM mlk_matmul calls with the same configurations
+ * (split_k 1).
  */
 mlk_status mlk_batched_matmul(mlk_dtype in, mlk_dtype out, int64_t count,
-                              const mlk_gemm_desc* descs, const mlk_tile_config* cfg,
+                              const mlk_gemm_desc* descs, const mlk_tile_config* cfgs, int64_t ncfgs,
                               int accumulate, uint32_t flags, void* stream);
 
 /*

@@ -267,8 +267,10 @@ def quantize(x: torch.Tensor, fmt: str, q=None, scale=None, stream=None):
 class BatchedCall:
     """A batch of GEMMs bound once to its tensors.  The descriptor array is built
     here, once; each call is then a single library call (with `graph`, a replay
-    of the captured persistent launch), so a serving loop pays no per-GEMM host
-    work.  The tensors are kept alive by the object; their storage must not move
+    of the captured launches), so a serving loop pays no per-GEMM host work.
+    cfg: None (the batch's tuned choice, else the heuristic), one TileConfig for
+    every GEMM, or a list of one per GEMM (None entries: that GEMM chooses).
+    The tensors are kept alive by the object; their storage must not move
     between calls."""
 
     def __init__(self, problems, accumulate: bool = True, cfg=None, persistent: bool = False,
@@ -291,18 +293,29 @@ class BatchedCall:
                                       _on_device(B).data_ptr(), _row_major_ld(B), _on_device(C).data_ptr(),
                                       _row_major_ld(C))
         self._din, self._dout = _dt(A0), _dt(C0)
-        self._cfg = None if cfg is None else (cfg if isinstance(cfg, TileConfig) else TileConfig(*cfg))
+        if cfg is None:
+            self._cfgs, self._ncfgs = None, 0
+        elif isinstance(cfg, list):
+            _need(len(cfg) == len(self._problems), 9,
+                  f"batched: {len(cfg)} configurations for {len(self._problems)} GEMMs")
+            self._cfgs = (TileConfig * len(cfg))(*[TileConfig() if c is None else
+                                                   (c if isinstance(c, TileConfig) else TileConfig(*c)) for c in cfg])
+            self._ncfgs = len(cfg)
+        else:
+            self._cfgs = (TileConfig * 1)(cfg if isinstance(cfg, TileConfig) else TileConfig(*cfg))
+            self._ncfgs = 1
         self._acc = int(bool(accumulate))
         self._flags = (MLK_BATCH_PERSISTENT if persistent else 0) | (MLK_BATCH_GRAPH if graph else 0)
 
     def __call__(self, stream=None):
         L.check(L.lib().mlk_batched_matmul(self._din, self._dout, len(self._problems), self._descs,
-                                           _cfg(self._cfg), self._acc, self._flags, _stream(stream)))
+                                           self._cfgs, self._ncfgs, self._acc, self._flags, _stream(stream)))
 
 
 def batched_matmul(problems, accumulate: bool = True, cfg=None, persistent: bool = False,
                    graph: bool = False, stream=None):
-    """problems: list of (A, B, C) CUDA tensors (same dtypes across the list)."""
+    """problems: list of (A, B, C) CUDA tensors (same dtypes across the list).
+    cfg: None, one TileConfig for all, or a list with one per GEMM."""
     BatchedCall(problems, accumulate, cfg, persistent, graph)(stream)
 
 

@@ -92,7 +92,7 @@ SIGNATURES = {
     "mlk_conv2d_plan_config": (_st, [_vp, _cfgp]),
     "mlk_conv2d_plan_destroy": (None, [_vp]),
     "mlk_quantize": (_st, [_int, _i64, _vp, _vp, _vp, _vp]),
-    "mlk_batched_matmul": (_st, [_int, _int, _i64, ctypes.POINTER(GemmDesc), _cfgp, _int, _u32,
+    "mlk_batched_matmul": (_st, [_int, _int, _i64, ctypes.POINTER(GemmDesc), _cfgp, _i64, _int, _u32,
                                  _vp]),
     "mlk_err_stats": (_st, [_int, _i64, _vp, _vp, _vp, _vp, _vp]),
     "mlk_tune": (_st, [_probp, ctypes.POINTER(TuneOpts), _cfgp, ctypes.POINTER(TuneReport)]),

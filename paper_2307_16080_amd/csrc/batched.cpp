@@ -12,10 +12,13 @@
 // same code as a plain launch of its tile shape with split_k = 1, so results
 // equal per-GEMM launches of that shape bit for bit.
 //
+// Each GEMM may have its own tile configuration: in persistent mode the GEMMs
+// are grouped by kernel and each group is one persistent launch.
+//
 // Graph mode: the launch(es) are captured once into a hipGraph on a private
 // stream and replayed on the caller's stream; the graph and its device task
-// list are cached per (descriptors, configuration, flags) and freed by
-// mlk_release().
+// lists are cached per (descriptors, configurations, flags), at most 16
+// batches (least recently used freed first), and freed by mlk_release().
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -58,20 +61,56 @@ void free_plan(Plan& p) {
     p = Plan();
 }
 
+// The GEMMs of a batch whose configurations share one compiled kernel: in
+// persistent mode each group is one persistent launch over the whole device,
+// the groups launched one after another on the stream.
+struct Group {
+    const KernelEntry* e = nullptr;
+    mlk_tile_config c{};
+    std::vector<int64_t> idx;  // the group's GEMMs (indices into the batch)
+    Plan plan;
+};
+
+struct BatchPlan {
+    std::vector<Group> groups;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    void* ws = nullptr;  // graph of per-GEMM launches: their packing workspace (one GEMM at a time)
+    size_t ws_bytes = 0;
+};
+
+void free_batch(BatchPlan& b) {
+    if (b.exec) (void)hipGraphExecDestroy(b.exec);
+    if (b.graph) (void)hipGraphDestroy(b.graph);
+    for (Group& g : b.groups) free_plan(g.plan);
+    if (b.ws) (void)hipFree(b.ws);
+    b = BatchPlan();
+}
+
 std::mutex g_mu;
-std::map<std::string, Plan> g_plans;
+std::map<std::string, BatchPlan> g_plans;
 std::map<int, hipStream_t> g_capture_streams;
+// Cached batches (each holds device task lists and packed operand copies) are
+// kept up to this many; the least recently used one is freed beyond it.
+constexpr size_t kMaxCachedBatches = 16;
+std::vector<std::string> g_lru;  // keys, least recently used first
+
+void touch(const std::string& key) {
+    auto it = std::find(g_lru.begin(), g_lru.end(), key);
+    if (it != g_lru.end()) g_lru.erase(it);
+    g_lru.push_back(key);
+}
 
 int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
-std::string plan_key(int dt, int64_t count, const mlk_gemm_desc* d, const mlk_tile_config& c,
+std::string plan_key(int dt, int64_t count, const mlk_gemm_desc* d, const std::vector<mlk_tile_config>& cf,
                      int accumulate, uint32_t flags, int device) {
     std::string k;
     k.append((const char*)&dt, sizeof dt);
     k.append((const char*)&accumulate, sizeof accumulate);
     k.append((const char*)&flags, sizeof flags);
     k.append((const char*)&device, sizeof device);
-    k.append((const char*)&c, sizeof c);
+    k.append((const char*)cf.data(), sizeof(mlk_tile_config) * cf.size());
     k.append((const char*)d, sizeof(mlk_gemm_desc) * (size_t)count);
     return k;
 }
@@ -292,18 +331,22 @@ mlk_status build_plan(int dt, int64_t count, const mlk_gemm_desc* d, const Kerne
     return MLK_OK;
 }
 
-mlk_status launch_batch(int dt, int64_t count, const mlk_gemm_desc* d, const KernelEntry* e,
-                        const mlk_tile_config& c, int accumulate, uint32_t flags, Plan* plan,
-                        hipStream_t st) {
-    if (flags & MLK_BATCH_PERSISTENT) {
-        if (plan->nblk == 0) return MLK_OK;
-        hipError_t err = launch_pack(plan->jobs, plan->seg_start, plan->njobs, plan->pack_segs, plan->esize, st);
-        if (err != hipSuccess) return hip_fail(err, "operand packing");
-        err = e->persist(plan->gemms, plan->tasks, plan->bounds, plan->nblk, st);
-        if (err != hipSuccess) return hip_fail(err, "persistent launch");
-        return MLK_OK;
-    }
-    // one launch per GEMM, same code path as mlk_matmul
+// One launch per GEMM, each with its own configuration, on the mlk_matmul path.
+Shape gemm_shape(int dt, const mlk_gemm_desc& d, int accumulate) {
+    Shape s;
+    s.dt = dt;
+    s.conv = 0;
+    s.M = d.M;
+    s.N = d.N;
+    s.K = d.K;
+    s.accumulate = accumulate;
+    return s;
+}
+
+// ws: a workspace for the GEMMs' packed operand copies, used by one GEMM at a
+// time (the launches are ordered on the stream); null = the library's scratch
+mlk_status launch_each(int dt, int64_t count, const mlk_gemm_desc* d, const std::vector<mlk_tile_config>& cf,
+                       int accumulate, hipStream_t st, void* ws = nullptr, size_t ws_bytes = 0) {
     for (int64_t i = 0; i < count; ++i) {
         Shape s;
         s.dt = dt;
@@ -312,12 +355,25 @@ mlk_status launch_batch(int dt, int64_t count, const mlk_gemm_desc* d, const Ker
         s.N = d[i].N;
         s.K = d[i].K;
         s.accumulate = accumulate;
-        mlk_tile_config ci = c;
-        const int64_t stages = cdiv(std::max<int64_t>(s.K, 1), c.bk);
+        mlk_tile_config ci = cf[(size_t)i];
+        const int64_t stages = cdiv(std::max<int64_t>(s.K, 1), ci.bk);
         if (ci.split_k > stages) ci.split_k = 1;
         mlk_status r = launch_dense(s, d[i].A, d[i].lda, d[i].B, d[i].ldb, d[i].C, d[i].ldc,
-                                    nullptr, nullptr, ci, st);
+                                    nullptr, nullptr, ci, st, nullptr, ws, ws_bytes);
         if (r != MLK_OK) return r;
+    }
+    return MLK_OK;
+}
+
+// Every group's packing copy and persistent launch, in group order.
+mlk_status launch_groups(BatchPlan& b, hipStream_t st) {
+    for (Group& g : b.groups) {
+        Plan& p = g.plan;
+        if (p.nblk == 0) continue;
+        hipError_t err = launch_pack(p.jobs, p.seg_start, p.njobs, p.pack_segs, p.esize, st);
+        if (err != hipSuccess) return hip_fail(err, "operand packing");
+        err = g.e->persist(p.gemms, p.tasks, p.bounds, p.nblk, st);
+        if (err != hipSuccess) return hip_fail(err, "persistent launch");
     }
     return MLK_OK;
 }
@@ -330,9 +386,9 @@ using namespace mlk;
 
 extern "C" {
 
-mlk_status mlk_batched_matmul(mlk_dtype in, mlk_dtype out, int64_t count,
-                              const mlk_gemm_desc* descs, const mlk_tile_config* cfg,
-                              int accumulate, uint32_t flags, void* stream) {
+mlk_status mlk_batched_matmul(mlk_dtype in, mlk_dtype out, int64_t count, const mlk_gemm_desc* descs,
+                              const mlk_tile_config* cfgs, int64_t ncfgs, int accumulate, uint32_t flags,
+                              void* stream) {
     clear_error();
     if (flags & ~(MLK_BATCH_PERSISTENT | MLK_BATCH_GRAPH))
         return fail(MLK_ERR_ARG, "batched: unknown flag bits 0x%x", flags);
@@ -347,6 +403,10 @@ mlk_status mlk_batched_matmul(mlk_dtype in, mlk_dtype out, int64_t count,
     Shape s;
     mlk_status st = shape_of_problem(&p, &s);
     if (st != MLK_OK) return st;
+    if (ncfgs != 0 && ncfgs != 1 && ncfgs != count)
+        return fail(MLK_ERR_ARG, "batched: ncfgs must be 0, 1 or count (%lld), got %lld", (long long)count,
+                    (long long)ncfgs);
+    if (ncfgs > 0 && !cfgs) return fail(MLK_ERR_NULL, "batched: cfgs is NULL with ncfgs %lld", (long long)ncfgs);
     const int es = s.dt == DT_F32 ? 4 : s.dt == DT_BF16 ? 2 : 1;
     for (int64_t i = 0; i < count; ++i) {
         const mlk_gemm_desc& d = descs[i];
@@ -362,45 +422,112 @@ mlk_status mlk_batched_matmul(mlk_dtype in, mlk_dtype out, int64_t count,
         if (d.K > 0 && ((c0 < a1 && a0 < c1) || (c0 < b1 && b0 < c1)))
             return fail(MLK_ERR_LAYOUT, "batched: C overlaps A or B in desc %lld", (long long)i);
     }
-    mlk_tile_config c;
-    if (cfg && !(cfg->bm == 0 && cfg->bn == 0)) {
-        c = *cfg;
+    const bool persistent = (flags & MLK_BATCH_PERSISTENT) != 0;
+    const bool graph = (flags & MLK_BATCH_GRAPH) != 0;
+    auto zero = [](const mlk_tile_config& c) { return c.bm == 0 && c.bn == 0; };
+    auto norm = [](mlk_tile_config c) {
         if (c.group_m == 0) c.group_m = 1;
         if (c.split_k == 0) c.split_k = 1;
-        st = check_config(s, MLK_OP_BATCHED, c);
-        if (st != MLK_OK) return st;
-    } else if (!lookup_default(problem_key(&p), &c)) {
-        c = heuristic_config(s, MLK_OP_BATCHED);
+        return c;
+    };
+    // the batch's own choice: its tuned configuration, else the heuristic
+    mlk_tile_config batch_c;
+    if (!lookup_default(problem_key(&p), &batch_c)) batch_c = heuristic_config(s, MLK_OP_BATCHED);
+    // one configuration per GEMM
+    std::vector<mlk_tile_config> cf((size_t)count, batch_c);
+    if (ncfgs == 1 && !zero(cfgs[0])) {
+        const mlk_tile_config c = norm(cfgs[0]);
+        if ((st = check_config(s, MLK_OP_BATCHED, c)) != MLK_OK) return st;
+        std::fill(cf.begin(), cf.end(), c);
+    } else if (ncfgs == count) {
+        for (int64_t i = 0; i < count; ++i) {
+            mlk_problem q;
+            memset(&q, 0, sizeof q);
+            q.op = MLK_OP_MATMUL;
+            q.in = in;
+            q.out = out;
+            q.accumulate = p.accumulate;
+            q.M = descs[i].M;
+            q.N = descs[i].N;
+            q.K = descs[i].K;
+            Shape si;
+            if ((st = shape_of_problem(&q, &si)) != MLK_OK) return st;
+            if (zero(cfgs[i])) {
+                // a GEMM left to choose: its own tuned matmul configuration when the
+                // launch mode can run it, else the batch's choice
+                mlk_tile_config c;
+                if (!persistent && lookup_default(problem_key(&q), &c)) cf[(size_t)i] = c;
+                else if (!persistent) cf[(size_t)i] = heuristic_config(si, MLK_OP_MATMUL);
+                continue;
+            }
+            const mlk_tile_config c = norm(cfgs[i]);
+            if ((st = check_config(si, persistent ? MLK_OP_BATCHED : MLK_OP_MATMUL, c)) != MLK_OK)
+                return fail(st, "batched: configuration of desc %lld: %s", (long long)i, mlk_last_error());
+            cf[(size_t)i] = c;
+        }
     }
-    const KernelEntry* e = find_kernel(s.dt, 0, c);
-    if (!e) return fail(MLK_ERR_CONFIG, "batched: no kernel for configuration");
-    if ((flags & MLK_BATCH_PERSISTENT) && !e->persist)
-        return fail(MLK_ERR_CONFIG, "batched: tile %dx%dx%d has no persistent variant", c.bm, c.bn, c.bk);
-    // the direct-layout tiles address their output tile with 32-bit offsets
-    for (int64_t i = 0; e->stages >= 1 && i < count; ++i)
-        if ((int64_t)(e->bm - 1) * descs[i].ldc + e->bn >= ((int64_t)1 << 31))
+    // kernels, and the direct-layout tiles' 32-bit output offsets
+    for (int64_t i = 0; i < count; ++i) {
+        const KernelEntry* e = find_kernel(s.dt, 0, cf[(size_t)i]);
+        if (!e) return fail(MLK_ERR_CONFIG, "batched: no kernel for the configuration of desc %lld", (long long)i);
+        if (persistent && !e->persist)
+            return fail(MLK_ERR_CONFIG, "batched: tile %dx%dx%d (desc %lld) has no persistent variant", cf[i].bm,
+                        cf[i].bn, cf[i].bk, (long long)i);
+        if (e->stages >= 1 && (int64_t)(e->bm - 1) * descs[i].ldc + e->bn >= ((int64_t)1 << 31))
             return fail(MLK_ERR_CONFIG, "batched: ldc of desc %lld too large for a %d-row direct-layout tile",
                         (long long)i, e->bm);
+    }
     hipStream_t user = (hipStream_t)stream;
     int dev = 0;
     hipError_t herr = hipGetDevice(&dev);
     if (herr != hipSuccess) return hip_fail(herr, "hipGetDevice");
 
-    const bool need_plan = (flags & MLK_BATCH_PERSISTENT) != 0;
-    const bool graph = (flags & MLK_BATCH_GRAPH) != 0;
-    if (!need_plan && !graph) {
-        Plan none;
-        return launch_batch(s.dt, count, descs, e, c, p.accumulate, flags, &none, user);
-    }
+    if (!persistent && !graph) return launch_each(s.dt, count, descs, cf, p.accumulate, user);
     std::lock_guard<std::mutex> g(g_mu);
-    const std::string key = plan_key(s.dt, count, descs, c, p.accumulate, flags, dev);
+    const std::string key = plan_key(s.dt, count, descs, cf, p.accumulate, flags, dev);
     auto it = g_plans.find(key);
     if (it == g_plans.end()) {
-        Plan plan;
-        plan.device = dev;
-        if (need_plan) {
-            st = build_plan(s.dt, count, descs, e, c, p.accumulate, &plan);
-            if (st != MLK_OK) return st;
+        BatchPlan bp;
+        if (persistent) {
+            // group the GEMMs by kernel, in order of first appearance
+            for (int64_t i = 0; i < count; ++i) {
+                const KernelEntry* e = find_kernel(s.dt, 0, cf[(size_t)i]);
+                Group* gr = nullptr;
+                for (Group& x : bp.groups)
+                    if (x.e == e) gr = &x;
+                if (!gr) {
+                    bp.groups.push_back(Group());
+                    gr = &bp.groups.back();
+                    gr->e = e;
+                    gr->c = cf[(size_t)i];
+                }
+                gr->idx.push_back(i);
+            }
+            for (Group& gr : bp.groups) {
+                std::vector<mlk_gemm_desc> gd;
+                for (int64_t i : gr.idx) gd.push_back(descs[i]);
+                gr.plan.device = dev;
+                if ((st = build_plan(s.dt, (int64_t)gd.size(), gd.data(), gr.e, gr.c, p.accumulate, &gr.plan)) !=
+                    MLK_OK) {
+                    free_batch(bp);
+                    return st;
+                }
+            }
+        }
+        if (graph && !persistent) {
+            // per-GEMM launches recorded into a graph take no scratch memory: the
+            // batch owns one workspace for the largest packing any GEMM needs
+            int64_t need = 0;
+            for (int64_t i = 0; i < count; ++i)
+                need = std::max(need, dense_workspace_bytes(gemm_shape(s.dt, descs[i], p.accumulate), descs[i].A,
+                                                            descs[i].lda, descs[i].B, descs[i].ldb, cf[(size_t)i]));
+            if (need > 0) {
+                if ((herr = hipMalloc(&bp.ws, (size_t)need)) != hipSuccess) {
+                    free_batch(bp);
+                    return hip_fail(herr, "batched graph workspace");
+                }
+                bp.ws_bytes = (size_t)need;
+            }
         }
         if (graph) {
             hipStream_t cap = nullptr;
@@ -408,7 +535,7 @@ mlk_status mlk_batched_matmul(mlk_dtype in, mlk_dtype out, int64_t count,
             if (cs == g_capture_streams.end()) {
                 herr = hipStreamCreateWithFlags(&cap, hipStreamNonBlocking);
                 if (herr != hipSuccess) {
-                    free_plan(plan);
+                    free_batch(bp);
                     return hip_fail(herr, "capture stream");
                 }
                 g_capture_streams[dev] = cap;
@@ -417,43 +544,57 @@ mlk_status mlk_batched_matmul(mlk_dtype in, mlk_dtype out, int64_t count,
             }
             herr = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
             if (herr != hipSuccess) {
-                free_plan(plan);
+                free_batch(bp);
                 return hip_fail(herr, "hipStreamBeginCapture");
             }
-            st = launch_batch(s.dt, count, descs, e, c, p.accumulate, flags, &plan, cap);
+            st = persistent ? launch_groups(bp, cap)
+                            : launch_each(s.dt, count, descs, cf, p.accumulate, cap, bp.ws, bp.ws_bytes);
             hipGraph_t gr = nullptr;
             hipError_t endc = hipStreamEndCapture(cap, &gr);
-            plan.graph = gr;
+            bp.graph = gr;
             if (st != MLK_OK) {
-                free_plan(plan);
+                free_batch(bp);
                 return st;
             }
             if (endc != hipSuccess) {
-                free_plan(plan);
+                free_batch(bp);
                 return hip_fail(endc, "hipStreamEndCapture");
             }
-            herr = hipGraphInstantiate(&plan.exec, gr, nullptr, nullptr, 0);
+            herr = hipGraphInstantiate(&bp.exec, gr, nullptr, nullptr, 0);
             if (herr != hipSuccess) {
-                free_plan(plan);
+                free_batch(bp);
                 return hip_fail(herr, "hipGraphInstantiate");
             }
         }
-        it = g_plans.emplace(key, plan).first;
+        // keep at most kMaxCachedBatches: free the least recently used (after
+        // the device has finished with it)
+        if (g_plans.size() >= kMaxCachedBatches && !g_lru.empty()) {
+            auto old = g_plans.find(g_lru.front());
+            if (old != g_plans.end()) {
+                (void)hipDeviceSynchronize();
+                free_batch(old->second);
+                g_plans.erase(old);
+            }
+            g_lru.erase(g_lru.begin());
+        }
+        it = g_plans.emplace(key, std::move(bp)).first;
     }
-    Plan& plan = it->second;
+    touch(key);
+    BatchPlan& bp = it->second;
     if (graph) {
-        herr = hipGraphLaunch(plan.exec, user);
+        herr = hipGraphLaunch(bp.exec, user);
         if (herr != hipSuccess) return hip_fail(herr, "hipGraphLaunch");
         return MLK_OK;
     }
-    return launch_batch(s.dt, count, descs, e, c, p.accumulate, flags, &plan, user);
+    return launch_groups(bp, user);
 }
 
 void mlk_release(void) {
     std::lock_guard<std::mutex> g(g_mu);
     (void)hipDeviceSynchronize();
-    for (auto& kv : g_plans) free_plan(kv.second);
+    for (auto& kv : g_plans) free_batch(kv.second);
     g_plans.clear();
+    g_lru.clear();
     for (auto& kv : g_capture_streams) (void)hipStreamDestroy(kv.second);
     g_capture_streams.clear();
     release_scratch();

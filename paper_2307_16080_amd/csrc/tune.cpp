@@ -203,7 +203,7 @@ mlk_status run_once(const mlk_problem* p, const Shape& s, const Scratch& sc,
                            ho, wo, sc.B, sc.A, sc.C, c, st);
     }
     return mlk_batched_matmul((mlk_dtype)p->in, (mlk_dtype)p->out, (int64_t)sc.descs.size(),
-                              sc.descs.data(), &c, p->accumulate, MLK_BATCH_PERSISTENT, st);
+                              sc.descs.data(), &c, 1, p->accumulate, MLK_BATCH_PERSISTENT, st);
 }
 
 // median time (us) of one configuration; < 0 if it failed to launch

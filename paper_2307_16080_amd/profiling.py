@@ -7,7 +7,11 @@ for the batched workload to run under the profiler.
     python -m paper_2307_16080_amd.profiling batched <tile> <launches>
     python -m paper_2307_16080_amd.profiling paperconv <tile> <launches>
     python -m paper_2307_16080_amd.profiling gemm <bf16|e4m3|f32|i8> <tile> <launches> [size]
+    python -m paper_2307_16080_amd.profiling counters <counter_collection.csv> <kernel-name-substring>
+    python -m paper_2307_16080_amd.profiling window <kernel_trace.csv> <kernel-name-substring> <first> <count>
+    python -m paper_2307_16080_amd.profiling gemm-summary <dir> <source_hash> <tile> [<tile> ...]
     python -m paper_2307_16080_amd.profiling resnet <batch> <launches>
+    python -m paper_2307_16080_amd.profiling convf32 <tile> <launches>
 
 `batched` runs the 256 uneven bf16 GEMMs of the benchmark (seeded shapes and
 inputs) as persistent launches, replayed from a hipGraph, with the given tile
@@ -54,6 +58,56 @@ def _counter_per_dispatch(path, counter, name_sub, largest=False):
     if largest:
         return max(per.values()), len(per)
     return sum(per.values()) / len(per), len(per)
+
+
+def counters(path, kernel_sub):
+    """Every counter of a --pmc run, per dispatch of kernels matching
+    kernel_sub: summed over the counter's instances (the largest instance for
+    the GRBM_* counters, which count whole-GPU cycles), averaged over the
+    dispatches."""
+    per = {}
+    for r in _rows(path):
+        if kernel_sub not in r.get("Kernel_Name", ""):
+            continue
+        name = r["Counter_Name"]
+        d = r.get("Dispatch_Id") or r.get("Correlation_Id")
+        v = float(r["Counter_Value"])
+        slot = per.setdefault(name, {})
+        slot[d] = max(slot.get(d, 0.0), v) if name.startswith("GRBM_") else slot.get(d, 0.0) + v
+    return {k: sum(v.values()) / len(v) for k, v in per.items()}, {k: len(v) for k, v in per.items()}
+
+
+def window(trace_csv, kernel_sub, first, count):
+    """Durations (us) of dispatches first .. first+count-1 (negative first counts
+    from the end) of the kernels matching kernel_sub, in dispatch order."""
+    rows = [r for r in _rows(trace_csv) if kernel_sub in r["Kernel_Name"]]
+    rows.sort(key=lambda r: int(r["Start_Timestamp"]))
+    sel = rows[first:first + count] if first >= 0 else rows[len(rows) + first:len(rows) + first + count]
+    return [(int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3 for r in sel]
+
+
+def gemm_summary(root, tile, source_hash, copy_bytes=256 << 20, warmup=5, steps=20):
+    """One JSON-able record for one bf16 4096^3 tile from its four rocprofv3
+    runs under root: t_<tile> (kernel trace of the benchmark command), f_ and
+    w_ (FETCH_SIZE / WRITE_SIZE), m_ (SQ_VALU_MFMA_BUSY_CYCLES, GRBM_GUI_ACTIVE,
+    SQ_BUSY_CU_CYCLES with a kernel trace).  MFMA utilisation follows the
+    profiler's own MfmaUtil definition: busy cycles / (GRBM_GUI_ACTIVE of one
+    XCD x 1024 SIMDs); the CSV's GRBM_GUI_ACTIVE is summed over the 8 XCDs."""
+    w = tile.split(",")
+    kname = f"k_gemm_fast<1, {w[0]}, {w[1]}, {w[3]}, {w[4]}, {w[8]}, 0>"
+    every = window(f"{root}/t_{tile}/t_kernel_trace.csv", kname, 0, 1 << 30)
+    timed = window(f"{root}/t_{tile}/t_kernel_trace.csv", kname, warmup, steps)
+    tr = traffic(f"{root}/f_{tile}/f_counter_collection.csv", f"{root}/w_{tile}/w_counter_collection.csv", kname,
+                 copy_bytes)
+    cnt, _ = counters(f"{root}/m_{tile}/m_counter_collection.csv", kname)
+    grbm_xcd = cnt["GRBM_GUI_ACTIVE"] / 8.0
+    return {"config": [int(v) for v in w], "kernel": kname, "source_hash": source_hash,
+            "trace": {"dispatches": len(every), "avg_us": round(sum(every) / len(every), 2),
+                      "timed_window_avg_us": round(sum(timed) / len(timed), 2), "timed_window_min_us": round(min(timed), 2)},
+            "fetch_bytes": round(tr["fetch_bytes"]), "write_bytes": round(tr["write_bytes"]),
+            "bytes_per_launch": round(tr["bytes_per_launch"]),
+            "mfma_busy_cycles": cnt["SQ_VALU_MFMA_BUSY_CYCLES"], "grbm_gui_active_per_xcd": round(grbm_xcd),
+            "mfma_util_pct": round(100.0 * cnt["SQ_VALU_MFMA_BUSY_CYCLES"] / (grbm_xcd * 1024), 1)}
 
 
 def traffic(fetch_csv, write_csv, kernel_sub, copy_bytes, copy_sub="copy"):
@@ -170,6 +224,30 @@ def run_gemm(kind, tile, launches, size=4096):
     print(f"gemm {kind} {n}^3: {launches} launches, tile {tile}; one 256 MiB copy", flush=True)
 
 
+def run_conv_f32(tile, launches):
+    """The fp32 conv of the benchmark (1 x 64 x 56 x 56, 64 filters 3 x 3, stride
+    1, pad 1, normal(0, 1) from seed 0, y += conv) bound once and called back
+    to back with one fixed tile, then the reference copy."""
+    import os
+
+    import torch
+
+    sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+    import paper_2307_16080_amd as mlk
+    from workloads import CFG_CONV_F32 as cs, conv_inputs
+
+    x, w = conv_inputs(cs.N, cs.C, cs.H, cs.W, cs.F, cs.KH, cs.KW, seed=0)
+    xd, wd = torch.from_numpy(x).cuda(), torch.from_numpy(w).cuda()
+    y = torch.zeros(cs.N, cs.F, *cs.out_hw(), device="cuda")
+    call = mlk.ConvCall(xd, wd, y, (cs.stride,) * 2, (cs.pad,) * 2,
+                        cfg=mlk.TileConfig(*[int(v) for v in tile.split(",")]))
+    for _ in range(launches):
+        call()
+    torch.cuda.synchronize()
+    _copy_reference()
+    print(f"conv f32 56x56x64: {launches} calls, tile {tile}; one 256 MiB copy", flush=True)
+
+
 def run_resnet(batch, launches):
     """The ResNet-18 conv stack (bf16, seeded inputs) at one batch size: each
     layer shape tuned exhaustively (as the benchmark does), then every layer of
@@ -206,6 +284,8 @@ def run_resnet(batch, launches):
 if __name__ == "__main__":
     if sys.argv[1] == "gemm":
         run_gemm(sys.argv[2], sys.argv[3], int(sys.argv[4]), *(int(v) for v in sys.argv[5:6]))
+    elif sys.argv[1] == "convf32":
+        run_conv_f32(sys.argv[2], int(sys.argv[3]))
     elif sys.argv[1] == "resnet":
         run_resnet(int(sys.argv[2]), int(sys.argv[3]))
     elif sys.argv[1] == "batched":
@@ -214,6 +294,14 @@ if __name__ == "__main__":
         run_paper_conv(sys.argv[2], int(sys.argv[3]))
     elif sys.argv[1] == "stats":
         print(stats(sys.argv[2]))
+    elif sys.argv[1] == "gemm-summary":
+        for t in sys.argv[4:]:
+            print(json.dumps(gemm_summary(sys.argv[2], t, sys.argv[3])))
+    elif sys.argv[1] == "counters":
+        print(json.dumps(counters(sys.argv[2], sys.argv[3])))
+    elif sys.argv[1] == "window":
+        d = window(sys.argv[2], sys.argv[3], int(sys.argv[4]), int(sys.argv[5]))
+        print(json.dumps({"n": len(d), "avg_us": sum(d) / max(len(d), 1), "min_us": min(d), "max_us": max(d)}))
     elif sys.argv[1] == "traffic":
         t = traffic(sys.argv[2], sys.argv[3], sys.argv[4], int(sys.argv[5]))
         if len(sys.argv) > 7:

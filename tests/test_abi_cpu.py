@@ -199,12 +199,12 @@ def test_batched_validation():
     d = (L.GemmDesc * 2)()
     d[0] = L.GemmDesc(4, 4, 4, 0x1000, 4, 0x2000, 4, 0x3000, 4)
     d[1] = L.GemmDesc(4, 4, 4, 0x4000, 4, 0x5000, 3, 0x6000, 4)
-    assert lib.mlk_batched_matmul(L.MLK_BF16, L.MLK_F32, 2, d, NULL, 1, 0, NULL) == 3
-    assert lib.mlk_batched_matmul(L.MLK_BF16, L.MLK_F32, 0, d, NULL, 1, 0, NULL) == 2
-    assert lib.mlk_batched_matmul(L.MLK_I8, L.MLK_I32, 2, d, NULL, 1, 0, NULL) == 4
-    assert lib.mlk_batched_matmul(L.MLK_BF16, L.MLK_F32, 2, d, NULL, 1, 0x8, NULL) == 9
+    assert lib.mlk_batched_matmul(L.MLK_BF16, L.MLK_F32, 2, d, NULL, 0, 1, 0, NULL) == 3
+    assert lib.mlk_batched_matmul(L.MLK_BF16, L.MLK_F32, 0, d, NULL, 0, 1, 0, NULL) == 2
+    assert lib.mlk_batched_matmul(L.MLK_I8, L.MLK_I32, 2, d, NULL, 0, 1, 0, NULL) == 4
+    assert lib.mlk_batched_matmul(L.MLK_BF16, L.MLK_F32, 2, d, NULL, 0, 1, 0x8, NULL) == 9
     d[1] = L.GemmDesc(4, 4, 4, 0x4000, 4, NULL, 4, 0x6000, 4)
-    assert lib.mlk_batched_matmul(L.MLK_BF16, L.MLK_F32, 2, d, NULL, 1, 0, NULL) == 1
+    assert lib.mlk_batched_matmul(L.MLK_BF16, L.MLK_F32, 2, d, NULL, 0, 1, 0, NULL) == 1
 
 
 def test_config_space():
@@ -429,3 +429,17 @@ def test_matmul_noalloc_validation():
     st = call(4096, 64, 8193, 0x10000000, 8193, 0x20000000, 64, 0x30000000, 64, ctypes.byref(packed))
     msg = lib.mlk_last_error().decode()
     assert st == 2 and "no-alloc workspace" in msg, msg
+
+
+def test_batched_config_count_validation():
+    """ncfgs must be 0, 1 or count; a per-GEMM configuration is checked against
+    its own GEMM; all before any HIP call."""
+    lib = L.lib()
+    d = (L.GemmDesc * 2)(L.GemmDesc(4, 4, 4, 0x1000, 4, 0x2000, 4, 0x3000, 4),
+                         L.GemmDesc(8, 8, 8, 0x4000, 8, 0x5000, 8, 0x6000, 8))
+    good = L.TileConfig(64, 64, 64, 2, 2, 1, 1, 0, 0, 0)
+    assert lib.mlk_batched_matmul(L.MLK_BF16, L.MLK_F32, 2, d, ctypes.byref(good), 3, 1, 0, NULL) == 9
+    assert lib.mlk_batched_matmul(L.MLK_BF16, L.MLK_F32, 2, d, NULL, 1, 1, 0, NULL) == 1
+    bad = (L.TileConfig * 2)(good, L.TileConfig(48, 64, 32, 2, 2, 1, 1, 0, 0, 0))
+    st = lib.mlk_batched_matmul(L.MLK_BF16, L.MLK_F32, 2, d, bad, 2, 1, 0, NULL)
+    assert st == 5 and "desc 1" in lib.mlk_last_error().decode()

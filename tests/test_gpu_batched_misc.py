@@ -232,3 +232,49 @@ def test_tune_measured_small_problem(tmp_path):
     C = torch.zeros(512, 384, device="cuda")
     mlk.matmul(dev(A, torch.bfloat16), dev(B, torch.bfloat16), C)
     assert np.array_equal(host(C).astype(np.float64), oracle.matmul_f64(A, B))
+
+
+def test_batched_per_gemm_configs():
+    """One configuration per GEMM: per-GEMM launches honour each (split K
+    included); the persistent launch groups the GEMMs by kernel (here a
+    register-staged tile, the register-loaded direct-layout tile and a
+    direct-to-LDS tile with packing) and equals per-GEMM launches of the same
+    configurations (split 1) bit for bit on every graph replay; a zeroed entry
+    leaves that GEMM to choose."""
+    shapes = batched_shapes(36, seed=11) + [(64, 128, 128), (1, 1, 1), (300, 8, 64)]
+    probs, codes = _batch(shapes, seed=12)
+    fam = [mlk.TileConfig(64, 64, 64, 2, 2, 1, 1, 0, 0, 0), mlk.TileConfig(128, 128, 64, 2, 2, 1, 1, 0, 1, 0),
+           mlk.TileConfig(256, 128, 64, 2, 2, 1, 1, 0, 3, 0)]
+    cfgs = [fam[i % 3] for i in range(len(shapes))]
+    split = [mlk.TileConfig(*(list(c.as_tuple())[:5] + [2 if s[2] >= 512 and c.stages == 0 else 1] +
+                              list(c.as_tuple())[6:])) for c, s in zip(cfgs, shapes)]
+    # per-GEMM launches with split K where the depth allows it: oracle
+    _zero(probs)
+    mlk.batched_matmul(probs, cfg=split)
+    got = _outs(probs)
+    for i in range(0, len(shapes), 5):
+        qa, qb = codes[i]
+        ref = oracle.matmul_f64(oracle.bf16_decode(qa), oracle.bf16_decode(qb), threads=oracle.default_threads())
+        assert normwise(got[i], ref) <= 1e-5, (i, shapes[i], split[i])
+    # split 1 per-GEMM launches, the reference for the persistent groups
+    _zero(probs)
+    mlk.batched_matmul(probs, cfg=cfgs)
+    base = _outs(probs)
+    call = mlk.BatchedCall(probs, cfg=cfgs, persistent=True, graph=True)
+    for rep in range(3):
+        _zero(probs)
+        junk = torch.randn(1000, device="cuda").sum()
+        call()
+        for i, (a, b) in enumerate(zip(base, _outs(probs))):
+            assert np.array_equal(a, b), (rep, i, shapes[i], cfgs[i])
+        del junk
+    # zeroed entries: those GEMMs choose (persistent: the batch's choice)
+    mixed = [None if i % 4 == 0 else c for i, c in enumerate(cfgs)]
+    _zero(probs)
+    mlk.batched_matmul(probs, cfg=mixed, persistent=True)
+    got = _outs(probs)
+    for i in (0, 4, 8, len(shapes) - 1):
+        qa, qb = codes[i]
+        ref = oracle.matmul_f64(oracle.bf16_decode(qa), oracle.bf16_decode(qb), threads=oracle.default_threads())
+        assert normwise(got[i], ref) <= 1e-5, (i, shapes[i])
+    mlk.release()
