@@ -493,6 +493,24 @@ def main():
                                       "p90_us": round(single[180], 2), "launches": 200,
                                       "graph_amortised_us": round(us_graph, 2),
                                       "TFLOP/s_graph": round(2 * 128 ** 3 / us_graph / 1e6, 3)}
+        # the OpenMP host kernels (separate library, the paper's CPU lowering):
+        # tiling and unroll factor searched on this host's cores, next to their
+        # untiled unroll-1 form, for the small matmul, the fp32 conv and the
+        # paper's own layer
+        from paper_2307_16080_amd import host as H
+        host_rows = {}
+        for name, kind, dims, flops in (("matmul_f32_128", "matmul", (128, 128, 128), 2 * 128 ** 3),
+                                        ("conv_f32_56x56x64", "conv", (1, 64, 56, 56, 64, 3, 3, 1, 1, 1, 1),
+                                         CFG_CONV_F32.flops()),
+                                        ("conv_f32_paper_1280x1280x3", "conv", (1, 1, 1280, 1280, 3, 3, 3, 1, 1, 0, 0),
+                                         2 * 3 * 1278 * 1278 * 9)):
+            hb, hus, ht = H.tune(kind, dims, strategy=0, reps=3, want_times=True)
+            cf = H.configs(kind, dims)
+            u1 = [t for c, t in zip(cf, ht) if c.unroll == 1 and t > 0]
+            host_rows[name] = {"us": round(hus, 2), "GFLOP/s": round(flops / hus / 1e3, 2),
+                               "config": list(hb.as_tuple()), "threads": hb.threads or H.max_threads(),
+                               "best_unroll_1_us": round(min(u1), 2) if u1 else None, "configs": len(cf)}
+        rows_out["host_openmp_tuned"] = host_rows
     result["rows"] = rows_out
 
     # ---------------------------------------------------------------- CPU oracle baseline

@@ -28,7 +28,7 @@ class TileConfig(ctypes.Structure):
     _fields_ = [("bm", ctypes.c_int32), ("bn", ctypes.c_int32), ("bk", ctypes.c_int32),
                 ("wm", ctypes.c_int32), ("wn", ctypes.c_int32), ("split_k", ctypes.c_int32),
                 ("group_m", ctypes.c_int32), ("xcd_remap", ctypes.c_int32),
-                ("stages", ctypes.c_int32), ("layout", ctypes.c_int32)]
+                ("stages", ctypes.c_int32), ("layout", ctypes.c_int32), ("mfma", ctypes.c_int32)]
 
     def as_tuple(self):
         return tuple(getattr(self, f) for f, _ in self._fields_)

@@ -1,8 +1,10 @@
-"""Build the HIP library ``libmlk.so`` for gfx950 in-tree.
+"""Build the HIP library ``libmlk.so`` for gfx950 in-tree, and the OpenMP
+host-kernel library ``libmlkhost.so``.
 
 Every source under ``csrc/`` is compiled by hipcc to an object file in
 ``_build/`` (in parallel), then linked into ``libmlk.so`` next to this file.
-The C ABI is declared in ``include/mlk.h`` at the repository root.
+The C ABI is declared in ``include/mlk.h`` at the repository root; the host
+kernels' in ``include/mlk_host.h``.
 """
 import concurrent.futures
 import os
@@ -41,6 +43,22 @@ def _compile(src: str, verbose: bool) -> str:
     return obj
 
 
+HOST_SRC = os.path.join(HERE, "host", "mlk_host.cpp")
+HOST_LIB = os.path.join(HERE, "libmlkhost.so")
+
+
+def build_host(verbose: bool = False) -> str:
+    """The OpenMP host kernels (include/mlk_host.h) as their own library,
+    libmlkhost.so: g++, no HIP, nothing shared with libmlk.so."""
+    cmd = ["g++", "-O3", "-std=c++17", "-fopenmp", "-mavx2", "-mfma", "-fPIC", "-shared", "-Wall",
+           HOST_SRC, "-o", HOST_LIB + ".tmp"]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    subprocess.run(cmd, check=True)
+    os.replace(HOST_LIB + ".tmp", HOST_LIB)
+    return HOST_LIB
+
+
 def build(verbose: bool = False, jobs: int = 0) -> str:
     os.makedirs(BUILD, exist_ok=True)
     jobs = jobs or min(len(SOURCES), max(1, len(os.sched_getaffinity(0))))
@@ -52,6 +70,7 @@ def build(verbose: bool = False, jobs: int = 0) -> str:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)
     os.replace(tmp, LIB)
+    build_host(verbose)
     return LIB
 
 

@@ -76,10 +76,14 @@ const std::vector<const KernelEntry*>& registry() {
     return all;
 }
 
+// the MFMA tile of an entry or configuration: 32, or 16 (also written 0)
+static int mfma_of(int v) { return v == 32 ? 32 : 16; }
+
 const KernelEntry* find_kernel(int dt, int conv, const mlk_tile_config& c) {
+    if (c.mfma != 0 && c.mfma != 16 && c.mfma != 32) return nullptr;
     for (const KernelEntry* e : registry())
         if (e->dt == dt && e->conv == conv && e->bm == c.bm && e->bn == c.bn && e->bk == c.bk &&
-            e->wm == c.wm && e->wn == c.wn && e->stages == c.stages)
+            e->wm == c.wm && e->wn == c.wn && e->stages == c.stages && mfma_of(e->mfma) == mfma_of(c.mfma))
             return e;
     return nullptr;
 }
@@ -211,8 +215,8 @@ static bool direct_ok(const Shape& s) {
 mlk_status check_config(const Shape& s, int op, const mlk_tile_config& c) {
     const KernelEntry* e = find_kernel(s.dt, s.conv, c);
     if (!e)
-        return fail(MLK_ERR_CONFIG, "no compiled kernel for tile %dx%dx%d waves %dx%d stages %d (dtype %d%s)",
-                    c.bm, c.bn, c.bk, c.wm, c.wn, c.stages, s.dt, s.conv ? ", conv" : "");
+        return fail(MLK_ERR_CONFIG, "no compiled kernel for tile %dx%dx%d waves %dx%d stages %d mfma %d (dtype %d%s)",
+                    c.bm, c.bn, c.bk, c.wm, c.wn, c.stages, c.mfma, s.dt, s.conv ? ", conv" : "");
     if (!fast_ldc_ok(s, e))
         return fail(MLK_ERR_CONFIG, "direct-layout tile: N too large for its %d-row tile (32-bit output offsets)",
                     e->bm);
@@ -230,8 +234,8 @@ mlk_status check_config(const Shape& s, int op, const mlk_tile_config& c) {
     if (c.split_k > 1 && s.out16)
         return fail(MLK_ERR_CONFIG, "a bf16 output is rounded once from the whole sum: split_k must be 1");
     if (s.out16 && !e->launch_epi16)
-        return fail(MLK_ERR_CONFIG, "a bf16 output is written by the direct-to-LDS (stages >= 2) and plain "
-                    "(stages 0) tiles, not the register-loaded fast tiles");
+        return fail(MLK_ERR_CONFIG, "a bf16 output is written by the direct-to-LDS (stages >= 2, 16x16 MFMA) and "
+                    "plain (stages 0) tiles, not the register-loaded fast tiles or the 32x32 MFMA tiles");
     if (c.group_m < 0 || c.group_m > 64) return fail(MLK_ERR_CONFIG, "group_m must be in [0, 64]");
     if (c.xcd_remap != 0 && c.xcd_remap != 1) return fail(MLK_ERR_CONFIG, "xcd_remap must be 0 or 1");
     if (is_direct(e)) {
@@ -260,7 +264,7 @@ std::vector<mlk_tile_config> enumerate_configs(const mlk_problem* p, const Shape
         if (e->dt != s.dt || e->conv != s.conv) continue;
         if (batched && !e->persist) continue;
         if (is_direct(e)) {
-            if (direct_ok(s)) out.push_back(mlk_tile_config{e->bm, e->bn, e->bk, 0, 0, 1, 1, 0, 0, 2});
+            if (direct_ok(s)) out.push_back(mlk_tile_config{e->bm, e->bn, e->bk, 0, 0, 1, 1, 0, 0, 2, 0});
             continue;
         }
         if (e->stages >= 2 && !batched && !fast_shape_ok(s, e->bk)) continue;
@@ -272,9 +276,12 @@ std::vector<mlk_tile_config> enumerate_configs(const mlk_problem* p, const Shape
         const int64_t stages = cdiv(std::max<int64_t>(s.K, 1), e->bk);
         const int64_t tiles = cdiv(std::max<int64_t>(s.M, 1), e->bm) * cdiv(std::max<int64_t>(s.N, 1), e->bn);
         const int64_t tm = cdiv(std::max<int64_t>(s.M, 1), e->bm);
-        for (int sk : {1, 2, 4, 8}) {
+        // deep, narrow problems (batch-1 convolutions) fill the device only by splitting K far
+        for (int sk : {1, 2, 4, 8, 16, 32}) {
             if ((batched || s.out16) && sk > 1) break;
             if (sk > 1 && stages < 2 * sk) break;
+            // past 8, split only problems with too few tiles for four rounds of the device
+            if (sk > 8 && tiles * sk > 4 * device_cus()) break;
             for (int gm : {1, 8}) {
                 if (gm == 8 && (batched || tm < 16)) continue;
                 for (int xcd : {0, 1}) {
@@ -284,7 +291,8 @@ std::vector<mlk_tile_config> enumerate_configs(const mlk_problem* p, const Shape
                         if (lay == 1 && !(s.conv && e->launch_nhwc && s.conv_c % (16 / esize_in(s.dt)) == 0))
                             continue;
                         if (lay == 0 && !e->launch) continue;
-                        mlk_tile_config c{e->bm, e->bn, e->bk, e->wm, e->wn, sk, gm, xcd, e->stages, lay};
+                        mlk_tile_config c{e->bm, e->bn, e->bk, e->wm, e->wn, sk, gm, xcd, e->stages, lay,
+                                          e->mfma == 32 ? 32 : 0};
                         out.push_back(c);
                     }
                 }
@@ -313,15 +321,15 @@ mlk_tile_config heuristic_config(const Shape& s, int op) {
             best = e;
     }
     const KernelEntry* e = best ? best : smallest;
-    mlk_tile_config c{e->bm, e->bn, e->bk, e->wm, e->wn, 1, 1, 0, 0, 0};
+    mlk_tile_config c{e->bm, e->bn, e->bk, e->wm, e->wn, 1, 1, 0, 0, 0, 0};
     // large bf16 / e4m3 matmuls: the 8-wave direct-to-LDS tile, grouped raster
     if (op == MLK_OP_MATMUL && (s.dt == DT_BF16 || s.dt == DT_F8) &&
         cdiv(s.M, 256) * cdiv(s.N, 256) >= cus && s.K >= 256) {
         for (const KernelEntry* f : registry())
             if (f->dt == s.dt && !f->conv && f->stages == 2 && f->bm == 256 && f->bn == 256 &&
-                f->wm == 2 && f->wn == 4 && fast_shape_ok(s, f->bk) && fast_ldc_ok(s, f)) {
+                f->wm == 2 && f->wn == 4 && mfma_of(f->mfma) == 16 && fast_shape_ok(s, f->bk) && fast_ldc_ok(s, f)) {
                 const int64_t tiles = cdiv(s.M, 256) * cdiv(s.N, 256);
-                return mlk_tile_config{256, 256, f->bk, 2, 4, 1, 8, tiles % 8 == 0 ? 1 : 0, 2, 0};
+                return mlk_tile_config{256, 256, f->bk, 2, 4, 1, 8, tiles % 8 == 0 ? 1 : 0, 2, 0, 0};
             }
     }
     // few filters over a shallow depth: the direct (stencil) conv, whose MFMA
@@ -329,7 +337,7 @@ mlk_tile_config heuristic_config(const Shape& s, int op) {
     if (s.conv && direct_ok(s) && (s.dt == DT_F32 || s.K <= 64)) {
         for (const KernelEntry* d : registry())
             if (is_direct(d) && d->dt == s.dt && d->bm == 16)
-                return mlk_tile_config{d->bm, d->bn, d->bk, 0, 0, 1, 1, 0, 0, 2};
+                return mlk_tile_config{d->bm, d->bn, d->bk, 0, 0, 1, 1, 0, 0, 2, 0};
     }
     // channels-last pays a transpose of the input: worth it for large images
     if (s.conv && e->launch_nhwc && s.conv_c % (16 / esize_in(s.dt)) == 0 && s.N >= 16384) c.layout = 1;

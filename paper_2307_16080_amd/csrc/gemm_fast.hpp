@@ -41,6 +41,7 @@ namespace mlk {
 typedef __bf16 bf4_t __attribute__((ext_vector_type(4)));
 typedef int i2_t __attribute__((ext_vector_type(2)));
 typedef int32_t i32x4_t __attribute__((ext_vector_type(4)));
+typedef float f16v_t __attribute__((ext_vector_type(16)));
 
 // 16-byte buffer load per lane whose data goes to LDS at m0 + 16 * lane.
 // Written as inline asm so that the compiler does not treat it as a pending
@@ -91,18 +92,27 @@ __device__ inline int fa(int r) { return (r & 7) ^ ((r >> 2) & 2); }
 // Output stage: EPI = 0 the plain product; 1 adds the Linear layer's bias to
 // an fp32 C; 2 writes a bf16 C (bias optional).  Each is its own instantiation,
 // so no kernel carries a branch between them.
-template <int DT, int BM, int BN, int WM, int WN, int STAGES, int CONV = 0, int EPI = 0>
+// MF: the MFMA tile, 16 (16x16 outputs per instruction; every dtype) or 32
+// (bf16 v_mfma_f32_32x32x16_bf16: twice the flops per operand byte a lane
+// reads from LDS, 16 accumulators per lane per tile; GEMM policy, fp32 or
+// bias output stages).
+template <int DT, int BM, int BN, int WM, int WN, int STAGES, int CONV = 0, int EPI = 0, int MF = 16>
 struct FastGemm {
     static_assert(DT == DT_BF16 || DT == DT_F8 || DT == DT_I8, "direct-layout kernel: bf16, e4m3 or int8");
     static_assert(CONV == 0 || (CONV == 2 && DT == DT_BF16), "implicit convolution: bf16");
     static_assert(DT != DT_I8 || EPI == 0, "int8: plain int32 output stage only");
+    static_assert(MF == 16 || (MF == 32 && DT == DT_BF16 && CONV == 0 && EPI != 2),
+                  "32x32 MFMA tiles: bf16 GEMM policy, fp32 or bias output");
     static constexpr int KB = 128;                 // bytes of K per A row per stage
     static constexpr int ES = DT == DT_BF16 ? 2 : 1;
     static constexpr int BK = KB / ES;             // elements per A row per stage
     // k per MFMA: 16x16x32 bf16, 16x16x128 f8f6f4, 16x16x64 i8
-    static constexpr int KSTEP = DT == DT_BF16 ? 32 : DT == DT_F8 ? 128 : 64;
+    static constexpr int KSTEP = DT == DT_BF16 ? (MF == 32 ? 16 : 32) : DT == DT_F8 ? 128 : 64;
+    // accumulator registers per lane per MFMA tile
+    static constexpr int NR = MF == 32 ? 16 : 4;
     // int8: int32 accumulators and output (sums wrap modulo 2^32)
-    typedef typename std::conditional<DT == DT_I8, i4_t, f4_t>::type acc_t;
+    typedef typename std::conditional<DT == DT_I8, i4_t,
+                                      typename std::conditional<MF == 32, f16v_t, f4_t>::type>::type acc_t;
     typedef typename std::conditional<DT == DT_I8, int32_t, float>::type out_t;
     static constexpr int NW = WM * WN;
     static constexpr int NT = 64 * NW;
@@ -122,7 +132,7 @@ struct FastGemm {
     static constexpr int NB = B_SLABS / NW;
     static constexpr int LOADS = NA + NB;
     static constexpr int WTM = BM / WM, WTN = BN / WN;
-    static constexpr int TM = WTM / 16, TN = WTN / 16;
+    static constexpr int TM = WTM / MF, TN = WTN / MF;
     static constexpr int A_ROWS_PER_SLAB = 1024 / A_ROW;
     static constexpr int B_ROWS_PER_SLAB = 1024 / B_ROW;
     static constexpr int B_CHUNKS = B_ROW / 16;
@@ -138,14 +148,16 @@ struct FastGemm {
     // bytes maps every row to the same banks (chunks 0..15 must differ), 128
     // bytes alternates two halves by k & 1, 64 bytes four quarters by k & 3.
     __device__ static inline int fb(int k) {
-        if constexpr (DT == DT_BF16) return ((k & 3) << 1) | (((k >> 3) & 1) << 3);
+        // 32x32 tiles: a half-wave's transpose read covers 4 rows x 4 chunks
+        if constexpr (DT == DT_BF16 && MF == 32) return (k & 3) << 2;
+        else if constexpr (DT == DT_BF16) return ((k & 3) << 1) | (((k >> 3) & 1) << 3);
         else if constexpr (DT == DT_F8) return (k & 7) | (B_CHUNKS >= 16 ? (((k >> 5) & 1) << 3) : 0);
         else if constexpr (B_CHUNKS >= 16) return (k & 7) | (((k >> 4) & 1) << 3);
         else if constexpr (B_CHUNKS == 8) return ((k >> 1) & 3) | (((k >> 4) & 1) << 2);
         else return ((k >> 2) & 1) | (((k >> 4) & 1) << 1);
     }
     static_assert(LDS_BYTES <= 160 * 1024, "LDS budget");
-    static_assert(WTM % 16 == 0 && WTN % 16 == 0, "wave tile");
+    static_assert(WTM % MF == 0 && WTN % MF == 0, "wave tile");
     static_assert(STAGES >= 1 && (STAGES - 1) * LOADS < 64, "pipeline depth");
 
     // wait until stage `it` has landed: at most `later` stages (issued after
@@ -362,7 +374,34 @@ struct FastGemm {
 #pragma unroll
         for (int ks = 0; ks < KSTEPS; ++ks) {
             if (ks == MID_AT) mid();
-            if constexpr (DT == DT_BF16) {
+            if constexpr (DT == DT_BF16 && MF == 32) {
+                // 32x32x16: lane l supplies row (or column) l % 32 and k
+                // 8 * (l / 32) .. +7 of the 16-deep step: A as one 16-byte read,
+                // B as two transpose reads of 4 rows x 16 columns per 16-lane group
+                const int l32 = lg * 16 + lr, half = lg >> 1;
+                u4_t af[TM];
+#pragma unroll
+                for (int i = 0; i < TM; ++i) {
+                    const int r = wy * WTM + i * 32 + (l32 & 31);
+                    af[i] = *(const u4_t*)(sa + r * A_ROW + (((ks * 2 + half) ^ fa(r)) * 16));
+                }
+#pragma unroll
+                for (int j = 0; j < TN; ++j) {
+                    const int nb = wx * WTN + j * 32 + (lg & 1) * 16 + 4 * (lr & 3);
+                    bf4_t h[2];
+#pragma unroll
+                    for (int hh = 0; hh < 2; ++hh) {
+                        const int k = ks * 16 + half * 8 + hh * 4 + (lr >> 2);
+                        const int c = (nb >> 3) ^ fb(k);
+                        h[hh] = __builtin_amdgcn_ds_read_tr16_b64_v4bf16((tp)(sb + k * B_ROW + c * 16 + (nb & 7) * 2));
+                    }
+                    const bf8_t bj = bf8_t{h[0][0], h[0][1], h[0][2], h[0][3], h[1][0], h[1][1], h[1][2], h[1][3]};
+#pragma unroll
+                    for (int i = 0; i < TM; ++i)
+                        acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf8_t, af[i]), bj,
+                                                                            acc[i][j], 0, 0, 0);
+                }
+            } else if constexpr (DT == DT_BF16) {
                 u4_t af[TM];
 #pragma unroll
                 for (int i = 0; i < TM; ++i) {
@@ -520,7 +559,10 @@ struct FastGemm {
 #pragma unroll
         for (int i = 0; i < TM; ++i)
 #pragma unroll
-            for (int j = 0; j < TN; ++j) acc[i][j] = acc_t{0, 0, 0, 0};
+            for (int j = 0; j < TN; ++j) {
+                if constexpr (MF == 32) acc[i][j] = acc_t{};
+                else acc[i][j] = acc_t{0, 0, 0, 0};
+            }
 
         // prologue: STAGES-1 stages in flight (direct), or stage 0 in LDS (registers)
         if constexpr (!REG) {
@@ -541,12 +583,16 @@ struct FastGemm {
         const int lr = lane & 15, lg = lane >> 4;
         // This lane's outputs: rows wy*WTM + i*16 + lg*4 + r, columns
         // wx*WTN + j*16 + lr of the tile whose corner is Ct (a uniform base);
+        // with 32x32 MFMA tiles rows wy*WTM + i*32 + 8*(r/4) + 4*(lane/32) + r%4,
+        // columns wx*WTN + j*32 + lane%32;
         // offsets inside the tile are 32-bit.
         MLK_GLOBAL out_t* const Ct = (MLK_GLOBAL out_t*)g.C + (CONV ? 0 : m0 * g.ldc + n0);
         // bf16 output (GEMM policy only): the same tile of C as 16-bit codes
         MLK_GLOBAL uint16_t* const Cb = (MLK_GLOBAL uint16_t*)g.C + (CONV ? 0 : m0 * g.ldc + n0);
         const int ldc = (int)g.ldc;
-        const int row0 = wy * WTM + lg * 4, col0 = wx * WTN + lr;
+        const int row0 = wy * WTM + (MF == 32 ? 4 * (lane >> 5) : lg * 4);
+        const int col0 = wx * WTN + (MF == 32 ? (lane & 31) : lr);
+        auto rowof = [&](int i, int r) { return MF == 32 ? row0 + i * 32 + 8 * (r >> 2) + (r & 3) : row0 + i * 16 + r; };
         const bool full = m0 + BM <= g.M && n0 + BN <= g.N;
         const int mrem = (int)min<int64_t>(BM, g.M - m0), nrem = (int)min<int64_t>(BN, g.N - n0);
         // conv: output (f, n) of NFHW lives at img(n)*F*HW + f*HW + pix(n); this
@@ -556,7 +602,7 @@ struct FastGemm {
         if constexpr (CONV) {
 #pragma unroll
             for (int j = 0; j < TN; ++j) {
-                const int64_t n = n0 + col0 + j * 16;
+                const int64_t n = n0 + col0 + j * MF;
                 const int64_t img = (uint32_t)n / (uint32_t)hw;  // n < N*HO*WO < 2^31
                 cbase[j] = img * g.M * hw + (n - img * hw) + m0 * hw;
             }
@@ -583,8 +629,8 @@ struct FastGemm {
 #pragma unroll
                 for (int i = 0; i < TM; ++i)
 #pragma unroll
-                    for (int r = 0; r < 4; ++r) {
-                        const int row = row0 + i * 16 + r, col = col0 + j * 16;
+                    for (int r = 0; r < NR; ++r) {
+                        const int row = rowof(i, r), col = col0 + j * MF;
                         const bool in = full || (row < mrem && col < nrem);
                         out_t x = 0;
                         if constexpr (CONV) {
@@ -606,7 +652,10 @@ struct FastGemm {
 #pragma unroll
                     for (int i = 0; i < TM; ++i)
 #pragma unroll
-                        for (int j = 0; j < TN; ++j) acc[i][j] = acc_t{0, 0, 0, 0};
+                        for (int j = 0; j < TN; ++j) {
+                        if constexpr (MF == 32) acc[i][j] = acc_t{};
+                        else acc[i][j] = acc_t{0, 0, 0, 0};
+                    }
                 }
             }
         }
@@ -697,13 +746,13 @@ struct FastGemm {
         } else {
 #pragma unroll
             for (int j = 0; j < TN; ++j) {
-                const int col = col0 + j * 16;
+                const int col = col0 + j * MF;
                 const float bn = bias && (full || col < nrem) ? bias[n0 + col] : 0.0f;
 #pragma unroll
                 for (int i = 0; i < TM; ++i)
 #pragma unroll
-                    for (int r = 0; r < 4; ++r) {
-                        const int row = row0 + i * 16 + r;
+                    for (int r = 0; r < NR; ++r) {
+                        const int row = rowof(i, r);
                         if (!(full || (row < mrem && col < nrem))) continue;
                         MLK_GLOBAL out_t* p = CONV ? Ct + cbase[j] + row * hw : Ct + row * ldc + col;
                         out_t v;

@@ -15,6 +15,10 @@ const KernelEntry* kernels_i8(int* n) {
         MLK_ENTRY(DT_I8, 256, 256, 128, 2, 2, false),
         // direct-layout kernel (MFMA 16x16x64 i8, B transposed by ds_read_b64_tr_b8):
         // direct-to-LDS rings of 2-4 stages, and the register-loaded form (any alignment)
+        MLK_ENTRY_FAST_I8(32, 64, 1, 2, 3),   // 2 waves: twice the workgroups of 64 x 64
+        MLK_ENTRY_FAST_I8(32, 64, 1, 2, 4),
+        MLK_ENTRY_FAST_I8(64, 64, 1, 2, 4),
+        MLK_ENTRY_FAST_I8(64, 64, 2, 4, 4),   // 8 waves: more in flight per CU
         MLK_ENTRY_FAST_I8(64, 64, 2, 2, 2),
         MLK_ENTRY_FAST_I8(64, 64, 2, 2, 3),
         MLK_ENTRY_FAST_I8(64, 64, 2, 2, 4),

@@ -49,6 +49,7 @@ struct KernelEntry {
     occupancy_fn occupancy; // with persist: resident workgroups per CU
     launch_fn launch_epi;   // GEMM entries: the Linear variant, bias added to an fp32 C (EPI = 1)
     launch_fn launch_epi16; // GEMM entries that write a bf16 C (EPI = 2); null where not built
+    int mfma;               // MFMA output tile: 16 (16 x 16) or 32 (32 x 32, bf16 direct-layout tiles)
 };
 
 template <int DT, int BM, int BN, int KB, int WM, int WN, int CONV, int EPI = 0>
@@ -90,9 +91,9 @@ __global__ __launch_bounds__(64 * WM * WN) void k_gemm_persist(const GemmArgs* _
     }
 }
 
-template <int DT, int BM, int BN, int WM, int WN, int STAGES, int EPI = 0>
+template <int DT, int BM, int BN, int WM, int WN, int STAGES, int EPI = 0, int MF = 16>
 __global__ __launch_bounds__(64 * WM * WN) void k_gemm_fast(GemmArgs g) {
-    typedef FastGemm<DT, BM, BN, WM, WN, STAGES, 0, EPI> TL;
+    typedef FastGemm<DT, BM, BN, WM, WN, STAGES, 0, EPI, MF> TL;
     __shared__ __attribute__((aligned(1024))) uint8_t lds[TL::LDS_BYTES];
     int tm, tn, kz;
     tile_coords(g, blockIdx.x, gridDim.x, tm, tn, kz);
@@ -115,9 +116,9 @@ hipError_t launch_fast_conv(const GemmArgs& g, int nblk, hipStream_t s) {
     return hipGetLastError();
 }
 
-template <int DT, int BM, int BN, int WM, int WN, int STAGES, int EPI = 0>
+template <int DT, int BM, int BN, int WM, int WN, int STAGES, int EPI = 0, int MF = 16>
 hipError_t launch_fast(const GemmArgs& g, int nblk, hipStream_t s) {
-    hipLaunchKernelGGL((k_gemm_fast<DT, BM, BN, WM, WN, STAGES, EPI>), dim3(nblk), dim3(64 * WM * WN), 0,
+    hipLaunchKernelGGL((k_gemm_fast<DT, BM, BN, WM, WN, STAGES, EPI, MF>), dim3(nblk), dim3(64 * WM * WN), 0,
                        s, g);
     return hipGetLastError();
 }
@@ -125,11 +126,11 @@ hipError_t launch_fast(const GemmArgs& g, int nblk, hipStream_t s) {
 // Persistent form of the direct-layout kernel (one tile shape).  The
 // direct-to-LDS form (STAGES >= 2) runs batches whose operands were packed
 // into aligned, zero-padded buffers first.
-template <int DT, int BM, int BN, int WM, int WN, int STAGES>
+template <int DT, int BM, int BN, int WM, int WN, int STAGES, int MF = 16>
 __global__ __launch_bounds__(64 * WM * WN) void k_fast_persist(const GemmArgs* __restrict__ gemms,
                                                                const Task* __restrict__ tasks,
                                                                const int32_t* __restrict__ bounds) {
-    typedef FastGemm<DT, BM, BN, WM, WN, STAGES> TL;
+    typedef FastGemm<DT, BM, BN, WM, WN, STAGES, 0, 0, MF> TL;
     __shared__ __attribute__((aligned(1024))) uint8_t lds[TL::LDS_BYTES];
     const int b = blockIdx.x;
     const int t0 = bounds[b], t1 = bounds[b + 1];
@@ -141,10 +142,10 @@ __global__ __launch_bounds__(64 * WM * WN) void k_fast_persist(const GemmArgs* _
     }
 }
 
-template <int DT, int BM, int BN, int WM, int WN, int STAGES>
+template <int DT, int BM, int BN, int WM, int WN, int STAGES, int MF = 16>
 hipError_t launch_fast_persist(const GemmArgs* gemms, const Task* tasks, const int32_t* bounds,
                                int nblk, hipStream_t s) {
-    hipLaunchKernelGGL((k_fast_persist<DT, BM, BN, WM, WN, STAGES>), dim3(nblk), dim3(64 * WM * WN), 0,
+    hipLaunchKernelGGL((k_fast_persist<DT, BM, BN, WM, WN, STAGES, MF>), dim3(nblk), dim3(64 * WM * WN), 0,
                        s, gemms, tasks, bounds);
     return hipGetLastError();
 }
@@ -161,9 +162,9 @@ template <int DT, int BM, int BN, int KB, int WM, int WN>
 int occupancy_persist() {
     return occupancy_of(k_gemm_persist<DT, BM, BN, KB, WM, WN>, 64 * WM * WN);
 }
-template <int DT, int BM, int BN, int WM, int WN, int STAGES>
+template <int DT, int BM, int BN, int WM, int WN, int STAGES, int MF = 16>
 int occupancy_fast_persist() {
-    return occupancy_of(k_fast_persist<DT, BM, BN, WM, WN, STAGES>, 64 * WM * WN);
+    return occupancy_of(k_fast_persist<DT, BM, BN, WM, WN, STAGES, MF>, 64 * WM * WN);
 }
 
 template <int DT, int BM, int BN, int KB, int WM, int WN, int CONV, int EPI = 0>
@@ -203,7 +204,7 @@ launch_fn fast_epi16() {
             &launch_gemm<DT, BM, BN, KB, WM, WN, (CONV) ? 1 : 0>, nullptr,                     \
             (CONV) ? &launch_gemm<DT, BM, BN, KB, WM, WN, 2> : nullptr, nullptr,              \
             tile_epi<DT, BM, BN, KB, WM, WN, (CONV) ? 1 : 0, 1>(),                             \
-            tile_epi<DT, BM, BN, KB, WM, WN, (CONV) ? 1 : 0, 2>()                              \
+            tile_epi<DT, BM, BN, KB, WM, WN, (CONV) ? 1 : 0, 2>(), 16                          \
     }
 
 #define MLK_ENTRY_P(DT, BM, BN, KB, WM, WN)                                                  \
@@ -212,7 +213,7 @@ launch_fn fast_epi16() {
             Tile<DT, BM, BN, KB, WM, WN, 0>::LDS_BYTES, 64 * (WM) * (WN),                    \
             &launch_gemm<DT, BM, BN, KB, WM, WN, 0>, &launch_persist<DT, BM, BN, KB, WM, WN>,  \
             nullptr, &occupancy_persist<DT, BM, BN, KB, WM, WN>,                             \
-            tile_epi<DT, BM, BN, KB, WM, WN, 0, 1>(), tile_epi<DT, BM, BN, KB, WM, WN, 0, 2>()   \
+            tile_epi<DT, BM, BN, KB, WM, WN, 0, 1>(), tile_epi<DT, BM, BN, KB, WM, WN, 0, 2>(), 16 \
     }
 
 #define MLK_ENTRY_FAST(DT, BM, BN, WM, WN, STAGES)                                           \
@@ -222,7 +223,18 @@ launch_fn fast_epi16() {
             &launch_fast<DT, BM, BN, WM, WN, STAGES>,                                        \
             &launch_fast_persist<DT, BM, BN, WM, WN, STAGES>, nullptr,                       \
             &occupancy_fast_persist<DT, BM, BN, WM, WN, STAGES>,                             \
-            &launch_fast<DT, BM, BN, WM, WN, STAGES, 1>, fast_epi16<DT, BM, BN, WM, WN, STAGES>() \
+            &launch_fast<DT, BM, BN, WM, WN, STAGES, 1>, fast_epi16<DT, BM, BN, WM, WN, STAGES>(), 16 \
+    }
+
+// the same direct-layout GEMM with 32 x 32 MFMA tiles (bf16): no bf16-output variant
+#define MLK_ENTRY_FAST32(BM, BN, WM, WN, STAGES)                                             \
+    KernelEntry {                                                                            \
+        DT_BF16, 0, STAGES, BM, BN, FastGemm<DT_BF16, BM, BN, WM, WN, STAGES, 0, 0, 32>::BK, WM, WN, \
+            FastGemm<DT_BF16, BM, BN, WM, WN, STAGES, 0, 0, 32>::LDS_BYTES, 64 * (WM) * (WN),   \
+            &launch_fast<DT_BF16, BM, BN, WM, WN, STAGES, 0, 32>,                            \
+            &launch_fast_persist<DT_BF16, BM, BN, WM, WN, STAGES, 32>, nullptr,              \
+            &occupancy_fast_persist<DT_BF16, BM, BN, WM, WN, STAGES, 32>,                    \
+            &launch_fast<DT_BF16, BM, BN, WM, WN, STAGES, 1, 32>, nullptr, 32                \
     }
 
 // int8 direct-layout entry: the plain int32 output stage only (no Linear or
@@ -231,7 +243,7 @@ launch_fn fast_epi16() {
     KernelEntry {                                                                            \
         DT_I8, 0, STAGES, BM, BN, FastGemm<DT_I8, BM, BN, WM, WN, STAGES>::BK, WM, WN,        \
             FastGemm<DT_I8, BM, BN, WM, WN, STAGES>::LDS_BYTES, 64 * (WM) * (WN),            \
-            &launch_fast<DT_I8, BM, BN, WM, WN, STAGES>, nullptr, nullptr, nullptr, nullptr, nullptr \
+            &launch_fast<DT_I8, BM, BN, WM, WN, STAGES>, nullptr, nullptr, nullptr, nullptr, nullptr, 16 \
     }
 
 // conv entry: channels-last layout only (launch_nhwc); no NCHW form, no persistent form
@@ -239,7 +251,7 @@ launch_fn fast_epi16() {
     KernelEntry {                                                                            \
         DT, 1, STAGES, BM, BN, FastGemm<DT, BM, BN, WM, WN, STAGES, 2>::BK, WM, WN,          \
             FastGemm<DT, BM, BN, WM, WN, STAGES, 2>::LDS_BYTES, 64 * (WM) * (WN), nullptr,   \
-            nullptr, &launch_fast_conv<DT, BM, BN, WM, WN, STAGES>, nullptr                  \
+            nullptr, &launch_fast_conv<DT, BM, BN, WM, WN, STAGES>, nullptr, nullptr, nullptr, 16 \
     }
 
 // Tables defined by the instantiation units (host functions: the tables hold

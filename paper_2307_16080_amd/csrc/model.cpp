@@ -39,7 +39,7 @@ namespace mlk {
 
 namespace {
 
-constexpr int kFeatures = 36;
+constexpr int kFeatures = 37;
 // The model is a small ensemble: kMembers networks of the same shape, started
 // from different initial weights and batch orders, whose log-time predictions
 // are averaged (one network's ranking of close configurations varies with its
@@ -110,6 +110,7 @@ void model_features(const Shape& s, const mlk_tile_config& c, int cus, float* f)
     f[i++] = c.layout == 1 ? (float)lg(in_el) : 0.f;
     f[i++] = c.layout == 1 && taps > 1 ? (float)lg((double)M * K) : 0.f;
     f[i++] = c.layout == 2 ? 1.f : 0.f;
+    f[i++] = c.mfma == 32 ? 1.f : 0.f;  // 32 x 32 MFMA tiles
 }
 
 static mlk_status upload_params(mlk_cost_model* m) {

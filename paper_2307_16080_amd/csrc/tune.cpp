@@ -78,9 +78,11 @@ bool db_lookup(const char* path, const std::string& key, const std::string& dev,
         size_t ut = s.find("\"us\": ");
         if (at == std::string::npos || ut == std::string::npos) continue;
         mlk_tile_config t;
-        if (sscanf(s.c_str() + at + 8, "%d, %d, %d, %d, %d, %d, %d, %d, %d, %d", &t.bm, &t.bn, &t.bk,
-                   &t.wm, &t.wn, &t.split_k, &t.group_m, &t.xcd_remap, &t.stages, &t.layout) != 10)
-            continue;
+        memset(&t, 0, sizeof t);
+        // eleven fields; lines written before the mfma field hold ten (mfma 0)
+        const int got = sscanf(s.c_str() + at + 8, "%d, %d, %d, %d, %d, %d, %d, %d, %d, %d, %d", &t.bm, &t.bn, &t.bk,
+                               &t.wm, &t.wn, &t.split_k, &t.group_m, &t.xcd_remap, &t.stages, &t.layout, &t.mfma);
+        if (got != 10 && got != 11) continue;
         double u = 0;
         if (sscanf(s.c_str() + ut + 6, "%lf", &u) != 1) continue;
         *c = t;
@@ -97,10 +99,10 @@ bool db_append(const char* path, const std::string& key, const std::string& dev,
     FILE* f = fopen(path, "a");
     if (!f) return false;
     fprintf(f,
-            "{\"key\": \"%s\", \"device\": \"%s\", \"cfg\": [%d, %d, %d, %d, %d, %d, %d, %d, %d, %d], "
+            "{\"key\": \"%s\", \"device\": \"%s\", \"cfg\": [%d, %d, %d, %d, %d, %d, %d, %d, %d, %d, %d], "
             "\"us\": %.4f, \"measured\": %d, \"legal\": %d, \"strategy\": %d, \"lib\": \"%s\"}\n",
             key.c_str(), dev.c_str(), c.bm, c.bn, c.bk, c.wm, c.wn, c.split_k, c.group_m,
-            c.xcd_remap, c.stages, c.layout, us, n_measured, n_legal, strategy, mlk_version());
+            c.xcd_remap, c.stages, c.layout, c.mfma, us, n_measured, n_legal, strategy, mlk_version());
     const bool ok = fflush(f) == 0;
     fclose(f);
     return ok;
@@ -233,15 +235,15 @@ double measure(const mlk_problem* p, const Shape& s, const Scratch& sc, const ml
 }
 
 // The fields of a configuration as the evolution strategy mutates them: the
-// kernel (tile shape, waves and stages together), split_k, group_m,
-// xcd_remap and layout.
-constexpr int kGenes = 5;
+// kernel (tile shape, waves and stages together), the MFMA shape, split_k,
+// group_m, xcd_remap and layout.
+constexpr int kGenes = 6;
 
 int gene_distance(const mlk_tile_config& a, const mlk_tile_config& b) {
     const bool kernel = a.bm == b.bm && a.bn == b.bn && a.bk == b.bk && a.wm == b.wm && a.wn == b.wn &&
                         a.stages == b.stages;
-    return (kernel ? 0 : 1) + (a.split_k != b.split_k) + (a.group_m != b.group_m) + (a.xcd_remap != b.xcd_remap) +
-           (a.layout != b.layout);
+    return (kernel ? 0 : 1) + (a.mfma != b.mfma) + (a.split_k != b.split_k) + (a.group_m != b.group_m) +
+           (a.xcd_remap != b.xcd_remap) + (a.layout != b.layout);
 }
 
 // (1+1) evolution strategy over the legal configurations.  The parent starts

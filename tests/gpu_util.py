@@ -47,10 +47,10 @@ def all_tiles(in_dtype, out_dtype, conv=False):
         p = mlk.matmul_problem(8192, 8192, 8192, in_dtype, out_dtype)
     seen, out = set(), []
     for c in mlk.configs(p):
-        key = (c.bm, c.bn, c.bk, c.wm, c.wn, c.stages, c.layout)
+        key = (c.bm, c.bn, c.bk, c.wm, c.wn, c.stages, c.layout, c.mfma)
         if key not in seen:
             seen.add(key)
-            out.append(mlk.TileConfig(*key[:5], 1, 1, 0, key[5], key[6]))
+            out.append(mlk.TileConfig(*key[:5], 1, 1, 0, key[5], key[6], key[7]))
     return out
 
 

@@ -52,13 +52,14 @@ def _tiles():
     """Every tile that writes a bf16 C (the register-loaded fast tiles do not)."""
     out = []
     for dt in (L.MLK_BF16, L.MLK_F8E4M3):
-        out += [(dt, c) for c in all_tiles(dt, L.MLK_F32) if c.stages != 1]
+        # (the register-loaded fast tiles and the 32x32 MFMA tiles have no bf16 output stage)
+        out += [(dt, c) for c in all_tiles(dt, L.MLK_F32) if c.stages != 1 and c.mfma != 32]
     return out
 
 
 def _id(p):
     dt, c = p
-    return f"{'bf16' if dt == L.MLK_BF16 else 'e4m3'}_{c.bm}x{c.bn}x{c.bk}_{c.wm}{c.wn}_s{c.stages}"
+    return f"{'bf16' if dt == L.MLK_BF16 else 'e4m3'}_{c.bm}x{c.bn}x{c.bk}_{c.wm}{c.wn}_s{c.stages}_m{c.mfma}"
 
 
 @pytest.mark.parametrize("p", _tiles(), ids=_id)
@@ -140,10 +141,11 @@ def test_bf16_out_refuses_split_k_and_register_loaded_tiles():
     c = all_tiles(L.MLK_BF16, L.MLK_F32)[0]
     with pytest.raises(mlk.MlkError):
         mlk.matmul(A, B, C, cfg=mlk.TileConfig(c.bm, c.bn, c.bk, c.wm, c.wn, 2, 1, 0, c.stages, c.layout))
-    reg = [t for t in all_tiles(L.MLK_BF16, L.MLK_F32) if t.stages == 1]
-    if reg:
+    reg = [t for t in all_tiles(L.MLK_BF16, L.MLK_F32) if t.stages == 1 or t.mfma == 32]
+    assert any(t.mfma == 32 for t in reg)
+    for t in reg:
         with pytest.raises(mlk.MlkError):
-            mlk.matmul(A, B, C, cfg=reg[0])
+            mlk.matmul(A, B, C, cfg=t)
     # the default (heuristic) configuration of a small-M, deep product does not split
     mlk.matmul(A, B, C)
     assert not torch.any(C.float() != 0).item()

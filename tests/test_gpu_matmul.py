@@ -55,7 +55,7 @@ def test_f32_config0_128():
     assert err <= 1e-5
 
 
-@pytest.mark.parametrize("cfg", all_tiles(L.MLK_F32, L.MLK_F32), ids=lambda c: f"{c.bm}x{c.bn}x{c.bk}_{c.wm}{c.wn}_s{c.stages}")
+@pytest.mark.parametrize("cfg", all_tiles(L.MLK_F32, L.MLK_F32), ids=lambda c: f"{c.bm}x{c.bn}x{c.bk}_{c.wm}{c.wn}_s{c.stages}_m{c.mfma}")
 def test_f32_every_tile_ragged(cfg):
     for (M, N, K) in RAGGED:
         say("f32", cfg, M, N, K)
@@ -112,7 +112,7 @@ def test_i8_1024_bit_exact():
     assert np.array_equal(host(C), ref)
 
 
-@pytest.mark.parametrize("cfg", all_tiles(L.MLK_I8, L.MLK_I32), ids=lambda c: f"{c.bm}x{c.bn}x{c.bk}_{c.wm}{c.wn}_s{c.stages}")
+@pytest.mark.parametrize("cfg", all_tiles(L.MLK_I8, L.MLK_I32), ids=lambda c: f"{c.bm}x{c.bn}x{c.bk}_{c.wm}{c.wn}_s{c.stages}_m{c.mfma}")
 def test_i8_every_tile_ragged(cfg):
     for (M, N, K) in RAGGED:
         say("i8", cfg, M, N, K)
@@ -211,7 +211,7 @@ BF16_TILES = all_tiles(L.MLK_BF16, L.MLK_F32)
 ALIGNED = [(1, 8, 64), (100, 136, 192), (257, 520, 640), (300, 264, 128), (512, 512, 1024), (33, 1000, 64)]
 
 
-@pytest.mark.parametrize("cfg", [c for c in BF16_TILES if c.stages >= 2], ids=lambda c: f"{c.bm}x{c.bn}x{c.bk}_{c.wm}{c.wn}_s{c.stages}")
+@pytest.mark.parametrize("cfg", [c for c in BF16_TILES if c.stages >= 2], ids=lambda c: f"{c.bm}x{c.bn}x{c.bk}_{c.wm}{c.wn}_s{c.stages}_m{c.mfma}")
 def test_bf16_direct_to_lds_tiles(cfg):
     for (M, N, K) in ALIGNED:
         say("bf16 direct", cfg, M, N, K)
@@ -255,7 +255,7 @@ def test_bf16_direct_to_lds_tiles(cfg):
     assert np.array_equal(host(C).astype(np.float64), oracle.matmul_f64(A, B))
 
 
-@pytest.mark.parametrize("cfg", [c for c in BF16_TILES if c.stages < 2], ids=lambda c: f"{c.bm}x{c.bn}x{c.bk}_{c.wm}{c.wn}_s{c.stages}")
+@pytest.mark.parametrize("cfg", [c for c in BF16_TILES if c.stages < 2], ids=lambda c: f"{c.bm}x{c.bn}x{c.bk}_{c.wm}{c.wn}_s{c.stages}_m{c.mfma}")
 def test_bf16_every_tile_ragged(cfg):
     for (M, N, K) in RAGGED:
         say("bf16", cfg, M, N, K)
@@ -280,7 +280,7 @@ E4M3_TILES = all_tiles(L.MLK_F8E4M3, L.MLK_F32)
 ALIGNED8 = [(1, 16, 128), (100, 144, 256), (257, 528, 640), (300, 272, 128), (512, 512, 1024), (33, 1008, 128)]
 
 
-@pytest.mark.parametrize("cfg", [c for c in E4M3_TILES if c.stages >= 2], ids=lambda c: f"{c.bm}x{c.bn}x{c.bk}_{c.wm}{c.wn}_s{c.stages}")
+@pytest.mark.parametrize("cfg", [c for c in E4M3_TILES if c.stages >= 2], ids=lambda c: f"{c.bm}x{c.bn}x{c.bk}_{c.wm}{c.wn}_s{c.stages}_m{c.mfma}")
 def test_e4m3_direct_to_lds_tiles(cfg):
     for (M, N, K) in ALIGNED8:
         say("e4m3 direct", cfg, M, N, K)
@@ -342,7 +342,7 @@ def test_e4m3_direct_scaled_accumulate_extremes():
         assert np.all(np.abs(got - ref) <= bound), float(np.max(np.abs(got - ref) / bound))
 
 
-@pytest.mark.parametrize("cfg", [c for c in E4M3_TILES if c.stages < 2], ids=lambda c: f"{c.bm}x{c.bn}x{c.bk}_{c.wm}{c.wn}_s{c.stages}")
+@pytest.mark.parametrize("cfg", [c for c in E4M3_TILES if c.stages < 2], ids=lambda c: f"{c.bm}x{c.bn}x{c.bk}_{c.wm}{c.wn}_s{c.stages}_m{c.mfma}")
 def test_e4m3_every_tile_ragged(cfg):
     for (M, N, K) in RAGGED:
         say("e4m3", cfg, M, N, K)
