@@ -107,7 +107,14 @@ typedef enum {
  *              channels-last (NHWC) and the filter to F x KH x KW x C in the
  *              library's scratch memory (one launch for both), so every
  *              operand load is one aligned 16-byte read; needs C a multiple
- *              of 8 (bf16) or 4 (fp32) and 16-byte aligned x and w.  2: the
+ *              of 8 (bf16) or 4 (fp32) and 16-byte aligned x and w.  3: the
+ *              channel gather (bf16, register-loaded conv tiles, stages 1):
+ *              the kernel reads the NCHW input itself, each 16-byte LDS chunk
+ *              being 8 channels of one input pixel (8 two-byte loads H*W
+ *              elements apart), so no input copy is made; the filter is used
+ *              as F x KH x KW x C (a 1 x 1 filter as it is; otherwise a
+ *              transposed copy in scratch memory per call, or once per bound
+ *              convolution); needs C a multiple of 8 and F <= 65535.  2: the
  *              direct (stencil) conv, no GEMM tiling: a workgroup computes a
  *              bm x bn block of output pixels (bn = 64) for all F filters
  *              from the input window staged in LDS; its configurations have
@@ -238,7 +245,9 @@ mlk_status mlk_conv2d_nchw_fchw(mlk_dtype in, mlk_dtype out, int64_t N, int64_t 
  * mlk_conv2d_nchw_fchw), and, for the channels-last layout (layout 1),
  * allocates the plan's own buffers (an NHWC copy of the input and, for
  * filters larger than 1 x 1, the filter as F x KH x KW x C) and enqueues the
- * filter's transpose on `stream`.  It must not be called on a capturing
+ * filter's transpose on `stream`; for the channel-gather layout (layout 3)
+ * only the transposed filter (none for a 1 x 1 filter), so that each run is
+ * a single kernel launch.  It must not be called on a capturing
  * stream (MLK_ERR_CONFIG).  `w` (device, FCHW) is bound to the plan: runs use
  * its values as of creation (or of the last mlk_conv2d_plan_update_filter,
  * which re-reads it, stream-ordered); it must stay allocated while the plan

@@ -194,7 +194,7 @@ class ConvCall:
     into a captured graph.  The filter's values are those at binding (or at
     the last update_filter()).  The tensors are kept alive by the object; their
     storage must not move between calls.  `stream`, if given here, orders the
-    binding's own work (the channels-last filter transpose) and is the default
+    binding's own work (the filter transpose of the channels-last and channel-gather layouts) and is the default
     for every call."""
 
     def __init__(self, x, w, y, stride=(1, 1), pad=(0, 0), accumulate: bool = True, cfg=None,

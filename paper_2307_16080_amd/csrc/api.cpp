@@ -246,12 +246,15 @@ mlk_status check_config(const Shape& s, int op, const mlk_tile_config& c) {
                         kDirectMaxF, kDirectMaxStride, kDirectMaxTap, kDirectMaxTap);
         return MLK_OK;
     }
-    if (c.layout != 0 && !(s.conv && c.layout == 1))
-        return fail(MLK_ERR_CONFIG, "layout must be 0, or 1 for conv2d (2 only for the direct conv tiles)");
-    if (s.conv && !e->launch && c.layout != 1)
-        return fail(MLK_ERR_CONFIG, "this conv tile runs only the channels-last layout (layout 1)");
+    if (c.layout != 0 && !(s.conv && (c.layout == 1 || c.layout == 3)))
+        return fail(MLK_ERR_CONFIG, "layout must be 0, or 1 or 3 for conv2d (2 only for the direct conv tiles)");
+    if (s.conv && !e->launch && c.layout == 0)
+        return fail(MLK_ERR_CONFIG, "this conv tile runs only the channels-last layouts (layout 1 or 3)");
     if (c.layout == 1 && (!e->launch_nhwc || s.conv_c % (16 / esize_in(s.dt)) != 0))
         return fail(MLK_ERR_CONFIG, "channels-last layout needs C a multiple of %d", 16 / esize_in(s.dt));
+    if (c.layout == 3 && (!e->launch_gather || s.conv_c % (16 / esize_in(s.dt)) != 0 || s.M > 65535))
+        return fail(MLK_ERR_CONFIG, "the channel-gather layout (3) needs a register-loaded bf16 conv tile, C a "
+                    "multiple of %d and F <= 65535", 16 / esize_in(s.dt));
     const int64_t tiles = cdiv(s.M, c.bm) * cdiv(s.N, c.bn) * c.split_k;
     if (tiles > ((int64_t)1 << 31) - 1) return fail(MLK_ERR_CONFIG, "too many workgroups");
     return MLK_OK;
@@ -287,9 +290,10 @@ std::vector<mlk_tile_config> enumerate_configs(const mlk_problem* p, const Shape
                 for (int xcd : {0, 1}) {
                     const int64_t nblk = tiles * sk;
                     if (xcd == 1 && (batched || nblk < 64 || nblk % 8 != 0)) continue;
-                    for (int lay = 0; lay < 2; ++lay) {
-                        if (lay == 1 && !(s.conv && e->launch_nhwc && s.conv_c % (16 / esize_in(s.dt)) == 0))
-                            continue;
+                    for (int lay : {0, 1, 3}) {
+                        const bool cl = s.conv && s.conv_c % (16 / esize_in(s.dt)) == 0;
+                        if (lay == 1 && !(cl && e->launch_nhwc)) continue;
+                        if (lay == 3 && !(cl && e->launch_gather && s.M <= 65535)) continue;
                         if (lay == 0 && !e->launch) continue;
                         mlk_tile_config c{e->bm, e->bn, e->bk, e->wm, e->wn, sk, gm, xcd, e->stages, lay,
                                           e->mfma == 32 ? 32 : 0};
@@ -600,7 +604,14 @@ mlk_status launch_conv(const Shape& s, int64_t n, int64_t c, int64_t h, int64_t 
         return err == hipSuccess ? MLK_OK : hip_fail(err, "direct conv launch");
     }
     const int epv = 16 / es;
-    if (cfg.layout == 1) {
+    if (cfg.layout == 3) {
+        if (!(e->launch_gather && c % epv == 0 && f <= 65535))
+            return fail(MLK_ERR_CONFIG, "the channel-gather layout needs a register-loaded bf16 conv tile, C %% %d == 0 "
+                        "and F <= 65535", epv);
+        if (!prep && kh * kw != 1)
+            if (mlk_status rc = refuse_under_capture(st, "the channel-gather conv layout without a plan"); rc != MLK_OK)
+                return rc;
+    } else if (cfg.layout == 1) {
         if (!(e->launch_nhwc && c % epv == 0 && (uintptr_t)x % 16 == 0 && (uintptr_t)wt % 16 == 0 &&
               n <= 65535 && f <= 65535))
             return fail(MLK_ERR_CONFIG, "channels-last layout needs C %% %d == 0, aligned x and w, N, F <= 65535", epv);
@@ -614,6 +625,33 @@ mlk_status launch_conv(const Shape& s, int64_t n, int64_t c, int64_t h, int64_t 
         if (z != hipSuccess) return hip_fail(z, "zero output");
     }
     const int64_t nblk = (int64_t)g.tiles_m * g.tiles_n * g.split_k;
+    // Channel-gather route: the kernel reads the NCHW input itself (8 channels
+    // of one pixel per 16-byte LDS chunk); only the filter is needed as
+    // F x KH x KW x C -- the plan's copy, the filter itself when 1 x 1, else
+    // a transposed copy in the library's scratch buffer.
+    if (cfg.layout == 3) {
+        g.B = x;
+        const void* a = prep ? prep->w_cl : kh * kw == 1 ? wt : nullptr;
+        if (a) {
+            g.A = a;
+            g.vec_a = (uintptr_t)a % 16 == 0 && (g.lda * es) % 16 == 0;
+            const hipError_t err = e->launch_gather(g, (int)nblk, st);
+            return err == hipSuccess ? MLK_OK : hip_fail(err, "conv launch");
+        }
+        ScratchUse scratch;
+        if (mlk_status rc = scratch.begin((size_t)(f * c * kh * kw) * es, st, "the channel-gather conv layout");
+            rc != MLK_OK)
+            return rc;
+        hipError_t err = launch_transpose_pair(nullptr, nullptr, 0, 0, 0, wt, scratch.ptr(), f, c, kh * kw, es, st);
+        if (err == hipSuccess) {
+            g.A = scratch.ptr();
+            g.vec_a = 1;
+            err = e->launch_gather(g, (int)nblk, st);
+        }
+        const mlk_status rel = scratch.end();
+        if (err != hipSuccess) return hip_fail(err, "conv launch");
+        return rel;
+    }
     // Channels-last route: with C a multiple of the 16-byte vector, transpose
     // x to NHWC and the filter to F x KH x KW x C in the library's scratch
     // buffer, so every operand load of the tile kernel is one aligned 16-byte
@@ -859,16 +897,17 @@ struct mlk_conv_plan {
     mlk_tile_config cfg{};
     const void* filter = nullptr;  // the caller's FCHW filter
     void* buf = nullptr;           // channels-last layout: NHWC input copy, then the transposed filter
-    size_t xb = 0;                 // bytes of the input copy (256-byte multiple)
+                                   // (channel-gather layout: the transposed filter only)
+    size_t xb = 0;                 // bytes of the input copy (256-byte multiple; 0 for channel gather)
     int device = 0;
 };
 
 namespace {
 
-// the filter in F x KH x KW x C for a channels-last plan (a 1 x 1 filter is
-// used as it is)
+// the filter in F x KH x KW x C for a channels-last or channel-gather plan
+// (a 1 x 1 filter is used as it is)
 mlk_status plan_transpose_filter(const mlk_conv_plan* pl, hipStream_t st) {
-    if (pl->cfg.layout != 1 || pl->kh * pl->kw == 1) return MLK_OK;
+    if ((pl->cfg.layout != 1 && pl->cfg.layout != 3) || pl->kh * pl->kw == 1) return MLK_OK;
     const int es = esize_in(pl->s.dt);
     const hipError_t e = launch_transpose_pair(nullptr, nullptr, 0, 0, 0, pl->filter, (char*)pl->buf + pl->xb,
                                                pl->f, pl->c, pl->kh * pl->kw, es, st);
@@ -946,10 +985,9 @@ mlk_status mlk_conv2d_plan_create(mlk_dtype in, mlk_dtype out, int64_t N, int64_
         delete pl;
         return hip_fail(e, "hipGetDevice");
     }
-    if (c.layout == 1) {
-        const int es = esize_in(s.dt);
-        pl->xb = ((size_t)(N * C * H * W) * es + 255) & ~(size_t)255;
-        const size_t wb = KH * KW == 1 ? 0 : (size_t)(F * C * KH * KW) * es;
+    const size_t wb = KH * KW == 1 ? 0 : (size_t)(F * C * KH * KW) * esize_in(s.dt);
+    if (c.layout == 1 || (c.layout == 3 && wb > 0)) {
+        pl->xb = c.layout == 1 ? ((size_t)(N * C * H * W) * esize_in(s.dt) + 255) & ~(size_t)255 : 0;
         if ((e = hipMalloc(&pl->buf, pl->xb + wb)) != hipSuccess) {
             delete pl;
             return hip_fail(e, "conv plan buffers");
@@ -987,7 +1025,8 @@ mlk_status mlk_conv2d_plan_run(const mlk_conv_plan* plan, const void* x, void* y
     if (dev != pl.device) return fail(MLK_ERR_ARG, "conv plan: created on device %d, run on device %d", pl.device, dev);
     ConvPrep prep{pl.buf, pl.kh * pl.kw == 1 ? pl.filter : (const void*)((const char*)pl.buf + pl.xb)};
     return launch_conv(pl.s, pl.n, pl.c, pl.h, pl.w, pl.f, pl.kh, pl.kw, pl.sh, pl.sw, pl.ph, pl.pw, pl.ho, pl.wo, x,
-                       pl.filter, y, pl.cfg, (hipStream_t)stream, pl.cfg.layout == 1 ? &prep : nullptr);
+                       pl.filter, y, pl.cfg, (hipStream_t)stream,
+                       pl.cfg.layout == 1 || pl.cfg.layout == 3 ? &prep : nullptr);
 }
 
 mlk_status mlk_conv2d_plan_config(const mlk_conv_plan* plan, mlk_tile_config* cfg) {

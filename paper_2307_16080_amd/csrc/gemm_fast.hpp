@@ -89,6 +89,9 @@ __device__ inline int fa(int r) { return (r & 7) ^ ((r >> 2) & 2); }
 // of 8), through registers (STAGES = 1) or as direct-to-LDS copies (STAGES >=
 // 2, C*KH*KW a multiple of BK), and kept in LDS like A (rows of BK k), so the
 // MFMA's B operand is read as A's is.  The output is NFHW.
+// CONV = 3: the same tile fed from the NCHW input itself (no channels-last
+// copy): each 16-byte chunk -- 8 channels of one input pixel -- is assembled
+// in registers from 8 two-byte loads H*W elements apart (STAGES = 1 only).
 // Output stage: EPI = 0 the plain product; 1 adds the Linear layer's bias to
 // an fp32 C; 2 writes a bf16 C (bias optional).  Each is its own instantiation,
 // so no kernel carries a branch between them.
@@ -99,7 +102,8 @@ __device__ inline int fa(int r) { return (r & 7) ^ ((r >> 2) & 2); }
 template <int DT, int BM, int BN, int WM, int WN, int STAGES, int CONV = 0, int EPI = 0, int MF = 16>
 struct FastGemm {
     static_assert(DT == DT_BF16 || DT == DT_F8 || DT == DT_I8, "direct-layout kernel: bf16, e4m3 or int8");
-    static_assert(CONV == 0 || (CONV == 2 && DT == DT_BF16), "implicit convolution: bf16");
+    static_assert(CONV == 0 || ((CONV == 2 || CONV == 3) && DT == DT_BF16), "implicit convolution: bf16");
+    static_assert(CONV != 3 || STAGES == 1, "the NCHW channel gather is register-loaded");
     static_assert(DT != DT_I8 || EPI == 0, "int8: plain int32 output stage only");
     static_assert(MF == 16 || (MF == 32 && DT == DT_BF16 && CONV == 0 && EPI != 2),
                   "32x32 MFMA tiles: bf16 GEMM policy, fp32 or bias output");
@@ -273,7 +277,9 @@ struct FastGemm {
                 // below 2^31): 32-bit divisions
                 const int img = rs.p_ok[i] ? (int)((uint32_t)p / (uint32_t)hw) : 0;
                 const int q = rs.p_ok[i] ? (int)p - img * hw : 0;
-                rs.p_img[i] = (int64_t)img * g.ch * g.cw;
+                // image base in elements: NHWC (CONV 2) counts pixels, scaled by C
+                // at the load; NCHW (CONV 3) is the image's first element
+                rs.p_img[i] = CONV == 3 ? (int64_t)img * g.cc * g.ch * g.cw : (int64_t)img * g.ch * g.cw;
                 rs.p_ih0[i] = (q / g.cwo) * g.csh - g.cph;
                 rs.p_iw0[i] = (q % g.cwo) * g.csw - g.cpw;
                 const int k = (int)kfirst + rs.b_col[i];
@@ -319,9 +325,22 @@ struct FastGemm {
                 const int64_t k = k0 + rs.b_col[i];
                 if (rs.p_ok[i] && k < g.K) {
                     const int ih = rs.p_ih0[i] + rs.k_kh[i], iw = rs.p_iw0[i] + rs.k_kw[i];
-                    if ((unsigned)ih < (unsigned)g.ch && (unsigned)iw < (unsigned)g.cw)
-                        v = *(const MLK_GLOBAL u4_t*)(B + ((rs.p_img[i] + (int64_t)ih * g.cw + iw) * g.cc +
-                                                           rs.k_ci[i]) * ES);
+                    if ((unsigned)ih < (unsigned)g.ch && (unsigned)iw < (unsigned)g.cw) {
+                        if constexpr (CONV == 3) {
+                            // channels ci..ci+7 of pixel (ih, iw): one plane (H*W elements) apart
+                            const int64_t plane = (int64_t)g.ch * g.cw;
+                            const MLK_GLOBAL uint16_t* src = (const MLK_GLOBAL uint16_t*)B + rs.p_img[i] +
+                                                             (int64_t)rs.k_ci[i] * plane + (int64_t)ih * g.cw + iw;
+                            uint32_t h[8];
+#pragma unroll
+                            for (int e = 0; e < 8; ++e) h[e] = src[e * plane];
+                            v = u4_t{h[0] | (h[1] << 16), h[2] | (h[3] << 16), h[4] | (h[5] << 16),
+                                     h[6] | (h[7] << 16)};
+                        } else {
+                            v = *(const MLK_GLOBAL u4_t*)(B + ((rs.p_img[i] + (int64_t)ih * g.cw + iw) * g.cc +
+                                                               rs.k_ci[i]) * ES);
+                        }
+                    }
                 }
                 rb[i] = v;
                 rs.k_ci[i] += BK;

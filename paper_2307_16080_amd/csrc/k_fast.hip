@@ -31,7 +31,9 @@ const KernelEntry* kernels_fast(int* n) {
         MLK_ENTRY_FAST(DT_F8, 128, 128, 2, 2, 4),
         MLK_ENTRY_FAST(DT_F8, 128, 128, 2, 2, 2),
         MLK_ENTRY_FAST(DT_F8, 128, 128, 2, 2, 1),
-        // channels-last implicit-GEMM convolution (bf16, C a multiple of 8)
+        // channels-last implicit-GEMM convolution (bf16, C a multiple of 8);
+        // these register-loaded tiles also gather straight from NCHW (layout 3)
+        MLK_ENTRY_FASTCONV(DT_BF16, 64, 64, 2, 2, 1),
         MLK_ENTRY_FASTCONV(DT_BF16, 128, 128, 2, 2, 1),
         MLK_ENTRY_FASTCONV(DT_BF16, 64, 128, 2, 2, 1),
         MLK_ENTRY_FASTCONV(DT_BF16, 128, 256, 2, 2, 1),

@@ -22,6 +22,14 @@ const KernelEntry* kernels_i8(int* n) {
         MLK_ENTRY_FAST_I8(64, 64, 2, 2, 2),
         MLK_ENTRY_FAST_I8(64, 64, 2, 2, 3),
         MLK_ENTRY_FAST_I8(64, 64, 2, 2, 4),
+        // deep rings: at K = 1024 every stage of a 64 x 64 tile is in flight
+        // from the start (8 x 16 KB of LDS), so the loop waits once per stage
+        // for data already requested instead of for a copy issued a few
+        // stages earlier
+        MLK_ENTRY_FAST_I8(64, 64, 2, 2, 6),
+        MLK_ENTRY_FAST_I8(64, 64, 2, 2, 8),
+        MLK_ENTRY_FAST_I8(64, 64, 1, 2, 8),
+        MLK_ENTRY_FAST_I8(32, 64, 1, 2, 8),
         MLK_ENTRY_FAST_I8(128, 64, 2, 2, 3),
         MLK_ENTRY_FAST_I8(64, 128, 2, 2, 3),
         MLK_ENTRY_FAST_I8(128, 128, 2, 2, 2),

@@ -50,6 +50,7 @@ struct KernelEntry {
     launch_fn launch_epi;   // GEMM entries: the Linear variant, bias added to an fp32 C (EPI = 1)
     launch_fn launch_epi16; // GEMM entries that write a bf16 C (EPI = 2); null where not built
     int mfma;               // MFMA output tile: 16 (16 x 16) or 32 (32 x 32, bf16 direct-layout tiles)
+    launch_fn launch_gather;  // conv entries: the NCHW channel-gather variant (CONV = 3); null where not built
 };
 
 template <int DT, int BM, int BN, int KB, int WM, int WN, int CONV, int EPI = 0>
@@ -100,20 +101,28 @@ __global__ __launch_bounds__(64 * WM * WN) void k_gemm_fast(GemmArgs g) {
     TL::run(g, tm, tn, kz, lds);
 }
 
-// The channels-last implicit-GEMM convolution form of the direct-layout kernel.
-template <int DT, int BM, int BN, int WM, int WN, int STAGES>
+// The implicit-GEMM convolution forms of the direct-layout kernel: CONV 2
+// gathers from a channels-last copy of the input, CONV 3 from NCHW itself.
+template <int DT, int BM, int BN, int WM, int WN, int STAGES, int CONV = 2>
 __global__ __launch_bounds__(64 * WM * WN) void k_fast_conv(GemmArgs g) {
-    typedef FastGemm<DT, BM, BN, WM, WN, STAGES, 2> TL;
+    typedef FastGemm<DT, BM, BN, WM, WN, STAGES, CONV> TL;
     __shared__ __attribute__((aligned(1024))) uint8_t lds[TL::LDS_BYTES];
     int tm, tn, kz;
     tile_coords(g, blockIdx.x, gridDim.x, tm, tn, kz);
     TL::run(g, tm, tn, kz, lds);
 }
 
-template <int DT, int BM, int BN, int WM, int WN, int STAGES>
+template <int DT, int BM, int BN, int WM, int WN, int STAGES, int CONV = 2>
 hipError_t launch_fast_conv(const GemmArgs& g, int nblk, hipStream_t s) {
-    hipLaunchKernelGGL((k_fast_conv<DT, BM, BN, WM, WN, STAGES>), dim3(nblk), dim3(64 * WM * WN), 0, s, g);
+    hipLaunchKernelGGL((k_fast_conv<DT, BM, BN, WM, WN, STAGES, CONV>), dim3(nblk), dim3(64 * WM * WN), 0, s, g);
     return hipGetLastError();
+}
+
+// the channel-gather variant exists for the register-loaded conv tiles only
+template <int DT, int BM, int BN, int WM, int WN, int STAGES>
+constexpr launch_fn gather_fn() {
+    if constexpr (STAGES == 1) return &launch_fast_conv<DT, BM, BN, WM, WN, 1, 3>;
+    else return nullptr;
 }
 
 template <int DT, int BM, int BN, int WM, int WN, int STAGES, int EPI = 0, int MF = 16>
@@ -246,12 +255,15 @@ launch_fn fast_epi16() {
             &launch_fast<DT_I8, BM, BN, WM, WN, STAGES>, nullptr, nullptr, nullptr, nullptr, nullptr, 16 \
     }
 
-// conv entry: channels-last layout only (launch_nhwc); no NCHW form, no persistent form
+// conv entry: the channels-last layout (launch_nhwc) and, for the
+// register-loaded tiles, the NCHW channel gather (launch_gather); no plain
+// NCHW form (launch), no persistent form
 #define MLK_ENTRY_FASTCONV(DT, BM, BN, WM, WN, STAGES)                                       \
     KernelEntry {                                                                            \
         DT, 1, STAGES, BM, BN, FastGemm<DT, BM, BN, WM, WN, STAGES, 2>::BK, WM, WN,          \
             FastGemm<DT, BM, BN, WM, WN, STAGES, 2>::LDS_BYTES, 64 * (WM) * (WN), nullptr,   \
-            nullptr, &launch_fast_conv<DT, BM, BN, WM, WN, STAGES>, nullptr, nullptr, nullptr, 16 \
+            nullptr, &launch_fast_conv<DT, BM, BN, WM, WN, STAGES>, nullptr, nullptr, nullptr, 16, \
+            gather_fn<DT, BM, BN, WM, WN, STAGES>()                                             \
     }
 
 // Tables defined by the instantiation units (host functions: the tables hold

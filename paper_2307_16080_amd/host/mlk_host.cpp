@@ -333,7 +333,7 @@ int mlkh_tune(int32_t op, const int64_t* d, int32_t strategy, double budget_frac
                 parent = child;
                 tp = tc;
                 fails = 0;
-            } else if (++fails >= 8) {  // restart from an unmeasured configuration
+            } else if (++fails >= 8 && used < budget) {  // restart from an unmeasured configuration
                 std::vector<int> fresh;
                 for (int i = 0; i < S; ++i)
                     if (t[(size_t)i] < 0) fresh.push_back(i);

@@ -10,7 +10,8 @@ for the batched workload to run under the profiler.
     python -m paper_2307_16080_amd.profiling counters <counter_collection.csv> <kernel-name-substring>
     python -m paper_2307_16080_amd.profiling window <kernel_trace.csv> <kernel-name-substring> <first> <count>
     python -m paper_2307_16080_amd.profiling gemm-summary <dir> <source_hash> <tile> [<tile> ...]
-    python -m paper_2307_16080_amd.profiling resnet <batch> <launches>
+    python -m paper_2307_16080_amd.profiling resnet <batch> <launches> [graph]
+    python -m paper_2307_16080_amd.profiling lastpass <kernel_trace.csv> <dispatches per pass> [passes]
     python -m paper_2307_16080_amd.profiling convf32 <tile> <launches>
 
 `batched` runs the 256 uneven bf16 GEMMs of the benchmark (seeded shapes and
@@ -84,6 +85,33 @@ def window(trace_csv, kernel_sub, first, count):
     rows.sort(key=lambda r: int(r["Start_Timestamp"]))
     sel = rows[first:first + count] if first >= 0 else rows[len(rows) + first:len(rows) + first + count]
     return [(int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3 for r in sel]
+
+
+def last_pass(trace_csv, count, passes=1):
+    """The last `passes` runs of a sequence of `count` dispatches (the trace's
+    last count * passes dispatches, in start order): per dispatch its kernel,
+    duration and the gap since the previous dispatch ended, and per pass the
+    kernel time summed by kernel family against first start to last end."""
+    rows = sorted(_rows(trace_csv), key=lambda r: int(r["Start_Timestamp"]))
+    rows = rows[len(rows) - count * passes:]
+    out = []
+    for p in range(passes):
+        sel = rows[p * count:(p + 1) * count]
+        t0, t1 = int(sel[0]["Start_Timestamp"]), max(int(r["End_Timestamp"]) for r in sel)
+        fam, items, prev_end = {}, [], None
+        for r in sel:
+            st, en = int(r["Start_Timestamp"]), int(r["End_Timestamp"])
+            name = r["Kernel_Name"].replace("(anonymous namespace)::", "").split("(")[0]
+            name = name.replace("void ", "").replace("mlk::", "")
+            key = name.split("<")[0]
+            fam[key] = fam.get(key, 0.0) + (en - st) / 1e3
+            items.append({"kernel": name[:70], "us": round((en - st) / 1e3, 2),
+                          "gap_us": round((st - prev_end) / 1e3, 2) if prev_end is not None else None})
+            prev_end = en
+        out.append({"span_us": round((t1 - t0) / 1e3, 1), "kernel_us": round(sum(fam.values()), 1),
+                    "by_family_us": {k: round(v, 1) for k, v in sorted(fam.items(), key=lambda kv: -kv[1])},
+                    "dispatches": items})
+    return out
 
 
 def gemm_summary(root, tile, source_hash, copy_bytes=256 << 20, warmup=5, steps=20):
@@ -248,10 +276,12 @@ def run_conv_f32(tile, launches):
     print(f"conv f32 56x56x64: {launches} calls, tile {tile}; one 256 MiB copy", flush=True)
 
 
-def run_resnet(batch, launches):
+def run_resnet(batch, launches, graph=False):
     """The ResNet-18 conv stack (bf16, seeded inputs) at one batch size: each
     layer shape tuned exhaustively (as the benchmark does), then every layer of
-    the stack launched `launches` times in stack order with its tuned tile."""
+    the stack launched `launches` times in stack order with its tuned tile;
+    with `graph`, the stack is captured once as one graph and the graph is
+    replayed `launches` times (the benchmark's timing of the stack)."""
     import os
 
     import torch
@@ -274,11 +304,24 @@ def run_resnet(batch, launches):
         calls += [call] * count
         print(f"layer {shape}: tile {list(best.as_tuple())}", flush=True)
     torch.cuda.synchronize()
-    for _ in range(launches):
-        for call in calls:
+    if graph:
+        for call in calls:      # first runs (plan set-up) outside the capture
             call()
+        torch.cuda.synchronize()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            for call in calls:
+                call()
+        torch.cuda.synchronize()
+        for _ in range(launches):
+            g.replay()
+    else:
+        for _ in range(launches):
+            for call in calls:
+                call()
     torch.cuda.synchronize()
-    print(f"resnet18 b{batch}: {launches} passes over {len(calls)} layers", flush=True)
+    print(f"resnet18 b{batch}: {launches} {'graph replays' if graph else 'passes'} over {len(calls)} layers",
+          flush=True)
 
 
 if __name__ == "__main__":
@@ -287,7 +330,7 @@ if __name__ == "__main__":
     elif sys.argv[1] == "convf32":
         run_conv_f32(sys.argv[2], int(sys.argv[3]))
     elif sys.argv[1] == "resnet":
-        run_resnet(int(sys.argv[2]), int(sys.argv[3]))
+        run_resnet(int(sys.argv[2]), int(sys.argv[3]), len(sys.argv) > 4 and sys.argv[4] == "graph")
     elif sys.argv[1] == "batched":
         run_batched(sys.argv[2], int(sys.argv[3]))
     elif sys.argv[1] == "paperconv":
@@ -299,6 +342,12 @@ if __name__ == "__main__":
             print(json.dumps(gemm_summary(sys.argv[2], t, sys.argv[3])))
     elif sys.argv[1] == "counters":
         print(json.dumps(counters(sys.argv[2], sys.argv[3])))
+    elif sys.argv[1] == "lastpass":
+        for p in last_pass(sys.argv[2], int(sys.argv[3]), int(sys.argv[4]) if len(sys.argv) > 4 else 1):
+            d = p.pop("dispatches")
+            print(json.dumps(p))
+            for it in d:
+                print(f"  {it['us']:8.2f} us  gap {it['gap_us'] if it['gap_us'] is not None else '-':>6}  {it['kernel']}")
     elif sys.argv[1] == "window":
         d = window(sys.argv[2], sys.argv[3], int(sys.argv[4]), int(sys.argv[5]))
         print(json.dumps({"n": len(d), "avg_us": sum(d) / max(len(d), 1), "min_us": min(d), "max_us": max(d)}))

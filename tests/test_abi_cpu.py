@@ -220,12 +220,16 @@ def test_config_space():
     # conv and batched spaces
     cp = mlk.conv_problem(32, 64, 56, 56, 64, 3, 3, 1, 1)
     assert mlk.config_count(cp) > 20
-    assert {c.layout for c in mlk.configs(cp)} == {0, 1}
-    # channels-last needs C a multiple of the 16-byte vector (8 bf16); with
-    # F <= 16 the direct (stencil) conv adds its layout-2 tiles
+    assert {c.layout for c in mlk.configs(cp)} == {0, 1, 3}
+    # layout 3 (NCHW channel gather): the register-loaded channels-last tiles only
+    assert all(c.stages == 1 for c in mlk.configs(cp) if c.layout == 3)
+    assert {c.layout for c in mlk.configs(mlk.conv_problem(2, 64, 16, 16, 64, 3, 3, 1, 1, L.MLK_F32))} == {0, 1}
+    # channels-last and channel gather need C a multiple of the 16-byte vector
+    # (8 bf16); with F <= 16 the direct (stencil) conv adds its layout-2 tiles
     c3 = mlk.conv_problem(1, 3, 32, 32, 16, 3, 3, 1, 1)
     assert {c.layout for c in mlk.configs(c3)} == {0, 2}
     assert not mlk.config_legal(c3, mlk.TileConfig(32, 32, 32, 1, 1, 1, 1, 0, 0, 1))
+    assert not mlk.config_legal(c3, mlk.TileConfig(64, 64, 64, 2, 2, 1, 1, 0, 1, 3))
     direct = [c for c in mlk.configs(c3) if c.layout == 2]
     assert direct and all(c.wm == 0 and c.wn == 0 and c.split_k == 1 and c.bk == 1 for c in direct)
     d0 = direct[0]
@@ -239,9 +243,10 @@ def test_config_space():
     # and layout is meaningless for matmul
     assert not mlk.config_legal(mlk.matmul_problem(64, 64, 64, L.MLK_BF16, L.MLK_F32),
                                 mlk.TileConfig(64, 64, 32, 2, 2, 1, 1, 0, 0, 1))
-    # the direct-layout conv form (stages 1) exists only channels-last
+    # the direct-layout conv form (stages 1) exists channels-last and as the
+    # NCHW channel gather, never as the plain NCHW form (layout 0)
     fast_conv = [c for c in mlk.configs(cp) if c.stages == 1]
-    assert fast_conv and all(c.layout == 1 for c in fast_conv)
+    assert fast_conv and {c.layout for c in fast_conv} == {1, 3}
     f0 = fast_conv[0]
     assert not mlk.config_legal(cp, mlk.TileConfig(*list(f0.as_tuple())[:9], 0))
     assert not any(c.stages == 1 for c in mlk.configs(c3))

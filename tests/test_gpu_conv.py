@@ -81,7 +81,8 @@ def test_every_conv_tile(cfg):
             assert np.array_equal(host(y).astype(np.float64), oracle.conv2d_f64(x, w, (s, s), (p, p))), case
 
 
-FAST_CONV = [c for c in all_tiles(L.MLK_BF16, L.MLK_F32, conv=True) if c.stages == 1]
+FAST_CONV = [c for c in all_tiles(L.MLK_BF16, L.MLK_F32, conv=True) if c.stages == 1 and c.layout == 1]
+GATHER_CONV = [c for c in all_tiles(L.MLK_BF16, L.MLK_F32, conv=True) if c.layout == 3]
 # channels-last shapes (C a multiple of 8): strides, padding, K = C*KH*KW not a
 # multiple of the 64-deep stage, tiles that span images, ragged F and pixels
 FAST_CASES = [
@@ -122,6 +123,48 @@ def test_fast_conv_tiles(cfg):
             mlk.conv2d_nchw_fchw(from_bf16_codes(oracle.bf16_encode(x)), from_bf16_codes(oracle.bf16_encode(w)),
                                  y, (s, s), (p, p), cfg=cfg, accumulate=acc)
             assert np.array_equal(host(y).astype(np.float64), oracle.conv2d_f64(x, w, (s, s), (p, p))), (case, acc)
+
+
+@pytest.mark.parametrize("cfg", GATHER_CONV, ids=lambda c: f"{c.bm}x{c.bn}x{c.bk}_{c.wm}{c.wn}")
+def test_gather_conv_tiles(cfg):
+    """Layout 3: the register-loaded conv tile reading the NCHW input itself
+    (8 channels of a pixel gathered per 16-byte chunk), per call (the filter
+    transposed in scratch memory, or used as it is when 1 x 1) and bound
+    (mlk.ConvCall: the filter transposed once), overwrite and accumulate, with
+    split K; C not a multiple of 8 is refused."""
+    assert GATHER_CONV and cfg.stages == 1
+    assert not mlk.config_legal(mlk.conv_problem(1, 12, 8, 8, 16, 3, 3, 1, 1, L.MLK_BF16, L.MLK_F32), cfg)
+    for case in FAST_CASES:
+        N, C, H, W, F, KH, KW, s, p = case
+        say("gather conv", cfg, case)
+        prob = mlk.conv_problem(N, C, H, W, F, KH, KW, s, p, L.MLK_BF16, L.MLK_F32)
+        x, w = conv_inputs(N, C, H, W, F, KH, KW, seed=sum(case) + 11)
+        ho, wo = (H + 2 * p - KH) // s + 1, (W + 2 * p - KW) // s + 1
+        y0 = np.random.default_rng(5).uniform(-1, 1, (N, F, ho, wo)).astype(np.float32)
+        qx, qw = oracle.bf16_encode(x), oracle.bf16_encode(w)
+        ref = oracle.conv2d_f64(oracle.bf16_decode(qx), oracle.bf16_decode(qw), (s, s), (p, p), y=y0)
+        y = dev(y0)
+        mlk.conv2d_nchw_fchw(from_bf16_codes(qx), from_bf16_codes(qw), y, (s, s), (p, p), cfg=cfg)
+        assert normwise(host(y), ref) <= 1e-5, case
+        xi, wi = conv_inputs(N, C, H, W, F, KH, KW, seed=6, dist="small_int")
+        exact = oracle.conv2d_f64(xi, wi, (s, s), (p, p))
+        dx, dw = from_bf16_codes(oracle.bf16_encode(xi)), from_bf16_codes(oracle.bf16_encode(wi))
+        for sk in (1, 2):
+            c = mlk.TileConfig(cfg.bm, cfg.bn, cfg.bk, cfg.wm, cfg.wn, sk, 1, 0, 1, 3)
+            if not mlk.config_legal(prob, c):
+                continue
+            for acc in (True, False):
+                y = torch.zeros(N, F, ho, wo, device="cuda") if acc else \
+                    torch.full((N, F, ho, wo), float("nan"), device="cuda")
+                mlk.conv2d_nchw_fchw(dx, dw, y, (s, s), (p, p), cfg=c, accumulate=acc)
+                assert np.array_equal(host(y).astype(np.float64), exact), (case, sk, acc)
+            # bound: one launch per call, the filter transposed at creation
+            y = torch.full((N, F, ho, wo), float("nan"), device="cuda")
+            call = mlk.ConvCall(dx, dw, y, (s, s), (p, p), cfg=c, accumulate=False)
+            assert call.config.layout == 3
+            call()
+            call()
+            assert np.array_equal(host(y).astype(np.float64), exact), (case, sk, "plan")
 
 
 FAST_CONV_DMA = [c for c in all_tiles(L.MLK_BF16, L.MLK_F32, conv=True) if c.stages >= 2]
