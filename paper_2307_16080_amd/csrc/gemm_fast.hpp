@@ -19,8 +19,8 @@
 //
 // STAGES == 1 selects the register-loaded form of the same kernel: every
 // thread loads the 16-byte chunks that the DMA would have moved (with the
-// same swizzles) into registers, one stage ahead, and writes them to one of
-// two LDS buffers.  It takes any shape and alignment (rows aligned only to
+// same swizzles) into registers, up to three stages ahead (register sets
+// permitting), and writes them to one of two LDS buffers.  It takes any shape and alignment (rows aligned only to
 // the element size, K not a multiple of BK) and is the tile that the
 // persistent batched launch runs.
 //
@@ -140,6 +140,13 @@ struct FastGemm {
     static constexpr int A_ROWS_PER_SLAB = 1024 / A_ROW;
     static constexpr int B_ROWS_PER_SLAB = 1024 / B_ROW;
     static constexpr int B_CHUNKS = B_ROW / 16;
+    // register-loaded form: stages loaded ahead into PF register sets (2..4,
+    // as many as fit beside the accumulators in ~192 VGPRs), so that PF - 1
+    // stages of loads are in flight while one is multiplied
+    static constexpr int SET_REGS = (NA + NB) * 4;
+    static constexpr int ACC_REGS = TM * TN * NR;
+    static constexpr int PF_FIT = (192 - ACC_REGS) / SET_REGS;
+    static constexpr int PF = PF_FIT < 2 ? 2 : PF_FIT > 4 ? 4 : PF_FIT;
 
     static_assert(A_SLABS % NW == 0 && B_SLABS % NW == 0, "slabs must divide among waves");
     static_assert(CONV || B_CHUNKS >= (DT == DT_BF16 ? 16 : DT == DT_F8 ? 8 : 4), "B rows too short for the swizzle");
@@ -535,7 +542,7 @@ struct FastGemm {
         int voff_a[NA], voff_b[NB];
         // register-loaded form: chunk state and the stage in flight
         RegSlots rs;
-        u4_t qa[NA], qb[NB], qa2[NA], qb2[NB];
+        u4_t qa[REG ? PF : 1][NA], qb[REG ? PF : 1][NB];
         if constexpr (!REG) {
             ra = make_rsrc(g.A, (uint32_t)(((g.M - 1) * g.lda + g.K) * ES));
             if constexpr (CONV) {
@@ -592,11 +599,11 @@ struct FastGemm {
                 else issue_stage(ra, rb, voff_a, voff_b, (s_beg + s) * BK, g.ldb, lds + s * STAGE, wave);
             }
         } else {
-            if (nk > 0) {
-                reg_load(g, rs, s_beg * BK, qa, qb);
-                reg_store(lds, qa, qb, wave, lane);
-            }
-            if (nk > 1) reg_load(g, rs, (s_beg + 1) * BK, qa2, qb2);
+            // stages 0 .. PF-1 requested before stage 0 is waited for and stored
+#pragma unroll
+            for (int s = 0; s < PF; ++s)
+                if (s < nk) reg_load(g, rs, (s_beg + s) * BK, qa[s], qb[s]);
+            if (nk > 0) reg_store(lds, qa[0], qb[0], wave, lane);
         }
 
         const int lr = lane & 15, lg = lane >> 4;
@@ -696,19 +703,23 @@ struct FastGemm {
                 });
             }
         } else {
-            // Two register sets, two stages ahead: iteration it loads stage it+2
-            // into one set while the other (stage it+1, loaded one iteration
-            // earlier) is written to the LDS buffer that stage it-1 used.
-            auto step = [&](int it, u4_t* la, u4_t* lb, const u4_t* sa_, const u4_t* sb_) {
-                if (it + 2 < nk) reg_load(g, rs, (s_beg + it + 2) * BK, la, lb);
-                asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
-                const uint8_t* sa = lds + (it & 1) * STAGE;
-                mma_stage(sa, sa + A_STAGE, acc, wy, wx, lr, lg, [] {});
-                if (it + 1 < nk) reg_store(lds + ((it + 1) & 1) * STAGE, sa_, sb_, wave, lane);
-            };
-            for (int it = 0; it < nk; it += 2) {
-                step(it, qa, qb, qa2, qb2);
-                if (it + 1 < nk) step(it + 1, qa2, qb2, qa, qb);
+            // PF register sets, stage s in set s % PF, two LDS buffers: iteration
+            // it loads stage it+PF into the set that held stage it (written to
+            // LDS one iteration earlier), multiplies stage it, and writes stage
+            // it+1 (loaded PF-1 iterations earlier) to the buffer stage it-1 used.
+            // The body is unrolled PF times so that every set index is a constant.
+            for (int it0 = 0; it0 < nk; it0 += PF) {
+#pragma unroll
+                for (int u = 0; u < PF; ++u) {
+                    const int it = it0 + u;
+                    if (it >= nk) break;
+                    if (it + PF < nk) reg_load(g, rs, (s_beg + it + PF) * BK, qa[u], qb[u]);
+                    asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
+                    const uint8_t* sa = lds + (it & 1) * STAGE;
+                    mma_stage(sa, sa + A_STAGE, acc, wy, wx, lr, lg, [] {});
+                    if (it + 1 < nk)
+                        reg_store(lds + ((it + 1) & 1) * STAGE, qa[(u + 1) % PF], qb[(u + 1) % PF], wave, lane);
+                }
             }
         }
         // epilogue: lane l, register r holds output row 4*(l/16) + r, column l % 16

@@ -5,10 +5,14 @@ measured on the GPU; for each held-out layer, a model is trained on the GPU
 (the library's own MLP kernels) on the tables of every OTHER layer (both batch
 sizes of the held-out layer excluded), and the library's model-guided search
 (mlk_tune, MLK_TUNE_MODEL) then tunes each batch variant of the held-out
-layer by timing configurations live.  Its choice is judged on the held-out
-problem's exhaustive table: regret = t(chosen) / t(exhaustive best) - 1,
-with at most ceil(0.2 S) configurations measured, against the library's
-random search at the same budget (replayed on the same table, 21 seeds).
+layer by timing configurations live, with at most ceil(0.2 S) measured; its
+choice is re-timed beside the exhaustive table's best under the same
+conditions (alternating bursts) and must be within 5%.  A live choice judged
+on a table measured at another moment is not (a batch-1 layer's times move
+by tens of percent between bursts), so the comparison with the library's
+random search at the same budget replays both strategies on the same table:
+regret = t(chosen) / t(table best) - 1, the model strategy against the
+median of 21 random seeds.
 """
 import math
 
@@ -91,19 +95,24 @@ def test_model_guided_search_live_on_held_out_layers(measured):
                                     want_times=True)
             assert rep.n_measured <= math.ceil(BUDGET * S - 1e-9), (rep.n_measured, S)
             assert sum(1 for v in seen if v > 0) == rep.n_measured
-            regret = float(t[rep.best_index] / best - 1.0)
+            live_table_regret = float(t[rep.best_index] / best - 1.0)
+            # the model strategy replayed on the table, as random search is below
+            _, rm, _ = mlk.tune(p, mlk.MLK_TUNE_MODEL, budget_frac=BUDGET, model=model, table=list(t))
+            assert rm.n_measured <= math.ceil(BUDGET * S - 1e-9)
+            regret = float(t[rm.best_index] / best - 1.0)
             cfgs = mlk.configs(p)
             paired = paired_regret(p, cfgs[rep.best_index], cfgs[int(np.argmin(np.where(t > 0, t, np.inf)))])
             rand = []
             for s in range(21):
                 _, rr, _ = mlk.tune(p, mlk.MLK_TUNE_RANDOM, budget_frac=BUDGET, seed=100 + s, table=list(t))
                 rand.append(float(t[rr.best_index] / best - 1.0))
-            say(f"  batch {p.n}: S={S} measured {rep.n_measured}, model regret {regret:.4f} on the table, "
-                f"{paired:.4f} re-timed beside the exhaustive best; random median {np.median(rand):.4f}")
+            say(f"  batch {p.n}: S={S} measured {rep.n_measured}; live choice {paired:.4f} re-timed beside the "
+                f"exhaustive best ({live_table_regret:.4f} on the table); replayed on the table: model "
+                f"{regret:.4f}, random median {np.median(rand):.4f}")
             model_r.append(regret)
             random_r.append(float(np.median(rand)))
             # within 5% of the exhaustive best, both timed under the same conditions
-            assert paired <= 0.05, (key, p.n, regret, paired)
+            assert paired <= 0.05, (key, p.n, live_table_regret, paired)
     # what the network gains over the method without it, at the same budget
     assert np.mean(model_r) < np.mean(random_r), (model_r, random_r)
 
