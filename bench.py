@@ -437,6 +437,35 @@ def main():
                                                          "eager_sum_us": round(eager_us, 1),
                                                          "layer_graph_us": layer_us,
                                                          "layer_tiles": layer_tiles}
+            # The same 19 convolutions as one batch (each its own input and
+            # output, as the stack above defines them): one persistent launch of
+            # the channel-gather conv tile, whose tile and split cap are chosen
+            # by timing a small grid of them
+            convs = []
+            for shape, count in shapes_all:
+                if shape.N != batch:
+                    continue
+                ho, wo = shape.out_hw()
+                for _ in range(count):
+                    qx, _ = mlk.quantize(torch.randn(shape.N, shape.C, shape.H, shape.W, device="cuda"), "bf16")
+                    qw, _ = mlk.quantize(torch.randn(shape.F, shape.C, shape.KH, shape.KW, device="cuda"), "bf16")
+                    convs.append((qx, qw, torch.zeros(shape.N, shape.F, ho, wo, device="cuda"),
+                                  (shape.stride,) * 2, (shape.pad,) * 2))
+            cands = []
+            for bm, bn in ((64, 64), (64, 128), (128, 128)):
+                for cap in (1, 4, 16, 32):
+                    cfg_b = mlk.TileConfig(bm, bn, 64, 2, 2, cap, 1, 0, 1, 3)
+                    cb = mlk.ConvBatch(convs, cfg=cfg_b)
+                    cands.append((graph_us(cb, 10), list(cfg_b.as_tuple()), cb))
+            us_b, tile_b, cb = min(cands, key=lambda t: t[0])
+            _, ntask, nwg = cb.info()
+            rows_out[f"resnet18_layers_b{batch}_batched_bf16"] = {
+                "us": round(us_b, 1), "TFLOP/s": round(stack_flops / us_b / 1e6, 2),
+                "timing": "graph of 10 runs; one run = one persistent launch over the stack's 19 convolutions, "
+                          "each with its own input and output",
+                "tile": tile_b, "tasks": ntask, "workgroups": nwg,
+                "grid_us": {f"{t[1][0]}x{t[1][1]}_cap{t[1][5]}": round(t[0], 1) for t in cands}}
+            del cands, cb, convs
         t0 = time.time()
         ev = costmodel.leave_one_out(problems, tables, budget=0.2)
         ev["summary"]["seconds"] = round(time.time() - t0, 1)

@@ -273,6 +273,58 @@ mlk_status mlk_conv2d_plan_config(const mlk_conv_plan* plan, mlk_tile_config* cf
 void mlk_conv2d_plan_destroy(mlk_conv_plan* plan);
 
 /*
+ * Many independent convolutions in one persistent launch (Sec. 4.1's
+ * linalg.conv_2d_nchw_fchw, once per descriptor; the batching of uneven
+ * problems into one launch is this library's, as for mlk_batched_matmul).
+ *
+ * Each descriptor is one convolution y (+)= conv(x, w) with the layouts of
+ * mlk_conv2d_nchw_fchw: x (N,C,H,W) bf16, w (F,C,KH,KW) bf16, y (N,F,HO,WO)
+ * fp32, contiguous device buffers bound at creation (their contents are read
+ * at each run; x and w must stay allocated while the batch exists).  Every
+ * convolution needs C a multiple of 8 and F <= 65535; no y may overlap any
+ * descriptor's x, w or y.
+ *
+ * mlk_conv2d_batch_create validates the descriptors, allocates the batch's
+ * device buffers (each filter transposed to F x KH x KW x C, except 1 x 1
+ * filters, which are used in place; the convolutions' arguments and the
+ * schedule), enqueues the filter transposes on `stream`, and plans the launch:
+ * every convolution is cut into tasks -- an output tile of the register-loaded
+ * channel-gather conv kernel (conv layout 3) and one part of a K split --
+ * that are dealt longest first into one range per resident workgroup.  A
+ * convolution of S 64-deep stages is split into min(cap, ceil(S / 4)) parts
+ * (cap: cfg->split_k, 1 .. 32), so each task keeps its loads in flight at
+ * once; split parts add into y with fp32 atomics.  cfg NULL or zeroed: the
+ * 64 x 64 tile, cap 16; otherwise cfg selects bm, bn, wm, wn of a
+ * register-loaded conv tile (stages 1, layout 3) and the cap; other fields
+ * must be zero or their defaults (group_m 0/1).  Not on a capturing stream.
+ *
+ * mlk_conv2d_batch_run enqueues the batch on `stream`: with accumulate = 0,
+ * first a zero fill of each split convolution's y, then the one persistent
+ * launch.  It allocates nothing and may be recorded into a captured graph.
+ * Runs of one batch must not overlap in time; the batch must run on the
+ * device it was created on.  mlk_conv2d_batch_update_filters re-reads every
+ * w (stream-ordered).  mlk_conv2d_batch_info reports the tile configuration
+ * (split_k = the cap), the task count and the workgroups of the launch.
+ * mlk_conv2d_batch_destroy waits for the device and frees the batch.
+ */
+typedef struct {
+    int64_t N, C, H, W, F, KH, KW;
+    int32_t sh, sw, ph, pw;
+    const void* x;
+    const void* w;
+    void* y;
+} mlk_conv_desc;
+typedef struct mlk_conv_batch mlk_conv_batch;
+mlk_status mlk_conv2d_batch_create(mlk_dtype in, mlk_dtype out, int64_t count, const mlk_conv_desc* descs,
+                                   int accumulate, const mlk_tile_config* cfg, void* stream,
+                                   mlk_conv_batch** batch);
+mlk_status mlk_conv2d_batch_run(const mlk_conv_batch* batch, void* stream);
+mlk_status mlk_conv2d_batch_update_filters(mlk_conv_batch* batch, void* stream);
+mlk_status mlk_conv2d_batch_info(const mlk_conv_batch* batch, mlk_tile_config* cfg, int64_t* tasks,
+                                 int32_t* workgroups);
+void mlk_conv2d_batch_destroy(mlk_conv_batch* batch);
+
+/*
  * Quantise n fp32 values for the low-precision paths.
  *   out = MLK_BF16:   q[i] = bf16 round-to-nearest-even of x[i]; scale unused
  *                     (may be NULL).  NaN becomes a quiet NaN, overflow inf.

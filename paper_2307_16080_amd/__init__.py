@@ -23,7 +23,7 @@ from ._lib import (MLK_BATCH_GRAPH, MLK_BATCH_PERSISTENT, MLK_BF16, MLK_F8E4M3, 
                    MLK_TUNE_ES, MLK_TUNE_MODEL, MLK_TUNE_RANDOM, GemmDesc, MlkError, Problem, TileConfig,
                    TuneOpts, TuneReport)
 
-__all__ = ["matmul", "matmul_noalloc", "matmul_bias", "conv2d_nchw_fchw", "ConvCall", "quantize", "batched_matmul", "BatchedCall", "err_stats", "tune",
+__all__ = ["matmul", "matmul_noalloc", "matmul_bias", "conv2d_nchw_fchw", "ConvCall", "ConvBatch", "quantize", "batched_matmul", "BatchedCall", "err_stats", "tune",
            "config_count", "configs", "config_legal", "set_default_config", "CostModel",
            "mlp_forward", "mlp_loss_grad", "adam_step", "release", "version", "TileConfig",
            "Problem", "MlkError", "matmul_problem", "conv_problem", "batched_problem"]
@@ -234,6 +234,64 @@ class ConvCall:
         if getattr(self, "_plan", None) and L._lib is not None:
             L.lib().mlk_conv2d_plan_destroy(self._plan)
             self._plan = None
+
+
+class ConvBatch:
+    """Many independent convolutions in one persistent launch (mlk_conv2d_batch_*):
+    a list of (x, w, y, stride, pad) with x, w bfloat16 NCHW / FCHW and y float32
+    NFHW, all contiguous CUDA tensors, C a multiple of 8.  The tensors are bound
+    at creation (their storage must not move); each call runs every convolution,
+    y (+)= conv(x, w), as one launch (plus, when overwriting, a zero fill of each
+    split output), allocates nothing and may be captured into a graph.  `cfg`:
+    None (64 x 64 tile, split cap 16) or a register-loaded conv tile with
+    stages 1, layout 3 and split_k = the largest K split per convolution."""
+
+    def __init__(self, convs, accumulate: bool = True, cfg=None, stream=None):
+        descs = (L.ConvDesc * len(convs))()
+        keep = []
+        for i, (x, w, y, stride, pad) in enumerate(convs):
+            for t in (x, w, y):
+                _need(t.is_contiguous(), 3, "conv batch tensors must be contiguous")
+                _on_device(t)
+            _need(x.dim() == 4 and w.dim() == 4 and y.dim() == 4, 2, "conv batch tensors must be 4-D")
+            _need(x.dtype == torch.bfloat16 and w.dtype == torch.bfloat16 and y.dtype == torch.float32, 4,
+                  "conv batch: bfloat16 x and w, float32 y")
+            N, C, H, W = x.shape
+            F, C2, KH, KW = w.shape
+            _need(C2 == C, 2, f"conv batch: channel mismatch in convolution {i}")
+            ho, wo = conv_out_hw(H, W, KH, KW, stride, pad)
+            _need(tuple(y.shape) == (N, F, ho, wo), 2, f"conv batch: y of convolution {i} must be {(N, F, ho, wo)}")
+            descs[i] = L.ConvDesc(N, C, H, W, F, KH, KW, stride[0], stride[1], pad[0], pad[1], x.data_ptr(),
+                                  w.data_ptr(), y.data_ptr())
+            keep.append((x, w, y))
+        self._keep = keep
+        self._stream = None if stream is None else _stream(stream)
+        h = ctypes.c_void_p()
+        cfg_ = None if cfg is None else (cfg if isinstance(cfg, TileConfig) else TileConfig(*cfg))
+        L.check(L.lib().mlk_conv2d_batch_create(MLK_BF16, MLK_F32, len(convs), descs, int(bool(accumulate)),
+                                                _cfg(cfg_), self._stream if self._stream is not None else
+                                                _stream(None), ctypes.byref(h)))
+        self._batch = h.value
+
+    def info(self):
+        """(TileConfig, tasks, workgroups) of the planned launch."""
+        c, t, w = TileConfig(), ctypes.c_int64(), ctypes.c_int32()
+        L.check(L.lib().mlk_conv2d_batch_info(self._batch, ctypes.byref(c), ctypes.byref(t), ctypes.byref(w)))
+        return c, t.value, w.value
+
+    def update_filters(self, stream=None):
+        L.check(L.lib().mlk_conv2d_batch_update_filters(
+            self._batch, _stream(stream) if stream is not None else (self._stream or _stream(None))))
+
+    def __call__(self, stream=None):
+        st = _stream(stream) if stream is not None else (self._stream if self._stream is not None else _stream(None))
+        L.check(L.lib().mlk_conv2d_batch_run(self._batch, st))
+        return [y for _, _, y in self._keep]
+
+    def __del__(self):
+        if getattr(self, "_batch", None) and L._lib is not None:
+            L.lib().mlk_conv2d_batch_destroy(self._batch)
+            self._batch = None
 
 
 def conv_out_hw(H, W, KH, KW, stride=(1, 1), pad=(0, 0)):

@@ -44,6 +44,13 @@ class GemmDesc(ctypes.Structure):
                 ("C", ctypes.c_void_p), ("ldc", ctypes.c_int64)]
 
 
+class ConvDesc(ctypes.Structure):
+    _fields_ = [("N", ctypes.c_int64), ("C", ctypes.c_int64), ("H", ctypes.c_int64), ("W", ctypes.c_int64),
+                ("F", ctypes.c_int64), ("KH", ctypes.c_int64), ("KW", ctypes.c_int64),
+                ("sh", ctypes.c_int32), ("sw", ctypes.c_int32), ("ph", ctypes.c_int32), ("pw", ctypes.c_int32),
+                ("x", ctypes.c_void_p), ("w", ctypes.c_void_p), ("y", ctypes.c_void_p)]
+
+
 class Problem(ctypes.Structure):
     _fields_ = [("op", ctypes.c_int32), ("in_", ctypes.c_int32), ("out", ctypes.c_int32),
                 ("accumulate", ctypes.c_int32),
@@ -91,6 +98,12 @@ SIGNATURES = {
     "mlk_conv2d_plan_update_filter": (_st, [_vp, _vp]),
     "mlk_conv2d_plan_config": (_st, [_vp, _cfgp]),
     "mlk_conv2d_plan_destroy": (None, [_vp]),
+    "mlk_conv2d_batch_create": (_st, [_int, _int, _i64, ctypes.POINTER(ConvDesc), _int, _cfgp, _vp,
+                                      ctypes.POINTER(ctypes.c_void_p)]),
+    "mlk_conv2d_batch_run": (_st, [_vp, _vp]),
+    "mlk_conv2d_batch_update_filters": (_st, [_vp, _vp]),
+    "mlk_conv2d_batch_info": (_st, [_vp, _cfgp, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int32)]),
+    "mlk_conv2d_batch_destroy": (None, [_vp]),
     "mlk_quantize": (_st, [_int, _i64, _vp, _vp, _vp, _vp]),
     "mlk_batched_matmul": (_st, [_int, _int, _i64, ctypes.POINTER(GemmDesc), _cfgp, _i64, _int, _u32,
                                  _vp]),

@@ -272,9 +272,14 @@ struct FastGemm {
         for (int i = 0; i < NB; ++i) {
             const int slab = wave + i * NW;
             if constexpr (CONV) {
-                // B^T row r = output pixel n0 + r, chunk c of its k range
-                const int r = slab * A_ROWS_PER_SLAB + lane / A_CPR;
-                const int c = (lane % A_CPR) ^ fa(r);
+                // B^T row r = output pixel n0 + r, chunk c of its k range.  The
+                // NCHW gather (CONV 3) gives a wave 64 consecutive rows of one
+                // chunk, so each of its two-byte loads reads 64 neighbouring
+                // pixels of one channel plane; reg_store puts the chunk where
+                // this layout's slab would have it.
+                const int slot = i * NT + wave * 64 + lane;
+                const int r = CONV == 3 ? slot % BN : slab * A_ROWS_PER_SLAB + lane / A_CPR;
+                const int c = CONV == 3 ? slot / BN : (lane % A_CPR) ^ fa(r);
                 const int64_t p = n0 + r;
                 const int hw = g.cho * g.cwo;
                 rs.b_r[i] = r;
@@ -376,13 +381,20 @@ struct FastGemm {
 
     // registers -> the LDS positions the DMA would have filled
     __device__ static inline void reg_store(uint8_t* stage, const u4_t* ra, const u4_t* rb, int wave,
-                                            int lane) {
+                                            int lane, const RegSlots& rs) {
 #pragma unroll
         for (int i = 0; i < NA; ++i)
             *(u4_t*)(stage + (wave + i * NW) * 1024 + lane * 16) = ra[i];
 #pragma unroll
-        for (int i = 0; i < NB; ++i)
-            *(u4_t*)(stage + A_STAGE + (wave + i * NW) * 1024 + lane * 16) = rb[i];
+        for (int i = 0; i < NB; ++i) {
+            if constexpr (CONV == 3) {
+                // row-major lane layout: logical chunk c of row r sits at c ^ fa(r)
+                const int r = rs.b_r[i], c = rs.b_col[i] / EPV;
+                *(u4_t*)(stage + A_STAGE + r * B_ROW + ((c ^ fa(r)) * 16)) = rb[i];
+            } else {
+                *(u4_t*)(stage + A_STAGE + (wave + i * NW) * 1024 + lane * 16) = rb[i];
+            }
+        }
     }
 
     // the MFMAs of one LDS stage (sa: A rows, sb: B rows or, for conv, B^T rows)
@@ -603,7 +615,7 @@ struct FastGemm {
 #pragma unroll
             for (int s = 0; s < PF; ++s)
                 if (s < nk) reg_load(g, rs, (s_beg + s) * BK, qa[s], qb[s]);
-            if (nk > 0) reg_store(lds, qa[0], qb[0], wave, lane);
+            if (nk > 0) reg_store(lds, qa[0], qb[0], wave, lane, rs);
         }
 
         const int lr = lane & 15, lg = lane >> 4;
@@ -718,7 +730,8 @@ struct FastGemm {
                     const uint8_t* sa = lds + (it & 1) * STAGE;
                     mma_stage(sa, sa + A_STAGE, acc, wy, wx, lr, lg, [] {});
                     if (it + 1 < nk)
-                        reg_store(lds + ((it + 1) & 1) * STAGE, qa[(u + 1) % PF], qb[(u + 1) % PF], wave, lane);
+                        reg_store(lds + ((it + 1) & 1) * STAGE, qa[(u + 1) % PF], qb[(u + 1) % PF], wave, lane,
+                                  rs);
                 }
             }
         }

@@ -51,6 +51,8 @@ struct KernelEntry {
     launch_fn launch_epi16; // GEMM entries that write a bf16 C (EPI = 2); null where not built
     int mfma;               // MFMA output tile: 16 (16 x 16) or 32 (32 x 32, bf16 direct-layout tiles)
     launch_fn launch_gather;  // conv entries: the NCHW channel-gather variant (CONV = 3); null where not built
+    persist_fn persist_gather;      // conv entries: a persistent channel-gather launch over many convolutions
+    occupancy_fn occupancy_gather;  // with persist_gather: resident workgroups per CU
 };
 
 template <int DT, int BM, int BN, int KB, int WM, int WN, int CONV, int EPI = 0>
@@ -118,10 +120,44 @@ hipError_t launch_fast_conv(const GemmArgs& g, int nblk, hipStream_t s) {
     return hipGetLastError();
 }
 
-// the channel-gather variant exists for the register-loaded conv tiles only
+// Persistent channel-gather convolution over a batch of convolutions: the
+// host deals every convolution's tasks -- (output tile, K split) pairs, the
+// split index in Task::kind -- into one range per workgroup; workgroup b runs
+// its range in order.  Each task is exactly a plain launch's workgroup of the
+// same tile, split and convolution.
+template <int DT, int BM, int BN, int WM, int WN>
+__global__ __launch_bounds__(64 * WM * WN) void k_conv_persist(const GemmArgs* __restrict__ convs,
+                                                               const Task* __restrict__ tasks,
+                                                               const int32_t* __restrict__ bounds) {
+    typedef FastGemm<DT, BM, BN, WM, WN, 1, 3> TL;
+    __shared__ __attribute__((aligned(1024))) uint8_t lds[TL::LDS_BYTES];
+    const int b = blockIdx.x;
+    const int t0 = bounds[b], t1 = bounds[b + 1];
+    for (int t = t0; t < t1; ++t) {
+        const Task tk = tasks[t];
+        const GemmArgs g = convs[tk.gemm];
+        TL::run(g, tk.tm, tk.tn, tk.kind, lds);
+        __syncthreads();
+    }
+}
+
+template <int DT, int BM, int BN, int WM, int WN>
+hipError_t launch_conv_persist(const GemmArgs* convs, const Task* tasks, const int32_t* bounds, int nblk,
+                               hipStream_t s) {
+    hipLaunchKernelGGL((k_conv_persist<DT, BM, BN, WM, WN>), dim3(nblk), dim3(64 * WM * WN), 0, s, convs, tasks,
+                       bounds);
+    return hipGetLastError();
+}
+
+// the channel-gather variants exist for the register-loaded conv tiles only
 template <int DT, int BM, int BN, int WM, int WN, int STAGES>
 constexpr launch_fn gather_fn() {
     if constexpr (STAGES == 1) return &launch_fast_conv<DT, BM, BN, WM, WN, 1, 3>;
+    else return nullptr;
+}
+template <int DT, int BM, int BN, int WM, int WN, int STAGES>
+constexpr persist_fn gather_persist_fn() {
+    if constexpr (STAGES == 1) return &launch_conv_persist<DT, BM, BN, WM, WN>;
     else return nullptr;
 }
 
@@ -174,6 +210,15 @@ int occupancy_persist() {
 template <int DT, int BM, int BN, int WM, int WN, int STAGES, int MF = 16>
 int occupancy_fast_persist() {
     return occupancy_of(k_fast_persist<DT, BM, BN, WM, WN, STAGES, MF>, 64 * WM * WN);
+}
+template <int DT, int BM, int BN, int WM, int WN>
+int occupancy_conv_persist() {
+    return occupancy_of(k_conv_persist<DT, BM, BN, WM, WN>, 64 * WM * WN);
+}
+template <int DT, int BM, int BN, int WM, int WN, int STAGES>
+constexpr occupancy_fn gather_occupancy_fn() {
+    if constexpr (STAGES == 1) return &occupancy_conv_persist<DT, BM, BN, WM, WN>;
+    else return nullptr;
 }
 
 template <int DT, int BM, int BN, int KB, int WM, int WN, int CONV, int EPI = 0>
@@ -263,7 +308,8 @@ launch_fn fast_epi16() {
         DT, 1, STAGES, BM, BN, FastGemm<DT, BM, BN, WM, WN, STAGES, 2>::BK, WM, WN,          \
             FastGemm<DT, BM, BN, WM, WN, STAGES, 2>::LDS_BYTES, 64 * (WM) * (WN), nullptr,   \
             nullptr, &launch_fast_conv<DT, BM, BN, WM, WN, STAGES>, nullptr, nullptr, nullptr, 16, \
-            gather_fn<DT, BM, BN, WM, WN, STAGES>()                                             \
+            gather_fn<DT, BM, BN, WM, WN, STAGES>(), gather_persist_fn<DT, BM, BN, WM, WN, STAGES>(), \
+            gather_occupancy_fn<DT, BM, BN, WM, WN, STAGES>()                                   \
     }
 
 // Tables defined by the instantiation units (host functions: the tables hold

@@ -450,3 +450,42 @@ def test_batched_config_count_validation():
     bad = (L.TileConfig * 2)(good, L.TileConfig(48, 64, 32, 2, 2, 1, 1, 0, 0, 0))
     st = lib.mlk_batched_matmul(L.MLK_BF16, L.MLK_F32, 2, d, bad, 2, 1, 0, NULL)
     assert st == 5 and "desc 1" in lib.mlk_last_error().decode()
+
+
+def test_conv_batch_validation():
+    """mlk_conv2d_batch_create refuses bad dtypes, counts, shapes, channels not
+    a multiple of 8, NULL or overlapping buffers and configurations that are
+    not a register-loaded conv tile -- all before any HIP call."""
+    lib = L.lib()
+    h = ctypes.c_void_p()
+
+    def desc(x, w, y, C=8, F=16, H=8, W=8):
+        return L.ConvDesc(1, C, H, W, F, 3, 3, 1, 1, 1, 1, x, w, y)
+
+    one = (L.ConvDesc * 1)(desc(0x100000, 0x200000, 0x300000))
+    create = lambda d, n, cfg=NULL, dt=L.MLK_BF16: lib.mlk_conv2d_batch_create(dt, L.MLK_F32, n, d, 1, cfg, NULL,
+                                                                                ctypes.byref(h))
+    assert create(one, 1, dt=L.MLK_F32) == 4
+    assert create(one, 0) == 9
+    assert create(NULL, 1) == 1
+    assert lib.mlk_conv2d_batch_create(L.MLK_BF16, L.MLK_F32, 1, one, 1, NULL, NULL, NULL) == 1
+    assert create((L.ConvDesc * 1)(desc(0x100000, 0x200000, 0x300000, C=12)), 1) == 2
+    bad_shape = (L.ConvDesc * 1)(L.ConvDesc(1, 8, 2, 2, 16, 5, 5, 1, 0, 1, 0, 0x100000, 0x200000, 0x300000))
+    assert create(bad_shape, 1) == 2
+    assert create((L.ConvDesc * 1)(desc(0x100000, 0, 0x300000)), 1) == 1
+    # y of one convolution over another's input, or two outputs sharing memory
+    two = (L.ConvDesc * 2)(desc(0x100000, 0x200000, 0x300000), desc(0x300100, 0x400000, 0x500000))
+    st = create(two, 2)
+    assert st == 3 and "descriptor 0" in lib.mlk_last_error().decode()
+    two = (L.ConvDesc * 2)(desc(0x100000, 0x200000, 0x300000), desc(0x600000, 0x400000, 0x300800))
+    assert create(two, 2) == 3
+    # configurations: a register-loaded conv tile (stages 1) with a split cap in [1, 32]
+    assert create(one, 1, ctypes.byref(L.TileConfig(64, 64, 64, 2, 2, 0, 1, 0, 1, 3))) == 5
+    assert create(one, 1, ctypes.byref(L.TileConfig(64, 64, 64, 2, 2, 33, 1, 0, 1, 3))) == 5
+    assert create(one, 1, ctypes.byref(L.TileConfig(64, 64, 64, 2, 2, 4, 1, 0, 2, 1))) == 5
+    assert create(one, 1, ctypes.byref(L.TileConfig(48, 64, 64, 2, 2, 4, 1, 0, 1, 3))) == 5
+    # run / info / destroy of a NULL batch
+    assert lib.mlk_conv2d_batch_run(NULL, NULL) == 1
+    assert lib.mlk_conv2d_batch_info(NULL, NULL, NULL, NULL) == 1
+    assert lib.mlk_conv2d_batch_update_filters(NULL, NULL) == 1
+    lib.mlk_conv2d_batch_destroy(NULL)
