@@ -414,10 +414,16 @@ def main():
                 ho, wo = shape.out_hw()
                 ys = torch.zeros(shape.N, shape.F, ho, wo, device="cuda")
                 # the layer bound once (mlk.ConvCall: a plan whose filter is transposed
-                # once): the exhaustive table's six fastest re-timed as bound calls, in
-                # graphs of 10 calls (no host time), and the fastest kept
+                # once): the exhaustive table's six fastest, and the two fastest of each
+                # conv layout, re-timed as bound calls in graphs of 10 calls (no host
+                # time), and the fastest kept.  The table times unbound calls, in which
+                # the channel gather (layout 3) also transposes a 3 x 3 filter each
+                # time, so its ranking there understates the bound form.
                 cfgs = mlk.configs(p)
-                order = [i for _, i in sorted((v, i) for i, v in enumerate(t) if v > 0)[:6]]
+                ranked = [i for _, i in sorted((v, i) for i, v in enumerate(t) if v > 0)]
+                order = ranked[:6]
+                for lay in sorted({cfgs[i].layout for i in ranked}):
+                    order += [i for i in ranked if cfgs[i].layout == lay and i not in order][:2]
                 cands = [mlk.ConvCall(qx, qw, ys, (shape.stride,) * 2, (shape.pad,) * 2, cfg=cfgs[i])
                          for i in order]
                 us_c = [graph_us(c, 10) for c in cands]

@@ -306,7 +306,7 @@ std::vector<mlk_tile_config> enumerate_configs(const mlk_problem* p, const Shape
     return out;
 }
 
-mlk_tile_config heuristic_config(const Shape& s, int op) {
+mlk_tile_config heuristic_config(const Shape& s, int op, bool conv_gather) {
     const int cus = device_cus();
     // biggest tile (by area, then by fewer waves) that still gives >= one tile per CU
     const KernelEntry* best = nullptr;
@@ -342,6 +342,19 @@ mlk_tile_config heuristic_config(const Shape& s, int op) {
         for (const KernelEntry* d : registry())
             if (is_direct(d) && d->dt == s.dt && d->bm == 16)
                 return mlk_tile_config{d->bm, d->bn, d->bk, 0, 0, 1, 1, 0, 0, 2, 0};
+    }
+    // bf16 convolutions with C a multiple of 8: the 64 x 64 channel-gather
+    // tile (one launch, no input copy, any depth), K split while the device
+    // has fewer than two tiles per CU and each split keeps two stages
+    if (conv_gather && s.conv && s.dt == DT_BF16 && s.conv_c % 8 == 0 && s.M <= 65535 && op == MLK_OP_CONV2D) {
+        for (const KernelEntry* f : registry())
+            if (f->dt == DT_BF16 && f->conv && f->stages == 1 && f->bm == 64 && f->bn == 64 && f->launch_gather) {
+                mlk_tile_config h{64, 64, f->bk, f->wm, f->wn, 1, 1, 0, 1, 3, 0};
+                const int64_t tiles = cdiv(s.M, 64) * cdiv(s.N, 64);
+                const int64_t stages = cdiv(s.K, f->bk);
+                while (h.split_k < 16 && tiles * h.split_k * 2 <= cus && stages >= 2 * 2 * h.split_k) h.split_k *= 2;
+                return h;
+            }
     }
     // channels-last pays a transpose of the input: worth it for large images
     if (s.conv && e->launch_nhwc && s.conv_c % (16 / esize_in(s.dt)) == 0 && s.N >= 16384) c.layout = 1;
@@ -880,6 +893,14 @@ mlk_status mlk_conv2d_nchw_fchw(mlk_dtype in, mlk_dtype out, int64_t N, int64_t 
     mlk_tile_config c;
     st = resolve(p, s, cfg, &c);
     if (st != MLK_OK) return st;
+    if (cfg_is_zero(cfg) && c.layout == 3 && KH * KW != 1) {
+        // the chosen channel gather would transpose the filter into scratch
+        // memory, which a capturing stream cannot take: the plain tile instead
+        hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+        const hipError_t e = hipStreamIsCapturing((hipStream_t)stream, &cs);
+        if (e != hipSuccess) return hip_fail(e, "hipStreamIsCapturing");
+        if (cs != hipStreamCaptureStatusNone) c = heuristic_config(s, p.op, false);
+    }
     if (c.layout == 1 && cfg_is_zero(cfg) &&
         ((uintptr_t)x % 16 != 0 || (uintptr_t)w % 16 != 0 || N > 65535 || F > 65535))
         c.layout = 0;

@@ -611,11 +611,11 @@ struct FastGemm {
                 else issue_stage(ra, rb, voff_a, voff_b, (s_beg + s) * BK, g.ldb, lds + s * STAGE, wave);
             }
         } else {
-            // stages 0 .. PF-1 requested before stage 0 is waited for and stored
+            // stages 0 .. PF-1 requested here; stage 0 is waited for and stored
+            // after C's read below has been issued too
 #pragma unroll
             for (int s = 0; s < PF; ++s)
                 if (s < nk) reg_load(g, rs, (s_beg + s) * BK, qa[s], qb[s]);
-            if (nk > 0) reg_store(lds, qa[0], qb[0], wave, lane, rs);
         }
 
         const int lr = lane & 15, lg = lane >> 4;
@@ -698,6 +698,9 @@ struct FastGemm {
             }
         }
 
+        if constexpr (REG) {
+            if (nk > 0) reg_store(lds, qa[0], qb[0], wave, lane, rs);
+        }
         if constexpr (!REG) {
             for (int it = 0; it < nk; ++it) {
                 // stage `it` has landed once at most (stages issued after it) loads remain

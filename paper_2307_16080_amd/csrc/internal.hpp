@@ -46,7 +46,9 @@ mlk_status shape_of_problem(const mlk_problem* p, Shape* s);
 // the legal configuration space of a problem, in enumeration order
 std::vector<mlk_tile_config> enumerate_configs(const mlk_problem* p, const Shape& s);
 mlk_status check_config(const Shape& s, int op, const mlk_tile_config& c);
-mlk_tile_config heuristic_config(const Shape& s, int op);
+// conv_gather = false leaves out the channel-gather conv tile (whose filter
+// transpose takes scratch memory in an unbound call)
+mlk_tile_config heuristic_config(const Shape& s, int op, bool conv_gather = true);
 std::string problem_key(const mlk_problem* p);
 
 // tuned defaults consulted by launches that pass no configuration

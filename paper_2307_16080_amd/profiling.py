@@ -13,6 +13,7 @@ for the batched workload to run under the profiler.
     python -m paper_2307_16080_amd.profiling resnet <batch> <launches> [graph]
     python -m paper_2307_16080_amd.profiling lastpass <kernel_trace.csv> <dispatches per pass> [passes]
     python -m paper_2307_16080_amd.profiling convf32 <tile> <launches>
+    python -m paper_2307_16080_amd.profiling convbatch <batch> <tile|default> <launches>
 
 `batched` runs the 256 uneven bf16 GEMMs of the benchmark (seeded shapes and
 inputs) as persistent launches, replayed from a hipGraph, with the given tile
@@ -122,7 +123,8 @@ def gemm_summary(root, tile, source_hash, copy_bytes=256 << 20, warmup=5, steps=
     profiler's own MfmaUtil definition: busy cycles / (GRBM_GUI_ACTIVE of one
     XCD x 1024 SIMDs); the CSV's GRBM_GUI_ACTIVE is summed over the 8 XCDs."""
     w = tile.split(",")
-    kname = f"k_gemm_fast<1, {w[0]}, {w[1]}, {w[3]}, {w[4]}, {w[8]}, 0>"
+    mf = 32 if len(w) > 10 and int(w[10]) == 32 else 16
+    kname = f"k_gemm_fast<1, {w[0]}, {w[1]}, {w[3]}, {w[4]}, {w[8]}, 0, {mf}>"
     every = window(f"{root}/t_{tile}/t_kernel_trace.csv", kname, 0, 1 << 30)
     timed = window(f"{root}/t_{tile}/t_kernel_trace.csv", kname, warmup, steps)
     tr = traffic(f"{root}/f_{tile}/f_counter_collection.csv", f"{root}/w_{tile}/w_counter_collection.csv", kname,
@@ -324,6 +326,37 @@ def run_resnet(batch, launches, graph=False):
           flush=True)
 
 
+def run_conv_batch(batch, tile, launches):
+    """The ResNet-18 stack's 19 convolutions (bf16, seeded inputs, each its own
+    input and output) as one mlk.ConvBatch with the given configuration
+    (eleven comma-separated fields, or "default"), run `launches` times."""
+    import os
+
+    import torch
+
+    sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+    import paper_2307_16080_amd as mlk
+    from workloads import resnet18_conv_stack
+
+    torch.manual_seed(0)
+    convs = []
+    for shape, count in resnet18_conv_stack(batch):
+        ho, wo = shape.out_hw()
+        for _ in range(count):
+            qx, _ = mlk.quantize(torch.randn(shape.N, shape.C, shape.H, shape.W, device="cuda"), "bf16")
+            qw, _ = mlk.quantize(torch.randn(shape.F, shape.C, shape.KH, shape.KW, device="cuda"), "bf16")
+            convs.append((qx, qw, torch.zeros(shape.N, shape.F, ho, wo, device="cuda"), (shape.stride,) * 2,
+                          (shape.pad,) * 2))
+    cfg = None if tile == "default" else mlk.TileConfig(*[int(v) for v in tile.split(",")])
+    cb = mlk.ConvBatch(convs, cfg=cfg)
+    for _ in range(launches):
+        cb()
+    torch.cuda.synchronize()
+    c, tasks, wgs = cb.info()
+    print(f"conv batch b{batch}: {launches} runs, {list(c.as_tuple())}, {tasks} tasks on {wgs} workgroups",
+          flush=True)
+
+
 if __name__ == "__main__":
     if sys.argv[1] == "gemm":
         run_gemm(sys.argv[2], sys.argv[3], int(sys.argv[4]), *(int(v) for v in sys.argv[5:6]))
@@ -331,6 +364,8 @@ if __name__ == "__main__":
         run_conv_f32(sys.argv[2], int(sys.argv[3]))
     elif sys.argv[1] == "resnet":
         run_resnet(int(sys.argv[2]), int(sys.argv[3]), len(sys.argv) > 4 and sys.argv[4] == "graph")
+    elif sys.argv[1] == "convbatch":
+        run_conv_batch(int(sys.argv[2]), sys.argv[3], int(sys.argv[4]))
     elif sys.argv[1] == "batched":
         run_batched(sys.argv[2], int(sys.argv[3]))
     elif sys.argv[1] == "paperconv":

@@ -259,6 +259,11 @@ def test_workspace_routes_refused_under_capture():
             mlk.conv2d_nchw_fchw(x, w, y, (1, 1), (1, 1), cfg=mlk.TileConfig(128, 128, 64, 2, 2, 1, 1, 0, 1, 1))
         with pytest.raises(mlk.MlkError, match="CONFIG"):
             mlk.matmul(A, B, C, cfg=mlk.TileConfig(128, 128, 64, 2, 2, 1, 1, 0, 2, 0))
+        # the channel gather transposes a 3 x 3 filter into scratch memory
+        with pytest.raises(mlk.MlkError, match="CONFIG"):
+            mlk.conv2d_nchw_fchw(x, w, y, (1, 1), (1, 1), cfg=mlk.TileConfig(64, 64, 64, 2, 2, 1, 1, 0, 1, 3))
+        # a defaulted conv whose default is the channel gather takes the plain tile instead
+        mlk.conv2d_nchw_fchw(x, w, y, (1, 1), (1, 1))
     del graph
     torch.cuda.synchronize()
 
