@@ -16,6 +16,7 @@ reference kernel for HBM byte counters.
 """
 import argparse
 import hashlib
+import re
 import json
 import os
 import sys
@@ -45,11 +46,17 @@ KERNEL_SOURCES = ["gemm_fast.hpp", "gemm_tile.hpp", "kernels.hpp", "k_fast.hip"]
 
 
 def source_hash():
+    """Hash of the kernel sources' code: comments removed and runs of white
+    space folded, so that editing a comment keeps the hash of profiled code."""
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2307_16080_amd", "csrc")
     for name in KERNEL_SOURCES:
-        with open(os.path.join(csrc, name), "rb") as f:
-            h.update(name.encode() + f.read())
+        with open(os.path.join(csrc, name)) as f:
+            text = f.read()
+        text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+        text = re.sub(r"//[^\n]*", " ", text)
+        text = re.sub(r"\s+", " ", text).strip()
+        h.update(name.encode() + text.encode())
     return h.hexdigest()[:16]
 
 

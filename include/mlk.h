@@ -121,9 +121,9 @@ typedef enum {
  *              bk = 1, wm = wn = 0, split_k = 1, and it needs F <= 16,
  *              strides <= 2 and filters up to 7 x 7.  Must be 0 for matmul.
  *   mfma       output tile of one MFMA instruction: 0 or 16 (16 x 16, every
- *              kernel), 32 (32 x 32 x 16 bf16: twice the flops per operand
- *              byte read from LDS; direct-layout bf16 matmul tiles, fp32 or
- *              bias outputs).
+ *              kernel), 32 (32 x 32 x 16 bf16: twice the flops per MFMA
+ *              instruction, half the instructions; direct-layout bf16 matmul
+ *              tiles, fp32 or bias outputs).
  * A zeroed struct or a NULL pointer means "choose": the tuning database
  * entry for this problem if one was loaded, else a built-in heuristic.
  */

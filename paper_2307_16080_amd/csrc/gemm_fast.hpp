@@ -96,9 +96,10 @@ __device__ inline int fa(int r) { return (r & 7) ^ ((r >> 2) & 2); }
 // an fp32 C; 2 writes a bf16 C (bias optional).  Each is its own instantiation,
 // so no kernel carries a branch between them.
 // MF: the MFMA tile, 16 (16x16 outputs per instruction; every dtype) or 32
-// (bf16 v_mfma_f32_32x32x16_bf16: twice the flops per operand byte a lane
-// reads from LDS, 16 accumulators per lane per tile; GEMM policy, fp32 or
-// bias output stages).
+// (bf16 v_mfma_f32_32x32x16_bf16: twice the flops per instruction, so half
+// the MFMA and LDS read instructions -- the LDS bytes per k a wave reads are
+// set by its tile, not the MFMA shape -- and 16 accumulators per lane per
+// tile; GEMM policy, fp32 or bias output stages).
 template <int DT, int BM, int BN, int WM, int WN, int STAGES, int CONV = 0, int EPI = 0, int MF = 16>
 struct FastGemm {
     static_assert(DT == DT_BF16 || DT == DT_F8 || DT == DT_I8, "direct-layout kernel: bf16, e4m3 or int8");

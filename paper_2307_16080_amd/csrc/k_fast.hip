@@ -16,7 +16,7 @@ const KernelEntry* kernels_fast(int* n) {
         // operands loaded through registers: any shape and alignment, persistent batches
         MLK_ENTRY_FAST(DT_BF16, 128, 128, 2, 2, 1),
         MLK_ENTRY_FAST(DT_BF16, 256, 128, 2, 2, 1),
-        // 32 x 32 MFMA tiles (half the LDS operand bytes per flop)
+        // 32 x 32 MFMA tiles (half the MFMA and LDS read instructions)
         MLK_ENTRY_FAST32(256, 256, 2, 4, 2),
         MLK_ENTRY_FAST32(256, 256, 4, 2, 2),
         MLK_ENTRY_FAST32(256, 256, 2, 2, 2),

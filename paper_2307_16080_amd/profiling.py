@@ -280,8 +280,9 @@ def run_conv_f32(tile, launches):
 
 def run_resnet(batch, launches, graph=False):
     """The ResNet-18 conv stack (bf16, seeded inputs) at one batch size: each
-    layer shape tuned exhaustively (as the benchmark does), then every layer of
-    the stack launched `launches` times in stack order with its tuned tile;
+    layer's tile picked as the benchmark picks it (exhaustive table, then its
+    fastest entries re-timed as bound calls in graphs), then every layer of
+    the stack launched `launches` times in stack order with that tile;
     with `graph`, the stack is captured once as one graph and the graph is
     replayed `launches` times (the benchmark's timing of the stack)."""
     import os
@@ -293,18 +294,44 @@ def run_resnet(batch, launches, graph=False):
     from paper_2307_16080_amd import _lib as L
     from workloads import resnet18_conv_stack
 
+    def graph_us(fn, n=10, replays=10):
+        fn()
+        torch.cuda.synchronize()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            for _ in range(n):
+                fn()
+        g.replay()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(replays):
+            g.replay()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) * 1e3 / (n * replays)
+
     calls = []
     for shape, count in resnet18_conv_stack(batch):
         p = mlk.conv_problem(shape.N, shape.C, shape.H, shape.W, shape.F, shape.KH, shape.KW, shape.stride,
                              shape.pad, L.MLK_BF16, L.MLK_F32)
-        best, _, _ = mlk.tune(p, mlk.MLK_TUNE_EXHAUSTIVE, reps=3, warmup=1)
+        _, _, t = mlk.tune(p, mlk.MLK_TUNE_EXHAUSTIVE, reps=3, warmup=1, want_times=True)
         qx, _ = mlk.quantize(torch.randn(shape.N, shape.C, shape.H, shape.W, device="cuda"), "bf16")
         qw, _ = mlk.quantize(torch.randn(shape.F, shape.C, shape.KH, shape.KW, device="cuda"), "bf16")
         ho, wo = shape.out_hw()
         y = torch.zeros(shape.N, shape.F, ho, wo, device="cuda")
-        call = mlk.ConvCall(qx, qw, y, (shape.stride,) * 2, (shape.pad,) * 2, cfg=best)
-        calls += [call] * count
-        print(f"layer {shape}: tile {list(best.as_tuple())}", flush=True)
+        # as the benchmark picks: the table's six fastest and the two fastest of
+        # each conv layout, re-timed as bound calls in graphs
+        cfgs = mlk.configs(p)
+        ranked = [i for _, i in sorted((v, i) for i, v in enumerate(t) if v > 0)]
+        order = ranked[:6]
+        for lay in sorted({cfgs[i].layout for i in ranked}):
+            order += [i for i in ranked if cfgs[i].layout == lay and i not in order][:2]
+        cands = [mlk.ConvCall(qx, qw, y, (shape.stride,) * 2, (shape.pad,) * 2, cfg=cfgs[i]) for i in order]
+        us = [graph_us(c) for c in cands]
+        k = min(range(len(us)), key=lambda j: us[j])
+        calls += [cands[k]] * count
+        print(f"layer {shape}: tile {list(cfgs[order[k]].as_tuple())} {us[k]:.2f} us", flush=True)
     torch.cuda.synchronize()
     if graph:
         for call in calls:      # first runs (plan set-up) outside the capture

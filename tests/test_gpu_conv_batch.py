@@ -7,7 +7,8 @@ within 1e-5 normwise of the double result.  Cases: the ResNet-18 conv stack
 at batch 1 (19 convolutions, each its own input, as the benchmark's stack),
 ragged shapes (strides, padding, F and pixel counts that cut tiles, 1 x 1 and
 5 x 5 filters), overwrite and accumulate, every persistent tile with split
-caps 1 and 16, replays of a captured graph of the batch, and a filter update.
+caps 1 and 16, replays of a captured graph of the batch, a filter update, and
+the batch-32 stack in the benchmark's configuration on sampled images.
 """
 import numpy as np
 import pytest
@@ -135,3 +136,33 @@ def test_conv_batch_graph_replays_and_filter_update():
     torch.cuda.synchronize()
     for i, (y, ref) in enumerate(zip(ys, refs)):
         assert np.array_equal(host(y).astype(np.float64), -ref), i
+
+
+def test_conv_batch_resnet18_b32_sampled_images():
+    """The b32 stack's 19 convolutions as one batch, in the configuration the
+    benchmark times at batch 32 (64 x 64 tile, no split) and the default one:
+    images 0 and 31 of every output against the oracle on those images alone
+    (a convolution treats each image on its own), small integers exact, and
+    every output finite."""
+    cases = []
+    for shape, count in resnet18_conv_stack(32):
+        cases += [(shape.N, shape.C, shape.H, shape.W, shape.F, shape.KH, shape.KW, shape.stride, shape.pad)] * count
+    ops = []
+    for i, (N, C, H, W, F, KH, KW, s, p) in enumerate(cases):
+        rng = np.random.default_rng(40 + i)
+        x = rng.integers(-4, 5, (N, C, H, W)).astype(np.float32)
+        w = rng.integers(-4, 5, (F, C, KH, KW)).astype(np.float32)
+        ho, wo = (H + 2 * p - KH) // s + 1, (W + 2 * p - KW) // s + 1
+        ops.append(dict(x=from_bf16_codes(oracle.bf16_encode(x)), w=from_bf16_codes(oracle.bf16_encode(w)),
+                        xs=x[[0, N - 1]], wv=w, shape=(N, F, ho, wo), stride=(s, s), pad=(p, p)))
+    refs = [oracle.conv2d_f64(o["xs"], o["wv"], o["stride"], o["pad"], threads=8) for o in ops]
+    for cfg in (mlk.TileConfig(64, 64, 64, 2, 2, 1, 1, 0, 1, 3), None):
+        say("conv batch resnet18 b32", cfg)
+        ys = [torch.full(o["shape"], float("nan"), device="cuda") for o in ops]
+        batch = mlk.ConvBatch([(o["x"], o["w"], y, o["stride"], o["pad"]) for o, y in zip(ops, ys)],
+                              accumulate=False, cfg=cfg)
+        batch()
+        for i, (y, ref) in enumerate(zip(ys, refs)):
+            assert torch.isfinite(y).all().item(), i
+            got = host(y[[0, y.shape[0] - 1]]).astype(np.float64)
+            assert np.array_equal(got, ref), (i, cfg)
