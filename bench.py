@@ -241,6 +241,19 @@ def main():
     # ---------------------------------------------------------------- other rows
     rows_out = {}
     if not args.quick:
+        # the matrix cores' sustained rate (mlk_mfma_rate: back-to-back MFMAs on
+        # register operands over the whole device, ~100 us per launch), beside
+        # the datasheet peak, and the headline GEMM's fraction of it
+        mr = {}
+        for dt, iters in (("bf16", 1024), ("e4m3", 512)):
+            for _ in range(10):
+                fl, _ = mlk.mfma_rate(dt, iters)
+            us = time_us(lambda: mlk.mfma_rate(dt, iters), 20)
+            tf = fl / us / 1e6
+            mr[dt] = {"TFLOP/s": round(tf, 1), "frac_datasheet_peak": round(tf / PEAK[dt if dt == "bf16" else "fp8"], 3),
+                      "us_per_launch": round(us, 1)}
+        mr["bf16"]["headline_frac_of_measured"] = round(achieved / mr["bf16"]["TFLOP/s"], 3)
+        rows_out["mfma_rate_measured"] = mr
         # fp32 plain kernel at the same size (the comparator)
         pf = mlk.matmul_problem(M, N, K, L.MLK_F32, L.MLK_F32)
         bf, _, _ = mlk.tune(pf, mlk.MLK_TUNE_EXHAUSTIVE, reps=3, warmup=1)
@@ -263,6 +276,7 @@ def main():
         outputs["e4m3"] = C.cpu().numpy()
         rows_out["matmul_e4m3_4096"] = {"us": round(us, 1), "TFLOP/s": round(flops / us / 1e6, 1),
                                         "frac_peak": round(flops / us / 1e6 / PEAK["fp8"], 3), "tile": list(b8.as_tuple())}
+        mr["e4m3"]["gemm_frac_of_measured"] = round(flops / us / 1e6 / mr["e4m3"]["TFLOP/s"], 3)
         # Linear: the same product with the bias add fused into its output stage
         # (C = A B + bias), beside the plain product in overwrite mode (C = A B),
         # both in the timed tile: the difference is the cost of the fusion

@@ -325,6 +325,20 @@ mlk_status mlk_conv2d_batch_info(const mlk_conv_batch* batch, mlk_tile_config* c
 void mlk_conv2d_batch_destroy(mlk_conv_batch* batch);
 
 /*
+ * The matrix cores' sustained rate, to set beside the datasheet peak (the
+ * measured ceiling that a GEMM's roofline fraction can be read against): one
+ * launch of 2 x CUs workgroups of four waves, each wave running `iters` steps
+ * of eight independent 16x16x32 bf16 (in = MLK_BF16) or 16x16x128 e4m3
+ * (MLK_F8E4M3) MFMAs on register operands, with no memory traffic in the
+ * loop.  *flops receives the launch's flop count (the caller times the
+ * launch, e.g. with events on `stream`).  Every operand is 1.0 and chain c
+ * starts at c, so wave w writes out[w] = 28 + 8 * iters * k exactly (k = 32
+ * bf16, 128 e4m3).  out: device
+ * buffer of out_len >= 8 * CUs floats; iters in [1, 16384].
+ */
+mlk_status mlk_mfma_rate(mlk_dtype in, int64_t iters, float* out, int64_t out_len, int64_t* flops, void* stream);
+
+/*
  * Quantise n fp32 values for the low-precision paths.
  *   out = MLK_BF16:   q[i] = bf16 round-to-nearest-even of x[i]; scale unused
  *                     (may be NULL).  NaN becomes a quiet NaN, overflow inf.

@@ -24,7 +24,7 @@ from ._lib import (MLK_BATCH_GRAPH, MLK_BATCH_PERSISTENT, MLK_BF16, MLK_F8E4M3, 
                    TuneOpts, TuneReport)
 
 __all__ = ["matmul", "matmul_noalloc", "matmul_bias", "conv2d_nchw_fchw", "ConvCall", "ConvBatch", "quantize", "batched_matmul", "BatchedCall", "err_stats", "tune",
-           "config_count", "configs", "config_legal", "set_default_config", "CostModel",
+           "config_count", "configs", "config_legal", "mfma_rate", "set_default_config", "CostModel",
            "mlp_forward", "mlp_loss_grad", "adam_step", "release", "version", "TileConfig",
            "Problem", "MlkError", "matmul_problem", "conv_problem", "batched_problem"]
 
@@ -292,6 +292,17 @@ class ConvBatch:
         if getattr(self, "_batch", None) and L._lib is not None:
             L.lib().mlk_conv2d_batch_destroy(self._batch)
             self._batch = None
+
+
+def mfma_rate(dtype="bf16", iters=4096, stream=None):
+    """Launch the MFMA rate probe once (mlk_mfma_rate): returns (flops of the
+    launch, the per-wave float32 results, each exactly 28 + 8 * iters * k)."""
+    props = torch.cuda.get_device_properties(torch.cuda.current_device())
+    out = torch.empty(8 * props.multi_processor_count, dtype=torch.float32, device="cuda")
+    flops = ctypes.c_int64()
+    L.check(L.lib().mlk_mfma_rate({"bf16": MLK_BF16, "e4m3": MLK_F8E4M3}[dtype], int(iters), _ptr(out), out.numel(),
+                                  ctypes.byref(flops), _stream(stream)))
+    return flops.value, out
 
 
 def conv_out_hw(H, W, KH, KW, stride=(1, 1), pad=(0, 0)):

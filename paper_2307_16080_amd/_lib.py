@@ -104,6 +104,7 @@ SIGNATURES = {
     "mlk_conv2d_batch_update_filters": (_st, [_vp, _vp]),
     "mlk_conv2d_batch_info": (_st, [_vp, _cfgp, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int32)]),
     "mlk_conv2d_batch_destroy": (None, [_vp]),
+    "mlk_mfma_rate": (_st, [_int, _i64, _vp, _i64, ctypes.POINTER(ctypes.c_int64), _vp]),
     "mlk_quantize": (_st, [_int, _i64, _vp, _vp, _vp, _vp]),
     "mlk_batched_matmul": (_st, [_int, _int, _i64, ctypes.POINTER(GemmDesc), _cfgp, _i64, _int, _u32,
                                  _vp]),

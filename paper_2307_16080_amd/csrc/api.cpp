@@ -1063,6 +1063,22 @@ void mlk_conv2d_plan_destroy(mlk_conv_plan* plan) {
     delete plan;
 }
 
+mlk_status mlk_mfma_rate(mlk_dtype in, int64_t iters, float* out, int64_t out_len, int64_t* flops, void* stream) {
+    clear_error();
+    if (in != MLK_BF16 && in != MLK_F8E4M3) return fail(MLK_ERR_DTYPE, "mfma_rate: MLK_BF16 or MLK_F8E4M3");
+    if (iters < 1 || iters > 16384) return fail(MLK_ERR_ARG, "mfma_rate: iters must be in [1, 16384]");
+    if (!out || !flops) return fail(MLK_ERR_NULL, "mfma_rate: out or flops is NULL");
+    if (out_len < 1) return fail(MLK_ERR_SHAPE, "mfma_rate: out_len must be >= 1");
+    const int blocks = 2 * device_cus();
+    const int64_t waves = (int64_t)blocks * 4;
+    if (out_len < waves)
+        return fail(MLK_ERR_SHAPE, "mfma_rate: out holds %lld floats, the launch writes %lld", (long long)out_len,
+                    (long long)waves);
+    *flops = waves * iters * 8 * (in == MLK_BF16 ? 2LL * 16 * 16 * 32 : 2LL * 16 * 16 * 128);
+    const hipError_t e = launch_mfma_rate(in == MLK_BF16 ? DT_BF16 : DT_F8, iters, blocks, out, (hipStream_t)stream);
+    return e == hipSuccess ? MLK_OK : hip_fail(e, "mfma_rate launch");
+}
+
 mlk_status mlk_quantize(mlk_dtype out, int64_t n, const float* x, void* q, float* scale,
                         void* stream) {
     clear_error();

@@ -77,6 +77,10 @@ mlk_status launch_conv(const Shape& s, int64_t n, int64_t c, int64_t h, int64_t 
 
 int64_t conv_out(int64_t in, int64_t k, int64_t stride, int64_t pad);
 
+// the MFMA rate probe (probe.hip): `blocks` workgroups of four waves, each
+// wave `iters` steps of eight independent MFMAs (dt DT_BF16 or DT_F8)
+hipError_t launch_mfma_rate(int dt, int64_t iters, int blocks, float* out, hipStream_t s);
+
 // One use of the library's scratch memory (scratch.cpp).  begin() returns
 // with the device's buffer (at least `bytes`) locked for this call and the
 // stream ordered after the buffer's previous use; end(), or the destructor,

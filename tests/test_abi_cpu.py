@@ -489,3 +489,19 @@ def test_conv_batch_validation():
     assert lib.mlk_conv2d_batch_info(NULL, NULL, NULL, NULL) == 1
     assert lib.mlk_conv2d_batch_update_filters(NULL, NULL) == 1
     lib.mlk_conv2d_batch_destroy(NULL)
+
+
+def test_mfma_rate_validation():
+    """mlk_mfma_rate refuses other dtypes, iteration counts outside [1, 16384],
+    NULL pointers and an output buffer shorter than the launch writes, before
+    launching anything."""
+    lib = L.lib()
+    fl = ctypes.c_int64()
+    buf = 0x100000
+    assert lib.mlk_mfma_rate(L.MLK_F32, 16, buf, 1 << 20, ctypes.byref(fl), NULL) == 4
+    assert lib.mlk_mfma_rate(L.MLK_BF16, 0, buf, 1 << 20, ctypes.byref(fl), NULL) == 9
+    assert lib.mlk_mfma_rate(L.MLK_BF16, 16385, buf, 1 << 20, ctypes.byref(fl), NULL) == 9
+    assert lib.mlk_mfma_rate(L.MLK_BF16, 16, NULL, 1 << 20, ctypes.byref(fl), NULL) == 1
+    assert lib.mlk_mfma_rate(L.MLK_F8E4M3, 16, buf, 1 << 20, NULL, NULL) == 1
+    assert lib.mlk_mfma_rate(L.MLK_BF16, 16, buf, 0, ctypes.byref(fl), NULL) == 2
+    assert lib.mlk_mfma_rate(L.MLK_BF16, 16, buf, 8, ctypes.byref(fl), NULL) == 2   # fewer than one per wave

@@ -364,18 +364,24 @@ def test_conv_plan_every_config(case):
         assert normwise(host(y1), 2.0 * ref) <= 1e-5, cfg
         assert normwise(host(y2), 2.0 * ref) <= 1e-5, cfg
     # the bound filter: changed values reach the plan only through update_filter
-    call = mlk.ConvCall(qx, qw, y1, (s, s), (p, p), cfg=mlk.configs(prob)[-1])
-    w_saved = qw.clone()
-    qw.zero_()
-    y1.zero_()
-    call.update_filter()
-    call()
-    assert torch.count_nonzero(y1).item() == 0
-    qw.copy_(w_saved)
-    call.update_filter()
-    y1.zero_()
-    call()
-    assert normwise(host(y1), ref) <= 1e-5
+    # (one configuration of each layout: the channels-last and channel-gather
+    # plans hold a transposed copy of a filter larger than 1 x 1)
+    firsts = {}
+    for c in mlk.configs(prob):
+        firsts.setdefault(c.layout, c)
+    for cfg in firsts.values():
+        call = mlk.ConvCall(qx, qw, y1, (s, s), (p, p), cfg=cfg)
+        w_saved = qw.clone()
+        qw.zero_()
+        y1.zero_()
+        call.update_filter()
+        call()
+        assert torch.count_nonzero(y1).item() == 0, cfg
+        qw.copy_(w_saved)
+        call.update_filter()
+        y1.zero_()
+        call()
+        assert normwise(host(y1), ref) <= 1e-5, cfg
 
 
 
