@@ -294,6 +294,17 @@ def main():
                                         "matmul_overwrite_us": round(us_ow, 1),
                                         "bf16_output_us": round(us_lin16, 1), "tile": list(best.as_tuple()),
                                         "bf16_output_tile": list(t16.as_tuple())}
+        # context, not a target: the vendor library (hipBLASLt through torch.matmul)
+        # on the same bf16 operands, bf16 output, same box; beside it this
+        # library's plain product with a bf16 output, same tile as above
+        Y16 = torch.empty(M, N, dtype=torch.bfloat16, device="cuda")
+        us_lib16 = time_us(lambda: mlk.matmul(qa, qb, Y16, accumulate=False, cfg=t16), 20)
+        us_torch = time_us(lambda: torch.matmul(qa, qb, out=Y16), 20)
+        del Y16
+        rows_out["context_vendor_gemm_bf16_out"] = {
+            "torch_matmul_us": round(us_torch, 1), "torch_matmul_TFLOP/s": round(flops / us_torch / 1e6, 1),
+            "this_library_us": round(us_lib16, 1), "this_library_TFLOP/s": round(flops / us_lib16 / 1e6, 1),
+            "note": "C = A B with a bf16 output (no accumulation into C): the same operands as the headline"}
         # quantisation (HBM-bound)
         us_q16 = time_us(lambda: mlk.quantize(Ad, "bf16", q=qa), 20)
         us_q8 = time_us(lambda: mlk.quantize(Ad, "e4m3", q=qa8, scale=sa), 20)

@@ -202,6 +202,7 @@ mlk_status mlk_conv2d_batch_create(mlk_dtype in, mlk_dtype out, int64_t count, c
         const int64_t per = cdiv64(stages, sk);
         for (int kz = 0; kz < sk; ++kz) {
             const int64_t part = std::max<int64_t>(0, std::min<int64_t>(stages, (kz + 1) * per) - kz * per);
+            if (part == 0) continue;  // e.g. 25 stages in 6 parts of 5: the last part has nothing to add
             for (int32_t tm = 0; tm < g.tiles_m; ++tm)
                 for (int32_t tn = 0; tn < g.tiles_n; ++tn)
                     all.push_back(T{(double)(part + 2), Task{(int32_t)i, tm, tn, kz}});

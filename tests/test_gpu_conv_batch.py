@@ -99,6 +99,22 @@ def test_conv_batch_resnet18_b1_default():
     _run_and_check(_make(cases, "normal", seed=22), True, None, exact=False)
 
 
+def test_conv_batch_resnet18_b1_benchmark_grid():
+    """Every configuration the benchmark times the b1 batch in (64 x 64, 64 x 128
+    and 128 x 128 tiles, split caps 1, 4, 16, 32), exact on small integers."""
+    ops = _make(_resnet_b1(), "small_int", seed=23)
+    refs = [oracle.conv2d_f64(o["xv"], o["wv"], o["stride"], o["pad"], threads=8) for o in ops]
+    for bm, bn in ((64, 64), (64, 128), (128, 128)):
+        for cap in (1, 4, 16, 32):
+            cfg = mlk.TileConfig(bm, bn, 64, 2, 2, cap, 1, 0, 1, 3)
+            ys = [torch.full(o["y0"].shape, float("nan"), device="cuda") for o in ops]
+            batch = mlk.ConvBatch([(o["x"], o["w"], y, o["stride"], o["pad"]) for o, y in zip(ops, ys)],
+                                  accumulate=False, cfg=cfg)
+            batch()
+            for i, (y, ref) in enumerate(zip(ys, refs)):
+                assert np.array_equal(host(y).astype(np.float64), ref), (cfg, i)
+
+
 def test_conv_batch_graph_replays_and_filter_update():
     """The batch captured into a graph (zero fills and persistent launch),
     replayed three times with eager work between replays: each replay equals

@@ -179,6 +179,32 @@ def test_resnet18_b32_every_config():
         assert e <= 1e-5, (shape, _tag(best), e)
 
 
+def test_resnet18_b1_every_config_bound():
+    """Every legal configuration of every batch-1 ResNet-18 layer, bound as the
+    benchmark's stack binds it (mlk.ConvCall), against the oracle on the whole
+    output."""
+    total = 0
+    for li, (shape, _count) in enumerate(resnet18_conv_stack(1)):
+        x, w = conv_inputs(shape.N, shape.C, shape.H, shape.W, shape.F, shape.KH, shape.KW, seed=70 + li)
+        ox, ow = oracle.bf16_encode(x), oracle.bf16_encode(w)
+        ref = oracle.conv2d_f64(oracle.bf16_decode(ox), oracle.bf16_decode(ow), (shape.stride,) * 2,
+                                (shape.pad,) * 2, threads=oracle.default_threads())
+        qx, qw = from_bf16_codes(ox), from_bf16_codes(ow)
+        ho, wo = shape.out_hw()
+        y = torch.empty(shape.N, shape.F, ho, wo, device="cuda")
+        p = mlk.conv_problem(shape.N, shape.C, shape.H, shape.W, shape.F, shape.KH, shape.KW,
+                             shape.stride, shape.pad, L.MLK_BF16, L.MLK_F32)
+        cfgs = mlk.configs(p)
+        say("layer", shape, len(cfgs), "configurations, bound")
+        for c in cfgs:
+            y.zero_()
+            mlk.ConvCall(qx, qw, y, (shape.stride,) * 2, (shape.pad,) * 2, cfg=c)()
+            e = normwise(host(y), ref)
+            assert e <= 1e-5, (shape, _tag(c), e)
+        total += len(cfgs)
+    say("b1 stack:", total, "bound configurations")
+
+
 def test_batched_256_every_config_all_gemms():
     shapes = batched_shapes(256, seed=0)
     ins = batched_inputs(shapes, seed=1)
