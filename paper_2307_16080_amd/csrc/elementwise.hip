@@ -163,6 +163,33 @@ __device__ inline uint32_t e4m3_of_quotient(float x, float s, float r, bool fast
     return e4m3_rne_sat(__fdiv_rn(x, s));
 }
 
+// y = x * RN(1/s) is safe to encode in place of RN(x / s) (see e4m3_of_quotient):
+// a normal e4m3 input at least 5 ulps from a rounding step
+__device__ inline bool e4m3_safe(float y) {
+    const uint32_t mag = __float_as_uint(y) & 0x7FFFFFFFu;
+    const uint32_t rest = mag & 0xFFFFFu;
+    const uint32_t d = rest > 0x80000u ? rest - 0x80000u : 0x80000u - rest;
+    return mag >= 0x3C800000u && mag < 0x43E00000u && d > 4u;
+}
+
+// Four codes packed in a word.  When all four products are safe, the gfx950
+// packed conversion v_cvt_pk_fp8_f32 (round to nearest even into OCP e4m3)
+// encodes them, two per instruction: it gives e4m3_rne_sat's code for every
+// fp32 value below 464 in magnitude (checked on the GPU over all 2,278,555,648 such
+// bit patterns of both signs), and safe products lie below 448.  Otherwise
+// each value takes e4m3_of_quotient.
+__device__ inline uint32_t e4m3_encode4(const f4_t& a, float s, float r, bool fast) {
+    if (fast) {
+        const float y0 = a[0] * r, y1 = a[1] * r, y2 = a[2] * r, y3 = a[3] * r;
+        if (e4m3_safe(y0) && e4m3_safe(y1) && e4m3_safe(y2) && e4m3_safe(y3)) {
+            const int lo = __builtin_amdgcn_cvt_pk_fp8_f32(y0, y1, 0, false);
+            return (uint32_t)__builtin_amdgcn_cvt_pk_fp8_f32(y2, y3, lo, true);
+        }
+    }
+    return e4m3_of_quotient(a[0], s, r, fast) | (e4m3_of_quotient(a[1], s, r, fast) << 8) |
+           (e4m3_of_quotient(a[2], s, r, fast) << 16) | (e4m3_of_quotient(a[3], s, r, fast) << 24);
+}
+
 __global__ __launch_bounds__(kThreads) void k_quant_e4m3(const float* __restrict__ x, int64_t n,
                                                          const float* __restrict__ part, int nparts,
                                                          uint8_t* __restrict__ q, float* scale) {
@@ -173,10 +200,7 @@ __global__ __launch_bounds__(kThreads) void k_quant_e4m3(const float* __restrict
     // instruction of a wave covers one contiguous block), four groups in flight
     const int64_t n4 = n / 4;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    auto encode4 = [&](const f4_t& a) {
-        return e4m3_of_quotient(a[0], s, r, fast) | (e4m3_of_quotient(a[1], s, r, fast) << 8) |
-               (e4m3_of_quotient(a[2], s, r, fast) << 16) | (e4m3_of_quotient(a[3], s, r, fast) << 24);
-    };
+    auto encode4 = [&](const f4_t& a) { return e4m3_encode4(a, s, r, fast); };
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     for (; i + 3 * stride < n4; i += 4 * stride) {
         f4_t a[4];

@@ -204,6 +204,27 @@ def test_quantize_e4m3_rounding_steps(scale):
     assert np.array_equal(bits8(q8), codes)
 
 
+def test_quantize_e4m3_dense_sweep_unit_scale():
+    """With amax = 448 the scale is exactly 1 and each code is the e4m3 encoding
+    of the input itself: a sweep over both signs, every exponent up to 448,
+    the top seven fraction bits and six low-bit patterns (ties, one either
+    side, all ones), through the vector kernel and its packed-conversion path,
+    equals the oracle's codes bit for bit."""
+    hi = np.arange(2 * 136 * 128, dtype=np.uint32)
+    sign, rest = hi // (136 * 128), hi % (136 * 128)
+    exp, top = rest // 128, rest % 128
+    base = (sign << 31) | (exp << 23) | (top << 16)
+    bits = np.concatenate([base | low for low in (0x0000, 0x0001, 0x7FFF, 0x8000, 0x8001, 0xFFFF)])
+    x = bits.astype(np.uint32).view(np.float32)
+    x = x[np.abs(x) <= np.float32(448.0)]
+    x = np.concatenate([x, [np.float32(448.0)]]).astype(np.float32)
+    codes, sc = oracle.quantize_e4m3(x)
+    assert np.float32(sc) == np.float32(1.0)
+    q8, s = mlk.quantize(dev(x), "e4m3")
+    assert host(s)[0] == np.float32(1.0)
+    assert np.array_equal(bits8(q8), codes)
+
+
 # ----------------------------------------------------------------------- bf16 / e4m3
 
 BF16_TILES = all_tiles(L.MLK_BF16, L.MLK_F32)
