@@ -101,7 +101,12 @@ typedef enum {
  *              same kernel with its operands loaded through registers into
  *              two LDS buffers (bf16, e4m3; bf16 channels-last conv): any
  *              shape and alignment, and usable by the persistent batched
- *              launch.
+ *              launch.  For fp32 conv (layout 0), 1 is the chunk-gather
+ *              tile: bk-deep chunks of filter and im2col input requested
+ *              whole, up to six chunks in flight in registers, one LDS
+ *              buffer; any shape with N*C*H*W below 2^31 and
+ *              C*KH*KW*KH*KW below 2^32; its split_k may leave one chunk
+ *              per part.
  *   layout     conv2d only.  0: the kernel gathers its operands straight from
  *              the NCHW input (any C).  1: the input is first transposed to
  *              channels-last (NHWC) and the filter to F x KH x KW x C in the

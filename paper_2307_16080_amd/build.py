@@ -23,7 +23,7 @@ FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Wall",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-I", os.path.join(ROOT, "include"), "-I", CSRC]
 
-SOURCES = ["k_f32.hip", "k_bf16.hip", "k_fast.hip", "k_i8.hip", "k_f8.hip", "k_conv.hip", "k_direct.hip", "elementwise.hip", "probe.hip",
+SOURCES = ["k_f32.hip", "k_bf16.hip", "k_fast.hip", "k_i8.hip", "k_f8.hip", "k_conv.hip", "k_conv_f32.hip", "k_direct.hip", "elementwise.hip", "probe.hip",
            "mlp.hip", "api.cpp", "batched.cpp", "conv_batch.cpp", "tune.cpp", "model.cpp", "scratch.cpp"]
 
 

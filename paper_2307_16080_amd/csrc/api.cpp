@@ -65,7 +65,7 @@ const std::vector<const KernelEntry*>& registry() {
     static std::vector<const KernelEntry*> all = [] {
         std::vector<const KernelEntry*> v;
         const KernelEntry* (*tables[])(int*) = {kernels_f32, kernels_bf16, kernels_i8, kernels_f8,
-                                                kernels_conv, kernels_fast, kernels_direct};
+                                                kernels_conv, kernels_fast, kernels_direct, kernels_conv_chunk};
         for (auto t : tables) {
             int n = 0;
             const KernelEntry* e = t(&n);
@@ -199,6 +199,13 @@ static bool fast_shape_ok(const Shape& s, int bk) {
 
 static bool is_direct(const KernelEntry* e) { return e->conv && e->wm == 0; }
 
+bool is_chunk_conv(const KernelEntry* e) { return e->conv && e->dt == DT_F32 && e->stages == 1; }
+
+bool chunk_conv_ok(const Shape& s) {
+    const int64_t taps = (int64_t)s.conv_kh * s.conv_kw;
+    return s.conv && s.conv_in < ((int64_t)1 << 31) && s.K * std::max<int64_t>(taps, 1) < ((int64_t)1 << 32);
+}
+
 // The direct-layout matmul tiles address their output tile with 32-bit
 // offsets from its corner; with ldc >= N the rows of a tile span at least
 // (bm - 1) * N + bn elements.
@@ -246,6 +253,9 @@ mlk_status check_config(const Shape& s, int op, const mlk_tile_config& c) {
                         kDirectMaxF, kDirectMaxStride, kDirectMaxTap, kDirectMaxTap);
         return MLK_OK;
     }
+    if (is_chunk_conv(e) && (c.layout != 0 || !chunk_conv_ok(s)))
+        return fail(MLK_ERR_CONFIG, "the fp32 chunk-gather conv tile runs as layout 0 and needs C*H*W*N below 2^31 "
+                    "and C*KH*KW*KH*KW below 2^32");
     if (c.layout != 0 && !(s.conv && (c.layout == 1 || c.layout == 3)))
         return fail(MLK_ERR_CONFIG, "layout must be 0, or 1 or 3 for conv2d (2 only for the direct conv tiles)");
     if (s.conv && !e->launch && c.layout == 0)
@@ -271,6 +281,7 @@ std::vector<mlk_tile_config> enumerate_configs(const mlk_problem* p, const Shape
             continue;
         }
         if (e->stages >= 2 && !batched && !fast_shape_ok(s, e->bk)) continue;
+        if (is_chunk_conv(e) && !chunk_conv_ok(s)) continue;
         if (!fast_ldc_ok(s, e)) continue;
         if (s.out16 && !e->launch_epi16) continue;
         // a tile at least twice the problem in a dimension only adds padding
@@ -282,7 +293,8 @@ std::vector<mlk_tile_config> enumerate_configs(const mlk_problem* p, const Shape
         // deep, narrow problems (batch-1 convolutions) fill the device only by splitting K far
         for (int sk : {1, 2, 4, 8, 16, 32}) {
             if ((batched || s.out16) && sk > 1) break;
-            if (sk > 1 && stages < 2 * sk) break;
+            // (the chunk-gather conv tiles are built for one or two chunks per split)
+            if (sk > 1 && stages < (is_chunk_conv(e) ? 1 : 2) * sk) break;
             // past 8, split only problems with too few tiles for four rounds of the device
             if (sk > 8 && tiles * sk > 4 * device_cus()) break;
             for (int gm : {1, 8}) {
@@ -353,6 +365,22 @@ mlk_tile_config heuristic_config(const Shape& s, int op, bool conv_gather) {
                 const int64_t tiles = cdiv(s.M, 64) * cdiv(s.N, 64);
                 const int64_t stages = cdiv(s.K, f->bk);
                 while (h.split_k < 16 && tiles * h.split_k * 2 <= cus && stages >= 2 * 2 * h.split_k) h.split_k *= 2;
+                return h;
+            }
+    }
+    // fp32 convolutions with fewer 64 x 64 tiles than CUs: the chunk-gather
+    // tile (one launch, no input copy), K split into at most 16 parts while the
+    // parts keep two 16-deep chunks each and the grid stays within two
+    // workgroups per CU
+    if (s.conv && s.dt == DT_F32 && op == MLK_OP_CONV2D && chunk_conv_ok(s) &&
+        cdiv(s.M, 64) * cdiv(s.N, 64) < cus) {
+        for (const KernelEntry* f : registry())
+            if (is_chunk_conv(f) && f->bm == 64 && f->bn == 64 && f->bk == 16) {
+                mlk_tile_config h{64, 64, 16, f->wm, f->wn, 1, 1, 0, 1, 0, 0};
+                const int64_t tiles = cdiv(s.M, 64) * cdiv(s.N, 64);
+                const int64_t stages = cdiv(s.K, 16);
+                while (h.split_k < 16 && tiles * h.split_k * 2 <= 2 * cus && stages >= 2 * 2 * h.split_k)
+                    h.split_k *= 2;
                 return h;
             }
     }

@@ -36,6 +36,13 @@ struct Shape {
 
 // registry of compiled kernels
 const std::vector<const KernelEntry*>& registry();
+// the fp32 conv tiles that gather whole K chunks (k_conv_f32.hip)
+const KernelEntry* kernels_conv_chunk(int* n);
+// such a tile (fp32 conv, stages 1) and the limits of its 32-bit gather
+// offsets and reciprocal divisions: C*H*W per image below 2^31 and
+// C*KH*KW * KH*KW below 2^32
+bool is_chunk_conv(const KernelEntry* e);
+bool chunk_conv_ok(const Shape& s);
 const KernelEntry* find_kernel(int dt, int conv, const mlk_tile_config& c);
 
 int dt_of(mlk_dtype in, mlk_dtype out, int conv, bool* ok);
