@@ -14,6 +14,7 @@ for the batched workload to run under the profiler.
     python -m paper_2307_16080_amd.profiling lastpass <kernel_trace.csv> <dispatches per pass> [passes]
     python -m paper_2307_16080_amd.profiling convf32 <tile> <launches>
     python -m paper_2307_16080_amd.profiling convbatch <batch> <tile|default> <launches>
+    python -m paper_2307_16080_amd.profiling quantize <bf16|e4m3> <launches>
 
 `batched` runs the 256 uneven bf16 GEMMs of the benchmark (seeded shapes and
 inputs) as persistent launches, replayed from a hipGraph, with the given tile
@@ -177,6 +178,28 @@ def run_batched(tile, launches):
         call()
     torch.cuda.synchronize()
     print(f"batched: {launches} persistent launches of {len(shapes)} GEMMs, tile {tile}", flush=True)
+
+
+def run_quantize(fmt, launches):
+    """The benchmark's quantisation: the 4096 x 4096 float32 A operand
+    (normal(0, 1), seed 0) quantised to bf16 or e4m3 into the same output
+    buffers, back to back, then the reference copy."""
+    import os
+
+    import torch
+
+    sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+    import paper_2307_16080_amd as mlk
+    from workloads import matmul_inputs
+
+    a, _ = matmul_inputs(4096, 4096, 4096, seed=0, dist="normal")
+    x = torch.from_numpy(a).cuda()
+    q, s = mlk.quantize(x, fmt)
+    for _ in range(launches):
+        mlk.quantize(x, fmt, q=q, scale=s)
+    torch.cuda.synchronize()
+    _copy_reference()
+    print(f"quantize {fmt} 4096x4096: {launches} calls; one 256 MiB copy", flush=True)
 
 
 def run_paper_conv(tile, launches):
@@ -391,6 +414,8 @@ if __name__ == "__main__":
         run_conv_f32(sys.argv[2], int(sys.argv[3]))
     elif sys.argv[1] == "resnet":
         run_resnet(int(sys.argv[2]), int(sys.argv[3]), len(sys.argv) > 4 and sys.argv[4] == "graph")
+    elif sys.argv[1] == "quantize":
+        run_quantize(sys.argv[2], int(sys.argv[3]))
     elif sys.argv[1] == "convbatch":
         run_conv_batch(int(sys.argv[2]), sys.argv[3], int(sys.argv[4]))
     elif sys.argv[1] == "batched":
