@@ -219,6 +219,19 @@ struct FastGemm {
             const int slab = wave + i * NW;
             dma_load16(__builtin_amdgcn_readfirstlane(base + slab * 1024), voff_a[i], ra, sa);
         }
+        if (rs.tap_uniform) {
+            const int dk = (rs.t_kh * g.cw + rs.t_kw) * g.cc + rs.t_c0;
+#pragma unroll
+            for (int i = 0; i < NB; ++i) {
+                const int slab = wave + i * NW;
+                const bool in = rs.p_ok[i] && (unsigned)(rs.p_ih0[i] + rs.t_kh) < (unsigned)g.ch &&
+                                (unsigned)(rs.p_iw0[i] + rs.t_kw) < (unsigned)g.cw;
+                const int off = in ? (rs.p_base[i] + dk) * ES : 0x7FFFFFF0;
+                dma_load16(__builtin_amdgcn_readfirstlane(base + A_STAGE + slab * 1024), off, rb, 0);
+            }
+            tap_step(g, rs);
+            return;
+        }
 #pragma unroll
         for (int i = 0; i < NB; ++i) {
             const int slab = wave + i * NW;
@@ -255,10 +268,38 @@ struct FastGemm {
         int p_ih0[NB], p_iw0[NB];
         int p_ok[NB];
         int k_ci[NB], k_kh[NB], k_kw[NB];
+        // C a multiple of BK (every stage inside one filter tap, the same for all
+        // lanes): the tap (kh, kw) and first channel c0 of the next stage to
+        // load, stepped once per stage as wave-uniform values, and per chunk the
+        // element offset of its first channel at tap (0, 0) (NHWC: pixel * C +
+        // channel; NCHW: image base + window origin + channel * H * W)
+        bool tap_uniform;
+        int t_c0, t_kh, t_kw;
+        int p_base[NB];
     };
+
+    // step the uniform tap state past one stage (C a multiple of BK)
+    __device__ static inline void tap_step(const GemmArgs& g, RegSlots& rs) {
+        rs.t_c0 += BK;
+        if (rs.t_c0 >= g.cc) {
+            rs.t_c0 = 0;
+            if (++rs.t_kw == g.ckw) {
+                rs.t_kw = 0;
+                ++rs.t_kh;
+            }
+        }
+    }
 
     __device__ static inline void reg_slots(const GemmArgs& g, int64_t m0, int64_t n0, int64_t kfirst,
                                             int wave, int lane, RegSlots& rs) {
+        if constexpr (CONV) {
+            rs.tap_uniform = g.cc % BK == 0;
+            const int k = __builtin_amdgcn_readfirstlane((int)kfirst);
+            const int tap = k / g.cc;
+            rs.t_c0 = k - tap * g.cc;
+            rs.t_kh = tap / g.ckw;
+            rs.t_kw = tap - rs.t_kh * g.ckw;
+        }
 #pragma unroll
         for (int i = 0; i < NA; ++i) {
             const int slab = wave + i * NW;
@@ -300,6 +341,11 @@ struct FastGemm {
                 rs.k_ci[i] = k - tap * g.cc;
                 rs.k_kh[i] = tap / g.ckw;
                 rs.k_kw[i] = tap - rs.k_kh[i] * g.ckw;
+                // (operands below 2 GiB: element offsets fit 32 bits; a window
+                // origin above or left of the image makes the base negative,
+                // and it is used only for taps inside the image)
+                rs.p_base[i] = CONV == 3 ? (int)rs.p_img[i] + rs.p_ih0[i] * g.cw + rs.p_iw0[i] + rs.b_col[i] * g.ch * g.cw
+                                         : ((int)rs.p_img[i] + rs.p_ih0[i] * g.cw + rs.p_iw0[i]) * g.cc + rs.b_col[i];
             } else {
                 const int r = slab * B_ROWS_PER_SLAB + lane / B_CHUNKS;
                 const int c = (lane % B_CHUNKS) ^ fb(r);
@@ -329,6 +375,32 @@ struct FastGemm {
             ra[i] = v;
         }
         if constexpr (CONV) {
+            if (rs.tap_uniform) {
+                // the whole stage lies in tap (t_kh, t_kw), channels t_c0 ..
+                const int dk = CONV == 3 ? rs.t_c0 * g.ch * g.cw + rs.t_kh * g.cw + rs.t_kw
+                                         : (rs.t_kh * g.cw + rs.t_kw) * g.cc + rs.t_c0;
+#pragma unroll
+                for (int i = 0; i < NB; ++i) {
+                    u4_t v = u4_t{0u, 0u, 0u, 0u};
+                    if (rs.p_ok[i] && (unsigned)(rs.p_ih0[i] + rs.t_kh) < (unsigned)g.ch &&
+                        (unsigned)(rs.p_iw0[i] + rs.t_kw) < (unsigned)g.cw) {
+                        if constexpr (CONV == 3) {
+                            const int plane = g.ch * g.cw;
+                            const MLK_GLOBAL uint16_t* src = (const MLK_GLOBAL uint16_t*)B + (rs.p_base[i] + dk);
+                            uint32_t h[8];
+#pragma unroll
+                            for (int e = 0; e < 8; ++e) h[e] = src[e * plane];
+                            v = u4_t{h[0] | (h[1] << 16), h[2] | (h[3] << 16), h[4] | (h[5] << 16),
+                                     h[6] | (h[7] << 16)};
+                        } else {
+                            v = *(const MLK_GLOBAL u4_t*)(B + (int64_t)(rs.p_base[i] + dk) * ES);
+                        }
+                    }
+                    rb[i] = v;
+                }
+                tap_step(g, rs);
+                return;
+            }
             // chunk k..k+7 lies in one filter tap (C is a multiple of 8): channels
             // ci..ci+7 of input pixel (ih, iw), zero outside the image
             // (stages are loaded in order, so each call steps every chunk by BK)
@@ -673,7 +745,9 @@ struct FastGemm {
                         const bool in = full || (row < mrem && col < nrem);
                         out_t x = 0;
                         if constexpr (CONV) {
-                            if (in) x = Ct[cbase[j] + row * hw];
+                            // column pointer at this lane's first row, plus the
+                            // row's distance from it times H*W (wave-uniform)
+                            if (in) x = Ct[cbase[j] + (int64_t)row0 * hw + (int64_t)(row - row0) * hw];
                         } else {
                             x = in ? Ct[row * ldc + col] : (out_t)0;
                         }
@@ -790,6 +864,40 @@ struct FastGemm {
                     }
                 }
             }
+        } else if constexpr (CONV) {
+            // NFHW outputs: one pointer per column tile at this lane's first row,
+            // rows at a compile-time distance times H*W; the store mode (plain,
+            // read-add-write, atomic) is chosen once for the tile
+            // (tiles wholly inside the output skip the bounds tests)
+            auto conv_out = [&](auto mode, auto whole) {
+                constexpr int MODE = decltype(mode)::value;
+                constexpr bool WHOLE = decltype(whole)::value;
+#pragma unroll
+                for (int j = 0; j < TN; ++j) {
+                    const int col = col0 + j * MF;
+                    const bool colok = WHOLE || col < nrem;
+                    MLK_GLOBAL out_t* const pj = Ct + cbase[j] + (int64_t)row0 * hw;
+#pragma unroll
+                    for (int i = 0; i < TM; ++i)
+#pragma unroll
+                        for (int r = 0; r < NR; ++r) {
+                            const int dr = rowof(i, r) - row0;
+                            if (!(WHOLE || (colok && row0 + dr < mrem))) continue;
+                            MLK_GLOBAL out_t* p = pj + (int64_t)dr * hw;
+                            const out_t v = DT == DT_F8 ? alpha * acc[i][j][r] : acc[i][j][r];
+                            if constexpr (MODE == 2) __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                            else if constexpr (MODE == 0) *p = v;
+                            else *p = *p + v;
+                        }
+                }
+            };
+            auto by_extent = [&](auto mode) {
+                if (full) conv_out(mode, std::true_type{});
+                else conv_out(mode, std::false_type{});
+            };
+            if (g.atomic) by_extent(std::integral_constant<int, 2>{});
+            else if (c_in_acc || !g.accumulate) by_extent(std::integral_constant<int, 0>{});
+            else by_extent(std::integral_constant<int, 1>{});
         } else {
 #pragma unroll
             for (int j = 0; j < TN; ++j) {

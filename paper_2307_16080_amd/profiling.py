@@ -15,6 +15,7 @@ for the batched workload to run under the profiler.
     python -m paper_2307_16080_amd.profiling convf32 <tile> <launches>
     python -m paper_2307_16080_amd.profiling convbatch <batch> <tile|default> <launches>
     python -m paper_2307_16080_amd.profiling quantize <bf16|e4m3> <launches>
+    python -m paper_2307_16080_amd.profiling conv <N,C,H,W,F,KH,KW,stride,pad> <tile> <launches>
 
 `batched` runs the 256 uneven bf16 GEMMs of the benchmark (seeded shapes and
 inputs) as persistent launches, replayed from a hipGraph, with the given tile
@@ -178,6 +179,31 @@ def run_batched(tile, launches):
         call()
     torch.cuda.synchronize()
     print(f"batched: {launches} persistent launches of {len(shapes)} GEMMs, tile {tile}", flush=True)
+
+
+def run_conv(shape, tile, launches):
+    """One bf16 convolution (normal(0, 1) inputs from seed 0, quantised to bf16
+    on the GPU; y += conv) bound once with one fixed tile and called back to
+    back, then the reference copy."""
+    import os
+
+    import torch
+
+    sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+    import paper_2307_16080_amd as mlk
+    from workloads import conv_inputs
+
+    n, c, h, w, f, kh, kw, st, pd = [int(v) for v in shape.split(",")]
+    x, wt = conv_inputs(n, c, h, w, f, kh, kw, seed=0)
+    xq, _ = mlk.quantize(torch.from_numpy(x).cuda(), "bf16")
+    wq, _ = mlk.quantize(torch.from_numpy(wt).cuda(), "bf16")
+    y = torch.zeros(n, f, (h + 2 * pd - kh) // st + 1, (w + 2 * pd - kw) // st + 1, device="cuda")
+    call = mlk.ConvCall(xq, wq, y, (st, st), (pd, pd), cfg=mlk.TileConfig(*[int(v) for v in tile.split(",")]))
+    for _ in range(launches):
+        call()
+    torch.cuda.synchronize()
+    _copy_reference()
+    print(f"conv {shape} bf16: {launches} calls, tile {tile}; one 256 MiB copy", flush=True)
 
 
 def run_quantize(fmt, launches):
@@ -414,6 +440,8 @@ if __name__ == "__main__":
         run_conv_f32(sys.argv[2], int(sys.argv[3]))
     elif sys.argv[1] == "resnet":
         run_resnet(int(sys.argv[2]), int(sys.argv[3]), len(sys.argv) > 4 and sys.argv[4] == "graph")
+    elif sys.argv[1] == "conv":
+        run_conv(sys.argv[2], sys.argv[3], int(sys.argv[4]))
     elif sys.argv[1] == "quantize":
         run_quantize(sys.argv[2], int(sys.argv[3]))
     elif sys.argv[1] == "convbatch":
