@@ -369,34 +369,34 @@ __device__ inline void transpose_tile32(const T* __restrict__ src, T* __restrict
     }
 }
 
-// 2-byte elements with rows and cols multiples of 8 (16-byte rows on both
-// sides): 64 x 64 tiles, 16-byte loads along the input rows and 16-byte stores
-// along the output rows; the LDS tile row pitch (144 bytes) keeps the column
-// gathers of the transposed read on distinct banks.
-__device__ inline void transpose_tile64_16(const uint16_t* __restrict__ src, uint16_t* __restrict__ dst,
-                                           int64_t rows, int64_t cols, int64_t bx, int64_t by, uint8_t* lds) {
-    uint16_t (*tile)[72] = (uint16_t (*)[72])lds;
-    const int64_t c0 = bx * 64, r0 = by * 64;
+// 2-byte elements with rows and columns multiples of 8 and 16-byte aligned
+// rows: each thread moves one 8 x 8 block through registers, no LDS.  It reads
+// the block's 8 rows as 16-byte loads (8 columns each), pairs the rows'
+// halves into 32-bit words (column p of rows 2a and 2a + 1), and writes the
+// block's 8 columns as 16-byte stores (8 rows each).  Lanes take the row
+// groups fastest, so one load instruction of a wave reads 8 row segments of
+// 128 bytes and one store instruction writes 8 output segments of 128 bytes.
+// A workgroup covers 64 rows x 256 columns; a block is either whole or
+// outside the matrix.
+__device__ inline void transpose_blocks8_16(const uint16_t* __restrict__ src, uint16_t* __restrict__ dst,
+                                            int64_t rows, int64_t cols, int64_t bx, int64_t by) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int64_t r = by * 64 + 8 * (lane & 7);
+    const int64_t c = bx * 256 + 8 * ((lane >> 3) + 8 * wave);
+    if (r >= rows || c >= cols) return;
+    u4_t in[8];
 #pragma unroll
-    for (int i = 0; i < 2; ++i) {
-        const int k = threadIdx.x + 256 * i;
-        const int r = k >> 3, cc = (k & 7) * 8;
-        u4_t v = u4_t{0u, 0u, 0u, 0u};
-        if (r0 + r < rows && c0 + cc < cols) v = *(const u4_t*)(src + (r0 + r) * cols + c0 + cc);
-        *(u4_t*)&tile[r][cc] = v;
-    }
-    __syncthreads();
+    for (int e = 0; e < 8; ++e) in[e] = *(const u4_t*)(src + (r + e) * cols + c);
 #pragma unroll
-    for (int i = 0; i < 2; ++i) {
-        const int k = threadIdx.x + 256 * i;
-        const int oc = k >> 3, rc = (k & 7) * 8;
-        if (c0 + oc < cols && r0 + rc < rows) {
-            u4_t v;
+    for (int j = 0; j < 8; ++j) {
+        const int w = j >> 1;
+        u4_t out;
 #pragma unroll
-            for (int t = 0; t < 4; ++t)
-                v[t] = (uint32_t)tile[rc + 2 * t][oc] | ((uint32_t)tile[rc + 2 * t + 1][oc] << 16);
-            *(u4_t*)(dst + (c0 + oc) * rows + r0 + rc) = v;
+        for (int a = 0; a < 4; ++a) {
+            const uint32_t x = in[2 * a][w], y = in[2 * a + 1][w];
+            out[a] = (j & 1) ? (x >> 16) | (y & 0xFFFF0000u) : (x & 0xFFFFu) | (y << 16);
         }
+        *(u4_t*)(dst + (c + j) * rows + r) = out;
     }
 }
 
@@ -407,7 +407,7 @@ struct TransposeJob {
     int64_t rows, cols;
     int64_t tiles_x, tiles_y;
     int64_t blocks;  // tiles_x * tiles_y * batch
-    int wide;        // 2-byte elements in the 64 x 64 16-byte form
+    int wide;        // 2-byte elements moved as 8 x 8 blocks through registers
 };
 
 // Two batched transposes in one launch (the conv's input and filter to
@@ -415,8 +415,7 @@ struct TransposeJob {
 // second.  The job choice is uniform per workgroup.
 template <typename T>
 __global__ __launch_bounds__(256) void k_transpose_pair(TransposeJob j0, TransposeJob j1) {
-    __shared__ __attribute__((aligned(16))) uint8_t lds[64 * 72 * 2 > 32 * 33 * sizeof(T) ? 64 * 72 * 2
-                                                                                           : 32 * 33 * sizeof(T)];
+    __shared__ __attribute__((aligned(16))) uint8_t lds[32 * 33 * sizeof(T)];
     int64_t id = blockIdx.x;
     const bool second = id >= j0.blocks;
     const TransposeJob j = second ? j1 : j0;
@@ -425,7 +424,7 @@ __global__ __launch_bounds__(256) void k_transpose_pair(TransposeJob j0, Transpo
     const int64_t off = bz * j.rows * j.cols;
     if constexpr (sizeof(T) == 2) {
         if (j.wide) {
-            transpose_tile64_16((const uint16_t*)j.in + off, (uint16_t*)j.out + off, j.rows, j.cols, bx, by, lds);
+            transpose_blocks8_16((const uint16_t*)j.in + off, (uint16_t*)j.out + off, j.rows, j.cols, bx, by);
             return;
         }
     }
@@ -534,9 +533,9 @@ static TransposeJob transpose_job(const void* in, void* out, int64_t batch, int6
     TransposeJob j{in, out, rows, cols, 0, 0, 0, 0};
     if (batch <= 0 || rows <= 0 || cols <= 0) return j;
     j.wide = esize == 2 && rows % 8 == 0 && cols % 8 == 0 && (uintptr_t)in % 16 == 0 && (uintptr_t)out % 16 == 0;
-    const int t = j.wide ? 64 : 32;
-    j.tiles_x = (cols + t - 1) / t;
-    j.tiles_y = (rows + t - 1) / t;
+    // the wide form: 64 rows x 256 columns per workgroup; else 32 x 32 tiles
+    j.tiles_x = (cols + (j.wide ? 255 : 31)) / (j.wide ? 256 : 32);
+    j.tiles_y = (rows + (j.wide ? 63 : 31)) / (j.wide ? 64 : 32);
     j.blocks = j.tiles_x * j.tiles_y * batch;
     return j;
 }
