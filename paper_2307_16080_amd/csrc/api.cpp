@@ -1128,7 +1128,8 @@ mlk_status mlk_quantize(mlk_dtype out, int64_t n, const float* x, void* q, float
             rc != MLK_OK)
             return rc;
     }
-    const hipError_t e = launch_quant_e4m3(x, n, (uint8_t*)q, scale, (float*)scratch.ptr(), st);
+    hipError_t e = launch_quant_e4m3_fused(x, n, (uint8_t*)q, scale, st);
+    if (e == hipErrorNotSupported) e = launch_quant_e4m3(x, n, (uint8_t*)q, scale, (float*)scratch.ptr(), st);
     const mlk_status rel = scratch.end();
     if (e != hipSuccess) return hip_fail(e, "quantize launch");
     return rel;

@@ -10,7 +10,10 @@
 
 #include <algorithm>
 #include <cstring>
+#include <map>
+#include <mutex>
 
+#include "internal.hpp"
 #include "kernels.hpp"
 
 namespace mlk {
@@ -163,27 +166,29 @@ __device__ inline uint32_t e4m3_of_quotient(float x, float s, float r, bool fast
     return e4m3_rne_sat(__fdiv_rn(x, s));
 }
 
-// y = x * RN(1/s) is safe to encode in place of RN(x / s) (see e4m3_of_quotient):
-// a normal e4m3 input at least 5 ulps from a rounding step
-__device__ inline bool e4m3_safe(float y) {
-    const uint32_t mag = __float_as_uint(y) & 0x7FFFFFFFu;
-    const uint32_t rest = mag & 0xFFFFFu;
-    const uint32_t d = rest > 0x80000u ? rest - 0x80000u : 0x80000u - rest;
-    return mag >= 0x3C800000u && mag < 0x43E00000u && d > 4u;
-}
-
-// Four codes packed in a word.  When all four products are safe, the gfx950
-// packed conversion v_cvt_pk_fp8_f32 (round to nearest even into OCP e4m3)
-// encodes them, two per instruction: it gives e4m3_rne_sat's code for every
-// fp32 value below 464 in magnitude (checked on the GPU over all 2,278,555,648 such
-// bit patterns of both signs), and safe products lie below 448.  Otherwise
-// each value takes e4m3_of_quotient.
+// Four codes packed in a word, through the gfx950 packed conversion
+// v_cvt_pk_fp8_f32 (round to nearest even into OCP e4m3, two values per
+// instruction): it gives e4m3_rne_sat's code for every fp32 value below 464
+// in magnitude (checked on the GPU over all 2,278,555,648 such bit patterns
+// of both signs), and it is monotonic.  y = x * RN(1/s) is within 1.5 * 2^-23
+// of RN(x / s) relatively (see e4m3_of_quotient), so when y * (1 - 2^-21)
+// and y * (1 + 2^-21) (which bracket that interval) encode to y's own code,
+// no rounding step lies between y and RN(x / s) and the code is RN(x / s)'s.
+// Values of 448 or more in magnitude (or NaN), or a bracket that straddles a
+// step, take e4m3_of_quotient per value.
 __device__ inline uint32_t e4m3_encode4(const f4_t& a, float s, float r, bool fast) {
     if (fast) {
         const float y0 = a[0] * r, y1 = a[1] * r, y2 = a[2] * r, y3 = a[3] * r;
-        if (e4m3_safe(y0) && e4m3_safe(y1) && e4m3_safe(y2) && e4m3_safe(y3)) {
-            const int lo = __builtin_amdgcn_cvt_pk_fp8_f32(y0, y1, 0, false);
-            return (uint32_t)__builtin_amdgcn_cvt_pk_fp8_f32(y2, y3, lo, true);
+        // (a NaN compares false)
+        if (fabsf(y0) < 448.0f && fabsf(y1) < 448.0f && fabsf(y2) < 448.0f && fabsf(y3) < 448.0f) {
+            const float up = 1.0f + 0x1p-21f, dn = 1.0f - 0x1p-21f;
+            const uint32_t c = (uint32_t)__builtin_amdgcn_cvt_pk_fp8_f32(
+                y2, y3, __builtin_amdgcn_cvt_pk_fp8_f32(y0, y1, 0, false), true);
+            const uint32_t cu = (uint32_t)__builtin_amdgcn_cvt_pk_fp8_f32(
+                y2 * up, y3 * up, __builtin_amdgcn_cvt_pk_fp8_f32(y0 * up, y1 * up, 0, false), true);
+            const uint32_t cd = (uint32_t)__builtin_amdgcn_cvt_pk_fp8_f32(
+                y2 * dn, y3 * dn, __builtin_amdgcn_cvt_pk_fp8_f32(y0 * dn, y1 * dn, 0, false), true);
+            if (cu == c && cd == c) return c;
         }
     }
     return e4m3_of_quotient(a[0], s, r, fast) | (e4m3_of_quotient(a[1], s, r, fast) << 8) |
@@ -227,6 +232,140 @@ __global__ __launch_bounds__(kThreads) void k_quant_e4m3_scalar(const float* __r
 }
 
 __global__ __launch_bounds__(kThreads) void k_scale_one(float* scale) { *scale = 1.0f; }
+
+// One-pass e4m3 quantisation.  Every workgroup of the grid is resident (the
+// launcher sizes the grid by the kernel's occupancy), each thread holds up to
+// kFusedVec groups of four inputs in registers, and the scale, which depends
+// on every element, comes from a grid-wide exchange of single 64-bit words:
+// each workgroup publishes (epoch << 32 | bits of its maximum |x|) in its own
+// word; workgroup 0 reads every word of this call's epoch, forms amax, and
+// publishes (epoch << 32 | bits of amax) in each workgroup's own release word,
+// which that workgroup polls.  A value and its epoch travel in one atomic
+// word, so the exchange needs no fences (fences here are cache write-backs
+// and invalidations, thousands of them at once); the input is read-only and
+// each workgroup writes only its own codes.  Epochs only grow from call to
+// call (calls are serialised), so nothing is reset.  Every wait is bounded: a
+// workgroup that gives up computes the maximum over the whole input itself
+// (slow, and the same value), so the kernel always ends, with the right codes.
+constexpr int kFusedVec = 16;
+constexpr int kFusedMaxGrid = 1024;  // 4 words per thread of workgroup 0 (16.8 M elements)
+__device__ unsigned long long g_quant_part[kFusedMaxGrid];
+__device__ unsigned long long g_quant_release[kFusedMaxGrid];
+
+// the low 32 bits of *word once its high 32 bits equal epoch (relaxed polls);
+// false after spin_limit polls
+__device__ inline bool wait_for_epoch(const unsigned long long* word, unsigned int epoch,
+                                      unsigned int spin_limit, uint32_t* value) {
+    unsigned int spins = 0;
+    for (;;) {
+        const unsigned long long v = __hip_atomic_load(word, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if ((unsigned int)(v >> 32) == epoch) {
+            *value = (uint32_t)v;
+            return true;
+        }
+        if (++spins > spin_limit) return false;
+        __builtin_amdgcn_s_sleep(8);
+    }
+}
+
+__device__ inline float block_max(float m, float* wmax) {
+    for (int off = 32; off > 0; off >>= 1) m = fmaxf(m, __shfl_xor(m, off, 64));
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) wmax[threadIdx.x >> 6] = m;
+    __syncthreads();
+    m = wmax[0];
+    for (int w = 1; w < kThreads / 64; ++w) m = fmaxf(m, wmax[w]);
+    return m;
+}
+
+__global__ __launch_bounds__(kThreads) void k_quant_e4m3_fused(const float* __restrict__ x, int64_t n,
+                                                               uint8_t* __restrict__ q, float* scale,
+                                                               unsigned int epoch, unsigned int spin_limit) {
+    const int64_t n4 = n / 4;
+    const int64_t stride = (int64_t)gridDim.x * kThreads;
+    const int64_t first = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+    f4_t a[kFusedVec];
+    float m = 0.0f;
+#pragma unroll
+    for (int u = 0; u < kFusedVec; ++u) {
+        const int64_t i = first + u * stride;
+        a[u] = i < n4 ? *(const f4_t*)(x + 4 * i) : f4_t{0.0f, 0.0f, 0.0f, 0.0f};
+        m = fmaxf(m, fmaxf(fmaxf(fabsf(a[u][0]), fabsf(a[u][1])), fmaxf(fabsf(a[u][2]), fabsf(a[u][3]))));
+    }
+    if (blockIdx.x == 0)
+        for (int64_t j = n4 * 4 + threadIdx.x; j < n; j += blockDim.x) m = fmaxf(m, fabsf(x[j]));
+    // (fmaxf drops NaN operands, so NaNs never reach the maximum)
+    __shared__ float wmax[kThreads / 64];
+    __shared__ float shared_amax;
+    __shared__ int released;
+    m = block_max(m, wmax);
+    const unsigned long long tag = (unsigned long long)epoch << 32;
+    if (threadIdx.x == 0)
+        __hip_atomic_store(&g_quant_part[blockIdx.x], tag | __float_as_uint(m), __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
+    if (blockIdx.x == 0) {
+        // each thread gathers its (up to kFusedMaxGrid / kThreads) words, all of
+        // them polled together so that every round waits one memory latency
+        constexpr int kWords = kFusedMaxGrid / kThreads;
+        uint32_t pending = 0;
+#pragma unroll
+        for (int k = 0; k < kWords; ++k)
+            if (threadIdx.x + k * kThreads < (int)gridDim.x) pending |= 1u << k;
+        float mm = 0.0f;
+        unsigned int spins = 0;
+        while (pending != 0 && spins <= spin_limit) {
+            unsigned long long v[kWords];
+#pragma unroll
+            for (int k = 0; k < kWords; ++k)
+                v[k] = (pending >> k) & 1u ? __hip_atomic_load(&g_quant_part[threadIdx.x + k * kThreads],
+                                                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
+                                           : 0ull;
+#pragma unroll
+            for (int k = 0; k < kWords; ++k)
+                if (((pending >> k) & 1u) && (unsigned int)(v[k] >> 32) == epoch) {
+                    mm = fmaxf(mm, __uint_as_float((uint32_t)v[k]));
+                    pending &= ~(1u << k);
+                }
+            if (pending != 0) {
+                ++spins;
+                __builtin_amdgcn_s_sleep(2);
+            }
+        }
+        const bool all = __syncthreads_and(pending == 0);
+        mm = block_max(mm, wmax);
+        if (all)
+            for (int b = threadIdx.x + 1; b < (int)gridDim.x; b += blockDim.x)
+                __hip_atomic_store(&g_quant_release[b], tag | __float_as_uint(mm), __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_AGENT);
+        if (threadIdx.x == 0) {
+            released = all;
+            shared_amax = mm;
+        }
+    } else if (threadIdx.x == 0) {
+        uint32_t bits = 0;
+        released = wait_for_epoch(&g_quant_release[blockIdx.x], epoch, spin_limit, &bits);
+        shared_amax = __uint_as_float(bits);
+    }
+    __syncthreads();
+    float amax = shared_amax;
+    if (!released) {
+        float mm = 0.0f;
+        for (int64_t j = threadIdx.x; j < n; j += blockDim.x) mm = fmaxf(mm, fabsf(x[j]));
+        amax = block_max(mm, wmax);
+    }
+    const float s = e4m3_scale_from_amax(amax);
+    if (blockIdx.x == 0 && threadIdx.x == 0) *scale = s;
+    const float r = __frcp_rn(s);
+    const bool fast = __builtin_isfinite(r) && r > 0.0f;
+#pragma unroll
+    for (int u = 0; u < kFusedVec; ++u) {
+        const int64_t i = first + u * stride;
+        if (i < n4) *(uint32_t*)(q + 4 * i) = e4m3_encode4(a[u], s, r, fast);
+    }
+    if (blockIdx.x == 0)
+        for (int64_t j = n4 * 4 + threadIdx.x; j < n; j += blockDim.x)
+            q[j] = (uint8_t)e4m3_of_quotient(x[j], s, r, fast);
+}
 
 // ------------------------------------------------------------------ fills
 
@@ -506,6 +645,48 @@ hipError_t launch_quant_bf16(const float* x, int64_t n, uint16_t* q, hipStream_t
         hipLaunchKernelGGL(k_quant_bf16_scalar, dim3(grid_for(n, kThreads * 8)), dim3(kThreads), 0, s,
                            x, n, q);
     return hipGetLastError();
+}
+
+// The one-pass form when the whole input fits the resident grid's registers
+// (16.8 M elements take 1,024 workgroups of 256 threads); hipErrorNotSupported,
+// with nothing enqueued, otherwise.  Callers serialise through the library's
+// scratch lock, so one launch at a time uses the exchange words of a device;
+// the host keeps the last epoch it used there.
+namespace {
+struct FusedQuant {
+    int grid_cap = 0;
+    unsigned int epoch = 0;  // the last call's (device flags start at 0)
+};
+std::mutex g_fused_mu;
+std::map<int, FusedQuant> g_fused;
+}  // namespace
+
+hipError_t launch_quant_e4m3_fused(const float* x, int64_t n, uint8_t* q, float* scale, hipStream_t s) {
+    if (n <= 0 || (uintptr_t)x % 16 != 0 || (uintptr_t)q % 4 != 0) return hipErrorNotSupported;
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    std::lock_guard<std::mutex> lk(g_fused_mu);
+    FusedQuant& st = g_fused[dev];
+    if (st.grid_cap == 0) {
+        int per_cu = 0, cus = 0;
+        if ((e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_quant_e4m3_fused, kThreads, 0)) !=
+            hipSuccess)
+            return e;
+        if ((e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess) return e;
+        st.grid_cap = std::max(1, std::min(per_cu * cus, kFusedMaxGrid));
+    }
+    const int64_t need = (n / 4 + (int64_t)kThreads * kFusedVec - 1) / ((int64_t)kThreads * kFusedVec);
+    if (need > st.grid_cap) return hipErrorNotSupported;
+    const int grid = (int)std::max<int64_t>(1, need);
+    // (an epoch of 0 would match the flags' initial value: skip it on wrap)
+    const unsigned int epoch = st.epoch + 1 == 0 ? 1 : st.epoch + 1;
+    // ~1 << 18 sleeps of ~512 cycles: tens of milliseconds before a workgroup
+    // stops waiting and computes the maximum itself
+    hipLaunchKernelGGL(k_quant_e4m3_fused, dim3(grid), dim3(kThreads), 0, s, x, n, q, scale, epoch, 1u << 18);
+    e = hipGetLastError();
+    if (e == hipSuccess) st.epoch = epoch;
+    return e;
 }
 
 hipError_t launch_quant_e4m3(const float* x, int64_t n, uint8_t* q, float* scale, float* part,

@@ -34,6 +34,13 @@ struct Shape {
     int conv_kh = 0, conv_kw = 0, conv_sh = 0, conv_sw = 0;  // conv: filter taps and strides
 };
 
+// one-pass e4m3 quantisation (elementwise.hip): the whole input held in the
+// registers of a resident grid across a grid-wide exchange of the workgroups'
+// maxima.  hipErrorNotSupported, with nothing enqueued, when the input does
+// not fit or is not aligned (the two-pass form then runs).  Callers serialise
+// through the scratch lock (held around the launch).
+hipError_t launch_quant_e4m3_fused(const float* x, int64_t n, uint8_t* q, float* scale, hipStream_t s);
+
 // registry of compiled kernels
 const std::vector<const KernelEntry*>& registry();
 // the fp32 conv tiles that gather whole K chunks (k_conv_f32.hip)

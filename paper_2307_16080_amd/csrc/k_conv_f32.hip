@@ -66,8 +66,9 @@ struct ChunkConv {
     static_assert(LDS_BYTES <= 160 * 1024, "LDS budget");
 
     struct Pix {
-        const float* base;  // x + img*C*H*W + ih0*W + iw0 (address of tap (0, 0, 0))
-        int ih0, iw0;       // window origin; far outside the image for a pixel past P
+        int64_t base;  // element offset of tap (0, 0, 0): img*C*H*W + ih0*W + iw0 (negative
+                       // when the window starts in the padding; used only for taps inside)
+        int ih0, iw0;  // window origin; far outside the image for a pixel past P
     };
 
     __device__ static inline void load(const GemmArgs& g, int64_t k0, int tid, uint32_t wb, const Pix* px,
@@ -94,6 +95,7 @@ struct ChunkConv {
             ra[i] = v;
         }
         // B: implicit im2col; this wave's groups all have the same k
+        const float* X = (const float*)g.B;
         const int hw = g.ch * g.cw;
 #pragma unroll
         for (int i = 0; i < NB; ++i) {
@@ -112,7 +114,7 @@ struct ChunkConv {
                 const int off = (int)c * hw + (int)kh * g.cw + (int)kw;
                 const bool in = k < g.K && (unsigned)(p.ih0 + (int)kh) < (unsigned)g.ch &&
                                 (unsigned)(p.iw0 + (int)kw) < (unsigned)g.cw;
-                v[e] = in ? p.base[off] : 0.f;
+                v[e] = in ? X[p.base + off] : 0.f;
             }
             rb[i] = v;
         }
@@ -155,7 +157,6 @@ struct ChunkConv {
         {
             const int64_t P = (int64_t)g.cn * g.cho * g.cwo;
             const int hwo = g.cho * g.cwo;
-            const float* X = (const float*)g.B;
 #pragma unroll
             for (int s = 0; s < NPIX; ++s) {
                 const int pn = NT >= BN ? tid % BN : tid + NT * s;
@@ -165,11 +166,11 @@ struct ChunkConv {
                     const int oh = q / g.cwo, ow = q - oh * g.cwo;
                     px[s].ih0 = oh * g.csh - g.cph;
                     px[s].iw0 = ow * g.csw - g.cpw;
-                    px[s].base = X + (int64_t)img * g.cc * g.ch * g.cw + (int64_t)px[s].ih0 * g.cw + px[s].iw0;
+                    px[s].base = (int64_t)img * g.cc * g.ch * g.cw + (int64_t)px[s].ih0 * g.cw + px[s].iw0;
                 } else {
                     px[s].ih0 = -(1 << 28);
                     px[s].iw0 = -(1 << 28);
-                    px[s].base = X;
+                    px[s].base = 0;
                 }
             }
         }

@@ -225,6 +225,41 @@ def test_quantize_e4m3_dense_sweep_unit_scale():
     assert np.array_equal(bits8(q8), codes)
 
 
+def test_quantize_e4m3_calls_in_sequence():
+    """e4m3 quantisation runs in one pass when the input fits the registers of a
+    resident grid (a grid-wide barrier whose device arrival counter only grows
+    from launch to launch) and in two passes beyond that.  Sizes in sequence,
+    twice over, with other library work between them: every call's codes and
+    scale equal the oracle's bit for bit."""
+    sizes = [1 << 20, 5, 3 << 20, 65537, 1 << 22, 3]
+    rng = np.random.default_rng(17)
+    xs = [(rng.standard_normal(n) * rng.uniform(0.01, 100)).astype(np.float32) for n in sizes]
+    refs = [oracle.quantize_e4m3(x) for x in xs]
+    for rep in range(2):
+        for x, (codes, sc) in zip(xs, refs):
+            q8, s = mlk.quantize(dev(x), "e4m3")
+            mlk.quantize(dev(x), "bf16")                 # other scratch-free work between calls
+            assert host(s)[0] == np.float32(sc), (rep, x.size)
+            assert np.array_equal(bits8(q8), codes), (rep, x.size)
+
+
+@pytest.mark.parametrize("n", [1 << 24, (1 << 24) + 4, (1 << 24) + 4096 * 4 + 3])
+def test_quantize_e4m3_at_and_past_the_resident_grid(n):
+    """The benchmark's 16.8 M elements (one pass, every resident workgroup) and
+    sizes just past what the resident grid holds (two passes): the scale equals
+    amax / 448 exactly and the codes equal the oracle's on the first and last
+    4096 elements and on a million sampled ones."""
+    x = np.random.default_rng(n % 1000).standard_normal(n).astype(np.float32)
+    x[n // 3] = np.float32(-7.5)                     # a known maximum |x|
+    q8, s = mlk.quantize(dev(x), "e4m3")
+    sc = oracle.e4m3_scale(oracle.amax(x))
+    assert host(s)[0] == np.float32(sc)
+    got = bits8(q8)
+    idx = np.concatenate([np.arange(4096), np.arange(n - 4096, n),
+                          np.random.default_rng(3).integers(0, n, 1 << 20)])
+    assert np.array_equal(got[idx], oracle.e4m3_encode(x[idx], sc))
+
+
 # ----------------------------------------------------------------------- bf16 / e4m3
 
 BF16_TILES = all_tiles(L.MLK_BF16, L.MLK_F32)
