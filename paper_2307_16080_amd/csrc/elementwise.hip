@@ -9,6 +9,7 @@
 #include <stdint.h>
 
 #include <algorithm>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <mutex>
@@ -682,8 +683,12 @@ hipError_t launch_quant_e4m3_fused(const float* x, int64_t n, uint8_t* q, float*
     // (an epoch of 0 would match the flags' initial value: skip it on wrap)
     const unsigned int epoch = st.epoch + 1 == 0 ? 1 : st.epoch + 1;
     // ~1 << 18 sleeps of ~512 cycles: tens of milliseconds before a workgroup
-    // stops waiting and computes the maximum itself
-    hipLaunchKernelGGL(k_quant_e4m3_fused, dim3(grid), dim3(kThreads), 0, s, x, n, q, scale, epoch, 1u << 18);
+    // stops waiting and computes the maximum itself.  MLK_QUANT_WAIT_POLLS
+    // sets the bound instead (0: one round of polls), so that a test can
+    // drive the fallback from the host.
+    unsigned int polls = 1u << 18;
+    if (const char* env = getenv("MLK_QUANT_WAIT_POLLS")) polls = (unsigned int)strtoul(env, nullptr, 10);
+    hipLaunchKernelGGL(k_quant_e4m3_fused, dim3(grid), dim3(kThreads), 0, s, x, n, q, scale, epoch, polls);
     e = hipGetLastError();
     if (e == hipSuccess) st.epoch = epoch;
     return e;

@@ -243,6 +243,26 @@ def test_quantize_e4m3_calls_in_sequence():
             assert np.array_equal(bits8(q8), codes), (rep, x.size)
 
 
+def test_quantize_e4m3_wait_fallback(monkeypatch):
+    """The one-pass kernel's waits are bounded; a workgroup that stops waiting
+    scans the whole input for the maximum itself.  With the bound forced to a
+    single round of polls from the host (MLK_QUANT_WAIT_POLLS=0), most
+    workgroups take that path, and every call still gives the oracle's codes
+    and scale; the next calls, with the default bound, are exact too (the
+    exchange words are consistent after a fallback)."""
+    rng = np.random.default_rng(23)
+    xs = [(rng.standard_normal(n) * 3).astype(np.float32) for n in (1 << 20, 1 << 22, 1001)]
+    refs = [oracle.quantize_e4m3(x) for x in xs]
+    monkeypatch.setenv("MLK_QUANT_WAIT_POLLS", "0")
+    for x, (codes, sc) in zip(xs, refs):
+        q8, s = mlk.quantize(dev(x), "e4m3")
+        assert host(s)[0] == np.float32(sc) and np.array_equal(bits8(q8), codes), x.size
+    monkeypatch.delenv("MLK_QUANT_WAIT_POLLS")
+    for x, (codes, sc) in zip(xs, refs):
+        q8, s = mlk.quantize(dev(x), "e4m3")
+        assert host(s)[0] == np.float32(sc) and np.array_equal(bits8(q8), codes), x.size
+
+
 @pytest.mark.parametrize("n", [1 << 24, (1 << 24) + 4, (1 << 24) + 4096 * 4 + 3])
 def test_quantize_e4m3_at_and_past_the_resident_grid(n):
     """The benchmark's 16.8 M elements (one pass, every resident workgroup) and
