@@ -353,6 +353,16 @@ mlk_status mlk_mfma_rate(mlk_dtype in, int64_t iters, float* out, int64_t out_le
  *                     fp32 first and magnitudes beyond 448 saturated to 448;
  *                     *scale = s (device float).
  * x, q, scale device pointers; q has n elements of the output type.
+ * e4m3 runs in one launch when x is 16-byte aligned and fits the registers of
+ * a grid that is all resident at once (up to 16.8 M values on an MI355X): the
+ * workgroups exchange their maxima through device words and then encode.  Its
+ * waits are bounded (if work on other streams keeps some workgroups from
+ * starting, the resident ones wait up to that bound); a workgroup that stops
+ * waiting scans x for the maximum itself, so the codes are the same.  The
+ * environment variable MLK_QUANT_WAIT_POLLS sets the bound in polls (tests).
+ * Larger or unaligned inputs take two launches (maximum, then codes).
+ * e4m3 takes the library's scratch memory (not under stream capture), which
+ * also orders concurrent e4m3 calls on any streams.
  * Per-tensor scaling as in the fp8 extension; the paper itself is fp32-only.
  */
 mlk_status mlk_quantize(mlk_dtype out, int64_t n, const float* x, void* q, float* scale,
