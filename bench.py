@@ -90,7 +90,7 @@ def host_facts():
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print(json.dumps({"error": "this build runs on one GPU only: the kernels work on one "
+        print(json.dumps({"error": "this library runs on one GPU only: the kernels work on one "
                                    "device's share and no multi-GPU path exists; run with --gpus 1"}))
         sys.exit(2)
 
