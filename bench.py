@@ -295,7 +295,7 @@ def main():
                                         "bf16_output_us": round(us_lin16, 1), "tile": list(best.as_tuple()),
                                         "bf16_output_tile": list(t16.as_tuple())}
         # context, not a target: the vendor library (hipBLASLt through torch.matmul)
-        # on the same bf16 operands, bf16 output, same box; beside it this
+        # on the same bf16 operands, bf16 output, same GPU; beside it this
         # library's plain product with a bf16 output, same tile as above
         Y16 = torch.empty(M, N, dtype=torch.bfloat16, device="cuda")
         us_lib16 = time_us(lambda: mlk.matmul(qa, qb, Y16, accumulate=False, cfg=t16), 20)
