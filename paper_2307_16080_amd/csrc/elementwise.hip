@@ -177,23 +177,34 @@ __device__ inline uint32_t e4m3_of_quotient(float x, float s, float r, bool fast
 // no rounding step lies between y and RN(x / s) and the code is RN(x / s)'s.
 // Values of 448 or more in magnitude (or NaN), or a bracket that straddles a
 // step, take e4m3_of_quotient per value.
-__device__ inline uint32_t e4m3_encode4(const f4_t& a, float s, float r, bool fast) {
-    if (fast) {
-        const float y0 = a[0] * r, y1 = a[1] * r, y2 = a[2] * r, y3 = a[3] * r;
-        // (a NaN compares false)
-        if (fabsf(y0) < 448.0f && fabsf(y1) < 448.0f && fabsf(y2) < 448.0f && fabsf(y3) < 448.0f) {
-            const float up = 1.0f + 0x1p-21f, dn = 1.0f - 0x1p-21f;
-            const uint32_t c = (uint32_t)__builtin_amdgcn_cvt_pk_fp8_f32(
-                y2, y3, __builtin_amdgcn_cvt_pk_fp8_f32(y0, y1, 0, false), true);
-            const uint32_t cu = (uint32_t)__builtin_amdgcn_cvt_pk_fp8_f32(
-                y2 * up, y3 * up, __builtin_amdgcn_cvt_pk_fp8_f32(y0 * up, y1 * up, 0, false), true);
-            const uint32_t cd = (uint32_t)__builtin_amdgcn_cvt_pk_fp8_f32(
-                y2 * dn, y3 * dn, __builtin_amdgcn_cvt_pk_fp8_f32(y0 * dn, y1 * dn, 0, false), true);
-            if (cu == c && cd == c) return c;
-        }
-    }
+// The packed conversion's code for four values into *code; true when the
+// bracket test settles all four (every |y| below 448 and neither bracket end
+// changes the code).
+__device__ inline bool e4m3_try_pack4(const f4_t& a, float r, uint32_t* code) {
+    const float y0 = a[0] * r, y1 = a[1] * r, y2 = a[2] * r, y3 = a[3] * r;
+    // (a NaN compares false)
+    if (!(fabsf(y0) < 448.0f && fabsf(y1) < 448.0f && fabsf(y2) < 448.0f && fabsf(y3) < 448.0f)) return false;
+    const float up = 1.0f + 0x1p-21f, dn = 1.0f - 0x1p-21f;
+    const uint32_t c = (uint32_t)__builtin_amdgcn_cvt_pk_fp8_f32(
+        y2, y3, __builtin_amdgcn_cvt_pk_fp8_f32(y0, y1, 0, false), true);
+    const uint32_t cu = (uint32_t)__builtin_amdgcn_cvt_pk_fp8_f32(
+        y2 * up, y3 * up, __builtin_amdgcn_cvt_pk_fp8_f32(y0 * up, y1 * up, 0, false), true);
+    const uint32_t cd = (uint32_t)__builtin_amdgcn_cvt_pk_fp8_f32(
+        y2 * dn, y3 * dn, __builtin_amdgcn_cvt_pk_fp8_f32(y0 * dn, y1 * dn, 0, false), true);
+    *code = c;
+    return cu == c && cd == c;
+}
+
+// four codes value by value
+__device__ inline uint32_t e4m3_slow4(const f4_t& a, float s, float r, bool fast) {
     return e4m3_of_quotient(a[0], s, r, fast) | (e4m3_of_quotient(a[1], s, r, fast) << 8) |
            (e4m3_of_quotient(a[2], s, r, fast) << 16) | (e4m3_of_quotient(a[3], s, r, fast) << 24);
+}
+
+__device__ inline uint32_t e4m3_encode4(const f4_t& a, float s, float r, bool fast) {
+    uint32_t c;
+    if (fast && e4m3_try_pack4(a, r, &c)) return c;
+    return e4m3_slow4(a, s, r, fast);
 }
 
 __global__ __launch_bounds__(kThreads) void k_quant_e4m3(const float* __restrict__ x, int64_t n,
@@ -358,10 +369,28 @@ __global__ __launch_bounds__(kThreads) void k_quant_e4m3_fused(const float* __re
     if (blockIdx.x == 0 && threadIdx.x == 0) *scale = s;
     const float r = __frcp_rn(s);
     const bool fast = __builtin_isfinite(r) && r > 0.0f;
+    // Codes that the packed conversion settles are stored at once; the other
+    // groups (the one holding the maximum, values next to a rounding step) are
+    // read again and take the per-value path in one loop, so the kernel holds
+    // one copy of that long path rather than one per register group (inlined
+    // into all sixteen, it made the kernel four times larger).
+    uint32_t rest = 0;
 #pragma unroll
     for (int u = 0; u < kFusedVec; ++u) {
         const int64_t i = first + u * stride;
-        if (i < n4) *(uint32_t*)(q + 4 * i) = e4m3_encode4(a[u], s, r, fast);
+        uint32_t c;
+        if (i < n4) {
+            if (fast && e4m3_try_pack4(a[u], r, &c))
+                *(uint32_t*)(q + 4 * i) = c;
+            else
+                rest |= 1u << u;
+        }
+    }
+    while (rest != 0) {
+        const int u = __builtin_ctz(rest);
+        rest &= rest - 1;
+        const int64_t i = first + u * stride;
+        *(uint32_t*)(q + 4 * i) = e4m3_slow4(*(const f4_t*)(x + 4 * i), s, r, fast);
     }
     if (blockIdx.x == 0)
         for (int64_t j = n4 * 4 + threadIdx.x; j < n; j += blockDim.x)
