@@ -263,6 +263,23 @@ def test_quantize_e4m3_wait_fallback(monkeypatch):
         assert host(s)[0] == np.float32(sc) and np.array_equal(bits8(q8), codes), x.size
 
 
+@pytest.mark.parametrize("n", [1001, 1 << 20, (1 << 24) + 4])
+def test_quantize_e4m3_subnormal_inputs(n):
+    """Every input an fp32 subnormal: the scale amax / 448 is subnormal too
+    and 1 / scale overflows, so the multiply-by-reciprocal encoder is off and
+    every value takes the exact per-value division (in the one-pass kernel,
+    every register group through its second loop; in the two-pass one past
+    the resident grid).  Codes and scale equal the oracle's bit for bit."""
+    x = (np.random.default_rng(n % 997).standard_normal(n) * 1e-41).astype(np.float32)
+    assert np.all(np.abs(x) < np.finfo(np.float32).tiny)
+    codes, sc = oracle.quantize_e4m3(x)
+    with np.errstate(over="ignore"):
+        assert not np.isfinite(np.float32(1.0) / np.float32(sc))
+    q8, s = mlk.quantize(dev(x), "e4m3")
+    assert host(s)[0] == np.float32(sc)
+    assert np.array_equal(bits8(q8), codes)
+
+
 @pytest.mark.parametrize("n", [1 << 24, (1 << 24) + 4, (1 << 24) + 4096 * 4 + 3])
 def test_quantize_e4m3_at_and_past_the_resident_grid(n):
     """The benchmark's 16.8 M elements (one pass, every resident workgroup) and
